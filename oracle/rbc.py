@@ -1,0 +1,242 @@
+"""2D Rayleigh-Benard convection, Fourier (x) x Chebyshev (z), as a dense FP64 oracle.
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
+
+The equations are written in the paper's IVP form M dX/dt + L X = F(X)
+(Supplementary, "Initial value problems"); the sparse ultraspherical
+discretization with tau terms follows "Sparse spectral methods".  Readings the
+paper leaves open (all listed in the design doc):
+
+* free-fall units: nu = (Ra/Pr)^(-1/2), kappa = (Ra Pr)^(-1/2); buoyancy b with
+  b(z=0) = 1, b(z=1) = 0 and no-slip walls u = w = 0;
+* first-order lifted-tau formulation: grad(u) is augmented by e_z lift(tau_1) with
+  lift into the last C1 mode, the second tau of each field enters its C2 equation
+  as the last C2 mode, the pressure gauge int p dz = 0 carries tau_p at k = 0;
+* every block has S = 4N + 7 slots:
+      u[0:N], w[N:2N], b[2N:3N], p[3N:4N],
+      tau_u1, tau_w1, tau_b1, tau_u2, tau_w2, tau_b2, tau_p;
+  equation rows use the same slot numbers: u-, w-, b-momentum (C2 coefficients),
+  continuity (C1), six boundary rows u(0), u(1), w(0), w(1), b(0), b(1), and the
+  gauge row (k = 0) or the row tau_p = 0 (k != 0).
+"""
+import numpy as np
+
+from . import spectral as sp
+
+
+class RBC:
+    def __init__(self, Nx=256, Nz=64, Lx=4.0, Ra=1e6, Pr=1.0, dealias=1.5):
+        assert Nx % 2 == 0
+        self.Nx, self.Nz, self.Lx, self.Ra, self.Pr = Nx, Nz, Lx, Ra, Pr
+        self.K = Nx // 2
+        self.N = Nz
+        self.S = 4 * Nz + 7
+        self.nu = (Ra / Pr) ** -0.5
+        self.kappa = (Ra * Pr) ** -0.5
+        self.Ngx = int(round(dealias * Nx))
+        self.Ngz = int(round(dealias * Nz))
+        self.kx = sp.fourier_wavenumbers(self.K, Lx)
+        # transforms on the dealiased grid
+        self.Bx = sp.fourier_backward_matrix(self.K, self.Ngx, Lx)
+        self.Fx = sp.fourier_forward_matrix(self.K, self.Ngx, Lx)
+        self.Bz = sp.chebyshev_backward_matrix(self.N, self.Ngz)
+        self.Fz = sp.chebyshev_forward_matrix(self.N, self.Ngz)
+        # derivative d/dz within the T basis on [0, 1]: dz = 2 d/dx
+        self.Dz = 2.0 * sp.cheb_derivative_T(self.N)
+        self.S10 = sp.S1(self.N) @ sp.S0(self.N)
+        self.M, self.L, self.Fconst = self._build_matrices()
+
+    # ------------------------------------------------------------------ slots
+    def sl(self, name):
+        N = self.N
+        base = {"u": 0, "w": N, "b": 2 * N, "p": 3 * N}
+        if name in base:
+            return slice(base[name], base[name] + N)
+        taus = ["tau_u1", "tau_w1", "tau_b1", "tau_u2", "tau_w2", "tau_b2", "tau_p"]
+        return 4 * N + taus.index(name)
+
+    # ------------------------------------------------------------------ matrices
+    def _build_matrices(self):
+        N, K, S = self.N, self.K, self.S
+        nu, ka = self.nu, self.kappa
+        S0, S1, D0, D1 = sp.S0(N), sp.S1(N), sp.D0(N), sp.D1(N)
+        S10 = S1 @ S0
+        DZ1 = 2.0 * D0                      # d/dz: T -> C1 on [0, 1]
+        DZZ = 4.0 * (D1 @ D0)               # d2/dz2: T -> C2
+        SD = S1 @ DZ1                       # d/dz: T -> C2
+        eN1 = np.zeros(N); eN1[N - 1] = 1.0
+        eN2 = np.zeros(N); eN2[N - 2] = 1.0
+        e0 = np.zeros(N); e0[0] = 1.0
+        lift_dz = 4.0                        # d/dz U_{N-1}(2z-1) = 4 C2_{N-2}
+        bot, top = sp.boundary_row(N, -1), sp.boundary_row(N, +1)
+        integ = sp.integral_row(N, 0.0, 1.0)
+        u, w, b, p = self.sl("u"), self.sl("w"), self.sl("b"), self.sl("p")
+        tu1, tw1, tb1 = self.sl("tau_u1"), self.sl("tau_w1"), self.sl("tau_b1")
+        tu2, tw2, tb2, tp = self.sl("tau_u2"), self.sl("tau_w2"), self.sl("tau_b2"), self.sl("tau_p")
+        # equation rows share the slot numbers of the unknown blocks
+        ru, rw, rb, rc = u, w, b, p
+        bc_rows = [tu1, tw1, tb1, tu2, tw2, tb2]   # 6 boundary rows
+        r_gauge = tp
+        M = np.zeros((K, S, S), dtype=complex)
+        L = np.zeros((K, S, S), dtype=complex)
+        Fc = np.zeros((K, S), dtype=complex)
+        for k in range(K):
+            kx = self.kx[k]
+            lap = DZZ - kx * kx * S10
+            # mass matrix: d/dt of u, w, b in the C2 rows
+            M[k][ru, u] = S10
+            M[k][rw, w] = S10
+            M[k][rb, b] = S10
+            # x-momentum
+            L[k][ru, u] = -nu * lap
+            L[k][ru, p] = 1j * kx * S10
+            L[k][ru, tu1] = -nu * lift_dz * eN2
+            L[k][ru, tu2] = eN1
+            # z-momentum
+            L[k][rw, w] = -nu * lap
+            L[k][rw, p] = SD
+            L[k][rw, b] = -S10
+            L[k][rw, tw1] = -nu * lift_dz * eN2
+            L[k][rw, tw2] = eN1
+            # buoyancy
+            L[k][rb, b] = -ka * lap
+            L[k][rb, tb1] = -ka * lift_dz * eN2
+            L[k][rb, tb2] = eN1
+            # continuity (C1 rows): div u + lift(tau_w1) (+ tau_p at k = 0)
+            L[k][rc, u] = 1j * kx * S0
+            L[k][rc, w] = DZ1
+            L[k][rc, tw1] = eN1
+            # boundary rows
+            L[k][bc_rows[0], u] = bot
+            L[k][bc_rows[1], u] = top
+            L[k][bc_rows[2], w] = bot
+            L[k][bc_rows[3], w] = top
+            L[k][bc_rows[4], b] = bot
+            L[k][bc_rows[5], b] = top
+            if k == 0:
+                L[k][rc, tp] = e0
+                L[k][r_gauge, p] = integ
+                Fc[k, bc_rows[4]] = 1.0     # b(z=0) = 1 for the horizontal mean
+            else:
+                L[k][r_gauge, tp] = 1.0     # tau_p = 0 away from k = 0
+        return M, L, Fc
+
+    # ------------------------------------------------------------------ transforms of (K, N) coefficient fields
+    def to_grid(self, c):
+        """(K, N) complex coefficients -> (Ngx, Ngz) real grid values."""
+        return sp.fourier_backward(c @ self.Bz.T, self.Bx)
+
+    def to_grid_adjoint(self, g):
+        return sp.fourier_backward_adjoint(g, self.Bx) @ self.Bz
+
+    def from_grid(self, g):
+        """(Ngx, Ngz) real grid values -> (K, N) coefficients (truncating)."""
+        return sp.fourier_forward(g, self.Fx) @ self.Fz.T
+
+    def from_grid_adjoint(self, cbar):
+        return sp.fourier_forward_adjoint(cbar @ self.Fz, self.Fx)
+
+    def ddx(self, c):
+        return 1j * self.kx[:, None] * c
+
+    def ddz(self, c):
+        return c @ self.Dz.T
+
+    # ------------------------------------------------------------------ explicit term
+    def _grid_fields(self, X):
+        u, w, b = X[:, self.sl("u")], X[:, self.sl("w")], X[:, self.sl("b")]
+        g = {}
+        g["u"], g["w"] = self.to_grid(u), self.to_grid(w)
+        g["ux"], g["uz"] = self.to_grid(self.ddx(u)), self.to_grid(self.ddz(u))
+        g["wx"], g["wz"] = self.to_grid(self.ddx(w)), self.to_grid(self.ddz(w))
+        g["bx"], g["bz"] = self.to_grid(self.ddx(b)), self.to_grid(self.ddz(b))
+        return g
+
+    def nonlinear_coeffs(self, X):
+        """T coefficients (first N) of N_u, N_w, N_b = -(u.grad) of (u, w, b)."""
+        g = self._grid_fields(X)
+        Nu = -(g["u"] * g["ux"] + g["w"] * g["uz"])
+        Nw = -(g["u"] * g["wx"] + g["w"] * g["wz"])
+        Nb = -(g["u"] * g["bx"] + g["w"] * g["bz"])
+        return self.from_grid(Nu), self.from_grid(Nw), self.from_grid(Nb)
+
+    def F(self, X):
+        Nu, Nw, Nb = self.nonlinear_coeffs(X)
+        out = self.Fconst.copy()
+        out[:, self.sl("u")] += Nu @ self.S10.T
+        out[:, self.sl("w")] += Nw @ self.S10.T
+        out[:, self.sl("b")] += Nb @ self.S10.T
+        return out
+
+    def F_vjp(self, X, Ybar):
+        """(dF/dX)^H Ybar: transposes of the conversion, of the forward and backward
+        transforms and of the derivatives, and the product rule."""
+        g = self._grid_fields(X)
+        # conversion S10 and forward transform, transposed
+        Nub = self.from_grid_adjoint(Ybar[:, self.sl("u")] @ self.S10)
+        Nwb = self.from_grid_adjoint(Ybar[:, self.sl("w")] @ self.S10)
+        Nbb = self.from_grid_adjoint(Ybar[:, self.sl("b")] @ self.S10)
+        # product rule
+        ub = -(Nub * g["ux"] + Nwb * g["wx"] + Nbb * g["bx"])
+        wb = -(Nub * g["uz"] + Nwb * g["wz"] + Nbb * g["bz"])
+        uxb, uzb = -Nub * g["u"], -Nub * g["w"]
+        wxb, wzb = -Nwb * g["u"], -Nwb * g["w"]
+        bxb, bzb = -Nbb * g["u"], -Nbb * g["w"]
+        # backward transforms and derivatives, transposed
+        ikx = 1j * self.kx[:, None]
+        Xb = np.zeros_like(Ybar)
+        Xb[:, self.sl("u")] = (self.to_grid_adjoint(ub)
+                              + np.conj(ikx) * self.to_grid_adjoint(uxb)
+                              + self.to_grid_adjoint(uzb) @ self.Dz)
+        Xb[:, self.sl("w")] = (self.to_grid_adjoint(wb)
+                              + np.conj(ikx) * self.to_grid_adjoint(wxb)
+                              + self.to_grid_adjoint(wzb) @ self.Dz)
+        Xb[:, self.sl("b")] = (np.conj(ikx) * self.to_grid_adjoint(bxb)
+                              + self.to_grid_adjoint(bzb) @ self.Dz)
+        return Xb
+
+    # ------------------------------------------------------------------ scale-1 grid, initial state, cost
+    def scale1(self):
+        """Transforms on the un-padded Nx x Nz grid used for inputs and gradients."""
+        Fx = sp.fourier_forward_matrix(self.K, self.Nx, self.Lx)
+        Fz = sp.chebyshev_forward_matrix(self.N, self.Nz)
+        return Fx, Fz
+
+    def grid_points(self):
+        """Scale-1 grid: x_j = j Lx / Nx, z on the Nz Gauss nodes mapped to [0, 1]."""
+        return sp.fourier_grid(self.Nx, self.Lx), sp.z_of_x(sp.chebyshev_nodes(self.Nz), 0.0, 1.0)
+
+    def initial_state(self, b0_grid):
+        """State with u = w = p = taus = 0 and b from its (Nx, Nz) scale-1 grid values."""
+        Fx, Fz = self.scale1()
+        X = np.zeros((self.K, self.S), dtype=complex)
+        X[:, self.sl("b")] = sp.fourier_forward(b0_grid, Fx) @ Fz.T
+        return X
+
+    def initial_state_adjoint(self, Xbar):
+        """Gradient with respect to the scale-1 grid values of b0."""
+        Fx, Fz = self.scale1()
+        return sp.fourier_forward_adjoint(Xbar[:, self.sl("b")] @ Fz, Fx)
+
+    def kinetic_energy(self, X):
+        """J = 1/2 int_0^Lx int_0^1 (u^2 + w^2) dz dx, exactly, from the coefficients:
+        J = Lx/2 sum_k w_k Re(u_k^H G u_k + w_k^H G w_k), w_0 = 1, w_k = 2, with the
+        k = 0 coefficients taken by their real parts."""
+        G = sp.gram_T(self.N, 0.0, 1.0)
+        wk = np.full(self.K, 2.0); wk[0] = 1.0
+        J = 0.0
+        for f in ("u", "w"):
+            c = X[:, self.sl(f)].copy()
+            c[0] = c[0].real
+            J += 0.5 * self.Lx * np.sum(wk * np.real(np.einsum("km,mn,kn->k", c.conj(), G, c)))
+        return J
+
+    def kinetic_energy_grad(self, X):
+        G = sp.gram_T(self.N, 0.0, 1.0)
+        wk = np.full(self.K, 2.0); wk[0] = 1.0
+        Xb = np.zeros_like(X)
+        for f in ("u", "w"):
+            c = X[:, self.sl(f)].copy()
+            c[0] = c[0].real
+            Xb[:, self.sl(f)] = self.Lx * wk[:, None] * (c @ G.T)
+        return Xb

@@ -1,0 +1,127 @@
+"""Pins of the oracle's IMEX timesteppers and their adjoints (Supplementary, "Initial
+value problems") on problems with closed-form solutions, and the inner-product test
+<Y, Phi X> = <Phi^* Y, X> on a linear trajectory (Supplementary, "Verification")."""
+import numpy as np
+import pytest
+
+from oracle import imex
+
+GAMMA = 1.0 - 1.0 / np.sqrt(2.0)
+
+
+class Linear:
+    """M dX/dt + L X = C X with dense random blocks (F linear: F' = C)."""
+
+    def __init__(self, M, L, C):
+        self.M, self.L, self.C = M, L, C
+
+    def F(self, X):
+        return np.einsum("kij,kj->ki", self.C, X)
+
+    def F_vjp(self, X, Yb):
+        return np.einsum("kji,kj->ki", self.C.conj(), Yb)
+
+
+def scalar(lam, a=0.0):
+    one = np.ones((1, 1, 1), dtype=complex)
+    return Linear(one, lam * one, a * one)
+
+
+def test_rk222_implicit_amplification_closed_form():
+    """For dX/dt = -lam X treated implicitly: X1 = X0/(1 + g z), X2 = (X0 - (1-g) z X1)/(1 + g z)."""
+    lam, dt, n = 3.7, 0.05, 40
+    P = scalar(lam)
+    XN, _ = imex.rk_forward(P, np.ones((1, 1)), dt, n)
+    z = dt * lam
+    R = (1.0 - (1.0 - GAMMA) * z / (1.0 + GAMMA * z)) / (1.0 + GAMMA * z)
+    assert abs(XN[0, 0] - R ** n) < 1e-14
+
+
+def test_rk222_explicit_part_is_second_order_taylor():
+    a, dt, n = 0.8, 0.1, 10
+    XN, _ = imex.rk_forward(scalar(0.0, a), np.ones((1, 1)), dt, n)
+    z = dt * a
+    assert abs(XN[0, 0] - (1 + z + z * z / 2) ** n) < 1e-13
+
+
+@pytest.mark.parametrize("stepper", ["rk", "sbdf"])
+def test_second_order_convergence_to_exponential(stepper):
+    lam, a, T = 2.0, 0.5, 1.0
+    errs = []
+    for n in (40, 80, 160):
+        dt = T / n
+        P = scalar(lam, a)
+        if stepper == "rk":
+            XN, _ = imex.rk_forward(P, np.ones((1, 1)), dt, n)
+        else:
+            XN, _ = imex.sbdf_forward(P, np.ones((1, 1)), dt, n)
+        errs.append(abs(XN[0, 0] - np.exp((a - lam) * T)))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(np.abs(rates - 2.0) < 0.1), rates
+
+
+def test_sbdf2_matches_two_root_recurrence():
+    """Implicit heat: SBDF1 step then (3/2 + z) X_n = 2 X_{n-1} - X_{n-2}/2."""
+    lam, dt, n = 1.3, 0.1, 30
+    XN, states = imex.sbdf_forward(scalar(lam), np.ones((1, 1)), dt, n)
+    z = dt * lam
+    x = [1.0, 1.0 / (1.0 + z)]
+    # closed form of the linear recurrence from its characteristic roots
+    r1, r2 = np.roots([1.5 + z, -2.0, 0.5])
+    A = np.array([[1.0, 1.0], [r1, r2]])
+    c1, c2 = np.linalg.solve(A, np.array(x, dtype=complex))
+    ref = c1 * r1 ** n + c2 * r2 ** n
+    assert abs(XN[0, 0] - ref) < 1e-14
+
+
+def test_heat_adjoint_closed_form():
+    """J = 1/2 |X_N|^2 with X_N = R^N X_0 gives dJ/dX_0 = R^(2N) X_0 (real R)."""
+    lam, dt, n = 3.7, 0.05, 25
+    X0 = np.array([[0.7 + 0.2j]])
+    P = scalar(lam)
+    XN, hist = imex.rk_forward(P, X0, dt, n)
+    g = imex.rk_adjoint(P, XN, hist, dt)
+    G = (XN[0, 0] / X0[0, 0]).real
+    assert abs(G - ((1.0 - (1.0 - GAMMA) * dt * lam / (1.0 + GAMMA * dt * lam))
+                    / (1.0 + GAMMA * dt * lam)) ** n) < 1e-15
+    assert abs(g[0, 0] - G * G * X0[0, 0]) < 1e-15
+    XN, states = imex.sbdf_forward(P, X0, dt, n)
+    g = imex.sbdf_adjoint(P, XN, states, dt)
+    G = (XN[0, 0] / X0[0, 0]).real
+    assert abs(g[0, 0] - G * G * X0[0, 0]) < 1e-15
+
+
+def random_linear(seed, K=3, S=4):
+    rng = np.random.default_rng(seed)
+    c = lambda: rng.standard_normal((K, S, S)) + 1j * rng.standard_normal((K, S, S))
+    M = c() + 4 * np.eye(S)[None]
+    return Linear(M, 0.5 * c(), 0.3 * c())
+
+
+@pytest.mark.parametrize("stepper", ["rk", "sbdf"])
+def test_linear_trajectory_inner_product(stepper):
+    P = random_linear(5)
+    rng = np.random.default_rng(6)
+    X0 = rng.standard_normal((3, 4)) + 1j * rng.standard_normal((3, 4))
+    Yb = rng.standard_normal((3, 4)) + 1j * rng.standard_normal((3, 4))
+    dt, n = 0.05, 12
+    if stepper == "rk":
+        XN, hist = imex.rk_forward(P, X0, dt, n)
+        Xb = imex.rk_adjoint(P, Yb, hist, dt)
+    else:
+        XN, states = imex.sbdf_forward(P, X0, dt, n)
+        Xb = imex.sbdf_adjoint(P, Yb, states, dt)
+    lhs = np.real(np.vdot(Yb, XN))
+    rhs = np.real(np.vdot(Xb, X0))
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+def test_block_lu_adjoint_solve_inner_product():
+    P = random_linear(7, K=2, S=9)
+    lu = imex.BlockLU(P.M, P.L, 1.0, 0.3)
+    rng = np.random.default_rng(8)
+    x = rng.standard_normal((2, 9)) + 1j * rng.standard_normal((2, 9))
+    y = rng.standard_normal((2, 9)) + 1j * rng.standard_normal((2, 9))
+    lhs = np.real(np.vdot(y, lu.solve(x)))
+    rhs = np.real(np.vdot(lu.solve_adjoint(y), x))
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)

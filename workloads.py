@@ -1,0 +1,44 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle checks.
+
+This module draws random numbers and lays them out on the problem's grid points;
+it holds none of the solver's arithmetic (no transforms, operators or timesteps).
+All generators use numpy's PCG64 (numpy.random.default_rng(seed)) in FP64.
+"""
+import numpy as np
+
+
+def gauss_nodes_unit(Nz):
+    """Gauss-Chebyshev (root) nodes mapped to [0, 1], ascending."""
+    return 0.5 * (1.0 - np.cos(np.pi * (np.arange(Nz) + 0.5) / Nz))
+
+
+def rbc_b0(seed=0, Nx=256, Nz=64, amp=1e-3):
+    """Initial buoyancy on the (Nx, Nz) scale-1 grid: the conduction profile 1 - z plus
+    i.i.d. standard normal noise of amplitude amp damped at the walls by 4 z (1 - z)."""
+    rng = np.random.default_rng(seed)
+    xi = rng.standard_normal((Nx, Nz))
+    z = gauss_nodes_unit(Nz)
+    return (1.0 - z)[None, :] + amp * xi * (4.0 * z * (1.0 - z))[None, :]
+
+
+def ks_c0(seed=0, Nx=64, amp=1e-2):
+    """Initial half-spectrum coefficients c_m = amp (1 + m)^-2 (xi + i eta), m < Nx/2,
+    with a real mean mode; returned as an (Nx/2,) complex array."""
+    rng = np.random.default_rng(seed)
+    K = Nx // 2
+    xi = rng.standard_normal(K)
+    eta = rng.standard_normal(K)
+    m = np.arange(K)
+    c = amp * (1.0 + m) ** -2.0 * (xi + 1j * eta)
+    c[0] = c[0].real
+    return c
+
+
+def random_state(seed, shape, real_first_row=True):
+    """Complex normal test vector of the given shape; the first block (the mean mode)
+    is made real when real_first_row is set."""
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    if real_first_row:
+        X[0] = X[0].real
+    return X
