@@ -1,0 +1,141 @@
+/*
+ * sps.h — C ABI of the MI355X spectral IMEX timestep and discrete-adjoint library.
+ *
+ * The library advances an initial-value problem written as
+ *     M dX/dt + L X = F(X)                     (paper, Supplementary: Initial value problems)
+ * with a sparse ultraspherical/tau discretization (paper: Sparse spectral methods),
+ * an IMEX scheme (ARS(2,2,2) Runge-Kutta or SBDF2 multistep), and computes gradients by
+ * the adjoint-state method (paper: equ:adjoint and equ:efficient_gradient): a forward
+ * sweep with checkpoints, a reverse sweep through transposed solves that reuse the LU
+ * factors (paper, Methods: Linear system solves) and vector-Jacobian products of F
+ * through adjoint transforms (paper, Methods: Spectral transforms).
+ *
+ * Conventions shared by every entry point
+ *  - All array arguments are DEVICE pointers (allocated by the caller, e.g. torch tensors)
+ *    unless stated otherwise; the caller keeps ownership.  Complex numbers are stored as
+ *    (re, im) pairs of doubles.
+ *  - State layout: X[k][s], k = 0..K-1 Fourier wavenumbers (half spectrum, Nyquist dropped),
+ *    s = 0..S-1 slots of one wavenumber block; complex.  For the 2D Rayleigh-Benard problem
+ *    S = 4N + 7: u[0:N], w[N:2N], b[2N:3N], p[3N:4N] (Chebyshev-T coefficients), then
+ *    tau_u1, tau_w1, tau_b1, tau_u2, tau_w2, tau_b2, tau_p.  For 1D Kuramoto-Sivashinsky
+ *    S = 1.  sps_state_size() returns K*S*2 doubles.
+ *  - Cotangents (Xbar, dJdX) use the same layout and the real inner product
+ *    <a, b> = sum Re(conj(a) b) of the real parameterization.
+ *  - Calls are asynchronous on the stream given to sps_build_problem; results are valid
+ *    after sps_sync() or a synchronization of that stream.  Argument errors are returned
+ *    at once; device-detected errors (zero pivot, non-finite state) set a sticky flag
+ *    that the next sps_sync() reports.  No C++ exception crosses this interface.
+ *  - A handle is used from one host thread at a time.
+ */
+#ifndef SPS_H
+#define SPS_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sps_problem sps_problem;
+
+enum sps_status {
+  SPS_OK = 0,
+  SPS_E_ARG = -1,          /* invalid argument or unsupported size */
+  SPS_E_NOMEM = -2,        /* device allocation failed */
+  SPS_E_HIP = -3,          /* HIP runtime error */
+  SPS_E_SINGULAR = -4,     /* zero pivot in the LU factorization */
+  SPS_E_NONFINITE = -5,    /* a state became NaN or infinite */
+  SPS_E_STATE = -6,        /* call out of order (e.g. adjoint without a recorded forward run) */
+  SPS_E_UNSUPPORTED = -7
+};
+
+enum sps_equation { SPS_RBC2D = 1, SPS_KS1D = 2 };
+enum sps_scheme { SPS_RK222 = 1, SPS_SBDF2 = 2 };
+
+typedef struct {
+  int equation;          /* sps_equation */
+  int scheme;            /* sps_scheme; RBC uses SPS_RK222, KS uses SPS_SBDF2 */
+  int nx;                /* Fourier grid points at scale 1 (K = nx/2 stored wavenumbers) */
+  int nz;                /* Chebyshev modes N (RBC), ignored for KS */
+  double lx;             /* Fourier period */
+  double param0;         /* RBC: Rayleigh number Ra */
+  double param1;         /* RBC: Prandtl number Pr */
+  double dealias;        /* padding factor of the collocation grid (1.5) */
+  double dt;             /* timestep */
+  int checkpoint_every;  /* steps between stored checkpoints in the forward sweep */
+  int max_steps;         /* largest nsteps accepted by sps_step / sps_gradient */
+} sps_desc;
+
+/* Build a problem: assembles the banded operators and transform tables on the host,
+ * allocates device workspace and the checkpoint store (paper, Supplementary: Initial
+ * value problems; checkpointing).  hip_stream may be NULL (the null stream).
+ * Returns SPS_E_ARG for unsupported sizes.  *out owns all device memory it allocates. */
+int sps_build_problem(const sps_desc *desc, void *hip_stream, sps_problem **out);
+
+/* Number of doubles in one state vector (K * S * 2). */
+long long sps_state_size(const sps_problem *P);
+
+/* LU-factor the implicit matrices of the scheme for every wavenumber (paper, Methods:
+ * Linear system solves; factors are reused until dt changes).  Idempotent. */
+int sps_factor(sps_problem *P);
+
+/* Forward sweep: advance X (in/out, state layout) by nsteps steps of the IMEX scheme
+ * (paper, equ:imex and the IMEX Runge-Kutta stage equations), storing a checkpoint
+ * every checkpoint_every steps so that sps_adjoint_step can reverse this run.
+ * 1 <= nsteps <= max_steps.  Factors automatically if needed. */
+int sps_step(sps_problem *P, double *X, int nsteps);
+
+/* Reverse sweep over the run recorded by the last sps_step (paper, equ:IMEX_adjoint
+ * and the RK adjoint equations): on entry Xbar holds the cotangent of the final state,
+ * on exit the cotangent of the initial state.  Segments between checkpoints are
+ * recomputed.  nsteps must equal the recorded run length, else SPS_E_STATE. */
+int sps_adjoint_step(sps_problem *P, double *Xbar, int nsteps);
+
+/* Cost functional and its gradient at a state (paper, equ:efficient_gradient seed):
+ * RBC: J = 1/2 int int (u^2 + w^2) dz dx; KS: J = 1/2 (1/L) int u^2 dx.
+ * J_out: device pointer to one double; dJdX: cotangent in state layout. */
+int sps_cost(sps_problem *P, const double *X, double *J_out, double *dJdX);
+
+/* Full gradient: X0 -> forward nsteps with checkpoints -> J and dJ/dX_N -> reverse sweep.
+ * Outputs XN (final state), dJdX0 (state layout) and J_out (one double); any output may
+ * be NULL except dJdX0. */
+int sps_gradient(sps_problem *P, const double *X0, int nsteps, double *XN, double *dJdX0,
+                 double *J_out);
+
+/* Initial state from scale-1 grid values (paper, Methods: Spectral transforms, forward
+ * transform f_hat = T f).  RBC: grid is b0[x][z], nx * nz doubles; the state gets b and
+ * zero u, w, p, taus.  KS: grid is u0[x], nx doubles. */
+int sps_initial_state(sps_problem *P, const double *grid, double *X);
+
+/* Adjoint of sps_initial_state (T^H applied to the cotangent): gradient with respect to
+ * the scale-1 grid values. */
+int sps_initial_state_adjoint(sps_problem *P, const double *Xbar, double *grid_bar);
+
+/* Components of one step, exposed for verification of single rows of the path. */
+/* F(X) in state layout (rows are equation slots). */
+int sps_eval_F(sps_problem *P, const double *X, double *F);
+/* (dF/dX)^H Fbar at X. */
+int sps_eval_F_vjp(sps_problem *P, const double *X, const double *Fbar, double *Xbar);
+/* Solve A x = r (adjoint = 0) or A^H x = r (adjoint = 1) with the current factors of the
+ * scheme's implicit matrix (RK222: M + dt*gamma*L; SBDF2: 3/(2dt) M + L). */
+int sps_solve(sps_problem *P, const double *R, double *X, int adjoint);
+
+/* Kernel timing of one kernel class inside the library (HIP events around each launch on
+ * the problem's stream).  kind: 0 = per-wavenumber forward stage kernel (transforms in z,
+ * RHS assembly, banded solve).  sps_timer_read returns launches and total milliseconds
+ * since sps_timer_enable and resets the counters. */
+int sps_timer_enable(sps_problem *P, int kind, int on);
+int sps_timer_read(sps_problem *P, long long *launches, double *total_ms);
+
+/* Wait for the problem's stream; report a deferred device error. */
+int sps_sync(sps_problem *P);
+
+/* Message of the last error on this thread (static storage). */
+const char *sps_last_error(void);
+
+/* Release everything the handle owns. */
+void sps_destroy(sps_problem *P);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPS_H */

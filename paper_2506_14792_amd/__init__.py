@@ -1,0 +1,6 @@
+"""MI355X-native spectral IMEX timestep and discrete adjoint (Python binding of libsps.so).
+
+The compute path is the HIP library; this package only marshals arguments.  Importing it
+does not load the library; the first call does, and fails loudly if it is missing.
+"""
+from .sps import (Problem, SpsError, lib, rbc_host_bands, RBC2D, KS1D, RK222, SBDF2)  # noqa: F401

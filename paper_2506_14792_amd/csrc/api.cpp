@@ -1,0 +1,154 @@
+// C ABI entry points: argument checks, exception-to-status translation, error strings.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+
+#include "sps_internal.h"
+
+struct sps_problem {
+  sps::ProblemImpl* impl;
+};
+
+namespace {
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+template <typename F>
+int guard(sps_problem* P, F&& f) {
+  if (!P || !P->impl) return fail(SPS_E_ARG, "null problem handle");
+  try {
+    f(*P->impl);
+    return SPS_OK;
+  } catch (const sps::Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::exception& e) {
+    return fail(SPS_E_HIP, e.what());
+  }
+}
+}  // namespace
+
+namespace sps {
+
+std::vector<double2> twiddles(int n) {
+  std::vector<double2> t(n);
+  const long double tau = 6.28318530717958647692528676655900577L;
+  for (int i = 0; i < n; ++i) {
+    const long double a = tau * (long double)i / (long double)n;
+    t[i] = make_double2((double)cosl(a), (double)-sinl(a));
+  }
+  return t;
+}
+
+bool fft_plan(int n, int* radix, int* nst) {
+  int m = n, s = 0;
+  while (m % 3 == 0) { radix[s++] = 3; m /= 3; if (s >= 12) return false; }
+  while (m % 4 == 0) { radix[s++] = 4; m /= 4; if (s >= 12) return false; }
+  while (m % 2 == 0) { radix[s++] = 2; m /= 2; if (s >= 12) return false; }
+  *nst = s;
+  return m == 1 && s > 0;
+}
+
+}  // namespace sps
+
+extern "C" {
+
+int sps_build_problem(const sps_desc* desc, void* hip_stream, sps_problem** out) {
+  if (!desc || !out) return fail(SPS_E_ARG, "null argument");
+  *out = nullptr;
+  try {
+    sps::ProblemImpl* impl = nullptr;
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    switch (desc->equation) {
+      case SPS_RBC2D: impl = sps::make_rbc(*desc, s); break;
+      case SPS_KS1D: impl = sps::make_ks(*desc, s); break;
+      default: return fail(SPS_E_ARG, "unknown equation");
+    }
+    *out = new sps_problem{impl};
+    return SPS_OK;
+  } catch (const sps::Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::exception& e) {
+    return fail(SPS_E_HIP, e.what());
+  }
+}
+
+long long sps_state_size(const sps_problem* P) { return (P && P->impl) ? P->impl->state_size() : -1; }
+
+int sps_factor(sps_problem* P) {
+  return guard(P, [](sps::ProblemImpl& p) { p.factor(); });
+}
+
+int sps_step(sps_problem* P, double* X, int nsteps) {
+  return guard(P, [&](sps::ProblemImpl& p) { p.step(X, nsteps); });
+}
+
+int sps_adjoint_step(sps_problem* P, double* Xbar, int nsteps) {
+  return guard(P, [&](sps::ProblemImpl& p) { p.adjoint_step(Xbar, nsteps); });
+}
+
+int sps_cost(sps_problem* P, const double* X, double* J_out, double* dJdX) {
+  return guard(P, [&](sps::ProblemImpl& p) { p.cost(X, J_out, dJdX); });
+}
+
+int sps_gradient(sps_problem* P, const double* X0, int nsteps, double* XN, double* dJdX0, double* J_out) {
+  return guard(P, [&](sps::ProblemImpl& p) { p.gradient(X0, nsteps, XN, dJdX0, J_out); });
+}
+
+int sps_initial_state(sps_problem* P, const double* grid, double* X) {
+  return guard(P, [&](sps::ProblemImpl& p) { p.initial_state(grid, X); });
+}
+
+int sps_initial_state_adjoint(sps_problem* P, const double* Xbar, double* grid_bar) {
+  return guard(P, [&](sps::ProblemImpl& p) { p.initial_state_adjoint(Xbar, grid_bar); });
+}
+
+int sps_eval_F(sps_problem* P, const double* X, double* F) {
+  return guard(P, [&](sps::ProblemImpl& p) { p.eval_F(X, F); });
+}
+
+int sps_eval_F_vjp(sps_problem* P, const double* X, const double* Fbar, double* Xbar) {
+  return guard(P, [&](sps::ProblemImpl& p) { p.eval_F_vjp(X, Fbar, Xbar); });
+}
+
+int sps_solve(sps_problem* P, const double* R, double* X, int adjoint) {
+  return guard(P, [&](sps::ProblemImpl& p) { p.solve(R, X, adjoint); });
+}
+
+int sps_timer_enable(sps_problem* P, int kind, int on) {
+  return guard(P, [&](sps::ProblemImpl& p) { p.timer_enable(kind, on != 0); });
+}
+
+int sps_timer_read(sps_problem* P, long long* launches, double* total_ms) {
+  if (!launches || !total_ms) return fail(SPS_E_ARG, "null argument");
+  return guard(P, [&](sps::ProblemImpl& p) { p.timer_read(launches, total_ms); });
+}
+
+int sps_sync(sps_problem* P) {
+  int flag = 0;
+  int rc = guard(P, [&](sps::ProblemImpl& p) {
+    SPS_HIP(hipStreamSynchronize(p.stream));
+    flag = p.device_error();
+  });
+  if (rc != SPS_OK) return rc;
+  if (flag & 1) return fail(SPS_E_SINGULAR, "zero pivot in the LU factorization");
+  if (flag & 2) return fail(SPS_E_NONFINITE, "state became non-finite");
+  return SPS_OK;
+}
+
+const char* sps_last_error(void) { return g_last_error.c_str(); }
+
+void sps_destroy(sps_problem* P) {
+  if (!P) return;
+  if (P->impl) {
+    (void)hipStreamSynchronize(P->impl->stream);
+    delete P->impl;
+  }
+  delete P;
+}
+
+}  // extern "C"

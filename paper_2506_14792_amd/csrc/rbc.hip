@@ -1,0 +1,1449 @@
+// 2D Rayleigh-Benard convection, Fourier (x) x Chebyshev (z), RK222 IMEX, and its
+// discrete adjoint on gfx950.
+//
+// Equations (paper, Supplementary: Initial value problems) in the form
+// M dX/dt + L X = F(X) with the ultraspherical/tau discretization (paper: Sparse spectral
+// methods).  Per wavenumber k the unknowns are u, w, b, p (Chebyshev-T coefficients,
+// N each) and the tau variables tau_u1, tau_w1, tau_b1, tau_u2, tau_w2, tau_b2, tau_p
+// (S = 4N + 7 slots).  Equation rows share the slot numbers: u-, w-, b-momentum in C2
+// coefficients, continuity in C1, boundary rows u(0), u(1), w(0), w(1), b(0), b(1), and
+// the pressure gauge int p dz = 0 (k = 0) or tau_p = 0 (k != 0).
+//
+// Device data flow of one RK222 stage:
+//   grid-row kernel (one block per Gauss node z_j): inverse real FFTs of the 8 fields
+//     (u, w, ux, uz, wx, wz, bx, bz) from their x-spectra at z_j, products
+//     N = -(u.grad)(u, w, b), forward real FFTs, truncation  -> nl[3][Ngz][K]
+//   per-wavenumber kernel (one block per k): Chebyshev forward transform of nl, S10
+//     conversion, stage right-hand side, banded LU solve of the real-ified system,
+//     Chebyshev backward transforms of the new state and its z-derivatives
+//     -> state[k], zgrid[6][Ngz][K]
+// The adjoint runs the transposed chain: transposed solve, S10^T, adjoint Chebyshev
+// forward transform, adjoint real FFTs with the product rule, adjoint Chebyshev
+// backward transform and derivative transposes (paper, Methods: Spectral transforms;
+// Nonlinear operator graphs).
+//
+// Linear solves: per k the system A = a M + b L is made real by the diagonal phases
+// D_r (u rows times -i) and D_c (u and its taus times i), its boundary rows are made
+// sparse by the right preconditioner R (Dirichlet recombination T_n - T_{n-2} for u, w, b
+// and an integral-free recombination for p), and rows/columns are interleaved by mode.
+// B = D_r A D_c R is then a real banded matrix (kl = 7, ku = 20 at N = 64) factored by
+// banded LU with partial pivoting.  A x = r is solved as B y = D_r r, x = D_c R y, and
+// A^H z = g as B^T w = R^T D_c^H g, z = D_r^H w, through the same factors.
+#include <math.h>
+
+#include <algorithm>
+#include <cstring>
+#include <memory>
+
+#include "band_lu.h"
+#include "sps_device.h"
+#include "sps_internal.h"
+
+namespace sps {
+namespace {
+
+constexpr int NT = 256;  // threads per block of every RBC kernel
+
+struct RbcDev {
+  int K, N, S, Ngx, Ngz, Nx1, Nz1;
+  int n, kl, ku, uw;
+  double Lx, nu, ka;
+  const double* kx;     // [K]
+  const double* Cb_nj;  // [N][Ngz]  T_n(x_j)
+  const double* Cb_jn;  // [Ngz][N]  T_n(x_j)
+  const double* Cf_jn;  // [Ngz][N]  (2 - delta_n0)/Ngz T_n(x_j)
+  const double* Cf_nj;  // [N][Ngz]
+  const double* C1f_jn; // scale-1 forward [Nz1][N]
+  const double* C1f_nj; // [N][Nz1]
+  const cplx* twx;      // [Ngx]
+  const cplx* twx1;     // [Nx1]
+  FftPlan px, px1;
+  const int* rowmap;    // [S] solver row i  <- ABI row slot
+  const int* colmap;    // [S] solver col i  -> ABI column slot
+  const signed char* rowph;  // [S] 1: row slot multiplied by -i
+  const signed char* colph;  // [S] 1: column slot multiplied by +i
+  const double* rho;    // [S] X[s] = y[s] + rho[s] y[s+2]
+  const double* gram;   // [N][N] int_0^1 T_m T_n dz
+  BandFactors fac;      // base pointers; per-k offsets applied in kernels
+  int* err;             // bit 0 singular pivot, bit 1 non-finite state
+};
+
+__device__ __forceinline__ BandFactors fac_k(const RbcDev& d, int k) {
+  BandFactors f;
+  f.Lc = d.fac.Lc + (size_t)k * d.n * d.kl;
+  f.Uc = d.fac.Uc + (size_t)k * d.n * d.uw;
+  f.Ur = d.fac.Ur + (size_t)k * d.n * d.uw;
+  f.piv = d.fac.piv + (size_t)k * d.n;
+  return f;
+}
+
+// ---------------------------------------------------------------------------- operators
+// Sparse ultraspherical operators on [0,1] applied to length-N coefficient arrays in LDS.
+__device__ __forceinline__ double s0d(int m) { return m == 0 ? 1.0 : 0.5; }
+
+// (S0 c)[m] = s0d(m) c[m] - c[m+2]/2 : T -> C1
+__device__ __forceinline__ cplx s0_at(const cplx* c, int m, int N) {
+  cplx v = cscale(c[m], s0d(m));
+  if (m + 2 < N) v = csub(v, cscale(c[m + 2], 0.5));
+  return v;
+}
+// (S10 c)[n] = (S0 c)[n]/(n+1) - (S0 c)[n+2]/(n+3) : T -> C2
+__device__ __forceinline__ cplx s10_at(const cplx* c, int n, int N) {
+  cplx v = cscale(s0_at(c, n, N), 1.0 / (n + 1));
+  if (n + 2 < N) v = csub(v, cscale(s0_at(c, n + 2, N), 1.0 / (n + 3)));
+  return v;
+}
+// (DZZ c)[n] = 4 (D1 D0 c)[n] = 8 (n+2) c[n+2]
+__device__ __forceinline__ cplx dzz_at(const cplx* c, int n, int N) {
+  return (n + 2 < N) ? cscale(c[n + 2], 8.0 * (n + 2)) : czero();
+}
+// (S1 DZ1 c)[n] = 2 (c[n+1] - c[n+3])
+__device__ __forceinline__ cplx s1dz_at(const cplx* c, int n, int N) {
+  cplx v = (n + 1 < N) ? cscale(c[n + 1], 2.0) : czero();
+  if (n + 3 < N) v = csub(v, cscale(c[n + 3], 2.0));
+  return v;
+}
+// (DZ1 c)[n] = 2 (n+1) c[n+1] : T -> C1
+__device__ __forceinline__ cplx dz1_at(const cplx* c, int n, int N) {
+  return (n + 1 < N) ? cscale(c[n + 1], 2.0 * (n + 1)) : czero();
+}
+// transposes
+__device__ __forceinline__ cplx s1t_at(const cplx* y, int j, int N) {  // (S1^T y)[j]
+  cplx v = cscale(y[j], 1.0 / (j + 1));
+  if (j >= 2) v = csub(v, cscale(y[j - 2], 1.0 / (j + 1)));
+  return v;
+}
+__device__ __forceinline__ cplx s0t_at(const cplx* y, int m, int N) {  // (S0^T y)[m]
+  cplx v = cscale(y[m], s0d(m));
+  if (m >= 2) v = csub(v, cscale(y[m - 2], 0.5));
+  return v;
+}
+__device__ __forceinline__ cplx s10t_at(const cplx* y, int m, int N) {  // (S0^T S1^T y)[m]
+  cplx v = cscale(s1t_at(y, m, N), s0d(m));
+  if (m >= 2) v = csub(v, cscale(s1t_at(y, m - 2, N), 0.5));
+  return v;
+}
+__device__ __forceinline__ cplx dzzt_at(const cplx* y, int m, int N) {
+  return (m >= 2) ? cscale(y[m - 2], 8.0 * m) : czero();
+}
+__device__ __forceinline__ cplx s1dzt_at(const cplx* y, int m, int N) {
+  cplx v = (m >= 1) ? cscale(y[m - 1], 2.0) : czero();
+  if (m >= 3) v = csub(v, cscale(y[m - 3], 2.0));
+  return v;
+}
+__device__ __forceinline__ cplx dz1t_at(const cplx* y, int m, int N) {
+  return (m >= 1) ? cscale(y[m - 1], 2.0 * m) : czero();
+}
+
+__device__ __forceinline__ double integ_w(int m) {  // int_0^1 T_m(2z-1) dz
+  return (m % 2 == 0) ? 1.0 / (1.0 - (double)m * m) : 0.0;
+}
+
+// Row s of (M X) and (L X) for wavenumber k.  X in ABI column slots.
+struct MLRow {
+  cplx m, l;
+};
+__device__ MLRow ml_row(const RbcDev& d, int k, const cplx* X, int s) {
+  const int N = d.N;
+  const double kx = d.kx[k], k2 = kx * kx;
+  const cplx* u = X;
+  const cplx* w = X + N;
+  const cplx* b = X + 2 * N;
+  const cplx* p = X + 3 * N;
+  const cplx* tau = X + 4 * N;
+  MLRow r{czero(), czero()};
+  if (s < 3 * N) {
+    const int f = s / N, n = s - f * N;
+    const cplx* c = X + f * N;
+    const double dif = (f == 2) ? d.ka : d.nu;
+    const cplx sc = s10_at(c, n, N);
+    r.m = sc;
+    cplx l = cadd(cscale(dzz_at(c, n, N), -dif), cscale(sc, dif * k2));
+    if (f == 0) l = cadd(l, cmul_i(cscale(s10_at(p, n, N), kx)));
+    if (f == 1) l = csub(cadd(l, s1dz_at(p, n, N)), s10_at(b, n, N));
+    if (n == N - 2) l = csub(l, cscale(tau[f], 4.0 * dif));   // lifted tau_1
+    if (n == N - 1) l = cadd(l, tau[3 + f]);                  // tau_2
+    r.l = l;
+  } else if (s < 4 * N) {
+    const int n = s - 3 * N;
+    cplx l = cadd(cmul_i(cscale(s0_at(u, n, N), kx)), dz1_at(w, n, N));
+    if (n == N - 1) l = cadd(l, tau[1]);
+    if (k == 0 && n == 0) l = cadd(l, tau[6]);
+    r.l = l;
+  } else if (s < 4 * N + 6) {
+    const int q = s - 4 * N;
+    const cplx* c = X + (q / 2) * N;
+    const bool bottom = (q % 2) == 0;
+    cplx acc = czero();
+    for (int m = 0; m < N; ++m) acc = cadd(acc, (bottom && (m & 1)) ? cscale(c[m], -1.0) : c[m]);
+    r.l = acc;
+  } else {
+    if (k == 0) {
+      cplx acc = czero();
+      for (int m = 0; m < N; m += 2) acc = cadd(acc, cscale(p[m], integ_w(m)));
+      r.l = acc;
+    } else {
+      r.l = tau[6];
+    }
+  }
+  return r;
+}
+
+// Column s of (M^H Y) and (L^H Y); Y in ABI row slots.
+__device__ MLRow mlt_col(const RbcDev& d, int k, const cplx* Y, int s) {
+  const int N = d.N;
+  const double kx = d.kx[k], k2 = kx * kx;
+  const cplx* yu = Y;
+  const cplx* yw = Y + N;
+  const cplx* yb = Y + 2 * N;
+  const cplx* yc = Y + 3 * N;
+  const cplx* ybc = Y + 4 * N;
+  MLRow r{czero(), czero()};
+  if (s < 3 * N) {
+    const int f = s / N, m = s - f * N;
+    const cplx* yf = Y + f * N;
+    const double dif = (f == 2) ? d.ka : d.nu;
+    const cplx st = s10t_at(yf, m, N);
+    r.m = st;
+    cplx l = cadd(cscale(dzzt_at(yf, m, N), -dif), cscale(st, dif * k2));
+    if (f == 0) l = cadd(l, cmul_mi(cscale(s0t_at(yc, m, N), kx)));   // (i kx S0)^H
+    if (f == 1) l = cadd(l, dz1t_at(yc, m, N));
+    if (f == 2) l = csub(l, s10t_at(yw, m, N));                        // -S10 b in w rows
+    const cplx bot = ybc[2 * f], top = ybc[2 * f + 1];
+    l = cadd(l, (m & 1) ? csub(top, bot) : cadd(top, bot));
+    r.l = l;
+  } else if (s < 4 * N) {
+    const int m = s - 3 * N;
+    cplx l = cadd(cmul_mi(cscale(s10t_at(yu, m, N), kx)), s1dzt_at(yw, m, N));
+    if (k == 0 && (m % 2 == 0)) l = cadd(l, cscale(Y[4 * N + 6], integ_w(m)));
+    r.l = l;
+  } else {
+    const int t = s - 4 * N;
+    cplx l;
+    switch (t) {
+      case 0: l = cscale(yu[N - 2], -4.0 * d.nu); break;
+      case 1: l = cadd(cscale(yw[N - 2], -4.0 * d.nu), yc[N - 1]); break;
+      case 2: l = cscale(yb[N - 2], -4.0 * d.ka); break;
+      case 3: l = yu[N - 1]; break;
+      case 4: l = yw[N - 1]; break;
+      case 5: l = yb[N - 1]; break;
+      default: l = (k == 0) ? yc[0] : Y[4 * N + 6]; break;
+    }
+    r.l = l;
+  }
+  return r;
+}
+
+// d/dz of a T series on [0,1]: 2 x the T-basis derivative by its backward recurrence
+// d[N-1] = 0, d[m] = d[m+2] + 2(m+1) c[m+1] (m >= 1), d[0] = c[1] + d[2]/2.  One thread.
+__device__ void dz_series(const cplx* c, cplx* dcf, int N) {
+  cplx dp2 = czero(), dp1 = czero();  // d[m+2], d[m+1]
+  for (int m = N - 1; m >= 0; --m) {
+    cplx dm;
+    if (m == N - 1) dm = czero();
+    else if (m >= 1) dm = cadd(dp2, cscale(c[m + 1], 2.0 * (m + 1)));
+    else dm = cadd(c[1], cscale(dp2, 0.5));
+    dcf[m] = cscale(dm, 2.0);
+    dp2 = dp1;
+    dp1 = dm;
+  }
+}
+// transpose of dz_series: e = (2 D_T)^T y
+__device__ void dz_series_t(const cplx* y, cplx* e, int N) {
+  cplx a_nm2 = czero(), a_nm1 = czero();  // A[n-2], A[n-1]
+  for (int n = 0; n < N; ++n) {
+    cplx a;
+    if (n == 0) a = czero();
+    else if (n == 1) a = cscale(y[0], 0.5);
+    else a = cadd(a_nm2, y[n - 1]);
+    e[n] = cscale(a, 4.0 * n);
+    a_nm2 = a_nm1;
+    a_nm1 = a;
+  }
+}
+
+// A x = r for wavenumber k: r in ABI row slots (LDS), result x in ABI column slots.
+// tmp: LDS scratch of S entries.  Block-wide (contains barriers).
+__device__ void rbc_solve(const RbcDev& d, int k, const cplx* r, cplx* x, cplx* tmp) {
+  const int tid = threadIdx.x, S = d.S;
+  for (int i = tid; i < S; i += blockDim.x) {
+    const int s = d.rowmap[i];
+    const cplx v = r[s];
+    tmp[i] = d.rowph[s] ? cmul_mi(v) : v;
+  }
+  __syncthreads();
+  if (tid < SPS_WAVE) band_solve_wave(fac_k(d, k), d.n, d.kl, d.uw, tmp);
+  __syncthreads();
+  for (int i = tid; i < S; i += blockDim.x) x[d.colmap[i]] = tmp[i];  // y in ABI order
+  __syncthreads();
+  for (int s = tid; s < S; s += blockDim.x) {   // x = D_c R y
+    cplx y = x[s];
+    const double rh = d.rho[s];
+    if (rh != 0.0) y = cadd(y, cscale(x[s + 2], rh));
+    tmp[s] = d.colph[s] ? cmul_i(y) : y;
+  }
+  __syncthreads();
+  for (int s = tid; s < S; s += blockDim.x) x[s] = tmp[s];
+  __syncthreads();
+}
+
+// A^H z = g: g in ABI column slots, result z in ABI row slots.
+__device__ void rbc_solve_h(const RbcDev& d, int k, const cplx* g, cplx* z, cplx* tmp) {
+  const int tid = threadIdx.x, S = d.S;
+  for (int i = tid; i < S; i += blockDim.x) {
+    const int s = d.colmap[i];
+    cplx h = g[s];
+    if (d.colph[s]) h = cmul_mi(h);
+    if (s >= 2) {
+      const double rh = d.rho[s - 2];
+      if (rh != 0.0) {
+        cplx h2 = g[s - 2];
+        if (d.colph[s - 2]) h2 = cmul_mi(h2);
+        h = cadd(h, cscale(h2, rh));
+      }
+    }
+    tmp[i] = h;
+  }
+  __syncthreads();
+  if (tid < SPS_WAVE) band_solve_t_wave(fac_k(d, k), d.n, d.kl, d.uw, tmp);
+  __syncthreads();
+  for (int i = tid; i < S; i += blockDim.x) {
+    const int s = d.rowmap[i];
+    z[s] = d.rowph[s] ? cmul_i(tmp[i]) : tmp[i];
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------- per-wavenumber forward kernel
+enum KfMode { KF_ZGRID = 0, KF_STAGE1 = 1, KF_STAGE2 = 2, KF_EVALF = 3, KF_SOLVE = 4 };
+
+struct KfArgs {
+  const cplx* X0;     // stage-0 state (ABI layout)
+  const cplx* X1;     // stage-1 state
+  cplx* Xout;         // new state (or F for KF_EVALF)
+  const cplx* nl;     // [3][Ngz][K] nonlinear terms in x-spectral, z-grid form
+  cplx* F0;           // [K][3][N] S10 N-hat of stage 0
+  cplx* zg;           // [6][Ngz][K] output x-spectral z-grid fields (may be null)
+  double dt, g, dl;   // dt, gamma, delta
+  int mode;
+};
+
+__global__ void __launch_bounds__(NT) rbc_kfwd(RbcDev d, KfArgs a) {
+  extern __shared__ double smem_d[];
+  cplx* sm = reinterpret_cast<cplx*>(smem_d);
+  const int k = blockIdx.x, tid = threadIdx.x;
+  const int N = d.N, S = d.S, K = d.K, Ngz = d.Ngz;
+  cplx* xa = sm;               // S : stage-0 state / solution
+  cplx* xb = xa + S;           // S : stage-1 state
+  cplx* rr = xb + S;           // S : right-hand side
+  cplx* tmp = rr + S;          // S
+  cplx* nlz = tmp + S;         // 3*Ngz
+  cplx* nh = nlz + 3 * Ngz;    // 3*N  (N-hat, then S10 N-hat)
+  cplx* fr = nh + 3 * N;       // 3*N
+  cplx* cf = fr + 3 * N;       // 6*N  coefficient fields for the backward transform
+  const int mode = a.mode;
+
+  if (mode == KF_STAGE1 || mode == KF_STAGE2 || mode == KF_EVALF) {
+    for (int e = tid; e < 3 * Ngz; e += NT) nlz[e] = a.nl[(size_t)e * K + k];
+    __syncthreads();
+    // Chebyshev forward transform (truncating) of the three nonlinear terms
+    for (int e = tid; e < 3 * N; e += NT) {
+      const int f = e / N, n = e - f * N;
+      double sr = 0.0, si = 0.0;
+      const cplx* v = nlz + f * Ngz;
+      for (int j = 0; j < Ngz; ++j) {
+        const double c = d.Cf_nj[n * Ngz + j];
+        sr += c * v[j].x;
+        si += c * v[j].y;
+      }
+      nh[e] = cmk(sr, si);
+    }
+    __syncthreads();
+    for (int e = tid; e < 3 * N; e += NT) {
+      const int f = e / N, n = e - f * N;
+      fr[e] = s10_at(nh + f * N, n, N);
+    }
+    __syncthreads();
+  }
+  if (mode == KF_EVALF) {
+    for (int s = tid; s < S; s += NT) {
+      cplx v = (s < 3 * N) ? fr[s] : czero();
+      if (k == 0 && s == 4 * N + 4) v = cadd(v, cmk(1.0, 0.0));
+      a.Xout[(size_t)k * S + s] = v;
+    }
+    return;
+  }
+  if (mode == KF_STAGE1) {
+    for (int e = tid; e < 3 * N; e += NT) a.F0[(size_t)k * 3 * N + e] = fr[e];
+  }
+  if (mode == KF_STAGE1 || mode == KF_STAGE2 || mode == KF_ZGRID) {
+    for (int s = tid; s < S; s += NT) xa[s] = a.X0[(size_t)k * S + s];
+  }
+  if (mode == KF_STAGE2) {
+    for (int s = tid; s < S; s += NT) xb[s] = a.X1[(size_t)k * S + s];
+  }
+  if (mode == KF_SOLVE) {
+    for (int s = tid; s < S; s += NT) rr[s] = a.X0[(size_t)k * S + s];
+  }
+  __syncthreads();
+
+  if (mode == KF_STAGE1 || mode == KF_STAGE2) {
+    const double dt = a.dt, g = a.g, dl = a.dl;
+    for (int s = tid; s < S; s += NT) {
+      const MLRow r0 = ml_row(d, k, xa, s);
+      const bool bc0 = (k == 0 && s == 4 * N + 4);
+      cplx f0 = (s < 3 * N) ? ((mode == KF_STAGE1) ? fr[s] : a.F0[(size_t)k * 3 * N + s]) : czero();
+      if (bc0) f0 = cadd(f0, cmk(1.0, 0.0));
+      cplx rhs;
+      if (mode == KF_STAGE1) {
+        rhs = cadd(r0.m, cscale(f0, dt * g));
+      } else {
+        cplx f1 = (s < 3 * N) ? fr[s] : czero();
+        if (bc0) f1 = cadd(f1, cmk(1.0, 0.0));
+        const MLRow r1 = ml_row(d, k, xb, s);
+        cplx comb = cadd(cscale(f0, dl), cscale(f1, 1.0 - dl));
+        comb = csub(comb, cscale(r1.l, 1.0 - g));
+        rhs = cadd(r0.m, cscale(comb, dt));
+      }
+      rr[s] = rhs;
+    }
+    __syncthreads();
+  }
+  if (mode != KF_ZGRID) {
+    rbc_solve(d, k, rr, xa, tmp);   // xa <- solution
+    for (int s = tid; s < S; s += NT) a.Xout[(size_t)k * S + s] = xa[s];
+    if (mode == KF_STAGE2 && tid < SPS_WAVE) {
+      int bad = 0;
+      for (int s = tid; s < S; s += SPS_WAVE) bad |= !(isfinite(xa[s].x) && isfinite(xa[s].y));
+      if (__any(bad) && tid == 0) atomicOr(d.err, 2);
+    }
+  }
+  if (a.zg == nullptr || mode == KF_SOLVE) return;
+  // backward Chebyshev transforms of u, w, b and their z-derivatives
+  for (int e = tid; e < 3 * N; e += NT) cf[e] = xa[e];
+  __syncthreads();
+  if (tid < 3) dz_series(xa + tid * N, cf + (3 + tid) * N, N);
+  __syncthreads();
+  for (int e = tid; e < 6 * Ngz; e += NT) {
+    const int f = e / Ngz, j = e - f * Ngz;
+    const cplx* c = cf + f * N;
+    double sr = 0.0, si = 0.0;
+    for (int n = 0; n < N; ++n) {
+      const double t = d.Cb_jn[j * N + n];
+      sr += t * c[n].x;
+      si += t * c[n].y;
+    }
+    a.zg[(size_t)e * K + k] = cmk(sr, si);
+  }
+}
+
+// ---------------------------------------------------------------------------- grid-row kernels
+// Hermitian packing of two half spectra U, V (K modes) into one length-n complex spectrum
+// whose inverse DFT is u + i v (u, v real).  scale multiplies modes m >= 1.
+__device__ __forceinline__ cplx pack_pair(const cplx* U, const cplx* V, int m, int n, int K, double scale) {
+  if (m == 0) return cmk(U[0].x, V ? V[0].x : 0.0);
+  if (m < K) {
+    const cplx u = U[m], v = V ? V[m] : czero();
+    return cscale(cmk(u.x - v.y, u.y + v.x), scale);
+  }
+  if (m > n - K) {
+    const int q = n - m;
+    const cplx u = U[q], v = V ? V[q] : czero();
+    return cscale(cmk(u.x + v.y, v.x - u.y), scale);
+  }
+  return czero();
+}
+
+struct XfArgs {
+  const cplx* zg;   // [6][Ngz][K] u, w, b, uz, wz, bz
+  cplx* nl;         // [3][Ngz][K]
+};
+
+__global__ void __launch_bounds__(NT) rbc_xfwd(RbcDev d, XfArgs a) {
+  extern __shared__ double smem_d[];
+  cplx* sm = reinterpret_cast<cplx*>(smem_d);
+  const int j = blockIdx.x, tid = threadIdx.x;
+  const int K = d.K, Ngx = d.Ngx, Ngz = d.Ngz;
+  cplx* spec = sm;                 // 9*K : u w b uz wz bz ux wx bx
+  cplx* buf0 = spec + 9 * K;       // 4*Ngx
+  cplx* buf1 = buf0 + 4 * Ngx;     // 4*Ngx
+  for (int e = tid; e < 6 * K; e += NT) {
+    const int f = e / K, m = e - f * K;
+    spec[e] = a.zg[((size_t)f * Ngz + j) * K + m];
+  }
+  __syncthreads();
+  for (int e = tid; e < 3 * K; e += NT) {
+    const int f = e / K, m = e - f * K;
+    spec[(6 + f) * K + m] = cscale(cmul_i(spec[f * K + m]), d.kx[m]);
+  }
+  __syncthreads();
+  // pairs: (u, w), (ux, uz), (wx, wz), (bx, bz)
+  const int pu[4] = {0, 6, 7, 8};
+  const int pv[4] = {1, 3, 4, 5};
+  for (int e = tid; e < 4 * Ngx; e += NT) {
+    const int q = e / Ngx, m = e - q * Ngx;
+    const cplx* U = spec + pu[q] * K;
+    const cplx* V = spec + pv[q] * K;
+    buf0[e] = pack_pair(U, V, m, Ngx, K, 1.0);
+  }
+  __syncthreads();
+  cplx* g = lds_fft(buf0, buf1, d.px, d.twx, +1, 4, Ngx, tid, NT);
+  cplx* o = (g == buf0) ? buf1 : buf0;
+  for (int x = tid; x < Ngx; x += NT) {
+    const double u = g[x].x, w = g[x].y;
+    const double ux = g[Ngx + x].x, uz = g[Ngx + x].y;
+    const double wx = g[2 * Ngx + x].x, wz = g[2 * Ngx + x].y;
+    const double bx = g[3 * Ngx + x].x, bz = g[3 * Ngx + x].y;
+    const double Nu = -(u * ux + w * uz);
+    const double Nw = -(u * wx + w * wz);
+    const double Nb = -(u * bx + w * bz);
+    o[x] = cmk(Nu, Nw);
+    o[Ngx + x] = cmk(Nb, 0.0);
+  }
+  __syncthreads();
+  cplx* h = lds_fft(o, g, d.px, d.twx, -1, 2, Ngx, tid, NT);
+  const double inv = 1.0 / Ngx;
+  for (int e = tid; e < 3 * K; e += NT) {
+    const int f = e / K, m = e - f * K;
+    const cplx* Z = h + (f == 2 ? Ngx : 0);
+    const cplx zm = Z[m], zq = Z[(Ngx - m) % Ngx];
+    cplx c;
+    if (f == 0) c = cmk(0.5 * (zm.x + zq.x), 0.5 * (zm.y - zq.y));
+    else if (f == 1) c = cmk(0.5 * (zm.y + zq.y), -0.5 * (zm.x - zq.x));
+    else c = cmk(0.5 * (zm.x + zq.x), 0.5 * (zm.y - zq.y));
+    a.nl[((size_t)f * Ngz + j) * K + m] = cscale(c, inv);
+  }
+}
+
+struct XaArgs {
+  const cplx* nlbar;  // [3][Ngz][K] cotangents of the x-spectra of N_u, N_w, N_b
+  const cplx* zg;     // [6][Ngz][K] primal fields of the stage
+  cplx* zbar;         // [6][Ngz][K] cotangents of u, w, b, uz, wz, bz x-spectra
+};
+
+__global__ void __launch_bounds__(NT) rbc_xadj(RbcDev d, XaArgs a) {
+  extern __shared__ double smem_d[];
+  cplx* sm = reinterpret_cast<cplx*>(smem_d);
+  const int j = blockIdx.x, tid = threadIdx.x;
+  const int K = d.K, Ngx = d.Ngx, Ngz = d.Ngz;
+  cplx* spec = sm;                  // 12*K: u w b uz wz bz ux wx bx | nub nwb nbb
+  cplx* buf0 = spec + 12 * K;       // 6*Ngx
+  cplx* buf1 = buf0 + 6 * Ngx;      // 6*Ngx
+  for (int e = tid; e < 6 * K; e += NT) {
+    const int f = e / K, m = e - f * K;
+    spec[e] = a.zg[((size_t)f * Ngz + j) * K + m];
+  }
+  for (int e = tid; e < 3 * K; e += NT) {
+    const int f = e / K, m = e - f * K;
+    spec[(9 + f) * K + m] = a.nlbar[((size_t)f * Ngz + j) * K + m];
+  }
+  __syncthreads();
+  for (int e = tid; e < 3 * K; e += NT) {
+    const int f = e / K, m = e - f * K;
+    spec[(6 + f) * K + m] = cscale(cmul_i(spec[f * K + m]), d.kx[m]);
+  }
+  __syncthreads();
+  // buffers 0..3: primal pairs; 4: (Nu_bar, Nw_bar) with halved m >= 1 weights; 5: (Nb_bar, 0)
+  const int pu[6] = {0, 6, 7, 8, 9, 11};
+  const int pv[6] = {1, 3, 4, 5, 10, -1};
+  for (int e = tid; e < 6 * Ngx; e += NT) {
+    const int q = e / Ngx, m = e - q * Ngx;
+    const cplx* U = spec + pu[q] * K;
+    const cplx* V = (pv[q] >= 0) ? spec + pv[q] * K : nullptr;
+    buf0[e] = pack_pair(U, V, m, Ngx, K, q >= 4 ? 0.5 : 1.0);
+  }
+  __syncthreads();
+  cplx* g = lds_fft(buf0, buf1, d.px, d.twx, +1, 6, Ngx, tid, NT);
+  cplx* o = (g == buf0) ? buf1 : buf0;
+  const double inv = 1.0 / Ngx;
+  for (int x = tid; x < Ngx; x += NT) {
+    const double u = g[x].x, w = g[x].y;
+    const double ux = g[Ngx + x].x, uz = g[Ngx + x].y;
+    const double wx = g[2 * Ngx + x].x, wz = g[2 * Ngx + x].y;
+    const double bx = g[3 * Ngx + x].x, bz = g[3 * Ngx + x].y;
+    const double Nub = g[4 * Ngx + x].x * inv, Nwb = g[4 * Ngx + x].y * inv;
+    const double Nbb = g[5 * Ngx + x].x * inv;
+    const double ub = -(Nub * ux + Nwb * wx + Nbb * bx);
+    const double wb = -(Nub * uz + Nwb * wz + Nbb * bz);
+    o[x] = cmk(ub, wb);
+    o[Ngx + x] = cmk(-Nub * u, -Nub * w);          // ux_bar, uz_bar
+    o[2 * Ngx + x] = cmk(-Nwb * u, -Nwb * w);      // wx_bar, wz_bar
+    o[3 * Ngx + x] = cmk(-Nbb * u, -Nbb * w);      // bx_bar, bz_bar
+  }
+  __syncthreads();
+  cplx* h = lds_fft(o, g, d.px, d.twx, -1, 4, Ngx, tid, NT);
+  // unpack: A_m = (Z_m + conj Z_-m)/2, B_m = (Z_m - conj Z_-m)/(2i); weight 1 at m = 0, 2 else
+  for (int e = tid; e < 3 * K; e += NT) {
+    const int f = e / K, m = e - f * K;
+    const double wgt = (m == 0) ? 1.0 : 2.0;
+    const double kx = d.kx[m];
+    auto unpack = [&](int q, cplx& A, cplx& B) {
+      const cplx zm = h[q * Ngx + m], zq = h[q * Ngx + (Ngx - m) % Ngx];
+      A = cscale(cmk(0.5 * (zm.x + zq.x), 0.5 * (zm.y - zq.y)), wgt);
+      B = cscale(cmk(0.5 * (zm.y + zq.y), -0.5 * (zm.x - zq.x)), wgt);
+    };
+    cplx A0, B0, Ad, Bd;
+    unpack(0, A0, B0);        // u_bar, w_bar
+    unpack(1 + f, Ad, Bd);    // (ux_bar, uz_bar) / (wx_bar, wz_bar) / (bx_bar, bz_bar)
+    // x-derivative transposed: conj(i kx) = -i kx
+    const cplx dxt = cscale(cmul_mi(Ad), kx);
+    cplx base = (f == 0) ? A0 : (f == 1 ? B0 : czero());
+    a.zbar[((size_t)f * Ngz + j) * K + m] = cadd(base, dxt);
+    a.zbar[((size_t)(3 + f) * Ngz + j) * K + m] = Bd;
+  }
+}
+
+// ---------------------------------------------------------------------------- per-wavenumber adjoint kernel
+enum KaFlags { KA_C = 1, KA_A = 2, KA_B = 4, KA_G = 8, KA_SOLVE_T = 16 };
+
+struct KaArgs {
+  const cplx* zbar;   // [6][Ngz][K]
+  const cplx* Xb_in;  // cotangent of the step's final state (KA_A without KA_C) or F-bar (KA_G) or rhs (KA_SOLVE_T)
+  cplx* Xb_out;       // cotangent of the step's initial state (KA_C) or solution (KA_SOLVE_T)
+  cplx* acc;          // [K][S] M^H (Y1 + Y2)
+  cplx* Ybuf;         // [K][S] Y2
+  cplx* nlbar;        // [3][Ngz][K]
+  double dt, g, dl;
+  int flags;
+};
+
+// c_bar for u, w, b from zbar (adjoint Chebyshev backward transform + derivative transposes)
+__device__ void zbar_to_coeffs(const RbcDev& d, const KaArgs& a, int k, cplx* zb, cplx* cb, cplx* out) {
+  const int tid = threadIdx.x, N = d.N, Ngz = d.Ngz, K = d.K;
+  for (int e = tid; e < 6 * Ngz; e += NT) zb[e] = a.zbar[(size_t)e * K + k];
+  __syncthreads();
+  for (int e = tid; e < 6 * N; e += NT) {
+    const int f = e / N, n = e - f * N;
+    const cplx* v = zb + f * Ngz;
+    double sr = 0.0, si = 0.0;
+    for (int j = 0; j < Ngz; ++j) {
+      const double t = d.Cb_nj[n * Ngz + j];
+      sr += t * v[j].x;
+      si += t * v[j].y;
+    }
+    cb[e] = cmk(sr, si);
+  }
+  __syncthreads();
+  if (tid < 3) dz_series_t(cb + (3 + tid) * N, out + tid * N, N);
+  __syncthreads();
+  for (int e = tid; e < 3 * N; e += NT) out[e] = cadd(out[e], cb[e]);
+  __syncthreads();
+}
+
+// cotangent G (ABI rows) of F -> nlbar (S10^T then adjoint Chebyshev forward transform)
+__device__ void g_to_nlbar(const RbcDev& d, const KaArgs& a, int k, const cplx* G, cplx* nhb) {
+  const int tid = threadIdx.x, N = d.N, Ngz = d.Ngz, K = d.K;
+  for (int e = tid; e < 3 * N; e += NT) {
+    const int f = e / N, m = e - f * N;
+    nhb[e] = s10t_at(G + f * N, m, N);
+  }
+  __syncthreads();
+  for (int e = tid; e < 3 * Ngz; e += NT) {
+    const int f = e / Ngz, j = e - f * Ngz;
+    const cplx* c = nhb + f * N;
+    double sr = 0.0, si = 0.0;
+    for (int n = 0; n < N; ++n) {
+      const double t = d.Cf_jn[j * N + n];
+      sr += t * c[n].x;
+      si += t * c[n].y;
+    }
+    a.nlbar[(size_t)e * K + k] = cmk(sr, si);
+  }
+}
+
+__global__ void __launch_bounds__(NT) rbc_kadj(RbcDev d, KaArgs a) {
+  extern __shared__ double smem_d[];
+  cplx* sm = reinterpret_cast<cplx*>(smem_d);
+  const int k = blockIdx.x, tid = threadIdx.x;
+  const int N = d.N, S = d.S, Ngz = d.Ngz;
+  cplx* xb = sm;               // S  cotangent of a state
+  cplx* y2 = xb + S;           // S
+  cplx* y1 = y2 + S;           // S
+  cplx* tmp = y1 + S;          // S
+  cplx* gg = tmp + S;          // S  cotangent of F (rows)
+  cplx* zb = gg + S;           // 6*Ngz
+  cplx* cb = zb + 6 * Ngz;     // 6*N
+  cplx* vv = cb + 6 * N;       // 3*N
+  const int fl = a.flags;
+  const double dt = a.dt, g = a.g, dl = a.dl;
+
+  if (fl & KA_SOLVE_T) {
+    for (int s = tid; s < S; s += NT) xb[s] = a.Xb_in[(size_t)k * S + s];
+    __syncthreads();
+    rbc_solve_h(d, k, xb, y1, tmp);
+    for (int s = tid; s < S; s += NT) a.Xb_out[(size_t)k * S + s] = y1[s];
+    return;
+  }
+  if (fl & KA_G) {
+    for (int s = tid; s < S; s += NT) gg[s] = a.Xb_in[(size_t)k * S + s];
+    __syncthreads();
+    g_to_nlbar(d, a, k, gg, cb);
+    return;
+  }
+  if (fl & KA_C) {
+    zbar_to_coeffs(d, a, k, zb, cb, vv);
+    for (int s = tid; s < S; s += NT) {
+      cplx v = a.acc ? a.acc[(size_t)k * S + s] : czero();
+      if (s < 3 * N) v = cadd(v, vv[s]);
+      xb[s] = v;
+    }
+    __syncthreads();
+    if (!(fl & KA_A)) {
+      for (int s = tid; s < S; s += NT) a.Xb_out[(size_t)k * S + s] = xb[s];
+      return;
+    }
+  } else if (fl & KA_A) {
+    for (int s = tid; s < S; s += NT) xb[s] = a.Xb_in[(size_t)k * S + s];
+    __syncthreads();
+  }
+  if (fl & KA_A) {
+    rbc_solve_h(d, k, xb, y2, tmp);
+    for (int s = tid; s < S; s += NT) {
+      a.Ybuf[(size_t)k * S + s] = y2[s];
+      gg[s] = cscale(y2[s], dt * (1.0 - dl));
+    }
+    __syncthreads();
+    g_to_nlbar(d, a, k, gg, cb);
+    return;
+  }
+  if (fl & KA_B) {
+    zbar_to_coeffs(d, a, k, zb, cb, vv);
+    for (int s = tid; s < S; s += NT) y2[s] = a.Ybuf[(size_t)k * S + s];
+    __syncthreads();
+    for (int s = tid; s < S; s += NT) {
+      const MLRow t = mlt_col(d, k, y2, s);
+      cplx v = cscale(t.l, -dt * (1.0 - g));
+      if (s < 3 * N) v = cadd(v, vv[s]);
+      xb[s] = v;
+    }
+    __syncthreads();
+    rbc_solve_h(d, k, xb, y1, tmp);
+    for (int s = tid; s < S; s += NT) tmp[s] = cadd(y1[s], y2[s]);
+    __syncthreads();
+    for (int s = tid; s < S; s += NT) {
+      const MLRow t = mlt_col(d, k, tmp, s);
+      a.acc[(size_t)k * S + s] = t.m;
+      gg[s] = cadd(cscale(y2[s], dt * dl), cscale(y1[s], dt * g));
+    }
+    __syncthreads();
+    g_to_nlbar(d, a, k, gg, cb);
+  }
+}
+
+// ---------------------------------------------------------------------------- factor
+__global__ void __launch_bounds__(NT) rbc_factor(RbcDev d, const double* BM, const double* BL, double am,
+                                                 double bl, double* Lc, double* Uc, double* Ur, int* piv) {
+  extern __shared__ double smem_d[];
+  __shared__ int sh[4];
+  const int k = blockIdx.x;
+  const size_t bw = d.kl + d.ku + 1;
+  band_factor_block(BM + (size_t)k * d.n * bw, BL + (size_t)k * d.n * bw, am, bl, d.n, d.kl, d.ku, smem_d,
+                    sh, Lc + (size_t)k * d.n * d.kl, Uc + (size_t)k * d.n * d.uw, Ur + (size_t)k * d.n * d.uw,
+                    piv + (size_t)k * d.n, d.err);
+}
+
+// ---------------------------------------------------------------------------- initial state and its adjoint
+// x pass: one block per scale-1 z node; b0 laid out [x][z].
+__global__ void __launch_bounds__(NT) rbc_init_x(RbcDev d, const double* grid, cplx* tmp) {
+  extern __shared__ double smem_d[];
+  cplx* sm = reinterpret_cast<cplx*>(smem_d);
+  const int zi = blockIdx.x, tid = threadIdx.x, n = d.Nx1, K = d.K;
+  cplx* b0 = sm;
+  cplx* b1 = sm + n;
+  for (int x = tid; x < n; x += NT) b0[x] = cmk(grid[(size_t)x * d.Nz1 + zi], 0.0);
+  __syncthreads();
+  cplx* h = lds_fft(b0, b1, d.px1, d.twx1, -1, 1, n, tid, NT);
+  for (int m = tid; m < K; m += NT) tmp[(size_t)zi * K + m] = cscale(h[m], 1.0 / n);
+}
+
+__global__ void __launch_bounds__(NT) rbc_init_z(RbcDev d, const cplx* tmp, cplx* X) {
+  const int k = blockIdx.x, tid = threadIdx.x, N = d.N, S = d.S, K = d.K, Nz1 = d.Nz1;
+  for (int s = tid; s < S; s += NT) {
+    cplx v = czero();
+    if (s >= 2 * N && s < 3 * N) {
+      const int n = s - 2 * N;
+      double sr = 0.0, si = 0.0;
+      for (int z = 0; z < Nz1; ++z) {
+        const double c = d.C1f_nj[n * Nz1 + z];
+        const cplx t = tmp[(size_t)z * K + k];
+        sr += c * t.x;
+        si += c * t.y;
+      }
+      v = cmk(sr, si);
+    }
+    X[(size_t)k * S + s] = v;
+  }
+}
+
+__global__ void __launch_bounds__(NT) rbc_init_adj_z(RbcDev d, const cplx* Xb, cplx* tmp) {
+  const int k = blockIdx.x, tid = threadIdx.x, N = d.N, S = d.S, K = d.K, Nz1 = d.Nz1;
+  for (int z = tid; z < Nz1; z += NT) {
+    double sr = 0.0, si = 0.0;
+    for (int n = 0; n < N; ++n) {
+      const double c = d.C1f_jn[z * N + n];
+      const cplx v = Xb[(size_t)k * S + 2 * N + n];
+      sr += c * v.x;
+      si += c * v.y;
+    }
+    tmp[(size_t)z * K + k] = cmk(sr, si);
+  }
+}
+
+__global__ void __launch_bounds__(NT) rbc_init_adj_x(RbcDev d, const cplx* tmp, double* gbar) {
+  extern __shared__ double smem_d[];
+  cplx* sm = reinterpret_cast<cplx*>(smem_d);
+  const int zi = blockIdx.x, tid = threadIdx.x, n = d.Nx1, K = d.K;
+  cplx* b0 = sm;
+  cplx* b1 = sm + n;
+  const cplx* t = tmp + (size_t)zi * K;
+  for (int m = tid; m < n; m += NT) {
+    cplx v = czero();
+    if (m == 0) v = cmk(t[0].x, 0.0);
+    else if (m < K) v = cscale(t[m], 0.5);
+    else if (m > n - K) v = cscale(cconj(t[n - m]), 0.5);
+    b0[m] = v;
+  }
+  __syncthreads();
+  cplx* h = lds_fft(b0, b1, d.px1, d.twx1, +1, 1, n, tid, NT);
+  for (int x = tid; x < n; x += NT) gbar[(size_t)x * d.Nz1 + zi] = h[x].x / n;
+}
+
+// ---------------------------------------------------------------------------- cost
+__global__ void __launch_bounds__(NT) rbc_cost(RbcDev d, const cplx* X, cplx* Xb, double* Jpart) {
+  __shared__ double red[NT];
+  __shared__ cplx cu[128], cw[128];
+  const int k = blockIdx.x, tid = threadIdx.x, N = d.N, S = d.S;
+  const double wk = (k == 0) ? 1.0 : 2.0;
+  for (int n = tid; n < N; n += NT) {
+    cplx a = X[(size_t)k * S + n], b = X[(size_t)k * S + N + n];
+    if (k == 0) { a.y = 0.0; b.y = 0.0; }
+    cu[n] = a;
+    cw[n] = b;
+  }
+  __syncthreads();
+  double part = 0.0;
+  for (int s = tid; s < S; s += NT) {
+    cplx v = czero();
+    if (s < 2 * N) {
+      const cplx* c = (s < N) ? cu : cw;
+      const int m = (s < N) ? s : s - N;
+      double gr = 0.0, gi = 0.0;
+      for (int n = 0; n < N; ++n) {
+        const double G = d.gram[m * N + n];
+        gr += G * c[n].x;
+        gi += G * c[n].y;
+      }
+      part += c[m].x * gr + c[m].y * gi;   // Re(conj(c_m) (G c)_m)
+      v = cmk(d.Lx * wk * gr, d.Lx * wk * gi);
+      if (k == 0) v.y = 0.0;
+    }
+    Xb[(size_t)k * S + s] = v;
+  }
+  red[tid] = part;
+  __syncthreads();
+  for (int o = NT / 2; o > 0; o >>= 1) {
+    if (tid < o) red[tid] += red[tid + o];
+    __syncthreads();
+  }
+  if (tid == 0) Jpart[k] = 0.5 * d.Lx * wk * red[0];
+}
+
+__global__ void sum_parts(const double* part, int n, double* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += part[i];
+    *out = s;
+  }
+}
+
+// ---------------------------------------------------------------------------- host: operators
+struct Cmat {
+  int n;
+  std::vector<double2> a;
+  explicit Cmat(int n_) : n(n_), a((size_t)n_ * n_, make_double2(0.0, 0.0)) {}
+  double2& at(int i, int j) { return a[(size_t)i * n + j]; }
+  void add(int i, int j, double re, double im = 0.0) {
+    at(i, j).x += re;
+    at(i, j).y += im;
+  }
+};
+
+// Dense N x N matrices of the ultraspherical operators (column n = image of basis n).
+static std::vector<double> op_S0(int N) {
+  std::vector<double> S((size_t)N * N, 0.0);
+  for (int n = 0; n < N; ++n) {
+    S[(size_t)n * N + n] = (n == 0) ? 1.0 : 0.5;
+    if (n >= 2) S[(size_t)(n - 2) * N + n] = -0.5;
+  }
+  return S;
+}
+static std::vector<double> op_S1(int N) {
+  std::vector<double> S((size_t)N * N, 0.0);
+  for (int n = 0; n < N; ++n) {
+    S[(size_t)n * N + n] = 1.0 / (n + 1);
+    if (n >= 2) S[(size_t)(n - 2) * N + n] = -1.0 / (n + 1);
+  }
+  return S;
+}
+static std::vector<double> op_D(int N, double v, bool scaled_by_index) {  // D[n-1][n]
+  std::vector<double> D((size_t)N * N, 0.0);
+  for (int n = 1; n < N; ++n) D[(size_t)(n - 1) * N + n] = scaled_by_index ? v * n : v;
+  return D;
+}
+static std::vector<double> matmul(const std::vector<double>& A, const std::vector<double>& B, int N) {
+  std::vector<double> C((size_t)N * N, 0.0);
+  for (int i = 0; i < N; ++i)
+    for (int k = 0; k < N; ++k) {
+      const double a = A[(size_t)i * N + k];
+      if (a == 0.0) continue;
+      for (int j = 0; j < N; ++j) C[(size_t)i * N + j] += a * B[(size_t)k * N + j];
+    }
+  return C;
+}
+
+// ---------------------------------------------------------------------------- host: banded systems
+struct RbcHostBands {
+  int kl = 0, ku = 0;
+  std::vector<double> BM, BL;   // [K][S][kl+ku+1] row bands of D_r M R D_c and D_r L R D_c
+  std::vector<int> rowmap, colmap;
+  std::vector<signed char> rowph, colph;
+  std::vector<double> rho;
+};
+
+// ABI-slot dense M_k, L_k (complex), written from the formulation of the header comment.
+static void rbc_assemble(const sps_desc& desc, int k, Cmat& M, Cmat& L) {
+  const int N = desc.nz;
+  const double kx = 2.0 * M_PI * k / desc.lx, k2 = kx * kx;
+  const double nu = std::pow(desc.param0 / desc.param1, -0.5), ka = std::pow(desc.param0 * desc.param1, -0.5);
+  const std::vector<double> S0 = op_S0(N), S1 = op_S1(N);
+  const std::vector<double> S10 = matmul(S1, S0, N);
+  const std::vector<double> D0 = op_D(N, 1.0, true), D1 = op_D(N, 2.0, false);
+  const std::vector<double> D10 = matmul(D1, D0, N);
+  const std::vector<double> S1D0 = matmul(S1, D0, N);
+  const int U = 0, W = N, B = 2 * N, P = 3 * N, T = 4 * N;
+  const double difs[3] = {nu, nu, ka};
+  for (int f = 0; f < 3; ++f) {
+    const int r0 = f * N, c0 = f * N;
+    const double dif = difs[f];
+    for (int i = 0; i < N; ++i)
+      for (int j = 0; j < N; ++j) {
+        const double s10 = S10[(size_t)i * N + j], dzz = 4.0 * D10[(size_t)i * N + j];
+        if (s10 != 0.0) M.add(r0 + i, c0 + j, s10);
+        const double lv = -dif * (dzz - k2 * s10);
+        if (lv != 0.0) L.add(r0 + i, c0 + j, lv);
+      }
+    L.add(r0 + N - 2, T + f, -4.0 * dif);   // lifted first-order tau
+    L.add(r0 + N - 1, T + 3 + f, 1.0);      // second tau
+  }
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      const double s10 = S10[(size_t)i * N + j];
+      if (s10 != 0.0) {
+        L.add(U + i, P + j, 0.0, kx * s10);   // i kx S10 p in x-momentum
+        L.add(W + i, B + j, -s10);            // -b in z-momentum
+      }
+      const double sd = 2.0 * S1D0[(size_t)i * N + j];
+      if (sd != 0.0) L.add(W + i, P + j, sd);   // dp/dz in z-momentum
+      const double s0 = S0[(size_t)i * N + j];
+      if (s0 != 0.0) L.add(P + i, U + j, 0.0, kx * s0);   // continuity i kx u
+      const double d0 = 2.0 * D0[(size_t)i * N + j];
+      if (d0 != 0.0) L.add(P + i, W + j, d0);             // continuity dw/dz
+    }
+  L.add(P + N - 1, T + 1, 1.0);  // lift(tau_w1) in continuity
+  for (int f = 0; f < 3; ++f)
+    for (int m = 0; m < N; ++m) {
+      L.add(T + 2 * f, f * N + m, (m & 1) ? -1.0 : 1.0);   // value at z = 0
+      L.add(T + 2 * f + 1, f * N + m, 1.0);                // value at z = 1
+    }
+  if (k == 0) {
+    L.add(P + 0, T + 6, 1.0);
+    for (int m = 0; m < N; m += 2) L.add(T + 6, P + m, 1.0 / (1.0 - (double)m * m));
+  } else {
+    L.add(T + 6, T + 6, 1.0);
+  }
+}
+
+
+void rbc_host_bands(const sps_desc& desc, RbcHostBands& hb) {
+  const int N = desc.nz, S = 4 * N + 7, K = desc.nx / 2;
+  // phases and recombination
+  std::vector<signed char> rowph(S, 0), colph(S, 0);
+  for (int i = 0; i < N; ++i) rowph[i] = 1;
+  rowph[4 * N + 0] = rowph[4 * N + 1] = 1;   // u boundary rows
+  for (int i = 0; i < N; ++i) colph[i] = 1;
+  colph[4 * N + 0] = colph[4 * N + 3] = 1;   // tau_u1, tau_u2
+  std::vector<double> rho(S, 0.0);
+  for (int f = 0; f < 3; ++f)
+    for (int m = 0; m + 2 < N; ++m) rho[f * N + m] = -1.0;
+  auto iw = [](int j) { return 1.0 / (1.0 - (double)j * j); };
+  for (int m = 0; m + 2 < N; ++m) {
+    const int j = m + 2;
+    rho[3 * N + m] = (j % 2 == 0) ? -(iw(j) / iw(j - 2)) : 0.0;
+  }
+  // interleaved orders
+  std::vector<int> rowmap, colmap;
+  rowmap.push_back(4 * N + 6);
+  for (int q = 0; q < 6; ++q) rowmap.push_back(4 * N + q);
+  for (int n = 0; n < N; ++n) {
+    rowmap.push_back(3 * N + n);
+    rowmap.push_back(n);
+    rowmap.push_back(N + n);
+    rowmap.push_back(2 * N + n);
+  }
+  colmap.push_back(4 * N + 6);
+  for (int n = 0; n < N; ++n)
+    for (int f = 0; f < 4; ++f) colmap.push_back(f * N + n);
+  for (int q = 0; q < 6; ++q) colmap.push_back(4 * N + q);
+  // B = D_r (A R) D_c per k, for A in {M, L}; find the band
+  std::vector<std::vector<double>> bm(K), bl(K);
+  int kl = 0, ku = 0;
+  auto transform = [&](Cmat& A, std::vector<double>& out) {
+    out.assign((size_t)S * S, 0.0);
+    for (int i = 0; i < S; ++i) {
+      const int r = rowmap[i];
+      double rowmax = 0.0;
+      std::vector<double2> row(S);
+      for (int j = 0; j < S; ++j) {
+        const int c = colmap[j];
+        double2 v = A.at(r, c);
+        if (c >= 2 && rho[c - 2] != 0.0) {
+          v.x += A.at(r, c - 2).x * rho[c - 2];
+          v.y += A.at(r, c - 2).y * rho[c - 2];
+        }
+        if (colph[c]) v = make_double2(-v.y, v.x);   // times i
+        if (rowph[r]) v = make_double2(v.y, -v.x);   // times -i
+        row[j] = v;
+        rowmax = std::max(rowmax, std::hypot(v.x, v.y));
+      }
+      for (int j = 0; j < S; ++j) {
+        double2 v = row[j];
+        if (std::hypot(v.x, v.y) <= 1e-14 * rowmax) continue;   // exact cancellations of R
+        if (std::fabs(v.y) > 1e-13 * rowmax) throw Error(SPS_E_ARG, "real-ified RBC block is not real");
+        out[(size_t)i * S + j] = v.x;
+        kl = std::max(kl, i - j);
+        ku = std::max(ku, j - i);
+      }
+    }
+  };
+  for (int k = 0; k < K; ++k) {
+    Cmat M(S), L(S);
+    rbc_assemble(desc, k, M, L);
+    transform(M, bm[k]);
+    transform(L, bl[k]);
+  }
+  const int bw = kl + ku + 1;
+  hb.kl = kl;
+  hb.ku = ku;
+  hb.BM.assign((size_t)K * S * bw, 0.0);
+  hb.BL.assign((size_t)K * S * bw, 0.0);
+  for (int k = 0; k < K; ++k)
+    for (int i = 0; i < S; ++i)
+      for (int j = std::max(0, i - kl); j <= std::min(S - 1, i + ku); ++j) {
+        hb.BM[((size_t)k * S + i) * bw + (j - i + kl)] = bm[k][(size_t)i * S + j];
+        hb.BL[((size_t)k * S + i) * bw + (j - i + kl)] = bl[k][(size_t)i * S + j];
+      }
+  hb.rowmap = rowmap;
+  hb.colmap = colmap;
+  hb.rowph = rowph;
+  hb.colph = colph;
+  hb.rho = rho;
+}
+
+class RbcProblem : public ProblemImpl {
+ public:
+  RbcProblem(const sps_desc& desc, hipStream_t s) : desc_(desc) {
+    stream = s;
+    SPS_REQUIRE(desc.scheme == SPS_RK222, "RBC supports the RK222 scheme");
+    SPS_REQUIRE(desc.nx >= 8 && desc.nx % 2 == 0, "nx must be even and >= 8");
+    SPS_REQUIRE(desc.nz >= 8 && desc.nz <= 128 && desc.nz % 2 == 0, "nz must be even in [8, 128]");
+    SPS_REQUIRE(desc.dealias == 1.5, "RBC uses 3/2 dealiasing");
+    SPS_REQUIRE(desc.dt > 0 && desc.checkpoint_every >= 1 && desc.max_steps >= 1, "bad dt / checkpoint / max_steps");
+    K_ = desc.nx / 2;
+    N_ = desc.nz;
+    S_ = 4 * N_ + 7;
+    Ngx_ = 3 * desc.nx / 2;
+    Ngz_ = 3 * N_ / 2;
+    SPS_REQUIRE(fft_plan(Ngx_, dv_.px.radix, &dv_.px.nst), "3/2 nx must factor into 2 and 3");
+    SPS_REQUIRE(fft_plan(desc.nx, dv_.px1.radix, &dv_.px1.nst), "nx must factor into 2 and 3");
+    dv_.px.n = Ngx_;
+    dv_.px1.n = desc.nx;
+    nu_ = std::pow(desc.param0 / desc.param1, -0.5);
+    ka_ = std::pow(desc.param0 * desc.param1, -0.5);
+    build_tables();
+    build_bands();
+    alloc_work();
+  }
+
+  long long state_size() const override { return (long long)K_ * S_ * 2; }
+
+  void factor() override {
+    if (factored_) return;
+    const double g = 1.0 - 1.0 / std::sqrt(2.0);
+    const size_t lds = (size_t)(2 * kl_ + ku_ + 1) * S_ * sizeof(double);
+    hipLaunchKernelGGL(rbc_factor, dim3(K_), dim3(NT), lds, stream, dv_, BM_, BL_, 1.0, desc_.dt * g,
+                       Lc_, Uc_, Ur_, piv_);
+    SPS_CHECK_LAUNCH();
+    factored_ = true;
+  }
+
+  void step(double* X, int nsteps) override {
+    SPS_REQUIRE(X != nullptr, "X is null");
+    SPS_REQUIRE(nsteps >= 1 && nsteps <= desc_.max_steps, "nsteps out of range");
+    factor();
+    forward(reinterpret_cast<cplx*>(X), nsteps);
+  }
+
+  void adjoint_step(double* Xbar, int nsteps) override {
+    SPS_REQUIRE(Xbar != nullptr, "Xbar is null");
+    if (tape_steps_ != nsteps) throw Error(SPS_E_STATE, "adjoint_step: nsteps does not match the recorded forward run");
+    reverse(reinterpret_cast<cplx*>(Xbar), nsteps);
+  }
+
+  void cost(const double* X, double* J, double* dJdX) override {
+    SPS_REQUIRE(X && dJdX, "null argument");
+    hipLaunchKernelGGL(rbc_cost, dim3(K_), dim3(NT), 0, stream, dv_, reinterpret_cast<const cplx*>(X),
+                       reinterpret_cast<cplx*>(dJdX), Jpart_);
+    SPS_CHECK_LAUNCH();
+    if (J) {
+      hipLaunchKernelGGL(sum_parts, dim3(1), dim3(64), 0, stream, Jpart_, K_, J);
+      SPS_CHECK_LAUNCH();
+    }
+  }
+
+  void gradient(const double* X0, int nsteps, double* XN, double* dJdX0, double* J) override {
+    SPS_REQUIRE(X0 && dJdX0, "null argument");
+    SPS_REQUIRE(nsteps >= 1 && nsteps <= desc_.max_steps, "nsteps out of range");
+    factor();
+    SPS_HIP(hipMemcpyAsync(Xg_, X0, sizeof(cplx) * K_ * S_, hipMemcpyDeviceToDevice, stream));
+    forward(Xg_, nsteps);
+    if (XN) SPS_HIP(hipMemcpyAsync(XN, Xg_, sizeof(cplx) * K_ * S_, hipMemcpyDeviceToDevice, stream));
+    cost(reinterpret_cast<const double*>(Xg_), J, dJdX0);
+    reverse(reinterpret_cast<cplx*>(dJdX0), nsteps);
+  }
+
+  void initial_state(const double* grid, double* X) override {
+    SPS_REQUIRE(grid && X, "null argument");
+    hipLaunchKernelGGL(rbc_init_x, dim3(N_), dim3(NT), 2 * desc_.nx * sizeof(cplx), stream, dv_, grid, itmp_);
+    SPS_CHECK_LAUNCH();
+    hipLaunchKernelGGL(rbc_init_z, dim3(K_), dim3(NT), 0, stream, dv_, itmp_, reinterpret_cast<cplx*>(X));
+    SPS_CHECK_LAUNCH();
+  }
+
+  void initial_state_adjoint(const double* Xbar, double* grid) override {
+    SPS_REQUIRE(grid && Xbar, "null argument");
+    hipLaunchKernelGGL(rbc_init_adj_z, dim3(K_), dim3(NT), 0, stream, dv_, reinterpret_cast<const cplx*>(Xbar), itmp_);
+    SPS_CHECK_LAUNCH();
+    hipLaunchKernelGGL(rbc_init_adj_x, dim3(N_), dim3(NT), 2 * desc_.nx * sizeof(cplx), stream, dv_, itmp_, grid);
+    SPS_CHECK_LAUNCH();
+  }
+
+  void eval_F(const double* X, double* F) override {
+    SPS_REQUIRE(X && F, "null argument");
+    launch_kf(KF_ZGRID, reinterpret_cast<const cplx*>(X), nullptr, nullptr, zgA_);
+    launch_xf(zgA_);
+    launch_kf(KF_EVALF, nullptr, nullptr, reinterpret_cast<cplx*>(F), nullptr);
+  }
+
+  void eval_F_vjp(const double* X, const double* Fbar, double* Xbar) override {
+    SPS_REQUIRE(X && Fbar && Xbar, "null argument");
+    launch_kf(KF_ZGRID, reinterpret_cast<const cplx*>(X), nullptr, nullptr, zgA_);
+    KaArgs a = ka_args(KA_G);
+    a.Xb_in = reinterpret_cast<const cplx*>(Fbar);
+    launch_ka(a);
+    launch_xa(zgA_);
+    a = ka_args(KA_C);
+    a.acc = nullptr;
+    a.Xb_out = reinterpret_cast<cplx*>(Xbar);
+    launch_ka(a);
+  }
+
+  void solve(const double* R, double* X, int adjoint) override {
+    SPS_REQUIRE(R && X, "null argument");
+    factor();
+    if (!adjoint) {
+      launch_kf(KF_SOLVE, reinterpret_cast<const cplx*>(R), nullptr, reinterpret_cast<cplx*>(X), nullptr);
+    } else {
+      KaArgs a = ka_args(KA_SOLVE_T);
+      a.Xb_in = reinterpret_cast<const cplx*>(R);
+      a.Xb_out = reinterpret_cast<cplx*>(X);
+      launch_ka(a);
+    }
+  }
+
+  void timer_enable(int kind, bool on) override {
+    SPS_REQUIRE(kind == 0, "unknown timer kind");
+    timer_.enable(on);
+  }
+  void timer_read(long long* launches, double* ms) override { timer_.read(launches, ms); }
+
+  int device_error() override {
+    int h = 0;
+    SPS_HIP(hipMemcpyAsync(&h, err_, sizeof(int), hipMemcpyDeviceToHost, stream));
+    SPS_HIP(hipStreamSynchronize(stream));
+    if (h) SPS_HIP(hipMemsetAsync(err_, 0, sizeof(int), stream));
+    return h;
+  }
+
+ private:
+  // ----------------------------------------------------------------- launches
+  size_t kf_lds() const { return sizeof(cplx) * (4 * S_ + 3 * Ngz_ + 12 * N_); }
+  size_t ka_lds() const { return sizeof(cplx) * (5 * S_ + 6 * Ngz_ + 9 * N_); }
+  size_t xf_lds() const { return sizeof(cplx) * (9 * K_ + 8 * Ngx_); }
+  size_t xa_lds() const { return sizeof(cplx) * (12 * K_ + 12 * Ngx_); }
+
+  void launch_kf(int mode, const cplx* X0, const cplx* X1, cplx* Xout, cplx* zg) {
+    KfArgs a;
+    a.X0 = X0;
+    a.X1 = X1;
+    a.Xout = Xout;
+    a.nl = nl_;
+    a.F0 = F0_;
+    a.zg = zg;
+    a.dt = desc_.dt;
+    a.g = 1.0 - 1.0 / std::sqrt(2.0);
+    a.dl = 1.0 - 1.0 / (2.0 * a.g);
+    a.mode = mode;
+    const bool timed = (mode == KF_STAGE1 || mode == KF_STAGE2);
+    if (timed) timer_.begin(stream);
+    hipLaunchKernelGGL(rbc_kfwd, dim3(K_), dim3(NT), kf_lds(), stream, dv_, a);
+    if (timed) timer_.end(stream);
+    SPS_CHECK_LAUNCH();
+  }
+  void launch_xf(const cplx* zg) {
+    XfArgs a{zg, nl_};
+    hipLaunchKernelGGL(rbc_xfwd, dim3(Ngz_), dim3(NT), xf_lds(), stream, dv_, a);
+    SPS_CHECK_LAUNCH();
+  }
+  KaArgs ka_args(int flags) {
+    KaArgs a;
+    a.zbar = zbar_;
+    a.Xb_in = nullptr;
+    a.Xb_out = nullptr;
+    a.acc = acc_;
+    a.Ybuf = Ybuf_;
+    a.nlbar = nlbar_;
+    a.dt = desc_.dt;
+    a.g = 1.0 - 1.0 / std::sqrt(2.0);
+    a.dl = 1.0 - 1.0 / (2.0 * a.g);
+    a.flags = flags;
+    return a;
+  }
+  void launch_ka(const KaArgs& a) {
+    hipLaunchKernelGGL(rbc_kadj, dim3(K_), dim3(NT), ka_lds(), stream, dv_, a);
+    SPS_CHECK_LAUNCH();
+  }
+  void launch_xa(const cplx* zg) {
+    XaArgs a{nlbar_, zg, zbar_};
+    hipLaunchKernelGGL(rbc_xadj, dim3(Ngz_), dim3(NT), xa_lds(), stream, dv_, a);
+    SPS_CHECK_LAUNCH();
+  }
+
+  cplx* slot(int s, int stage) { return seg_ + ((size_t)s * 2 + stage) * zsize_; }
+  cplx* ckpt(int c) { return ckpt_ + (size_t)c * K_ * S_; }
+
+  // One RK222 step from X (in place).  zin: x-spectral z-grid fields of X;
+  // zs1: where stage 1 writes its fields; zout: where the new state's fields go (or null).
+  void rk_step(cplx* X, const cplx* zin, cplx* zs1, cplx* zout) {
+    launch_xf(zin);
+    launch_kf(KF_STAGE1, X, nullptr, X1_, zs1);
+    launch_xf(zs1);
+    launch_kf(KF_STAGE2, X, X1_, X, zout);
+  }
+
+  void forward(cplx* X, int nsteps) {
+    const int ce = desc_.checkpoint_every;
+    const int nseg = (nsteps + ce - 1) / ce;
+    const int last0 = (nseg - 1) * ce;   // first step of the last segment: recorded now
+    // fields of step n, stage q: a single rolling buffer (kernels are stream ordered) or,
+    // inside the last segment, the segment store read back by the reverse sweep
+    auto zpos = [&](int n, int q) { return (n >= last0) ? slot(n - last0, q) : zgA_; };
+    launch_kf(KF_ZGRID, X, nullptr, nullptr, zpos(0, 0));
+    for (int n = 0; n < nsteps; ++n) {
+      if (n % ce == 0) SPS_HIP(hipMemcpyAsync(ckpt(n / ce), X, sizeof(cplx) * K_ * S_, hipMemcpyDeviceToDevice, stream));
+      rk_step(X, zpos(n, 0), zpos(n, 1), (n + 1 < nsteps) ? zpos(n + 1, 0) : nullptr);
+    }
+    tape_steps_ = nsteps;
+  }
+
+  void recompute(int seg, int len) {
+    SPS_HIP(hipMemcpyAsync(Xw_, ckpt(seg), sizeof(cplx) * K_ * S_, hipMemcpyDeviceToDevice, stream));
+    launch_kf(KF_ZGRID, Xw_, nullptr, nullptr, slot(0, 0));
+    for (int s = 0; s < len; ++s) rk_step(Xw_, slot(s, 0), slot(s, 1), (s + 1 < len) ? slot(s + 1, 0) : nullptr);
+  }
+
+  void reverse(cplx* Xbar, int nsteps) {
+    const int ce = desc_.checkpoint_every;
+    const int nseg = (nsteps + ce - 1) / ce;
+    bool first = true;
+    for (int seg = nseg - 1; seg >= 0; --seg) {
+      const int start = seg * ce;
+      const int len = std::min(ce, nsteps - start);
+      if (seg != nseg - 1) recompute(seg, len);
+      for (int s = len - 1; s >= 0; --s) {
+        KaArgs a = ka_args(first ? KA_A : (KA_C | KA_A));
+        a.Xb_in = Xbar;
+        launch_ka(a);
+        first = false;
+        launch_xa(slot(s, 1));
+        launch_ka(ka_args(KA_B));
+        launch_xa(slot(s, 0));
+      }
+    }
+    KaArgs a = ka_args(KA_C);
+    a.Xb_out = Xbar;
+    launch_ka(a);
+  }
+
+  // ----------------------------------------------------------------- tables
+  void build_tables() {
+    const int N = N_, K = K_, Ngz = Ngz_, Nz1 = desc_.nz;
+    auto Tn = [](int n, int j, int Ng) -> double {
+      // T_n at the ascending Gauss node j of Ng: cos(n * pi * (2(Ng - j) - 1) / (2 Ng)),
+      // with the integer argument reduced exactly modulo 4 Ng
+      const long long M = ((long long)n * (2LL * (Ng - j) - 1)) % (4LL * Ng);
+      return (double)cosl((long double)M * 3.14159265358979323846264338327950288L / (2.0L * Ng));
+    };
+    std::vector<double> kx(K), Cbnj((size_t)N * Ngz), Cbjn((size_t)Ngz * N), Cfjn((size_t)Ngz * N),
+        Cfnj((size_t)N * Ngz), C1fjn((size_t)Nz1 * N), C1fnj((size_t)N * Nz1);
+    for (int k = 0; k < K; ++k) kx[k] = 2.0 * M_PI * k / desc_.lx;
+    for (int n = 0; n < N; ++n)
+      for (int j = 0; j < Ngz; ++j) {
+        const double t = Tn(n, j, Ngz);
+        Cbnj[(size_t)n * Ngz + j] = t;
+        Cbjn[(size_t)j * N + n] = t;
+        const double f = (n == 0 ? 1.0 : 2.0) * t / Ngz;
+        Cfjn[(size_t)j * N + n] = f;
+        Cfnj[(size_t)n * Ngz + j] = f;
+      }
+    for (int n = 0; n < N; ++n)
+      for (int j = 0; j < Nz1; ++j) {
+        const double f = (n == 0 ? 1.0 : 2.0) * Tn(n, j, Nz1) / Nz1;
+        C1fjn[(size_t)j * N + n] = f;
+        C1fnj[(size_t)n * Nz1 + j] = f;
+      }
+    std::vector<double> gram((size_t)N * N);
+    auto I = [](int j) { return (j % 2 == 0) ? 2.0 / (1.0 - (double)j * j) : 0.0; };
+    for (int m = 0; m < N; ++m)
+      for (int n = 0; n < N; ++n) gram[(size_t)m * N + n] = 0.25 * (I(m + n) + I(std::abs(m - n)));
+    dv_.K = K;
+    dv_.N = N;
+    dv_.S = S_;
+    dv_.Ngx = Ngx_;
+    dv_.Ngz = Ngz;
+    dv_.Nx1 = desc_.nx;
+    dv_.Nz1 = Nz1;
+    dv_.Lx = desc_.lx;
+    dv_.nu = nu_;
+    dv_.ka = ka_;
+    dv_.kx = arena_.upload(kx, stream);
+    dv_.Cb_nj = arena_.upload(Cbnj, stream);
+    dv_.Cb_jn = arena_.upload(Cbjn, stream);
+    dv_.Cf_jn = arena_.upload(Cfjn, stream);
+    dv_.Cf_nj = arena_.upload(Cfnj, stream);
+    dv_.C1f_jn = arena_.upload(C1fjn, stream);
+    dv_.C1f_nj = arena_.upload(C1fnj, stream);
+    dv_.twx = arena_.upload(twiddles(Ngx_), stream);
+    dv_.twx1 = arena_.upload(twiddles(desc_.nx), stream);
+    dv_.gram = arena_.upload(gram, stream);
+  }
+
+  void build_bands() {
+    RbcHostBands hb;
+    rbc_host_bands(desc_, hb);
+    kl_ = hb.kl;
+    ku_ = hb.ku;
+    SPS_REQUIRE(kl_ + 1 <= SPS_WAVE && kl_ + ku_ + 1 <= SPS_WAVE, "band too wide for the wave solver");
+    BM_ = arena_.upload(hb.BM, stream);
+    BL_ = arena_.upload(hb.BL, stream);
+    dv_.n = S_;
+    dv_.kl = kl_;
+    dv_.ku = ku_;
+    dv_.uw = kl_ + ku_ + 1;
+    dv_.rowmap = arena_.upload(hb.rowmap, stream);
+    dv_.colmap = arena_.upload(hb.colmap, stream);
+    dv_.rowph = arena_.upload(hb.rowph, stream);
+    dv_.colph = arena_.upload(hb.colph, stream);
+    dv_.rho = arena_.upload(hb.rho, stream);
+  }
+
+  void alloc_work() {
+    const size_t st = (size_t)K_ * S_;
+    zsize_ = (size_t)6 * Ngz_ * K_;
+    Lc_ = arena_.alloc<double>((size_t)K_ * S_ * kl_);
+    Uc_ = arena_.alloc<double>((size_t)K_ * S_ * (kl_ + ku_ + 1));
+    Ur_ = arena_.alloc<double>((size_t)K_ * S_ * (kl_ + ku_ + 1));
+    piv_ = arena_.alloc<int>((size_t)K_ * S_);
+    dv_.fac.Lc = Lc_;
+    dv_.fac.Uc = Uc_;
+    dv_.fac.Ur = Ur_;
+    dv_.fac.piv = piv_;
+    err_ = arena_.alloc<int>(1);
+    SPS_HIP(hipMemsetAsync(err_, 0, sizeof(int), stream));
+    dv_.err = err_;
+    X1_ = arena_.alloc<cplx>(st);
+    Xw_ = arena_.alloc<cplx>(st);
+    Xg_ = arena_.alloc<cplx>(st);
+    acc_ = arena_.alloc<cplx>(st);
+    Ybuf_ = arena_.alloc<cplx>(st);
+    F0_ = arena_.alloc<cplx>((size_t)K_ * 3 * N_);
+    zgA_ = arena_.alloc<cplx>(zsize_);
+    zbar_ = arena_.alloc<cplx>(zsize_);
+    nl_ = arena_.alloc<cplx>((size_t)3 * Ngz_ * K_);
+    nlbar_ = arena_.alloc<cplx>((size_t)3 * Ngz_ * K_);
+    itmp_ = arena_.alloc<cplx>((size_t)desc_.nz * K_);
+    Jpart_ = arena_.alloc<double>(K_);
+    const int ce = desc_.checkpoint_every;
+    const int nck = (desc_.max_steps + ce - 1) / ce;
+    ckpt_ = arena_.alloc<cplx>((size_t)nck * st);
+    seg_ = arena_.alloc<cplx>((size_t)std::min(ce, desc_.max_steps) * 2 * zsize_);
+    const size_t fac_lds = (size_t)(2 * kl_ + ku_ + 1) * S_ * sizeof(double);
+    const std::pair<const void*, size_t> lds[] = {{(const void*)rbc_kfwd, kf_lds()}, {(const void*)rbc_kadj, ka_lds()},
+                                                  {(const void*)rbc_xfwd, xf_lds()}, {(const void*)rbc_xadj, xa_lds()},
+                                                  {(const void*)rbc_factor, fac_lds}};
+    for (const auto& fl : lds) {
+      SPS_REQUIRE(fl.second <= 160 * 1024, "problem too large for LDS");
+      SPS_HIP(hipFuncSetAttribute(fl.first, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fl.second));
+    }
+    SPS_HIP(hipStreamSynchronize(stream));
+  }
+
+  sps_desc desc_;
+  int K_, N_, S_, Ngx_, Ngz_, kl_ = 0, ku_ = 0;
+  double nu_, ka_;
+  RbcDev dv_{};
+  DevArena arena_;
+  double *BM_ = nullptr, *BL_ = nullptr, *Lc_ = nullptr, *Uc_ = nullptr, *Ur_ = nullptr, *Jpart_ = nullptr;
+  int *piv_ = nullptr, *err_ = nullptr;
+  cplx *X1_, *Xw_, *Xg_, *acc_, *Ybuf_, *F0_, *zgA_, *zbar_, *nl_, *nlbar_, *itmp_, *ckpt_, *seg_;
+  size_t zsize_ = 0;
+  bool factored_ = false;
+  int tape_steps_ = -1;
+  KernelTimer timer_;
+};
+
+}  // namespace
+
+ProblemImpl* make_rbc(const sps_desc& d, hipStream_t s) { return new RbcProblem(d, s); }
+
+}  // namespace sps
+
+extern "C" int sps_rbc_host_bands(const sps_desc* desc, int* kl, int* ku, double* BM, double* BL, int* rowmap,
+                                  int* colmap, signed char* rowph, signed char* colph, double* rho) {
+  try {
+    if (!desc || !kl || !ku) return SPS_E_ARG;
+    sps::RbcHostBands hb;
+    sps::rbc_host_bands(*desc, hb);
+    *kl = hb.kl;
+    *ku = hb.ku;
+    if (BM) std::copy(hb.BM.begin(), hb.BM.end(), BM);
+    if (BL) std::copy(hb.BL.begin(), hb.BL.end(), BL);
+    if (rowmap) std::copy(hb.rowmap.begin(), hb.rowmap.end(), rowmap);
+    if (colmap) std::copy(hb.colmap.begin(), hb.colmap.end(), colmap);
+    if (rowph) std::copy(hb.rowph.begin(), hb.rowph.end(), rowph);
+    if (colph) std::copy(hb.colph.begin(), hb.colph.end(), colph);
+    if (rho) std::copy(hb.rho.begin(), hb.rho.end(), rho);
+    return SPS_OK;
+  } catch (const sps::Error& e) {
+    return e.code;
+  }
+}

@@ -1,0 +1,138 @@
+// Host-side internals shared by the C ABI and the problem implementations.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/sps.h"
+
+namespace sps {
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define SPS_HIP(call)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      throw ::sps::Error(SPS_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+#define SPS_CHECK_LAUNCH() SPS_HIP(hipGetLastError())
+
+#define SPS_REQUIRE(cond, msg)                                  \
+  do {                                                          \
+    if (!(cond)) throw ::sps::Error(SPS_E_ARG, (msg));          \
+  } while (0)
+
+// Device allocation owned by a problem; freed in the destructor.
+class DevArena {
+ public:
+  ~DevArena() {
+    for (void* p : ptrs_) (void)hipFree(p);
+  }
+  template <typename T>
+  T* alloc(size_t count) {
+    void* p = nullptr;
+    if (count == 0) count = 1;
+    if (hipMalloc(&p, count * sizeof(T)) != hipSuccess)
+      throw Error(SPS_E_NOMEM, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    ptrs_.push_back(p);
+    return static_cast<T*>(p);
+  }
+  template <typename T>
+  T* upload(const std::vector<T>& h, hipStream_t s) {
+    T* d = alloc<T>(h.size());
+    SPS_HIP(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    SPS_HIP(hipStreamSynchronize(s));
+    return d;
+  }
+
+ private:
+  std::vector<void*> ptrs_;
+};
+
+// HIP-event timing of one kernel class (launches bracketed on the problem's stream).
+class KernelTimer {
+ public:
+  ~KernelTimer() { release(); }
+  void enable(bool on) {
+    release();
+    on_ = on;
+    launches_ = 0;
+    total_ms_ = 0.0;
+  }
+  bool on() const { return on_; }
+  void begin(hipStream_t s) {
+    if (!on_) return;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return;
+    if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
+    (void)hipEventRecord(a, s);
+    pending_.push_back({a, b});
+  }
+  void end(hipStream_t s) {
+    if (!on_ || pending_.empty()) return;
+    (void)hipEventRecord(pending_.back().second, s);
+    if (pending_.size() >= 4096) drain();
+  }
+  void read(long long* launches, double* total_ms) {
+    drain();
+    *launches = launches_;
+    *total_ms = total_ms_;
+    launches_ = 0;
+    total_ms_ = 0.0;
+  }
+
+ private:
+  void drain() {
+    for (auto& pr : pending_) {
+      float ms = 0.f;
+      if (hipEventSynchronize(pr.second) == hipSuccess && hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+        total_ms_ += ms;
+        ++launches_;
+      }
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+    pending_.clear();
+  }
+  void release() { drain(); }
+  bool on_ = false;
+  long long launches_ = 0;
+  double total_ms_ = 0.0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending_;
+};
+
+class ProblemImpl {
+ public:
+  virtual ~ProblemImpl() = default;
+  virtual long long state_size() const = 0;
+  virtual void factor() = 0;
+  virtual void step(double* X, int nsteps) = 0;
+  virtual void adjoint_step(double* Xbar, int nsteps) = 0;
+  virtual void cost(const double* X, double* J, double* dJdX) = 0;
+  virtual void gradient(const double* X0, int nsteps, double* XN, double* dJdX0, double* J) = 0;
+  virtual void initial_state(const double* grid, double* X) = 0;
+  virtual void initial_state_adjoint(const double* Xbar, double* grid) = 0;
+  virtual void eval_F(const double* X, double* F) = 0;
+  virtual void eval_F_vjp(const double* X, const double* Fbar, double* Xbar) = 0;
+  virtual void solve(const double* R, double* X, int adjoint) = 0;
+  virtual void timer_enable(int kind, bool on) = 0;
+  virtual void timer_read(long long* launches, double* ms) = 0;
+  virtual int device_error() = 0;  // reads and clears the sticky device flag
+  hipStream_t stream = nullptr;
+};
+
+ProblemImpl* make_rbc(const sps_desc& d, hipStream_t s);
+ProblemImpl* make_ks(const sps_desc& d, hipStream_t s);
+
+// Host helpers shared by problem builders.
+std::vector<double2> twiddles(int n);            // exp(-2 pi i t / n), t < n
+bool fft_plan(int n, int* radix, int* nst);       // radices 4/3/2, false if n has other factors
+
+}  // namespace sps

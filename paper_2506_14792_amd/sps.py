@@ -1,0 +1,182 @@
+"""ctypes binding of the C ABI declared in include/sps.h (argument marshalling only)."""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsps.so")
+
+RBC2D, KS1D = 1, 2
+RK222, SBDF2 = 1, 2
+
+_STATUS = {0: "SPS_OK", -1: "SPS_E_ARG", -2: "SPS_E_NOMEM", -3: "SPS_E_HIP", -4: "SPS_E_SINGULAR",
+           -5: "SPS_E_NONFINITE", -6: "SPS_E_STATE", -7: "SPS_E_UNSUPPORTED"}
+
+
+class SpsDesc(ctypes.Structure):
+    _fields_ = [("equation", ctypes.c_int), ("scheme", ctypes.c_int), ("nx", ctypes.c_int),
+                ("nz", ctypes.c_int), ("lx", ctypes.c_double), ("param0", ctypes.c_double),
+                ("param1", ctypes.c_double), ("dealias", ctypes.c_double), ("dt", ctypes.c_double),
+                ("checkpoint_every", ctypes.c_int), ("max_steps", ctypes.c_int)]
+
+
+class SpsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+_P = ctypes.c_void_p
+_D = ctypes.c_void_p  # device double*
+
+
+def lib():
+    """Load libsps.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing; build it with paper_2506_14792_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "sps_build_problem": (ctypes.c_int, [ctypes.POINTER(SpsDesc), _P, ctypes.POINTER(_P)]),
+        "sps_state_size": (ctypes.c_longlong, [_P]),
+        "sps_factor": (ctypes.c_int, [_P]),
+        "sps_step": (ctypes.c_int, [_P, _D, ctypes.c_int]),
+        "sps_adjoint_step": (ctypes.c_int, [_P, _D, ctypes.c_int]),
+        "sps_cost": (ctypes.c_int, [_P, _D, _D, _D]),
+        "sps_gradient": (ctypes.c_int, [_P, _D, ctypes.c_int, _D, _D, _D]),
+        "sps_initial_state": (ctypes.c_int, [_P, _D, _D]),
+        "sps_initial_state_adjoint": (ctypes.c_int, [_P, _D, _D]),
+        "sps_eval_F": (ctypes.c_int, [_P, _D, _D]),
+        "sps_eval_F_vjp": (ctypes.c_int, [_P, _D, _D, _D]),
+        "sps_solve": (ctypes.c_int, [_P, _D, _D, ctypes.c_int]),
+        "sps_timer_enable": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
+        "sps_timer_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double)]),
+        "sps_sync": (ctypes.c_int, [_P]),
+        "sps_last_error": (ctypes.c_char_p, []),
+        "sps_destroy": (None, [_P]),
+        "sps_rbc_host_bands": (ctypes.c_int, [ctypes.POINTER(SpsDesc), ctypes.POINTER(ctypes.c_int),
+                                              ctypes.POINTER(ctypes.c_int), _P, _P, _P, _P, _P, _P, _P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != 0:
+        raise SpsError(rc, lib().sps_last_error().decode())
+
+
+def _ptr(t, n=None):
+    """Device pointer of a contiguous float64 CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError("expected a contiguous float64 tensor on the GPU")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} doubles, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def make_desc(equation, nx, nz=0, lx=1.0, param0=0.0, param1=0.0, dealias=1.5, dt=1e-3,
+              checkpoint_every=1, max_steps=1, scheme=None):
+    if scheme is None:
+        scheme = RK222 if equation == RBC2D else SBDF2
+    return SpsDesc(equation, scheme, nx, nz, lx, param0, param1, dealias, dt, checkpoint_every, max_steps)
+
+
+class Problem:
+    """A built problem on the current HIP stream (torch.cuda.current_stream())."""
+
+    def __init__(self, equation, nx, nz=0, lx=1.0, param0=0.0, param1=0.0, dealias=1.5, dt=1e-3,
+                 checkpoint_every=1, max_steps=1, scheme=None, stream=None):
+        import torch
+        self.desc = make_desc(equation, nx, nz, lx, param0, param1, dealias, dt, checkpoint_every, max_steps, scheme)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self._stream = stream
+        h = _P()
+        _check(lib().sps_build_problem(ctypes.byref(self.desc), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self.n = int(lib().sps_state_size(h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sps_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- ABI calls
+    def factor(self):
+        _check(lib().sps_factor(self._h))
+
+    def step(self, X, nsteps):
+        _check(lib().sps_step(self._h, _ptr(X, self.n), nsteps))
+
+    def adjoint_step(self, Xbar, nsteps):
+        _check(lib().sps_adjoint_step(self._h, _ptr(Xbar, self.n), nsteps))
+
+    def cost(self, X, J, dJdX):
+        _check(lib().sps_cost(self._h, _ptr(X, self.n), _ptr(J, 1), _ptr(dJdX, self.n)))
+
+    def gradient(self, X0, nsteps, XN, dJdX0, J):
+        _check(lib().sps_gradient(self._h, _ptr(X0, self.n), nsteps, _ptr(XN, self.n), _ptr(dJdX0, self.n),
+                                  _ptr(J, 1)))
+
+    def initial_state(self, grid, X):
+        _check(lib().sps_initial_state(self._h, _ptr(grid), _ptr(X, self.n)))
+
+    def initial_state_adjoint(self, Xbar, grid_bar):
+        _check(lib().sps_initial_state_adjoint(self._h, _ptr(Xbar, self.n), _ptr(grid_bar)))
+
+    def eval_F(self, X, F):
+        _check(lib().sps_eval_F(self._h, _ptr(X, self.n), _ptr(F, self.n)))
+
+    def eval_F_vjp(self, X, Fbar, Xbar):
+        _check(lib().sps_eval_F_vjp(self._h, _ptr(X, self.n), _ptr(Fbar, self.n), _ptr(Xbar, self.n)))
+
+    def solve(self, R, X, adjoint=False):
+        _check(lib().sps_solve(self._h, _ptr(R, self.n), _ptr(X, self.n), int(bool(adjoint))))
+
+    def timer_enable(self, kind=0, on=True):
+        _check(lib().sps_timer_enable(self._h, kind, int(bool(on))))
+
+    def timer_read(self):
+        n = ctypes.c_longlong()
+        ms = ctypes.c_double()
+        _check(lib().sps_timer_read(self._h, ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
+
+    def sync(self):
+        _check(lib().sps_sync(self._h))
+
+
+def rbc_host_bands(nx, nz, lx, Ra, Pr, dt=1e-3):
+    """Host-assembled real banded systems of the RBC problem (no GPU needed)."""
+    d = make_desc(RBC2D, nx, nz, lx, Ra, Pr, 1.5, dt, 1, 1)
+    kl, ku = ctypes.c_int(), ctypes.c_int()
+    _check(lib().sps_rbc_host_bands(ctypes.byref(d), ctypes.byref(kl), ctypes.byref(ku),
+                                    None, None, None, None, None, None, None))
+    K, S = nx // 2, 4 * nz + 7
+    bw = kl.value + ku.value + 1
+    BM = np.zeros((K, S, bw)); BL = np.zeros((K, S, bw))
+    rowmap = np.zeros(S, np.int32); colmap = np.zeros(S, np.int32)
+    rowph = np.zeros(S, np.int8); colph = np.zeros(S, np.int8); rho = np.zeros(S)
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    _check(lib().sps_rbc_host_bands(ctypes.byref(d), ctypes.byref(kl), ctypes.byref(ku), p(BM), p(BL),
+                                    p(rowmap), p(colmap), p(rowph), p(colph), p(rho)))
+    return dict(kl=kl.value, ku=ku.value, BM=BM, BL=BL, rowmap=rowmap, colmap=colmap, rowph=rowph,
+                colph=colph, rho=rho)

@@ -1,0 +1,179 @@
+"""GPU parity of the Rayleigh-Benard path against the FP64 oracle, called through the
+C ABI: banded solves (forward and transposed), the explicit term F and its VJP, the
+RK222 step, the cost seed, the initial transform and its adjoint, and the full
+checkpointed gradient.  Tolerance: 1e-11 in max|gpu - oracle| / max|oracle| per array."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import imex
+from oracle.rbc import RBC
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+GAMMA = 1.0 - 1.0 / np.sqrt(2.0)
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2506_14792_amd as sps  # noqa: E402
+
+# (nx, nz, lx, Ra, Pr, dt): a small case spanning several wave tiles with a ragged tail,
+# and the full 256 x 64 configuration
+SMALL = (24, 16, 3.0, 1e5, 0.7, 2e-3)
+FULL = (256, 64, 4.0, 1e6, 1.0, 1e-3)
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(X):
+    return torch.from_numpy(np.ascontiguousarray(X).view(np.float64).ravel().copy()).cuda()
+
+
+def from_dev(t, shape):
+    return t.cpu().numpy().view(np.complex128).reshape(shape)
+
+
+def rel(a, b):
+    return np.max(np.abs(a - b)) / np.max(np.abs(b))
+
+
+def build(cfg, ce=1, max_steps=1):
+    nx, nz, lx, Ra, Pr, dt = cfg
+    P = RBC(Nx=nx, Nz=nz, Lx=lx, Ra=Ra, Pr=Pr)
+    G = sps.Problem(sps.RBC2D, nx, nz, lx, Ra, Pr, 1.5, dt, ce, max_steps)
+    return P, G
+
+
+@pytest.mark.parametrize("cfg", [SMALL, FULL], ids=["small", "full"])
+def test_banded_solve_and_transposed_solve(cfg):
+    note(f"solve parity {cfg}")
+    P, G = build(cfg)
+    lu = imex.BlockLU(P.M, P.L, 1.0, cfg[5] * GAMMA)
+    R = wl.random_state(1, (P.K, P.S), real_first_row=False)
+    x = torch.zeros(G.n, dtype=torch.float64, device="cuda")
+    G.solve(to_dev(R), x, adjoint=False)
+    G.sync()
+    assert rel(from_dev(x, R.shape), lu.solve(R)) < TOL
+    G.solve(to_dev(R), x, adjoint=True)
+    G.sync()
+    assert rel(from_dev(x, R.shape), lu.solve_adjoint(R)) < TOL
+
+
+@pytest.mark.parametrize("cfg", [SMALL, FULL], ids=["small", "full"])
+def test_explicit_term_and_vjp(cfg):
+    note(f"F and F-vjp parity {cfg}")
+    P, G = build(cfg)
+    X = 1e-2 * wl.random_state(2, (P.K, P.S))
+    Fb = wl.random_state(3, (P.K, P.S), real_first_row=False)
+    out = torch.zeros(G.n, dtype=torch.float64, device="cuda")
+    G.eval_F(to_dev(X), out)
+    G.sync()
+    assert rel(from_dev(out, X.shape), P.F(X)) < TOL
+    G.eval_F_vjp(to_dev(X), to_dev(Fb), out)
+    G.sync()
+    ref = P.F_vjp(X, Fb)
+    got = from_dev(out, X.shape)
+    got[0] = got[0].real  # the imaginary part of the mean mode carries no cotangent
+    ref[0] = ref[0].real
+    assert rel(got, ref) < TOL
+
+
+@pytest.mark.parametrize("cfg", [SMALL, FULL], ids=["small", "full"])
+def test_initial_state_cost_and_adjoints(cfg):
+    note(f"initial state / cost parity {cfg}")
+    P, G = build(cfg)
+    b0 = wl.rbc_b0(seed=4, Nx=cfg[0], Nz=cfg[1])
+    X = torch.zeros(G.n, dtype=torch.float64, device="cuda")
+    G.initial_state(torch.from_numpy(b0.ravel().copy()).cuda(), X)
+    G.sync()
+    assert rel(from_dev(X, (P.K, P.S)), P.initial_state(b0)) < TOL
+    Xb = wl.random_state(5, (P.K, P.S))
+    gb = torch.zeros(b0.size, dtype=torch.float64, device="cuda")
+    G.initial_state_adjoint(to_dev(Xb), gb)
+    G.sync()
+    assert rel(gb.cpu().numpy().reshape(b0.shape), P.initial_state_adjoint(Xb)) < TOL
+    Xs = wl.random_state(6, (P.K, P.S))
+    J = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dJ = torch.zeros(G.n, dtype=torch.float64, device="cuda")
+    G.cost(to_dev(Xs), J, dJ)
+    G.sync()
+    assert abs(J.item() - P.kinetic_energy(Xs)) < TOL * abs(P.kinetic_energy(Xs))
+    assert rel(from_dev(dJ, Xs.shape), P.kinetic_energy_grad(Xs)) < TOL
+
+
+@pytest.mark.parametrize("cfg,nsteps", [(SMALL, 7), (FULL, 3)], ids=["small", "full"])
+def test_forward_steps(cfg, nsteps):
+    note(f"forward parity {cfg} x {nsteps}")
+    P, G = build(cfg, ce=2, max_steps=nsteps)
+    b0 = wl.rbc_b0(seed=7, Nx=cfg[0], Nz=cfg[1], amp=0.1)
+    X0 = P.initial_state(b0)
+    X = to_dev(X0)
+    G.step(X, nsteps)
+    G.sync()
+    XN, _ = imex.rk_forward(P, X0, cfg[5], nsteps)
+    assert rel(from_dev(X, X0.shape), XN) < TOL
+
+
+@pytest.mark.parametrize("cfg,nsteps,ce", [(SMALL, 7, 3), (FULL, 6, 4)], ids=["small", "full"])
+def test_gradient(cfg, nsteps, ce):
+    note(f"gradient parity {cfg} x {nsteps} ce={ce}")
+    P, G = build(cfg, ce=ce, max_steps=nsteps)
+    b0 = wl.rbc_b0(seed=8, Nx=cfg[0], Nz=cfg[1], amp=0.1)
+    X0 = P.initial_state(b0)
+    XN_ref, hist = imex.rk_forward(P, X0, cfg[5], nsteps)
+    J_ref = P.kinetic_energy(XN_ref)
+    g_ref = imex.rk_adjoint(P, P.kinetic_energy_grad(XN_ref), hist, cfg[5])
+    XN = torch.zeros(G.n, dtype=torch.float64, device="cuda")
+    gX = torch.zeros(G.n, dtype=torch.float64, device="cuda")
+    J = torch.zeros(1, dtype=torch.float64, device="cuda")
+    G.gradient(to_dev(X0), nsteps, XN, gX, J)
+    G.sync()
+    assert rel(from_dev(XN, X0.shape), XN_ref) < TOL
+    assert abs(J.item() - J_ref) < TOL * abs(J_ref)
+    got = from_dev(gX, X0.shape)
+    assert rel(got, g_ref) < TOL
+    # and on the grid of b0
+    gb = torch.zeros(b0.size, dtype=torch.float64, device="cuda")
+    G.initial_state_adjoint(gX, gb)
+    G.sync()
+    assert rel(gb.cpu().numpy().reshape(b0.shape), P.initial_state_adjoint(g_ref)) < TOL
+
+
+def test_checkpoint_interval_does_not_change_the_gradient_bits():
+    note("checkpoint invariance")
+    cfg, nsteps = SMALL, 9
+    res = []
+    for ce in (1, 4, 9):
+        P, G = build(cfg, ce=ce, max_steps=nsteps)
+        X0 = to_dev(P.initial_state(wl.rbc_b0(seed=9, Nx=cfg[0], Nz=cfg[1], amp=0.1)))
+        gX = torch.zeros(G.n, dtype=torch.float64, device="cuda")
+        G.gradient(X0, nsteps, None, gX, None)
+        G.sync()
+        res.append(gX.cpu().numpy())
+    assert np.array_equal(res[0], res[1]) and np.array_equal(res[0], res[2])
+
+
+def test_step_then_adjoint_step_matches_gradient():
+    note("step + adjoint_step")
+    cfg, nsteps = SMALL, 5
+    P, G = build(cfg, ce=2, max_steps=nsteps)
+    X0 = P.initial_state(wl.rbc_b0(seed=10, Nx=cfg[0], Nz=cfg[1], amp=0.1))
+    X = to_dev(X0)
+    G.step(X, nsteps)
+    dJ = torch.zeros(G.n, dtype=torch.float64, device="cuda")
+    G.cost(X, None, dJ)
+    G.adjoint_step(dJ, nsteps)
+    G.sync()
+    XN_ref, hist = imex.rk_forward(P, X0, cfg[5], nsteps)
+    g_ref = imex.rk_adjoint(P, P.kinetic_energy_grad(XN_ref), hist, cfg[5])
+    assert rel(from_dev(dJ, X0.shape), g_ref) < TOL
+    with pytest.raises(sps.SpsError):
+        G.adjoint_step(dJ, nsteps + 1)
