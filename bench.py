@@ -1,0 +1,168 @@
+"""Benchmark: forward+adjoint timesteps/s and gradients/s of the 2D Rayleigh-Benard
+problem (Fourier x Chebyshev 256 x 64, FP64, RK222 dt = 1e-3, 1000 steps, checkpoint
+every 50) on one MI355X.
+
+One benchmark step is one full gradient: initial transform of b0, 1000 forward steps
+with checkpoints, cost seed, reverse sweep with segment recompute, and the gradient on
+the b0 grid.  Inputs are resident in HBM before the timed region starts.
+
+Prints one JSON line.  Extra modes: --copy-calibration (a plain device copy of known
+size, used to scale rocprof FETCH_SIZE / WRITE_SIZE counters) and --no-cpu.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "forward+adjoint timesteps/s and gradients/s, 2D Fourier×Chebyshev 256×64, FP64"
+CFG = dict(nx=256, nz=64, lx=4.0, Ra=1e6, Pr=1.0, dt=1e-3, nsteps=1000, checkpoint_every=50, seed=0)
+HBM_PEAK_GBS = 8000.0
+
+
+def stage_kernel_bytes(nx, nz):
+    """Algorithmic HBM bytes of one launch of the per-wavenumber forward stage kernel
+    (average of the two RK222 stages): each operand streamed once.
+    Per wavenumber: LU factors (n*kl multipliers + n*(kl+ku+1) U entries + n pivots),
+    state in/out, nonlinear terms in, stage-0 F out/in, six z-grid fields out."""
+    K, N = nx // 2, nz
+    S = 4 * N + 7
+    Ngz = 3 * N // 2
+    kl, ku = 7, 20
+    factors = S * (kl + kl + ku + 1) * 8 + S * 4
+    state = S * 16
+    nl = 3 * Ngz * 16
+    f0 = 3 * N * 16
+    zg = 6 * Ngz * 16
+    tables = 2 * N * Ngz * 8 / K          # Chebyshev matrices, shared by all wavenumbers
+    stage1 = factors + state + state + nl + f0 + zg + tables
+    stage2 = factors + 2 * state + state + nl + f0 + zg + tables
+    return K * 0.5 * (stage1 + stage2)
+
+
+def cpu_baseline(nsteps=20):
+    """The oracle (numpy/scipy FP64) on a bounded sample: nsteps forward + nsteps adjoint
+    steps of the same 256 x 64 problem from the same b0."""
+    from threadpoolctl import threadpool_info
+    from oracle import imex
+    from oracle.rbc import RBC
+    import workloads as wl
+    P = RBC(Nx=CFG["nx"], Nz=CFG["nz"], Lx=CFG["lx"], Ra=CFG["Ra"], Pr=CFG["Pr"])
+    X0 = P.initial_state(wl.rbc_b0(seed=CFG["seed"], Nx=CFG["nx"], Nz=CFG["nz"]))
+    t0 = time.perf_counter()
+    XN, hist = imex.rk_forward(P, X0, CFG["dt"], nsteps)
+    imex.rk_adjoint(P, P.kinetic_energy_grad(XN), hist, CFG["dt"])
+    t = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    return {"value": 2 * nsteps / t, "unit": "timesteps/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{nsteps} forward + {nsteps} adjoint RK222 steps at 256x64 (dense LU, matrix transforms), "
+                      f"{t:.1f} s; host has {os.cpu_count()} logical CPUs"}
+
+
+def copy_calibration(nbytes=1 << 28, reps=5):
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_per_dispatch": nbytes, "reps": reps}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--nsteps", type=int, default=CFG["nsteps"])
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); the multi-GPU "
+              "sharding is a design note only", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
+    import torch
+    import paper_2506_14792_amd as sps
+    import workloads as wl
+
+    torch.cuda.set_device(0)
+    c = CFG
+    n = args.nsteps
+    G = sps.Problem(sps.RBC2D, c["nx"], c["nz"], c["lx"], c["Ra"], c["Pr"], 1.5, c["dt"], c["checkpoint_every"], n)
+    b0 = torch.from_numpy(wl.rbc_b0(seed=c["seed"], Nx=c["nx"], Nz=c["nz"]).ravel().copy()).cuda()
+    X0 = torch.zeros(G.n, dtype=torch.float64, device="cuda")
+    gX = torch.zeros_like(X0)
+    gb = torch.zeros_like(b0)
+    J = torch.zeros(1, dtype=torch.float64, device="cuda")
+
+    def one_gradient():
+        G.initial_state(b0, X0)
+        G.gradient(X0, n, None, gX, J)
+        G.initial_state_adjoint(gX, gb)
+
+    G.factor()
+    for _ in range(args.warmup):
+        one_gradient()
+    G.sync()
+    G.timer_enable(0, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_gradient()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    G.sync()
+    launches, kern_ms = G.timer_read()
+    G.timer_enable(0, False)
+    sec = (t1 - t0) / args.steps
+    grads_per_s = 1.0 / sec
+    bytes_launch = stage_kernel_bytes(c["nx"], c["nz"])
+    avg_ms = kern_ms / max(launches, 1)
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    traffic_path = os.path.join(ROOT, "profiles", "traffic_rbc_kfwd_256x64.json")
+    traffic = None
+    if os.path.exists(traffic_path):
+        traffic = json.load(open(traffic_path)).get("hbm_bytes_per_launch")
+    cpu = None if args.no_cpu else cpu_baseline(args.cpu_steps)
+    out = {
+        "metric": METRIC,
+        "value": 2 * n * grads_per_s,
+        "unit": "timesteps/s",
+        "gradients_per_s": grads_per_s,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "Rayleigh-Benard 2D, Fourier(x, Lx=4) x Chebyshev(z, [0,1]) 256x64, Ra=1e6, Pr=1, "
+                               "RK222 dt=1e-3, 1000 steps, checkpoint every 50, gradient of final kinetic energy "
+                               "w.r.t. initial buoyancy",
+                   "nx": c["nx"], "nz": c["nz"], "nsteps": n, "checkpoint_every": c["checkpoint_every"],
+                   "seed": c["seed"], "step": "one full gradient (forward + recompute + adjoint)"},
+        "roofline": {"bound": "hbm", "kernel": "rbc_kfwd (RK222 stage: z-transforms, RHS, banded LU solve)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "bytes_per_launch": bytes_launch, "avg_launch_ms": avg_ms,
+                     "launches_timed": launches},
+        "cpu_baseline": cpu,
+        "J": J.item(),
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,122 +1,140 @@
 // Batched banded LU with partial pivoting (one real system per wavenumber) and its
-// forward and transposed solves, executed by one wave64 per right-hand side pair
-// (the real and imaginary parts share the real factors).
-//
-// Factor storage of one system (n rows, kl sub-diagonals, ku super-diagonals of the
-// unfactored matrix, uw = kl + ku + 1 entries per row of U after pivoting fill):
-//   Lc[j*kl + i]  multiplier of row j+1+i in column j (i < kl)
-//   Uc[j*uw + t]  t = 0: 1/U[j][j];  t >= 1: U[j-t][j]   (column j of U, upward)
-//   Ur[j*uw + t]  t = 0: 1/U[j][j];  t >= 1: U[j][j+t]   (row j of U, rightward)
-//   piv[j]        row exchanged with row j at elimination step j (>= j)
-// Column-wise L and U serve the forward solve, row-wise U and column-wise L the
-// transposed solve, so both sweeps are axpy-shaped except the final L^T sweep.
+// forward and transposed solves.  The factorization is LAPACK-style (row exchanges
+// interleaved with the eliminations, kl sub- and ku super-diagonals, U fill up to
+// kl + ku); its factors are then condensed into dense block operators (below) that the
+// solves apply.
 #pragma once
 #include "sps_device.h"
 
-struct BandFactors {
-  const double* Lc;
-  const double* Uc;
-  const double* Ur;
-  const int* piv;
+// Uniform value v placed into lane `lane` of a wave-distributed value (a lane select).
+__device__ __forceinline__ double writelane_d(double v, int lane, double old) {
+  return (lane_id() == lane) ? v : old;
+}
+
+// Blocked solves.  The factor kernel turns the banded LU factors into dense block operators
+// (one set per system) so that a solve is a short chain of small matrix-vector products
+// with no per-row lane broadcasts:
+//   T_t  (TW x TW): the row exchanges and eliminations of L-sweep steps t*BLK .. t*BLK+BLK-1
+//        acting on the window [t*BLK, t*BLK + TW) (identity beyond BLK + kl); the L sweep is
+//        T_last ... T_1 T_0.
+//   G_t  (BLK x GW): back substitution of U rows t*BLK .. t*BLK+BLK-1,
+//        x_block = G_t [y_block; x(t*BLK + BLK .. t*BLK + GW)], G_t = [U_tt^{-1} | -U_tt^{-1} U_t,off]
+//        (zero beyond BLK + uw - 1); the U sweep applies G_t for t descending.
+// The transposed solve applies G_t^T for t ascending, then T_t^T for t descending.
+// Block shapes are compile-time so every read is unconditional: the right-hand side must
+// be followed by at least SPS_PAD zero entries (positions n .. n + SPS_PAD - 1), which the
+// operators keep at zero.
+// Layout per system: T[nblk][TW][TW] (row-major) followed by G[nblk][BLK][GW].
+// One real right-hand side per wave (the real and imaginary parts of a complex right-hand
+// side run on two waves): b[2*i] in LDS; operators in LDS.
+#define SPS_BLK 8
+#define SPS_TW 16     // T window: needs SPS_BLK + kl <= SPS_TW
+#define SPS_GW 36     // G width: needs SPS_BLK + uw - 1 <= SPS_GW
+#define SPS_PAD 40    // zero tail after the right-hand side (>= SPS_GW)
+
+__host__ __device__ inline int blk_count(int n) { return (n + SPS_BLK - 1) / SPS_BLK; }
+// doubles per system (a multiple of 4, so every system's operators start 32-byte aligned)
+__host__ __device__ inline int blk_ops_size(int n) {
+  return blk_count(n) * (SPS_TW * SPS_TW + SPS_BLK * SPS_GW);
+}
+
+// x = A^{-1} b
+__device__ inline void blk_solve_part(const double* ops, int nblk, double* b) {
+  const int lane = lane_id();
+  const double* T = ops;
+  const double* G = ops + nblk * SPS_TW * SPS_TW;
+  const int r = lane & (SPS_TW - 1);
+  for (int t = 0; t < nblk; ++t) {
+    const double* v = b + 2 * (t * SPS_BLK);
+    const double* Tr = T + (t * SPS_TW + r) * SPS_TW;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+    for (int c = 0; c < SPS_TW; c += 4) {
+      a0 = fma(Tr[c], v[2 * c], a0);
+      a1 = fma(Tr[c + 1], v[2 * c + 2], a1);
+      a2 = fma(Tr[c + 2], v[2 * c + 4], a2);
+      a3 = fma(Tr[c + 3], v[2 * c + 6], a3);
+    }
+    const double out = (a0 + a1) + (a2 + a3);
+    if (lane < SPS_TW) b[2 * (t * SPS_BLK + r)] = out;
+  }
+  const int i = lane & (SPS_BLK - 1);
+  for (int t = nblk - 1; t >= 0; --t) {
+    const double* v = b + 2 * (t * SPS_BLK);
+    const double* Gr = G + (t * SPS_BLK + i) * SPS_GW;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+    for (int c = 0; c < SPS_GW; c += 4) {
+      a0 = fma(Gr[c], v[2 * c], a0);
+      a1 = fma(Gr[c + 1], v[2 * c + 2], a1);
+      a2 = fma(Gr[c + 2], v[2 * c + 4], a2);
+      a3 = fma(Gr[c + 3], v[2 * c + 6], a3);
+    }
+    const double out = (a0 + a1) + (a2 + a3);
+    if (lane < SPS_BLK) b[2 * (t * SPS_BLK + i)] = out;
+  }
+}
+
+// x = A^{-T} b
+__device__ inline void blk_solve_t_part(const double* ops, int nblk, double* b) {
+  const int lane = lane_id();
+  const double* T = ops;
+  const double* G = ops + nblk * SPS_TW * SPS_TW;
+  const int c = (lane < SPS_GW) ? lane : SPS_GW - 1;
+  for (int t = 0; t < nblk; ++t) {
+    const double* v = b + 2 * (t * SPS_BLK);
+    const double* Gc = G + t * SPS_BLK * SPS_GW + c;
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+    for (int i = 0; i < SPS_BLK; i += 2) {
+      a0 = fma(Gc[i * SPS_GW], v[2 * i], a0);
+      a1 = fma(Gc[(i + 1) * SPS_GW], v[2 * i + 2], a1);
+    }
+    const double keep = (c >= SPS_BLK) ? v[2 * c] : 0.0;
+    if (lane < SPS_GW) b[2 * (t * SPS_BLK + c)] = keep + (a0 + a1);
+  }
+  const int cc = lane & (SPS_TW - 1);
+  for (int t = nblk - 1; t >= 0; --t) {
+    const double* v = b + 2 * (t * SPS_BLK);
+    const double* Tc = T + t * SPS_TW * SPS_TW + cc;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+    for (int rr = 0; rr < SPS_TW; rr += 4) {
+      a0 = fma(Tc[rr * SPS_TW], v[2 * rr], a0);
+      a1 = fma(Tc[(rr + 1) * SPS_TW], v[2 * rr + 2], a1);
+      a2 = fma(Tc[(rr + 2) * SPS_TW], v[2 * rr + 4], a2);
+      a3 = fma(Tc[(rr + 3) * SPS_TW], v[2 * rr + 6], a3);
+    }
+    const double out = (a0 + a1) + (a2 + a3);
+    if (lane < SPS_TW) b[2 * (t * SPS_BLK + cc)] = out;
+  }
+}
+
+// One system's block operators are brought into LDS in two steps so that their memory
+// latency overlaps other work: ops_issue() starts all global loads of this thread's share
+// into registers, ops_store() writes them into LDS once the destination is free.
+// count (doubles) must be a multiple of 2; at most SPS_OPS_REG 16-byte loads per thread.
+#define SPS_OPS_REG 36
+struct OpsRegs {
+  double2 v[SPS_OPS_REG];
 };
-
-// Shift a wave-resident window toward lower lanes: lane l receives lane l+1.
-__device__ __forceinline__ cplx wave_shift_down(cplx w) {
-  return cmk(__shfl_down(w.x, 1), __shfl_down(w.y, 1));
-}
-__device__ __forceinline__ cplx wave_shift_up(cplx w) {
-  return cmk(__shfl_up(w.x, 1), __shfl_up(w.y, 1));
-}
-
-// x = A^{-1} b for one system; b (LDS, n complex) is overwritten by x.
-// Must be executed by all 64 lanes of one wave, with nothing else writing b.
-__device__ inline void band_solve_wave(const BandFactors f, int n, int kl, int uw, cplx* b) {
-  const int lane = lane_id();
-  // ---- forward sweep: row exchanges and unit-lower L, window lane l = b[j + l]
-  cplx w = (lane < n) ? b[lane] : czero();
-  double lnext = (lane >= 1 && lane <= kl) ? f.Lc[lane - 1] : 0.0;
-  int pnext = f.piv[0];
-  for (int j = 0; j < n; ++j) {
-    const double lj = lnext;
-    const int p = pnext - j;
-    if (j + 1 < n) {
-      lnext = (lane >= 1 && lane <= kl) ? f.Lc[(j + 1) * kl + lane - 1] : 0.0;
-      pnext = f.piv[j + 1];
-    }
-    const double vr = readlane_d(w.x, p), vi = readlane_d(w.y, p);
-    const double ur = readlane_d(w.x, 0), ui = readlane_d(w.y, 0);
-    if (lane == p) w = cmk(ur, ui);
-    w.x -= lj * vr;
-    w.y -= lj * vi;
-    if (lane == 0) b[j] = cmk(vr, vi);
-    w = wave_shift_down(w);
-    if (lane == SPS_WAVE - 1) w = (j + SPS_WAVE < n) ? b[j + SPS_WAVE] : czero();
-  }
-  // ---- back substitution with column-wise U, window lane l = b[j - l]
-  w = (n - 1 - lane >= 0) ? b[n - 1 - lane] : czero();
-  double unext = (lane < uw) ? f.Uc[(n - 1) * uw + lane] : 0.0;
-  for (int j = n - 1; j >= 0; --j) {
-    const double uj = unext;
-    if (j > 0) unext = (lane < uw) ? f.Uc[(j - 1) * uw + lane] : 0.0;
-    const double inv = readlane_d(uj, 0);
-    const double xr = readlane_d(w.x, 0) * inv, xi = readlane_d(w.y, 0) * inv;
-    if (lane >= 1) {
-      w.x -= uj * xr;
-      w.y -= uj * xi;
-    }
-    if (lane == 0) b[j] = cmk(xr, xi);
-    w = wave_shift_down(w);
-    if (lane == SPS_WAVE - 1) w = (j - SPS_WAVE >= 0) ? b[j - SPS_WAVE] : czero();
+__device__ __forceinline__ void ops_issue(const double* g, int count, OpsRegs& r) {
+  const double2* g2 = reinterpret_cast<const double2*>(g);
+  const int h = count / 2;
+#pragma unroll
+  for (int i = 0; i < SPS_OPS_REG; ++i) {
+    const int e = threadIdx.x + i * blockDim.x;
+    r.v[i] = (e < h) ? g2[e] : make_double2(0.0, 0.0);
   }
 }
-
-// x = A^{-T} b (the real factors transposed; complex b handled part by part).
-__device__ inline void band_solve_t_wave(const BandFactors f, int n, int kl, int uw, cplx* b) {
-  const int lane = lane_id();
-  // ---- U^T z = b, forward, row-wise U, window lane l = b[j + l]
-  cplx w = (lane < n) ? b[lane] : czero();
-  double unext = (lane < uw) ? f.Ur[lane] : 0.0;
-  for (int j = 0; j < n; ++j) {
-    const double uj = unext;
-    if (j + 1 < n) unext = (lane < uw) ? f.Ur[(j + 1) * uw + lane] : 0.0;
-    const double inv = readlane_d(uj, 0);
-    const double zr = readlane_d(w.x, 0) * inv, zi = readlane_d(w.y, 0) * inv;
-    if (lane >= 1) {
-      w.x -= uj * zr;
-      w.y -= uj * zi;
-    }
-    if (lane == 0) b[j] = cmk(zr, zi);
-    w = wave_shift_down(w);
-    if (lane == SPS_WAVE - 1) w = (j + SPS_WAVE < n) ? b[j + SPS_WAVE] : czero();
+__device__ __forceinline__ void ops_store(const OpsRegs& r, int count, double* dst) {
+  double2* d2 = reinterpret_cast<double2*>(dst);
+  const int h = count / 2;
+#pragma unroll
+  for (int i = 0; i < SPS_OPS_REG; ++i) {
+    const int e = threadIdx.x + i * blockDim.x;
+    if (e < h) d2[e] = r.v[i];
   }
-  // ---- L^T and the exchanges in reverse order; window lane l = b[j + l]
-  w = (lane == 0) ? b[n - 1] : czero();
-  double lnext = (lane >= 1 && lane <= kl) ? f.Lc[(n - 1) * kl + lane - 1] : 0.0;
-  int pnext = f.piv[n - 1];
-  for (int j = n - 1; j >= 0; --j) {
-    const double lj = lnext;
-    const int p = pnext - j;
-    if (j > 0) {
-      lnext = (lane >= 1 && lane <= kl) ? f.Lc[(j - 1) * kl + lane - 1] : 0.0;
-      pnext = f.piv[j - 1];
-    }
-    double sr = lj * w.x, si = lj * w.y;   // lanes 1..kl hold b[j+1..j+kl]
-    sr += __shfl_xor(sr, 1); si += __shfl_xor(si, 1);
-    sr += __shfl_xor(sr, 2); si += __shfl_xor(si, 2);
-    sr += __shfl_xor(sr, 4); si += __shfl_xor(si, 4);
-    if (lane == 0) { w.x -= sr; w.y -= si; }
-    const double vr = readlane_d(w.x, p), vi = readlane_d(w.y, p);
-    const double ur = readlane_d(w.x, 0), ui = readlane_d(w.y, 0);
-    if (lane == p) w = cmk(ur, ui);
-    if (lane == 0) w = cmk(vr, vi);
-    // position j + 63 can no longer be reached by an exchange: it is final
-    if (lane == SPS_WAVE - 1 && j + SPS_WAVE - 1 < n) b[j + SPS_WAVE - 1] = w;
-    if (j > 0) {
-      w = wave_shift_up(w);
-      if (lane == 0) w = b[j - 1];
-    }
-  }
-  if (lane < SPS_WAVE - 1 && lane < n) b[lane] = w;
 }
 
 // ---------------------------------------------------------------------------- factor
@@ -126,8 +144,7 @@ __device__ inline void band_solve_t_wave(const BandFactors f, int n, int kl, int
 // ldab = 2kl + ku + 1, kv = kl + ku.
 __device__ inline void band_factor_block(const double* __restrict__ BM, const double* __restrict__ BL,
                                          double a, double bcoef, int n, int kl, int ku, double* ab,
-                                         int* sh, double* Lc, double* Uc, double* Ur, int* piv,
-                                         int* err) {
+                                         int* sh, int* spiv, double* OPS, int* err) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int ldab = 2 * kl + ku + 1, kv = kl + ku, bw = kl + ku + 1, uw = kl + ku + 1;
   for (int e = tid; e < n * ldab; e += nt) ab[e] = 0.0;
@@ -149,7 +166,7 @@ __device__ inline void band_factor_block(const double* __restrict__ BM, const do
         if (v > best) { best = v; jp = i; }
       }
       sh[0] = jp;
-      piv[j] = j + jp;
+      spiv[j] = j + jp;
       if (!(best > 0.0) || !isfinite(best)) atomicOr(err, 1);
     }
     __syncthreads();
@@ -173,21 +190,69 @@ __device__ inline void band_factor_block(const double* __restrict__ BM, const do
     }
     __syncthreads();
   }
-  // export
-  for (int e = tid; e < n * kl; e += nt) {
-    const int j = e / kl, i = e - j * kl;
-    Lc[e] = (i + 1 <= n - 1 - j) ? ab[j * ldab + kv + 1 + i] : 0.0;
-  }
-  for (int e = tid; e < n * uw; e += nt) {
-    const int j = e / uw, t = e - j * uw;
-    double vc, vr;
-    if (t == 0) {
-      vc = vr = 1.0 / ab[j * ldab + kv];
-    } else {
-      vc = (j - t >= 0) ? ab[j * ldab + kv - t] : 0.0;                 // U[j-t][j]
-      vr = (j + t < n) ? ab[(j + t) * ldab + kv - t] : 0.0;            // U[j][j+t]
+  // block operators (see above); T_t column c is the image of the window's unit vector e_c
+  __syncthreads();
+  const int nblk = blk_count(n);
+  double* T = OPS;
+  double* G = OPS + nblk * SPS_TW * SPS_TW;
+  for (int e = tid; e < nblk * SPS_TW; e += nt) {
+    const int t = e / SPS_TW, c = e - t * SPS_TW, tb = t * SPS_BLK;
+    double v[SPS_TW];
+#pragma unroll
+    for (int r = 0; r < SPS_TW; ++r) v[r] = (r == c) ? 1.0 : 0.0;
+    for (int q = 0; q < SPS_BLK; ++q) {
+      const int j = tb + q;
+      if (j >= n) break;
+      const int p = spiv[j] - j;
+      double vq = 0.0, vp = 0.0;
+#pragma unroll
+      for (int r = 0; r < SPS_TW; ++r) {
+        if (r == q) vq = v[r];
+        if (r == q + p) vp = v[r];
+      }
+#pragma unroll
+      for (int r = 0; r < SPS_TW; ++r) {
+        if (r == q) v[r] = vp;
+        else if (r == q + p) v[r] = vq;
+      }
+      const int km = min(kl, n - 1 - j);
+#pragma unroll
+      for (int r = 0; r < SPS_TW; ++r) {
+        const int i = r - q;   // row j + i
+        if (i >= 1 && i <= km) v[r] -= ab[j * ldab + kv + i] * vp;
+      }
     }
-    Uc[e] = vc;
-    Ur[e] = vr;
+    for (int r = 0; r < SPS_TW; ++r) T[(t * SPS_TW + r) * SPS_TW + c] = v[r];
+  }
+  // G_t row i: Ui[i][c] for c < BLK (row i of the inverse of the diagonal block of U),
+  // then -sum_i' Ui[i][i'] U[tb+i'][tb+c] for BLK <= c < GW
+  auto Uat = [&](int i, int c) -> double {   // U[i][c] of the factored band
+    return (i < n && c < n && c >= i && c - i <= kv) ? ab[c * ldab + kv + i - c] : 0.0;
+  };
+  for (int e = tid; e < nblk * SPS_BLK; e += nt) {
+    const int t = e / SPS_BLK, i = e - t * SPS_BLK, tb = t * SPS_BLK;
+    double ui[SPS_BLK];
+#pragma unroll
+    for (int c = 0; c < SPS_BLK; ++c) ui[c] = 0.0;
+    if (tb + i < n) {
+#pragma unroll
+      for (int c = 0; c < SPS_BLK; ++c) {
+        if (c < i || tb + c >= n) continue;
+        double sacc = (c == i) ? 1.0 : 0.0;
+#pragma unroll
+        for (int ip = 0; ip < SPS_BLK; ++ip)
+          if (ip >= i && ip < c) sacc -= ui[ip] * Uat(tb + ip, tb + c);
+        ui[c] = sacc / Uat(tb + c, tb + c);
+      }
+    }
+    double* Gr = G + (t * SPS_BLK + i) * SPS_GW;
+#pragma unroll
+    for (int c = 0; c < SPS_BLK; ++c) Gr[c] = ui[c];
+    for (int c = SPS_BLK; c < SPS_GW; ++c) {
+      double sacc = 0.0;
+#pragma unroll
+      for (int ip = 0; ip < SPS_BLK; ++ip) sacc -= ui[ip] * Uat(tb + ip, tb + c);
+      Gr[c] = sacc;
+    }
   }
 }

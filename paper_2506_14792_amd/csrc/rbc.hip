@@ -49,12 +49,10 @@ struct RbcDev {
   int n, kl, ku, uw;
   double Lx, nu, ka;
   const double* kx;     // [K]
-  const double* Cb_nj;  // [N][Ngz]  T_n(x_j)
-  const double* Cb_jn;  // [Ngz][N]  T_n(x_j)
-  const double* Cf_jn;  // [Ngz][N]  (2 - delta_n0)/Ngz T_n(x_j)
-  const double* Cf_nj;  // [N][Ngz]
-  const double* C1f_jn; // scale-1 forward [Nz1][N]
-  const double* C1f_nj; // [N][Nz1]
+  // T_n at the ascending Gauss node j of an Ng-point grid equals cos(pi M / (2 Ng)) with
+  // M = n (2 (Ng - j) - 1) mod 4 Ng, so one table of 4 Ng cosines serves every (n, j).
+  const double* cosz;   // [4 Ngz]
+  const double* cosz1;  // [4 Nz1] (scale-1 grid)
   const cplx* twx;      // [Ngx]
   const cplx* twx1;     // [Nx1]
   FftPlan px, px1;
@@ -64,18 +62,10 @@ struct RbcDev {
   const signed char* colph;  // [S] 1: column slot multiplied by +i
   const double* rho;    // [S] X[s] = y[s] + rho[s] y[s+2]
   const double* gram;   // [N][N] int_0^1 T_m T_n dz
-  BandFactors fac;      // base pointers; per-k offsets applied in kernels
+  const double* ops;    // [K][opsize] block operators of the LU factors (T blocks, then G blocks)
+  int opsize;
   int* err;             // bit 0 singular pivot, bit 1 non-finite state
 };
-
-__device__ __forceinline__ BandFactors fac_k(const RbcDev& d, int k) {
-  BandFactors f;
-  f.Lc = d.fac.Lc + (size_t)k * d.n * d.kl;
-  f.Uc = d.fac.Uc + (size_t)k * d.n * d.uw;
-  f.Ur = d.fac.Ur + (size_t)k * d.n * d.uw;
-  f.piv = d.fac.piv + (size_t)k * d.n;
-  return f;
-}
 
 // ---------------------------------------------------------------------------- operators
 // Sparse ultraspherical operators on [0,1] applied to length-N coefficient arrays in LDS.
@@ -262,35 +252,73 @@ __device__ void dz_series_t(const cplx* y, cplx* e, int N) {
   }
 }
 
-// A x = r for wavenumber k: r in ABI row slots (LDS), result x in ABI column slots.
-// tmp: LDS scratch of S entries.  Block-wide (contains barriers).
-__device__ void rbc_solve(const RbcDev& d, int k, const cplx* r, cplx* x, cplx* tmp) {
-  const int tid = threadIdx.x, S = d.S;
-  for (int i = tid; i < S; i += blockDim.x) {
-    const int s = d.rowmap[i];
-    const cplx v = r[s];
-    tmp[i] = d.rowph[s] ? cmul_mi(v) : v;
+// ---------------------------------------------------------------------------- Chebyshev sums
+// Stage the cosine table of an Ng-point Gauss grid into LDS (block-wide; caller syncs).
+__device__ __forceinline__ void stage_cos(const double* g, double* ct, int Ng) {
+  for (int e = threadIdx.x; e < 4 * Ng; e += blockDim.x) ct[e] = g[e];
+}
+// sum_j T_n(x_j) v[j] over the Ng nodes (complex v in LDS), cos table ct in LDS.
+__device__ __forceinline__ cplx cheb_sum_nodes(const double* ct, const cplx* v, int n, int Ng) {
+  const int P = 4 * Ng, dn = (2 * n) % P;
+  int M = (int)(((long long)n * (2 * Ng - 1)) % P);
+  double sr = 0.0, si = 0.0;
+#pragma unroll 8
+  for (int j = 0; j < Ng; ++j) {
+    const double t = ct[M];
+    sr += t * v[j].x;
+    si += t * v[j].y;
+    M -= dn;
+    if (M < 0) M += P;
   }
-  __syncthreads();
-  if (tid < SPS_WAVE) band_solve_wave(fac_k(d, k), d.n, d.kl, d.uw, tmp);
-  __syncthreads();
-  for (int i = tid; i < S; i += blockDim.x) x[d.colmap[i]] = tmp[i];  // y in ABI order
-  __syncthreads();
-  for (int s = tid; s < S; s += blockDim.x) {   // x = D_c R y
-    cplx y = x[s];
-    const double rh = d.rho[s];
-    if (rh != 0.0) y = cadd(y, cscale(x[s + 2], rh));
-    tmp[s] = d.colph[s] ? cmul_i(y) : y;
+  return cmk(sr, si);
+}
+// sum_n T_n(x_j) c[n] over N modes at node j.
+__device__ __forceinline__ cplx cheb_sum_modes(const double* ct, const cplx* c, int j, int N, int Ng) {
+  const int P = 4 * Ng, dm = 2 * (Ng - j) - 1;
+  int M = 0;
+  double sr = 0.0, si = 0.0;
+#pragma unroll 8
+  for (int n = 0; n < N; ++n) {
+    const double t = ct[M];
+    sr += t * c[n].x;
+    si += t * c[n].y;
+    M += dm;
+    if (M >= P) M -= P;
   }
-  __syncthreads();
-  for (int s = tid; s < S; s += blockDim.x) x[s] = tmp[s];
-  __syncthreads();
+  return cmk(sr, si);
 }
 
-// A^H z = g: g in ABI column slots, result z in ABI row slots.
-__device__ void rbc_solve_h(const RbcDev& d, int k, const cplx* g, cplx* z, cplx* tmp) {
-  const int tid = threadIdx.x, S = d.S;
-  for (int i = tid; i < S; i += blockDim.x) {
+// The banded solves run in solver coordinates: real-ified (phases D_r, D_c), recombined (R)
+// and interleaved by mode (rowmap, colmap).
+// A x = r:  vA = (D_r r)[rowmap];  B y = vA;  x = D_c R y.
+// A^H z = g: vA = (R^T D_c^H g)[colmap];  B^T w = vA;  z[rowmap] = D_r^H w.
+
+// r (ABI row slots) -> vA (solver rows).  Block-wide, ends with a barrier.
+__device__ void rbc_gather(const RbcDev& d, const cplx* r, cplx* vA) {
+  for (int i = threadIdx.x; i < d.S + SPS_PAD; i += blockDim.x) {
+    if (i >= d.S) { vA[i] = czero(); continue; }   // zero tail read by the block solver
+    const int s = d.rowmap[i];
+    const cplx v = r[s];
+    vA[i] = d.rowph[s] ? cmul_mi(v) : v;
+  }
+  __syncthreads();
+}
+// vA (solution y, solver columns) -> x = D_c R y (ABI column slots); vB scratch.
+__device__ void rbc_scatter(const RbcDev& d, const cplx* vA, cplx* vB, cplx* x) {
+  for (int i = threadIdx.x; i < d.S; i += blockDim.x) vB[d.colmap[i]] = vA[i];
+  __syncthreads();
+  for (int s = threadIdx.x; s < d.S; s += blockDim.x) {
+    cplx y = vB[s];
+    const double rh = d.rho[s];
+    if (rh != 0.0) y = cadd(y, cscale(vB[s + 2], rh));
+    x[s] = d.colph[s] ? cmul_i(y) : y;
+  }
+  __syncthreads();
+}
+// g (ABI column slots) -> vA = (R^T D_c^H g)[colmap].
+__device__ void rbc_gather_h(const RbcDev& d, const cplx* g, cplx* vA) {
+  for (int i = threadIdx.x; i < d.S + SPS_PAD; i += blockDim.x) {
+    if (i >= d.S) { vA[i] = czero(); continue; }   // zero tail read by the block solver
     const int s = d.colmap[i];
     cplx h = g[s];
     if (d.colph[s]) h = cmul_mi(h);
@@ -302,14 +330,27 @@ __device__ void rbc_solve_h(const RbcDev& d, int k, const cplx* g, cplx* z, cplx
         h = cadd(h, cscale(h2, rh));
       }
     }
-    tmp[i] = h;
+    vA[i] = h;
   }
   __syncthreads();
-  if (tid < SPS_WAVE) band_solve_t_wave(fac_k(d, k), d.n, d.kl, d.uw, tmp);
-  __syncthreads();
-  for (int i = tid; i < S; i += blockDim.x) {
+}
+// vA (solver rows) -> z (ABI row slots) = D_r^H w.
+__device__ void rbc_scatter_h(const RbcDev& d, const cplx* vA, cplx* z) {
+  for (int i = threadIdx.x; i < d.S; i += blockDim.x) {
     const int s = d.rowmap[i];
-    z[s] = d.rowph[s] ? cmul_i(tmp[i]) : tmp[i];
+    z[s] = d.rowph[s] ? cmul_i(vA[i]) : vA[i];
+  }
+  __syncthreads();
+}
+// Write the prefetched block operators into LDS and solve in place on vA (forward or
+// transposed); waves 0 and 1 take the real and imaginary parts.  Block-wide.
+__device__ void rbc_solve_staged(const RbcDev& d, const OpsRegs& regs, double* ops_lds, cplx* vA, bool transposed) {
+  ops_store(regs, d.opsize, ops_lds);
+  __syncthreads();
+  if (threadIdx.x < 2 * SPS_WAVE) {
+    double* b = reinterpret_cast<double*>(vA) + (threadIdx.x >> 6);
+    if (transposed) blk_solve_t_part(ops_lds, blk_count(d.n), b);
+    else blk_solve_part(ops_lds, blk_count(d.n), b);
   }
   __syncthreads();
 }
@@ -328,35 +369,76 @@ struct KfArgs {
   int mode;
 };
 
+// LDS: vA, vB (S complex each) persist; the rest is a union reused by the phases
+// (transforms and right-hand side | block operators of the solve | output transforms).
 __global__ void __launch_bounds__(NT) rbc_kfwd(RbcDev d, KfArgs a) {
   extern __shared__ double smem_d[];
   cplx* sm = reinterpret_cast<cplx*>(smem_d);
   const int k = blockIdx.x, tid = threadIdx.x;
   const int N = d.N, S = d.S, K = d.K, Ngz = d.Ngz;
-  cplx* xa = sm;               // S : stage-0 state / solution
-  cplx* xb = xa + S;           // S : stage-1 state
-  cplx* rr = xb + S;           // S : right-hand side
-  cplx* tmp = rr + S;          // S
-  cplx* nlz = tmp + S;         // 3*Ngz
-  cplx* nh = nlz + 3 * Ngz;    // 3*N  (N-hat, then S10 N-hat)
-  cplx* fr = nh + 3 * N;       // 3*N
-  cplx* cf = fr + 3 * N;       // 6*N  coefficient fields for the backward transform
   const int mode = a.mode;
+  cplx* vA = sm;                // S + SPS_PAD : right-hand side, then solution / state
+  cplx* vB = vA + S + SPS_PAD;  // S : scratch
+  cplx* un = vB + S;            // union
+  // phase A views
+  cplx* xa = un;                // S : stage-0 state
+  cplx* xb = xa + S;            // S : stage-1 state
+  cplx* rr = xb + S;            // S : right-hand side (equation slots)
+  cplx* nlz = rr + S;           // 3*Ngz
+  cplx* nh = nlz + 3 * Ngz;     // 3*N  N-hat
+  cplx* fr = nh + 3 * N;        // 3*N  S10 N-hat
+  double* ct = reinterpret_cast<double*>(fr + 3 * N);   // 4*Ngz cosines
 
+  const bool solving = (mode == KF_STAGE1 || mode == KF_STAGE2 || mode == KF_SOLVE);
+  OpsRegs opsr;
+  if (solving) ops_issue(d.ops + (size_t)k * d.opsize, d.opsize, opsr);
+  if (mode == KF_STAGE1 || mode == KF_STAGE2) {
+    // all phase-A global reads issued together
+    cplx rx0[3], rx1[3], rf0[2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int s = tid + i * NT;
+      rx0[i] = (s < S) ? a.X0[(size_t)k * S + s] : czero();
+      rx1[i] = (mode == KF_STAGE2 && s < S) ? a.X1[(size_t)k * S + s] : czero();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int e = tid + i * NT;
+      rf0[i] = (mode == KF_STAGE2 && e < 3 * N) ? a.F0[(size_t)k * 3 * N + e] : czero();
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int s = tid + i * NT;
+      if (s < S) {
+        xa[s] = rx0[i];
+        xb[s] = rx1[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int e = tid + i * NT;
+      if (e < 3 * N) vB[e] = rf0[i];   // stage-0 F (stage 2); vB is free until the solve
+    }
+  }
+  const cplx* f0s = vB;
   if (mode == KF_STAGE1 || mode == KF_STAGE2 || mode == KF_EVALF) {
-    for (int e = tid; e < 3 * Ngz; e += NT) nlz[e] = a.nl[(size_t)e * K + k];
+    stage_cos(d.cosz, ct, Ngz);
+    cplx rn[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int e = tid + i * NT;
+      rn[i] = (e < 3 * Ngz) ? a.nl[(size_t)e * K + k] : czero();
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int e = tid + i * NT;
+      if (e < 3 * Ngz) nlz[e] = rn[i];
+    }
     __syncthreads();
     // Chebyshev forward transform (truncating) of the three nonlinear terms
     for (int e = tid; e < 3 * N; e += NT) {
       const int f = e / N, n = e - f * N;
-      double sr = 0.0, si = 0.0;
-      const cplx* v = nlz + f * Ngz;
-      for (int j = 0; j < Ngz; ++j) {
-        const double c = d.Cf_nj[n * Ngz + j];
-        sr += c * v[j].x;
-        si += c * v[j].y;
-      }
-      nh[e] = cmk(sr, si);
+      nh[e] = cscale(cheb_sum_nodes(ct, nlz + f * Ngz, n, Ngz), (n == 0 ? 1.0 : 2.0) / Ngz);
     }
     __syncthreads();
     for (int e = tid; e < 3 * N; e += NT) {
@@ -364,35 +446,23 @@ __global__ void __launch_bounds__(NT) rbc_kfwd(RbcDev d, KfArgs a) {
       fr[e] = s10_at(nh + f * N, n, N);
     }
     __syncthreads();
-  }
-  if (mode == KF_EVALF) {
-    for (int s = tid; s < S; s += NT) {
-      cplx v = (s < 3 * N) ? fr[s] : czero();
-      if (k == 0 && s == 4 * N + 4) v = cadd(v, cmk(1.0, 0.0));
-      a.Xout[(size_t)k * S + s] = v;
+    if (mode == KF_EVALF) {
+      for (int s = tid; s < S; s += NT) {
+        cplx v = (s < 3 * N) ? fr[s] : czero();
+        if (k == 0 && s == 4 * N + 4) v = cadd(v, cmk(1.0, 0.0));
+        a.Xout[(size_t)k * S + s] = v;
+      }
+      return;
     }
-    return;
+    if (mode == KF_STAGE1)
+      for (int e = tid; e < 3 * N; e += NT) a.F0[(size_t)k * 3 * N + e] = fr[e];
   }
-  if (mode == KF_STAGE1) {
-    for (int e = tid; e < 3 * N; e += NT) a.F0[(size_t)k * 3 * N + e] = fr[e];
-  }
-  if (mode == KF_STAGE1 || mode == KF_STAGE2 || mode == KF_ZGRID) {
-    for (int s = tid; s < S; s += NT) xa[s] = a.X0[(size_t)k * S + s];
-  }
-  if (mode == KF_STAGE2) {
-    for (int s = tid; s < S; s += NT) xb[s] = a.X1[(size_t)k * S + s];
-  }
-  if (mode == KF_SOLVE) {
-    for (int s = tid; s < S; s += NT) rr[s] = a.X0[(size_t)k * S + s];
-  }
-  __syncthreads();
-
   if (mode == KF_STAGE1 || mode == KF_STAGE2) {
     const double dt = a.dt, g = a.g, dl = a.dl;
     for (int s = tid; s < S; s += NT) {
       const MLRow r0 = ml_row(d, k, xa, s);
       const bool bc0 = (k == 0 && s == 4 * N + 4);
-      cplx f0 = (s < 3 * N) ? ((mode == KF_STAGE1) ? fr[s] : a.F0[(size_t)k * 3 * N + s]) : czero();
+      cplx f0 = (s < 3 * N) ? ((mode == KF_STAGE1) ? fr[s] : f0s[s]) : czero();
       if (bc0) f0 = cadd(f0, cmk(1.0, 0.0));
       cplx rhs;
       if (mode == KF_STAGE1) {
@@ -408,32 +478,35 @@ __global__ void __launch_bounds__(NT) rbc_kfwd(RbcDev d, KfArgs a) {
       rr[s] = rhs;
     }
     __syncthreads();
+  } else if (mode == KF_SOLVE) {
+    for (int s = tid; s < S; s += NT) rr[s] = a.X0[(size_t)k * S + s];
+    __syncthreads();
   }
-  if (mode != KF_ZGRID) {
-    rbc_solve(d, k, rr, xa, tmp);   // xa <- solution
-    for (int s = tid; s < S; s += NT) a.Xout[(size_t)k * S + s] = xa[s];
+  if (mode == KF_ZGRID) {
+    for (int s = tid; s < S; s += NT) vA[s] = a.X0[(size_t)k * S + s];
+    __syncthreads();
+  } else {
+    rbc_gather(d, rr, vA);
+    rbc_solve_staged(d, opsr, reinterpret_cast<double*>(un), vA, false);
+    rbc_scatter(d, vA, vB, vA);   // vA <- new state (ABI slots)
+    for (int s = tid; s < S; s += NT) a.Xout[(size_t)k * S + s] = vA[s];
     if (mode == KF_STAGE2 && tid < SPS_WAVE) {
       int bad = 0;
-      for (int s = tid; s < S; s += SPS_WAVE) bad |= !(isfinite(xa[s].x) && isfinite(xa[s].y));
+      for (int s = tid; s < S; s += SPS_WAVE) bad |= !(isfinite(vA[s].x) && isfinite(vA[s].y));
       if (__any(bad) && tid == 0) atomicOr(d.err, 2);
     }
   }
   if (a.zg == nullptr || mode == KF_SOLVE) return;
-  // backward Chebyshev transforms of u, w, b and their z-derivatives
-  for (int e = tid; e < 3 * N; e += NT) cf[e] = xa[e];
-  __syncthreads();
-  if (tid < 3) dz_series(xa + tid * N, cf + (3 + tid) * N, N);
+  // backward Chebyshev transforms of u, w, b (from vA) and of their z-derivatives
+  double* ct2 = reinterpret_cast<double*>(un);
+  cplx* dz = reinterpret_cast<cplx*>(ct2 + 4 * Ngz);   // 3*N
+  stage_cos(d.cosz, ct2, Ngz);
+  if (tid < 3) dz_series(vA + tid * N, dz + tid * N, N);
   __syncthreads();
   for (int e = tid; e < 6 * Ngz; e += NT) {
     const int f = e / Ngz, j = e - f * Ngz;
-    const cplx* c = cf + f * N;
-    double sr = 0.0, si = 0.0;
-    for (int n = 0; n < N; ++n) {
-      const double t = d.Cb_jn[j * N + n];
-      sr += t * c[n].x;
-      si += t * c[n].y;
-    }
-    a.zg[(size_t)e * K + k] = cmk(sr, si);
+    const cplx* c = (f < 3) ? vA + f * N : dz + (f - 3) * N;
+    a.zg[(size_t)e * K + k] = cheb_sum_modes(ct2, c, j, N, Ngz);
   }
 }
 
@@ -467,6 +540,8 @@ __global__ void __launch_bounds__(NT) rbc_xfwd(RbcDev d, XfArgs a) {
   cplx* spec = sm;                 // 9*K : u w b uz wz bz ux wx bx
   cplx* buf0 = spec + 9 * K;       // 4*Ngx
   cplx* buf1 = buf0 + 4 * Ngx;     // 4*Ngx
+  cplx* tw = buf1 + 4 * Ngx;       // Ngx twiddles
+  for (int e = tid; e < Ngx; e += NT) tw[e] = d.twx[e];
   for (int e = tid; e < 6 * K; e += NT) {
     const int f = e / K, m = e - f * K;
     spec[e] = a.zg[((size_t)f * Ngz + j) * K + m];
@@ -487,7 +562,7 @@ __global__ void __launch_bounds__(NT) rbc_xfwd(RbcDev d, XfArgs a) {
     buf0[e] = pack_pair(U, V, m, Ngx, K, 1.0);
   }
   __syncthreads();
-  cplx* g = lds_fft(buf0, buf1, d.px, d.twx, +1, 4, Ngx, tid, NT);
+  cplx* g = lds_fft(buf0, buf1, d.px, tw, +1, 4, Ngx, tid, NT);
   cplx* o = (g == buf0) ? buf1 : buf0;
   for (int x = tid; x < Ngx; x += NT) {
     const double u = g[x].x, w = g[x].y;
@@ -501,7 +576,7 @@ __global__ void __launch_bounds__(NT) rbc_xfwd(RbcDev d, XfArgs a) {
     o[Ngx + x] = cmk(Nb, 0.0);
   }
   __syncthreads();
-  cplx* h = lds_fft(o, g, d.px, d.twx, -1, 2, Ngx, tid, NT);
+  cplx* h = lds_fft(o, g, d.px, tw, -1, 2, Ngx, tid, NT);
   const double inv = 1.0 / Ngx;
   for (int e = tid; e < 3 * K; e += NT) {
     const int f = e / K, m = e - f * K;
@@ -529,6 +604,8 @@ __global__ void __launch_bounds__(NT) rbc_xadj(RbcDev d, XaArgs a) {
   cplx* spec = sm;                  // 12*K: u w b uz wz bz ux wx bx | nub nwb nbb
   cplx* buf0 = spec + 12 * K;       // 6*Ngx
   cplx* buf1 = buf0 + 6 * Ngx;      // 6*Ngx
+  cplx* tw = buf1 + 6 * Ngx;        // Ngx twiddles
+  for (int e = tid; e < Ngx; e += NT) tw[e] = d.twx[e];
   for (int e = tid; e < 6 * K; e += NT) {
     const int f = e / K, m = e - f * K;
     spec[e] = a.zg[((size_t)f * Ngz + j) * K + m];
@@ -553,7 +630,7 @@ __global__ void __launch_bounds__(NT) rbc_xadj(RbcDev d, XaArgs a) {
     buf0[e] = pack_pair(U, V, m, Ngx, K, q >= 4 ? 0.5 : 1.0);
   }
   __syncthreads();
-  cplx* g = lds_fft(buf0, buf1, d.px, d.twx, +1, 6, Ngx, tid, NT);
+  cplx* g = lds_fft(buf0, buf1, d.px, tw, +1, 6, Ngx, tid, NT);
   cplx* o = (g == buf0) ? buf1 : buf0;
   const double inv = 1.0 / Ngx;
   for (int x = tid; x < Ngx; x += NT) {
@@ -571,7 +648,7 @@ __global__ void __launch_bounds__(NT) rbc_xadj(RbcDev d, XaArgs a) {
     o[3 * Ngx + x] = cmk(-Nbb * u, -Nbb * w);      // bx_bar, bz_bar
   }
   __syncthreads();
-  cplx* h = lds_fft(o, g, d.px, d.twx, -1, 4, Ngx, tid, NT);
+  cplx* h = lds_fft(o, g, d.px, tw, -1, 4, Ngx, tid, NT);
   // unpack: A_m = (Z_m + conj Z_-m)/2, B_m = (Z_m - conj Z_-m)/(2i); weight 1 at m = 0, 2 else
   for (int e = tid; e < 3 * K; e += NT) {
     const int f = e / K, m = e - f * K;
@@ -607,21 +684,16 @@ struct KaArgs {
   int flags;
 };
 
-// c_bar for u, w, b from zbar (adjoint Chebyshev backward transform + derivative transposes)
-__device__ void zbar_to_coeffs(const RbcDev& d, const KaArgs& a, int k, cplx* zb, cplx* cb, cplx* out) {
+// c_bar for u, w, b from zbar (adjoint Chebyshev backward transform + derivative transposes).
+// zb: 6*Ngz, cb: 6*N, out: 3*N, ct: staged cosines.  Block-wide.
+__device__ void zbar_to_coeffs(const RbcDev& d, const KaArgs& a, int k, const double* ct, cplx* zb, cplx* cb,
+                               cplx* out) {
   const int tid = threadIdx.x, N = d.N, Ngz = d.Ngz, K = d.K;
   for (int e = tid; e < 6 * Ngz; e += NT) zb[e] = a.zbar[(size_t)e * K + k];
   __syncthreads();
   for (int e = tid; e < 6 * N; e += NT) {
     const int f = e / N, n = e - f * N;
-    const cplx* v = zb + f * Ngz;
-    double sr = 0.0, si = 0.0;
-    for (int j = 0; j < Ngz; ++j) {
-      const double t = d.Cb_nj[n * Ngz + j];
-      sr += t * v[j].x;
-      si += t * v[j].y;
-    }
-    cb[e] = cmk(sr, si);
+    cb[e] = cheb_sum_nodes(ct, zb + f * Ngz, n, Ngz);
   }
   __syncthreads();
   if (tid < 3) dz_series_t(cb + (3 + tid) * N, out + tid * N, N);
@@ -630,116 +702,137 @@ __device__ void zbar_to_coeffs(const RbcDev& d, const KaArgs& a, int k, cplx* zb
   __syncthreads();
 }
 
-// cotangent G (ABI rows) of F -> nlbar (S10^T then adjoint Chebyshev forward transform)
-__device__ void g_to_nlbar(const RbcDev& d, const KaArgs& a, int k, const cplx* G, cplx* nhb) {
+// cotangent G (equation slots) of F -> nlbar (S10^T, then the transposed Chebyshev forward
+// transform).  nhb: 3*N scratch.  Block-wide.
+__device__ void g_to_nlbar(const RbcDev& d, const KaArgs& a, int k, const double* ct, const cplx* G, cplx* nhb) {
   const int tid = threadIdx.x, N = d.N, Ngz = d.Ngz, K = d.K;
   for (int e = tid; e < 3 * N; e += NT) {
     const int f = e / N, m = e - f * N;
-    nhb[e] = s10t_at(G + f * N, m, N);
+    nhb[e] = cscale(s10t_at(G + f * N, m, N), (m == 0 ? 1.0 : 2.0) / Ngz);
   }
   __syncthreads();
   for (int e = tid; e < 3 * Ngz; e += NT) {
     const int f = e / Ngz, j = e - f * Ngz;
-    const cplx* c = nhb + f * N;
-    double sr = 0.0, si = 0.0;
-    for (int n = 0; n < N; ++n) {
-      const double t = d.Cf_jn[j * N + n];
-      sr += t * c[n].x;
-      si += t * c[n].y;
-    }
-    a.nlbar[(size_t)e * K + k] = cmk(sr, si);
+    a.nlbar[(size_t)e * K + k] = cheb_sum_modes(ct, nhb + f * N, j, N, Ngz);
   }
 }
 
+// LDS: vA, vB (S complex each) persist; the rest is a union of phase buffers and the
+// staged block operators.
 __global__ void __launch_bounds__(NT) rbc_kadj(RbcDev d, KaArgs a) {
   extern __shared__ double smem_d[];
   cplx* sm = reinterpret_cast<cplx*>(smem_d);
   const int k = blockIdx.x, tid = threadIdx.x;
   const int N = d.N, S = d.S, Ngz = d.Ngz;
-  cplx* xb = sm;               // S  cotangent of a state
-  cplx* y2 = xb + S;           // S
-  cplx* y1 = y2 + S;           // S
-  cplx* tmp = y1 + S;          // S
-  cplx* gg = tmp + S;          // S  cotangent of F (rows)
-  cplx* zb = gg + S;           // 6*Ngz
-  cplx* cb = zb + 6 * Ngz;     // 6*N
-  cplx* vv = cb + 6 * N;       // 3*N
   const int fl = a.flags;
   const double dt = a.dt, g = a.g, dl = a.dl;
+  cplx* vA = sm;                // S + SPS_PAD : solver-order vector
+  cplx* vB = vA + S + SPS_PAD;  // S : solve result in equation slots (Y)
+  cplx* un = vB + S;            // union
+  double* ops = reinterpret_cast<double*>(un);
+  // phase views (before the solve)
+  double* ct = reinterpret_cast<double*>(un);           // 4*Ngz
+  cplx* xbar = reinterpret_cast<cplx*>(ct + 4 * Ngz);   // S   cotangent of a state
+  cplx* y2 = xbar + S;                                  // S
+  cplx* zb = y2 + S;                                    // 6*Ngz
+  cplx* cb = zb + 6 * Ngz;                              // 6*N
+  cplx* vv = cb + 6 * N;                                // 3*N
+  // views after the solve
+  cplx* p_y2 = xbar;                                    // S
+  cplx* p_t = y2;                                       // S  (Y1 + Y2)
+  cplx* p_g = zb;                                       // S  cotangent of F
+  cplx* p_nh = p_g + S;                                 // 3*N
 
+  OpsRegs opsr;
+  if (fl & (KA_A | KA_B | KA_SOLVE_T)) ops_issue(d.ops + (size_t)k * d.opsize, d.opsize, opsr);
+  stage_cos(d.cosz, ct, Ngz);
   if (fl & KA_SOLVE_T) {
-    for (int s = tid; s < S; s += NT) xb[s] = a.Xb_in[(size_t)k * S + s];
+    for (int s = tid; s < S; s += NT) xbar[s] = a.Xb_in[(size_t)k * S + s];
     __syncthreads();
-    rbc_solve_h(d, k, xb, y1, tmp);
-    for (int s = tid; s < S; s += NT) a.Xb_out[(size_t)k * S + s] = y1[s];
+    rbc_gather_h(d, xbar, vA);
+    rbc_solve_staged(d, opsr, ops, vA, true);
+    rbc_scatter_h(d, vA, vB);
+    for (int s = tid; s < S; s += NT) a.Xb_out[(size_t)k * S + s] = vB[s];
     return;
   }
   if (fl & KA_G) {
-    for (int s = tid; s < S; s += NT) gg[s] = a.Xb_in[(size_t)k * S + s];
+    for (int s = tid; s < S; s += NT) p_g[s] = a.Xb_in[(size_t)k * S + s];
     __syncthreads();
-    g_to_nlbar(d, a, k, gg, cb);
+    g_to_nlbar(d, a, k, ct, p_g, p_nh);
     return;
   }
   if (fl & KA_C) {
-    zbar_to_coeffs(d, a, k, zb, cb, vv);
+    zbar_to_coeffs(d, a, k, ct, zb, cb, vv);
     for (int s = tid; s < S; s += NT) {
       cplx v = a.acc ? a.acc[(size_t)k * S + s] : czero();
       if (s < 3 * N) v = cadd(v, vv[s]);
-      xb[s] = v;
+      xbar[s] = v;
     }
     __syncthreads();
     if (!(fl & KA_A)) {
-      for (int s = tid; s < S; s += NT) a.Xb_out[(size_t)k * S + s] = xb[s];
+      for (int s = tid; s < S; s += NT) a.Xb_out[(size_t)k * S + s] = xbar[s];
       return;
     }
   } else if (fl & KA_A) {
-    for (int s = tid; s < S; s += NT) xb[s] = a.Xb_in[(size_t)k * S + s];
+    for (int s = tid; s < S; s += NT) xbar[s] = a.Xb_in[(size_t)k * S + s];
     __syncthreads();
   }
   if (fl & KA_A) {
-    rbc_solve_h(d, k, xb, y2, tmp);
+    // Y2 = A^{-H} xbar;  F cotangent of the stage-1 state: dt (1 - delta) Y2
+    rbc_gather_h(d, xbar, vA);
+    rbc_solve_staged(d, opsr, ops, vA, true);
+    rbc_scatter_h(d, vA, vB);
+    stage_cos(d.cosz, ct, Ngz);
     for (int s = tid; s < S; s += NT) {
-      a.Ybuf[(size_t)k * S + s] = y2[s];
-      gg[s] = cscale(y2[s], dt * (1.0 - dl));
+      a.Ybuf[(size_t)k * S + s] = vB[s];
+      p_g[s] = cscale(vB[s], dt * (1.0 - dl));
     }
     __syncthreads();
-    g_to_nlbar(d, a, k, gg, cb);
+    g_to_nlbar(d, a, k, ct, p_g, p_nh);
     return;
   }
   if (fl & KA_B) {
-    zbar_to_coeffs(d, a, k, zb, cb, vv);
+    zbar_to_coeffs(d, a, k, ct, zb, cb, vv);
     for (int s = tid; s < S; s += NT) y2[s] = a.Ybuf[(size_t)k * S + s];
     __syncthreads();
+    // xbar_1 = F-VJP part - dt (1 - gamma) L^H Y2
     for (int s = tid; s < S; s += NT) {
       const MLRow t = mlt_col(d, k, y2, s);
       cplx v = cscale(t.l, -dt * (1.0 - g));
       if (s < 3 * N) v = cadd(v, vv[s]);
-      xb[s] = v;
+      xbar[s] = v;
     }
     __syncthreads();
-    rbc_solve_h(d, k, xb, y1, tmp);
-    for (int s = tid; s < S; s += NT) tmp[s] = cadd(y1[s], y2[s]);
+    rbc_gather_h(d, xbar, vA);
+    rbc_solve_staged(d, opsr, ops, vA, true);
+    rbc_scatter_h(d, vA, vB);     // vB = Y1
+    stage_cos(d.cosz, ct, Ngz);
+    for (int s = tid; s < S; s += NT) {
+      const cplx y2s = a.Ybuf[(size_t)k * S + s];
+      p_y2[s] = y2s;
+      p_t[s] = cadd(vB[s], y2s);
+    }
     __syncthreads();
     for (int s = tid; s < S; s += NT) {
-      const MLRow t = mlt_col(d, k, tmp, s);
+      const MLRow t = mlt_col(d, k, p_t, s);
       a.acc[(size_t)k * S + s] = t.m;
-      gg[s] = cadd(cscale(y2[s], dt * dl), cscale(y1[s], dt * g));
+      p_g[s] = cadd(cscale(p_y2[s], dt * dl), cscale(vB[s], dt * g));
     }
     __syncthreads();
-    g_to_nlbar(d, a, k, gg, cb);
+    g_to_nlbar(d, a, k, ct, p_g, p_nh);
   }
 }
 
 // ---------------------------------------------------------------------------- factor
 __global__ void __launch_bounds__(NT) rbc_factor(RbcDev d, const double* BM, const double* BL, double am,
-                                                 double bl, double* Lc, double* Uc, double* Ur, int* piv) {
+                                                 double bl, double* ops) {
   extern __shared__ double smem_d[];
   __shared__ int sh[4];
   const int k = blockIdx.x;
   const size_t bw = d.kl + d.ku + 1;
+  int* spiv = reinterpret_cast<int*>(smem_d + (size_t)d.n * (2 * d.kl + d.ku + 1));
   band_factor_block(BM + (size_t)k * d.n * bw, BL + (size_t)k * d.n * bw, am, bl, d.n, d.kl, d.ku, smem_d,
-                    sh, Lc + (size_t)k * d.n * d.kl, Uc + (size_t)k * d.n * d.uw, Ur + (size_t)k * d.n * d.uw,
-                    piv + (size_t)k * d.n, d.err);
+                    sh, spiv, ops + (size_t)k * d.opsize, d.err);
 }
 
 // ---------------------------------------------------------------------------- initial state and its adjoint
@@ -757,36 +850,30 @@ __global__ void __launch_bounds__(NT) rbc_init_x(RbcDev d, const double* grid, c
 }
 
 __global__ void __launch_bounds__(NT) rbc_init_z(RbcDev d, const cplx* tmp, cplx* X) {
+  __shared__ double ct[4 * 256];
+  __shared__ cplx col[256];
   const int k = blockIdx.x, tid = threadIdx.x, N = d.N, S = d.S, K = d.K, Nz1 = d.Nz1;
+  stage_cos(d.cosz1, ct, Nz1);
+  for (int z = tid; z < Nz1; z += NT) col[z] = tmp[(size_t)z * K + k];
+  __syncthreads();
   for (int s = tid; s < S; s += NT) {
     cplx v = czero();
     if (s >= 2 * N && s < 3 * N) {
       const int n = s - 2 * N;
-      double sr = 0.0, si = 0.0;
-      for (int z = 0; z < Nz1; ++z) {
-        const double c = d.C1f_nj[n * Nz1 + z];
-        const cplx t = tmp[(size_t)z * K + k];
-        sr += c * t.x;
-        si += c * t.y;
-      }
-      v = cmk(sr, si);
+      v = cscale(cheb_sum_nodes(ct, col, n, Nz1), (n == 0 ? 1.0 : 2.0) / Nz1);
     }
     X[(size_t)k * S + s] = v;
   }
 }
 
 __global__ void __launch_bounds__(NT) rbc_init_adj_z(RbcDev d, const cplx* Xb, cplx* tmp) {
+  __shared__ double ct[4 * 256];
+  __shared__ cplx cw[128];
   const int k = blockIdx.x, tid = threadIdx.x, N = d.N, S = d.S, K = d.K, Nz1 = d.Nz1;
-  for (int z = tid; z < Nz1; z += NT) {
-    double sr = 0.0, si = 0.0;
-    for (int n = 0; n < N; ++n) {
-      const double c = d.C1f_jn[z * N + n];
-      const cplx v = Xb[(size_t)k * S + 2 * N + n];
-      sr += c * v.x;
-      si += c * v.y;
-    }
-    tmp[(size_t)z * K + k] = cmk(sr, si);
-  }
+  stage_cos(d.cosz1, ct, Nz1);
+  for (int n = tid; n < N; n += NT) cw[n] = cscale(Xb[(size_t)k * S + 2 * N + n], (n == 0 ? 1.0 : 2.0) / Nz1);
+  __syncthreads();
+  for (int z = tid; z < Nz1; z += NT) tmp[(size_t)z * K + k] = cheb_sum_modes(ct, cw, z, N, Nz1);
 }
 
 __global__ void __launch_bounds__(NT) rbc_init_adj_x(RbcDev d, const cplx* tmp, double* gbar) {
@@ -1079,9 +1166,7 @@ class RbcProblem : public ProblemImpl {
   void factor() override {
     if (factored_) return;
     const double g = 1.0 - 1.0 / std::sqrt(2.0);
-    const size_t lds = (size_t)(2 * kl_ + ku_ + 1) * S_ * sizeof(double);
-    hipLaunchKernelGGL(rbc_factor, dim3(K_), dim3(NT), lds, stream, dv_, BM_, BL_, 1.0, desc_.dt * g,
-                       Lc_, Uc_, Ur_, piv_);
+    hipLaunchKernelGGL(rbc_factor, dim3(K_), dim3(NT), factor_lds(), stream, dv_, BM_, BL_, 1.0, desc_.dt * g, ops_);
     SPS_CHECK_LAUNCH();
     factored_ = true;
   }
@@ -1186,10 +1271,20 @@ class RbcProblem : public ProblemImpl {
 
  private:
   // ----------------------------------------------------------------- launches
-  size_t kf_lds() const { return sizeof(cplx) * (4 * S_ + 3 * Ngz_ + 12 * N_); }
-  size_t ka_lds() const { return sizeof(cplx) * (5 * S_ + 6 * Ngz_ + 9 * N_); }
-  size_t xf_lds() const { return sizeof(cplx) * (9 * K_ + 8 * Ngx_); }
-  size_t xa_lds() const { return sizeof(cplx) * (12 * K_ + 12 * Ngx_); }
+  size_t factor_lds() const { return (size_t)(2 * kl_ + ku_ + 1) * S_ * sizeof(double) + sizeof(int) * S_; }
+  size_t ops_bytes() const { return sizeof(double) * (size_t)blk_ops_size(S_); }
+  size_t kf_lds() const {
+    const size_t pre = sizeof(cplx) * (3 * S_ + 3 * Ngz_ + 6 * N_) + sizeof(double) * 4 * Ngz_;
+    const size_t post = sizeof(double) * 4 * Ngz_ + sizeof(cplx) * 3 * N_;
+    return sizeof(cplx) * (2 * S_ + SPS_PAD) + std::max({pre, post, ops_bytes()});
+  }
+  size_t ka_lds() const {
+    const size_t pre = sizeof(double) * 4 * Ngz_ + sizeof(cplx) * (2 * S_ + 6 * Ngz_ + 9 * N_);
+    const size_t post = sizeof(double) * 4 * Ngz_ + sizeof(cplx) * (3 * S_ + 3 * N_);
+    return sizeof(cplx) * (2 * S_ + SPS_PAD) + std::max({pre, post, ops_bytes()});
+  }
+  size_t xf_lds() const { return sizeof(cplx) * (9 * K_ + 9 * Ngx_); }
+  size_t xa_lds() const { return sizeof(cplx) * (12 * K_ + 13 * Ngx_); }
 
   void launch_kf(int mode, const cplx* X0, const cplx* X1, cplx* Xout, cplx* zg) {
     KfArgs a;
@@ -1297,30 +1392,15 @@ class RbcProblem : public ProblemImpl {
   // ----------------------------------------------------------------- tables
   void build_tables() {
     const int N = N_, K = K_, Ngz = Ngz_, Nz1 = desc_.nz;
-    auto Tn = [](int n, int j, int Ng) -> double {
-      // T_n at the ascending Gauss node j of Ng: cos(n * pi * (2(Ng - j) - 1) / (2 Ng)),
-      // with the integer argument reduced exactly modulo 4 Ng
-      const long long M = ((long long)n * (2LL * (Ng - j) - 1)) % (4LL * Ng);
-      return (double)cosl((long double)M * 3.14159265358979323846264338327950288L / (2.0L * Ng));
+    // cos(pi m / (2 Ng)), m < 4 Ng, in extended precision
+    auto costab = [](int Ng) {
+      std::vector<double> c(4 * Ng);
+      for (int m = 0; m < 4 * Ng; ++m)
+        c[m] = (double)cosl((long double)m * 3.14159265358979323846264338327950288L / (2.0L * Ng));
+      return c;
     };
-    std::vector<double> kx(K), Cbnj((size_t)N * Ngz), Cbjn((size_t)Ngz * N), Cfjn((size_t)Ngz * N),
-        Cfnj((size_t)N * Ngz), C1fjn((size_t)Nz1 * N), C1fnj((size_t)N * Nz1);
+    std::vector<double> kx(K);
     for (int k = 0; k < K; ++k) kx[k] = 2.0 * M_PI * k / desc_.lx;
-    for (int n = 0; n < N; ++n)
-      for (int j = 0; j < Ngz; ++j) {
-        const double t = Tn(n, j, Ngz);
-        Cbnj[(size_t)n * Ngz + j] = t;
-        Cbjn[(size_t)j * N + n] = t;
-        const double f = (n == 0 ? 1.0 : 2.0) * t / Ngz;
-        Cfjn[(size_t)j * N + n] = f;
-        Cfnj[(size_t)n * Ngz + j] = f;
-      }
-    for (int n = 0; n < N; ++n)
-      for (int j = 0; j < Nz1; ++j) {
-        const double f = (n == 0 ? 1.0 : 2.0) * Tn(n, j, Nz1) / Nz1;
-        C1fjn[(size_t)j * N + n] = f;
-        C1fnj[(size_t)n * Nz1 + j] = f;
-      }
     std::vector<double> gram((size_t)N * N);
     auto I = [](int j) { return (j % 2 == 0) ? 2.0 / (1.0 - (double)j * j) : 0.0; };
     for (int m = 0; m < N; ++m)
@@ -1336,12 +1416,8 @@ class RbcProblem : public ProblemImpl {
     dv_.nu = nu_;
     dv_.ka = ka_;
     dv_.kx = arena_.upload(kx, stream);
-    dv_.Cb_nj = arena_.upload(Cbnj, stream);
-    dv_.Cb_jn = arena_.upload(Cbjn, stream);
-    dv_.Cf_jn = arena_.upload(Cfjn, stream);
-    dv_.Cf_nj = arena_.upload(Cfnj, stream);
-    dv_.C1f_jn = arena_.upload(C1fjn, stream);
-    dv_.C1f_nj = arena_.upload(C1fnj, stream);
+    dv_.cosz = arena_.upload(costab(Ngz), stream);
+    dv_.cosz1 = arena_.upload(costab(Nz1), stream);
     dv_.twx = arena_.upload(twiddles(Ngx_), stream);
     dv_.twx1 = arena_.upload(twiddles(desc_.nx), stream);
     dv_.gram = arena_.upload(gram, stream);
@@ -1352,7 +1428,8 @@ class RbcProblem : public ProblemImpl {
     rbc_host_bands(desc_, hb);
     kl_ = hb.kl;
     ku_ = hb.ku;
-    SPS_REQUIRE(kl_ + 1 <= SPS_WAVE && kl_ + ku_ + 1 <= SPS_WAVE, "band too wide for the wave solver");
+    SPS_REQUIRE(kl_ + SPS_BLK <= SPS_TW && SPS_BLK + kl_ + ku_ <= SPS_GW, "band too wide for the block solver");
+    SPS_REQUIRE(blk_ops_size(S_) <= 2 * SPS_OPS_REG * NT, "nz too large for the staged block solver");
     BM_ = arena_.upload(hb.BM, stream);
     BL_ = arena_.upload(hb.BL, stream);
     dv_.n = S_;
@@ -1369,14 +1446,9 @@ class RbcProblem : public ProblemImpl {
   void alloc_work() {
     const size_t st = (size_t)K_ * S_;
     zsize_ = (size_t)6 * Ngz_ * K_;
-    Lc_ = arena_.alloc<double>((size_t)K_ * S_ * kl_);
-    Uc_ = arena_.alloc<double>((size_t)K_ * S_ * (kl_ + ku_ + 1));
-    Ur_ = arena_.alloc<double>((size_t)K_ * S_ * (kl_ + ku_ + 1));
-    piv_ = arena_.alloc<int>((size_t)K_ * S_);
-    dv_.fac.Lc = Lc_;
-    dv_.fac.Uc = Uc_;
-    dv_.fac.Ur = Ur_;
-    dv_.fac.piv = piv_;
+    dv_.opsize = blk_ops_size(S_);
+    ops_ = arena_.alloc<double>((size_t)K_ * dv_.opsize);
+    dv_.ops = ops_;
     err_ = arena_.alloc<int>(1);
     SPS_HIP(hipMemsetAsync(err_, 0, sizeof(int), stream));
     dv_.err = err_;
@@ -1396,7 +1468,7 @@ class RbcProblem : public ProblemImpl {
     const int nck = (desc_.max_steps + ce - 1) / ce;
     ckpt_ = arena_.alloc<cplx>((size_t)nck * st);
     seg_ = arena_.alloc<cplx>((size_t)std::min(ce, desc_.max_steps) * 2 * zsize_);
-    const size_t fac_lds = (size_t)(2 * kl_ + ku_ + 1) * S_ * sizeof(double);
+    const size_t fac_lds = factor_lds();
     const std::pair<const void*, size_t> lds[] = {{(const void*)rbc_kfwd, kf_lds()}, {(const void*)rbc_kadj, ka_lds()},
                                                   {(const void*)rbc_xfwd, xf_lds()}, {(const void*)rbc_xadj, xa_lds()},
                                                   {(const void*)rbc_factor, fac_lds}};
@@ -1412,8 +1484,8 @@ class RbcProblem : public ProblemImpl {
   double nu_, ka_;
   RbcDev dv_{};
   DevArena arena_;
-  double *BM_ = nullptr, *BL_ = nullptr, *Lc_ = nullptr, *Uc_ = nullptr, *Ur_ = nullptr, *Jpart_ = nullptr;
-  int *piv_ = nullptr, *err_ = nullptr;
+  double *BM_ = nullptr, *BL_ = nullptr, *ops_ = nullptr, *Jpart_ = nullptr;
+  int *err_ = nullptr;
   cplx *X1_, *Xw_, *Xg_, *acc_, *Ybuf_, *F0_, *zgA_, *zbar_, *nl_, *nlbar_, *itmp_, *ckpt_, *seg_;
   size_t zsize_ = 0;
   bool factored_ = false;

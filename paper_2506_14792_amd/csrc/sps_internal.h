@@ -56,56 +56,61 @@ class DevArena {
   std::vector<void*> ptrs_;
 };
 
-// HIP-event timing of one kernel class (launches bracketed on the problem's stream).
+// HIP-event timing of one kernel class: launches are bracketed by events from a pool
+// created when timing is enabled, so recording never synchronizes the stream.  Once the
+// pool is used up further launches are not timed (the first `capacity` are a sample).
 class KernelTimer {
  public:
+  static constexpr int kCapacity = 8192;
   ~KernelTimer() { release(); }
   void enable(bool on) {
     release();
     on_ = on;
-    launches_ = 0;
-    total_ms_ = 0.0;
+    if (!on) return;
+    pool_.resize(2 * kCapacity);
+    for (auto& e : pool_)
+      if (hipEventCreate(&e) != hipSuccess) { e = nullptr; on_ = false; }
+    used_ = 0;
   }
-  bool on() const { return on_; }
   void begin(hipStream_t s) {
-    if (!on_) return;
-    hipEvent_t a, b;
-    if (hipEventCreate(&a) != hipSuccess) return;
-    if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
-    (void)hipEventRecord(a, s);
-    pending_.push_back({a, b});
+    if (!on_ || used_ >= kCapacity) return;
+    (void)hipEventRecord(pool_[2 * used_], s);
+    open_ = true;
   }
   void end(hipStream_t s) {
-    if (!on_ || pending_.empty()) return;
-    (void)hipEventRecord(pending_.back().second, s);
-    if (pending_.size() >= 4096) drain();
+    if (!on_ || !open_) return;
+    (void)hipEventRecord(pool_[2 * used_ + 1], s);
+    ++used_;
+    open_ = false;
   }
   void read(long long* launches, double* total_ms) {
-    drain();
-    *launches = launches_;
-    *total_ms = total_ms_;
-    launches_ = 0;
-    total_ms_ = 0.0;
+    double tot = 0.0;
+    long long n = 0;
+    for (int i = 0; i < used_; ++i) {
+      float ms = 0.f;
+      if (hipEventSynchronize(pool_[2 * i + 1]) == hipSuccess &&
+          hipEventElapsedTime(&ms, pool_[2 * i], pool_[2 * i + 1]) == hipSuccess) {
+        tot += ms;
+        ++n;
+      }
+    }
+    used_ = 0;
+    *launches = n;
+    *total_ms = tot;
   }
 
  private:
-  void drain() {
-    for (auto& pr : pending_) {
-      float ms = 0.f;
-      if (hipEventSynchronize(pr.second) == hipSuccess && hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
-        total_ms_ += ms;
-        ++launches_;
-      }
-      (void)hipEventDestroy(pr.first);
-      (void)hipEventDestroy(pr.second);
-    }
-    pending_.clear();
+  void release() {
+    for (auto e : pool_)
+      if (e) (void)hipEventDestroy(e);
+    pool_.clear();
+    used_ = 0;
+    open_ = false;
+    on_ = false;
   }
-  void release() { drain(); }
-  bool on_ = false;
-  long long launches_ = 0;
-  double total_ms_ = 0.0;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending_;
+  bool on_ = false, open_ = false;
+  int used_ = 0;
+  std::vector<hipEvent_t> pool_;
 };
 
 class ProblemImpl {
