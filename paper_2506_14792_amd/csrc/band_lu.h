@@ -24,29 +24,31 @@ __device__ __forceinline__ double writelane_d(double v, int lane, double old) {
 // Block shapes are compile-time so every read is unconditional: the right-hand side must
 // be followed by at least SPS_PAD zero entries (positions n .. n + SPS_PAD - 1), which the
 // operators keep at zero.
-// Layout per system: T[nblk][TW][TW] (row-major) followed by G[nblk][BLK][GW].
+// Layout per system: T[nblk][TW][TS] (row-major, padded rows) followed by G[nblk][BLK][GS].
 // One real right-hand side per wave (the real and imaginary parts of a complex right-hand
 // side run on two waves): b[2*i] in LDS; operators in LDS.
 #define SPS_BLK 8
 #define SPS_TW 16     // T window: needs SPS_BLK + kl <= SPS_TW
 #define SPS_GW 36     // G width: needs SPS_BLK + uw - 1 <= SPS_GW
+#define SPS_TS 17     // row stride of T (odd: rows and columns are both read without LDS bank conflicts)
+#define SPS_GS 37     // row stride of G
 #define SPS_PAD 40    // zero tail after the right-hand side (>= SPS_GW)
 
 __host__ __device__ inline int blk_count(int n) { return (n + SPS_BLK - 1) / SPS_BLK; }
 // doubles per system (a multiple of 4, so every system's operators start 32-byte aligned)
 __host__ __device__ inline int blk_ops_size(int n) {
-  return blk_count(n) * (SPS_TW * SPS_TW + SPS_BLK * SPS_GW);
+  return ((blk_count(n) * (SPS_TW * SPS_TS + SPS_BLK * SPS_GS) + 3) / 4) * 4;
 }
 
 // x = A^{-1} b
 __device__ inline void blk_solve_part(const double* ops, int nblk, double* b) {
   const int lane = lane_id();
   const double* T = ops;
-  const double* G = ops + nblk * SPS_TW * SPS_TW;
+  const double* G = ops + nblk * SPS_TW * SPS_TS;
   const int r = lane & (SPS_TW - 1);
   for (int t = 0; t < nblk; ++t) {
     const double* v = b + 2 * (t * SPS_BLK);
-    const double* Tr = T + (t * SPS_TW + r) * SPS_TW;
+    const double* Tr = T + (t * SPS_TW + r) * SPS_TS;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
 #pragma unroll
     for (int c = 0; c < SPS_TW; c += 4) {
@@ -61,7 +63,7 @@ __device__ inline void blk_solve_part(const double* ops, int nblk, double* b) {
   const int i = lane & (SPS_BLK - 1);
   for (int t = nblk - 1; t >= 0; --t) {
     const double* v = b + 2 * (t * SPS_BLK);
-    const double* Gr = G + (t * SPS_BLK + i) * SPS_GW;
+    const double* Gr = G + (t * SPS_BLK + i) * SPS_GS;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
 #pragma unroll
     for (int c = 0; c < SPS_GW; c += 4) {
@@ -79,16 +81,16 @@ __device__ inline void blk_solve_part(const double* ops, int nblk, double* b) {
 __device__ inline void blk_solve_t_part(const double* ops, int nblk, double* b) {
   const int lane = lane_id();
   const double* T = ops;
-  const double* G = ops + nblk * SPS_TW * SPS_TW;
+  const double* G = ops + nblk * SPS_TW * SPS_TS;
   const int c = (lane < SPS_GW) ? lane : SPS_GW - 1;
   for (int t = 0; t < nblk; ++t) {
     const double* v = b + 2 * (t * SPS_BLK);
-    const double* Gc = G + t * SPS_BLK * SPS_GW + c;
+    const double* Gc = G + t * SPS_BLK * SPS_GS + c;
     double a0 = 0.0, a1 = 0.0;
 #pragma unroll
     for (int i = 0; i < SPS_BLK; i += 2) {
-      a0 = fma(Gc[i * SPS_GW], v[2 * i], a0);
-      a1 = fma(Gc[(i + 1) * SPS_GW], v[2 * i + 2], a1);
+      a0 = fma(Gc[i * SPS_GS], v[2 * i], a0);
+      a1 = fma(Gc[(i + 1) * SPS_GS], v[2 * i + 2], a1);
     }
     const double keep = (c >= SPS_BLK) ? v[2 * c] : 0.0;
     if (lane < SPS_GW) b[2 * (t * SPS_BLK + c)] = keep + (a0 + a1);
@@ -96,14 +98,14 @@ __device__ inline void blk_solve_t_part(const double* ops, int nblk, double* b) 
   const int cc = lane & (SPS_TW - 1);
   for (int t = nblk - 1; t >= 0; --t) {
     const double* v = b + 2 * (t * SPS_BLK);
-    const double* Tc = T + t * SPS_TW * SPS_TW + cc;
+    const double* Tc = T + t * SPS_TW * SPS_TS + cc;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
 #pragma unroll
     for (int rr = 0; rr < SPS_TW; rr += 4) {
-      a0 = fma(Tc[rr * SPS_TW], v[2 * rr], a0);
-      a1 = fma(Tc[(rr + 1) * SPS_TW], v[2 * rr + 2], a1);
-      a2 = fma(Tc[(rr + 2) * SPS_TW], v[2 * rr + 4], a2);
-      a3 = fma(Tc[(rr + 3) * SPS_TW], v[2 * rr + 6], a3);
+      a0 = fma(Tc[rr * SPS_TS], v[2 * rr], a0);
+      a1 = fma(Tc[(rr + 1) * SPS_TS], v[2 * rr + 2], a1);
+      a2 = fma(Tc[(rr + 2) * SPS_TS], v[2 * rr + 4], a2);
+      a3 = fma(Tc[(rr + 3) * SPS_TS], v[2 * rr + 6], a3);
     }
     const double out = (a0 + a1) + (a2 + a3);
     if (lane < SPS_TW) b[2 * (t * SPS_BLK + cc)] = out;
@@ -114,7 +116,7 @@ __device__ inline void blk_solve_t_part(const double* ops, int nblk, double* b) 
 // latency overlaps other work: ops_issue() starts all global loads of this thread's share
 // into registers, ops_store() writes them into LDS once the destination is free.
 // count (doubles) must be a multiple of 2; at most SPS_OPS_REG 16-byte loads per thread.
-#define SPS_OPS_REG 36
+#define SPS_OPS_REG 37
 struct OpsRegs {
   double2 v[SPS_OPS_REG];
 };
@@ -194,7 +196,7 @@ __device__ inline void band_factor_block(const double* __restrict__ BM, const do
   __syncthreads();
   const int nblk = blk_count(n);
   double* T = OPS;
-  double* G = OPS + nblk * SPS_TW * SPS_TW;
+  double* G = OPS + nblk * SPS_TW * SPS_TS;
   for (int e = tid; e < nblk * SPS_TW; e += nt) {
     const int t = e / SPS_TW, c = e - t * SPS_TW, tb = t * SPS_BLK;
     double v[SPS_TW];
@@ -222,7 +224,7 @@ __device__ inline void band_factor_block(const double* __restrict__ BM, const do
         if (i >= 1 && i <= km) v[r] -= ab[j * ldab + kv + i] * vp;
       }
     }
-    for (int r = 0; r < SPS_TW; ++r) T[(t * SPS_TW + r) * SPS_TW + c] = v[r];
+    for (int r = 0; r < SPS_TW; ++r) T[(t * SPS_TW + r) * SPS_TS + c] = v[r];
   }
   // G_t row i: Ui[i][c] for c < BLK (row i of the inverse of the diagonal block of U),
   // then -sum_i' Ui[i][i'] U[tb+i'][tb+c] for BLK <= c < GW
@@ -245,10 +247,10 @@ __device__ inline void band_factor_block(const double* __restrict__ BM, const do
         ui[c] = sacc / Uat(tb + c, tb + c);
       }
     }
-    double* Gr = G + (t * SPS_BLK + i) * SPS_GW;
+    double* Gr = G + (t * SPS_BLK + i) * SPS_GS;
 #pragma unroll
     for (int c = 0; c < SPS_BLK; ++c) Gr[c] = ui[c];
-    for (int c = SPS_BLK; c < SPS_GW; ++c) {
+    for (int c = SPS_BLK; c < SPS_GS; ++c) {
       double sacc = 0.0;
 #pragma unroll
       for (int ip = 0; ip < SPS_BLK; ++ip) sacc -= ui[ip] * Uat(tb + ip, tb + c);

@@ -61,7 +61,13 @@ struct RbcDev {
   const signed char* rowph;  // [S] 1: row slot multiplied by -i
   const signed char* colph;  // [S] 1: column slot multiplied by +i
   const double* rho;    // [S] X[s] = y[s] + rho[s] y[s+2]
+  // per-thread copies of the permutation tables (index i < S):
+  const int* gmap;      // rowmap[i] | rowph(rowmap[i]) << 30
+  const int* hmap;      // colmap[i] | colph(s) << 30 | colph(s-2) << 29, s = colmap[i]
+  const double* hrho;   // rho[s - 2] for s = colmap[i] (0 if s < 2)
+  const int* sflag;     // colph[i] (slot i)
   const double* gram;   // [N][N] int_0^1 T_m T_n dz
+  const double* intw;   // [N] int_0^1 T_m(2z-1) dz
   const double* ops;    // [K][opsize] block operators of the LU factors (T blocks, then G blocks)
   int opsize;
   int* err;             // bit 0 singular pivot, bit 1 non-finite state
@@ -125,9 +131,6 @@ __device__ __forceinline__ cplx dz1t_at(const cplx* y, int m, int N) {
   return (m >= 1) ? cscale(y[m - 1], 2.0 * m) : czero();
 }
 
-__device__ __forceinline__ double integ_w(int m) {  // int_0^1 T_m(2z-1) dz
-  return (m % 2 == 0) ? 1.0 / (1.0 - (double)m * m) : 0.0;
-}
 
 // Row s of (M X) and (L X) for wavenumber k.  X in ABI column slots.
 struct MLRow {
@@ -161,17 +164,26 @@ __device__ MLRow ml_row(const RbcDev& d, int k, const cplx* X, int s) {
     if (k == 0 && n == 0) l = cadd(l, tau[6]);
     r.l = l;
   } else if (s < 4 * N + 6) {
+    // boundary value at z = 0 (sum of (-1)^m c_m) or z = 1 (sum of c_m)
     const int q = s - 4 * N;
     const cplx* c = X + (q / 2) * N;
     const bool bottom = (q % 2) == 0;
-    cplx acc = czero();
-    for (int m = 0; m < N; ++m) acc = cadd(acc, (bottom && (m & 1)) ? cscale(c[m], -1.0) : c[m]);
-    r.l = acc;
+    cplx ev = czero(), od = czero();
+#pragma unroll 8
+    for (int m = 0; m < N; m += 2) {
+      ev = cadd(ev, c[m]);
+      od = cadd(od, c[m + 1]);
+    }
+    r.l = bottom ? csub(ev, od) : cadd(ev, od);
   } else {
     if (k == 0) {
-      cplx acc = czero();
-      for (int m = 0; m < N; m += 2) acc = cadd(acc, cscale(p[m], integ_w(m)));
-      r.l = acc;
+      cplx a0 = czero(), a1 = czero();
+#pragma unroll 8
+      for (int m = 0; m < N; m += 4) {
+        a0 = cadd(a0, cscale(p[m], d.intw[m]));
+        a1 = cadd(a1, cscale(p[m + 2], d.intw[m + 2]));
+      }
+      r.l = cadd(a0, a1);
     } else {
       r.l = tau[6];
     }
@@ -205,7 +217,7 @@ __device__ MLRow mlt_col(const RbcDev& d, int k, const cplx* Y, int s) {
   } else if (s < 4 * N) {
     const int m = s - 3 * N;
     cplx l = cadd(cmul_mi(cscale(s10t_at(yu, m, N), kx)), s1dzt_at(yw, m, N));
-    if (k == 0 && (m % 2 == 0)) l = cadd(l, cscale(Y[4 * N + 6], integ_w(m)));
+    if (k == 0) l = cadd(l, cscale(Y[4 * N + 6], d.intw[m]));
     r.l = l;
   } else {
     const int t = s - 4 * N;
@@ -293,52 +305,90 @@ __device__ __forceinline__ cplx cheb_sum_modes(const double* ct, const cplx* c, 
 // A x = r:  vA = (D_r r)[rowmap];  B y = vA;  x = D_c R y.
 // A^H z = g: vA = (R^T D_c^H g)[colmap];  B^T w = vA;  z[rowmap] = D_r^H w.
 
-// r (ABI row slots) -> vA (solver rows).  Block-wide, ends with a barrier.
-__device__ void rbc_gather(const RbcDev& d, const cplx* r, cplx* vA) {
-  for (int i = threadIdx.x; i < d.S + SPS_PAD; i += blockDim.x) {
-    if (i >= d.S) { vA[i] = czero(); continue; }   // zero tail read by the block solver
-    const int s = d.rowmap[i];
-    const cplx v = r[s];
-    vA[i] = d.rowph[s] ? cmul_mi(v) : v;
+// Per-thread entries of the permutation tables for indices i = tid and tid + NT (S <= 2 NT),
+// loaded once at kernel start so the gathers and scatters do not wait on global memory.
+struct MapRegs {
+  int gm[2], hm[2], cm[2], sf[2];
+  double hr[2], rh[2];
+};
+__device__ __forceinline__ void load_maps(const RbcDev& d, MapRegs& m) {
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int i = threadIdx.x + q * NT;
+    const bool ok = i < d.S;
+    m.gm[q] = ok ? d.gmap[i] : 0;
+    m.hm[q] = ok ? d.hmap[i] : 0;
+    m.cm[q] = ok ? d.colmap[i] : 0;
+    m.sf[q] = ok ? d.sflag[i] : 0;
+    m.hr[q] = ok ? d.hrho[i] : 0.0;
+    m.rh[q] = ok ? d.rho[i] : 0.0;
   }
+}
+
+// r (ABI row slots) -> vA (solver rows), zero tail.  Block-wide, ends with a barrier.
+__device__ void rbc_gather(const RbcDev& d, const MapRegs& m, const cplx* r, cplx* vA) {
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int i = threadIdx.x + q * NT;
+    if (i < d.S) {
+      const int g = m.gm[q], s = g & 0xffff;
+      const cplx v = r[s];
+      vA[i] = (g >> 30) ? cmul_mi(v) : v;
+    }
+  }
+  for (int i = d.S + threadIdx.x; i < d.S + SPS_PAD; i += NT) vA[i] = czero();
   __syncthreads();
 }
 // vA (solution y, solver columns) -> x = D_c R y (ABI column slots); vB scratch.
-__device__ void rbc_scatter(const RbcDev& d, const cplx* vA, cplx* vB, cplx* x) {
-  for (int i = threadIdx.x; i < d.S; i += blockDim.x) vB[d.colmap[i]] = vA[i];
+__device__ void rbc_scatter(const RbcDev& d, const MapRegs& m, const cplx* vA, cplx* vB, cplx* x) {
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int i = threadIdx.x + q * NT;
+    if (i < d.S) vB[m.cm[q]] = vA[i];
+  }
   __syncthreads();
-  for (int s = threadIdx.x; s < d.S; s += blockDim.x) {
-    cplx y = vB[s];
-    const double rh = d.rho[s];
-    if (rh != 0.0) y = cadd(y, cscale(vB[s + 2], rh));
-    x[s] = d.colph[s] ? cmul_i(y) : y;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int s = threadIdx.x + q * NT;
+    if (s < d.S) {
+      cplx y = vB[s];
+      const double rh = m.rh[q];
+      if (rh != 0.0) y = cadd(y, cscale(vB[s + 2], rh));
+      x[s] = m.sf[q] ? cmul_i(y) : y;
+    }
   }
   __syncthreads();
 }
-// g (ABI column slots) -> vA = (R^T D_c^H g)[colmap].
-__device__ void rbc_gather_h(const RbcDev& d, const cplx* g, cplx* vA) {
-  for (int i = threadIdx.x; i < d.S + SPS_PAD; i += blockDim.x) {
-    if (i >= d.S) { vA[i] = czero(); continue; }   // zero tail read by the block solver
-    const int s = d.colmap[i];
-    cplx h = g[s];
-    if (d.colph[s]) h = cmul_mi(h);
-    if (s >= 2) {
-      const double rh = d.rho[s - 2];
+// g (ABI column slots) -> vA = (R^T D_c^H g)[colmap], zero tail.
+__device__ void rbc_gather_h(const RbcDev& d, const MapRegs& m, const cplx* g, cplx* vA) {
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int i = threadIdx.x + q * NT;
+    if (i < d.S) {
+      const int h = m.hm[q], s = h & 0xffff;
+      cplx v = g[s];
+      if ((h >> 30) & 1) v = cmul_mi(v);
+      const double rh = m.hr[q];
       if (rh != 0.0) {
-        cplx h2 = g[s - 2];
-        if (d.colph[s - 2]) h2 = cmul_mi(h2);
-        h = cadd(h, cscale(h2, rh));
+        cplx v2 = g[s - 2];
+        if ((h >> 29) & 1) v2 = cmul_mi(v2);
+        v = cadd(v, cscale(v2, rh));
       }
+      vA[i] = v;
     }
-    vA[i] = h;
   }
+  for (int i = d.S + threadIdx.x; i < d.S + SPS_PAD; i += NT) vA[i] = czero();
   __syncthreads();
 }
 // vA (solver rows) -> z (ABI row slots) = D_r^H w.
-__device__ void rbc_scatter_h(const RbcDev& d, const cplx* vA, cplx* z) {
-  for (int i = threadIdx.x; i < d.S; i += blockDim.x) {
-    const int s = d.rowmap[i];
-    z[s] = d.rowph[s] ? cmul_i(vA[i]) : vA[i];
+__device__ void rbc_scatter_h(const RbcDev& d, const MapRegs& m, const cplx* vA, cplx* z) {
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int i = threadIdx.x + q * NT;
+    if (i < d.S) {
+      const int g = m.gm[q], s = g & 0xffff;
+      z[s] = (g >> 30) ? cmul_i(vA[i]) : vA[i];
+    }
   }
   __syncthreads();
 }
@@ -391,7 +441,11 @@ __global__ void __launch_bounds__(NT) rbc_kfwd(RbcDev d, KfArgs a) {
 
   const bool solving = (mode == KF_STAGE1 || mode == KF_STAGE2 || mode == KF_SOLVE);
   OpsRegs opsr;
-  if (solving) ops_issue(d.ops + (size_t)k * d.opsize, d.opsize, opsr);
+  MapRegs mr;
+  if (solving) {
+    ops_issue(d.ops + (size_t)k * d.opsize, d.opsize, opsr);
+    load_maps(d, mr);
+  }
   if (mode == KF_STAGE1 || mode == KF_STAGE2) {
     // all phase-A global reads issued together
     cplx rx0[3], rx1[3], rf0[2];
@@ -486,9 +540,9 @@ __global__ void __launch_bounds__(NT) rbc_kfwd(RbcDev d, KfArgs a) {
     for (int s = tid; s < S; s += NT) vA[s] = a.X0[(size_t)k * S + s];
     __syncthreads();
   } else {
-    rbc_gather(d, rr, vA);
+    rbc_gather(d, mr, rr, vA);
     rbc_solve_staged(d, opsr, reinterpret_cast<double*>(un), vA, false);
-    rbc_scatter(d, vA, vB, vA);   // vA <- new state (ABI slots)
+    rbc_scatter(d, mr, vA, vB, vA);   // vA <- new state (ABI slots)
     for (int s = tid; s < S; s += NT) a.Xout[(size_t)k * S + s] = vA[s];
     if (mode == KF_STAGE2 && tid < SPS_WAVE) {
       int bad = 0;
@@ -744,14 +798,18 @@ __global__ void __launch_bounds__(NT) rbc_kadj(RbcDev d, KaArgs a) {
   cplx* p_nh = p_g + S;                                 // 3*N
 
   OpsRegs opsr;
-  if (fl & (KA_A | KA_B | KA_SOLVE_T)) ops_issue(d.ops + (size_t)k * d.opsize, d.opsize, opsr);
+  MapRegs mr;
+  if (fl & (KA_A | KA_B | KA_SOLVE_T)) {
+    ops_issue(d.ops + (size_t)k * d.opsize, d.opsize, opsr);
+    load_maps(d, mr);
+  }
   stage_cos(d.cosz, ct, Ngz);
   if (fl & KA_SOLVE_T) {
     for (int s = tid; s < S; s += NT) xbar[s] = a.Xb_in[(size_t)k * S + s];
     __syncthreads();
-    rbc_gather_h(d, xbar, vA);
+    rbc_gather_h(d, mr, xbar, vA);
     rbc_solve_staged(d, opsr, ops, vA, true);
-    rbc_scatter_h(d, vA, vB);
+    rbc_scatter_h(d, mr, vA, vB);
     for (int s = tid; s < S; s += NT) a.Xb_out[(size_t)k * S + s] = vB[s];
     return;
   }
@@ -779,9 +837,9 @@ __global__ void __launch_bounds__(NT) rbc_kadj(RbcDev d, KaArgs a) {
   }
   if (fl & KA_A) {
     // Y2 = A^{-H} xbar;  F cotangent of the stage-1 state: dt (1 - delta) Y2
-    rbc_gather_h(d, xbar, vA);
+    rbc_gather_h(d, mr, xbar, vA);
     rbc_solve_staged(d, opsr, ops, vA, true);
-    rbc_scatter_h(d, vA, vB);
+    rbc_scatter_h(d, mr, vA, vB);
     stage_cos(d.cosz, ct, Ngz);
     for (int s = tid; s < S; s += NT) {
       a.Ybuf[(size_t)k * S + s] = vB[s];
@@ -803,9 +861,9 @@ __global__ void __launch_bounds__(NT) rbc_kadj(RbcDev d, KaArgs a) {
       xbar[s] = v;
     }
     __syncthreads();
-    rbc_gather_h(d, xbar, vA);
+    rbc_gather_h(d, mr, xbar, vA);
     rbc_solve_staged(d, opsr, ops, vA, true);
-    rbc_scatter_h(d, vA, vB);     // vB = Y1
+    rbc_scatter_h(d, mr, vA, vB);     // vB = Y1
     stage_cos(d.cosz, ct, Ngz);
     for (int s = tid; s < S; s += NT) {
       const cplx y2s = a.Ybuf[(size_t)k * S + s];
@@ -1421,6 +1479,9 @@ class RbcProblem : public ProblemImpl {
     dv_.twx = arena_.upload(twiddles(Ngx_), stream);
     dv_.twx1 = arena_.upload(twiddles(desc_.nx), stream);
     dv_.gram = arena_.upload(gram, stream);
+    std::vector<double> intw(N, 0.0);
+    for (int m = 0; m < N; m += 2) intw[m] = 1.0 / (1.0 - (double)m * m);
+    dv_.intw = arena_.upload(intw, stream);
   }
 
   void build_bands() {
@@ -1441,6 +1502,20 @@ class RbcProblem : public ProblemImpl {
     dv_.rowph = arena_.upload(hb.rowph, stream);
     dv_.colph = arena_.upload(hb.colph, stream);
     dv_.rho = arena_.upload(hb.rho, stream);
+    std::vector<int> gmap(S_), hmap(S_), sflag(S_);
+    std::vector<double> hrho(S_, 0.0);
+    for (int i = 0; i < S_; ++i) {
+      const int r = hb.rowmap[i], c = hb.colmap[i];
+      gmap[i] = r | (hb.rowph[r] ? (1 << 30) : 0);
+      hmap[i] = c | (hb.colph[c] ? (1 << 30) : 0) | ((c >= 2 && hb.colph[c - 2]) ? (1 << 29) : 0);
+      hrho[i] = (c >= 2) ? hb.rho[c - 2] : 0.0;
+      sflag[i] = hb.colph[i];
+    }
+    SPS_REQUIRE(S_ <= 2 * NT && S_ < 0xffff, "nz too large for the per-thread maps");
+    dv_.gmap = arena_.upload(gmap, stream);
+    dv_.hmap = arena_.upload(hmap, stream);
+    dv_.hrho = arena_.upload(hrho, stream);
+    dv_.sflag = arena_.upload(sflag, stream);
   }
 
   void alloc_work() {
