@@ -40,75 +40,100 @@ __host__ __device__ inline int blk_ops_size(int n) {
   return ((blk_count(n) * (SPS_TW * SPS_TS + SPS_BLK * SPS_GS) + 3) / 4) * 4;
 }
 
-// x = A^{-1} b
+// Quad-local exchanges (DPP quad_perm) of a double: lane i receives lane i^1 / i^2 of its quad.
+__device__ __forceinline__ double dpp_xor1(double v) {
+  const int64_t b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffff), 0xB1, 0xF, 0xF, false);   // [1,0,3,2]
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0xB1, 0xF, 0xF, false);
+  return __longlong_as_double(((int64_t)(uint32_t)lo) | ((int64_t)hi << 32));
+}
+__device__ __forceinline__ double dpp_xor2(double v) {
+  const int64_t b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffff), 0x4E, 0xF, 0xF, false);   // [2,3,0,1]
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x4E, 0xF, 0xF, false);
+  return __longlong_as_double(((int64_t)(uint32_t)lo) | ((int64_t)hi << 32));
+}
+
+// x = A^{-1} b for one real vector b (element x at b[2*x], n + SPS_PAD entries, zero tail), one wave.
 __device__ inline void blk_solve_part(const double* ops, int nblk, double* b) {
   const int lane = lane_id();
   const double* T = ops;
   const double* G = ops + nblk * SPS_TW * SPS_TS;
-  const int r = lane & (SPS_TW - 1);
-  for (int t = 0; t < nblk; ++t) {
-    const double* v = b + 2 * (t * SPS_BLK);
-    const double* Tr = T + (t * SPS_TW + r) * SPS_TS;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  // L sweep: output r = lane/2 (32 lanes), half h = lane&1 sums columns 8h .. 8h+7
+  {
+    const int r = (lane >> 1) & (SPS_TW - 1), h = lane & 1;
+    for (int t = 0; t < nblk; ++t) {
+      const double* v = b + 2 * (t * SPS_BLK + 8 * h);
+      const double* Tr = T + (t * SPS_TW + r) * SPS_TS + 8 * h;
+      double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-    for (int c = 0; c < SPS_TW; c += 4) {
-      a0 = fma(Tr[c], v[2 * c], a0);
-      a1 = fma(Tr[c + 1], v[2 * c + 2], a1);
-      a2 = fma(Tr[c + 2], v[2 * c + 4], a2);
-      a3 = fma(Tr[c + 3], v[2 * c + 6], a3);
+      for (int c = 0; c < 8; c += 2) {
+        a0 = fma(Tr[c], v[2 * (c)], a0);
+        a1 = fma(Tr[c + 1], v[2 * (c + 1)], a1);
+      }
+      double s = a0 + a1;
+      s += dpp_xor1(s);
+      if (lane < 2 * SPS_TW && h == 0) b[2 * (t * SPS_BLK + r)] = s;
     }
-    const double out = (a0 + a1) + (a2 + a3);
-    if (lane < SPS_TW) b[2 * (t * SPS_BLK + r)] = out;
   }
-  const int i = lane & (SPS_BLK - 1);
-  for (int t = nblk - 1; t >= 0; --t) {
-    const double* v = b + 2 * (t * SPS_BLK);
-    const double* Gr = G + (t * SPS_BLK + i) * SPS_GS;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  // U sweep: output i = lane/4 (32 lanes), quarter q = lane&3 sums columns 9q .. 9q+8
+  {
+    const int i = (lane >> 2) & (SPS_BLK - 1), q = lane & 3;
+    for (int t = nblk - 1; t >= 0; --t) {
+      const double* v = b + 2 * (t * SPS_BLK + 9 * q);
+      const double* Gr = G + (t * SPS_BLK + i) * SPS_GS + 9 * q;
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0;
 #pragma unroll
-    for (int c = 0; c < SPS_GW; c += 4) {
-      a0 = fma(Gr[c], v[2 * c], a0);
-      a1 = fma(Gr[c + 1], v[2 * c + 2], a1);
-      a2 = fma(Gr[c + 2], v[2 * c + 4], a2);
-      a3 = fma(Gr[c + 3], v[2 * c + 6], a3);
+      for (int c = 0; c < 9; c += 3) {
+        a0 = fma(Gr[c], v[2 * (c)], a0);
+        a1 = fma(Gr[c + 1], v[2 * (c + 1)], a1);
+        a2 = fma(Gr[c + 2], v[2 * (c + 2)], a2);
+      }
+      double s = (a0 + a1) + a2;
+      s += dpp_xor1(s);
+      s += dpp_xor2(s);
+      if (lane < 4 * SPS_BLK && q == 0) b[2 * (t * SPS_BLK + i)] = s;
     }
-    const double out = (a0 + a1) + (a2 + a3);
-    if (lane < SPS_BLK) b[2 * (t * SPS_BLK + i)] = out;
   }
 }
 
-// x = A^{-T} b
+// x = A^{-T} b for one real vector b (element x at b[2*x], zero tail), one wave.
 __device__ inline void blk_solve_t_part(const double* ops, int nblk, double* b) {
   const int lane = lane_id();
   const double* T = ops;
   const double* G = ops + nblk * SPS_TW * SPS_TS;
-  const int c = (lane < SPS_GW) ? lane : SPS_GW - 1;
-  for (int t = 0; t < nblk; ++t) {
-    const double* v = b + 2 * (t * SPS_BLK);
-    const double* Gc = G + t * SPS_BLK * SPS_GS + c;
-    double a0 = 0.0, a1 = 0.0;
+  // U^T sweep: output c = lane (36 lanes) sums the BLK rows of its column
+  {
+    const int c = (lane < SPS_GW) ? lane : SPS_GW - 1;
+    for (int t = 0; t < nblk; ++t) {
+      const double* v = b + 2 * (t * SPS_BLK);
+      const double* Gc = G + t * SPS_BLK * SPS_GS + c;
+      double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-    for (int i = 0; i < SPS_BLK; i += 2) {
-      a0 = fma(Gc[i * SPS_GS], v[2 * i], a0);
-      a1 = fma(Gc[(i + 1) * SPS_GS], v[2 * i + 2], a1);
+      for (int i = 0; i < SPS_BLK; i += 2) {
+        a0 = fma(Gc[i * SPS_GS], v[2 * (i)], a0);
+        a1 = fma(Gc[(i + 1) * SPS_GS], v[2 * (i + 1)], a1);
+      }
+      const double keep = (c >= SPS_BLK) ? v[2 * (c)] : 0.0;
+      if (lane < SPS_GW) b[2 * (t * SPS_BLK + c)] = keep + (a0 + a1);
     }
-    const double keep = (c >= SPS_BLK) ? v[2 * c] : 0.0;
-    if (lane < SPS_GW) b[2 * (t * SPS_BLK + c)] = keep + (a0 + a1);
   }
-  const int cc = lane & (SPS_TW - 1);
-  for (int t = nblk - 1; t >= 0; --t) {
-    const double* v = b + 2 * (t * SPS_BLK);
-    const double* Tc = T + t * SPS_TW * SPS_TS + cc;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  // L^T sweep: output c = lane/2 (32 lanes), half h sums rows 8h .. 8h+7 of column c
+  {
+    const int c = (lane >> 1) & (SPS_TW - 1), h = lane & 1;
+    for (int t = nblk - 1; t >= 0; --t) {
+      const double* v = b + 2 * (t * SPS_BLK + 8 * h);
+      const double* Tc = T + (t * SPS_TW + 8 * h) * SPS_TS + c;
+      double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-    for (int rr = 0; rr < SPS_TW; rr += 4) {
-      a0 = fma(Tc[rr * SPS_TS], v[2 * rr], a0);
-      a1 = fma(Tc[(rr + 1) * SPS_TS], v[2 * rr + 2], a1);
-      a2 = fma(Tc[(rr + 2) * SPS_TS], v[2 * rr + 4], a2);
-      a3 = fma(Tc[(rr + 3) * SPS_TS], v[2 * rr + 6], a3);
+      for (int r = 0; r < 8; r += 2) {
+        a0 = fma(Tc[r * SPS_TS], v[2 * (r)], a0);
+        a1 = fma(Tc[(r + 1) * SPS_TS], v[2 * (r + 1)], a1);
+      }
+      double s = a0 + a1;
+      s += dpp_xor1(s);
+      if (lane < 2 * SPS_TW && h == 0) b[2 * (t * SPS_BLK + c)] = s;
     }
-    const double out = (a0 + a1) + (a2 + a3);
-    if (lane < SPS_TW) b[2 * (t * SPS_BLK + cc)] = out;
   }
 }
 

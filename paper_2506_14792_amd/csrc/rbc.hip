@@ -1217,6 +1217,16 @@ class RbcProblem : public ProblemImpl {
     build_tables();
     build_bands();
     alloc_work();
+    // the reverse sweep recomputes segment j-1 on a second stream while the adjoint of segment
+    // j runs on the caller's; non-blocking so a legacy default caller stream does not serialize
+    SPS_HIP(hipStreamCreateWithFlags(&aux_, hipStreamNonBlocking));
+    for (auto& e : ev_) SPS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  ~RbcProblem() override {
+    if (aux_) (void)hipStreamSynchronize(aux_);
+    for (auto e : ev_)
+      if (e) (void)hipEventDestroy(e);
+    if (aux_) (void)hipStreamDestroy(aux_);
   }
 
   long long state_size() const override { return (long long)K_ * S_ * 2; }
@@ -1345,6 +1355,11 @@ class RbcProblem : public ProblemImpl {
   size_t xa_lds() const { return sizeof(cplx) * (12 * K_ + 13 * Ngx_); }
 
   void launch_kf(int mode, const cplx* X0, const cplx* X1, cplx* Xout, cplx* zg) {
+    launch_kf_on(stream, mode, X0, X1, Xout, zg);
+  }
+  // stage launches on the caller's stream are timed (on the auxiliary stream a launch may share
+  // the chip with the adjoint sweep)
+  void launch_kf_on(hipStream_t s, int mode, const cplx* X0, const cplx* X1, cplx* Xout, cplx* zg) {
     KfArgs a;
     a.X0 = X0;
     a.X1 = X1;
@@ -1356,15 +1371,15 @@ class RbcProblem : public ProblemImpl {
     a.g = 1.0 - 1.0 / std::sqrt(2.0);
     a.dl = 1.0 - 1.0 / (2.0 * a.g);
     a.mode = mode;
-    const bool timed = (mode == KF_STAGE1 || mode == KF_STAGE2);
-    if (timed) timer_.begin(stream);
-    hipLaunchKernelGGL(rbc_kfwd, dim3(K_), dim3(NT), kf_lds(), stream, dv_, a);
-    if (timed) timer_.end(stream);
+    const bool timed = (mode == KF_STAGE1 || mode == KF_STAGE2) && s == stream;
+    if (timed) timer_.begin(s);
+    hipLaunchKernelGGL(rbc_kfwd, dim3(K_), dim3(NT), kf_lds(), s, dv_, a);
+    if (timed) timer_.end(s);
     SPS_CHECK_LAUNCH();
   }
-  void launch_xf(const cplx* zg) {
+  void launch_xf(const cplx* zg, hipStream_t s = nullptr) {
     XfArgs a{zg, nl_};
-    hipLaunchKernelGGL(rbc_xfwd, dim3(Ngz_), dim3(NT), xf_lds(), stream, dv_, a);
+    hipLaunchKernelGGL(rbc_xfwd, dim3(Ngz_), dim3(NT), xf_lds(), s ? s : stream, dv_, a);
     SPS_CHECK_LAUNCH();
   }
   KaArgs ka_args(int flags) {
@@ -1391,56 +1406,74 @@ class RbcProblem : public ProblemImpl {
     SPS_CHECK_LAUNCH();
   }
 
-  cplx* slot(int s, int stage) { return seg_ + ((size_t)s * 2 + stage) * zsize_; }
+  // segment store: two buffers of z-grid fields (step s, stage q), used by alternate segments
+  cplx* slot(int buf, int s, int stage) { return seg_ + (((size_t)buf * seglen_ + s) * 2 + stage) * zsize_; }
   cplx* ckpt(int c) { return ckpt_ + (size_t)c * K_ * S_; }
 
-  // One RK222 step from X (in place).  zin: x-spectral z-grid fields of X;
+  // One RK222 step from X (in place) on stream s.  zin: x-spectral z-grid fields of X;
   // zs1: where stage 1 writes its fields; zout: where the new state's fields go (or null).
-  void rk_step(cplx* X, const cplx* zin, cplx* zs1, cplx* zout) {
-    launch_xf(zin);
-    launch_kf(KF_STAGE1, X, nullptr, X1_, zs1);
-    launch_xf(zs1);
-    launch_kf(KF_STAGE2, X, X1_, X, zout);
+  void rk_step(hipStream_t s, cplx* X, const cplx* zin, cplx* zs1, cplx* zout) {
+    launch_xf(zin, s);
+    launch_kf_on(s, KF_STAGE1, X, nullptr, X1_, zs1);
+    launch_xf(zs1, s);
+    launch_kf_on(s, KF_STAGE2, X, X1_, X, zout);
   }
 
   void forward(cplx* X, int nsteps) {
     const int ce = desc_.checkpoint_every;
     const int nseg = (nsteps + ce - 1) / ce;
     const int last0 = (nseg - 1) * ce;   // first step of the last segment: recorded now
+    const int lb = (nseg - 1) & 1;
     // fields of step n, stage q: a single rolling buffer (kernels are stream ordered) or,
     // inside the last segment, the segment store read back by the reverse sweep
-    auto zpos = [&](int n, int q) { return (n >= last0) ? slot(n - last0, q) : zgA_; };
+    auto zpos = [&](int n, int q) { return (n >= last0) ? slot(lb, n - last0, q) : zgA_; };
     launch_kf(KF_ZGRID, X, nullptr, nullptr, zpos(0, 0));
     for (int n = 0; n < nsteps; ++n) {
       if (n % ce == 0) SPS_HIP(hipMemcpyAsync(ckpt(n / ce), X, sizeof(cplx) * K_ * S_, hipMemcpyDeviceToDevice, stream));
-      rk_step(X, zpos(n, 0), zpos(n, 1), (n + 1 < nsteps) ? zpos(n + 1, 0) : nullptr);
+      rk_step(stream, X, zpos(n, 0), zpos(n, 1), (n + 1 < nsteps) ? zpos(n + 1, 0) : nullptr);
     }
     tape_steps_ = nsteps;
   }
 
-  void recompute(int seg, int len) {
-    SPS_HIP(hipMemcpyAsync(Xw_, ckpt(seg), sizeof(cplx) * K_ * S_, hipMemcpyDeviceToDevice, stream));
-    launch_kf(KF_ZGRID, Xw_, nullptr, nullptr, slot(0, 0));
-    for (int s = 0; s < len; ++s) rk_step(Xw_, slot(s, 0), slot(s, 1), (s + 1 < len) ? slot(s + 1, 0) : nullptr);
+  // re-run segment seg from its checkpoint on stream s into segment buffer seg & 1
+  void recompute(int seg, int len, hipStream_t s) {
+    const int b = seg & 1;
+    SPS_HIP(hipMemcpyAsync(Xw_, ckpt(seg), sizeof(cplx) * K_ * S_, hipMemcpyDeviceToDevice, s));
+    launch_kf_on(s, KF_ZGRID, Xw_, nullptr, nullptr, slot(b, 0, 0));
+    for (int j = 0; j < len; ++j) rk_step(s, Xw_, slot(b, j, 0), slot(b, j, 1), (j + 1 < len) ? slot(b, j + 1, 0) : nullptr);
   }
 
+  // Reverse sweep.  The recompute of segment seg-1 (auxiliary stream, scratch X1_, Xw_, nl_, F0_,
+  // segment buffer (seg-1)&1) overlaps the adjoint of segment seg (caller's stream, scratch
+  // acc_, Ybuf_, nlbar_, zbar_, segment buffer seg&1).  Events order (i) every recompute after
+  // the forward sweep, (ii) the adjoint of seg after its recompute, (iii) the recompute into a
+  // buffer after the adjoint that last read it; the caller's stream waits for all of it.
   void reverse(cplx* Xbar, int nsteps) {
     const int ce = desc_.checkpoint_every;
     const int nseg = (nsteps + ce - 1) / ce;
+    auto seglen = [&](int g) { return std::min(ce, nsteps - g * ce); };
+    hipEvent_t ev_fwd = ev_[0], ev_rec = ev_[1], ev_adj = ev_[2];
+    SPS_HIP(hipEventRecord(ev_fwd, stream));
+    SPS_HIP(hipStreamWaitEvent(aux_, ev_fwd, 0));
     bool first = true;
     for (int seg = nseg - 1; seg >= 0; --seg) {
-      const int start = seg * ce;
-      const int len = std::min(ce, nsteps - start);
-      if (seg != nseg - 1) recompute(seg, len);
-      for (int s = len - 1; s >= 0; --s) {
+      const int len = seglen(seg), b = seg & 1;
+      if (seg != nseg - 1) SPS_HIP(hipStreamWaitEvent(stream, ev_rec, 0));
+      if (seg >= 1) {
+        if (seg != nseg - 1) SPS_HIP(hipStreamWaitEvent(aux_, ev_adj, 0));
+        recompute(seg - 1, seglen(seg - 1), aux_);
+        SPS_HIP(hipEventRecord(ev_rec, aux_));
+      }
+      for (int j = len - 1; j >= 0; --j) {
         KaArgs a = ka_args(first ? KA_A : (KA_C | KA_A));
         a.Xb_in = Xbar;
         launch_ka(a);
         first = false;
-        launch_xa(slot(s, 1));
+        launch_xa(slot(b, j, 1));
         launch_ka(ka_args(KA_B));
-        launch_xa(slot(s, 0));
+        launch_xa(slot(b, j, 0));
       }
+      SPS_HIP(hipEventRecord(ev_adj, stream));
     }
     KaArgs a = ka_args(KA_C);
     a.Xb_out = Xbar;
@@ -1542,7 +1575,8 @@ class RbcProblem : public ProblemImpl {
     const int ce = desc_.checkpoint_every;
     const int nck = (desc_.max_steps + ce - 1) / ce;
     ckpt_ = arena_.alloc<cplx>((size_t)nck * st);
-    seg_ = arena_.alloc<cplx>((size_t)std::min(ce, desc_.max_steps) * 2 * zsize_);
+    seglen_ = std::min(ce, desc_.max_steps);
+    seg_ = arena_.alloc<cplx>((size_t)2 * seglen_ * 2 * zsize_);
     const size_t fac_lds = factor_lds();
     const std::pair<const void*, size_t> lds[] = {{(const void*)rbc_kfwd, kf_lds()}, {(const void*)rbc_kadj, ka_lds()},
                                                   {(const void*)rbc_xfwd, xf_lds()}, {(const void*)rbc_xadj, xa_lds()},
@@ -1563,6 +1597,9 @@ class RbcProblem : public ProblemImpl {
   int *err_ = nullptr;
   cplx *X1_, *Xw_, *Xg_, *acc_, *Ybuf_, *F0_, *zgA_, *zbar_, *nl_, *nlbar_, *itmp_, *ckpt_, *seg_;
   size_t zsize_ = 0;
+  int seglen_ = 0;
+  hipStream_t aux_ = nullptr;
+  hipEvent_t ev_[3] = {nullptr, nullptr, nullptr};
   bool factored_ = false;
   int tape_steps_ = -1;
   KernelTimer timer_;
