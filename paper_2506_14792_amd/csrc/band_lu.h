@@ -40,20 +40,6 @@ __host__ __device__ inline int blk_ops_size(int n) {
   return ((blk_count(n) * (SPS_TW * SPS_TS + SPS_BLK * SPS_GS) + 3) / 4) * 4;
 }
 
-// Quad-local exchanges (DPP quad_perm) of a double: lane i receives lane i^1 / i^2 of its quad.
-__device__ __forceinline__ double dpp_xor1(double v) {
-  const int64_t b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffff), 0xB1, 0xF, 0xF, false);   // [1,0,3,2]
-  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0xB1, 0xF, 0xF, false);
-  return __longlong_as_double(((int64_t)(uint32_t)lo) | ((int64_t)hi << 32));
-}
-__device__ __forceinline__ double dpp_xor2(double v) {
-  const int64_t b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffff), 0x4E, 0xF, 0xF, false);   // [2,3,0,1]
-  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x4E, 0xF, 0xF, false);
-  return __longlong_as_double(((int64_t)(uint32_t)lo) | ((int64_t)hi << 32));
-}
-
 // x = A^{-1} b for one real vector b (element x at b[2*x], n + SPS_PAD entries, zero tail), one wave.
 __device__ inline void blk_solve_part(const double* ops, int nblk, double* b) {
   const int lane = lane_id();
@@ -141,7 +127,7 @@ __device__ inline void blk_solve_t_part(const double* ops, int nblk, double* b) 
 // latency overlaps other work: ops_issue() starts all global loads of this thread's share
 // into registers, ops_store() writes them into LDS once the destination is free.
 // count (doubles) must be a multiple of 2; at most SPS_OPS_REG 16-byte loads per thread.
-#define SPS_OPS_REG 37
+#define SPS_OPS_REG 19
 struct OpsRegs {
   double2 v[SPS_OPS_REG];
 };

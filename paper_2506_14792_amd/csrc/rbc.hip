@@ -42,7 +42,8 @@
 namespace sps {
 namespace {
 
-constexpr int NT = 256;  // threads per block of every RBC kernel
+constexpr int NT = 256;   // threads per block of the grid-row, factor and set-up kernels
+constexpr int NTK = 512;  // threads per block of the per-wavenumber step kernels
 
 struct RbcDev {
   int K, N, S, Ngx, Ngz, Nx1, Nz1;
@@ -132,7 +133,8 @@ __device__ __forceinline__ cplx dz1t_at(const cplx* y, int m, int N) {
 }
 
 
-// Row s of (M X) and (L X) for wavenumber k.  X in ABI column slots.
+// Row s < 4N of (M X) and (L X) for wavenumber k (momentum, buoyancy and continuity rows).
+// X in ABI column slots.
 struct MLRow {
   cplx m, l;
 };
@@ -157,38 +159,43 @@ __device__ MLRow ml_row(const RbcDev& d, int k, const cplx* X, int s) {
     if (n == N - 2) l = csub(l, cscale(tau[f], 4.0 * dif));   // lifted tau_1
     if (n == N - 1) l = cadd(l, tau[3 + f]);                  // tau_2
     r.l = l;
-  } else if (s < 4 * N) {
+  } else {
     const int n = s - 3 * N;
     cplx l = cadd(cmul_i(cscale(s0_at(u, n, N), kx)), dz1_at(w, n, N));
     if (n == N - 1) l = cadd(l, tau[1]);
     if (k == 0 && n == 0) l = cadd(l, tau[6]);
     r.l = l;
-  } else if (s < 4 * N + 6) {
-    // boundary value at z = 0 (sum of (-1)^m c_m) or z = 1 (sum of c_m)
-    const int q = s - 4 * N;
-    const cplx* c = X + (q / 2) * N;
-    const bool bottom = (q % 2) == 0;
-    cplx ev = czero(), od = czero();
-#pragma unroll 8
-    for (int m = 0; m < N; m += 2) {
-      ev = cadd(ev, c[m]);
-      od = cadd(od, c[m + 1]);
-    }
-    r.l = bottom ? csub(ev, od) : cadd(ev, od);
-  } else {
-    if (k == 0) {
-      cplx a0 = czero(), a1 = czero();
-#pragma unroll 8
-      for (int m = 0; m < N; m += 4) {
-        a0 = cadd(a0, cscale(p[m], d.intw[m]));
-        a1 = cadd(a1, cscale(p[m + 2], d.intw[m + 2]));
-      }
-      r.l = cadd(a0, a1);
-    } else {
-      r.l = tau[6];
-    }
   }
   return r;
+}
+
+// Rows 4N + q (q < 7) of L X, the boundary values and the gauge row, summed by an aligned quad:
+// lane h takes the modes m = h, h + 4, ...  Row 4N + q, q < 6: field q/2 at z = 0 (q even,
+// sum of (-1)^m c_m) or z = 1 (sum of c_m).  Row 4N + 6: the mean of p at k = 0, else tau_p.
+// Every lane of the quad returns the row value.
+__device__ __forceinline__ cplx l_bc_row(const RbcDev& d, int k, const cplx* X, int q, int h) {
+  const int N = d.N;
+  double sr = 0.0, si = 0.0;
+  if (q < 6) {
+    const cplx* c = X + (q / 2) * N;
+    const double sg = ((q & 1) == 0 && (h & 1)) ? -1.0 : 1.0;   // m has the parity of h
+    for (int m = h; m < N; m += 4) {
+      sr += c[m].x;
+      si += c[m].y;
+    }
+    sr *= sg;
+    si *= sg;
+  } else if (k == 0) {
+    const cplx* p = X + 3 * N;
+    for (int m = h; m < N; m += 4) {
+      sr = fma(d.intw[m], p[m].x, sr);
+      si = fma(d.intw[m], p[m].y, si);
+    }
+  } else if (h == 0) {
+    sr = X[4 * N + 6].x;
+    si = X[4 * N + 6].y;
+  }
+  return group_sum<4>(cmk(sr, si));
 }
 
 // Column s of (M^H Y) and (L^H Y); Y in ABI row slots.
@@ -300,95 +307,167 @@ __device__ __forceinline__ cplx cheb_sum_modes(const double* ct, const cplx* c, 
   return cmk(sr, si);
 }
 
+// Mirror-symmetric forms.  The Gauss nodes j and j' = Ng-1-j are mirror images (x -> -x) and
+// T_n(-x) = (-1)^n T_n(x).  A node sum over all Ng nodes is therefore a sum over the Hc =
+// ceil(Ng/2) pairs of P_j = v_j + v_j' (n even) or Q_j = v_j - v_j' (n odd), and the mode sums
+// at node j give node j' from the same even and odd parts: v_j = E + O, v_j' = E - O.
+__host__ __device__ inline int half_nodes(int Ng) { return (Ng + 1) / 2; }
+
+// P, Q of a mirror pair (the middle node of an odd grid is its own mirror: P = Q = v_j),
+// stored as pq[2 i] = P, pq[2 i + 1] = Q.
+__device__ __forceinline__ void store_mirror_pair(cplx vj, cplx vm, bool middle, cplx* pq2) {
+  pq2[0] = middle ? vj : cadd(vj, vm);
+  pq2[1] = middle ? vj : csub(vj, vm);
+}
+
+// sum_j T_n(x_j) v_f[j] for NF fields at once from their mirror sums pq (field f at
+// pq + 2 f Hc).  SPL lanes (an aligned group) share one mode n; lane h takes pairs
+// j = h, h + SPL, ...  Every lane of the group returns the full sums.
+template <int NF, int SPL>
+__device__ __forceinline__ void nodes_to_mode(const double* ct, const cplx* pq, int Hc, int Ng, int n, int h,
+                                              cplx (&acc)[NF]) {
+  const int P4 = 4 * Ng, par = n & 1;
+  int M = (int)(((long long)n * (2 * (Ng - h) - 1)) % P4);     // T_n(x_j) = ct[n (2 (Ng - j) - 1) mod 4 Ng]
+  const int dn = (int)(((long long)2 * SPL * n) % P4);
+#pragma unroll
+  for (int f = 0; f < NF; ++f) acc[f] = czero();
+  for (int j = h; j < Hc; j += SPL) {
+    const double t = ct[M];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const cplx v = pq[2 * (f * Hc + j) + par];
+      acc[f].x = fma(t, v.x, acc[f].x);
+      acc[f].y = fma(t, v.y, acc[f].y);
+    }
+    M -= dn;
+    if (M < 0) M += P4;
+  }
+#pragma unroll
+  for (int f = 0; f < NF; ++f) acc[f] = group_sum<SPL>(acc[f]);
+}
+
+// Values at the mirror pair (j, j') of NF series (field f at c + f cstride, N modes).  Four
+// lanes (an aligned quad) share the pair; lane h sums modes n = h, h + 4, ... (one parity).
+// Returns in lane h = 0 the values at j, in lane h = 1 the values at j'.
+template <int NF>
+__device__ __forceinline__ void modes_to_pair(const double* ct, const cplx* c, int cstride, int N, int Ng, int j,
+                                              int h, cplx (&val)[NF]) {
+  const int P4 = 4 * Ng, dm = 2 * (Ng - j) - 1;
+  int M = (int)(((long long)h * dm) % P4);
+  const int step = (int)(((long long)4 * dm) % P4);
+#pragma unroll
+  for (int f = 0; f < NF; ++f) val[f] = czero();
+  for (int n = h; n < N; n += 4) {
+    const double t = ct[M];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const cplx v = c[f * cstride + n];
+      val[f].x = fma(t, v.x, val[f].x);
+      val[f].y = fma(t, v.y, val[f].y);
+    }
+    M += step;
+    if (M >= P4) M -= P4;
+  }
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    const cplx s = make_double2(val[f].x + dpp_xor2(val[f].x), val[f].y + dpp_xor2(val[f].y));   // E (h even), O (h odd)
+    const cplx o = make_double2(dpp_xor1(s.x), dpp_xor1(s.y));
+    val[f] = (h & 1) ? csub(o, s) : cadd(s, o);
+  }
+}
+
+// Coefficient m of d/dz of a T series on [0,1] (twice the T-basis derivative):
+// 4 sum_{p > m, p - m odd} p c_p, halved for m = 0.
+__device__ __forceinline__ cplx dz_coef(const cplx* c, int m, int N) {
+  double sr = 0.0, si = 0.0;
+  for (int p = m + 1; p < N; p += 2) {
+    sr = fma((double)p, c[p].x, sr);
+    si = fma((double)p, c[p].y, si);
+  }
+  const double sc = (m == 0) ? 2.0 : 4.0;
+  return cmk(sc * sr, sc * si);
+}
+// Entry n of the transpose of that map applied to y: 4 n sum_{p < n, n - p odd} y_p, with y_0 halved.
+__device__ __forceinline__ cplx dzt_coef(const cplx* y, int n) {
+  double sr = 0.0, si = 0.0;
+  for (int p = n - 1; p >= 0; p -= 2) {
+    const double w = (p == 0) ? 0.5 : 1.0;
+    sr = fma(w, y[p].x, sr);
+    si = fma(w, y[p].y, si);
+  }
+  return cmk(4.0 * n * sr, 4.0 * n * si);
+}
+
 // The banded solves run in solver coordinates: real-ified (phases D_r, D_c), recombined (R)
 // and interleaved by mode (rowmap, colmap).
 // A x = r:  vA = (D_r r)[rowmap];  B y = vA;  x = D_c R y.
 // A^H z = g: vA = (R^T D_c^H g)[colmap];  B^T w = vA;  z[rowmap] = D_r^H w.
 
-// Per-thread entries of the permutation tables for indices i = tid and tid + NT (S <= 2 NT),
-// loaded once at kernel start so the gathers and scatters do not wait on global memory.
+// Per-thread entries of the permutation tables for index i = tid (S <= NTK), loaded once at
+// kernel start so the gathers and scatters do not wait on global memory.
 struct MapRegs {
-  int gm[2], hm[2], cm[2], sf[2];
-  double hr[2], rh[2];
+  int gm, hm, cm, sf;
+  double hr, rh;
 };
 __device__ __forceinline__ void load_maps(const RbcDev& d, MapRegs& m) {
-#pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int i = threadIdx.x + q * NT;
-    const bool ok = i < d.S;
-    m.gm[q] = ok ? d.gmap[i] : 0;
-    m.hm[q] = ok ? d.hmap[i] : 0;
-    m.cm[q] = ok ? d.colmap[i] : 0;
-    m.sf[q] = ok ? d.sflag[i] : 0;
-    m.hr[q] = ok ? d.hrho[i] : 0.0;
-    m.rh[q] = ok ? d.rho[i] : 0.0;
-  }
+  const int i = threadIdx.x;
+  const bool ok = i < d.S;
+  m.gm = ok ? d.gmap[i] : 0;
+  m.hm = ok ? d.hmap[i] : 0;
+  m.cm = ok ? d.colmap[i] : 0;
+  m.sf = ok ? d.sflag[i] : 0;
+  m.hr = ok ? d.hrho[i] : 0.0;
+  m.rh = ok ? d.rho[i] : 0.0;
 }
 
 // r (ABI row slots) -> vA (solver rows), zero tail.  Block-wide, ends with a barrier.
 __device__ void rbc_gather(const RbcDev& d, const MapRegs& m, const cplx* r, cplx* vA) {
-#pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int i = threadIdx.x + q * NT;
-    if (i < d.S) {
-      const int g = m.gm[q], s = g & 0xffff;
-      const cplx v = r[s];
-      vA[i] = (g >> 30) ? cmul_mi(v) : v;
-    }
+  const int i = threadIdx.x;
+  if (i < d.S) {
+    const int s = m.gm & 0xffff;
+    const cplx v = r[s];
+    vA[i] = (m.gm >> 30) ? cmul_mi(v) : v;
+  } else if (i < d.S + SPS_PAD) {
+    vA[i] = czero();
   }
-  for (int i = d.S + threadIdx.x; i < d.S + SPS_PAD; i += NT) vA[i] = czero();
   __syncthreads();
 }
 // vA (solution y, solver columns) -> x = D_c R y (ABI column slots); vB scratch.
 __device__ void rbc_scatter(const RbcDev& d, const MapRegs& m, const cplx* vA, cplx* vB, cplx* x) {
-#pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int i = threadIdx.x + q * NT;
-    if (i < d.S) vB[m.cm[q]] = vA[i];
-  }
+  const int i = threadIdx.x;
+  if (i < d.S) vB[m.cm] = vA[i];
   __syncthreads();
-#pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int s = threadIdx.x + q * NT;
-    if (s < d.S) {
-      cplx y = vB[s];
-      const double rh = m.rh[q];
-      if (rh != 0.0) y = cadd(y, cscale(vB[s + 2], rh));
-      x[s] = m.sf[q] ? cmul_i(y) : y;
-    }
+  if (i < d.S) {
+    cplx y = vB[i];
+    if (m.rh != 0.0) y = cadd(y, cscale(vB[i + 2], m.rh));
+    x[i] = m.sf ? cmul_i(y) : y;
   }
   __syncthreads();
 }
 // g (ABI column slots) -> vA = (R^T D_c^H g)[colmap], zero tail.
 __device__ void rbc_gather_h(const RbcDev& d, const MapRegs& m, const cplx* g, cplx* vA) {
-#pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int i = threadIdx.x + q * NT;
-    if (i < d.S) {
-      const int h = m.hm[q], s = h & 0xffff;
-      cplx v = g[s];
-      if ((h >> 30) & 1) v = cmul_mi(v);
-      const double rh = m.hr[q];
-      if (rh != 0.0) {
-        cplx v2 = g[s - 2];
-        if ((h >> 29) & 1) v2 = cmul_mi(v2);
-        v = cadd(v, cscale(v2, rh));
-      }
-      vA[i] = v;
+  const int i = threadIdx.x;
+  if (i < d.S) {
+    const int s = m.hm & 0xffff;
+    cplx v = g[s];
+    if ((m.hm >> 30) & 1) v = cmul_mi(v);
+    if (m.hr != 0.0) {
+      cplx v2 = g[s - 2];
+      if ((m.hm >> 29) & 1) v2 = cmul_mi(v2);
+      v = cadd(v, cscale(v2, m.hr));
     }
+    vA[i] = v;
+  } else if (i < d.S + SPS_PAD) {
+    vA[i] = czero();
   }
-  for (int i = d.S + threadIdx.x; i < d.S + SPS_PAD; i += NT) vA[i] = czero();
   __syncthreads();
 }
 // vA (solver rows) -> z (ABI row slots) = D_r^H w.
 __device__ void rbc_scatter_h(const RbcDev& d, const MapRegs& m, const cplx* vA, cplx* z) {
-#pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int i = threadIdx.x + q * NT;
-    if (i < d.S) {
-      const int g = m.gm[q], s = g & 0xffff;
-      z[s] = (g >> 30) ? cmul_i(vA[i]) : vA[i];
-    }
+  const int i = threadIdx.x;
+  if (i < d.S) {
+    const int s = m.gm & 0xffff;
+    z[s] = (m.gm >> 30) ? cmul_i(vA[i]) : vA[i];
   }
   __syncthreads();
 }
@@ -421,11 +500,12 @@ struct KfArgs {
 
 // LDS: vA, vB (S complex each) persist; the rest is a union reused by the phases
 // (transforms and right-hand side | block operators of the solve | output transforms).
-__global__ void __launch_bounds__(NT) rbc_kfwd(RbcDev d, KfArgs a) {
+// One entry of every length-S vector per thread (S + SPS_PAD <= NTK).
+__global__ void __launch_bounds__(NTK) rbc_kfwd(RbcDev d, KfArgs a) {
   extern __shared__ double smem_d[];
   cplx* sm = reinterpret_cast<cplx*>(smem_d);
   const int k = blockIdx.x, tid = threadIdx.x;
-  const int N = d.N, S = d.S, K = d.K, Ngz = d.Ngz;
+  const int N = d.N, S = d.S, K = d.K, Ngz = d.Ngz, Hc = half_nodes(Ngz);
   const int mode = a.mode;
   cplx* vA = sm;                // S + SPS_PAD : right-hand side, then solution / state
   cplx* vB = vA + S + SPS_PAD;  // S : scratch
@@ -434,116 +514,109 @@ __global__ void __launch_bounds__(NT) rbc_kfwd(RbcDev d, KfArgs a) {
   cplx* xa = un;                // S : stage-0 state
   cplx* xb = xa + S;            // S : stage-1 state
   cplx* rr = xb + S;            // S : right-hand side (equation slots)
-  cplx* nlz = rr + S;           // 3*Ngz
-  cplx* nh = nlz + 3 * Ngz;     // 3*N  N-hat
+  cplx* pq = rr + S;            // 6*Hc mirror sums of the three nonlinear terms
+  cplx* nh = pq + 6 * Hc;       // 3*N  N-hat
   cplx* fr = nh + 3 * N;        // 3*N  S10 N-hat
   double* ct = reinterpret_cast<double*>(fr + 3 * N);   // 4*Ngz cosines
+  const bool stage = (mode == KF_STAGE1 || mode == KF_STAGE2);
 
-  const bool solving = (mode == KF_STAGE1 || mode == KF_STAGE2 || mode == KF_SOLVE);
   OpsRegs opsr;
   MapRegs mr;
-  if (solving) {
+  if (stage || mode == KF_SOLVE) {
     ops_issue(d.ops + (size_t)k * d.opsize, d.opsize, opsr);
     load_maps(d, mr);
   }
-  if (mode == KF_STAGE1 || mode == KF_STAGE2) {
-    // all phase-A global reads issued together
-    cplx rx0[3], rx1[3], rf0[2];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const int s = tid + i * NT;
-      rx0[i] = (s < S) ? a.X0[(size_t)k * S + s] : czero();
-      rx1[i] = (mode == KF_STAGE2 && s < S) ? a.X1[(size_t)k * S + s] : czero();
+  if (stage) {
+    const cplx x0 = (tid < S) ? a.X0[(size_t)k * S + tid] : czero();
+    const cplx x1 = (mode == KF_STAGE2 && tid < S) ? a.X1[(size_t)k * S + tid] : czero();
+    const cplx f0 = (mode == KF_STAGE2 && tid < 3 * N) ? a.F0[(size_t)k * 3 * N + tid] : czero();
+    if (tid < S) {
+      xa[tid] = x0;
+      xb[tid] = x1;
     }
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int e = tid + i * NT;
-      rf0[i] = (mode == KF_STAGE2 && e < 3 * N) ? a.F0[(size_t)k * 3 * N + e] : czero();
-    }
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const int s = tid + i * NT;
-      if (s < S) {
-        xa[s] = rx0[i];
-        xb[s] = rx1[i];
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int e = tid + i * NT;
-      if (e < 3 * N) vB[e] = rf0[i];   // stage-0 F (stage 2); vB is free until the solve
-    }
+    if (tid < 3 * N) vB[tid] = f0;   // stage-0 F (stage 2); vB is free until the solve
   }
   const cplx* f0s = vB;
-  if (mode == KF_STAGE1 || mode == KF_STAGE2 || mode == KF_EVALF) {
+  if (stage || mode == KF_EVALF) {
     stage_cos(d.cosz, ct, Ngz);
-    cplx rn[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const int e = tid + i * NT;
-      rn[i] = (e < 3 * Ngz) ? a.nl[(size_t)e * K + k] : czero();
-    }
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const int e = tid + i * NT;
-      if (e < 3 * Ngz) nlz[e] = rn[i];
+    if (tid < 3 * Hc) {
+      const int f = tid / Hc, j = tid - f * Hc, jm = Ngz - 1 - j;
+      const cplx vj = a.nl[((size_t)f * Ngz + j) * K + k];
+      const cplx vm = a.nl[((size_t)f * Ngz + jm) * K + k];
+      store_mirror_pair(vj, vm, jm == j, pq + 2 * (f * Hc + j));
     }
     __syncthreads();
-    // Chebyshev forward transform (truncating) of the three nonlinear terms
-    for (int e = tid; e < 3 * N; e += NT) {
-      const int f = e / N, n = e - f * N;
-      nh[e] = cscale(cheb_sum_nodes(ct, nlz + f * Ngz, n, Ngz), (n == 0 ? 1.0 : 2.0) / Ngz);
+    // Chebyshev forward transform (truncating) of the three nonlinear terms: 8 lanes per mode
+    for (int e = tid; e < 8 * N; e += NTK) {
+      const int n = e >> 3, h = e & 7;
+      cplx acc[3];
+      nodes_to_mode<3, 8>(ct, pq, Hc, Ngz, n, h, acc);
+      const double sc = (n == 0 ? 1.0 : 2.0) / Ngz;
+      if (h == 0) {
+#pragma unroll
+        for (int f = 0; f < 3; ++f) nh[f * N + n] = cscale(acc[f], sc);
+      }
     }
     __syncthreads();
-    for (int e = tid; e < 3 * N; e += NT) {
-      const int f = e / N, n = e - f * N;
-      fr[e] = s10_at(nh + f * N, n, N);
+    if (tid < 3 * N) {
+      const int f = tid / N, n = tid - f * N;
+      fr[tid] = s10_at(nh + f * N, n, N);
     }
     __syncthreads();
     if (mode == KF_EVALF) {
-      for (int s = tid; s < S; s += NT) {
-        cplx v = (s < 3 * N) ? fr[s] : czero();
-        if (k == 0 && s == 4 * N + 4) v = cadd(v, cmk(1.0, 0.0));
-        a.Xout[(size_t)k * S + s] = v;
+      if (tid < S) {
+        cplx v = (tid < 3 * N) ? fr[tid] : czero();
+        if (k == 0 && tid == 4 * N + 4) v = cadd(v, cmk(1.0, 0.0));
+        a.Xout[(size_t)k * S + tid] = v;
       }
       return;
     }
-    if (mode == KF_STAGE1)
-      for (int e = tid; e < 3 * N; e += NT) a.F0[(size_t)k * 3 * N + e] = fr[e];
+    if (mode == KF_STAGE1 && tid < 3 * N) a.F0[(size_t)k * 3 * N + tid] = fr[tid];
   }
-  if (mode == KF_STAGE1 || mode == KF_STAGE2) {
+  if (stage) {
     const double dt = a.dt, g = a.g, dl = a.dl;
-    for (int s = tid; s < S; s += NT) {
+    if (tid < 4 * N) {
+      const int s = tid;
       const MLRow r0 = ml_row(d, k, xa, s);
-      const bool bc0 = (k == 0 && s == 4 * N + 4);
-      cplx f0 = (s < 3 * N) ? ((mode == KF_STAGE1) ? fr[s] : f0s[s]) : czero();
-      if (bc0) f0 = cadd(f0, cmk(1.0, 0.0));
+      const cplx f0 = (s < 3 * N) ? ((mode == KF_STAGE1) ? fr[s] : f0s[s]) : czero();
       cplx rhs;
       if (mode == KF_STAGE1) {
         rhs = cadd(r0.m, cscale(f0, dt * g));
       } else {
-        cplx f1 = (s < 3 * N) ? fr[s] : czero();
-        if (bc0) f1 = cadd(f1, cmk(1.0, 0.0));
+        const cplx f1 = (s < 3 * N) ? fr[s] : czero();
         const MLRow r1 = ml_row(d, k, xb, s);
         cplx comb = cadd(cscale(f0, dl), cscale(f1, 1.0 - dl));
         comb = csub(comb, cscale(r1.l, 1.0 - g));
         rhs = cadd(r0.m, cscale(comb, dt));
       }
       rr[s] = rhs;
+    } else if (tid < 4 * N + 28) {
+      // boundary and gauge rows: M is zero there and F holds the boundary data (b = 1 at
+      // z = 0 for k = 0), so stage 1 gives dt g F and stage 2 dt (F - (1 - g) L X1)
+      const int q = (tid - 4 * N) >> 2, h = tid & 3;
+      const double fbc = (k == 0 && q == 4) ? 1.0 : 0.0;
+      cplx rhs;
+      if (mode == KF_STAGE1) {
+        rhs = cmk(dt * g * fbc, 0.0);
+      } else {
+        const cplx lx = l_bc_row(d, k, xb, q, h);
+        rhs = cscale(csub(cmk(fbc, 0.0), cscale(lx, 1.0 - g)), dt);
+      }
+      if (h == 0) rr[4 * N + q] = rhs;
     }
     __syncthreads();
   } else if (mode == KF_SOLVE) {
-    for (int s = tid; s < S; s += NT) rr[s] = a.X0[(size_t)k * S + s];
+    if (tid < S) rr[tid] = a.X0[(size_t)k * S + tid];
     __syncthreads();
   }
   if (mode == KF_ZGRID) {
-    for (int s = tid; s < S; s += NT) vA[s] = a.X0[(size_t)k * S + s];
+    if (tid < S) vA[tid] = a.X0[(size_t)k * S + tid];
     __syncthreads();
   } else {
     rbc_gather(d, mr, rr, vA);
     rbc_solve_staged(d, opsr, reinterpret_cast<double*>(un), vA, false);
     rbc_scatter(d, mr, vA, vB, vA);   // vA <- new state (ABI slots)
-    for (int s = tid; s < S; s += NT) a.Xout[(size_t)k * S + s] = vA[s];
+    if (tid < S) a.Xout[(size_t)k * S + tid] = vA[tid];
     if (mode == KF_STAGE2 && tid < SPS_WAVE) {
       int bad = 0;
       for (int s = tid; s < S; s += SPS_WAVE) bad |= !(isfinite(vA[s].x) && isfinite(vA[s].y));
@@ -555,12 +628,21 @@ __global__ void __launch_bounds__(NT) rbc_kfwd(RbcDev d, KfArgs a) {
   double* ct2 = reinterpret_cast<double*>(un);
   cplx* dz = reinterpret_cast<cplx*>(ct2 + 4 * Ngz);   // 3*N
   stage_cos(d.cosz, ct2, Ngz);
-  if (tid < 3) dz_series(vA + tid * N, dz + tid * N, N);
+  if (tid < 3 * N) {
+    const int f = tid / N, m = tid - f * N;
+    dz[tid] = dz_coef(vA + f * N, m, N);
+  }
   __syncthreads();
-  for (int e = tid; e < 6 * Ngz; e += NT) {
-    const int f = e / Ngz, j = e - f * Ngz;
-    const cplx* c = (f < 3) ? vA + f * N : dz + (f - 3) * N;
-    a.zg[(size_t)e * K + k] = cheb_sum_modes(ct2, c, j, N, Ngz);
+  // a quad per (field group, mirror pair): group 0 = u, w, b; group 1 = their z-derivatives
+  for (int e = tid; e < 8 * Hc; e += NTK) {
+    const int h = e & 3, it = e >> 2, grp = it / Hc, j = it - grp * Hc, jm = Ngz - 1 - j;
+    cplx val[3];
+    modes_to_pair<3>(ct2, grp == 0 ? vA : dz, N, N, Ngz, j, h, val);
+    if (h == 0 || (h == 1 && jm != j)) {
+      const int jj = (h == 0) ? j : jm;
+#pragma unroll
+      for (int f = 0; f < 3; ++f) a.zg[((size_t)(3 * grp + f) * Ngz + jj) * K + k] = val[f];
+    }
   }
 }
 
@@ -739,47 +821,67 @@ struct KaArgs {
 };
 
 // c_bar for u, w, b from zbar (adjoint Chebyshev backward transform + derivative transposes).
-// zb: 6*Ngz, cb: 6*N, out: 3*N, ct: staged cosines.  Block-wide.
-__device__ void zbar_to_coeffs(const RbcDev& d, const KaArgs& a, int k, const double* ct, cplx* zb, cplx* cb,
+// pqz: 12*Hc, cb: 6*N, out: 3*N, ct: staged cosines.  Block-wide.
+__device__ void zbar_to_coeffs(const RbcDev& d, const KaArgs& a, int k, const double* ct, cplx* pqz, cplx* cb,
                                cplx* out) {
-  const int tid = threadIdx.x, N = d.N, Ngz = d.Ngz, K = d.K;
-  for (int e = tid; e < 6 * Ngz; e += NT) zb[e] = a.zbar[(size_t)e * K + k];
-  __syncthreads();
-  for (int e = tid; e < 6 * N; e += NT) {
-    const int f = e / N, n = e - f * N;
-    cb[e] = cheb_sum_nodes(ct, zb + f * Ngz, n, Ngz);
+  const int tid = threadIdx.x, N = d.N, Ngz = d.Ngz, K = d.K, Hc = half_nodes(Ngz);
+  for (int e = tid; e < 6 * Hc; e += NTK) {
+    const int f = e / Hc, j = e - f * Hc, jm = Ngz - 1 - j;
+    const cplx vj = a.zbar[((size_t)f * Ngz + j) * K + k];
+    const cplx vm = a.zbar[((size_t)f * Ngz + jm) * K + k];
+    store_mirror_pair(vj, vm, jm == j, pqz + 2 * (f * Hc + j));
   }
   __syncthreads();
-  if (tid < 3) dz_series_t(cb + (3 + tid) * N, out + tid * N, N);
+  // transposed (unscaled) backward transform: 4 lanes per (field group of 3, mode)
+  for (int e = tid; e < 8 * N; e += NTK) {
+    const int h = e & 3, it = e >> 2, grp = it / N, n = it - grp * N;
+    cplx acc[3];
+    nodes_to_mode<3, 4>(ct, pqz + 6 * Hc * grp, Hc, Ngz, n, h, acc);
+    if (h == 0) {
+#pragma unroll
+      for (int f = 0; f < 3; ++f) cb[(3 * grp + f) * N + n] = acc[f];
+    }
+  }
   __syncthreads();
-  for (int e = tid; e < 3 * N; e += NT) out[e] = cadd(out[e], cb[e]);
+  for (int e = tid; e < 3 * N; e += NTK) {
+    const int f = e / N, n = e - f * N;
+    out[e] = cadd(cb[e], dzt_coef(cb + (3 + f) * N, n));
+  }
   __syncthreads();
 }
 
 // cotangent G (equation slots) of F -> nlbar (S10^T, then the transposed Chebyshev forward
 // transform).  nhb: 3*N scratch.  Block-wide.
 __device__ void g_to_nlbar(const RbcDev& d, const KaArgs& a, int k, const double* ct, const cplx* G, cplx* nhb) {
-  const int tid = threadIdx.x, N = d.N, Ngz = d.Ngz, K = d.K;
-  for (int e = tid; e < 3 * N; e += NT) {
+  const int tid = threadIdx.x, N = d.N, Ngz = d.Ngz, K = d.K, Hc = half_nodes(Ngz);
+  for (int e = tid; e < 3 * N; e += NTK) {
     const int f = e / N, m = e - f * N;
     nhb[e] = cscale(s10t_at(G + f * N, m, N), (m == 0 ? 1.0 : 2.0) / Ngz);
   }
   __syncthreads();
-  for (int e = tid; e < 3 * Ngz; e += NT) {
-    const int f = e / Ngz, j = e - f * Ngz;
-    a.nlbar[(size_t)e * K + k] = cheb_sum_modes(ct, nhb + f * N, j, N, Ngz);
+  for (int e = tid; e < 4 * Hc; e += NTK) {
+    const int h = e & 3, j = e >> 2, jm = Ngz - 1 - j;
+    cplx val[3];
+    modes_to_pair<3>(ct, nhb, N, N, Ngz, j, h, val);
+    if (h == 0 || (h == 1 && jm != j)) {
+      const int jj = (h == 0) ? j : jm;
+#pragma unroll
+      for (int f = 0; f < 3; ++f) a.nlbar[((size_t)f * Ngz + jj) * K + k] = val[f];
+    }
   }
 }
 
 // LDS: vA, vB (S complex each) persist; the rest is a union of phase buffers and the
-// staged block operators.
-__global__ void __launch_bounds__(NT) rbc_kadj(RbcDev d, KaArgs a) {
+// staged block operators.  One entry of every length-S vector per thread.
+__global__ void __launch_bounds__(NTK) rbc_kadj(RbcDev d, KaArgs a) {
   extern __shared__ double smem_d[];
   cplx* sm = reinterpret_cast<cplx*>(smem_d);
   const int k = blockIdx.x, tid = threadIdx.x;
-  const int N = d.N, S = d.S, Ngz = d.Ngz;
+  const int N = d.N, S = d.S, Ngz = d.Ngz, Hc = half_nodes(Ngz);
   const int fl = a.flags;
   const double dt = a.dt, g = a.g, dl = a.dl;
+  const bool sl = tid < S;
+  const size_t ks = (size_t)k * S + tid;
   cplx* vA = sm;                // S + SPS_PAD : solver-order vector
   cplx* vB = vA + S + SPS_PAD;  // S : solve result in equation slots (Y)
   cplx* un = vB + S;            // union
@@ -788,13 +890,13 @@ __global__ void __launch_bounds__(NT) rbc_kadj(RbcDev d, KaArgs a) {
   double* ct = reinterpret_cast<double*>(un);           // 4*Ngz
   cplx* xbar = reinterpret_cast<cplx*>(ct + 4 * Ngz);   // S   cotangent of a state
   cplx* y2 = xbar + S;                                  // S
-  cplx* zb = y2 + S;                                    // 6*Ngz
-  cplx* cb = zb + 6 * Ngz;                              // 6*N
+  cplx* pqz = y2 + S;                                   // 12*Hc
+  cplx* cb = pqz + 12 * Hc;                             // 6*N
   cplx* vv = cb + 6 * N;                                // 3*N
   // views after the solve
   cplx* p_y2 = xbar;                                    // S
   cplx* p_t = y2;                                       // S  (Y1 + Y2)
-  cplx* p_g = zb;                                       // S  cotangent of F
+  cplx* p_g = pqz;                                      // S  cotangent of F
   cplx* p_nh = p_g + S;                                 // 3*N
 
   OpsRegs opsr;
@@ -805,34 +907,31 @@ __global__ void __launch_bounds__(NT) rbc_kadj(RbcDev d, KaArgs a) {
   }
   stage_cos(d.cosz, ct, Ngz);
   if (fl & KA_SOLVE_T) {
-    for (int s = tid; s < S; s += NT) xbar[s] = a.Xb_in[(size_t)k * S + s];
+    if (sl) xbar[tid] = a.Xb_in[ks];
     __syncthreads();
     rbc_gather_h(d, mr, xbar, vA);
     rbc_solve_staged(d, opsr, ops, vA, true);
     rbc_scatter_h(d, mr, vA, vB);
-    for (int s = tid; s < S; s += NT) a.Xb_out[(size_t)k * S + s] = vB[s];
+    if (sl) a.Xb_out[ks] = vB[tid];
     return;
   }
   if (fl & KA_G) {
-    for (int s = tid; s < S; s += NT) p_g[s] = a.Xb_in[(size_t)k * S + s];
+    if (sl) p_g[tid] = a.Xb_in[ks];
     __syncthreads();
     g_to_nlbar(d, a, k, ct, p_g, p_nh);
     return;
   }
   if (fl & KA_C) {
-    zbar_to_coeffs(d, a, k, ct, zb, cb, vv);
-    for (int s = tid; s < S; s += NT) {
-      cplx v = a.acc ? a.acc[(size_t)k * S + s] : czero();
-      if (s < 3 * N) v = cadd(v, vv[s]);
-      xbar[s] = v;
-    }
+    const cplx acc = (a.acc && sl) ? a.acc[ks] : czero();
+    zbar_to_coeffs(d, a, k, ct, pqz, cb, vv);
+    if (sl) xbar[tid] = (tid < 3 * N) ? cadd(acc, vv[tid]) : acc;
     __syncthreads();
     if (!(fl & KA_A)) {
-      for (int s = tid; s < S; s += NT) a.Xb_out[(size_t)k * S + s] = xbar[s];
+      if (sl) a.Xb_out[ks] = xbar[tid];
       return;
     }
   } else if (fl & KA_A) {
-    for (int s = tid; s < S; s += NT) xbar[s] = a.Xb_in[(size_t)k * S + s];
+    if (sl) xbar[tid] = a.Xb_in[ks];
     __syncthreads();
   }
   if (fl & KA_A) {
@@ -841,40 +940,40 @@ __global__ void __launch_bounds__(NT) rbc_kadj(RbcDev d, KaArgs a) {
     rbc_solve_staged(d, opsr, ops, vA, true);
     rbc_scatter_h(d, mr, vA, vB);
     stage_cos(d.cosz, ct, Ngz);
-    for (int s = tid; s < S; s += NT) {
-      a.Ybuf[(size_t)k * S + s] = vB[s];
-      p_g[s] = cscale(vB[s], dt * (1.0 - dl));
+    if (sl) {
+      a.Ybuf[ks] = vB[tid];
+      p_g[tid] = cscale(vB[tid], dt * (1.0 - dl));
     }
     __syncthreads();
     g_to_nlbar(d, a, k, ct, p_g, p_nh);
     return;
   }
   if (fl & KA_B) {
-    zbar_to_coeffs(d, a, k, ct, zb, cb, vv);
-    for (int s = tid; s < S; s += NT) y2[s] = a.Ybuf[(size_t)k * S + s];
+    const cplx y2v = sl ? a.Ybuf[ks] : czero();
+    zbar_to_coeffs(d, a, k, ct, pqz, cb, vv);
+    if (sl) y2[tid] = y2v;
     __syncthreads();
     // xbar_1 = F-VJP part - dt (1 - gamma) L^H Y2
-    for (int s = tid; s < S; s += NT) {
-      const MLRow t = mlt_col(d, k, y2, s);
+    if (sl) {
+      const MLRow t = mlt_col(d, k, y2, tid);
       cplx v = cscale(t.l, -dt * (1.0 - g));
-      if (s < 3 * N) v = cadd(v, vv[s]);
-      xbar[s] = v;
+      if (tid < 3 * N) v = cadd(v, vv[tid]);
+      xbar[tid] = v;
     }
     __syncthreads();
     rbc_gather_h(d, mr, xbar, vA);
     rbc_solve_staged(d, opsr, ops, vA, true);
     rbc_scatter_h(d, mr, vA, vB);     // vB = Y1
     stage_cos(d.cosz, ct, Ngz);
-    for (int s = tid; s < S; s += NT) {
-      const cplx y2s = a.Ybuf[(size_t)k * S + s];
-      p_y2[s] = y2s;
-      p_t[s] = cadd(vB[s], y2s);
+    if (sl) {
+      p_y2[tid] = y2v;
+      p_t[tid] = cadd(vB[tid], y2v);
     }
     __syncthreads();
-    for (int s = tid; s < S; s += NT) {
-      const MLRow t = mlt_col(d, k, p_t, s);
-      a.acc[(size_t)k * S + s] = t.m;
-      p_g[s] = cadd(cscale(p_y2[s], dt * dl), cscale(vB[s], dt * g));
+    if (sl) {
+      const MLRow t = mlt_col(d, k, p_t, tid);
+      a.acc[ks] = t.m;
+      p_g[tid] = cadd(cscale(p_y2[tid], dt * dl), cscale(vB[tid], dt * g));
     }
     __syncthreads();
     g_to_nlbar(d, a, k, ct, p_g, p_nh);
@@ -1342,12 +1441,12 @@ class RbcProblem : public ProblemImpl {
   size_t factor_lds() const { return (size_t)(2 * kl_ + ku_ + 1) * S_ * sizeof(double) + sizeof(int) * S_; }
   size_t ops_bytes() const { return sizeof(double) * (size_t)blk_ops_size(S_); }
   size_t kf_lds() const {
-    const size_t pre = sizeof(cplx) * (3 * S_ + 3 * Ngz_ + 6 * N_) + sizeof(double) * 4 * Ngz_;
+    const size_t pre = sizeof(cplx) * (3 * S_ + 6 * half_nodes(Ngz_) + 6 * N_) + sizeof(double) * 4 * Ngz_;
     const size_t post = sizeof(double) * 4 * Ngz_ + sizeof(cplx) * 3 * N_;
     return sizeof(cplx) * (2 * S_ + SPS_PAD) + std::max({pre, post, ops_bytes()});
   }
   size_t ka_lds() const {
-    const size_t pre = sizeof(double) * 4 * Ngz_ + sizeof(cplx) * (2 * S_ + 6 * Ngz_ + 9 * N_);
+    const size_t pre = sizeof(double) * 4 * Ngz_ + sizeof(cplx) * (2 * S_ + 12 * half_nodes(Ngz_) + 9 * N_);
     const size_t post = sizeof(double) * 4 * Ngz_ + sizeof(cplx) * (3 * S_ + 3 * N_);
     return sizeof(cplx) * (2 * S_ + SPS_PAD) + std::max({pre, post, ops_bytes()});
   }
@@ -1371,10 +1470,11 @@ class RbcProblem : public ProblemImpl {
     a.g = 1.0 - 1.0 / std::sqrt(2.0);
     a.dl = 1.0 - 1.0 / (2.0 * a.g);
     a.mode = mode;
-    const bool timed = (mode == KF_STAGE1 || mode == KF_STAGE2) && s == stream;
-    if (timed) timer_.begin(s);
-    hipLaunchKernelGGL(rbc_kfwd, dim3(K_), dim3(NT), kf_lds(), s, dv_, a);
-    if (timed) timer_.end(s);
+    hipEvent_t e0, e1;
+    if ((mode == KF_STAGE1 || mode == KF_STAGE2) && s == stream && timer_.take(&e0, &e1))
+      hipExtLaunchKernelGGL(rbc_kfwd, dim3(K_), dim3(NTK), kf_lds(), s, e0, e1, 0, dv_, a);
+    else
+      hipLaunchKernelGGL(rbc_kfwd, dim3(K_), dim3(NTK), kf_lds(), s, dv_, a);
     SPS_CHECK_LAUNCH();
   }
   void launch_xf(const cplx* zg, hipStream_t s = nullptr) {
@@ -1397,7 +1497,7 @@ class RbcProblem : public ProblemImpl {
     return a;
   }
   void launch_ka(const KaArgs& a) {
-    hipLaunchKernelGGL(rbc_kadj, dim3(K_), dim3(NT), ka_lds(), stream, dv_, a);
+    hipLaunchKernelGGL(rbc_kadj, dim3(K_), dim3(NTK), ka_lds(), stream, dv_, a);
     SPS_CHECK_LAUNCH();
   }
   void launch_xa(const cplx* zg) {
@@ -1523,7 +1623,8 @@ class RbcProblem : public ProblemImpl {
     kl_ = hb.kl;
     ku_ = hb.ku;
     SPS_REQUIRE(kl_ + SPS_BLK <= SPS_TW && SPS_BLK + kl_ + ku_ <= SPS_GW, "band too wide for the block solver");
-    SPS_REQUIRE(blk_ops_size(S_) <= 2 * SPS_OPS_REG * NT, "nz too large for the staged block solver");
+    SPS_REQUIRE(blk_ops_size(S_) <= 2 * SPS_OPS_REG * NTK, "nz too large for the staged block solver");
+    SPS_REQUIRE(S_ + SPS_PAD <= NTK && 4 * N_ + 28 <= NTK, "nz too large for one state entry per thread");
     BM_ = arena_.upload(hb.BM, stream);
     BL_ = arena_.upload(hb.BL, stream);
     dv_.n = S_;
@@ -1544,7 +1645,7 @@ class RbcProblem : public ProblemImpl {
       hrho[i] = (c >= 2) ? hb.rho[c - 2] : 0.0;
       sflag[i] = hb.colph[i];
     }
-    SPS_REQUIRE(S_ <= 2 * NT && S_ < 0xffff, "nz too large for the per-thread maps");
+    SPS_REQUIRE(S_ < 0xffff, "nz too large for the per-thread maps");
     dv_.gmap = arena_.upload(gmap, stream);
     dv_.hmap = arena_.upload(hmap, stream);
     dv_.hrho = arena_.upload(hrho, stream);

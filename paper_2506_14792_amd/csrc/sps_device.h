@@ -125,6 +125,31 @@ __device__ inline cplx* lds_fft(cplx* buf0, cplx* buf1, const FftPlan& p, const 
 
 // ---------------------------------------------------------------------------- lanes
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (SPS_WAVE - 1); }
+// Lane exchanges of a double inside groups of 4 or 8 lanes (DPP, no LDS traffic):
+// xor1 / xor2 swap with lane i^1 / i^2 of the quad; mirror8 takes lane 7-i of the group of 8.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int64_t b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffff), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((int64_t)(uint32_t)lo) | ((int64_t)hi << 32));
+}
+__device__ __forceinline__ double dpp_xor1(double v) { return dpp_d<0xB1>(v); }     // quad_perm [1,0,3,2]
+__device__ __forceinline__ double dpp_xor2(double v) { return dpp_d<0x4E>(v); }     // quad_perm [2,3,0,1]
+__device__ __forceinline__ double dpp_mirror8(double v) { return dpp_d<0x141>(v); } // row_half_mirror
+// sum over aligned groups of G lanes (G = 1, 2, 4 or 8); every lane of the group gets the sum
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+  if (G >= 2) v += dpp_xor1(v);
+  if (G >= 4) v += dpp_xor2(v);
+  if (G >= 8) v += dpp_mirror8(v);
+  return v;
+}
+template <int G>
+__device__ __forceinline__ cplx group_sum(cplx v) {
+  return make_double2(group_sum<G>(v.x), group_sum<G>(v.y));
+}
+
 
 // Value of v held by lane `src` (uniform across the wave).
 __device__ __forceinline__ double readlane_d(double v, int src) {

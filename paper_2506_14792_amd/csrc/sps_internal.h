@@ -1,6 +1,7 @@
 // Host-side internals shared by the C ABI and the problem implementations.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <stdexcept>
 #include <string>
@@ -72,16 +73,14 @@ class KernelTimer {
       if (hipEventCreate(&e) != hipSuccess) { e = nullptr; on_ = false; }
     used_ = 0;
   }
-  void begin(hipStream_t s) {
-    if (!on_ || used_ >= kCapacity) return;
-    (void)hipEventRecord(pool_[2 * used_], s);
-    open_ = true;
-  }
-  void end(hipStream_t s) {
-    if (!on_ || !open_) return;
-    (void)hipEventRecord(pool_[2 * used_ + 1], s);
+  // Event pair for the next timed launch (handed to hipExtLaunchKernelGGL, which stamps the
+  // dispatch itself), or false when timing is off or the pool is used up.
+  bool take(hipEvent_t* start, hipEvent_t* stop) {
+    if (!on_ || used_ >= kCapacity) return false;
+    *start = pool_[2 * used_];
+    *stop = pool_[2 * used_ + 1];
     ++used_;
-    open_ = false;
+    return true;
   }
   void read(long long* launches, double* total_ms) {
     double tot = 0.0;
@@ -105,10 +104,9 @@ class KernelTimer {
       if (e) (void)hipEventDestroy(e);
     pool_.clear();
     used_ = 0;
-    open_ = false;
     on_ = false;
   }
-  bool on_ = false, open_ = false;
+  bool on_ = false;
   int used_ = 0;
   std::vector<hipEvent_t> pool_;
 };

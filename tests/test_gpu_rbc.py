@@ -23,8 +23,10 @@ if not torch.cuda.is_available():
 import paper_2506_14792_amd as sps  # noqa: E402
 
 # (nx, nz, lx, Ra, Pr, dt): a small case spanning several wave tiles with a ragged tail,
-# and the full 256 x 64 configuration
+# one whose dealiased Chebyshev grid has an odd node count (21: the middle node is its own
+# mirror image), and the full 256 x 64 configuration
 SMALL = (24, 16, 3.0, 1e5, 0.7, 2e-3)
+ODD = (24, 14, 2.5, 3e4, 0.9, 2e-3)
 FULL = (256, 64, 4.0, 1e6, 1.0, 1e-3)
 
 
@@ -52,7 +54,7 @@ def build(cfg, ce=1, max_steps=1):
     return P, G
 
 
-@pytest.mark.parametrize("cfg", [SMALL, FULL], ids=["small", "full"])
+@pytest.mark.parametrize("cfg", [SMALL, ODD, FULL], ids=["small", "odd", "full"])
 def test_banded_solve_and_transposed_solve(cfg):
     note(f"solve parity {cfg}")
     P, G = build(cfg)
@@ -67,7 +69,7 @@ def test_banded_solve_and_transposed_solve(cfg):
     assert rel(from_dev(x, R.shape), lu.solve_adjoint(R)) < TOL
 
 
-@pytest.mark.parametrize("cfg", [SMALL, FULL], ids=["small", "full"])
+@pytest.mark.parametrize("cfg", [SMALL, ODD, FULL], ids=["small", "odd", "full"])
 def test_explicit_term_and_vjp(cfg):
     note(f"F and F-vjp parity {cfg}")
     P, G = build(cfg)
@@ -86,7 +88,7 @@ def test_explicit_term_and_vjp(cfg):
     assert rel(got, ref) < TOL
 
 
-@pytest.mark.parametrize("cfg", [SMALL, FULL], ids=["small", "full"])
+@pytest.mark.parametrize("cfg", [SMALL, ODD, FULL], ids=["small", "odd", "full"])
 def test_initial_state_cost_and_adjoints(cfg):
     note(f"initial state / cost parity {cfg}")
     P, G = build(cfg)
@@ -109,7 +111,7 @@ def test_initial_state_cost_and_adjoints(cfg):
     assert rel(from_dev(dJ, Xs.shape), P.kinetic_energy_grad(Xs)) < TOL
 
 
-@pytest.mark.parametrize("cfg,nsteps", [(SMALL, 7), (FULL, 3)], ids=["small", "full"])
+@pytest.mark.parametrize("cfg,nsteps", [(SMALL, 7), (ODD, 4), (FULL, 3)], ids=["small", "odd", "full"])
 def test_forward_steps(cfg, nsteps):
     note(f"forward parity {cfg} x {nsteps}")
     P, G = build(cfg, ce=2, max_steps=nsteps)
@@ -122,7 +124,7 @@ def test_forward_steps(cfg, nsteps):
     assert rel(from_dev(X, X0.shape), XN) < TOL
 
 
-@pytest.mark.parametrize("cfg,nsteps,ce", [(SMALL, 7, 3), (FULL, 6, 4)], ids=["small", "full"])
+@pytest.mark.parametrize("cfg,nsteps,ce", [(SMALL, 7, 3), (ODD, 5, 2), (FULL, 6, 4)], ids=["small", "odd", "full"])
 def test_gradient(cfg, nsteps, ce):
     note(f"gradient parity {cfg} x {nsteps} ce={ce}")
     P, G = build(cfg, ce=ce, max_steps=nsteps)
