@@ -4,6 +4,7 @@
 #include <cmath>
 #include <string>
 
+#include "fft_plan.h"
 #include "sps_internal.h"
 
 struct sps_problem {
@@ -44,13 +45,37 @@ std::vector<double2> twiddles(int n) {
   return t;
 }
 
-bool fft_plan(int n, int* radix, int* nst) {
-  int m = n, s = 0;
-  while (m % 3 == 0) { radix[s++] = 3; m /= 3; if (s >= 12) return false; }
-  while (m % 4 == 0) { radix[s++] = 4; m /= 4; if (s >= 12) return false; }
-  while (m % 2 == 0) { radix[s++] = 2; m /= 2; if (s >= 12) return false; }
-  *nst = s;
-  return m == 1 && s > 0;
+// Radices for length n = 2^a 3^b: 8s first, then 4 or 2 (a 2 joined with a 3 as a 6), then 3s.
+bool fft_plan(int n, FftPlan* p) {
+  if (n < 2 || n > 16384) return false;
+  int m = n, a = 0, b = 0;
+  while (m % 2 == 0) { m /= 2; ++a; }
+  while (m % 3 == 0) { m /= 3; ++b; }
+  if (m != 1) return false;
+  int r[32], s = 0;
+  for (; a >= 3; a -= 3) r[s++] = 8;
+  if (a == 2) r[s++] = 4;
+  if (a == 1) {
+    if (b > 0) { r[s++] = 6; --b; }
+    else r[s++] = 2;
+  }
+  for (; b > 0; --b) r[s++] = 3;
+  if (s > 12) return false;
+  auto mag = [](int d) -> unsigned {
+    return d == 1 ? 0u : (unsigned)(((1ull << 32) + (unsigned long long)d - 1) / (unsigned long long)d);
+  };
+  p->n = n;
+  p->nst = s;
+  int Ns = 1;
+  for (int i = 0; i < s; ++i) {
+    p->radix[i] = r[i];
+    p->ns[i] = Ns;
+    p->tst[i] = n / (Ns * r[i]);
+    p->mag_nr[i] = mag(n / r[i]);
+    p->mag_ns[i] = mag(Ns);
+    Ns *= r[i];
+  }
+  return true;
 }
 
 }  // namespace sps

@@ -44,6 +44,7 @@ namespace {
 
 constexpr int NT = 256;   // threads per block of the grid-row, factor and set-up kernels
 constexpr int NTK = 512;  // threads per block of the per-wavenumber step kernels
+constexpr int NTX = 512;  // threads per block of the grid-row step kernels
 
 struct RbcDev {
   int K, N, S, Ngx, Ngz, Nx1, Nz1;
@@ -668,22 +669,22 @@ struct XfArgs {
   cplx* nl;         // [3][Ngz][K]
 };
 
-__global__ void __launch_bounds__(NT) rbc_xfwd(RbcDev d, XfArgs a) {
+__global__ void __launch_bounds__(NTX) rbc_xfwd(RbcDev d, XfArgs a) {
   extern __shared__ double smem_d[];
   cplx* sm = reinterpret_cast<cplx*>(smem_d);
   const int j = blockIdx.x, tid = threadIdx.x;
   const int K = d.K, Ngx = d.Ngx, Ngz = d.Ngz;
   cplx* spec = sm;                 // 9*K : u w b uz wz bz ux wx bx
-  cplx* buf0 = spec + 9 * K;       // 4*Ngx
-  cplx* buf1 = buf0 + 4 * Ngx;     // 4*Ngx
-  cplx* tw = buf1 + 4 * Ngx;       // Ngx twiddles
-  for (int e = tid; e < Ngx; e += NT) tw[e] = d.twx[e];
-  for (int e = tid; e < 6 * K; e += NT) {
+  cplx* buf0 = spec + 9 * K;                // 4*Ngx (padded)
+  cplx* buf1 = buf0 + fpad_size(4 * Ngx);   // 4*Ngx (padded)
+  cplx* tw = buf1 + fpad_size(4 * Ngx);     // Ngx twiddles
+  for (int e = tid; e < Ngx; e += NTX) tw[e] = d.twx[e];
+  for (int e = tid; e < 6 * K; e += NTX) {
     const int f = e / K, m = e - f * K;
     spec[e] = a.zg[((size_t)f * Ngz + j) * K + m];
   }
   __syncthreads();
-  for (int e = tid; e < 3 * K; e += NT) {
+  for (int e = tid; e < 3 * K; e += NTX) {
     const int f = e / K, m = e - f * K;
     spec[(6 + f) * K + m] = cscale(cmul_i(spec[f * K + m]), d.kx[m]);
   }
@@ -691,33 +692,34 @@ __global__ void __launch_bounds__(NT) rbc_xfwd(RbcDev d, XfArgs a) {
   // pairs: (u, w), (ux, uz), (wx, wz), (bx, bz)
   const int pu[4] = {0, 6, 7, 8};
   const int pv[4] = {1, 3, 4, 5};
-  for (int e = tid; e < 4 * Ngx; e += NT) {
+  for (int e = tid; e < 4 * Ngx; e += NTX) {
     const int q = e / Ngx, m = e - q * Ngx;
     const cplx* U = spec + pu[q] * K;
     const cplx* V = spec + pv[q] * K;
-    buf0[e] = pack_pair(U, V, m, Ngx, K, 1.0);
+    buf0[fpad(e)] = pack_pair(U, V, m, Ngx, K, 1.0);
   }
   __syncthreads();
-  cplx* g = lds_fft(buf0, buf1, d.px, tw, +1, 4, Ngx, tid, NT);
+  cplx* g = lds_fft(buf0, buf1, d.px, tw, +1, 4, Ngx, tid, NTX);
   cplx* o = (g == buf0) ? buf1 : buf0;
-  for (int x = tid; x < Ngx; x += NT) {
-    const double u = g[x].x, w = g[x].y;
-    const double ux = g[Ngx + x].x, uz = g[Ngx + x].y;
-    const double wx = g[2 * Ngx + x].x, wz = g[2 * Ngx + x].y;
-    const double bx = g[3 * Ngx + x].x, bz = g[3 * Ngx + x].y;
+  for (int x = tid; x < Ngx; x += NTX) {
+    const double u = g[fpad(x)].x, w = g[fpad(x)].y;
+    const double ux = g[fpad(Ngx + x)].x, uz = g[fpad(Ngx + x)].y;
+    const double wx = g[fpad(2 * Ngx + x)].x, wz = g[fpad(2 * Ngx + x)].y;
+    const double bx = g[fpad(3 * Ngx + x)].x, bz = g[fpad(3 * Ngx + x)].y;
     const double Nu = -(u * ux + w * uz);
     const double Nw = -(u * wx + w * wz);
     const double Nb = -(u * bx + w * bz);
-    o[x] = cmk(Nu, Nw);
-    o[Ngx + x] = cmk(Nb, 0.0);
+    o[fpad(x)] = cmk(Nu, Nw);
+    o[fpad(Ngx + x)] = cmk(Nb, 0.0);
   }
   __syncthreads();
-  cplx* h = lds_fft(o, g, d.px, tw, -1, 2, Ngx, tid, NT);
+  cplx* h = lds_fft(o, g, d.px, tw, -1, 2, Ngx, tid, NTX);
   const double inv = 1.0 / Ngx;
-  for (int e = tid; e < 3 * K; e += NT) {
+  for (int e = tid; e < 3 * K; e += NTX) {
     const int f = e / K, m = e - f * K;
-    const cplx* Z = h + (f == 2 ? Ngx : 0);
-    const cplx zm = Z[m], zq = Z[(Ngx - m) % Ngx];
+    const cplx* Z = h;
+    const int zo = (f == 2) ? Ngx : 0;
+    const cplx zm = Z[fpad(zo + m)], zq = Z[fpad(zo + (m == 0 ? 0 : Ngx - m))];
     cplx c;
     if (f == 0) c = cmk(0.5 * (zm.x + zq.x), 0.5 * (zm.y - zq.y));
     else if (f == 1) c = cmk(0.5 * (zm.y + zq.y), -0.5 * (zm.x - zq.x));
@@ -732,26 +734,26 @@ struct XaArgs {
   cplx* zbar;         // [6][Ngz][K] cotangents of u, w, b, uz, wz, bz x-spectra
 };
 
-__global__ void __launch_bounds__(NT) rbc_xadj(RbcDev d, XaArgs a) {
+__global__ void __launch_bounds__(NTX) rbc_xadj(RbcDev d, XaArgs a) {
   extern __shared__ double smem_d[];
   cplx* sm = reinterpret_cast<cplx*>(smem_d);
   const int j = blockIdx.x, tid = threadIdx.x;
   const int K = d.K, Ngx = d.Ngx, Ngz = d.Ngz;
   cplx* spec = sm;                  // 12*K: u w b uz wz bz ux wx bx | nub nwb nbb
-  cplx* buf0 = spec + 12 * K;       // 6*Ngx
-  cplx* buf1 = buf0 + 6 * Ngx;      // 6*Ngx
-  cplx* tw = buf1 + 6 * Ngx;        // Ngx twiddles
-  for (int e = tid; e < Ngx; e += NT) tw[e] = d.twx[e];
-  for (int e = tid; e < 6 * K; e += NT) {
+  cplx* buf0 = spec + 12 * K;               // 6*Ngx (padded)
+  cplx* buf1 = buf0 + fpad_size(6 * Ngx);   // 6*Ngx (padded)
+  cplx* tw = buf1 + fpad_size(6 * Ngx);     // Ngx twiddles
+  for (int e = tid; e < Ngx; e += NTX) tw[e] = d.twx[e];
+  for (int e = tid; e < 6 * K; e += NTX) {
     const int f = e / K, m = e - f * K;
     spec[e] = a.zg[((size_t)f * Ngz + j) * K + m];
   }
-  for (int e = tid; e < 3 * K; e += NT) {
+  for (int e = tid; e < 3 * K; e += NTX) {
     const int f = e / K, m = e - f * K;
     spec[(9 + f) * K + m] = a.nlbar[((size_t)f * Ngz + j) * K + m];
   }
   __syncthreads();
-  for (int e = tid; e < 3 * K; e += NT) {
+  for (int e = tid; e < 3 * K; e += NTX) {
     const int f = e / K, m = e - f * K;
     spec[(6 + f) * K + m] = cscale(cmul_i(spec[f * K + m]), d.kx[m]);
   }
@@ -759,39 +761,39 @@ __global__ void __launch_bounds__(NT) rbc_xadj(RbcDev d, XaArgs a) {
   // buffers 0..3: primal pairs; 4: (Nu_bar, Nw_bar) with halved m >= 1 weights; 5: (Nb_bar, 0)
   const int pu[6] = {0, 6, 7, 8, 9, 11};
   const int pv[6] = {1, 3, 4, 5, 10, -1};
-  for (int e = tid; e < 6 * Ngx; e += NT) {
+  for (int e = tid; e < 6 * Ngx; e += NTX) {
     const int q = e / Ngx, m = e - q * Ngx;
     const cplx* U = spec + pu[q] * K;
     const cplx* V = (pv[q] >= 0) ? spec + pv[q] * K : nullptr;
-    buf0[e] = pack_pair(U, V, m, Ngx, K, q >= 4 ? 0.5 : 1.0);
+    buf0[fpad(e)] = pack_pair(U, V, m, Ngx, K, q >= 4 ? 0.5 : 1.0);
   }
   __syncthreads();
-  cplx* g = lds_fft(buf0, buf1, d.px, tw, +1, 6, Ngx, tid, NT);
+  cplx* g = lds_fft(buf0, buf1, d.px, tw, +1, 6, Ngx, tid, NTX);
   cplx* o = (g == buf0) ? buf1 : buf0;
   const double inv = 1.0 / Ngx;
-  for (int x = tid; x < Ngx; x += NT) {
-    const double u = g[x].x, w = g[x].y;
-    const double ux = g[Ngx + x].x, uz = g[Ngx + x].y;
-    const double wx = g[2 * Ngx + x].x, wz = g[2 * Ngx + x].y;
-    const double bx = g[3 * Ngx + x].x, bz = g[3 * Ngx + x].y;
-    const double Nub = g[4 * Ngx + x].x * inv, Nwb = g[4 * Ngx + x].y * inv;
-    const double Nbb = g[5 * Ngx + x].x * inv;
+  for (int x = tid; x < Ngx; x += NTX) {
+    const double u = g[fpad(x)].x, w = g[fpad(x)].y;
+    const double ux = g[fpad(Ngx + x)].x, uz = g[fpad(Ngx + x)].y;
+    const double wx = g[fpad(2 * Ngx + x)].x, wz = g[fpad(2 * Ngx + x)].y;
+    const double bx = g[fpad(3 * Ngx + x)].x, bz = g[fpad(3 * Ngx + x)].y;
+    const double Nub = g[fpad(4 * Ngx + x)].x * inv, Nwb = g[fpad(4 * Ngx + x)].y * inv;
+    const double Nbb = g[fpad(5 * Ngx + x)].x * inv;
     const double ub = -(Nub * ux + Nwb * wx + Nbb * bx);
     const double wb = -(Nub * uz + Nwb * wz + Nbb * bz);
-    o[x] = cmk(ub, wb);
-    o[Ngx + x] = cmk(-Nub * u, -Nub * w);          // ux_bar, uz_bar
-    o[2 * Ngx + x] = cmk(-Nwb * u, -Nwb * w);      // wx_bar, wz_bar
-    o[3 * Ngx + x] = cmk(-Nbb * u, -Nbb * w);      // bx_bar, bz_bar
+    o[fpad(x)] = cmk(ub, wb);
+    o[fpad(Ngx + x)] = cmk(-Nub * u, -Nub * w);          // ux_bar, uz_bar
+    o[fpad(2 * Ngx + x)] = cmk(-Nwb * u, -Nwb * w);      // wx_bar, wz_bar
+    o[fpad(3 * Ngx + x)] = cmk(-Nbb * u, -Nbb * w);      // bx_bar, bz_bar
   }
   __syncthreads();
-  cplx* h = lds_fft(o, g, d.px, tw, -1, 4, Ngx, tid, NT);
+  cplx* h = lds_fft(o, g, d.px, tw, -1, 4, Ngx, tid, NTX);
   // unpack: A_m = (Z_m + conj Z_-m)/2, B_m = (Z_m - conj Z_-m)/(2i); weight 1 at m = 0, 2 else
-  for (int e = tid; e < 3 * K; e += NT) {
+  for (int e = tid; e < 3 * K; e += NTX) {
     const int f = e / K, m = e - f * K;
     const double wgt = (m == 0) ? 1.0 : 2.0;
     const double kx = d.kx[m];
     auto unpack = [&](int q, cplx& A, cplx& B) {
-      const cplx zm = h[q * Ngx + m], zq = h[q * Ngx + (Ngx - m) % Ngx];
+      const cplx zm = h[fpad(q * Ngx + m)], zq = h[fpad(q * Ngx + (m == 0 ? 0 : Ngx - m))];
       A = cscale(cmk(0.5 * (zm.x + zq.x), 0.5 * (zm.y - zq.y)), wgt);
       B = cscale(cmk(0.5 * (zm.y + zq.y), -0.5 * (zm.x - zq.x)), wgt);
     };
@@ -999,11 +1001,11 @@ __global__ void __launch_bounds__(NT) rbc_init_x(RbcDev d, const double* grid, c
   cplx* sm = reinterpret_cast<cplx*>(smem_d);
   const int zi = blockIdx.x, tid = threadIdx.x, n = d.Nx1, K = d.K;
   cplx* b0 = sm;
-  cplx* b1 = sm + n;
-  for (int x = tid; x < n; x += NT) b0[x] = cmk(grid[(size_t)x * d.Nz1 + zi], 0.0);
+  cplx* b1 = sm + fpad_size(n);
+  for (int x = tid; x < n; x += NT) b0[fpad(x)] = cmk(grid[(size_t)x * d.Nz1 + zi], 0.0);
   __syncthreads();
   cplx* h = lds_fft(b0, b1, d.px1, d.twx1, -1, 1, n, tid, NT);
-  for (int m = tid; m < K; m += NT) tmp[(size_t)zi * K + m] = cscale(h[m], 1.0 / n);
+  for (int m = tid; m < K; m += NT) tmp[(size_t)zi * K + m] = cscale(h[fpad(m)], 1.0 / n);
 }
 
 __global__ void __launch_bounds__(NT) rbc_init_z(RbcDev d, const cplx* tmp, cplx* X) {
@@ -1038,18 +1040,18 @@ __global__ void __launch_bounds__(NT) rbc_init_adj_x(RbcDev d, const cplx* tmp, 
   cplx* sm = reinterpret_cast<cplx*>(smem_d);
   const int zi = blockIdx.x, tid = threadIdx.x, n = d.Nx1, K = d.K;
   cplx* b0 = sm;
-  cplx* b1 = sm + n;
+  cplx* b1 = sm + fpad_size(n);
   const cplx* t = tmp + (size_t)zi * K;
   for (int m = tid; m < n; m += NT) {
     cplx v = czero();
     if (m == 0) v = cmk(t[0].x, 0.0);
     else if (m < K) v = cscale(t[m], 0.5);
     else if (m > n - K) v = cscale(cconj(t[n - m]), 0.5);
-    b0[m] = v;
+    b0[fpad(m)] = v;
   }
   __syncthreads();
   cplx* h = lds_fft(b0, b1, d.px1, d.twx1, +1, 1, n, tid, NT);
-  for (int x = tid; x < n; x += NT) gbar[(size_t)x * d.Nz1 + zi] = h[x].x / n;
+  for (int x = tid; x < n; x += NT) gbar[(size_t)x * d.Nz1 + zi] = h[fpad(x)].x / n;
 }
 
 // ---------------------------------------------------------------------------- cost
@@ -1307,10 +1309,8 @@ class RbcProblem : public ProblemImpl {
     S_ = 4 * N_ + 7;
     Ngx_ = 3 * desc.nx / 2;
     Ngz_ = 3 * N_ / 2;
-    SPS_REQUIRE(fft_plan(Ngx_, dv_.px.radix, &dv_.px.nst), "3/2 nx must factor into 2 and 3");
-    SPS_REQUIRE(fft_plan(desc.nx, dv_.px1.radix, &dv_.px1.nst), "nx must factor into 2 and 3");
-    dv_.px.n = Ngx_;
-    dv_.px1.n = desc.nx;
+    SPS_REQUIRE(fft_plan(Ngx_, &dv_.px), "3/2 nx must factor into 2 and 3");
+    SPS_REQUIRE(fft_plan(desc.nx, &dv_.px1), "nx must factor into 2 and 3");
     nu_ = std::pow(desc.param0 / desc.param1, -0.5);
     ka_ = std::pow(desc.param0 * desc.param1, -0.5);
     build_tables();
@@ -1375,7 +1375,7 @@ class RbcProblem : public ProblemImpl {
 
   void initial_state(const double* grid, double* X) override {
     SPS_REQUIRE(grid && X, "null argument");
-    hipLaunchKernelGGL(rbc_init_x, dim3(N_), dim3(NT), 2 * desc_.nx * sizeof(cplx), stream, dv_, grid, itmp_);
+    hipLaunchKernelGGL(rbc_init_x, dim3(N_), dim3(NT), 2 * fpad_size(desc_.nx) * sizeof(cplx), stream, dv_, grid, itmp_);
     SPS_CHECK_LAUNCH();
     hipLaunchKernelGGL(rbc_init_z, dim3(K_), dim3(NT), 0, stream, dv_, itmp_, reinterpret_cast<cplx*>(X));
     SPS_CHECK_LAUNCH();
@@ -1385,7 +1385,7 @@ class RbcProblem : public ProblemImpl {
     SPS_REQUIRE(grid && Xbar, "null argument");
     hipLaunchKernelGGL(rbc_init_adj_z, dim3(K_), dim3(NT), 0, stream, dv_, reinterpret_cast<const cplx*>(Xbar), itmp_);
     SPS_CHECK_LAUNCH();
-    hipLaunchKernelGGL(rbc_init_adj_x, dim3(N_), dim3(NT), 2 * desc_.nx * sizeof(cplx), stream, dv_, itmp_, grid);
+    hipLaunchKernelGGL(rbc_init_adj_x, dim3(N_), dim3(NT), 2 * fpad_size(desc_.nx) * sizeof(cplx), stream, dv_, itmp_, grid);
     SPS_CHECK_LAUNCH();
   }
 
@@ -1450,8 +1450,8 @@ class RbcProblem : public ProblemImpl {
     const size_t post = sizeof(double) * 4 * Ngz_ + sizeof(cplx) * (3 * S_ + 3 * N_);
     return sizeof(cplx) * (2 * S_ + SPS_PAD) + std::max({pre, post, ops_bytes()});
   }
-  size_t xf_lds() const { return sizeof(cplx) * (9 * K_ + 9 * Ngx_); }
-  size_t xa_lds() const { return sizeof(cplx) * (12 * K_ + 13 * Ngx_); }
+  size_t xf_lds() const { return sizeof(cplx) * (9 * K_ + 2 * fpad_size(4 * Ngx_) + Ngx_); }
+  size_t xa_lds() const { return sizeof(cplx) * (12 * K_ + 2 * fpad_size(6 * Ngx_) + Ngx_); }
 
   void launch_kf(int mode, const cplx* X0, const cplx* X1, cplx* Xout, cplx* zg) {
     launch_kf_on(stream, mode, X0, X1, Xout, zg);
@@ -1479,7 +1479,7 @@ class RbcProblem : public ProblemImpl {
   }
   void launch_xf(const cplx* zg, hipStream_t s = nullptr) {
     XfArgs a{zg, nl_};
-    hipLaunchKernelGGL(rbc_xfwd, dim3(Ngz_), dim3(NT), xf_lds(), s ? s : stream, dv_, a);
+    hipLaunchKernelGGL(rbc_xfwd, dim3(Ngz_), dim3(NTX), xf_lds(), s ? s : stream, dv_, a);
     SPS_CHECK_LAUNCH();
   }
   KaArgs ka_args(int flags) {
@@ -1502,7 +1502,7 @@ class RbcProblem : public ProblemImpl {
   }
   void launch_xa(const cplx* zg) {
     XaArgs a{nlbar_, zg, zbar_};
-    hipLaunchKernelGGL(rbc_xadj, dim3(Ngz_), dim3(NT), xa_lds(), stream, dv_, a);
+    hipLaunchKernelGGL(rbc_xadj, dim3(Ngz_), dim3(NTX), xa_lds(), stream, dv_, a);
     SPS_CHECK_LAUNCH();
   }
 

@@ -22,13 +22,10 @@ __device__ __forceinline__ cplx czero() { return cmk(0.0, 0.0); }
 
 // ---------------------------------------------------------------------------- FFT plan
 // n = product of radices; every radix is 2, 3 or 4.  Twiddles tw[t] = exp(-2 pi i t / n).
-struct FftPlan {
-  int n;
-  int nst;
-  int radix[12];
-};
+#include "fft_plan.h"
 
-// Radix-R DFT in registers, sign = -1 forward, +1 inverse (unnormalized).
+// Radix-R DFT in registers: v_k <- sum_r v_r w^(r k), w = exp(sign 2 pi i / R)
+// (sign = -1 forward, +1 inverse, unnormalized).
 template <int R>
 __device__ __forceinline__ void dft_small(cplx* v, int sign);
 
@@ -46,7 +43,7 @@ __device__ __forceinline__ void dft_small<3>(cplx* v, int sign) {
   cplx s = cadd(b, c);
   cplx d = csub(b, c);
   cplx m = cmk(a.x - 0.5 * s.x, a.y - 0.5 * s.y);
-  // forward: y1 = m - i h d, y2 = m + i h d ; inverse swaps the sign of i
+  // w = -1/2 + sign i sqrt(3)/2: y1 = m + sign i h d, y2 = m - sign i h d
   cplx t = cscale(cmul_i(d), h * (double)sign);
   v[0] = cadd(a, s);
   v[1] = cadd(m, t);
@@ -58,7 +55,7 @@ __device__ __forceinline__ void dft_small<4>(cplx* v, int sign) {
   cplx a = v[0], b = v[1], c = v[2], d = v[3];
   cplx s0 = cadd(a, c), s1 = csub(a, c);
   cplx s2 = cadd(b, d), s3 = csub(b, d);
-  // forward (w = -i): y1 = s1 - i s3, y3 = s1 + i s3
+  // w = sign i: y1 = s1 + sign i s3, y3 = s1 - sign i s3
   cplx t = (sign < 0) ? cmul_mi(s3) : cmul_i(s3);
   v[0] = cadd(s0, s2);
   v[1] = cadd(s1, t);
@@ -66,59 +63,105 @@ __device__ __forceinline__ void dft_small<4>(cplx* v, int sign) {
   v[3] = csub(s1, t);
 }
 
+// Radix 6 = two radix-3 DFTs (even and odd inputs) joined by w6^k:
+// y_k = E_k + w6^k O_k, y_(k+3) = E_k - w6^k O_k.
+template <>
+__device__ __forceinline__ void dft_small<6>(cplx* v, int sign) {
+  const double h = 0.86602540378443864676;  // sqrt(3)/2
+  cplx e[3] = {v[0], v[2], v[4]};
+  cplx o[3] = {v[1], v[3], v[5]};
+  dft_small<3>(e, sign);
+  dft_small<3>(o, sign);
+  const double sh = h * (double)sign;
+  // w6 = 1/2 + sign i h, w6^2 = -1/2 + sign i h
+  const cplx o1 = cmk(0.5 * o[1].x - sh * o[1].y, 0.5 * o[1].y + sh * o[1].x);
+  const cplx o2 = cmk(-0.5 * o[2].x - sh * o[2].y, -0.5 * o[2].y + sh * o[2].x);
+  v[0] = cadd(e[0], o[0]);
+  v[3] = csub(e[0], o[0]);
+  v[1] = cadd(e[1], o1);
+  v[4] = csub(e[1], o1);
+  v[2] = cadd(e[2], o2);
+  v[5] = csub(e[2], o2);
+}
+
+// Radix 8 = two radix-4 DFTs joined by w8^k: w8 = (1 + sign i)/sqrt(2), w8^2 = sign i,
+// w8^3 = (-1 + sign i)/sqrt(2).
+template <>
+__device__ __forceinline__ void dft_small<8>(cplx* v, int sign) {
+  const double c = 0.70710678118654752440;  // 1/sqrt(2)
+  cplx e[4] = {v[0], v[2], v[4], v[6]};
+  cplx o[4] = {v[1], v[3], v[5], v[7]};
+  dft_small<4>(e, sign);
+  dft_small<4>(o, sign);
+  const double sg = (double)sign;
+  const cplx o1 = cmk(c * (o[1].x - sg * o[1].y), c * (o[1].y + sg * o[1].x));
+  const cplx o2 = cmk(-sg * o[2].y, sg * o[2].x);
+  const cplx o3 = cmk(c * (-o[3].x - sg * o[3].y), c * (-o[3].y + sg * o[3].x));
+  v[0] = cadd(e[0], o[0]);
+  v[4] = csub(e[0], o[0]);
+  v[1] = cadd(e[1], o1);
+  v[5] = csub(e[1], o1);
+  v[2] = cadd(e[2], o2);
+  v[6] = csub(e[2], o2);
+  v[3] = cadd(e[3], o3);
+  v[7] = csub(e[3], o3);
+}
+
+__device__ __forceinline__ int fdiv(int x, unsigned mag) { return mag ? (int)__umulhi((unsigned)x, mag) : x; }
+
+// One Stockham pass of radix R over nbatch sequences (batch q at q * bstride, padded).
+// tw[m] = exp(-2 pi i m / n); the inverse direction uses its conjugate.
 template <int R>
 __device__ __forceinline__ void stockham_pass(const cplx* __restrict__ src, cplx* __restrict__ dst,
-                                              int n, int Ns, const cplx* __restrict__ tw, int sign,
+                                              const FftPlan& p, int s, const cplx* __restrict__ tw, int sign,
                                               int nbatch, int bstride, int tid, int nthreads) {
-  const int nR = n / R;
-  const int tstride = n / (Ns * R);
+  const int nR = p.n / R, Ns = p.ns[s], tst = p.tst[s];
+  const unsigned mnr = p.mag_nr[s], mns = p.mag_ns[s];
   const int total = nbatch * nR;
   for (int it = tid; it < total; it += nthreads) {
-    const int q = it / nR;
+    const int q = fdiv(it, mnr);
     const int j = it - q * nR;
-    const cplx* a = src + q * bstride;
-    cplx* b = dst + q * bstride;
-    const int k = j % Ns;
-    const int t = k * tstride;
+    const int jh = fdiv(j, mns);
+    const int k = j - jh * Ns;
+    const int t = k * tst;   // r t < n for r < R
+    const int base = q * bstride;
     cplx v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      cplx x = a[j + r * nR];
-      if (r > 0 && t != 0) {
-        cplx w = tw[(r * t) % n];
+      cplx x = src[fpad(base + j + r * nR)];
+      if (r > 0) {
+        cplx w = tw[r * t];
         if (sign > 0) w = cconj(w);
         x = cmul(x, w);
       }
       v[r] = x;
     }
     dft_small<R>(v, sign);
-    const int idxD = (j / Ns) * Ns * R + k;
+    const int idxD = base + jh * Ns * R + k;
 #pragma unroll
-    for (int r = 0; r < R; ++r) b[idxD + r * Ns] = v[r];
+    for (int r = 0; r < R; ++r) dst[fpad(idxD + r * Ns)] = v[r];
   }
 }
 
-// Batched in-LDS FFT of nbatch sequences (stride bstride) held in buf0; buf1 is scratch
-// of the same size.  Returns the buffer holding the result.  Contains __syncthreads();
-// must be called by every thread of the block.
+// Batched in-LDS FFT of nbatch sequences (stride bstride, indices padded by fpad) held in
+// buf0; buf1 is scratch of the same size.  Returns the buffer holding the result.  Contains
+// __syncthreads(); must be called by every thread of the block.
 __device__ inline cplx* lds_fft(cplx* buf0, cplx* buf1, const FftPlan& p, const cplx* tw, int sign,
                                 int nbatch, int bstride, int tid, int nthreads) {
   cplx* src = buf0;
   cplx* dst = buf1;
-  int Ns = 1;
   for (int s = 0; s < p.nst; ++s) {
-    const int R = p.radix[s];
-    if (R == 4)
-      stockham_pass<4>(src, dst, p.n, Ns, tw, sign, nbatch, bstride, tid, nthreads);
-    else if (R == 3)
-      stockham_pass<3>(src, dst, p.n, Ns, tw, sign, nbatch, bstride, tid, nthreads);
-    else
-      stockham_pass<2>(src, dst, p.n, Ns, tw, sign, nbatch, bstride, tid, nthreads);
+    switch (p.radix[s]) {
+      case 8: stockham_pass<8>(src, dst, p, s, tw, sign, nbatch, bstride, tid, nthreads); break;
+      case 6: stockham_pass<6>(src, dst, p, s, tw, sign, nbatch, bstride, tid, nthreads); break;
+      case 4: stockham_pass<4>(src, dst, p, s, tw, sign, nbatch, bstride, tid, nthreads); break;
+      case 3: stockham_pass<3>(src, dst, p, s, tw, sign, nbatch, bstride, tid, nthreads); break;
+      default: stockham_pass<2>(src, dst, p, s, tw, sign, nbatch, bstride, tid, nthreads); break;
+    }
     __syncthreads();
     cplx* t = src;
     src = dst;
     dst = t;
-    Ns *= R;
   }
   return src;
 }

@@ -136,6 +136,5 @@ ProblemImpl* make_ks(const sps_desc& d, hipStream_t s);
 
 // Host helpers shared by problem builders.
 std::vector<double2> twiddles(int n);            // exp(-2 pi i t / n), t < n
-bool fft_plan(int n, int* radix, int* nst);       // radices 4/3/2, false if n has other factors
 
 }  // namespace sps
