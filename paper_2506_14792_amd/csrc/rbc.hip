@@ -520,7 +520,18 @@ __global__ void __launch_bounds__(NTK) rbc_kfwd(RbcDev d, KfArgs a) {
   cplx* fr = nh + 3 * N;        // 3*N  S10 N-hat
   double* ct = reinterpret_cast<double*>(fr + 3 * N);   // 4*Ngz cosines
   const bool stage = (mode == KF_STAGE1 || mode == KF_STAGE2);
+  const bool nonlin = stage || mode == KF_EVALF;
 
+  // Global reads, in the order they are needed: state, stage-0 F, the mirror pair of the
+  // nonlinear terms and one cosine per thread first, then the block operators (needed last).
+  const cplx x0 = (mode != KF_EVALF && tid < S) ? a.X0[(size_t)k * S + tid] : czero();
+  const cplx x1 = (mode == KF_STAGE2 && tid < S) ? a.X1[(size_t)k * S + tid] : czero();
+  const cplx f0v = (mode == KF_STAGE2 && tid < 3 * N) ? a.F0[(size_t)k * 3 * N + tid] : czero();
+  const int pf = tid / Hc, pj = tid - pf * Hc, pjm = Ngz - 1 - pj;
+  const bool pl = nonlin && tid < 3 * Hc;
+  const cplx nvj = pl ? a.nl[((size_t)pf * Ngz + pj) * K + k] : czero();
+  const cplx nvm = pl ? a.nl[((size_t)pf * Ngz + pjm) * K + k] : czero();
+  const double cosr = (tid < 4 * Ngz) ? d.cosz[tid] : 0.0;
   OpsRegs opsr;
   MapRegs mr;
   if (stage || mode == KF_SOLVE) {
@@ -528,24 +539,16 @@ __global__ void __launch_bounds__(NTK) rbc_kfwd(RbcDev d, KfArgs a) {
     load_maps(d, mr);
   }
   if (stage) {
-    const cplx x0 = (tid < S) ? a.X0[(size_t)k * S + tid] : czero();
-    const cplx x1 = (mode == KF_STAGE2 && tid < S) ? a.X1[(size_t)k * S + tid] : czero();
-    const cplx f0 = (mode == KF_STAGE2 && tid < 3 * N) ? a.F0[(size_t)k * 3 * N + tid] : czero();
     if (tid < S) {
       xa[tid] = x0;
       xb[tid] = x1;
     }
-    if (tid < 3 * N) vB[tid] = f0;   // stage-0 F (stage 2); vB is free until the solve
+    if (tid < 3 * N) vB[tid] = f0v;   // stage-0 F (stage 2); vB is free until the solve
   }
   const cplx* f0s = vB;
-  if (stage || mode == KF_EVALF) {
-    stage_cos(d.cosz, ct, Ngz);
-    if (tid < 3 * Hc) {
-      const int f = tid / Hc, j = tid - f * Hc, jm = Ngz - 1 - j;
-      const cplx vj = a.nl[((size_t)f * Ngz + j) * K + k];
-      const cplx vm = a.nl[((size_t)f * Ngz + jm) * K + k];
-      store_mirror_pair(vj, vm, jm == j, pq + 2 * (f * Hc + j));
-    }
+  if (nonlin) {
+    if (tid < 4 * Ngz) ct[tid] = cosr;
+    if (pl) store_mirror_pair(nvj, nvm, pjm == pj, pq + 2 * (pf * Hc + pj));
     __syncthreads();
     // Chebyshev forward transform (truncating) of the three nonlinear terms: 8 lanes per mode
     for (int e = tid; e < 8 * N; e += NTK) {
@@ -607,28 +610,27 @@ __global__ void __launch_bounds__(NTK) rbc_kfwd(RbcDev d, KfArgs a) {
     }
     __syncthreads();
   } else if (mode == KF_SOLVE) {
-    if (tid < S) rr[tid] = a.X0[(size_t)k * S + tid];
+    if (tid < S) rr[tid] = x0;
     __syncthreads();
   }
   if (mode == KF_ZGRID) {
-    if (tid < S) vA[tid] = a.X0[(size_t)k * S + tid];
+    if (tid < S) vA[tid] = x0;
     __syncthreads();
   } else {
     rbc_gather(d, mr, rr, vA);
     rbc_solve_staged(d, opsr, reinterpret_cast<double*>(un), vA, false);
     rbc_scatter(d, mr, vA, vB, vA);   // vA <- new state (ABI slots)
-    if (tid < S) a.Xout[(size_t)k * S + tid] = vA[tid];
-    if (mode == KF_STAGE2 && tid < SPS_WAVE) {
-      int bad = 0;
-      for (int s = tid; s < S; s += SPS_WAVE) bad |= !(isfinite(vA[s].x) && isfinite(vA[s].y));
-      if (__any(bad) && tid == 0) atomicOr(d.err, 2);
+    if (tid < S) {
+      const cplx v = vA[tid];
+      a.Xout[(size_t)k * S + tid] = v;
+      if (mode == KF_STAGE2 && __any(!(isfinite(v.x) && isfinite(v.y))) && lane_id() == 0) atomicOr(d.err, 2);
     }
   }
   if (a.zg == nullptr || mode == KF_SOLVE) return;
   // backward Chebyshev transforms of u, w, b (from vA) and of their z-derivatives
   double* ct2 = reinterpret_cast<double*>(un);
   cplx* dz = reinterpret_cast<cplx*>(ct2 + 4 * Ngz);   // 3*N
-  stage_cos(d.cosz, ct2, Ngz);
+  if (tid < 4 * Ngz) ct2[tid] = cosr;
   if (tid < 3 * N) {
     const int f = tid / N, m = tid - f * N;
     dz[tid] = dz_coef(vA + f * N, m, N);
@@ -822,16 +824,30 @@ struct KaArgs {
   int flags;
 };
 
+// The zbar entries of mirror pair (f, j) = (tid / Hc, tid % Hc), f < 6, read by each thread at
+// kernel start (6 Hc <= NTK).
+struct ZbarPair {
+  cplx vj, vm;
+  bool on;
+};
+__device__ __forceinline__ ZbarPair load_zbar_pair(const RbcDev& d, const KaArgs& a, int k, bool want) {
+  const int Hc = half_nodes(d.Ngz), tid = threadIdx.x;
+  const int f = tid / Hc, j = tid - f * Hc, jm = d.Ngz - 1 - j;
+  ZbarPair z;
+  z.on = want && tid < 6 * Hc;
+  z.vj = z.on ? a.zbar[((size_t)f * d.Ngz + j) * d.K + k] : czero();
+  z.vm = z.on ? a.zbar[((size_t)f * d.Ngz + jm) * d.K + k] : czero();
+  return z;
+}
+
 // c_bar for u, w, b from zbar (adjoint Chebyshev backward transform + derivative transposes).
 // pqz: 12*Hc, cb: 6*N, out: 3*N, ct: staged cosines.  Block-wide.
-__device__ void zbar_to_coeffs(const RbcDev& d, const KaArgs& a, int k, const double* ct, cplx* pqz, cplx* cb,
+__device__ void zbar_to_coeffs(const RbcDev& d, const ZbarPair& zp, const double* ct, cplx* pqz, cplx* cb,
                                cplx* out) {
-  const int tid = threadIdx.x, N = d.N, Ngz = d.Ngz, K = d.K, Hc = half_nodes(Ngz);
-  for (int e = tid; e < 6 * Hc; e += NTK) {
-    const int f = e / Hc, j = e - f * Hc, jm = Ngz - 1 - j;
-    const cplx vj = a.zbar[((size_t)f * Ngz + j) * K + k];
-    const cplx vm = a.zbar[((size_t)f * Ngz + jm) * K + k];
-    store_mirror_pair(vj, vm, jm == j, pqz + 2 * (f * Hc + j));
+  const int tid = threadIdx.x, N = d.N, Ngz = d.Ngz, Hc = half_nodes(Ngz);
+  if (zp.on) {
+    const int f = tid / Hc, j = tid - f * Hc;
+    store_mirror_pair(zp.vj, zp.vm, Ngz - 1 - j == j, pqz + 2 * (f * Hc + j));
   }
   __syncthreads();
   // transposed (unscaled) backward transform: 4 lanes per (field group of 3, mode)
@@ -901,15 +917,22 @@ __global__ void __launch_bounds__(NTK) rbc_kadj(RbcDev d, KaArgs a) {
   cplx* p_g = pqz;                                      // S  cotangent of F
   cplx* p_nh = p_g + S;                                 // 3*N
 
+  // global reads in the order they are needed, the block operators last
+  const bool in_x = (fl & (KA_SOLVE_T | KA_G)) || ((fl & KA_A) && !(fl & KA_C));
+  const cplx xin = (in_x && sl) ? a.Xb_in[ks] : czero();
+  const cplx accv = ((fl & KA_C) && a.acc && sl) ? a.acc[ks] : czero();
+  const cplx y2v = ((fl & KA_B) && sl) ? a.Ybuf[ks] : czero();
+  const ZbarPair zp = load_zbar_pair(d, a, k, (fl & (KA_C | KA_B)) != 0);
+  const double cosr = (tid < 4 * Ngz) ? d.cosz[tid] : 0.0;
   OpsRegs opsr;
   MapRegs mr;
   if (fl & (KA_A | KA_B | KA_SOLVE_T)) {
     ops_issue(d.ops + (size_t)k * d.opsize, d.opsize, opsr);
     load_maps(d, mr);
   }
-  stage_cos(d.cosz, ct, Ngz);
+  if (tid < 4 * Ngz) ct[tid] = cosr;
   if (fl & KA_SOLVE_T) {
-    if (sl) xbar[tid] = a.Xb_in[ks];
+    if (sl) xbar[tid] = xin;
     __syncthreads();
     rbc_gather_h(d, mr, xbar, vA);
     rbc_solve_staged(d, opsr, ops, vA, true);
@@ -918,22 +941,21 @@ __global__ void __launch_bounds__(NTK) rbc_kadj(RbcDev d, KaArgs a) {
     return;
   }
   if (fl & KA_G) {
-    if (sl) p_g[tid] = a.Xb_in[ks];
+    if (sl) p_g[tid] = xin;
     __syncthreads();
     g_to_nlbar(d, a, k, ct, p_g, p_nh);
     return;
   }
   if (fl & KA_C) {
-    const cplx acc = (a.acc && sl) ? a.acc[ks] : czero();
-    zbar_to_coeffs(d, a, k, ct, pqz, cb, vv);
-    if (sl) xbar[tid] = (tid < 3 * N) ? cadd(acc, vv[tid]) : acc;
+    zbar_to_coeffs(d, zp, ct, pqz, cb, vv);
+    if (sl) xbar[tid] = (tid < 3 * N) ? cadd(accv, vv[tid]) : accv;
     __syncthreads();
     if (!(fl & KA_A)) {
       if (sl) a.Xb_out[ks] = xbar[tid];
       return;
     }
   } else if (fl & KA_A) {
-    if (sl) xbar[tid] = a.Xb_in[ks];
+    if (sl) xbar[tid] = xin;
     __syncthreads();
   }
   if (fl & KA_A) {
@@ -941,7 +963,7 @@ __global__ void __launch_bounds__(NTK) rbc_kadj(RbcDev d, KaArgs a) {
     rbc_gather_h(d, mr, xbar, vA);
     rbc_solve_staged(d, opsr, ops, vA, true);
     rbc_scatter_h(d, mr, vA, vB);
-    stage_cos(d.cosz, ct, Ngz);
+    if (tid < 4 * Ngz) ct[tid] = cosr;
     if (sl) {
       a.Ybuf[ks] = vB[tid];
       p_g[tid] = cscale(vB[tid], dt * (1.0 - dl));
@@ -951,8 +973,7 @@ __global__ void __launch_bounds__(NTK) rbc_kadj(RbcDev d, KaArgs a) {
     return;
   }
   if (fl & KA_B) {
-    const cplx y2v = sl ? a.Ybuf[ks] : czero();
-    zbar_to_coeffs(d, a, k, ct, pqz, cb, vv);
+    zbar_to_coeffs(d, zp, ct, pqz, cb, vv);
     if (sl) y2[tid] = y2v;
     __syncthreads();
     // xbar_1 = F-VJP part - dt (1 - gamma) L^H Y2
@@ -966,7 +987,7 @@ __global__ void __launch_bounds__(NTK) rbc_kadj(RbcDev d, KaArgs a) {
     rbc_gather_h(d, mr, xbar, vA);
     rbc_solve_staged(d, opsr, ops, vA, true);
     rbc_scatter_h(d, mr, vA, vB);     // vB = Y1
-    stage_cos(d.cosz, ct, Ngz);
+    if (tid < 4 * Ngz) ct[tid] = cosr;
     if (sl) {
       p_y2[tid] = y2v;
       p_t[tid] = cadd(vB[tid], y2v);
@@ -1624,7 +1645,8 @@ class RbcProblem : public ProblemImpl {
     ku_ = hb.ku;
     SPS_REQUIRE(kl_ + SPS_BLK <= SPS_TW && SPS_BLK + kl_ + ku_ <= SPS_GW, "band too wide for the block solver");
     SPS_REQUIRE(blk_ops_size(S_) <= 2 * SPS_OPS_REG * NTK, "nz too large for the staged block solver");
-    SPS_REQUIRE(S_ + SPS_PAD <= NTK && 4 * N_ + 28 <= NTK, "nz too large for one state entry per thread");
+    SPS_REQUIRE(S_ + SPS_PAD <= NTK && 4 * N_ + 28 <= NTK && 4 * Ngz_ <= NTK && 6 * half_nodes(Ngz_) <= NTK,
+                "nz too large for one state entry per thread");
     BM_ = arena_.upload(hb.BM, stream);
     BL_ = arena_.upload(hb.BL, stream);
     dv_.n = S_;
