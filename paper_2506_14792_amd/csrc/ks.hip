@@ -1,8 +1,382 @@
-// 1D Kuramoto-Sivashinsky (Fourier, SBDF2) — placeholder until its kernels land.
+// 1D Kuramoto-Sivashinsky equation u_t + u_xx + u_xxxx + u u_x = 0 on a periodic interval,
+// in the IVP form M dX/dt + L X = F(X) (Supplementary, "Initial value problems") with one
+// unknown per stored Fourier mode m < K = nx/2: M = 1, L_m = -k_m^2 + k_m^4,
+// F = -1/2 d/dx(u^2) with the product on the 3/2 grid (Methods, dealiasing).  Timestepping is
+// SBDF2 with an SBDF1 first step (equ:imex); the reverse sweep is the multistep adjoint
+// recurrence (equ:IMEX_adjoint).  The implicit matrices are diagonal, so a whole sweep is
+// one block that loops over the steps (a persistent launch) and keeps the per-mode history
+// in registers; the states of the run are stored for the reverse sweep.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include <vector>
+
+#include "sps_device.h"
 #include "sps_internal.h"
 
 namespace sps {
-ProblemImpl* make_ks(const sps_desc&, hipStream_t) {
-  throw Error(SPS_E_UNSUPPORTED, "KS problem not built yet");
+namespace {
+
+constexpr int NTS = 256;  // threads of every KS block
+
+struct KsDev {
+  int K, Ng;
+  const double* kx;   // [K] k_m = 2 pi m / L
+  const double* lin;  // [K] L_m = -k_m^2 + k_m^4
+  const cplx* ex;     // [Ng] exp(2 pi i t / Ng)
+};
+
+// Multistep coefficients of step n (equ:imex): (a0 M + L) X_n = sum_i c_i F_{n-i} - a_i M X_{n-i}.
+struct SbdfCoef {
+  double a0, a1, a2, c1, c2;
+};
+__device__ __forceinline__ SbdfCoef sbdf_coef(int n, double dt) {
+  if (n == 1) return {1.0 / dt, -1.0 / dt, 0.0, 1.0, 0.0};
+  return {1.5 / dt, -2.0 / dt, 0.5 / dt, 2.0, -1.0};
 }
+
+// Grid values from half-spectrum coefficients (LDS), W = 2 for the real field
+// u_j = Re c_0 + 2 sum_{m>=1} Re(c_m e^{2 pi i j m / Ng}), W = 1 for the transposed forward
+// transform (unweighted).  Two series at once (b may be null).  Block-wide, no barrier.
+__device__ __forceinline__ void ks_grid_point(const KsDev& d, const cplx* ex, const cplx* a, double Wa,
+                                              const cplx* b, double Wb, int j, double& ua, double& ub) {
+  int t = 0;
+  double sa = 0.0, sb = 0.0;
+  for (int m = 1; m < d.K; ++m) {
+    t += j;
+    if (t >= d.Ng) t -= d.Ng;
+    const cplx e = ex[t];
+    sa = fma(a[m].x, e.x, fma(-a[m].y, e.y, sa));
+    if (b) sb = fma(b[m].x, e.x, fma(-b[m].y, e.y, sb));
+  }
+  ua = a[0].x + Wa * sa;
+  ub = b ? b[0].x + Wb * sb : 0.0;
+}
+
+// sum_j v_j e^{-2 pi i j m / Ng} over the grid, four lanes (an aligned quad) per mode; every
+// lane of the quad returns the sum.
+__device__ __forceinline__ cplx ks_mode_sum(const KsDev& d, const cplx* ex, const double* v, int m, int h) {
+  const int Ng = d.Ng;
+  int t = (h * m) % Ng;
+  const int st = (4 * m) % Ng;
+  double sr = 0.0, si = 0.0;
+  for (int j = h; j < Ng; j += 4) {
+    const cplx e = ex[t];
+    sr = fma(v[j], e.x, sr);
+    si = fma(-v[j], e.y, si);
+    t += st;
+    if (t >= Ng) t -= Ng;
+  }
+  return group_sum<4>(cmk(sr, si));
+}
+
+// F(X) for X in LDS c; result fo[m] (LDS).  u: Ng doubles scratch.  Starts after a barrier
+// that made c visible; ends with a barrier.
+__device__ void ks_eval_F(const KsDev& d, const cplx* ex, const cplx* c, double* u, cplx* fo) {
+  for (int j = threadIdx.x; j < d.Ng; j += NTS) {
+    double v, unused;
+    ks_grid_point(d, ex, c, 2.0, nullptr, 0.0, j, v, unused);
+    u[j] = v * v;
+  }
+  __syncthreads();
+  const double inv = 1.0 / d.Ng;
+  for (int e = threadIdx.x; e < 4 * d.K; e += NTS) {
+    const int m = e >> 2, h = e & 3;
+    const cplx s = ks_mode_sum(d, ex, u, m, h);
+    const double k = d.kx[m];
+    // -1/2 i k (s / Ng)
+    if (h == 0) fo[m] = cmk(0.5 * k * s.y * inv, -0.5 * k * s.x * inv);
+  }
+  __syncthreads();
+}
+
+// Vector-Jacobian product of F at X (LDS c) with cotangent G (LDS g): sqbar = (1/2) i k G,
+// ubar_j = 2 u_j (1/Ng) sum_m Re(sqbar_m e^{i theta_jm}), Xbar_m = w_m sum_j ubar_j e^{-i theta_jm}
+// (w_0 = 1, w_m = 2).  sb: K, u: Ng scratch; result xo[m].  Starts after a barrier that made
+// c and g visible; ends with a barrier.
+__device__ void ks_F_vjp(const KsDev& d, const cplx* ex, const cplx* c, const cplx* g, cplx* sb, double* u,
+                         cplx* xo) {
+  const int tid = threadIdx.x;
+  if (tid < d.K) {
+    const double k = d.kx[tid];
+    sb[tid] = cmk(-0.5 * k * g[tid].y, 0.5 * k * g[tid].x);
+  }
+  __syncthreads();
+  const double inv = 1.0 / d.Ng;
+  for (int j = tid; j < d.Ng; j += NTS) {
+    double uj, rj;
+    ks_grid_point(d, ex, c, 2.0, sb, 1.0, j, uj, rj);
+    u[j] = 2.0 * uj * rj * inv;
+  }
+  __syncthreads();
+  for (int e = tid; e < 4 * d.K; e += NTS) {
+    const int m = e >> 2, h = e & 3;
+    const cplx s = ks_mode_sum(d, ex, u, m, h);
+    if (h == 0) xo[m] = cscale(s, m == 0 ? 1.0 : 2.0);
+  }
+  __syncthreads();
+}
+
+// LDS of every KS kernel: ex (Ng), c, g, sb, fo (K each), u (Ng doubles)
+struct KsLds {
+  cplx *ex, *c, *g, *sb, *fo;
+  double* u;
+};
+__device__ __forceinline__ KsLds ks_lds(const KsDev& d, double* smem) {
+  KsLds L;
+  L.ex = reinterpret_cast<cplx*>(smem);
+  L.c = L.ex + d.Ng;
+  L.g = L.c + d.K;
+  L.sb = L.g + d.K;
+  L.fo = L.sb + d.K;
+  L.u = reinterpret_cast<double*>(L.fo + d.K);
+  for (int t = threadIdx.x; t < d.Ng; t += NTS) L.ex[t] = d.ex[t];
+  return L;
+}
+
+// Forward sweep: X (in: X_0, out: X_N), history H[n][K] of X_0 .. X_N.  One block.
+__global__ void __launch_bounds__(NTS) ks_forward(KsDev d, cplx* X, cplx* H, int nsteps, double dt, int* err) {
+  extern __shared__ double smem_d[];
+  const KsLds L = ks_lds(d, smem_d);
+  const int m = threadIdx.x, K = d.K;
+  const bool own = m < K;
+  const double lin = own ? d.lin[m] : 0.0;
+  cplx x1 = own ? X[m] : czero(), x2 = czero(), f1 = czero(), f2 = czero();
+  if (own) {
+    H[m] = x1;
+    L.c[m] = x1;
+  }
+  __syncthreads();
+  ks_eval_F(d, L.ex, L.c, L.u, L.fo);
+  if (own) f1 = L.fo[m];
+  for (int n = 1; n <= nsteps; ++n) {
+    const SbdfCoef q = sbdf_coef(n, dt);
+    cplx rhs = cadd(cscale(f1, q.c1), cscale(f2, q.c2));
+    rhs = csub(rhs, cadd(cscale(x1, q.a1), cscale(x2, q.a2)));
+    const cplx xn = cscale(rhs, 1.0 / (q.a0 + lin));
+    if (own) {
+      H[(size_t)n * K + m] = xn;
+      L.c[m] = xn;
+    }
+    x2 = x1;
+    x1 = xn;
+    f2 = f1;
+    if (n < nsteps) {
+      __syncthreads();
+      ks_eval_F(d, L.ex, L.c, L.u, L.fo);
+      if (own) f1 = L.fo[m];
+    }
+  }
+  if (own) {
+    X[m] = x1;
+    if (__any(!(isfinite(x1.x) && isfinite(x1.y))) && lane_id() == 0) atomicOr(err, 2);
+  }
+}
+
+// Reverse sweep: Xbar (in: dJ/dX_N, out: dJ/dX_0) through the history H of the forward run.
+// The cotangent of X_{n-1} collects Y_n (step n, i = 1) and Y_{n+1} (step n+1, i = 2), so it
+// is complete once Y_n is known; F's VJP, linear in its cotangent, is applied once per state.
+__global__ void __launch_bounds__(NTS) ks_adjoint(KsDev d, cplx* Xbar, const cplx* H, int nsteps, double dt) {
+  extern __shared__ double smem_d[];
+  const KsLds L = ks_lds(d, smem_d);
+  const int m = threadIdx.x, K = d.K;
+  const bool own = m < K;
+  const double lin = own ? d.lin[m] : 0.0;
+  cplx xb = own ? Xbar[m] : czero();   // cotangent of X_n (complete)
+  cplx ynext = czero();                // Y_{n+1}
+  cplx hnext = (own && nsteps >= 1) ? H[(size_t)(nsteps - 1) * K + m] : czero();
+  for (int n = nsteps; n >= 1; --n) {
+    const SbdfCoef q = sbdf_coef(n, dt);
+    const cplx y = cscale(xb, 1.0 / (q.a0 + lin));
+    const bool has_next = n + 1 <= nsteps;
+    const SbdfCoef qn = sbdf_coef(n + 1, dt);
+    cplx g = cscale(y, q.c1);
+    cplx lin_part = cscale(y, q.a1);
+    if (has_next) {
+      g = cadd(g, cscale(ynext, qn.c2));
+      lin_part = cadd(lin_part, cscale(ynext, qn.a2));
+    }
+    const cplx hcur = hnext;
+    if (own && n >= 2) hnext = H[(size_t)(n - 2) * K + m];   // next iteration's state, early
+    if (own) {
+      L.c[m] = hcur;
+      L.g[m] = g;
+    }
+    __syncthreads();
+    ks_F_vjp(d, L.ex, L.c, L.g, L.sb, L.u, L.fo);
+    xb = own ? csub(L.fo[m], lin_part) : czero();
+    ynext = y;
+  }
+  if (own) Xbar[m] = xb;
+}
+
+// F or its VJP at one state (one block).
+__global__ void __launch_bounds__(NTS) ks_eval(KsDev d, const cplx* X, const cplx* G, cplx* out) {
+  extern __shared__ double smem_d[];
+  const KsLds L = ks_lds(d, smem_d);
+  const int m = threadIdx.x;
+  if (m < d.K) {
+    L.c[m] = X[m];
+    if (G) L.g[m] = G[m];
+  }
+  __syncthreads();
+  if (G) ks_F_vjp(d, L.ex, L.c, L.g, L.sb, L.u, L.fo);
+  else ks_eval_F(d, L.ex, L.c, L.u, L.fo);
+  if (m < d.K) out[m] = L.fo[m];
+}
+
+// J = 1/2 sum_m w_m |c_m|^2 (Parseval of (1/L) int u^2 / 2, c_0 by its real part), dJ/dX = w c.
+__global__ void __launch_bounds__(NTS) ks_cost(KsDev d, const cplx* X, cplx* dJ, double* J) {
+  __shared__ double red[NTS];
+  const int m = threadIdx.x;
+  double part = 0.0;
+  if (m < d.K) {
+    cplx c = X[m];
+    if (m == 0) c.y = 0.0;
+    const double w = (m == 0) ? 1.0 : 2.0;
+    dJ[m] = cscale(c, w);
+    part = 0.5 * w * (c.x * c.x + c.y * c.y);
+  }
+  red[m] = part;
+  __syncthreads();
+  for (int s = NTS / 2; s > 0; s >>= 1) {
+    if (m < s) red[m] += red[m + s];
+    __syncthreads();
+  }
+  if (J && m == 0) J[0] = red[0];
+}
+
+// X = (1.5/dt M + L)^{-1} R, the SBDF2 matrix (real diagonal, so equal to its adjoint).
+__global__ void __launch_bounds__(NTS) ks_solve(KsDev d, const cplx* R, cplx* X, double dt) {
+  const int m = threadIdx.x;
+  if (m < d.K) X[m] = cscale(R[m], 1.0 / (1.5 / dt + d.lin[m]));
+}
+
+class KsProblem : public ProblemImpl {
+ public:
+  KsProblem(const sps_desc& desc, hipStream_t s) : desc_(desc) {
+    stream = s;
+    SPS_REQUIRE(desc.scheme == SPS_SBDF2, "KS supports the SBDF2 scheme");
+    SPS_REQUIRE(desc.nx >= 4 && desc.nx % 2 == 0 && desc.nx / 2 <= NTS, "nx must be even, 4 <= nx <= 512");
+    SPS_REQUIRE(desc.dealias == 1.5, "KS uses 3/2 dealiasing");
+    SPS_REQUIRE(desc.lx > 0 && desc.dt > 0 && desc.max_steps >= 1, "bad lx / dt / max_steps");
+    K_ = desc.nx / 2;
+    Ng_ = 3 * desc.nx / 2;
+    std::vector<double> kx(K_), lin(K_);
+    for (int m = 0; m < K_; ++m) {
+      kx[m] = 2.0 * M_PI * m / desc.lx;
+      lin[m] = -kx[m] * kx[m] + kx[m] * kx[m] * kx[m] * kx[m];
+    }
+    std::vector<double2> ex(Ng_);
+    const long double tau = 6.28318530717958647692528676655900577L;
+    for (int t = 0; t < Ng_; ++t) {
+      const long double a = tau * (long double)t / (long double)Ng_;
+      ex[t] = make_double2((double)cosl(a), (double)sinl(a));
+    }
+    dv_.K = K_;
+    dv_.Ng = Ng_;
+    dv_.kx = arena_.upload(kx, stream);
+    dv_.lin = arena_.upload(lin, stream);
+    dv_.ex = arena_.upload(ex, stream);
+    H_ = arena_.alloc<cplx>((size_t)(desc.max_steps + 1) * K_);
+    Xw_ = arena_.alloc<cplx>(K_);
+    err_ = arena_.alloc<int>(1);
+    SPS_HIP(hipMemsetAsync(err_, 0, sizeof(int), stream));
+    SPS_HIP(hipStreamSynchronize(stream));
+  }
+
+  long long state_size() const override { return 2LL * K_; }
+  void factor() override {}   // diagonal: nothing to factor
+
+  void step(double* X, int nsteps) override {
+    SPS_REQUIRE(X != nullptr, "X is null");
+    SPS_REQUIRE(nsteps >= 1 && nsteps <= desc_.max_steps, "nsteps out of range");
+    forward(reinterpret_cast<cplx*>(X), nsteps);
+  }
+  void adjoint_step(double* Xbar, int nsteps) override {
+    SPS_REQUIRE(Xbar != nullptr, "Xbar is null");
+    if (tape_steps_ != nsteps) throw Error(SPS_E_STATE, "adjoint_step: nsteps does not match the recorded forward run");
+    hipLaunchKernelGGL(ks_adjoint, dim3(1), dim3(NTS), lds(), stream, dv_, reinterpret_cast<cplx*>(Xbar), H_, nsteps,
+                       desc_.dt);
+    SPS_CHECK_LAUNCH();
+  }
+  void cost(const double* X, double* J, double* dJdX) override {
+    SPS_REQUIRE(X && dJdX, "null argument");
+    hipLaunchKernelGGL(ks_cost, dim3(1), dim3(NTS), 0, stream, dv_, reinterpret_cast<const cplx*>(X),
+                       reinterpret_cast<cplx*>(dJdX), J);
+    SPS_CHECK_LAUNCH();
+  }
+  void gradient(const double* X0, int nsteps, double* XN, double* dJdX0, double* J) override {
+    SPS_REQUIRE(X0 && dJdX0, "null argument");
+    SPS_REQUIRE(nsteps >= 1 && nsteps <= desc_.max_steps, "nsteps out of range");
+    SPS_HIP(hipMemcpyAsync(Xw_, X0, sizeof(cplx) * K_, hipMemcpyDeviceToDevice, stream));
+    forward(Xw_, nsteps);
+    if (XN) SPS_HIP(hipMemcpyAsync(XN, Xw_, sizeof(cplx) * K_, hipMemcpyDeviceToDevice, stream));
+    cost(reinterpret_cast<const double*>(Xw_), J, dJdX0);
+    adjoint_step(dJdX0, nsteps);
+  }
+  void initial_state(const double*, double*) override {
+    throw Error(SPS_E_UNSUPPORTED, "KS states are given as Fourier coefficients");
+  }
+  void initial_state_adjoint(const double*, double*) override {
+    throw Error(SPS_E_UNSUPPORTED, "KS states are given as Fourier coefficients");
+  }
+  void eval_F(const double* X, double* F) override {
+    SPS_REQUIRE(X && F, "null argument");
+    hipLaunchKernelGGL(ks_eval, dim3(1), dim3(NTS), lds(), stream, dv_, reinterpret_cast<const cplx*>(X), nullptr,
+                       reinterpret_cast<cplx*>(F));
+    SPS_CHECK_LAUNCH();
+  }
+  void eval_F_vjp(const double* X, const double* Fbar, double* Xbar) override {
+    SPS_REQUIRE(X && Fbar && Xbar, "null argument");
+    hipLaunchKernelGGL(ks_eval, dim3(1), dim3(NTS), lds(), stream, dv_, reinterpret_cast<const cplx*>(X),
+                       reinterpret_cast<const cplx*>(Fbar), reinterpret_cast<cplx*>(Xbar));
+    SPS_CHECK_LAUNCH();
+  }
+  void solve(const double* R, double* X, int) override {
+    SPS_REQUIRE(R && X, "null argument");
+    hipLaunchKernelGGL(ks_solve, dim3(1), dim3(NTS), 0, stream, dv_, reinterpret_cast<const cplx*>(R),
+                       reinterpret_cast<cplx*>(X), desc_.dt);
+    SPS_CHECK_LAUNCH();
+  }
+  void timer_enable(int kind, bool on) override {
+    SPS_REQUIRE(kind == 0, "unknown timer kind");
+    timer_.enable(on);
+  }
+  void timer_read(long long* launches, double* ms) override { timer_.read(launches, ms); }
+  int device_error() override {
+    int h = 0;
+    SPS_HIP(hipMemcpyAsync(&h, err_, sizeof(int), hipMemcpyDeviceToHost, stream));
+    SPS_HIP(hipStreamSynchronize(stream));
+    if (h) SPS_HIP(hipMemsetAsync(err_, 0, sizeof(int), stream));
+    return h;
+  }
+
+ private:
+  size_t lds() const { return sizeof(cplx) * (Ng_ + 4 * K_) + sizeof(double) * Ng_; }
+  void forward(cplx* X, int nsteps) {
+    hipEvent_t e0, e1;
+    if (timer_.take(&e0, &e1))
+      hipExtLaunchKernelGGL(ks_forward, dim3(1), dim3(NTS), lds(), stream, e0, e1, 0, dv_, X, H_, nsteps, desc_.dt,
+                            err_);
+    else
+      hipLaunchKernelGGL(ks_forward, dim3(1), dim3(NTS), lds(), stream, dv_, X, H_, nsteps, desc_.dt, err_);
+    SPS_CHECK_LAUNCH();
+    tape_steps_ = nsteps;
+  }
+
+  sps_desc desc_;
+  int K_ = 0, Ng_ = 0;
+  KsDev dv_{};
+  DevArena arena_;
+  cplx *H_ = nullptr, *Xw_ = nullptr;
+  int* err_ = nullptr;
+  int tape_steps_ = -1;
+  KernelTimer timer_;
+};
+
+}  // namespace
+
+ProblemImpl* make_ks(const sps_desc& d, hipStream_t s) { return new KsProblem(d, s); }
+
 }  // namespace sps
