@@ -89,6 +89,41 @@ def cpu_baseline(nsteps=60):
                       f"{t:.1f} s; host has {os.cpu_count()} logical CPUs"}
 
 
+KS_CFG = dict(nx=64, L=32.0 * np.pi, dt=0.05, nsteps=200, seed=0)
+
+
+def ks_timing(reps=20):
+    """The first configuration (1D Kuramoto-Sivashinsky, 64 modes, SBDF2 dt = 0.05, 200 steps,
+    gradient of 1/2 ||u(T)||^2 w.r.t. the initial coefficients): GPU gradient time and the
+    oracle's CPU seconds for the same gradient."""
+    import torch
+    import paper_2506_14792_amd as sps
+    import workloads as wl
+    from oracle import imex
+    from oracle.ks import KS
+    c = KS_CFG
+    G = sps.Problem(sps.KS1D, c["nx"], 0, c["L"], 0.0, 0.0, 1.5, c["dt"], 1, c["nsteps"])
+    c0 = wl.ks_c0(seed=c["seed"], Nx=c["nx"])[:, None]
+    X0 = torch.from_numpy(np.ascontiguousarray(c0).view(np.float64).ravel().copy()).cuda()
+    g = torch.zeros(G.n, dtype=torch.float64, device="cuda")
+    G.gradient(X0, c["nsteps"], None, g, None)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        G.gradient(X0, c["nsteps"], None, g, None)
+    torch.cuda.synchronize()
+    gpu_s = (time.perf_counter() - t0) / reps
+    G.sync()
+    P = KS(Nx=c["nx"], L=c["L"])
+    t0 = time.perf_counter()
+    XN, states = imex.sbdf_forward(P, c0, c["dt"], c["nsteps"])
+    imex.sbdf_adjoint(P, P.energy_grad(XN), states, c["dt"])
+    cpu_s = time.perf_counter() - t0
+    return {"workload": "Kuramoto-Sivashinsky 1D, 64 Fourier modes, L = 32 pi, SBDF2 dt = 0.05, 200 steps, "
+                        "gradient of 1/2 ||u(T)||^2", "gpu_gradient_s": gpu_s, "oracle_cpu_gradient_s": cpu_s,
+            "gpu_timesteps_per_s": 2 * c["nsteps"] / gpu_s}
+
+
 def copy_calibration(nbytes=1 << 28, reps=5):
     import torch
     src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
@@ -173,6 +208,7 @@ def main():
     avg_ms = kern_ms / max(launches, 1)
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
     traffic = measured_traffic()
+    ks = ks_timing()
     cpu = None if args.no_cpu else cpu_baseline(args.cpu_steps)
     out = {
         "metric": METRIC,
@@ -200,6 +236,7 @@ def main():
                      "traffic": traffic, "bytes_per_launch": bytes_launch, "avg_launch_ms": avg_ms,
                      "launches_timed": launches},
         "cpu_baseline": cpu,
+        "ks_config": ks,
         "J": J.item(),
     }
     print(json.dumps(out))

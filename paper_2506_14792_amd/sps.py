@@ -107,6 +107,7 @@ class Problem:
         _check(lib().sps_build_problem(ctypes.byref(self.desc), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
         self._h = h
         self.n = int(lib().sps_state_size(h))
+        self.tape_id = 0   # advanced by every forward sweep; a reverse sweep needs the latest one
 
     def close(self):
         if getattr(self, "_h", None):
@@ -125,6 +126,7 @@ class Problem:
 
     def step(self, X, nsteps):
         _check(lib().sps_step(self._h, _ptr(X, self.n), nsteps))
+        self.tape_id += 1
 
     def adjoint_step(self, Xbar, nsteps):
         _check(lib().sps_adjoint_step(self._h, _ptr(Xbar, self.n), nsteps))
@@ -133,6 +135,7 @@ class Problem:
         _check(lib().sps_cost(self._h, _ptr(X, self.n), _ptr(J, 1), _ptr(dJdX, self.n)))
 
     def gradient(self, X0, nsteps, XN, dJdX0, J):
+        self.tape_id += 1
         _check(lib().sps_gradient(self._h, _ptr(X0, self.n), nsteps, _ptr(XN, self.n), _ptr(dJdX0, self.n),
                                   _ptr(J, 1)))
 
