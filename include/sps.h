@@ -125,6 +125,18 @@ int sps_solve(sps_problem *P, const double *R, double *X, int adjoint);
 int sps_timer_enable(sps_problem *P, int kind, int on);
 int sps_timer_read(sps_problem *P, long long *launches, double *total_ms);
 
+/* Graph mode for sps_gradient (a step sequence captured once and replayed as one HIP graph;
+ * the paper's method is unchanged, only how the launches reach the GPU).  With on != 0 the
+ * first sps_gradient call for a given (X0, nsteps, XN, dJdX0, J) tuple records its whole
+ * launch sequence (forward sweep, checkpoint copies, cost seed, and the reverse sweep on
+ * both of the problem's streams) into a graph, on a private capture stream, and launches it
+ * on the problem's stream; later calls with the same tuple replay it.  Results are identical
+ * to eager launches.  The graphs hold kernel and device-to-device copy nodes only (no
+ * memsets) and keep the pointers of their tuple: the arrays must stay allocated while graph
+ * mode is on.  on = 0 (the default) launches eagerly and frees the recorded graphs.  The
+ * kernel timer is not fed by replays.  SPS_E_UNSUPPORTED for problems without graph mode. */
+int sps_set_graph(sps_problem *P, int on);
+
 /* Wait for the problem's stream; report a deferred device error. */
 int sps_sync(sps_problem *P);
 

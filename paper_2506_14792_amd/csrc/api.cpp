@@ -153,6 +153,10 @@ int sps_timer_read(sps_problem* P, long long* launches, double* total_ms) {
   return guard(P, [&](sps::ProblemImpl& p) { p.timer_read(launches, total_ms); });
 }
 
+int sps_set_graph(sps_problem* P, int on) {
+  return guard(P, [&](sps::ProblemImpl& p) { p.set_graph(on != 0); });
+}
+
 int sps_sync(sps_problem* P) {
   int flag = 0;
   int rc = guard(P, [&](sps::ProblemImpl& p) {

@@ -1343,6 +1343,8 @@ class RbcProblem : public ProblemImpl {
     for (auto& e : ev_) SPS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
   ~RbcProblem() override {
+    drop_graphs();
+    if (cap_) (void)hipStreamDestroy(cap_);
     if (aux_) (void)hipStreamSynchronize(aux_);
     for (auto e : ev_)
       if (e) (void)hipEventDestroy(e);
@@ -1383,10 +1385,33 @@ class RbcProblem : public ProblemImpl {
     }
   }
 
+  void set_graph(bool on) override {
+    if (!on) drop_graphs();
+    graph_on_ = on;
+  }
+
   void gradient(const double* X0, int nsteps, double* XN, double* dJdX0, double* J) override {
     SPS_REQUIRE(X0 && dJdX0, "null argument");
     SPS_REQUIRE(nsteps >= 1 && nsteps <= desc_.max_steps, "nsteps out of range");
     factor();
+    if (graph_on_) {
+      const GraphKey key{X0, XN, dJdX0, J, nsteps};
+      for (const auto& g : graphs_)
+        if (g.first == key) {
+          SPS_HIP(hipGraphLaunch(g.second, stream));
+          tape_steps_ = nsteps;
+          return;
+        }
+      graphs_.emplace_back(key, capture_gradient(X0, nsteps, XN, dJdX0, J));
+      SPS_HIP(hipGraphLaunch(graphs_.back().second, stream));
+      tape_steps_ = nsteps;
+      return;
+    }
+    gradient_launches(X0, nsteps, XN, dJdX0, J);
+  }
+
+  // the launch sequence of one gradient on `stream` (and the auxiliary stream)
+  void gradient_launches(const double* X0, int nsteps, double* XN, double* dJdX0, double* J) {
     SPS_HIP(hipMemcpyAsync(Xg_, X0, sizeof(cplx) * K_ * S_, hipMemcpyDeviceToDevice, stream));
     forward(Xg_, nsteps);
     if (XN) SPS_HIP(hipMemcpyAsync(XN, Xg_, sizeof(cplx) * K_ * S_, hipMemcpyDeviceToDevice, stream));
@@ -1474,6 +1499,50 @@ class RbcProblem : public ProblemImpl {
   size_t xf_lds() const { return sizeof(cplx) * (9 * K_ + 2 * fpad_size(4 * Ngx_) + Ngx_); }
   size_t xa_lds() const { return sizeof(cplx) * (12 * K_ + 2 * fpad_size(6 * Ngx_) + Ngx_); }
 
+  // ----------------------------------------------------------------- graphs
+  struct GraphKey {
+    const double* X0;
+    double *XN, *dJ, *J;
+    int nsteps;
+    bool operator==(const GraphKey& o) const {
+      return X0 == o.X0 && XN == o.XN && dJ == o.dJ && J == o.J && nsteps == o.nsteps;
+    }
+  };
+  // Record one gradient into a graph: the launches go to a private capture stream (the
+  // caller's stream may be the legacy null stream, which cannot be captured); the
+  // auxiliary stream joins the capture through the events of the reverse sweep.
+  hipGraphExec_t capture_gradient(const double* X0, int nsteps, double* XN, double* dJdX0, double* J) {
+    if (!cap_) SPS_HIP(hipStreamCreateWithFlags(&cap_, hipStreamNonBlocking));
+    hipStream_t user = stream;
+    stream = cap_;
+    capturing_ = true;
+    hipGraph_t graph = nullptr;
+    SPS_HIP(hipStreamBeginCapture(cap_, hipStreamCaptureModeThreadLocal));
+    try {
+      gradient_launches(X0, nsteps, XN, dJdX0, J);
+    } catch (...) {
+      (void)hipStreamEndCapture(cap_, &graph);
+      if (graph) (void)hipGraphDestroy(graph);
+      stream = user;
+      capturing_ = false;
+      throw;
+    }
+    const hipError_t e = hipStreamEndCapture(cap_, &graph);
+    stream = user;
+    capturing_ = false;
+    SPS_HIP(e);
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    SPS_HIP(ei);
+    return exec;
+  }
+  void drop_graphs() {
+    if (!graphs_.empty()) (void)hipStreamSynchronize(stream);
+    for (auto& g : graphs_) (void)hipGraphExecDestroy(g.second);
+    graphs_.clear();
+  }
+
   void launch_kf(int mode, const cplx* X0, const cplx* X1, cplx* Xout, cplx* zg) {
     launch_kf_on(stream, mode, X0, X1, Xout, zg);
   }
@@ -1492,7 +1561,7 @@ class RbcProblem : public ProblemImpl {
     a.dl = 1.0 - 1.0 / (2.0 * a.g);
     a.mode = mode;
     hipEvent_t e0, e1;
-    if ((mode == KF_STAGE1 || mode == KF_STAGE2) && s == stream && timer_.take(&e0, &e1))
+    if ((mode == KF_STAGE1 || mode == KF_STAGE2) && s == stream && !capturing_ && timer_.take(&e0, &e1))
       hipExtLaunchKernelGGL(rbc_kfwd, dim3(K_), dim3(NTK), kf_lds(), s, e0, e1, 0, dv_, a);
     else
       hipLaunchKernelGGL(rbc_kfwd, dim3(K_), dim3(NTK), kf_lds(), s, dv_, a);
@@ -1599,6 +1668,9 @@ class RbcProblem : public ProblemImpl {
     KaArgs a = ka_args(KA_C);
     a.Xb_out = Xbar;
     launch_ka(a);
+    // join the auxiliary stream explicitly (it may have waited without launching, nseg = 1)
+    SPS_HIP(hipEventRecord(ev_rec, aux_));
+    SPS_HIP(hipStreamWaitEvent(stream, ev_rec, 0));
   }
 
   // ----------------------------------------------------------------- tables
@@ -1721,8 +1793,10 @@ class RbcProblem : public ProblemImpl {
   cplx *X1_, *Xw_, *Xg_, *acc_, *Ybuf_, *F0_, *zgA_, *zbar_, *nl_, *nlbar_, *itmp_, *ckpt_, *seg_;
   size_t zsize_ = 0;
   int seglen_ = 0;
-  hipStream_t aux_ = nullptr;
+  hipStream_t aux_ = nullptr, cap_ = nullptr;
   hipEvent_t ev_[3] = {nullptr, nullptr, nullptr};
+  bool graph_on_ = false, capturing_ = false;
+  std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs_;
   bool factored_ = false;
   int tape_steps_ = -1;
   KernelTimer timer_;

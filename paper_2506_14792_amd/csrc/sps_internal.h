@@ -128,6 +128,9 @@ class ProblemImpl {
   virtual void timer_enable(int kind, bool on) = 0;
   virtual void timer_read(long long* launches, double* ms) = 0;
   virtual int device_error() = 0;  // reads and clears the sticky device flag
+  virtual void set_graph(bool on) {
+    if (on) throw Error(SPS_E_UNSUPPORTED, "graph mode is not available for this problem");
+  }
   hipStream_t stream = nullptr;
 };
 

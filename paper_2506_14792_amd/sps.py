@@ -55,6 +55,7 @@ def lib():
         "sps_solve": (ctypes.c_int, [_P, _D, _D, ctypes.c_int]),
         "sps_timer_enable": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
         "sps_timer_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double)]),
+        "sps_set_graph": (ctypes.c_int, [_P, ctypes.c_int]),
         "sps_sync": (ctypes.c_int, [_P]),
         "sps_last_error": (ctypes.c_char_p, []),
         "sps_destroy": (None, [_P]),
@@ -162,6 +163,9 @@ class Problem:
         ms = ctypes.c_double()
         _check(lib().sps_timer_read(self._h, ctypes.byref(n), ctypes.byref(ms)))
         return n.value, ms.value
+
+    def set_graph(self, on=True):
+        _check(lib().sps_set_graph(self._h, int(bool(on))))
 
     def sync(self):
         _check(lib().sps_sync(self._h))
