@@ -23,16 +23,27 @@ import scipy.linalg as sla
 
 
 class BlockLU:
-    """LU factors of A_k = a M_k + b L_k for every block k."""
+    """LU factors of A_k = a M_k + b L_k for every block k.  Blocks of size 1 (problems
+    whose operators are diagonal in the spectral basis) are solved by the division the
+    1x1 LU reduces to."""
 
     def __init__(self, M, L, a, b):
-        self.factors = [sla.lu_factor(a * M[k] + b * L[k]) for k in range(M.shape[0])]
+        A = a * M + b * L
+        self.diag = A.shape[1] == 1
+        if self.diag:
+            self.d = A[:, 0, 0]
+        else:
+            self.factors = [sla.lu_factor(A[k]) for k in range(A.shape[0])]
 
     def solve(self, R):
+        if self.diag:
+            return R / self.d[:, None]
         return np.stack([sla.lu_solve(f, R[k]) for k, f in enumerate(self.factors)])
 
     def solve_adjoint(self, G):
         """Solve A_k^H y = g through the same factors."""
+        if self.diag:
+            return G / np.conj(self.d)[:, None]
         return np.stack([sla.lu_solve(f, G[k], trans=2) for k, f in enumerate(self.factors)])
 
 
