@@ -47,7 +47,7 @@ enum sps_status {
   SPS_E_UNSUPPORTED = -7
 };
 
-enum sps_equation { SPS_RBC2D = 1, SPS_KS1D = 2 };
+enum sps_equation { SPS_RBC2D = 1, SPS_KS1D = 2, SPS_SH2D = 3 };
 enum sps_scheme { SPS_RK222 = 1, SPS_SBDF2 = 2 };
 
 typedef struct {
@@ -69,6 +69,30 @@ typedef struct {
  * value problems; checkpointing).  hip_stream may be NULL (the null stream).
  * Returns SPS_E_ARG for unsupported sizes.  *out owns all device memory it allocates. */
 int sps_build_problem(const sps_desc *desc, void *hip_stream, sps_problem **out);
+
+/* Batched 2D Swift-Hohenberg problems u_t = r u - (1 + Laplacian)^2 u - u^3 on [0, lx)^2,
+ * periodic (IVP form of the Supplementary, "Initial value problems": M = 1,
+ * L = -r + (1 - |k|^2)^2, F = -u^3 with the cube on a grid padded by 2), SBDF2 with an SBDF1
+ * first step, one independent instance per entry of n (N_i x N_i modes, N_i even, 8..512,
+ * factors 2 and 3 only) and r (host arrays of length batch, copied).  Every forward sweep,
+ * cost seed and reverse sweep of the whole batch runs as one cooperative persistent launch;
+ * at build time the library times a few steps of each tile configuration (columns per
+ * column tile and row pairs per row tile, per size class, and the block count) and keeps
+ * the fastest.
+ * Layouts: a state holds, per instance in order, X[m][iy] (m < N/2 the k_x index, iy < N the
+ * k_y index in FFT order, iy = N/2 unused and zero), complex as (re, im); grid arrays hold
+ * per instance u[y][x] (N x N).  sps_gradient's J output and sps_cost's J have one value per
+ * instance: J_i = 1/2 mean of u_i(T)^2 over the N_i x N_i grid; the gradient is of the sum.
+ * sps_initial_state maps grid fields to states (the N x N discrete Fourier transform / N^2,
+ * kept modes); sps_solve applies (1.5/dt + L)^-1.  max_steps bounds nsteps; the library
+ * keeps every state of the last forward sweep. */
+int sps_build_sh_batch(int batch, const int *n, const double *r, double lx, double dt, int max_steps,
+                       void *hip_stream, sps_problem **out);
+
+/* The tile configuration the build-time tuning chose for a batched Swift-Hohenberg problem:
+ * col_tile[4] and row_tile[4] for the size classes N <= 64, <= 96, <= 128, larger; the
+ * persistent block count; the measured time of one forward step of the batch (ms). */
+int sps_sh_tuning(const sps_problem *P, int *col_tile, int *row_tile, int *blocks, double *step_ms);
 
 /* Number of doubles in one state vector (K * S * 2). */
 long long sps_state_size(const sps_problem *P);

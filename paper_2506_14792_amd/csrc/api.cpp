@@ -153,6 +153,28 @@ int sps_timer_read(sps_problem* P, long long* launches, double* total_ms) {
   return guard(P, [&](sps::ProblemImpl& p) { p.timer_read(launches, total_ms); });
 }
 
+int sps_build_sh_batch(int batch, const int* n, const double* r, double lx, double dt, int max_steps,
+                       void* hip_stream, sps_problem** out) {
+  if (!out || !n || !r) return fail(SPS_E_ARG, "null argument");
+  *out = nullptr;
+  try {
+    sps::ProblemImpl* impl =
+        sps::make_sh_batch(batch, n, r, lx, dt, max_steps, reinterpret_cast<hipStream_t>(hip_stream));
+    *out = new sps_problem{impl};
+    return SPS_OK;
+  } catch (const sps::Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::exception& e) {
+    return fail(SPS_E_HIP, e.what());
+  }
+}
+
+int sps_sh_tuning(const sps_problem* P, int* col_tile, int* row_tile, int* blocks, double* step_ms) {
+  if (!col_tile || !row_tile || !blocks || !step_ms) return fail(SPS_E_ARG, "null argument");
+  return guard(const_cast<sps_problem*>(P),
+               [&](sps::ProblemImpl& p) { sps::sh_tuning(&p, col_tile, row_tile, blocks, step_ms); });
+}
+
 int sps_set_graph(sps_problem* P, int on) {
   return guard(P, [&](sps::ProblemImpl& p) { p.set_graph(on != 0); });
 }

@@ -7,7 +7,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsps.so")
 
-RBC2D, KS1D = 1, 2
+RBC2D, KS1D, SH2D = 1, 2, 3
 RK222, SBDF2 = 1, 2
 
 _STATUS = {0: "SPS_OK", -1: "SPS_E_ARG", -2: "SPS_E_NOMEM", -3: "SPS_E_HIP", -4: "SPS_E_SINGULAR",
@@ -56,6 +56,10 @@ def lib():
         "sps_timer_enable": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
         "sps_timer_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double)]),
         "sps_set_graph": (ctypes.c_int, [_P, ctypes.c_int]),
+        "sps_build_sh_batch": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
+                                              ctypes.c_double, ctypes.c_double, ctypes.c_int, _P, ctypes.POINTER(_P)]),
+        "sps_sh_tuning": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]),
         "sps_sync": (ctypes.c_int, [_P]),
         "sps_last_error": (ctypes.c_char_p, []),
         "sps_destroy": (None, [_P]),
@@ -169,6 +173,50 @@ class Problem:
 
     def sync(self):
         _check(lib().sps_sync(self._h))
+
+
+class ShBatch(Problem):
+    """A batch of independent 2D Swift-Hohenberg problems (sizes n[i] x n[i], parameters r[i])
+    in one problem handle; states and grids of the instances are concatenated."""
+
+    def __init__(self, n, r, lx=16.0 * np.pi, dt=0.02, max_steps=1, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self._stream = stream
+        self.sizes = [int(v) for v in n]
+        self.batch = len(self.sizes)
+        na = (ctypes.c_int * self.batch)(*self.sizes)
+        ra = (ctypes.c_double * self.batch)(*[float(v) for v in r])
+        h = _P()
+        _check(lib().sps_build_sh_batch(self.batch, na, ra, float(lx), float(dt), int(max_steps),
+                                        ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self.n = int(lib().sps_state_size(h))
+        self.tape_id = 0
+        self.grid_size = sum(v * v for v in self.sizes)
+
+    def cost(self, X, J, dJdX):
+        _check(lib().sps_cost(self._h, _ptr(X, self.n), _ptr(J, self.batch), _ptr(dJdX, self.n)))
+
+    def gradient(self, X0, nsteps, XN, dJdX0, J):
+        self.tape_id += 1
+        _check(lib().sps_gradient(self._h, _ptr(X0, self.n), nsteps, _ptr(XN, self.n), _ptr(dJdX0, self.n),
+                                  _ptr(J, self.batch)))
+
+    def initial_state(self, grid, X):
+        _check(lib().sps_initial_state(self._h, _ptr(grid, self.grid_size), _ptr(X, self.n)))
+
+    def initial_state_adjoint(self, Xbar, grid_bar):
+        _check(lib().sps_initial_state_adjoint(self._h, _ptr(Xbar, self.n), _ptr(grid_bar, self.grid_size)))
+
+    def tuning(self):
+        ct = (ctypes.c_int * 4)()
+        rt = (ctypes.c_int * 4)()
+        b = ctypes.c_int()
+        ms = ctypes.c_double()
+        _check(lib().sps_sh_tuning(self._h, ct, rt, ctypes.byref(b), ctypes.byref(ms)))
+        return {"col_tile": list(ct), "row_pairs": list(rt), "blocks": b.value, "step_ms": ms.value}
 
 
 def rbc_host_bands(nx, nz, lx, Ra, Pr, dt=1e-3):

@@ -42,3 +42,14 @@ def random_state(seed, shape, real_first_row=True):
     if real_first_row:
         X[0] = X[0].real
     return X
+
+
+def sh_batch(seed=0, batch=128, sizes=(64, 96, 128, 192), rmin=0.1, rmax=0.5, amp=0.1):
+    """A batch of Swift-Hohenberg instances: sizes drawn uniformly from `sizes`, r uniform in
+    [rmin, rmax], initial grid fields uniform in [-amp, amp] on each N x N grid.  Returns
+    (sizes, r, list of (N, N) arrays)."""
+    rng = np.random.default_rng(seed)
+    n = rng.choice(np.array(sizes), size=batch)
+    r = rng.uniform(rmin, rmax, size=batch)
+    u0 = [rng.uniform(-amp, amp, size=(int(k), int(k))) for k in n]
+    return [int(k) for k in n], [float(v) for v in r], u0
