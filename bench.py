@@ -127,6 +127,85 @@ def ks_timing(reps=20):
             "gpu_timesteps_per_s": 2 * c["nsteps"] / gpu_s}
 
 
+SH_CFG = dict(nsteps=500, dt=0.02, L=16.0 * np.pi, seed=0)
+
+
+def sh_state_complex(sizes):
+    return sum(n * (n // 2) for n in sizes)
+
+
+def sh_timing(reps=2):
+    """Batched Swift-Hohenberg configuration: 128 instances, sizes drawn from {64, 96, 128, 192}^2,
+    r in [0.1, 0.5], SBDF2 dt = 0.02, 500 steps; one gradient of the summed energies = one
+    persistent launch (forward sweep, cost seed, reverse sweep).  Reported beside the same
+    instances solved one problem at a time (plain launches, one instance of each size timed and
+    weighted by the batch's size counts) and the oracle on one instance of each size for 10
+    steps, extrapolated.  Algorithmic bytes per instance state of S complex modes: forward step
+    13 S x 16 B (column phase: products' x-spectra, two previous states, two F, the new state and
+    F, the new state's y-transform; row phase: 4 S in and out), reverse step 17 S x 16 B."""
+    import torch
+    import paper_2506_14792_amd as sps
+    import workloads as wl
+    from oracle import imex
+    from oracle.sh import SH
+    c = SH_CFG
+    sizes, rs, u0 = wl.sh_batch(seed=c["seed"])
+    G = sps.ShBatch(sizes, rs, c["L"], c["dt"], max_steps=c["nsteps"])
+    grid = torch.from_numpy(np.concatenate([u.ravel() for u in u0])).cuda()
+    X0 = torch.zeros(G.n, dtype=torch.float64, device="cuda")
+    g = torch.zeros_like(X0)
+    gb = torch.zeros_like(grid)
+    J = torch.zeros(len(sizes), dtype=torch.float64, device="cuda")
+
+    def one():
+        G.initial_state(grid, X0)
+        G.gradient(X0, c["nsteps"], None, g, J)
+        G.initial_state_adjoint(g, gb)
+
+    one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        one()
+    torch.cuda.synchronize()
+    batch_s = (time.perf_counter() - t0) / reps
+    G.sync()
+    S = sh_state_complex(sizes)
+    bytes_grad = c["nsteps"] * (13 + 17) * S * 16.0
+    # plain launches: each size alone
+    plain = 0.0
+    counts = {n: sizes.count(n) for n in set(sizes)}
+    for n in sorted(counts):
+        i = sizes.index(n)
+        G1 = sps.ShBatch([n], [rs[i]], c["L"], c["dt"], max_steps=c["nsteps"])
+        x1 = torch.zeros(G1.n, dtype=torch.float64, device="cuda")
+        G1.initial_state(torch.from_numpy(u0[i].ravel().copy()).cuda(), x1)
+        g1 = torch.zeros_like(x1)
+        G1.gradient(x1, c["nsteps"], None, g1, None)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        G1.gradient(x1, c["nsteps"], None, g1, None)
+        torch.cuda.synchronize()
+        plain += counts[n] * (time.perf_counter() - t1)
+        G1.sync()
+    # oracle sample
+    ocpu = 0.0
+    for n in sorted(counts):
+        i = sizes.index(n)
+        P = SH(n, rs[i], L=c["L"])
+        t1 = time.perf_counter()
+        XN, states = imex.sbdf_forward(P, P.initial_state(u0[i]), c["dt"], 10)
+        imex.sbdf_adjoint(P, P.energy_grad(XN), states, c["dt"])
+        ocpu += counts[n] * (time.perf_counter() - t1) * c["nsteps"] / 10
+    return {"workload": "batched Swift-Hohenberg: 128 instances, sizes {64,96,128,192}^2 (seeded), r in [0.1, 0.5], "
+                        "L = 16 pi, 2x padding, SBDF2 dt = 0.02, 500 steps, gradient of the summed energies",
+            "gpu_gradient_s": batch_s, "gpu_instance_timesteps_per_s": 2 * c["nsteps"] * len(sizes) / batch_s,
+            "hbm_achieved_GBps": bytes_grad / batch_s / 1e9, "hbm_frac": bytes_grad / batch_s / 1e9 / HBM_PEAK_GBS,
+            "algorithmic_bytes_per_gradient": bytes_grad, "tuning": G.tuning(),
+            "plain_launch_gradient_s": plain, "batched_speedup_vs_plain": plain / batch_s,
+            "oracle_cpu_gradient_s_extrapolated": ocpu}
+
+
 def copy_calibration(nbytes=1 << 28, reps=5):
     import torch
     src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
@@ -224,6 +303,7 @@ def main():
     graph_sec = (t7 - t6) / args.steps
     traffic = measured_traffic()
     ks = ks_timing()
+    sh = sh_timing()
     cpu = None if args.no_cpu else cpu_baseline(args.cpu_steps)
     out = {
         "metric": METRIC,
@@ -254,6 +334,7 @@ def main():
                      "launches_timed": launches},
         "cpu_baseline": cpu,
         "ks_config": ks,
+        "sh_batched_config": sh,
         "J": J.item(),
     }
     print(json.dumps(out))

@@ -91,8 +91,9 @@ int sps_build_sh_batch(int batch, const int *n, const double *r, double lx, doub
 
 /* The tile configuration the build-time tuning chose for a batched Swift-Hohenberg problem:
  * col_tile[4] and row_tile[4] for the size classes N <= 64, <= 96, <= 128, larger; the
- * persistent block count; the measured time of one forward step of the batch (ms). */
-int sps_sh_tuning(const sps_problem *P, int *col_tile, int *row_tile, int *blocks, double *step_ms);
+ * persistent block count and threads per block; the measured time of one forward step of
+ * the batch (ms). */
+int sps_sh_tuning(const sps_problem *P, int *col_tile, int *row_tile, int *blocks, int *threads, double *step_ms);
 
 /* Number of doubles in one state vector (K * S * 2). */
 long long sps_state_size(const sps_problem *P);

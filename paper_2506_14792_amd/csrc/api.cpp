@@ -169,10 +169,10 @@ int sps_build_sh_batch(int batch, const int* n, const double* r, double lx, doub
   }
 }
 
-int sps_sh_tuning(const sps_problem* P, int* col_tile, int* row_tile, int* blocks, double* step_ms) {
-  if (!col_tile || !row_tile || !blocks || !step_ms) return fail(SPS_E_ARG, "null argument");
+int sps_sh_tuning(const sps_problem* P, int* col_tile, int* row_tile, int* blocks, int* threads, double* step_ms) {
+  if (!col_tile || !row_tile || !blocks || !threads || !step_ms) return fail(SPS_E_ARG, "null argument");
   return guard(const_cast<sps_problem*>(P),
-               [&](sps::ProblemImpl& p) { sps::sh_tuning(&p, col_tile, row_tile, blocks, step_ms); });
+               [&](sps::ProblemImpl& p) { sps::sh_tuning(&p, col_tile, row_tile, blocks, threads, step_ms); });
 }
 
 int sps_set_graph(sps_problem* P, int on) {

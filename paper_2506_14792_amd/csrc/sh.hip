@@ -32,7 +32,7 @@
 namespace sps {
 namespace {
 
-constexpr int NTB = 256;                  // threads of every SH block
+constexpr int NTB = 256;                  // threads of the initial-transform and solve blocks
 constexpr unsigned kSpinLimit = 1u << 22; // bounded wait of a grid barrier (then abort)
 
 struct ShInst {
@@ -118,7 +118,7 @@ __device__ __forceinline__ cplx pack2(const cplx* U, const cplx* V, int m, int n
 
 __device__ __forceinline__ void stage_tw(const ShDev& d, int plan, int n, cplx* tw) {
   const cplx* g = d.tw + d.twoff[plan];
-  for (int e = threadIdx.x; e < n; e += NTB) tw[e] = g[e];
+  for (int e = threadIdx.x; e < n; e += blockDim.x) tw[e] = g[e];
 }
 
 // ---------------------------------------------------------------------------- grid barrier
@@ -153,6 +153,7 @@ __device__ bool grid_sync(const ShDev& d, unsigned& epoch, int* sh_ok) {
 enum ColKind { C_FWD_INIT, C_FWD_STEP, C_EVAL_INIT, C_EVAL_F, C_ADJ_INIT, C_ADJ_STEP, C_VJP_INIT, C_VJP_OUT };
 
 // LDS of a column item: twiddles (Ng), two FFT buffers of 2 tc Ng (padded)
+template <int NT>
 __device__ void col_item(const ShDev& d, const ShRun& a, int2 item, int kind, int n, double* smem) {
   const ShInst I = d.inst[item.x];
   const int N = I.N, Nh = I.Nh, Ng = I.Ng, c0 = item.y;
@@ -172,12 +173,12 @@ __device__ void col_item(const ShDev& d, const ShRun& a, int2 item, int kind, in
   // forward y-FFT of the x-spectra W for the tile's columns -> res (unnormalized)
   const cplx* res = nullptr;
   if (kind == C_FWD_STEP || kind == C_EVAL_F || kind == C_ADJ_STEP || kind == C_VJP_OUT) {
-    for (int e = tid; e < tcn * Ng; e += NTB) {
+    for (int e = tid; e < tcn * Ng; e += NT) {
       const int j = e / Ng, y = e - j * Ng;
       b0[fpad(e)] = W[(long long)(c0 + j) * Ng + y];
     }
     __syncthreads();
-    res = lds_fft(b0, b1, P, tw, -1, tcn, Ng, tid, NTB);
+    res = lds_fft(b0, b1, P, tw, -1, tcn, Ng, tid, NT);
   }
   cplx* ibuf = (res == b0) ? b1 : b0;   // free buffer for the inverse transforms
   // inverse y-FFTs to run per column: the new state (1), or the primal state and the
@@ -189,7 +190,7 @@ __device__ void col_item(const ShDev& d, const ShRun& a, int2 item, int kind, in
   const int ninv = inv ? (two ? 2 : 1) : 0;
   const double ng2 = 1.0 / ((double)Ng * Ng);
 
-  for (int e = tid; e < tcn * N; e += NTB) {
+  for (int e = tid; e < tcn * N; e += NT) {
     const int j = e / N, iy = e - j * N, m = c0 + j;
     const int row = pad_row(iy, N, Ng);
     const long long si = (long long)m * N + iy;     // index inside one [Nh][N] array
@@ -289,14 +290,14 @@ __device__ void col_item(const ShDev& d, const ShRun& a, int2 item, int kind, in
     // rows no mode maps to: N/2 .. Ng - N/2 (the Nyquist row and the padding), then the
     // inverse y-FFTs
     const int nz = Ng - N + 1;
-    for (int e = tid; e < ninv * tcn * nz; e += NTB) {
+    for (int e = tid; e < ninv * tcn * nz; e += NT) {
       const int col = e / nz, t = e - col * nz;
       ibuf[fpad(col * Ng + N / 2 + t)] = czero();
     }
     __syncthreads();
     cplx* other = (ibuf == b0) ? b1 : b0;
-    const cplx* out = lds_fft(ibuf, other, P, tw, +1, ninv * tcn, Ng, tid, NTB);
-    for (int e = tid; e < tcn * Ng; e += NTB) {
+    const cplx* out = lds_fft(ibuf, other, P, tw, +1, ninv * tcn, Ng, tid, NT);
+    for (int e = tid; e < tcn * Ng; e += NT) {
       const int j = e / Ng, y = e - j * Ng;
       Z[(long long)(c0 + j) * Ng + y] = out[fpad(e)];
       if (ninv == 2) Z2[(long long)(c0 + j) * Ng + y] = out[fpad((tcn + j) * Ng + y)];
@@ -310,6 +311,7 @@ enum RowKind { R_CUBE, R_VJP };
 
 // LDS of a row item: twiddles (Ng), spectra of the tile's rows (2 arrays x 2 trp x Nh), two
 // FFT buffers of 2 trp Ng (padded)
+template <int NT>
 __device__ void row_item(const ShDev& d, int2 item, int kind, double* smem) {
   const ShInst I = d.inst[item.x];
   const int Nh = I.Nh, Ng = I.Ng, p0 = item.y;
@@ -330,7 +332,7 @@ __device__ void row_item(const ShDev& d, int2 item, int kind, double* smem) {
   stage_tw(d, I.png, Ng, tw);
   // the tile's rows of the column-major x-spectra: rn consecutive y for each column m
   const int na = vjp ? 2 : 1;
-  for (int e = tid; e < na * Nh * rn; e += NTB) {
+  for (int e = tid; e < na * Nh * rn; e += NT) {
     const int arr = e / (Nh * rn), rem = e - arr * Nh * rn;
     const int m = rem / rn, yy = rem - m * rn;
     const cplx* src = arr ? Z2 : Z;
@@ -338,17 +340,17 @@ __device__ void row_item(const ShDev& d, int2 item, int kind, double* smem) {
   }
   __syncthreads();
   // pack row pairs (2q, 2q+1): batch q < pn (values u), pn + q (values q, weight-1 modes)
-  for (int e = tid; e < na * pn * Ng; e += NTB) {
+  for (int e = tid; e < na * pn * Ng; e += NT) {
     const int b = e / Ng, x = e - b * Ng;
     const int arr = b / pn, q = b - arr * pn;
     const cplx* U = sp + (arr * R + 2 * q) * Nh;
     b0[fpad(e)] = pack2(U, U + Nh, x, Ng, Nh, arr ? 0.5 : 1.0);
   }
   __syncthreads();
-  const cplx* g = lds_fft(b0, b1, P, tw, +1, na * pn, Ng, tid, NTB);
+  const cplx* g = lds_fft(b0, b1, P, tw, +1, na * pn, Ng, tid, NT);
   cplx* o = (g == b0) ? b1 : b0;
   const double ng2 = 1.0 / ((double)Ng * Ng);
-  for (int e = tid; e < pn * Ng; e += NTB) {
+  for (int e = tid; e < pn * Ng; e += NT) {
     const cplx u = g[fpad(e)];
     cplx v;
     if (!vjp) {
@@ -361,9 +363,9 @@ __device__ void row_item(const ShDev& d, int2 item, int kind, double* smem) {
   }
   __syncthreads();
   cplx* g2 = (o == b0) ? b1 : b0;
-  const cplx* h = lds_fft(o, g2, P, tw, -1, pn, Ng, tid, NTB);
+  const cplx* h = lds_fft(o, g2, P, tw, -1, pn, Ng, tid, NT);
   // unpack A_m = (Z_m + conj Z_-m)/2 (row 2q), B_m = (Z_m - conj Z_-m)/(2i) (row 2q+1), m < Nh
-  for (int e = tid; e < Nh * rn; e += NTB) {
+  for (int e = tid; e < Nh * rn; e += NT) {
     const int m = e / rn, yy = e - m * rn;
     const int q = yy >> 1;
     const cplx zm = h[fpad(q * Ng + m)], zq = h[fpad(q * Ng + (m == 0 ? 0 : Ng - m))];
@@ -376,13 +378,14 @@ __device__ void row_item(const ShDev& d, int2 item, int kind, double* smem) {
 // ---------------------------------------------------------------------------- cost phase
 // J = 1/2 mean over the N x N grid of u^2 = 1/2 sum w |c~|^2 with c~ the coefficients of
 // the real field (the k_x = 0 column made Hermitian in k_y), dJ/dX = w c~.
+template <int NT>
 __device__ void cost_item(const ShDev& d, const ShRun& a, int inst, double* smem) {
   const ShInst I = d.inst[inst];
   const int N = I.N, Nh = I.Nh, tid = threadIdx.x;
   const cplx* X = d.work + I.xo + (long long)a.nsteps * Nh * N;
   double* red = smem;
   double part = 0.0;
-  for (int e = tid; e < Nh * N; e += NTB) {
+  for (int e = tid; e < Nh * N; e += NT) {
     const int m = e / N, iy = e - m * N;
     cplx c = czero();
     if (iy != N / 2) {
@@ -401,7 +404,7 @@ __device__ void cost_item(const ShDev& d, const ShRun& a, int inst, double* smem
   }
   red[tid] = part;
   __syncthreads();
-  for (int s = NTB / 2; s > 0; s >>= 1) {
+  for (int s = NT / 2; s > 0; s >>= 1) {
     if (tid < s) red[tid] += red[tid + s];
     __syncthreads();
   }
@@ -410,16 +413,17 @@ __device__ void cost_item(const ShDev& d, const ShRun& a, int inst, double* smem
 }
 
 // ---------------------------------------------------------------------------- persistent launch
-__global__ void __launch_bounds__(NTB) sh_persistent(ShDev d, ShRun a) {
+template <int NT>
+__global__ void __launch_bounds__(NT) sh_persistent(ShDev d, ShRun a) {
   extern __shared__ double smem_d[];
   __shared__ int sh_ok;
   unsigned epoch = 0;
   const int b = blockIdx.x;
   auto cols = [&](int kind, int n) {
-    for (int it = d.cptr[b]; it < d.cptr[b + 1]; ++it) col_item(d, a, d.citem[it], kind, n, smem_d);
+    for (int it = d.cptr[b]; it < d.cptr[b + 1]; ++it) col_item<NT>(d, a, d.citem[it], kind, n, smem_d);
   };
   auto rows = [&](int kind) {
-    for (int it = d.rptr[b]; it < d.rptr[b + 1]; ++it) row_item(d, d.ritem[it], kind, smem_d);
+    for (int it = d.rptr[b]; it < d.rptr[b + 1]; ++it) row_item<NT>(d, d.ritem[it], kind, smem_d);
   };
   if (a.mode & RUN_FWD) {
     cols(C_FWD_INIT, 0);
@@ -432,7 +436,7 @@ __global__ void __launch_bounds__(NTB) sh_persistent(ShDev d, ShRun a) {
   }
   if (a.mode & RUN_COST) {
     if (!grid_sync(d, epoch, &sh_ok)) return;
-    for (int it = d.jptr[b]; it < d.jptr[b + 1]; ++it) cost_item(d, a, d.jitem[it], smem_d);
+    for (int it = d.jptr[b]; it < d.jptr[b + 1]; ++it) cost_item<NT>(d, a, d.jitem[it], smem_d);
   }
   if (a.mode & RUN_ADJ) {
     if (!grid_sync(d, epoch, &sh_ok)) return;
@@ -695,7 +699,8 @@ class ShProblem : public ProblemImpl {
     if (h) SPS_HIP(hipMemsetAsync(err_, 0, sizeof(int), stream));
     return h;
   }
-  void tuning(int* col_tile, int* row_tile, int* blocks, double* tuned_ms) const {
+  void tuning(int* col_tile, int* row_tile, int* blocks, int* threads, double* tuned_ms) const {
+    *threads = nt_;
     for (int k = 0; k < 4; ++k) {
       col_tile[k] = tc_by_size_[k];
       row_tile[k] = trp_by_size_[k];
@@ -784,12 +789,17 @@ class ShProblem : public ProblemImpl {
 
   // Work items for tiles (tc, trp) per size class and a block count: longest-first
   // assignment of the items of each phase to the least-loaded block (costs ~ points x log).
-  void schedule(const int* tcs, const int* trps, int blocks) {
+  static const void* kernel_of(int nt) {
+    return nt == 64 ? (const void*)sh_persistent<64> : nt == 128 ? (const void*)sh_persistent<128>
+                                                                  : (const void*)sh_persistent<256>;
+  }
+  void schedule(const int* tcs, const int* trps, int blocks, int nt) {
+    nt_ = nt;
     lds_ = 0;
     for (auto& I : inst_) {
       I.tc = tcs[size_class(I.N)];
       I.trp = trps[size_class(I.N)];
-      lds_ = std::max({lds_, col_lds(I, I.tc), row_lds(I, I.trp), sizeof(double) * NTB});
+      lds_ = std::max({lds_, col_lds(I, I.tc), row_lds(I, I.trp), sizeof(double) * nt});
     }
     struct It {
       double cost;
@@ -843,57 +853,60 @@ class ShProblem : public ProblemImpl {
   // class and the number of persistent blocks; each candidate that fits LDS and co-residency
   // is timed on a few forward steps of this batch and the fastest is kept.
   void tune() {
-    const int cand_c[3] = {512, 1024, 2048};   // points of one FFT batch (tile x Ng)
-    const int cand_r[3] = {512, 1024, 2048};
+    const int cand[4] = {256, 512, 1024, 2048};   // points of one FFT batch (tile x Ng)
+    const int cand_nt[3] = {64, 128, 256};
     const int Ngs[4] = {128, 192, 256, 384};
     double best = 1e30;
-    int best_tc[4] = {1, 1, 1, 1}, best_trp[4] = {1, 1, 1, 1}, best_blocks = cus_;
+    int best_tc[4] = {1, 1, 1, 1}, best_trp[4] = {1, 1, 1, 1}, best_blocks = cus_, best_nt = 256;
     const int nsteps = std::min(4, max_steps_);
     hipEvent_t e0, e1;
     SPS_HIP(hipEventCreate(&e0));
     SPS_HIP(hipEventCreate(&e1));
-    for (int bc : cand_c)
-      for (int br : cand_r)
-        for (int bmul = 1; bmul <= 2; ++bmul) {
-          int tcs[4], trps[4];
-          for (int k = 0; k < 4; ++k) {
-            tcs[k] = std::max(1, std::min(8, bc / Ngs[k]));
-            trps[k] = std::max(1, std::min(8, br / Ngs[k]));
-            while (tcs[k] & (tcs[k] - 1)) --tcs[k];
-            while (trps[k] & (trps[k] - 1)) --trps[k];
+    for (int nt : cand_nt)
+      for (int bc : cand)
+        for (int br : cand)
+          for (int bmul = 1; bmul <= 4; ++bmul) {
+            int tcs[4], trps[4];
+            for (int k = 0; k < 4; ++k) {
+              tcs[k] = std::max(1, std::min(8, bc / Ngs[k]));
+              trps[k] = std::max(1, std::min(8, br / Ngs[k]));
+              while (tcs[k] & (tcs[k] - 1)) --tcs[k];
+              while (trps[k] & (trps[k] - 1)) --trps[k];
+            }
+            const int blocks = bmul * cus_;
+            schedule(tcs, trps, blocks, nt);
+            if (lds_ > 160 * 1024 || !fits(blocks)) continue;
+            ShRun a{RUN_FWD, nsteps, tmp_, nullptr, nullptr, nullptr, nullptr, nullptr};
+            SPS_HIP(hipMemsetAsync(tmp_, 0, sizeof(cplx) * state_cplx_, stream));
+            run(a);   // warm
+            SPS_HIP(hipEventRecord(e0, stream));
+            run(a);
+            SPS_HIP(hipEventRecord(e1, stream));
+            SPS_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            SPS_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (check_error()) throw Error(SPS_E_HIP, "persistent launch aborted while tuning");
+            if (ms < best) {
+              best = ms;
+              std::copy(tcs, tcs + 4, best_tc);
+              std::copy(trps, trps + 4, best_trp);
+              best_blocks = blocks;
+              best_nt = nt;
+            }
           }
-          const int blocks = bmul * cus_;
-          schedule(tcs, trps, blocks);
-          if (lds_ > 160 * 1024 || !fits(blocks)) continue;
-          ShRun a{RUN_FWD, nsteps, tmp_, nullptr, nullptr, nullptr, nullptr, nullptr};
-          SPS_HIP(hipMemsetAsync(tmp_, 0, sizeof(cplx) * state_cplx_, stream));
-          run(a);   // warm
-          SPS_HIP(hipEventRecord(e0, stream));
-          run(a);
-          SPS_HIP(hipEventRecord(e1, stream));
-          SPS_HIP(hipEventSynchronize(e1));
-          float ms = 0.f;
-          SPS_HIP(hipEventElapsedTime(&ms, e0, e1));
-          if (check_error()) throw Error(SPS_E_HIP, "persistent launch aborted while tuning");
-          if (ms < best) {
-            best = ms;
-            std::copy(tcs, tcs + 4, best_tc);
-            std::copy(trps, trps + 4, best_trp);
-            best_blocks = blocks;
-          }
-        }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     SPS_REQUIRE(best < 1e29, "no tile configuration fits this batch");
-    schedule(best_tc, best_trp, best_blocks);
+    schedule(best_tc, best_trp, best_blocks, best_nt);
     std::copy(best_tc, best_tc + 4, tc_by_size_);
     std::copy(best_trp, best_trp + 4, trp_by_size_);
     tuned_ms_ = best / nsteps;
   }
   bool fits(int blocks) {
     int per = 0;
-    SPS_HIP(hipFuncSetAttribute((const void*)sh_persistent, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_));
-    SPS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, sh_persistent, NTB, lds_));
+    const void* k = kernel_of(nt_);
+    SPS_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_));
+    SPS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, nt_, lds_));
     return per * cus_ >= blocks;
   }
   int check_error() {
@@ -909,7 +922,8 @@ class ShProblem : public ProblemImpl {
                              hipMemcpyDeviceToDevice, stream));
   }
   void run(const ShRun& a) {
-    SPS_HIP(hipFuncSetAttribute((const void*)sh_persistent, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_));
+    const void* k = kernel_of(nt_);
+    SPS_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_));
     SPS_HIP(hipMemsetAsync(bar_, 0, sizeof(unsigned), stream));
     dv_.bar = bar_;
     dv_.err = err_;
@@ -919,7 +933,7 @@ class ShProblem : public ProblemImpl {
     hipEvent_t e0, e1;
     const bool timed = timer_.take(&e0, &e1);
     if (timed) SPS_HIP(hipEventRecord(e0, stream));
-    SPS_HIP(hipLaunchCooperativeKernel((const void*)sh_persistent, dim3(blocks_), dim3(NTB), args, lds_, stream));
+    SPS_HIP(hipLaunchCooperativeKernel(k, dim3(blocks_), dim3(nt_), args, lds_, stream));
     if (timed) SPS_HIP(hipEventRecord(e1, stream));
   }
 
@@ -942,7 +956,7 @@ class ShProblem : public ProblemImpl {
     }
   };
 
-  int batch_ = 0, max_steps_ = 0, cus_ = 0, blocks_ = 0;
+  int batch_ = 0, max_steps_ = 0, cus_ = 0, blocks_ = 0, nt_ = 256;
   double lx_ = 0, dt_ = 0, tuned_ms_ = 0;
   std::vector<int> ns_;
   std::vector<double> rs_;
@@ -969,10 +983,10 @@ ProblemImpl* make_sh_batch(int batch, const int* n, const double* r, double lx, 
   return new ShProblem(batch, n, r, lx, dt, max_steps, s);
 }
 
-void sh_tuning(ProblemImpl* p, int* col_tile, int* row_tile, int* blocks, double* tuned_ms) {
+void sh_tuning(ProblemImpl* p, int* col_tile, int* row_tile, int* blocks, int* threads, double* tuned_ms) {
   auto* sh = dynamic_cast<ShProblem*>(p);
   if (!sh) throw Error(SPS_E_ARG, "not a batched Swift-Hohenberg problem");
-  sh->tuning(col_tile, row_tile, blocks, tuned_ms);
+  sh->tuning(col_tile, row_tile, blocks, threads, tuned_ms);
 }
 
 }  // namespace sps

@@ -138,7 +138,7 @@ ProblemImpl* make_rbc(const sps_desc& d, hipStream_t s);
 ProblemImpl* make_ks(const sps_desc& d, hipStream_t s);
 ProblemImpl* make_sh_batch(int batch, const int* n, const double* r, double lx, double dt, int max_steps,
                            hipStream_t s);
-void sh_tuning(ProblemImpl* p, int* col_tile, int* row_tile, int* blocks, double* tuned_ms);
+void sh_tuning(ProblemImpl* p, int* col_tile, int* row_tile, int* blocks, int* threads, double* tuned_ms);
 
 // Host helpers shared by problem builders.
 std::vector<double2> twiddles(int n);            // exp(-2 pi i t / n), t < n

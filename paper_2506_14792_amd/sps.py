@@ -59,7 +59,8 @@ def lib():
         "sps_build_sh_batch": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
                                               ctypes.c_double, ctypes.c_double, ctypes.c_int, _P, ctypes.POINTER(_P)]),
         "sps_sh_tuning": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
-                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]),
+                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                         ctypes.POINTER(ctypes.c_double)]),
         "sps_sync": (ctypes.c_int, [_P]),
         "sps_last_error": (ctypes.c_char_p, []),
         "sps_destroy": (None, [_P]),
@@ -214,9 +215,11 @@ class ShBatch(Problem):
         ct = (ctypes.c_int * 4)()
         rt = (ctypes.c_int * 4)()
         b = ctypes.c_int()
+        t = ctypes.c_int()
         ms = ctypes.c_double()
-        _check(lib().sps_sh_tuning(self._h, ct, rt, ctypes.byref(b), ctypes.byref(ms)))
-        return {"col_tile": list(ct), "row_pairs": list(rt), "blocks": b.value, "step_ms": ms.value}
+        _check(lib().sps_sh_tuning(self._h, ct, rt, ctypes.byref(b), ctypes.byref(t), ctypes.byref(ms)))
+        return {"col_tile": list(ct), "row_pairs": list(rt), "blocks": b.value, "threads": t.value,
+                "step_ms": ms.value}
 
 
 def rbc_host_bands(nx, nz, lx, Ra, Pr, dt=1e-3):
