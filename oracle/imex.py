@@ -198,3 +198,36 @@ def sbdf_adjoint(P, Xbar_N, states, dt, order=2):
             Xbar[n - i] += P.F_vjp(states[n - i], c[i] * Y)
             Xbar[n - i] -= a[i] * apply_blocks_H(P.M, Y) + b[i] * apply_blocks_H(P.L, Y)
     return Xbar[0]
+
+
+def sbdf_adjoint_general(P, states, dt, Xbar_N=None, inject=None, param_vjp=False, order=2):
+    """The multistep reverse sweep of sbdf_adjoint with two additions: cotangents inject[k]
+    that a cost depending on intermediate states X_k adds to Xbar_k (entering before the solve
+    of step k), and, with param_vjp, the gradient with respect to parameters of F,
+    sum over steps n and i >= 1 of (dF/dp (X_{n-i}))^H c_i^n Y_n (equ:efficient_gradient),
+    from P.F_vjp(X, Ybar, with_params=True).  Returns (Xbar_0, pbar)."""
+    N = len(states) - 1
+    Xbar = [np.zeros_like(states[0]) for _ in range(N + 1)]
+    if Xbar_N is not None:
+        Xbar[N] += Xbar_N
+    pbar = None
+    lus = {}
+    for n in range(N, 0, -1):
+        if inject is not None and inject[n] is not None:
+            Xbar[n] += inject[n]
+        a, b, c = sbdf_coefficients(n, dt, order)
+        key = (a[0], b[0])
+        if key not in lus:
+            lus[key] = BlockLU(P.M, P.L, a[0], b[0])
+        Y = lus[key].solve_adjoint(Xbar[n])
+        for i in range(1, len(a)):
+            if param_vjp:
+                v, pv = P.F_vjp(states[n - i], c[i] * Y, with_params=True)
+                pbar = pv if pbar is None else pbar + pv
+            else:
+                v = P.F_vjp(states[n - i], c[i] * Y)
+            Xbar[n - i] += v
+            Xbar[n - i] -= a[i] * apply_blocks_H(P.M, Y) + b[i] * apply_blocks_H(P.L, Y)
+    if inject is not None and inject[0] is not None:
+        Xbar[0] += inject[0]
+    return Xbar[0], pbar
