@@ -162,6 +162,22 @@ int sps_timer_read(sps_problem *P, long long *launches, double *total_ms);
  * kernel timer is not fed by replays.  SPS_E_UNSUPPORTED for problems without graph mode. */
 int sps_set_graph(sps_problem *P, int on);
 
+/* Closure network on its own (the explicit-term closure of the Kolmogorov problem; not part
+ * of the paper's method): three periodic 3x3 convolutions 1 -> 32 -> 32 -> 1 with GELU, bf16
+ * weights and activations, FP32 accumulation (MFMA for the 32 -> 32 layer).  Images are FP64
+ * device arrays [batch][H][W] (W a multiple of 32); parameters one FP64 device vector of
+ * sps_cnn_nparam() values in the order w1 (32x1x3x3), b1, w2 (32x32x3x3), b2, w3 (1x32x3x3), b3,
+ * w[o][c][dy+1][dx+1] multiplying the input at (y+dy, x+dx), periodic.  sps_cnn_vjp writes the
+ * input cotangent and ADDS the parameter cotangent to theta_bar (nullable).  Calls run on the
+ * handle's stream. */
+typedef struct sps_cnn sps_cnn;
+int sps_cnn_build(int batch, int H, int W, void *hip_stream, sps_cnn **out);
+int sps_cnn_nparam(void);
+int sps_cnn_set_params(sps_cnn *C, const double *theta);
+int sps_cnn_forward(sps_cnn *C, const double *x, double *y);
+int sps_cnn_vjp(sps_cnn *C, const double *x, const double *ybar, double *xbar, double *theta_bar);
+void sps_cnn_destroy(sps_cnn *C);
+
 /* Wait for the problem's stream; report a deferred device error. */
 int sps_sync(sps_problem *P);
 

@@ -4,11 +4,16 @@
 #include <cmath>
 #include <string>
 
+#include "cnn.h"
 #include "fft_plan.h"
 #include "sps_internal.h"
 
 struct sps_problem {
   sps::ProblemImpl* impl;
+};
+struct sps_cnn {
+  sps::Cnn* net;
+  hipStream_t s;
 };
 
 namespace {
@@ -31,6 +36,19 @@ int guard(sps_problem* P, F&& f) {
     return fail(SPS_E_HIP, e.what());
   }
 }
+template <typename F>
+int cnn_guard(sps_cnn* C, F&& f) {
+  if (!C || !C->net) return fail(SPS_E_ARG, "null network handle");
+  try {
+    f(*C->net);
+    return SPS_OK;
+  } catch (const sps::Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::exception& e) {
+    return fail(SPS_E_HIP, e.what());
+  }
+}
+
 }  // namespace
 
 namespace sps {
@@ -173,6 +191,45 @@ int sps_sh_tuning(const sps_problem* P, int* col_tile, int* row_tile, int* block
   if (!col_tile || !row_tile || !blocks || !threads || !step_ms) return fail(SPS_E_ARG, "null argument");
   return guard(const_cast<sps_problem*>(P),
                [&](sps::ProblemImpl& p) { sps::sh_tuning(&p, col_tile, row_tile, blocks, threads, step_ms); });
+}
+
+
+int sps_cnn_build(int batch, int H, int W, void* hip_stream, sps_cnn** out) {
+  if (!out) return fail(SPS_E_ARG, "null argument");
+  *out = nullptr;
+  try {
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    *out = new sps_cnn{new sps::Cnn(batch, H, W, s), s};
+    return SPS_OK;
+  } catch (const sps::Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::exception& e) {
+    return fail(SPS_E_HIP, e.what());
+  }
+}
+
+int sps_cnn_nparam(void) { return sps::Cnn::nparam(); }
+
+int sps_cnn_set_params(sps_cnn* C, const double* theta) {
+  if (!theta) return fail(SPS_E_ARG, "null argument");
+  return cnn_guard(C, [&](sps::Cnn& n) { n.set_params(theta); });
+}
+
+int sps_cnn_forward(sps_cnn* C, const double* x, double* y) {
+  if (!x || !y) return fail(SPS_E_ARG, "null argument");
+  return cnn_guard(C, [&](sps::Cnn& n) { n.forward(x, y, 1.0, false); });
+}
+
+int sps_cnn_vjp(sps_cnn* C, const double* x, const double* ybar, double* xbar, double* theta_bar) {
+  if (!x || !ybar || !xbar) return fail(SPS_E_ARG, "null argument");
+  return cnn_guard(C, [&](sps::Cnn& n) { n.vjp(x, ybar, xbar, 1.0, false, theta_bar); });
+}
+
+void sps_cnn_destroy(sps_cnn* C) {
+  if (!C) return;
+  (void)hipStreamSynchronize(C->s);
+  delete C->net;
+  delete C;
 }
 
 int sps_set_graph(sps_problem* P, int on) {

@@ -1,0 +1,411 @@
+// Closure network for a coarse periodic 2D field: three periodic 3x3 convolutions
+// 1 -> 32 -> 32 -> 1 channels with GELU between them (exact erf form).  Weights and
+// activations are stored in bfloat16 and products accumulated in FP32; the 32 -> 32 layer
+// runs on MFMA (bf16 x bf16 -> f32 forward; f32 x f32 -> f32 for its input cotangent and
+// weight gradient).  The network is not part of the paper's method: its output is added to
+// the explicit term F of the coarse problem, and its parameters receive gradients through
+// the discrete adjoint like any parameter of F (equ:efficient_gradient).
+//
+// Layouts: images [B][H][W] (FP64 in and out); activations NHWC [B][H*W][32]; parameters as
+// one FP64 vector in the order w1 (32x1x3x3), b1 (32), w2 (32x32x3x3), b2 (32), w3 (1x32x3x3),
+// b3 (1), w[o][c][dy+1][dx+1] multiplying the input at (y + dy, x + dx) (periodic).
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include <vector>
+
+#include "cnn.h"
+#include "sps_internal.h"
+
+namespace sps {
+namespace {
+
+constexpr int CH = 32;                  // hidden channels
+constexpr int NP1 = CH * 9, NP2 = CH * CH * 9, NP3 = CH * 9;
+constexpr int OFF_W1 = 0, OFF_B1 = NP1, OFF_W2 = OFF_B1 + CH, OFF_B2 = OFF_W2 + NP2, OFF_W3 = OFF_B2 + CH,
+              OFF_B3 = OFF_W3 + NP3, NPARAM = OFF_B3 + 1;
+constexpr int NTC = 256;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+struct CnnDev {
+  int B, H, W;
+  const float* w1;     // [32][9]   bf16-rounded
+  const float* b1;     // [32]
+  const __bf16* w2r;   // [9][32 co][32 ci] bf16 (forward MFMA operand)
+  const float* w2f;    // [9][32 co][32 ci] the same values in FP32
+  const float* b2;     // [32]
+  const float* w3;     // [32][9]   bf16-rounded
+  const float* b3;     // [1]
+  __bf16 *a0, *a1, *a2;   // a0: [B][HW]; a1, a2: [B][HW][32]
+  float *z1, *z2;         // pre-activations [B][HW][32]
+  float *g1, *g2;         // cotangents of z1, z2
+  float* part;            // weight-gradient partial sums
+};
+
+__device__ __forceinline__ int nb(int p, int t, int H, int W) {
+  // pixel index of the neighbour (y + dy, x + dx) of pixel p for tap t = (dy+1)*3 + (dx+1)
+  const int y = p / W, x = p - y * W;
+  const int dy = t / 3 - 1, dx = t % 3 - 1;
+  int yy = y + dy, xx = x + dx;
+  yy += (yy < 0) ? H : (yy >= H ? -H : 0);
+  xx += (xx < 0) ? W : (xx >= W ? -W : 0);
+  return yy * W + xx;
+}
+__device__ __forceinline__ int nb_t(int p, int t, int H, int W) { return nb(p, 8 - t, H, W); }   // (y - dy, x - dx)
+__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_df(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+// parameters (FP64) -> stored tables
+__global__ void cnn_prepare(const double* th, float* w1, float* b1, __bf16* w2r, float* w2f, float* b2, float* w3,
+                            float* b3) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  auto r16 = [](double v) { return (float)(__bf16)(float)v; };
+  if (i < NP1) w1[i] = r16(th[OFF_W1 + i]);
+  if (i < CH) {
+    b1[i] = (float)th[OFF_B1 + i];
+    b2[i] = (float)th[OFF_B2 + i];
+  }
+  if (i < NP2) {   // i = (co * 32 + ci) * 9 + t
+    const int t = i % 9, ci = (i / 9) % CH, co = i / (9 * CH);
+    const float v = r16(th[OFF_W2 + i]);
+    w2r[(t * CH + co) * CH + ci] = (__bf16)v;
+    w2f[(t * CH + co) * CH + ci] = v;
+  }
+  if (i < NP3) w3[i] = r16(th[OFF_W3 + i]);
+  if (i == 0) b3[0] = (float)th[OFF_B3];
+}
+
+// ---------------------------------------------------------------------------- forward
+// layer 1 (1 -> 32) and GELU: one thread per pixel
+__global__ void __launch_bounds__(NTC) cnn_l1(CnnDev d, const double* x) {
+  const int HW = d.H * d.W;
+  const int g = blockIdx.x * NTC + threadIdx.x;
+  if (g >= d.B * HW) return;
+  const int b = g / HW, p = g - b * HW;
+  float v[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) v[t] = (float)(__bf16)(float)x[(long long)b * HW + nb(p, t, d.H, d.W)];
+  d.a0[g] = (__bf16)v[4];
+  for (int c = 0; c < CH; ++c) {
+    float z = d.b1[c];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) z = fmaf(d.w1[c * 9 + t], v[t], z);
+    d.z1[(long long)g * CH + c] = z;
+    d.a1[(long long)g * CH + c] = (__bf16)gelu_f(z);
+  }
+}
+
+// layer 2 (32 -> 32) and GELU on MFMA: each wave computes 32 pixels (a row segment) x 32
+// output channels; K = 9 taps x 32 input channels in 18 steps of 16.  LDS: w2r.
+__global__ void __launch_bounds__(NTC) cnn_l2(CnnDev d) {
+  __shared__ __bf16 w[9 * CH * CH];
+  for (int e = threadIdx.x; e < 9 * CH * CH; e += NTC) w[e] = d.w2r[e];
+  __syncthreads();
+  const int HW = d.H * d.W, lane = threadIdx.x & 63;
+  const int tile = blockIdx.x * (NTC / 64) + (threadIdx.x >> 6);   // 32-pixel tiles
+  const int tiles_per_img = HW / 32;
+  if (tile >= d.B * tiles_per_img) return;
+  const int b = tile / tiles_per_img, p0 = (tile - b * tiles_per_img) * 32;
+  const int row = lane & 31, half = lane >> 5;
+  const int p = p0 + row;
+  const __bf16* A = d.a1 + (long long)b * HW * CH;
+  f32x16 acc = {};
+#pragma unroll
+  for (int s = 0; s < 18; ++s) {
+    const int t = s >> 1, ci0 = (s & 1) * 16 + half * 8;
+    const bf16x8 av = *reinterpret_cast<const bf16x8*>(A + (long long)nb(p, t, d.H, d.W) * CH + ci0);
+    const bf16x8 bv = *reinterpret_cast<const bf16x8*>(w + (t * CH + row) * CH + ci0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+  }
+  // acc[r]: pixel p0 + 8 (r / 4) + 4 half + r % 4, channel `row`
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int pi = p0 + 8 * (r >> 2) + 4 * half + (r & 3);
+    const float z = acc[r] + d.b2[row];
+    const long long o = ((long long)b * HW + pi) * CH + row;
+    d.z2[o] = z;
+    d.a2[o] = (__bf16)gelu_f(z);
+  }
+}
+
+// layer 3 (32 -> 1): one thread per pixel; y (FP64) = scale * output (+= when accumulate)
+__global__ void __launch_bounds__(NTC) cnn_l3(CnnDev d, double* y, double scale, int accumulate) {
+  const int HW = d.H * d.W;
+  const int g = blockIdx.x * NTC + threadIdx.x;
+  if (g >= d.B * HW) return;
+  const int b = g / HW, p = g - b * HW;
+  float s = d.b3[0];
+  for (int t = 0; t < 9; ++t) {
+    const __bf16* a = d.a2 + ((long long)b * HW + nb(p, t, d.H, d.W)) * CH;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) s = fmaf(d.w3[c * 9 + t], (float)a[c], s);
+  }
+  const double v = scale * (double)s;
+  y[g] = accumulate ? y[g] + v : v;
+}
+
+// ---------------------------------------------------------------------------- backward
+// layer 3: g2 = (w3 conv^T ybar) * gelu'(z2); one thread per pixel
+__global__ void __launch_bounds__(NTC) cnn_l3_back(CnnDev d, const double* yb) {
+  const int HW = d.H * d.W;
+  const int g = blockIdx.x * NTC + threadIdx.x;
+  if (g >= d.B * HW) return;
+  const int b = g / HW, p = g - b * HW;
+  float ys[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) ys[t] = (float)yb[(long long)b * HW + nb_t(p, t, d.H, d.W)];
+  for (int c = 0; c < CH; ++c) {
+    float s = 0.f;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) s = fmaf(d.w3[c * 9 + t], ys[t], s);
+    const long long o = (long long)g * CH + c;
+    d.g2[o] = s * gelu_df(d.z2[o]);
+  }
+}
+
+// layer 2 input cotangent on MFMA f32: g1[p][ci] = gelu'(z1) sum_{t, co} w2[co][ci][t] g2[p - d_t][co];
+// each wave 32 pixels x 32 input channels, K = 9 x 32 in 144 steps of 2.
+__global__ void __launch_bounds__(NTC) cnn_l2_back_input(CnnDev d) {
+  __shared__ float w[9 * CH * CH];
+  for (int e = threadIdx.x; e < 9 * CH * CH; e += NTC) w[e] = d.w2f[e];
+  __syncthreads();
+  const int HW = d.H * d.W, lane = threadIdx.x & 63;
+  const int tile = blockIdx.x * (NTC / 64) + (threadIdx.x >> 6);
+  const int tiles_per_img = HW / 32;
+  if (tile >= d.B * tiles_per_img) return;
+  const int b = tile / tiles_per_img, p0 = (tile - b * tiles_per_img) * 32;
+  const int row = lane & 31, half = lane >> 5;
+  const float* G = d.g2 + (long long)b * HW * CH;
+  f32x16 acc = {};
+  for (int t = 0; t < 9; ++t) {
+    const float* Gt = G + (long long)nb_t(p0 + row, t, d.H, d.W) * CH;
+#pragma unroll 4
+    for (int c2 = 0; c2 < CH; c2 += 2) {
+      const int co = c2 + half;
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(Gt[co], w[(t * CH + co) * CH + row], acc, 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int pi = p0 + 8 * (r >> 2) + 4 * half + (r & 3);
+    const long long o = ((long long)b * HW + pi) * CH + row;
+    d.g1[o] = acc[r] * gelu_df(d.z1[o]);
+  }
+}
+
+// layer 2 weight gradient on MFMA f32: dw2[co][ci][t] = sum_q g2[q][co] a1[q + d_t][ci].  One wave
+// per (tap, chunk of pixels); partials [chunk][t][co][ci].
+constexpr int W2_CHUNK = 512;
+__global__ void __launch_bounds__(64) cnn_l2_back_weight(CnnDev d, float* part) {
+  const int HW = d.H * d.W, lane = threadIdx.x;
+  const int t = blockIdx.x % 9, chunk = blockIdx.x / 9;
+  const int q0 = chunk * W2_CHUNK;
+  const int total = d.B * HW;
+  const int row = lane & 31, half = lane >> 5;
+  f32x16 acc = {};
+  for (int k = 0; k < W2_CHUNK; k += 2) {
+    const int q = q0 + k + half;
+    float av = 0.f, bv = 0.f;
+    if (q < total) {
+      const int b = q / HW, p = q - b * HW;
+      av = d.g2[(long long)q * CH + row];
+      bv = (float)d.a1[((long long)b * HW + nb(p, t, d.H, d.W)) * CH + row];
+    }
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+  }
+  // acc[r]: co = 8 (r / 4) + 4 half + r % 4, ci = row
+  float* o = part + ((long long)chunk * 9 + t) * CH * CH;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) o[(8 * (r >> 2) + 4 * half + (r & 3)) * CH + row] = acc[r];
+}
+
+// layer 1 and the small weight gradients: one thread per pixel computes the input cotangent
+// and its contributions to dw1, db1, dw3, db3, db2; each is summed over the wave (shuffles)
+// and the block's waves in a fixed order into part1[block][SMALL].
+constexpr int SMALL = NP1 + CH + NP3 + 1 + CH;
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__global__ void __launch_bounds__(NTC) cnn_small_back(CnnDev d, const double* yb, double* xb, double xscale,
+                                                      int accumulate, float* part1) {
+  __shared__ float wsum[NTC / 64][SMALL];
+  const int HW = d.H * d.W;
+  const int g = blockIdx.x * NTC + threadIdx.x;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const bool on = g < d.B * HW;
+  const int b = on ? g / HW : 0, p = on ? g - b * HW : 0;
+  if (on) {   // input cotangent: sum_{t, c} w1[c][t] g1[p - d_t][c]
+    float s = 0.f;
+    for (int t = 0; t < 9; ++t) {
+      const float* G = d.g1 + ((long long)b * HW + nb_t(p, t, d.H, d.W)) * CH;
+#pragma unroll
+      for (int c = 0; c < CH; ++c) s = fmaf(d.w1[c * 9 + t], G[c], s);
+    }
+    const double v = xscale * (double)s;
+    xb[g] = accumulate ? xb[g] + v : v;
+  }
+  const float ybp = on ? (float)yb[g] : 0.f;
+  float a0n[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) a0n[t] = on ? (float)d.a0[(long long)b * HW + nb(p, t, d.H, d.W)] : 0.f;
+  for (int c = 0; c < CH; ++c) {
+    const float g1c = on ? d.g1[(long long)g * CH + c] : 0.f;
+    const float g2c = on ? d.g2[(long long)g * CH + c] : 0.f;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const float v1 = wave_sum(g1c * a0n[t]);
+      const float a2v = on ? (float)d.a2[((long long)b * HW + nb(p, t, d.H, d.W)) * CH + c] : 0.f;
+      const float v3 = wave_sum(ybp * a2v);
+      if (lane == 0) {
+        wsum[wv][c * 9 + t] = v1;
+        wsum[wv][NP1 + CH + c * 9 + t] = v3;
+      }
+    }
+    const float vb1 = wave_sum(g1c), vb2 = wave_sum(g2c);
+    if (lane == 0) {
+      wsum[wv][NP1 + c] = vb1;
+      wsum[wv][NP1 + CH + NP3 + 1 + c] = vb2;
+    }
+  }
+  const float vb3 = wave_sum(ybp);
+  if (lane == 0) wsum[wv][NP1 + CH + NP3] = vb3;
+  __syncthreads();
+  for (int e = threadIdx.x; e < SMALL; e += NTC) {
+    float s = 0.f;
+#pragma unroll
+    for (int w = 0; w < NTC / 64; ++w) s += wsum[w][e];
+    part1[(long long)blockIdx.x * SMALL + e] = s;
+  }
+}
+
+// sum the partials in a fixed order and add to the FP64 parameter gradient
+__global__ void cnn_reduce(const float* part1, int nblk1, const float* part2, int nchunk, double* th_bar) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < NP1 + CH) {   // w1, b1
+    double s = 0.0;
+    for (int k = 0; k < nblk1; ++k) s += part1[(long long)k * SMALL + i];
+    th_bar[OFF_W1 + i] += s;
+  } else if (i < NP1 + CH + NP2) {   // w2: i - (NP1 + CH) = (co * 32 + ci) * 9 + t
+    const int j = i - NP1 - CH, t = j % 9, ci = (j / 9) % CH, co = j / (9 * CH);
+    double s = 0.0;
+    for (int k = 0; k < nchunk; ++k) s += part2[(((long long)k * 9 + t) * CH + co) * CH + ci];
+    th_bar[OFF_W2 + j] += s;
+  } else if (i < NP1 + CH + NP2 + CH) {   // b2
+    const int c = i - (NP1 + CH + NP2);
+    double s = 0.0;
+    for (int k = 0; k < nblk1; ++k) s += part1[(long long)k * SMALL + NP1 + CH + NP3 + 1 + c];
+    th_bar[OFF_B2 + c] += s;
+  } else if (i < NPARAM) {   // w3, b3
+    const int j = i - (NP1 + CH + NP2 + CH);
+    double s = 0.0;
+    for (int k = 0; k < nblk1; ++k) s += part1[(long long)k * SMALL + NP1 + CH + j];
+    th_bar[OFF_W3 + j] += s;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------- host
+struct Cnn::Impl {
+  int B, H, W;
+  hipStream_t s;
+  DevArena arena;
+  CnnDev d{};
+  float *w1, *b1, *w2f, *b2, *w3, *b3, *part1, *part2;
+  __bf16* w2r;
+  int nblk1, nchunk;
+};
+
+Cnn::Cnn(int batch, int H, int W, hipStream_t s) : p_(new Impl) {
+  SPS_REQUIRE(batch >= 1 && H >= 3 && W >= 32 && W % 32 == 0, "closure images need W a multiple of 32");
+  Impl& m = *p_;
+  m.B = batch;
+  m.H = H;
+  m.W = W;
+  m.s = s;
+  const long long HW = (long long)H * W, n = batch * HW;
+  m.w1 = m.arena.alloc<float>(NP1);
+  m.b1 = m.arena.alloc<float>(CH);
+  m.w2r = m.arena.alloc<__bf16>(NP2);
+  m.w2f = m.arena.alloc<float>(NP2);
+  m.b2 = m.arena.alloc<float>(CH);
+  m.w3 = m.arena.alloc<float>(NP3);
+  m.b3 = m.arena.alloc<float>(1);
+  m.nblk1 = (int)((n + NTC - 1) / NTC);
+  m.nchunk = (int)((n + W2_CHUNK - 1) / W2_CHUNK);
+  m.part1 = m.arena.alloc<float>((size_t)m.nblk1 * SMALL);
+  m.part2 = m.arena.alloc<float>((size_t)m.nchunk * 9 * CH * CH);
+  CnnDev& d = m.d;
+  d.B = batch;
+  d.H = H;
+  d.W = W;
+  d.w1 = m.w1;
+  d.b1 = m.b1;
+  d.w2r = m.w2r;
+  d.w2f = m.w2f;
+  d.b2 = m.b2;
+  d.w3 = m.w3;
+  d.b3 = m.b3;
+  d.a0 = m.arena.alloc<__bf16>(n);
+  d.a1 = m.arena.alloc<__bf16>(n * CH);
+  d.a2 = m.arena.alloc<__bf16>(n * CH);
+  d.z1 = m.arena.alloc<float>(n * CH);
+  d.z2 = m.arena.alloc<float>(n * CH);
+  d.g1 = m.arena.alloc<float>(n * CH);
+  d.g2 = m.arena.alloc<float>(n * CH);
+}
+Cnn::~Cnn() = default;
+
+int Cnn::nparam() { return NPARAM; }
+
+void Cnn::set_params(const double* theta_dev) {
+  Impl& m = *p_;
+  hipLaunchKernelGGL(cnn_prepare, dim3((NP2 + 255) / 256), dim3(256), 0, m.s, theta_dev, m.w1, m.b1, m.w2r, m.w2f,
+                     m.b2, m.w3, m.b3);
+  SPS_CHECK_LAUNCH();
+}
+
+void Cnn::forward(const double* x, double* y, double scale, bool accumulate) {
+  Impl& m = *p_;
+  const long long n = (long long)m.B * m.H * m.W;
+  const int g1 = (int)((n + NTC - 1) / NTC), g2 = (int)((n / 32 + 3) / 4);
+  hipLaunchKernelGGL(cnn_l1, dim3(g1), dim3(NTC), 0, m.s, m.d, x);
+  SPS_CHECK_LAUNCH();
+  hipLaunchKernelGGL(cnn_l2, dim3(g2), dim3(NTC), 0, m.s, m.d);
+  SPS_CHECK_LAUNCH();
+  hipLaunchKernelGGL(cnn_l3, dim3(g1), dim3(NTC), 0, m.s, m.d, y, scale, (int)accumulate);
+  SPS_CHECK_LAUNCH();
+}
+
+void Cnn::vjp(const double* x, const double* yb, double* xb, double xscale, bool accumulate, double* th_bar) {
+  Impl& m = *p_;
+  const long long n = (long long)m.B * m.H * m.W;
+  const int g1 = (int)((n + NTC - 1) / NTC), g2 = (int)((n / 32 + 3) / 4);
+  // the forward activations of this input (recomputed: the adjoint sweep revisits states)
+  hipLaunchKernelGGL(cnn_l1, dim3(g1), dim3(NTC), 0, m.s, m.d, x);
+  SPS_CHECK_LAUNCH();
+  hipLaunchKernelGGL(cnn_l2, dim3(g2), dim3(NTC), 0, m.s, m.d);
+  SPS_CHECK_LAUNCH();
+  hipLaunchKernelGGL(cnn_l3_back, dim3(g1), dim3(NTC), 0, m.s, m.d, yb);
+  SPS_CHECK_LAUNCH();
+  hipLaunchKernelGGL(cnn_l2_back_input, dim3(g2), dim3(NTC), 0, m.s, m.d);
+  SPS_CHECK_LAUNCH();
+  hipLaunchKernelGGL(cnn_l2_back_weight, dim3(9 * m.nchunk), dim3(64), 0, m.s, m.d, m.part2);
+  SPS_CHECK_LAUNCH();
+  hipLaunchKernelGGL(cnn_small_back, dim3(m.nblk1), dim3(NTC), 0, m.s, m.d, yb, xb, xscale, (int)accumulate,
+                     m.part1);
+  SPS_CHECK_LAUNCH();
+  if (th_bar) {
+    hipLaunchKernelGGL(cnn_reduce, dim3((NPARAM + 255) / 256), dim3(256), 0, m.s, m.part1, m.nblk1, m.part2,
+                       m.nchunk, th_bar);
+    SPS_CHECK_LAUNCH();
+  }
+}
+
+}  // namespace sps

@@ -61,6 +61,12 @@ def lib():
         "sps_sh_tuning": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                          ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                          ctypes.POINTER(ctypes.c_double)]),
+        "sps_cnn_build": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, ctypes.POINTER(_P)]),
+        "sps_cnn_nparam": (ctypes.c_int, []),
+        "sps_cnn_set_params": (ctypes.c_int, [_P, _D]),
+        "sps_cnn_forward": (ctypes.c_int, [_P, _D, _D]),
+        "sps_cnn_vjp": (ctypes.c_int, [_P, _D, _D, _D, _D]),
+        "sps_cnn_destroy": (None, [_P]),
         "sps_sync": (ctypes.c_int, [_P]),
         "sps_last_error": (ctypes.c_char_p, []),
         "sps_destroy": (None, [_P]),
@@ -220,6 +226,42 @@ class ShBatch(Problem):
         _check(lib().sps_sh_tuning(self._h, ct, rt, ctypes.byref(b), ctypes.byref(t), ctypes.byref(ms)))
         return {"col_tile": list(ct), "row_pairs": list(rt), "blocks": b.value, "threads": t.value,
                 "step_ms": ms.value}
+
+
+class ClosureNet:
+    """The closure network alone (batch images of H x W on the GPU)."""
+
+    def __init__(self, batch, H, W, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.batch, self.H, self.W = batch, H, W
+        h = _P()
+        _check(lib().sps_cnn_build(batch, H, W, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self.nparam = int(lib().sps_cnn_nparam())
+        self.npix = batch * H * W
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sps_cnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, theta):
+        _check(lib().sps_cnn_set_params(self._h, _ptr(theta, self.nparam)))
+
+    def forward(self, x, y):
+        _check(lib().sps_cnn_forward(self._h, _ptr(x, self.npix), _ptr(y, self.npix)))
+
+    def vjp(self, x, ybar, xbar, theta_bar=None):
+        _check(lib().sps_cnn_vjp(self._h, _ptr(x, self.npix), _ptr(ybar, self.npix), _ptr(xbar, self.npix),
+                                 _ptr(theta_bar, self.nparam)))
 
 
 def rbc_host_bands(nx, nz, lx, Ra, Pr, dt=1e-3):
