@@ -95,6 +95,56 @@ int sps_build_sh_batch(int batch, const int *n, const double *r, double lx, doub
  * the batch (ms). */
 int sps_sh_tuning(const sps_problem *P, int *col_tile, int *row_tile, int *blocks, int *threads, double *step_ms);
 
+/* Batched 2D Kolmogorov flow in vorticity form on [0, 2 pi)^2, periodic:
+ * omega_t + u . grad omega = nu Laplacian omega - 4 cos 4y (+ closure), u = (d_y psi, -d_x psi),
+ * psi = omega / |k|^2, nu = 1/re.  IVP form of the Supplementary, "Initial value problems":
+ * M = 1, L = nu |k|^2, F = -u . grad omega + f (+ closure) with the advection on the 3/2
+ * padded grid; SBDF2 with an SBDF1 first step (equ:imex) and its discrete adjoint
+ * (equ:IMEX_adjoint).  batch independent instances of N x N modes (N a multiple of 4 with
+ * factors 2 and 3 only, 8..1024).  closure != 0 adds the closure network (sps_cnn_*) evaluated
+ * on the N x N vorticity grid to F (N a multiple of 32); its parameters start at zero.
+ * keep_history != 0 keeps every state of the last forward run (max_steps + 1 states), which
+ * the reverse sweep, sps_kolmo_rollout's gradients, sps_adjoint_step and sps_eval_F_vjp need;
+ * keep_history == 0 keeps three states, for long forward runs of any length.
+ * Layout: as the Swift-Hohenberg problems, per instance X[m][iy] (m < N/2, iy in FFT order,
+ * iy = N/2 unused and zero), complex (re, im); the grid values of a state are
+ * omega(x, y) = Re sum w_m X[m][iy] e^{i (m x + k_y y)}, w_0 = 1, w_m = 2.
+ * sps_step, sps_adjoint_step, sps_eval_F and sps_eval_F_vjp work as for every problem;
+ * sps_cost, sps_gradient, sps_solve and sps_initial_state* return SPS_E_UNSUPPORTED. */
+int sps_build_kolmo(int batch, int n, double re, double dt, int max_steps, int closure, int keep_history,
+                    void *hip_stream, sps_problem **out);
+
+/* Copy the closure parameters (FP64 device vector of sps_cnn_nparam() values, order as for
+ * sps_cnn_set_params) into the problem.  SPS_E_ARG without the closure. */
+int sps_kolmo_set_params(sps_problem *P, const double *theta);
+
+/* Forward run of nsteps steps from X0 (device state, read only); XN (nullable) receives the
+ * last state.  snap (nullable): every `every` steps the state truncated to the nc x nc modes
+ * of a coarse grid (|k_x|, |k_y| < nc/2, coarse Nyquist row zero) is written in the coarse
+ * state layout, snapshot s (steps (s+1) every) at snap + s * batch * nc * nc (doubles); the
+ * caller sizes it for nsteps / every snapshots.  Without keep_history nsteps is unbounded. */
+int sps_kolmo_forward(sps_problem *P, const double *X0, int nsteps, double *XN, double *snap, int every, int nc);
+
+/* Rollout loss and its gradients through the discrete adjoint (equ:efficient_gradient):
+ * J[b] = (1/nsteps) sum_{k=1..nsteps} mean over the N x N grid of (omega_k - target_k)^2 with
+ * targets[k-1] the k-th target state (device, nsteps * state size doubles, state layout);
+ * the cotangent of every intermediate state enters the reverse sweep.  XN, J (batch values),
+ * dJdX0 (state layout) and dJdtheta (sps_cnn_nparam() values, the SUM over instances of
+ * dJ[b]/dtheta, overwritten) are nullable; the gradients need keep_history and nsteps <=
+ * max_steps, dJdtheta the closure. */
+int sps_kolmo_rollout(sps_problem *P, const double *X0, const double *targets, int nsteps, double *XN, double *J,
+                      double *dJdX0, double *dJdtheta);
+
+/* theta_bar += (dF/dtheta)^T Fbar at state X (closure parameters' cotangent of one explicit-
+ * term evaluation, summed over instances).  Needs the closure and keep_history. */
+int sps_kolmo_param_vjp(sps_problem *P, const double *X, const double *Fbar, double *theta_bar);
+
+/* One Adam update of the problem's closure parameters with gradient grad and moment vectors
+ * m1, m2 (device, sps_cnn_nparam() values each, updated in place; start at zero), learning
+ * rate lr, step count t >= 1, beta1 = 0.9, beta2 = 0.999, eps = 1e-8.  Not part of the paper's
+ * method: the optimiser of the closure's training. */
+int sps_kolmo_adam(sps_problem *P, const double *grad, double *m1, double *m2, double lr, int t);
+
 /* Number of doubles in one state vector (K * S * 2). */
 long long sps_state_size(const sps_problem *P);
 

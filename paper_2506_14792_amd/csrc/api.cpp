@@ -193,6 +193,47 @@ int sps_sh_tuning(const sps_problem* P, int* col_tile, int* row_tile, int* block
                [&](sps::ProblemImpl& p) { sps::sh_tuning(&p, col_tile, row_tile, blocks, threads, step_ms); });
 }
 
+int sps_build_kolmo(int batch, int n, double re, double dt, int max_steps, int closure, int keep_history,
+                    void* hip_stream, sps_problem** out) {
+  if (!out) return fail(SPS_E_ARG, "null argument");
+  *out = nullptr;
+  try {
+    sps::ProblemImpl* impl = sps::make_kolmo(batch, n, re, dt, max_steps, closure, keep_history,
+                                             reinterpret_cast<hipStream_t>(hip_stream));
+    *out = new sps_problem{impl};
+    return SPS_OK;
+  } catch (const sps::Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::exception& e) {
+    return fail(SPS_E_HIP, e.what());
+  }
+}
+
+int sps_kolmo_set_params(sps_problem* P, const double* theta) {
+  if (!theta) return fail(SPS_E_ARG, "null argument");
+  return guard(P, [&](sps::ProblemImpl& p) { sps::kolmo_set_params(&p, theta); });
+}
+
+int sps_kolmo_forward(sps_problem* P, const double* X0, int nsteps, double* XN, double* snap, int every, int nc) {
+  return guard(P, [&](sps::ProblemImpl& p) { sps::kolmo_forward(&p, X0, nsteps, XN, snap, every, nc); });
+}
+
+int sps_kolmo_rollout(sps_problem* P, const double* X0, const double* targets, int nsteps, double* XN, double* J,
+                      double* dJdX0, double* dJdtheta) {
+  if (!X0 || !targets) return fail(SPS_E_ARG, "null argument");
+  return guard(P, [&](sps::ProblemImpl& p) { sps::kolmo_rollout(&p, X0, targets, nsteps, XN, J, dJdX0, dJdtheta); });
+}
+
+int sps_kolmo_param_vjp(sps_problem* P, const double* X, const double* Fbar, double* theta_bar) {
+  if (!X || !Fbar || !theta_bar) return fail(SPS_E_ARG, "null argument");
+  return guard(P, [&](sps::ProblemImpl& p) { sps::kolmo_param_vjp(&p, X, Fbar, theta_bar); });
+}
+
+int sps_kolmo_adam(sps_problem* P, const double* grad, double* m1, double* m2, double lr, int t) {
+  if (!grad || !m1 || !m2 || t < 1) return fail(SPS_E_ARG, "bad argument");
+  return guard(P, [&](sps::ProblemImpl& p) { sps::kolmo_adam(&p, grad, m1, m2, lr, t); });
+}
+
 
 int sps_cnn_build(int batch, int H, int W, void* hip_stream, sps_cnn** out) {
   if (!out) return fail(SPS_E_ARG, "null argument");

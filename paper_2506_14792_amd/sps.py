@@ -61,6 +61,13 @@ def lib():
         "sps_sh_tuning": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                          ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                          ctypes.POINTER(ctypes.c_double)]),
+        "sps_build_kolmo": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                           ctypes.c_int, ctypes.c_int, _P, ctypes.POINTER(_P)]),
+        "sps_kolmo_set_params": (ctypes.c_int, [_P, _D]),
+        "sps_kolmo_forward": (ctypes.c_int, [_P, _D, ctypes.c_int, _D, _D, ctypes.c_int, ctypes.c_int]),
+        "sps_kolmo_rollout": (ctypes.c_int, [_P, _D, _D, ctypes.c_int, _D, _D, _D, _D]),
+        "sps_kolmo_param_vjp": (ctypes.c_int, [_P, _D, _D, _D]),
+        "sps_kolmo_adam": (ctypes.c_int, [_P, _D, _D, _D, ctypes.c_double, ctypes.c_int]),
         "sps_cnn_build": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, ctypes.POINTER(_P)]),
         "sps_cnn_nparam": (ctypes.c_int, []),
         "sps_cnn_set_params": (ctypes.c_int, [_P, _D]),
@@ -226,6 +233,48 @@ class ShBatch(Problem):
         _check(lib().sps_sh_tuning(self._h, ct, rt, ctypes.byref(b), ctypes.byref(t), ctypes.byref(ms)))
         return {"col_tile": list(ct), "row_pairs": list(rt), "blocks": b.value, "threads": t.value,
                 "step_ms": ms.value}
+
+
+class Kolmogorov(Problem):
+    """A batch of 2D Kolmogorov flows (N x N modes on [0, 2 pi)^2, Re, SBDF2 step dt), with the
+    closure network in the explicit term when closure is set.  States of the instances are
+    concatenated; keep_history keeps every state of the last forward run for the gradients."""
+
+    def __init__(self, batch, N, Re=1000.0, dt=0.01, max_steps=1, closure=False, keep_history=True, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self._stream = stream
+        self.batch, self.N = int(batch), int(N)
+        h = _P()
+        _check(lib().sps_build_kolmo(self.batch, self.N, float(Re), float(dt), int(max_steps), int(bool(closure)),
+                                     int(bool(keep_history)), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self.n = int(lib().sps_state_size(h))
+        self.nparam = int(lib().sps_cnn_nparam())
+        self.tape_id = 0
+
+    def set_params(self, theta):
+        _check(lib().sps_kolmo_set_params(self._h, _ptr(theta, self.nparam)))
+
+    def forward(self, X0, nsteps, XN=None, snap=None, every=1, nc=0):
+        self.tape_id += 1
+        ns = None if snap is None else (nsteps // every) * self.batch * nc * nc
+        _check(lib().sps_kolmo_forward(self._h, _ptr(X0, self.n), int(nsteps), _ptr(XN, self.n), _ptr(snap, ns),
+                                       int(every), int(nc)))
+
+    def rollout(self, X0, targets, nsteps, XN=None, J=None, dJdX0=None, dJdtheta=None):
+        self.tape_id += 1
+        _check(lib().sps_kolmo_rollout(self._h, _ptr(X0, self.n), _ptr(targets, nsteps * self.n), int(nsteps),
+                                       _ptr(XN, self.n), _ptr(J, self.batch), _ptr(dJdX0, self.n),
+                                       _ptr(dJdtheta, self.nparam)))
+
+    def param_vjp(self, X, Fbar, theta_bar):
+        _check(lib().sps_kolmo_param_vjp(self._h, _ptr(X, self.n), _ptr(Fbar, self.n), _ptr(theta_bar, self.nparam)))
+
+    def adam(self, grad, m1, m2, lr, t):
+        _check(lib().sps_kolmo_adam(self._h, _ptr(grad, self.nparam), _ptr(m1, self.nparam), _ptr(m2, self.nparam),
+                                    float(lr), int(t)))
 
 
 class ClosureNet:

@@ -1,0 +1,188 @@
+"""Kolmogorov flow on the GPU (advection on the 3/2 grid, optional closure network in the
+explicit term, SBDF2 forward run, rollout loss, reverse sweep with injected cotangents and the
+closure-parameter gradient) against the FP64 oracle.
+
+Without the closure every result is FP64 on both sides: relative error <= 1e-11 of the largest
+magnitude.  With the closure the network runs in bf16/FP32 on the GPU and in FP64 with the same
+bf16 roundings in the oracle, whose per-pixel output bound (|dy_p| <= 2^-5 S_p, S_p the sum of
+|w3| |a2| over the pixel's inputs) gives |dF_k| <= 2^-5 max_p S_p for every coefficient (a
+coefficient is a grid mean of the output); over n steps of size dt a state moves by at most
+4 n dt times that (the SBDF2 extrapolation weights sum to 3 in magnitude, and the solve divides
+by 3/(2 dt) or more).  Cotangents and parameter gradients keep the closure network's own bound:
+max error <= 2^-7 and median <= 2^-13 of the array's largest magnitude."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import closure as cl
+from oracle import imex
+from oracle.kolmo import Kolmogorov, rollout_loss_and_gradients
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2506_14792_amd as sps  # noqa: E402
+
+
+def to_dev(cs):
+    """Oracle coefficient arrays c[iy, m] (or (K, 1) vectors) -> one device state X[b][m][iy]."""
+    arrs = []
+    for c in cs:
+        c = np.asarray(c)
+        if c.ndim == 2 and c.shape[1] == 1:
+            n = int(round(np.sqrt(2 * c.size)))
+            c = c.reshape(n, n // 2)
+        arrs.append(np.ascontiguousarray(c.T))
+    a = np.ascontiguousarray(np.stack(arrs))
+    return torch.from_numpy(a.view(np.float64).ravel().copy()).cuda()
+
+
+def from_dev(t, B, N):
+    a = t.cpu().numpy().view(np.complex128).reshape(B, N // 2, N)
+    return [a[b].T.copy() for b in range(B)]
+
+
+def rel(a, b):
+    return np.max(np.abs(np.asarray(a) - np.asarray(b))) / np.max(np.abs(b))
+
+
+def params(seed):
+    rng = np.random.default_rng(seed)
+    p = cl.init_params(seed=seed, C=32, scale=1.0)
+    p["w3"] = p["w3"] * 30.0
+    for k in ("b1", "b2", "b3"):
+        p[k] = 0.1 * rng.standard_normal(p[k].shape)
+    return p
+
+
+@pytest.mark.parametrize("N", [72, 16], ids=["72", "16"])
+def test_kolmo_no_closure_fp64(N):
+    print(f"kolmo no closure N={N}", flush=True)
+    B, dt, n = 2, 0.01, 6
+    c0 = workloads.kolmo_vorticity(seed=1, N=N, batch=B)
+    tg = [workloads.kolmo_vorticity(seed=10 + k, N=N, batch=B) for k in range(n)]
+    P = Kolmogorov(N, Re=1000.0)
+    G = sps.Kolmogorov(B, N, Re=1000.0, dt=dt, max_steps=n, closure=False, keep_history=True)
+    X0 = to_dev(list(c0))
+    # explicit term and its VJP
+    F = torch.zeros_like(X0)
+    G.eval_F(X0, F)
+    Yb = workloads.kolmo_vorticity(seed=5, N=N, batch=B)
+    Xb = torch.zeros_like(X0)
+    G.eval_F_vjp(X0, to_dev(list(Yb)), Xb)
+    Fg, Xbg = from_dev(F, B, N), from_dev(Xb, B, N)
+    for b in range(B):
+        X = c0[b].reshape(-1, 1)
+        ef = rel(Fg[b], P.F(X).reshape(N, N // 2))
+        ev = rel(Xbg[b], P.F_vjp(X, Yb[b].reshape(-1, 1)).reshape(N, N // 2))
+        print(f"  F rel {ef:.2e}  F_vjp rel {ev:.2e}", flush=True)
+        assert ef <= 1e-11 and ev <= 1e-11
+    # rollout loss and gradient
+    targets = torch.cat([to_dev(list(t)) for t in tg])
+    XN = torch.zeros_like(X0)
+    J = torch.zeros(B, dtype=torch.float64, device="cuda")
+    g0 = torch.zeros_like(X0)
+    G.rollout(X0, targets, n, XN=XN, J=J, dJdX0=g0)
+    XNg, g0g, Jg = from_dev(XN, B, N), from_dev(g0, B, N), J.cpu().numpy()
+    for b in range(B):
+        Jo, go, _, states = rollout_loss_and_gradients(P, c0[b].reshape(-1, 1), [t[b].reshape(-1, 1) for t in tg],
+                                                       dt, n)
+        ex = rel(XNg[b], states[-1].reshape(N, N // 2))
+        eg = rel(g0g[b], go.reshape(N, N // 2))
+        print(f"  XN rel {ex:.2e}  J {Jg[b]:.6e} vs {Jo:.6e}  dJ/dX0 rel {eg:.2e}", flush=True)
+        assert ex <= 1e-11 and abs(Jg[b] - Jo) <= 1e-11 * abs(Jo) and eg <= 1e-11
+    # plain adjoint of the last forward sweep with an external cotangent
+    G.step(X0.clone(), n)
+    Xbar = to_dev(list(Yb))
+    G.adjoint_step(Xbar, n)
+    Xbg = from_dev(Xbar, B, N)
+    for b in range(B):
+        _, states = imex.sbdf_forward(P, c0[b].reshape(-1, 1), dt, n)
+        go, _ = imex.sbdf_adjoint_general(P, states, dt, Xbar_N=Yb[b].reshape(-1, 1))
+        ea = rel(Xbg[b], go.reshape(N, N // 2))
+        print(f"  adjoint_step rel {ea:.2e}", flush=True)
+        assert ea <= 1e-11
+
+
+def test_kolmo_snapshots_and_ring_history():
+    """A forward run that keeps three states (the fine-run mode) gives the same final state as
+    the full-history run, and its snapshots are the states truncated to the coarse modes."""
+    print("kolmo snapshots", flush=True)
+    B, N, Nc, dt, n, every = 2, 48, 16, 0.005, 8, 2
+    c0 = workloads.kolmo_vorticity(seed=3, N=N, batch=B)
+    X0 = to_dev(list(c0))
+    G1 = sps.Kolmogorov(B, N, Re=1000.0, dt=dt, max_steps=n, keep_history=True)
+    G2 = sps.Kolmogorov(B, N, Re=1000.0, dt=dt, max_steps=1, keep_history=False)
+    X1, X2 = torch.zeros_like(X0), torch.zeros_like(X0)
+    snap = torch.full(((n // every) * B * Nc * Nc,), 7.0, dtype=torch.float64, device="cuda")
+    G1.forward(X0, n, XN=X1)
+    G2.forward(X0, n, XN=X2, snap=snap, every=every, nc=Nc)
+    assert torch.equal(X1, X2)
+    P = Kolmogorov(N, Re=1000.0)
+    s = snap.cpu().numpy().view(np.complex128).reshape(n // every, B, Nc // 2, Nc)
+    iyc = np.arange(Nc)
+    iyc = np.where(iyc < Nc // 2, iyc, iyc - Nc)
+    rows = np.where(iyc >= 0, iyc, iyc + N)
+    for b in range(B):
+        _, states = imex.sbdf_forward(P, c0[b].reshape(-1, 1), dt, n)
+        for j in range(n // every):
+            ref = states[(j + 1) * every].reshape(N, N // 2)[rows, : Nc // 2].copy()
+            ref[Nc // 2, :] = 0.0
+            got = s[j, b].T
+            assert rel(got, ref) <= 1e-11
+
+
+@pytest.mark.parametrize("N", [32, 96], ids=["32", "96"])
+def test_kolmo_closure_rollout(N):
+    print(f"kolmo closure N={N}", flush=True)
+    B, dt, n = 2, 0.01, 3
+    p = params(11)
+    theta = torch.from_numpy(cl.flatten(p)).cuda()
+    c0 = workloads.kolmo_vorticity(seed=2, N=N, batch=B)
+    tg = [workloads.kolmo_vorticity(seed=20 + k, N=N, batch=B) for k in range(n)]
+    P = Kolmogorov(N, Re=1000.0, params=p, bf=True)
+    G = sps.Kolmogorov(B, N, Re=1000.0, dt=dt, max_steps=n, closure=True, keep_history=True)
+    G.set_params(theta)
+    X0 = to_dev(list(c0))
+    F = torch.zeros_like(X0)
+    G.eval_F(X0, F)
+    Fg = from_dev(F, B, N)
+    smax = []
+    for b in range(B):
+        w = P.T.to_grid(c0[b], N)
+        _, cache = cl.forward(p, w, bf=True)
+        S = cl.conv3(np.abs(cache[4]), np.abs(cache[7]), np.zeros(1))[0]
+        smax.append(S.max())
+        dF = np.max(np.abs(Fg[b] - P.F(c0[b].reshape(-1, 1)).reshape(N, N // 2)))
+        clo = np.max(np.abs(P.closure_term(c0[b])))
+        print(f"  F: max err {dF:.2e}  bound {2.0 ** -5 * S.max():.2e}  closure max {clo:.2e}", flush=True)
+        assert clo > 1e-3 * np.max(np.abs(Fg[b]))          # the closure is not negligible
+        assert dF <= 2.0 ** -5 * S.max() + 1e-11 * np.max(np.abs(Fg[b]))
+    targets = torch.cat([to_dev(list(t)) for t in tg])
+    XN = torch.zeros_like(X0)
+    J = torch.zeros(B, dtype=torch.float64, device="cuda")
+    g0 = torch.zeros_like(X0)
+    gth = torch.zeros_like(theta)
+    G.rollout(X0, targets, n, XN=XN, J=J, dJdX0=g0, dJdtheta=gth)
+    XNg, g0g, Jg = from_dev(XN, B, N), from_dev(g0, B, N), J.cpu().numpy()
+    gth = gth.cpu().numpy()
+    tr = None
+    for b in range(B):
+        Jo, go, gp, states = rollout_loss_and_gradients(P, c0[b].reshape(-1, 1), [t[b].reshape(-1, 1) for t in tg],
+                                                        dt, n)
+        tr = gp if tr is None else tr + gp
+        dX = np.max(np.abs(XNg[b] - states[-1].reshape(N, N // 2)))
+        bound = 4 * n * dt * 2.0 ** -5 * smax[b]
+        e0 = np.abs(g0g[b] - go.reshape(N, N // 2)) / np.max(np.abs(go))
+        print(f"  XN err {dX:.2e} (bound {bound:.2e})  J {Jg[b]:.8e} vs {Jo:.8e}  "
+              f"dJ/dX0 max {e0.max():.2e} median {np.median(e0):.2e}", flush=True)
+        assert dX <= bound
+        assert e0.max() <= 2.0 ** -7 and np.median(e0) <= 2.0 ** -13
+    tp, to = cl.unflatten(gth), cl.unflatten(tr)
+    for k in cl.PARAM_ORDER:
+        e = np.abs(tp[k] - to[k]) / np.max(np.abs(to[k]))
+        print(f"  d/d{k}: max {e.max():.2e} median {np.median(e):.2e}", flush=True)
+        assert e.max() <= 2.0 ** -7 and np.median(e) <= 2.0 ** -13, k

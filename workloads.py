@@ -53,3 +53,24 @@ def sh_batch(seed=0, batch=128, sizes=(64, 96, 128, 192), rmin=0.1, rmax=0.5, am
     r = rng.uniform(rmin, rmax, size=batch)
     u0 = [rng.uniform(-amp, amp, size=(int(k), int(k))) for k in n]
     return [int(k) for k in n], [float(v) for v in r], u0
+
+
+def kolmo_vorticity(seed=0, N=64, batch=1, amp=0.4):
+    """Random initial vorticity coefficients of 2D Kolmogorov flow on [0, 2 pi)^2 with an
+    energy spectrum E(k) ~ k^-3: |omega_k| ~ amp |k|^-1 (complex Gaussian per mode, the k_x = 0
+    column Hermitian so that the field is real, mean and Nyquist row zero).  The expected mean
+    square velocity is about 6 amp^2 (a lattice sum of |k|^-4), so amp = 0.4 gives about 1.  Returns (batch, N, N/2) complex arrays c[iy, m] (iy in FFT order)."""
+    rng = np.random.default_rng(seed)
+    iy = np.arange(N)
+    ky = np.where(iy < N // 2, iy, iy - N).astype(float)
+    kx = np.arange(N // 2).astype(float)
+    k = np.sqrt(ky[:, None] ** 2 + kx[None, :] ** 2)
+    out = np.zeros((batch, N, N // 2), complex)
+    for b in range(batch):
+        c = (rng.standard_normal((N, N // 2)) + 1j * rng.standard_normal((N, N // 2))) / np.sqrt(2.0)
+        c *= amp / np.where(k > 0, k, 1.0)
+        c[0, 0] = 0.0
+        c[N // 2, :] = 0.0
+        c[N // 2 + 1:, 0] = np.conj(c[1:N // 2, 0][::-1])
+        out[b] = c
+    return out
