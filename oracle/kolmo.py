@@ -3,10 +3,12 @@ optionally with a learned closure added to its explicit term.
 
 TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
 
-omega_t + u . grad omega = nu Laplacian omega + f,  u = (d_y psi, -d_x psi),
+omega_t + u . grad omega = nu Laplacian omega - drag omega + f,  u = (d_y psi, -d_x psi),
 Laplacian psi = -omega, nu = 1 / Re, f = -4 cos(4 y) (the curl of the body force sin(4y) x^).
+The linear drag (bottom friction) is the usual companion of this forcing: without it the forced
+flow keeps accelerating at Re = 1000 and has no statistically steady state.
 IVP form M dX/dt + L X = F(X) (Supplementary, "Initial value problems") with one unknown per
-Fourier mode: M = 1, L_k = nu |k|^2, F = -u . grad omega + f (+ closure), the advection on the
+Fourier mode: M = 1, L_k = nu |k|^2 + drag, F = -u . grad omega + f (+ closure), the advection on the
 3/2-padded grid.  Modes, layout and transforms are those of the Swift-Hohenberg oracle
 (oracle/sh.py) on L = 2 pi.  The closure evaluates the network of oracle/closure.py on the
 vorticity at the N x N grid points and adds the coefficients of its output to F.
@@ -23,17 +25,18 @@ from .sh import SH
 
 
 class Kolmogorov:
-    def __init__(self, N, Re=1000.0, L=2.0 * np.pi, params=None, bf=True):
+    def __init__(self, N, Re=1000.0, L=2.0 * np.pi, params=None, bf=True, drag=0.0):
         self.T = SH(N, 0.0, L=L, dealias=1.5)
         T = self.T
         self.N, self.Nh, self.Ng, self.Lx = N, N // 2, T.Ng, L
         self.nu = 1.0 / Re
+        self.drag = drag
         self.params, self.bf = params, bf
         ky, kx = T.ky[:, None], T.kx[None, :]
         k2 = ky ** 2 + kx ** 2
         self.kx, self.ky = np.broadcast_to(kx, k2.shape), np.broadcast_to(ky, k2.shape)
         self.inv_k2 = np.where(k2 > 0, 1.0 / np.where(k2 > 0, k2, 1.0), 0.0)
-        lin = np.where(T.keep, self.nu * k2, 1.0)
+        lin = np.where(T.keep, self.nu * k2 + drag, 1.0)
         self.K = N * (N // 2)
         self.S = 1
         self.M = np.ones((self.K, 1, 1), dtype=complex)

@@ -4,6 +4,7 @@ conserves enstrophy and energy, the F-VJP passes the inner-product test against 
 differences, and the rollout-loss gradients with respect to the initial vorticity and the
 closure parameters match brute-force central differences and show the Taylor rate 2."""
 import numpy as np
+import pytest
 
 from oracle import closure as cl
 from oracle import imex
@@ -16,9 +17,11 @@ def coeffs(P, fn):
     return P.T.from_grid(fn(X, Y), P.N)
 
 
-def test_laminar_kolmogorov_state_is_steady():
-    P = Kolmogorov(16, Re=40.0)
-    lam = coeffs(P, lambda x, y: -np.cos(4 * y) / (4 * P.nu)).reshape(-1, 1)
+@pytest.mark.parametrize("drag", [0.0, 0.1])
+def test_laminar_kolmogorov_state_is_steady(drag):
+    # nu Laplacian omega - drag omega = 4 cos 4y  ->  omega = -4 cos(4y) / (16 nu + drag)
+    P = Kolmogorov(16, Re=40.0, drag=drag)
+    lam = coeffs(P, lambda x, y: -4.0 * np.cos(4 * y) / (16.0 * P.nu + drag)).reshape(-1, 1)
     assert np.max(np.abs(P.F(lam) - P.f.reshape(-1, 1))) < 1e-12 * np.max(np.abs(lam))
     X1, _ = imex.sbdf_forward(P, lam, 0.05, 3)
     assert np.max(np.abs(X1 - lam)) < 1e-12 * np.max(np.abs(lam))
