@@ -96,9 +96,10 @@ int sps_build_sh_batch(int batch, const int *n, const double *r, double lx, doub
 int sps_sh_tuning(const sps_problem *P, int *col_tile, int *row_tile, int *blocks, int *threads, double *step_ms);
 
 /* Batched 2D Kolmogorov flow in vorticity form on [0, 2 pi)^2, periodic:
- * omega_t + u . grad omega = nu Laplacian omega - 4 cos 4y (+ closure), u = (d_y psi, -d_x psi),
- * psi = omega / |k|^2, nu = 1/re.  IVP form of the Supplementary, "Initial value problems":
- * M = 1, L = nu |k|^2, F = -u . grad omega + f (+ closure) with the advection on the 3/2
+ * omega_t + u . grad omega = nu Laplacian omega - drag omega - 4 cos 4y (+ closure),
+ * u = (d_y psi, -d_x psi), psi = omega / |k|^2, nu = 1/re, drag >= 0 a linear friction.  IVP
+ * form of the Supplementary, "Initial value problems": M = 1, L = nu |k|^2 + drag,
+ * F = -u . grad omega + f (+ closure) with the advection on the 3/2
  * padded grid; SBDF2 with an SBDF1 first step (equ:imex) and its discrete adjoint
  * (equ:IMEX_adjoint).  batch independent instances of N x N modes (N a multiple of 4 with
  * factors 2 and 3 only, 8..1024).  closure != 0 adds the closure network (sps_cnn_*) evaluated
@@ -111,8 +112,8 @@ int sps_sh_tuning(const sps_problem *P, int *col_tile, int *row_tile, int *block
  * omega(x, y) = Re sum w_m X[m][iy] e^{i (m x + k_y y)}, w_0 = 1, w_m = 2.
  * sps_step, sps_adjoint_step, sps_eval_F and sps_eval_F_vjp work as for every problem;
  * sps_cost, sps_gradient, sps_solve and sps_initial_state* return SPS_E_UNSUPPORTED. */
-int sps_build_kolmo(int batch, int n, double re, double dt, int max_steps, int closure, int keep_history,
-                    void *hip_stream, sps_problem **out);
+int sps_build_kolmo(int batch, int n, double re, double drag, double dt, int max_steps, int closure,
+                    int keep_history, void *hip_stream, sps_problem **out);
 
 /* Copy the closure parameters (FP64 device vector of sps_cnn_nparam() values, order as for
  * sps_cnn_set_params) into the problem.  SPS_E_ARG without the closure. */
@@ -139,11 +140,12 @@ int sps_kolmo_rollout(sps_problem *P, const double *X0, const double *targets, i
  * term evaluation, summed over instances).  Needs the closure and keep_history. */
 int sps_kolmo_param_vjp(sps_problem *P, const double *X, const double *Fbar, double *theta_bar);
 
-/* One Adam update of the problem's closure parameters with gradient grad and moment vectors
- * m1, m2 (device, sps_cnn_nparam() values each, updated in place; start at zero), learning
- * rate lr, step count t >= 1, beta1 = 0.9, beta2 = 0.999, eps = 1e-8.  Not part of the paper's
- * method: the optimiser of the closure's training. */
-int sps_kolmo_adam(sps_problem *P, const double *grad, double *m1, double *m2, double lr, int t);
+/* One Adam update of the closure parameters theta (device, sps_cnn_nparam() values, updated in
+ * place and then loaded as the problem's parameters) with gradient grad and moment vectors m1,
+ * m2 (device, same length, updated in place; start at zero), learning rate lr, step count
+ * t >= 1, beta1 = 0.9, beta2 = 0.999, eps = 1e-8.  Not part of the paper's method: the
+ * optimiser of the closure's training. */
+int sps_kolmo_adam(sps_problem *P, double *theta, const double *grad, double *m1, double *m2, double lr, int t);
 
 /* Number of doubles in one state vector (K * S * 2). */
 long long sps_state_size(const sps_problem *P);

@@ -193,12 +193,12 @@ int sps_sh_tuning(const sps_problem* P, int* col_tile, int* row_tile, int* block
                [&](sps::ProblemImpl& p) { sps::sh_tuning(&p, col_tile, row_tile, blocks, threads, step_ms); });
 }
 
-int sps_build_kolmo(int batch, int n, double re, double dt, int max_steps, int closure, int keep_history,
-                    void* hip_stream, sps_problem** out) {
+int sps_build_kolmo(int batch, int n, double re, double drag, double dt, int max_steps, int closure,
+                    int keep_history, void* hip_stream, sps_problem** out) {
   if (!out) return fail(SPS_E_ARG, "null argument");
   *out = nullptr;
   try {
-    sps::ProblemImpl* impl = sps::make_kolmo(batch, n, re, dt, max_steps, closure, keep_history,
+    sps::ProblemImpl* impl = sps::make_kolmo(batch, n, re, drag, dt, max_steps, closure, keep_history,
                                              reinterpret_cast<hipStream_t>(hip_stream));
     *out = new sps_problem{impl};
     return SPS_OK;
@@ -229,9 +229,9 @@ int sps_kolmo_param_vjp(sps_problem* P, const double* X, const double* Fbar, dou
   return guard(P, [&](sps::ProblemImpl& p) { sps::kolmo_param_vjp(&p, X, Fbar, theta_bar); });
 }
 
-int sps_kolmo_adam(sps_problem* P, const double* grad, double* m1, double* m2, double lr, int t) {
-  if (!grad || !m1 || !m2 || t < 1) return fail(SPS_E_ARG, "bad argument");
-  return guard(P, [&](sps::ProblemImpl& p) { sps::kolmo_adam(&p, grad, m1, m2, lr, t); });
+int sps_kolmo_adam(sps_problem* P, double* theta, const double* grad, double* m1, double* m2, double lr, int t) {
+  if (!theta || !grad || !m1 || !m2 || t < 1) return fail(SPS_E_ARG, "bad argument");
+  return guard(P, [&](sps::ProblemImpl& p) { sps::kolmo_adam(&p, theta, grad, m1, m2, lr, t); });
 }
 
 

@@ -1,8 +1,8 @@
 // 2D Kolmogorov flow in vorticity form on the periodic square [0, 2 pi)^2, a batch of
 // independent runs of one size, optionally with a learned closure in the explicit term:
-//   omega_t + u . grad omega = nu Laplacian omega + f (+ C_theta(omega)),
+//   omega_t + u . grad omega = nu Laplacian omega - drag omega + f (+ C_theta(omega)),
 //   u = (d_y psi, -d_x psi), Laplacian psi = -omega, nu = 1/Re, f = -4 cos 4y.
-// IVP form (Supplementary, "Initial value problems"): M = 1, L_k = nu |k|^2, F = -u.grad omega
+// IVP form (Supplementary, "Initial value problems"): M = 1, L_k = nu |k|^2 + drag, F = -u.grad omega
 // + f (+ closure), the advection formed on the 3/2-padded grid; SBDF2 with an SBDF1 first step
 // (equ:imex) and the multistep adjoint recurrence (equ:IMEX_adjoint) with injected cotangents
 // of a rollout loss and the closure-parameter gradient (equ:efficient_gradient).
@@ -33,7 +33,7 @@ constexpr size_t kLdsBudget = 80 * 1024;
 
 struct KolDev {
   int B, N, Nh, Ng;
-  double nu, dt;
+  double nu, drag, dt;
   int pN, pNg;              // FFT plans of lengths N and Ng
   const FftPlan* plans;
   const cplx* tw;
@@ -253,7 +253,7 @@ __global__ void __launch_bounds__(NTK) kol_cols_fwd(KolDev d, KolCol a, int tc, 
     const long long si = io + (long long)m * N + iy;
     const int row = kol_pad_row(iy, N, Ng), rowc = kol_pad_row(iy, N, N);
     const double k2 = (double)m * m + kol_ky(iy, N) * kol_ky(iy, N);
-    const double lin = d.nu * k2, wm = (m == 0) ? 1.0 : 2.0;
+    const double lin = d.nu * k2 + d.drag, wm = (m == 0) ? 1.0 : 2.0;
     if (a.mode == K_STEP || a.mode == K_EVALF) {
       cplx F = czero();
       if (row >= 0) {
@@ -386,10 +386,11 @@ __global__ void kol_adam(int n, double* th, const double* g, double* m1, double*
 // ---------------------------------------------------------------------------- host
 class KolProblem : public ProblemImpl {
  public:
-  KolProblem(int batch, int N, double Re, double dt, int max_steps, int closure, int keep_history, hipStream_t s) {
+  KolProblem(int batch, int N, double Re, double drag, double dt, int max_steps, int closure, int keep_history,
+             hipStream_t s) {
     stream = s;
     SPS_REQUIRE(batch >= 1 && N >= 8 && N % 4 == 0 && N <= 1024, "need batch >= 1 and N a multiple of 4 in [8, 1024]");
-    SPS_REQUIRE(Re > 0 && dt > 0 && max_steps >= 1, "bad Re / dt / max_steps");
+    SPS_REQUIRE(Re > 0 && drag >= 0 && dt > 0 && max_steps >= 1, "bad Re / drag / dt / max_steps");
     SPS_REQUIRE(!closure || N % 32 == 0, "the closure needs N a multiple of 32");
     B_ = batch;
     N_ = N;
@@ -410,6 +411,7 @@ class KolProblem : public ProblemImpl {
     d_.Nh = Nh_;
     d_.Ng = Ng_;
     d_.nu = 1.0 / Re;
+    d_.drag = drag;
     d_.dt = dt;
     d_.pN = 0;
     d_.pNg = 1;
@@ -525,12 +527,14 @@ class KolProblem : public ProblemImpl {
     SPS_CHECK_LAUNCH();
   }
 
-  void adam(const double* grad, double* m1, double* m2, double lr, int t) {
+  // Adam update of the caller's parameter vector theta, which then becomes the problem's
+  void adam(double* theta, const double* grad, double* m1, double* m2, double lr, int t) {
+    SPS_REQUIRE(closure_, "this problem has no closure");
     const int n = Cnn::nparam();
-    hipLaunchKernelGGL(kol_adam, dim3((n + 255) / 256), dim3(256), 0, stream, n, theta_, grad, m1, m2, lr, 0.9, 0.999,
+    hipLaunchKernelGGL(kol_adam, dim3((n + 255) / 256), dim3(256), 0, stream, n, theta, grad, m1, m2, lr, 0.9, 0.999,
                        1e-8, t);
     SPS_CHECK_LAUNCH();
-    net_->set_params(theta_);
+    set_params(theta);
   }
 
   // ProblemImpl
@@ -668,9 +672,9 @@ class KolProblem : public ProblemImpl {
 
 }  // namespace
 
-ProblemImpl* make_kolmo(int batch, int N, double Re, double dt, int max_steps, int closure, int keep_history,
-                        hipStream_t s) {
-  return new KolProblem(batch, N, Re, dt, max_steps, closure, keep_history, s);
+ProblemImpl* make_kolmo(int batch, int N, double Re, double drag, double dt, int max_steps, int closure,
+                        int keep_history, hipStream_t s) {
+  return new KolProblem(batch, N, Re, drag, dt, max_steps, closure, keep_history, s);
 }
 void kolmo_set_params(ProblemImpl* p, const double* theta) {
   auto* k = dynamic_cast<KolProblem*>(p);
@@ -695,10 +699,10 @@ void kolmo_param_vjp(ProblemImpl* p, const double* X, const double* Fbar, double
   if (!k) throw Error(SPS_E_ARG, "not a Kolmogorov problem");
   k->param_vjp(X, Fbar, th_bar);
 }
-void kolmo_adam(ProblemImpl* p, const double* grad, double* m1, double* m2, double lr, int t) {
+void kolmo_adam(ProblemImpl* p, double* theta, const double* grad, double* m1, double* m2, double lr, int t) {
   auto* k = dynamic_cast<KolProblem*>(p);
   if (!k) throw Error(SPS_E_ARG, "not a Kolmogorov problem");
-  k->adam(grad, m1, m2, lr, t);
+  k->adam(theta, grad, m1, m2, lr, t);
 }
 
 }  // namespace sps

@@ -139,14 +139,14 @@ ProblemImpl* make_ks(const sps_desc& d, hipStream_t s);
 ProblemImpl* make_sh_batch(int batch, const int* n, const double* r, double lx, double dt, int max_steps,
                            hipStream_t s);
 void sh_tuning(ProblemImpl* p, int* col_tile, int* row_tile, int* blocks, int* threads, double* tuned_ms);
-ProblemImpl* make_kolmo(int batch, int N, double Re, double dt, int max_steps, int closure, int keep_history,
-                        hipStream_t s);
+ProblemImpl* make_kolmo(int batch, int N, double Re, double drag, double dt, int max_steps, int closure,
+                        int keep_history, hipStream_t s);
 void kolmo_set_params(ProblemImpl* p, const double* theta);
 void kolmo_forward(ProblemImpl* p, const double* X0, int nsteps, double* XN, double* snap, int every, int Nc);
 void kolmo_rollout(ProblemImpl* p, const double* X0, const double* targets, int nsteps, double* XN, double* J,
                    double* dJdX0, double* dJdtheta);
 void kolmo_param_vjp(ProblemImpl* p, const double* X, const double* Fbar, double* th_bar);
-void kolmo_adam(ProblemImpl* p, const double* grad, double* m1, double* m2, double lr, int t);
+void kolmo_adam(ProblemImpl* p, double* theta, const double* grad, double* m1, double* m2, double lr, int t);
 
 // Host helpers shared by problem builders.
 std::vector<double2> twiddles(int n);            // exp(-2 pi i t / n), t < n

@@ -61,13 +61,14 @@ def lib():
         "sps_sh_tuning": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                          ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                          ctypes.POINTER(ctypes.c_double)]),
-        "sps_build_kolmo": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+        "sps_build_kolmo": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_int,
                                            ctypes.c_int, ctypes.c_int, _P, ctypes.POINTER(_P)]),
         "sps_kolmo_set_params": (ctypes.c_int, [_P, _D]),
         "sps_kolmo_forward": (ctypes.c_int, [_P, _D, ctypes.c_int, _D, _D, ctypes.c_int, ctypes.c_int]),
         "sps_kolmo_rollout": (ctypes.c_int, [_P, _D, _D, ctypes.c_int, _D, _D, _D, _D]),
         "sps_kolmo_param_vjp": (ctypes.c_int, [_P, _D, _D, _D]),
-        "sps_kolmo_adam": (ctypes.c_int, [_P, _D, _D, _D, ctypes.c_double, ctypes.c_int]),
+        "sps_kolmo_adam": (ctypes.c_int, [_P, _D, _D, _D, _D, ctypes.c_double, ctypes.c_int]),
         "sps_cnn_build": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, ctypes.POINTER(_P)]),
         "sps_cnn_nparam": (ctypes.c_int, []),
         "sps_cnn_set_params": (ctypes.c_int, [_P, _D]),
@@ -236,18 +237,20 @@ class ShBatch(Problem):
 
 
 class Kolmogorov(Problem):
-    """A batch of 2D Kolmogorov flows (N x N modes on [0, 2 pi)^2, Re, SBDF2 step dt), with the
+    """A batch of 2D Kolmogorov flows (N x N modes on [0, 2 pi)^2, Re, linear drag, SBDF2 step dt), with the
     closure network in the explicit term when closure is set.  States of the instances are
     concatenated; keep_history keeps every state of the last forward run for the gradients."""
 
-    def __init__(self, batch, N, Re=1000.0, dt=0.01, max_steps=1, closure=False, keep_history=True, stream=None):
+    def __init__(self, batch, N, Re=1000.0, dt=0.01, max_steps=1, closure=False, keep_history=True, drag=0.0,
+                 stream=None):
         import torch
         if stream is None:
             stream = torch.cuda.current_stream()
         self._stream = stream
         self.batch, self.N = int(batch), int(N)
         h = _P()
-        _check(lib().sps_build_kolmo(self.batch, self.N, float(Re), float(dt), int(max_steps), int(bool(closure)),
+        _check(lib().sps_build_kolmo(self.batch, self.N, float(Re), float(drag), float(dt), int(max_steps),
+                                     int(bool(closure)),
                                      int(bool(keep_history)), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
         self._h = h
         self.n = int(lib().sps_state_size(h))
@@ -272,9 +275,9 @@ class Kolmogorov(Problem):
     def param_vjp(self, X, Fbar, theta_bar):
         _check(lib().sps_kolmo_param_vjp(self._h, _ptr(X, self.n), _ptr(Fbar, self.n), _ptr(theta_bar, self.nparam)))
 
-    def adam(self, grad, m1, m2, lr, t):
-        _check(lib().sps_kolmo_adam(self._h, _ptr(grad, self.nparam), _ptr(m1, self.nparam), _ptr(m2, self.nparam),
-                                    float(lr), int(t)))
+    def adam(self, theta, grad, m1, m2, lr, t):
+        _check(lib().sps_kolmo_adam(self._h, _ptr(theta, self.nparam), _ptr(grad, self.nparam), _ptr(m1, self.nparam),
+                                    _ptr(m2, self.nparam), float(lr), int(t)))
 
 
 class ClosureNet:

@@ -58,14 +58,14 @@ def params(seed):
     return p
 
 
-@pytest.mark.parametrize("N", [72, 16], ids=["72", "16"])
-def test_kolmo_no_closure_fp64(N):
-    print(f"kolmo no closure N={N}", flush=True)
+@pytest.mark.parametrize("N,drag", [(72, 0.1), (16, 0.0)], ids=["72-drag", "16"])
+def test_kolmo_no_closure_fp64(N, drag):
+    print(f"kolmo no closure N={N} drag={drag}", flush=True)
     B, dt, n = 2, 0.01, 6
     c0 = workloads.kolmo_vorticity(seed=1, N=N, batch=B)
     tg = [workloads.kolmo_vorticity(seed=10 + k, N=N, batch=B) for k in range(n)]
-    P = Kolmogorov(N, Re=1000.0)
-    G = sps.Kolmogorov(B, N, Re=1000.0, dt=dt, max_steps=n, closure=False, keep_history=True)
+    P = Kolmogorov(N, Re=1000.0, drag=drag)
+    G = sps.Kolmogorov(B, N, Re=1000.0, dt=dt, max_steps=n, closure=False, keep_history=True, drag=drag)
     X0 = to_dev(list(c0))
     # explicit term and its VJP
     F = torch.zeros_like(X0)
@@ -143,8 +143,8 @@ def test_kolmo_closure_rollout(N):
     theta = torch.from_numpy(cl.flatten(p)).cuda()
     c0 = workloads.kolmo_vorticity(seed=2, N=N, batch=B)
     tg = [workloads.kolmo_vorticity(seed=20 + k, N=N, batch=B) for k in range(n)]
-    P = Kolmogorov(N, Re=1000.0, params=p, bf=True)
-    G = sps.Kolmogorov(B, N, Re=1000.0, dt=dt, max_steps=n, closure=True, keep_history=True)
+    P = Kolmogorov(N, Re=1000.0, params=p, bf=True, drag=0.1)
+    G = sps.Kolmogorov(B, N, Re=1000.0, dt=dt, max_steps=n, closure=True, keep_history=True, drag=0.1)
     G.set_params(theta)
     X0 = to_dev(list(c0))
     F = torch.zeros_like(X0)
