@@ -206,6 +206,81 @@ def sh_timing(reps=2):
             "oracle_cpu_gradient_s_extrapolated": ocpu}
 
 
+KOL_CFG = dict(n_fine=512, factor=8, Re=1000.0, drag=0.1, dt=0.002, rollout=200, ntrain=4, ntest=2,
+               spinup=16000, nsnap=600, batch=16, iters=40, lr=1e-3, seed=100)
+
+
+def kolmo_timing():
+    """Learned-closure configuration: 2D Kolmogorov flow on [0, 2 pi)^2, Re = 1000, forcing
+    sin(4y), linear drag 0.1.  Fine runs of the unclosed solver (512^2 modes, 768^2 padded grid,
+    step dt/8) from seeded k^-3 vorticity give the truth, truncated to 64^2 modes every 8 steps;
+    the coarse solver (64^2, step dt = 0.002) carries the closure network (3x3 convolutions
+    1 -> 32 -> 32 -> 1, GELU, bf16 weights and activations, FP32 accumulation on MFMA), trained
+    with the rollout loss of 200-step coarse runs through the adjoint and Adam.  Reports the fine
+    solver's throughput (HBM bytes of the design: 21 S x 16 B per instance step, S = N^2/2
+    modes), the coarse step with and without the closure, one training iteration, and the
+    rollout error against the truncated fine run without and with the trained closure on
+    held-out runs."""
+    import torch
+    import workloads as wl
+    import paper_2506_14792_amd as sps
+    from paper_2506_14792_amd import closure_train as ct
+    from oracle import closure as cl
+    c = KOL_CFG
+    nf, fac, nc = c["n_fine"], c["factor"], c["n_fine"] // c["factor"]
+    nb = c["ntrain"] + c["ntest"]
+    v = wl.kolmo_vorticity(seed=c["seed"], N=nf, batch=nb)
+    X0 = torch.from_numpy(np.ascontiguousarray(np.transpose(v, (0, 2, 1))).view(np.float64).ravel().copy()).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S = ct.fine_snapshots(X0, nf, fac, c["Re"], c["drag"], c["dt"], c["spinup"], c["nsnap"])
+    t_fine = time.perf_counter() - t0
+    fine_steps = c["spinup"] + c["nsnap"] * fac
+    fine_bytes = 21 * (nf * nf // 2) * 16.0 * nb * fine_steps
+    Str, Ste = S[:, : c["ntrain"]].contiguous(), S[:, c["ntrain"]:].contiguous()
+    n, B = c["rollout"], c["batch"]
+    # coarse steps with and without the closure (forward runs of B windows, no history)
+    picks = [(s, b % c["ntrain"]) for b, s in enumerate(range(0, B * 10, 10))]
+    Xc, _ = ct.gather_windows(Str, picks, n)
+    theta0 = torch.from_numpy(cl.flatten(cl.init_params(seed=0, C=32, scale=1.0))).cuda()
+    step_ms = {}
+    for name, clo in (("plain", False), ("closure", True)):
+        G = sps.Kolmogorov(B, nc, Re=c["Re"], dt=c["dt"], max_steps=1, closure=clo, keep_history=False,
+                           drag=c["drag"])
+        if clo:
+            G.set_params(theta0)
+        XN = torch.empty_like(Xc)
+        G.forward(Xc, n, XN=XN)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        G.forward(Xc, n, XN=XN)
+        torch.cuda.synchronize()
+        step_ms[name] = (time.perf_counter() - t1) / n * 1e3
+        G.close()
+    held = [(s, b) for s in range(0, c["nsnap"] - n + 1, 100) for b in range(c["ntest"])]
+    J_plain = ct.rollout_losses(Ste, held, n, nc, c["Re"], c["drag"], c["dt"], None)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    theta, losses = ct.train(Str, theta0, n, nc, c["Re"], c["drag"], c["dt"], B, c["iters"], c["lr"],
+                             list(range(0, c["nsnap"] - n + 1, 10)), seed=0)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    J_closed = ct.rollout_losses(Ste, held, n, nc, c["Re"], c["drag"], c["dt"], theta)
+    return {"workload": "Kolmogorov flow 2D, Re=1000, forcing sin(4y), drag 0.1: coarse 64^2 (dt 0.002) with the "
+                        "closure network, trained on 8x spectrally truncated 512^2 fine runs (dt 0.00025) from "
+                        "seeded k^-3 vorticity, loss on 200-step coarse rollouts through the adjoint",
+            "fine_instances": nb, "fine_steps": fine_steps, "fine_s": t_fine,
+            "fine_instance_steps_per_s": nb * fine_steps / t_fine,
+            "fine_hbm_GBps": fine_bytes / t_fine / 1e9, "fine_hbm_frac": fine_bytes / t_fine / 1e9 / HBM_PEAK_GBS,
+            "coarse_batch": B, "coarse_plain_step_ms": step_ms["plain"], "coarse_closure_step_ms": step_ms["closure"],
+            "closure_step_cost_vs_plain": step_ms["closure"] / step_ms["plain"],
+            "train_iterations": c["iters"], "train_s_per_iteration": t_train / c["iters"],
+            "train_loss_first_last": [losses[0], losses[-1]],
+            "heldout_windows": len(held), "heldout_error_no_closure": float(J_plain.mean()),
+            "heldout_error_trained_closure": float(J_closed.mean()),
+            "error_ratio_no_closure_over_closure": float(J_plain.mean() / J_closed.mean())}
+
+
 def copy_calibration(nbytes=1 << 28, reps=5):
     import torch
     src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
@@ -304,6 +379,7 @@ def main():
     traffic = measured_traffic()
     ks = ks_timing()
     sh = sh_timing()
+    kol = kolmo_timing()
     cpu = None if args.no_cpu else cpu_baseline(args.cpu_steps)
     out = {
         "metric": METRIC,
@@ -335,6 +411,7 @@ def main():
         "cpu_baseline": cpu,
         "ks_config": ks,
         "sh_batched_config": sh,
+        "closure_config": kol,
         "J": J.item(),
     }
     print(json.dumps(out))

@@ -18,8 +18,15 @@ class Cnn {
   void forward(const double* x, double* y, double scale, bool accumulate);
   // xb = xscale * (d net / d x)^T yb (or +=), th_bar += (d net / d theta)^T yb (th_bar nullable)
   void vjp(const double* x, const double* yb, double* xb, double xscale, bool accumulate, double* th_bar);
+  // as vjp, with the parameter cotangent added to the network's own FP64 accumulators instead
+  // (chunk partials, one owner per slot); grad_reset zeroes them, grad_flush adds their sum over
+  // chunks (fixed order) to th_bar.  For sums over many calls, e.g. every step of a reverse sweep.
+  void vjp_accumulate(const double* x, const double* yb, double* xb, double xscale, bool accumulate);
+  void grad_reset();
+  void grad_flush(double* th_bar);
 
  private:
+  void backward(const double* x, const double* yb, double* xb, double xscale, bool accumulate, bool add);
   struct Impl;
   std::unique_ptr<Impl> p_;
 };

@@ -41,7 +41,6 @@ struct CnnDev {
   __bf16 *a0, *a1, *a2;   // a0: [B][HW]; a1, a2: [B][HW][32]
   float *z1, *z2;         // pre-activations [B][HW][32]
   float *g1, *g2;         // cotangents of z1, z2
-  float* part;            // weight-gradient partial sums
 };
 
 __device__ __forceinline__ int nb(int p, int t, int H, int W) {
@@ -197,17 +196,21 @@ __global__ void __launch_bounds__(NTC) cnn_l2_back_input(CnnDev d) {
   }
 }
 
-// layer 2 weight gradient on MFMA f32: dw2[co][ci][t] = sum_q g2[q][co] a1[q + d_t][ci].  One wave
-// per (tap, chunk of pixels); partials [chunk][t][co][ci].
+// layer 2 weight gradient on MFMA f32: dw2[co][ci][t] = sum_q g2[q][co] a1[q + d_t][ci].  One
+// block per (tap, chunk of W2_CHUNK pixels), its four waves on a quarter of the chunk each,
+// summed in a fixed order; the chunk's partial is written to (add == 0) or added to the FP64
+// accumulator acc2[chunk][t][co][ci] (each slot has one owner: deterministic).
 constexpr int W2_CHUNK = 512;
-__global__ void __launch_bounds__(64) cnn_l2_back_weight(CnnDev d, float* part) {
-  const int HW = d.H * d.W, lane = threadIdx.x;
+__global__ void __launch_bounds__(256) cnn_l2_back_weight(CnnDev d, double* acc2, int add) {
+  __shared__ float red[3][16][64];
+  const int HW = d.H * d.W, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int t = blockIdx.x % 9, chunk = blockIdx.x / 9;
-  const int q0 = chunk * W2_CHUNK;
+  const int q0 = chunk * W2_CHUNK + wv * (W2_CHUNK / 4);
   const int total = d.B * HW;
   const int row = lane & 31, half = lane >> 5;
   f32x16 acc = {};
-  for (int k = 0; k < W2_CHUNK; k += 2) {
+#pragma unroll 8
+  for (int k = 0; k < W2_CHUNK / 4; k += 2) {
     const int q = q0 + k + half;
     float av = 0.f, bv = 0.f;
     if (q < total) {
@@ -217,96 +220,113 @@ __global__ void __launch_bounds__(64) cnn_l2_back_weight(CnnDev d, float* part) 
     }
     acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
   }
-  // acc[r]: co = 8 (r / 4) + 4 half + r % 4, ci = row
-  float* o = part + ((long long)chunk * 9 + t) * CH * CH;
+  if (wv > 0) {
 #pragma unroll
-  for (int r = 0; r < 16; ++r) o[(8 * (r >> 2) + 4 * half + (r & 3)) * CH + row] = acc[r];
+    for (int r = 0; r < 16; ++r) red[wv - 1][r][lane] = acc[r];
+  }
+  __syncthreads();
+  if (wv != 0) return;
+  // acc[r]: co = 8 (r / 4) + 4 half + r % 4, ci = row
+  double* o = acc2 + ((long long)chunk * 9 + t) * CH * CH;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const float v = ((acc[r] + red[0][r][lane]) + red[1][r][lane]) + red[2][r][lane];
+    double* slot = o + (8 * (r >> 2) + 4 * half + (r & 3)) * CH + row;
+    *slot = add ? *slot + (double)v : (double)v;
+  }
 }
 
-// layer 1 and the small weight gradients: one thread per pixel computes the input cotangent
-// and its contributions to dw1, db1, dw3, db3, db2; each is summed over the wave (shuffles)
-// and the block's waves in a fixed order into part1[block][SMALL].
-constexpr int SMALL = NP1 + CH + NP3 + 1 + CH;
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-__global__ void __launch_bounds__(NTC) cnn_small_back(CnnDev d, const double* yb, double* xb, double xscale,
-                                                      int accumulate, float* part1) {
-  __shared__ float wsum[NTC / 64][SMALL];
+// layer 1 input cotangent, one thread per pixel: xb = xscale sum_{t, c} w1[c][t] g1[p - d_t][c]
+__global__ void __launch_bounds__(NTC) cnn_l1_back_input(CnnDev d, double* xb, double xscale, int accumulate) {
   const int HW = d.H * d.W;
   const int g = blockIdx.x * NTC + threadIdx.x;
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const bool on = g < d.B * HW;
-  const int b = on ? g / HW : 0, p = on ? g - b * HW : 0;
-  if (on) {   // input cotangent: sum_{t, c} w1[c][t] g1[p - d_t][c]
-    float s = 0.f;
-    for (int t = 0; t < 9; ++t) {
-      const float* G = d.g1 + ((long long)b * HW + nb_t(p, t, d.H, d.W)) * CH;
+  if (g >= d.B * HW) return;
+  const int b = g / HW, p = g - b * HW;
+  float s = 0.f;
+  for (int t = 0; t < 9; ++t) {
+    const float* G = d.g1 + ((long long)b * HW + nb_t(p, t, d.H, d.W)) * CH;
 #pragma unroll
-      for (int c = 0; c < CH; ++c) s = fmaf(d.w1[c * 9 + t], G[c], s);
-    }
-    const double v = xscale * (double)s;
-    xb[g] = accumulate ? xb[g] + v : v;
+    for (int c = 0; c < CH; ++c) s = fmaf(d.w1[c * 9 + t], G[c], s);
   }
-  const float ybp = on ? (float)yb[g] : 0.f;
-  float a0n[9];
-#pragma unroll
-  for (int t = 0; t < 9; ++t) a0n[t] = on ? (float)d.a0[(long long)b * HW + nb(p, t, d.H, d.W)] : 0.f;
-  for (int c = 0; c < CH; ++c) {
-    const float g1c = on ? d.g1[(long long)g * CH + c] : 0.f;
-    const float g2c = on ? d.g2[(long long)g * CH + c] : 0.f;
-#pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const float v1 = wave_sum(g1c * a0n[t]);
-      const float a2v = on ? (float)d.a2[((long long)b * HW + nb(p, t, d.H, d.W)) * CH + c] : 0.f;
-      const float v3 = wave_sum(ybp * a2v);
-      if (lane == 0) {
-        wsum[wv][c * 9 + t] = v1;
-        wsum[wv][NP1 + CH + c * 9 + t] = v3;
+  const double v = xscale * (double)s;
+  xb[g] = accumulate ? xb[g] + v : v;
+}
+
+// the small parameter gradients (dw1, db1, dw3, db3, db2) of one chunk of SW_CHUNK pixels: one
+// thread per parameter sums over the chunk's pixels in order; written to (add == 0) or added to
+// the FP64 accumulator acc1[chunk][SMALL] (one owner per slot).  SMALL layout: dw1 [c][t],
+// db1 [c], dw3 [c][t], db3, db2 [c].
+constexpr int SMALL = NP1 + CH + NP3 + 1 + CH;
+constexpr int SW_CHUNK = 128;
+constexpr int SW_THREADS = NP1 + CH;   // 288 (c, t) pairs + 32 channels
+__global__ void __launch_bounds__(SW_THREADS) cnn_small_weight(CnnDev d, const double* yb, double* acc1, int add) {
+  const int HW = d.H * d.W, total = d.B * HW, tid = threadIdx.x;
+  const int q0 = blockIdx.x * SW_CHUNK, q1 = min(q0 + SW_CHUNK, total);
+  double* o = acc1 + (long long)blockIdx.x * SMALL;
+  int b = q0 / HW, p = q0 - b * HW;
+  if (tid < NP1) {
+    const int c = tid & 31, t = tid >> 5;
+    float s1 = 0.f, s3 = 0.f;
+    for (int q = q0; q < q1; ++q) {
+      const long long nq = (long long)b * HW + nb(p, t, d.H, d.W);
+      s1 = fmaf(d.g1[(long long)q * CH + c], (float)d.a0[nq], s1);
+      s3 = fmaf((float)yb[q], (float)d.a2[nq * CH + c], s3);
+      if (++p == HW) {
+        p = 0;
+        ++b;
       }
     }
-    const float vb1 = wave_sum(g1c), vb2 = wave_sum(g2c);
-    if (lane == 0) {
-      wsum[wv][NP1 + c] = vb1;
-      wsum[wv][NP1 + CH + NP3 + 1 + c] = vb2;
+    double* s1p = o + c * 9 + t;
+    double* s3p = o + NP1 + CH + c * 9 + t;
+    *s1p = add ? *s1p + (double)s1 : (double)s1;
+    *s3p = add ? *s3p + (double)s3 : (double)s3;
+  } else {
+    const int c = tid - NP1;
+    float sb1 = 0.f, sb2 = 0.f, sb3 = 0.f;
+    for (int q = q0; q < q1; ++q) {
+      sb1 += d.g1[(long long)q * CH + c];
+      sb2 += d.g2[(long long)q * CH + c];
+      if (c == 0) sb3 += (float)yb[q];
     }
-  }
-  const float vb3 = wave_sum(ybp);
-  if (lane == 0) wsum[wv][NP1 + CH + NP3] = vb3;
-  __syncthreads();
-  for (int e = threadIdx.x; e < SMALL; e += NTC) {
-    float s = 0.f;
-#pragma unroll
-    for (int w = 0; w < NTC / 64; ++w) s += wsum[w][e];
-    part1[(long long)blockIdx.x * SMALL + e] = s;
+    double* p1 = o + NP1 + c;
+    double* p2 = o + NP1 + CH + NP3 + 1 + c;
+    *p1 = add ? *p1 + (double)sb1 : (double)sb1;
+    *p2 = add ? *p2 + (double)sb2 : (double)sb2;
+    if (c == 0) {
+      double* p3 = o + NP1 + CH + NP3;
+      *p3 = add ? *p3 + (double)sb3 : (double)sb3;
+    }
   }
 }
 
-// sum the partials in a fixed order and add to the FP64 parameter gradient
-__global__ void cnn_reduce(const float* part1, int nblk1, const float* part2, int nchunk, double* th_bar) {
+// sum the FP64 partials over chunks in a fixed order and add to the parameter gradient
+__global__ void cnn_reduce(const double* acc1, int n1, const double* acc2, int n2, double* th_bar) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < NP1 + CH) {   // w1, b1
     double s = 0.0;
-    for (int k = 0; k < nblk1; ++k) s += part1[(long long)k * SMALL + i];
+    for (int k = 0; k < n1; ++k) s += acc1[(long long)k * SMALL + i];
     th_bar[OFF_W1 + i] += s;
   } else if (i < NP1 + CH + NP2) {   // w2: i - (NP1 + CH) = (co * 32 + ci) * 9 + t
     const int j = i - NP1 - CH, t = j % 9, ci = (j / 9) % CH, co = j / (9 * CH);
     double s = 0.0;
-    for (int k = 0; k < nchunk; ++k) s += part2[(((long long)k * 9 + t) * CH + co) * CH + ci];
+    for (int k = 0; k < n2; ++k) s += acc2[(((long long)k * 9 + t) * CH + co) * CH + ci];
     th_bar[OFF_W2 + j] += s;
   } else if (i < NP1 + CH + NP2 + CH) {   // b2
     const int c = i - (NP1 + CH + NP2);
     double s = 0.0;
-    for (int k = 0; k < nblk1; ++k) s += part1[(long long)k * SMALL + NP1 + CH + NP3 + 1 + c];
+    for (int k = 0; k < n1; ++k) s += acc1[(long long)k * SMALL + NP1 + CH + NP3 + 1 + c];
     th_bar[OFF_B2 + c] += s;
   } else if (i < NPARAM) {   // w3, b3
     const int j = i - (NP1 + CH + NP2 + CH);
     double s = 0.0;
-    for (int k = 0; k < nblk1; ++k) s += part1[(long long)k * SMALL + NP1 + CH + j];
+    for (int k = 0; k < n1; ++k) s += acc1[(long long)k * SMALL + NP1 + CH + j];
     th_bar[OFF_W3 + j] += s;
   }
+}
+
+__global__ void cnn_zero(double* p, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
 }
 
 }  // namespace
@@ -317,9 +337,10 @@ struct Cnn::Impl {
   hipStream_t s;
   DevArena arena;
   CnnDev d{};
-  float *w1, *b1, *w2f, *b2, *w3, *b3, *part1, *part2;
+  float *w1, *b1, *w2f, *b2, *w3, *b3;
+  double *acc1, *acc2;
   __bf16* w2r;
-  int nblk1, nchunk;
+  int n1, n2;   // chunks of the small and the layer-2 weight gradients
 };
 
 Cnn::Cnn(int batch, int H, int W, hipStream_t s) : p_(new Impl) {
@@ -337,10 +358,10 @@ Cnn::Cnn(int batch, int H, int W, hipStream_t s) : p_(new Impl) {
   m.b2 = m.arena.alloc<float>(CH);
   m.w3 = m.arena.alloc<float>(NP3);
   m.b3 = m.arena.alloc<float>(1);
-  m.nblk1 = (int)((n + NTC - 1) / NTC);
-  m.nchunk = (int)((n + W2_CHUNK - 1) / W2_CHUNK);
-  m.part1 = m.arena.alloc<float>((size_t)m.nblk1 * SMALL);
-  m.part2 = m.arena.alloc<float>((size_t)m.nchunk * 9 * CH * CH);
+  m.n1 = (int)((n + SW_CHUNK - 1) / SW_CHUNK);
+  m.n2 = (int)((n + W2_CHUNK - 1) / W2_CHUNK);
+  m.acc1 = m.arena.alloc<double>((size_t)m.n1 * SMALL);
+  m.acc2 = m.arena.alloc<double>((size_t)m.n2 * 9 * CH * CH);
   CnnDev& d = m.d;
   d.B = batch;
   d.H = H;
@@ -383,7 +404,7 @@ void Cnn::forward(const double* x, double* y, double scale, bool accumulate) {
   SPS_CHECK_LAUNCH();
 }
 
-void Cnn::vjp(const double* x, const double* yb, double* xb, double xscale, bool accumulate, double* th_bar) {
+void Cnn::backward(const double* x, const double* yb, double* xb, double xscale, bool accumulate, bool add) {
   Impl& m = *p_;
   const long long n = (long long)m.B * m.H * m.W;
   const int g1 = (int)((n + NTC - 1) / NTC), g2 = (int)((n / 32 + 3) / 4);
@@ -396,16 +417,36 @@ void Cnn::vjp(const double* x, const double* yb, double* xb, double xscale, bool
   SPS_CHECK_LAUNCH();
   hipLaunchKernelGGL(cnn_l2_back_input, dim3(g2), dim3(NTC), 0, m.s, m.d);
   SPS_CHECK_LAUNCH();
-  hipLaunchKernelGGL(cnn_l2_back_weight, dim3(9 * m.nchunk), dim3(64), 0, m.s, m.d, m.part2);
+  hipLaunchKernelGGL(cnn_l2_back_weight, dim3(9 * m.n2), dim3(256), 0, m.s, m.d, m.acc2, (int)add);
   SPS_CHECK_LAUNCH();
-  hipLaunchKernelGGL(cnn_small_back, dim3(m.nblk1), dim3(NTC), 0, m.s, m.d, yb, xb, xscale, (int)accumulate,
-                     m.part1);
+  hipLaunchKernelGGL(cnn_small_weight, dim3(m.n1), dim3(SW_THREADS), 0, m.s, m.d, yb, m.acc1, (int)add);
   SPS_CHECK_LAUNCH();
-  if (th_bar) {
-    hipLaunchKernelGGL(cnn_reduce, dim3((NPARAM + 255) / 256), dim3(256), 0, m.s, m.part1, m.nblk1, m.part2,
-                       m.nchunk, th_bar);
-    SPS_CHECK_LAUNCH();
-  }
+  hipLaunchKernelGGL(cnn_l1_back_input, dim3(g1), dim3(NTC), 0, m.s, m.d, xb, xscale, (int)accumulate);
+  SPS_CHECK_LAUNCH();
+}
+
+void Cnn::vjp(const double* x, const double* yb, double* xb, double xscale, bool accumulate, double* th_bar) {
+  backward(x, yb, xb, xscale, accumulate, false);
+  if (th_bar) grad_flush(th_bar);
+}
+
+void Cnn::vjp_accumulate(const double* x, const double* yb, double* xb, double xscale, bool accumulate) {
+  backward(x, yb, xb, xscale, accumulate, true);
+}
+
+void Cnn::grad_reset() {
+  Impl& m = *p_;
+  const long long n1 = (long long)m.n1 * SMALL, n2 = (long long)m.n2 * 9 * CH * CH;
+  hipLaunchKernelGGL(cnn_zero, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, m.s, m.acc1, n1);
+  SPS_CHECK_LAUNCH();
+  hipLaunchKernelGGL(cnn_zero, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, m.s, m.acc2, n2);
+  SPS_CHECK_LAUNCH();
+}
+
+void Cnn::grad_flush(double* th_bar) {
+  Impl& m = *p_;
+  hipLaunchKernelGGL(cnn_reduce, dim3((NPARAM + 255) / 256), dim3(256), 0, m.s, m.acc1, m.n1, m.acc2, m.n2, th_bar);
+  SPS_CHECK_LAUNCH();
 }
 
 }  // namespace sps

@@ -127,7 +127,8 @@ enum RowMode { R_ADV, R_ADV_VJP, R_GRID, R_FWD_GRID };
 //  R_GRID:     Z (one field, modes m >= 1 scaled by `wscale`) -> grid[b][y][x] * gscale
 //  R_FWD_GRID: grid[b][y][x] -> W = r2c(grid)
 // LDS twiddles(G) + 2 cap, cap >= fpad_size(5 G) when R_ADV_VJP runs, else fpad_size(4 G).
-__global__ void __launch_bounds__(NTK) kol_rows(KolDev d, int mode, int G, int plan, int cap, const cplx* Z4,
+template <int NT>
+__global__ void __launch_bounds__(NT) kol_rows(KolDev d, int mode, int G, int plan, int cap, const cplx* Z4,
                                                  const cplx* Zg, double* grid, const double* gin, cplx* W,
                                                  double wscale, double gscale) {
   extern __shared__ double smem_d[];
@@ -138,13 +139,13 @@ __global__ void __launch_bounds__(NTK) kol_rows(KolDev d, int mode, int G, int p
   cplx* b0 = tw + G;
   cplx* b1 = b0 + cap;
   const cplx* g = d.tw + d.twoff[plan];
-  for (int e = tid; e < G; e += NTK) tw[e] = g[e];
+  for (int e = tid; e < G; e += NT) tw[e] = g[e];
   if (mode == R_FWD_GRID) {
     const double* r0 = gin + ((long long)b * G + y0) * G;
-    for (int x = tid; x < G; x += NTK) b0[fpad(x)] = cmk(r0[x], r0[G + x]);
+    for (int x = tid; x < G; x += NT) b0[fpad(x)] = cmk(r0[x], r0[G + x]);
   } else {
     const int nz = (mode == R_GRID) ? 1 : 4;
-    for (int e = tid; e < nin * G; e += NTK) {
+    for (int e = tid; e < nin * G; e += NT) {
       const int f = e / G, x = e - f * G;
       const cplx* U = (f == 4) ? Zg + ((long long)b * G + y0) * Nh : Z4 + (((long long)b * nz + f) * G + y0) * Nh;
       const double sc = (mode == R_GRID) ? wscale : (f == 4 ? 0.5 : 1.0);
@@ -153,10 +154,10 @@ __global__ void __launch_bounds__(NTK) kol_rows(KolDev d, int mode, int G, int p
   }
   __syncthreads();
   const FftPlan& P = d.plans[plan];
-  cplx* h = (mode == R_FWD_GRID) ? b0 : lds_fft(b0, b1, P, tw, +1, nin, G, tid, NTK);
+  cplx* h = (mode == R_FWD_GRID) ? b0 : lds_fft(b0, b1, P, tw, +1, nin, G, tid, NT);
   if (mode == R_GRID) {
     double* r0 = grid + ((long long)b * G + y0) * G;
-    for (int x = tid; x < G; x += NTK) {
+    for (int x = tid; x < G; x += NT) {
       const cplx v = h[fpad(x)];
       r0[x] = v.x * gscale;
       r0[G + x] = v.y * gscale;
@@ -167,7 +168,7 @@ __global__ void __launch_bounds__(NTK) kol_rows(KolDev d, int mode, int G, int p
   if (mode != R_FWD_GRID) {
     o = (h == b0) ? b1 : b0;
     const double inv2 = 1.0 / ((double)G * G);
-    for (int x = tid; x < G; x += NTK) {
+    for (int x = tid; x < G; x += NT) {
       const cplx u = h[fpad(x)], v = h[fpad(G + x)], wx = h[fpad(2 * G + x)], wy = h[fpad(3 * G + x)];
       if (mode == R_ADV) {
         o[fpad(x)] = cmk(-(u.x * wx.x + v.x * wy.x), -(u.y * wx.y + v.y * wy.y));
@@ -183,9 +184,9 @@ __global__ void __launch_bounds__(NTK) kol_rows(KolDev d, int mode, int G, int p
     __syncthreads();
   }
   cplx* o2 = (o == b0) ? b1 : b0;
-  const cplx* r = lds_fft(o, o2, P, tw, -1, nout, G, tid, NTK);
+  const cplx* r = lds_fft(o, o2, P, tw, -1, nout, G, tid, NT);
   // unpack the two real rows' half spectra: Y_y = (Z_m + conj Z_-m) / 2, Y_y+1 = (Z_m - conj Z_-m) / 2i
-  for (int e = tid; e < nout * 2 * Nh; e += NTK) {
+  for (int e = tid; e < nout * 2 * Nh; e += NT) {
     const int f = e / (2 * Nh), rr = e - f * 2 * Nh, yy = rr / Nh, m = rr - yy * Nh;
     const cplx zm = r[fpad(f * G + m)], zq = r[fpad(f * G + (m == 0 ? 0 : G - m))];
     const cplx v = yy ? cmk(0.5 * (zm.y + zq.y), -0.5 * (zm.x - zq.x)) : cmk(0.5 * (zm.x + zq.x), 0.5 * (zm.y - zq.y));
@@ -451,7 +452,8 @@ class KolProblem : public ProblemImpl {
     const size_t rl = sizeof(cplx) * (Ng_ + 2 * (size_t)rcap_);
     const size_t il = std::max(inv_lds(Ng_, tc_ig_), inv_lds(N_, tc_in_));
     SPS_REQUIRE(rl <= kLdsMax && il <= kLdsMax && fwd_lds(tc_f_) <= kLdsMax, "size too large for the Kolmogorov kernels");
-    for (const void* k : {(const void*)kol_cols_inv, (const void*)kol_rows, (const void*)kol_cols_fwd})
+    for (const void* k : {(const void*)kol_cols_inv, (const void*)kol_rows<256>, (const void*)kol_rows<512>,
+                          (const void*)kol_cols_fwd})
       SPS_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax));
     SPS_HIP(hipStreamSynchronize(stream));
   }
@@ -496,14 +498,19 @@ class KolProblem : public ProblemImpl {
     a.xin = xbN;
     a.out = xb0;
     launch_cols(a);
+    // the closure-parameter cotangent of every step is summed in the network's accumulators
+    // and added to th_bar once at the end of the sweep
+    const bool acc = closure_ && th_bar;
+    if (acc) net_->grad_reset();
     for (int n = nsteps; n >= 1; --n) {
       const cplx* Xp = H_ + (long long)(n - 1) * st_;
-      eval_vjp(Xp, Gk_, th_bar);
+      eval_vjp(Xp, Gk_, acc ? ACC_THETA : NO_THETA, nullptr);
       KolCol c = col_args(K_ADJ, n, nsteps);
       c.targ = targets;
       c.out = xb0;
       launch_cols(c);
     }
+    if (acc) net_->grad_flush(th_bar);
   }
 
   // forward run from X0, the rollout loss J[b] against targets and its gradients: dJdX0
@@ -567,14 +574,14 @@ class KolProblem : public ProblemImpl {
     launch_cols(a);
   }
   void eval_F_vjp(const double* X, const double* Fbar, double* Xbar) override {
-    eval_vjp(reinterpret_cast<const cplx*>(X), reinterpret_cast<const cplx*>(Fbar), nullptr);
+    eval_vjp(reinterpret_cast<const cplx*>(X), reinterpret_cast<const cplx*>(Fbar), NO_THETA, nullptr);
     KolCol a = col_args(K_VJP, 0, 0);
     a.out = reinterpret_cast<cplx*>(Xbar);
     launch_cols(a);
   }
   void param_vjp(const double* X, const double* Fbar, double* th_bar) {
     SPS_REQUIRE(closure_, "this problem has no closure");
-    eval_vjp(reinterpret_cast<const cplx*>(X), reinterpret_cast<const cplx*>(Fbar), th_bar);
+    eval_vjp(reinterpret_cast<const cplx*>(X), reinterpret_cast<const cplx*>(Fbar), ADD_THETA, th_bar);
   }
   void solve(const double*, double*, int) override {
     throw Error(SPS_E_UNSUPPORTED, "the Kolmogorov solve is internal to its steps");
@@ -629,8 +636,15 @@ class KolProblem : public ProblemImpl {
   }
   void rows(int mode, int G, int plan, const cplx* Z4, const cplx* Zg, double* grid, const double* gin, cplx* W,
             double wscale, double gscale) {
-    hipLaunchKernelGGL(kol_rows, dim3(G / 2, B_), dim3(NTK), sizeof(cplx) * (G + 2 * (size_t)rcap_), stream, d_,
-                       mode, G, plan, rcap_, Z4, Zg, grid, gin, W, wscale, gscale);
+    // rows of 384 points or more: 512 threads, so that a CU holding one block (LDS) still has
+    // eight waves
+    const size_t lds = sizeof(cplx) * (G + 2 * (size_t)rcap_);
+    if (G >= 384)
+      hipLaunchKernelGGL(kol_rows<512>, dim3(G / 2, B_), dim3(512), lds, stream, d_, mode, G, plan, rcap_, Z4, Zg, grid,
+                         gin, W, wscale, gscale);
+    else
+      hipLaunchKernelGGL(kol_rows<256>, dim3(G / 2, B_), dim3(256), lds, stream, d_, mode, G, plan, rcap_, Z4, Zg, grid,
+                         gin, W, wscale, gscale);
     SPS_CHECK_LAUNCH();
   }
   // x-spectra of the products of F at X (W) and of the closure output (Wc)
@@ -644,8 +658,11 @@ class KolProblem : public ProblemImpl {
       rows(R_FWD_GRID, N_, d_.pN, nullptr, nullptr, nullptr, yg_, Wc_, 1.0, 1.0);
     }
   }
-  // x-spectra of the VJP of F at X with cotangent G (W: 4 fields; Wc); th_bar += closure part
-  void eval_vjp(const cplx* X, const cplx* G, double* th_bar) {
+  // x-spectra of the VJP of F at X with cotangent G (W: 4 fields; Wc).  The closure's parameter
+  // cotangent: dropped (NO_THETA), added to th_bar (ADD_THETA) or to the network's accumulators
+  // (ACC_THETA).
+  enum ThetaMode { NO_THETA, ADD_THETA, ACC_THETA };
+  void eval_vjp(const cplx* X, const cplx* G, ThetaMode tm, double* th_bar) {
     SPS_REQUIRE(nwmax_ == 4, "VJPs need a problem built with keep_history");
     cols_inv(X, FS_PRIMAL4, Ng_, d_.pNg, Z4_);
     cols_inv(G, FS_ONE, Ng_, d_.pNg, Zg_);
@@ -655,7 +672,10 @@ class KolProblem : public ProblemImpl {
       rows(R_GRID, N_, d_.pN, Zc_, nullptr, og_, nullptr, nullptr, 1.0, 1.0);
       cols_inv(G, FS_ONE, N_, d_.pN, Zgc_);
       rows(R_GRID, N_, d_.pN, Zgc_, nullptr, yg_, nullptr, nullptr, 0.5, 1.0 / ((double)N_ * N_));
-      net_->vjp(og_, yg_, xg_, 1.0, false, th_bar);
+      if (tm == ACC_THETA)
+        net_->vjp_accumulate(og_, yg_, xg_, 1.0, false);
+      else
+        net_->vjp(og_, yg_, xg_, 1.0, false, tm == ADD_THETA ? th_bar : nullptr);
       rows(R_FWD_GRID, N_, d_.pN, nullptr, nullptr, nullptr, xg_, Wc_, 1.0, 1.0);
     }
   }
