@@ -300,6 +300,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--only", choices=["ks", "sh", "closure"], default=None,
+                    help="run one secondary configuration alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); the multi-GPU "
@@ -307,6 +309,12 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.only:
+        import torch
+        torch.cuda.set_device(0)
+        fn = {"ks": ks_timing, "sh": sh_timing, "closure": kolmo_timing}[args.only]
+        print(json.dumps({args.only: fn()}))
         return
 
     import torch
