@@ -74,3 +74,64 @@ def kolmo_vorticity(seed=0, N=64, batch=1, amp=0.4):
         c[N // 2 + 1:, 0] = np.conj(c[1:N // 2, 0][::-1])
         out[b] = c
     return out
+
+
+def couette_perturbation(seed=0, Nx=128, Ny=64, Nz=64, Lx=4.0 * np.pi, Lz=2.0 * np.pi, energy=1e-6,
+                         mmax=3, nmax=3, deg=8):
+    """Random divergence-free velocity perturbation of plane Couette flow with no-slip walls, as
+    Chebyshev coefficients per Fourier mode.  Modes k = m Nz + n (m < Nx/2, n < Nz in FFT order),
+    only |m| < mmax, |n| < nmax excited.  Per mode with kh = |(kx, kz)| > 0:
+        v = (1 - y^2)^2 q(y),  s = (1 - y^2) r(y),
+        (u, w) = i (kx, kz) v' / kh^2 + (-kz, kx) s / kh,
+    with q, r random complex polynomials of degree deg (coefficients decaying as 2^-j), so that
+    i kx u + v' + i kz w = 0 and u = v = w = 0 at y = -1, 1; the mean mode holds
+    u, w = (1 - y^2) r(y), v = 0 (real).  The m = 0 modes are Hermitian in n (a real field).
+    Scaled to kinetic energy `energy` = 1/2 int |u|^2 dV.  Returns (K, 3, Ny) complex
+    coefficients (u, v, w)."""
+    C = np.polynomial.chebyshev
+    rng = np.random.default_rng(seed)
+    Kx = Nx // 2
+    out = np.zeros((Kx * Nz, 3, Ny), complex)
+    one_m_y2 = np.array([0.5, 0.0, -0.5])          # 1 - y^2 in the T basis
+    wall2 = C.chebmul(one_m_y2, one_m_y2)
+
+    def poly():
+        dec = 2.0 ** -np.arange(deg + 1)
+        return dec * (rng.standard_normal(deg + 1) + 1j * rng.standard_normal(deg + 1))
+
+    def fit(c):
+        v = np.zeros(Ny, complex)
+        v[: min(Ny, len(c))] = c[:Ny]
+        return v
+
+    for m in range(min(mmax, Kx)):
+        for ns in range(-(nmax - 1), nmax):
+            if m == 0 and ns < 0:
+                continue
+            n = ns % Nz
+            k = m * Nz + n
+            kx, kz = 2.0 * np.pi * m / Lx, 2.0 * np.pi * ns / Lz
+            kh = np.hypot(kx, kz)
+            if kh == 0.0:
+                r1, r2 = poly().real, poly().real
+                out[k, 0] = fit(C.chebmul(one_m_y2, r1))
+                out[k, 2] = fit(C.chebmul(one_m_y2, r2))
+                continue
+            v = C.chebmul(wall2, poly())
+            s = C.chebmul(one_m_y2, poly())
+            dv = C.chebder(v)
+            out[k, 1] = fit(v)
+            out[k, 0] = fit(1j * kx * dv / kh ** 2) - fit(kz * s / kh)
+            out[k, 2] = fit(1j * kz * dv / kh ** 2) + fit(kx * s / kh)
+            if m == 0:
+                out[(-ns) % Nz] = np.conj(out[k])
+    # kinetic energy: 1/2 Lx Lz sum_k w_m int_{-1}^{1} |c_k(y)|^2 dy
+    e = 0.0
+    for k in range(Kx * Nz):
+        wm = 1.0 if k < Nz else 2.0
+        for f in range(3):
+            c = out[k, f]
+            sq = C.chebadd(C.chebmul(c.real, c.real), C.chebmul(c.imag, c.imag))
+            integ = C.chebint(sq)
+            e += 0.5 * Lx * Lz * wm * (C.chebval(1.0, integ) - C.chebval(-1.0, integ))
+    return out * np.sqrt(energy / e)
