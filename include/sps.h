@@ -47,7 +47,7 @@ enum sps_status {
   SPS_E_UNSUPPORTED = -7
 };
 
-enum sps_equation { SPS_RBC2D = 1, SPS_KS1D = 2, SPS_SH2D = 3 };
+enum sps_equation { SPS_RBC2D = 1, SPS_KS1D = 2, SPS_SH2D = 3, SPS_COUETTE3D = 4 };
 enum sps_scheme { SPS_RK222 = 1, SPS_SBDF2 = 2 };
 
 typedef struct {
@@ -94,6 +94,26 @@ int sps_build_sh_batch(int batch, const int *n, const double *r, double lx, doub
  * persistent block count and threads per block; the measured time of one forward step of
  * the batch (ms). */
 int sps_sh_tuning(const sps_problem *P, int *col_tile, int *row_tile, int *blocks, int *threads, double *step_ms);
+
+/* 3D plane Couette flow, Fourier (x, period lx) x Chebyshev (y in [-1, 1]) x Fourier (z, period lz):
+ * the perturbation u = (u, v, w) of the laminar flow U = y between walls moving with -1, +1,
+ * u_t + (u.grad) u + U u_x + v U' e_x + grad p - (1/re) Laplacian u = 0, div u = 0, u = 0 at the
+ * walls, in the IVP form of the Supplementary, "Initial value problems" (Stokes part implicit,
+ * products and base-flow terms explicit on the 3/2 padded grid), RK222 with checkpoints every
+ * checkpoint_every steps and the discrete adjoint of the sweep (equ:adjoint).  Modes: x index
+ * m < nx/2, z index n < nz in FFT order (the z Nyquist n = nz/2 unforced), mode k = m nz + n;
+ * nx, nz even with 3/2 nx and 3/2 nz factoring into 2 and 3; ny even in [8, 128].
+ * State layout per mode (S = 4 ny + 7 complex slots): u_par, v, u_perp, p (ny Chebyshev
+ * coefficients each, T_n(y)), then the tau slots (par, v, perp first-order, then second-order,
+ * then tau_p).  u_par = (kx u + kz w)/kh and u_perp = (-kz u + kx w)/kh in the frame of the wave
+ * vector (kh = |(kx, kz)|; at kh = 0, u_par = u and u_perp = w); tau values are those of the
+ * problem scaled to unit wall distance, twice the ones of the unscaled equations.
+ * sps_cost gives J = 1/2 int |u|^2 dV (mode 0 by its real part, z Nyquist modes excluded) and
+ * dJ/dX; sps_gradient, sps_step and sps_adjoint_step work as for the 2D problem;
+ * sps_eval_F, sps_eval_F_vjp and sps_solve act in the scaled frame (time unit t/2);
+ * sps_initial_state[_adjoint] return SPS_E_UNSUPPORTED (states are given as coefficients). */
+int sps_build_couette(int nx, int ny, int nz, double lx, double lz, double re, double dt, int checkpoint_every,
+                      int max_steps, void *hip_stream, sps_problem **out);
 
 /* Batched 2D Kolmogorov flow in vorticity form on [0, 2 pi)^2, periodic:
  * omega_t + u . grad omega = nu Laplacian omega - drag omega - 4 cos 4y (+ closure),

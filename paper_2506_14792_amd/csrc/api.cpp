@@ -193,6 +193,22 @@ int sps_sh_tuning(const sps_problem* P, int* col_tile, int* row_tile, int* block
                [&](sps::ProblemImpl& p) { sps::sh_tuning(&p, col_tile, row_tile, blocks, threads, step_ms); });
 }
 
+int sps_build_couette(int nx, int ny, int nz, double lx, double lz, double re, double dt, int checkpoint_every,
+                      int max_steps, void* hip_stream, sps_problem** out) {
+  if (!out) return fail(SPS_E_ARG, "null argument");
+  *out = nullptr;
+  try {
+    const sps::CouetteSpec c{nx, ny, nz, lx, lz, re, dt, checkpoint_every, max_steps};
+    sps::ProblemImpl* impl = sps::make_couette(c, reinterpret_cast<hipStream_t>(hip_stream));
+    *out = new sps_problem{impl};
+    return SPS_OK;
+  } catch (const sps::Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::exception& e) {
+    return fail(SPS_E_HIP, e.what());
+  }
+}
+
 int sps_build_kolmo(int batch, int n, double re, double drag, double dt, int max_steps, int closure,
                     int keep_history, void* hip_stream, sps_problem** out) {
   if (!out) return fail(SPS_E_ARG, "null argument");

@@ -33,9 +33,12 @@
 
 #include <algorithm>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <vector>
 
 #include "band_lu.h"
+#include "cou.h"
 #include "sps_device.h"
 #include "sps_internal.h"
 
@@ -50,7 +53,11 @@ struct RbcDev {
   int K, N, S, Ngx, Ngz, Nx1, Nz1;
   int n, kl, ku, uw;
   double Lx, nu, ka;
-  const double* kx;     // [K]
+  double cp, bc0;       // buoyancy coupling in the w rows (1, or 0 without buoyancy); b(0) at k = 0
+  double cost_scale;    // J = cost_scale / 2 sum_k w_k Re(c^H G c)
+  int Kz, ncost;        // modes per x wavenumber (cost weight of mode k: k / Kz == 0 ? 1 : 2); fields in J
+  const unsigned char* ckeep;   // [K] modes counted in J (null: all)
+  const double* kx;     // [K] horizontal wavenumber of each mode
   // T_n at the ascending Gauss node j of an Ng-point grid equals cos(pi M / (2 Ng)) with
   // M = n (2 (Ng - j) - 1) mod 4 Ng, so one table of 4 Ng cosines serves every (n, j).
   const double* cosz;   // [4 Ngz]
@@ -156,7 +163,7 @@ __device__ MLRow ml_row(const RbcDev& d, int k, const cplx* X, int s) {
     r.m = sc;
     cplx l = cadd(cscale(dzz_at(c, n, N), -dif), cscale(sc, dif * k2));
     if (f == 0) l = cadd(l, cmul_i(cscale(s10_at(p, n, N), kx)));
-    if (f == 1) l = csub(cadd(l, s1dz_at(p, n, N)), s10_at(b, n, N));
+    if (f == 1) l = csub(cadd(l, s1dz_at(p, n, N)), cscale(s10_at(b, n, N), d.cp));
     if (n == N - 2) l = csub(l, cscale(tau[f], 4.0 * dif));   // lifted tau_1
     if (n == N - 1) l = cadd(l, tau[3 + f]);                  // tau_2
     r.l = l;
@@ -218,7 +225,7 @@ __device__ MLRow mlt_col(const RbcDev& d, int k, const cplx* Y, int s) {
     cplx l = cadd(cscale(dzzt_at(yf, m, N), -dif), cscale(st, dif * k2));
     if (f == 0) l = cadd(l, cmul_mi(cscale(s0t_at(yc, m, N), kx)));   // (i kx S0)^H
     if (f == 1) l = cadd(l, dz1t_at(yc, m, N));
-    if (f == 2) l = csub(l, s10t_at(yw, m, N));                        // -S10 b in w rows
+    if (f == 2) l = csub(l, cscale(s10t_at(yw, m, N), d.cp));          // -S10 b in w rows
     const cplx bot = ybc[2 * f], top = ybc[2 * f + 1];
     l = cadd(l, (m & 1) ? csub(top, bot) : cadd(top, bot));
     r.l = l;
@@ -570,7 +577,7 @@ __global__ void __launch_bounds__(NTK) rbc_kfwd(RbcDev d, KfArgs a) {
     if (mode == KF_EVALF) {
       if (tid < S) {
         cplx v = (tid < 3 * N) ? fr[tid] : czero();
-        if (k == 0 && tid == 4 * N + 4) v = cadd(v, cmk(1.0, 0.0));
+        if (k == 0 && tid == 4 * N + 4) v = cadd(v, cmk(d.bc0, 0.0));
         a.Xout[(size_t)k * S + tid] = v;
       }
       return;
@@ -598,7 +605,7 @@ __global__ void __launch_bounds__(NTK) rbc_kfwd(RbcDev d, KfArgs a) {
       // boundary and gauge rows: M is zero there and F holds the boundary data (b = 1 at
       // z = 0 for k = 0), so stage 1 gives dt g F and stage 2 dt (F - (1 - g) L X1)
       const int q = (tid - 4 * N) >> 2, h = tid & 3;
-      const double fbc = (k == 0 && q == 4) ? 1.0 : 0.0;
+      const double fbc = (k == 0 && q == 4) ? d.bc0 : 0.0;
       cplx rhs;
       if (mode == KF_STAGE1) {
         rhs = cmk(dt * g * fbc, 0.0);
@@ -1076,24 +1083,27 @@ __global__ void __launch_bounds__(NT) rbc_init_adj_x(RbcDev d, const cplx* tmp, 
 }
 
 // ---------------------------------------------------------------------------- cost
+// J = cost_scale/2 sum_k w_k Re(c_k^H G c_k) over the first ncost fields (u, w for the 2D
+// problem; u_par, v, u_perp for the 3D one), w_k = 1 for the x wavenumber 0, else 2, the k = 0
+// coefficients taken by their real parts; dJ/dX alongside.  One block per mode.
 __global__ void __launch_bounds__(NT) rbc_cost(RbcDev d, const cplx* X, cplx* Xb, double* Jpart) {
   __shared__ double red[NT];
-  __shared__ cplx cu[128], cw[128];
-  const int k = blockIdx.x, tid = threadIdx.x, N = d.N, S = d.S;
-  const double wk = (k == 0) ? 1.0 : 2.0;
-  for (int n = tid; n < N; n += NT) {
-    cplx a = X[(size_t)k * S + n], b = X[(size_t)k * S + N + n];
-    if (k == 0) { a.y = 0.0; b.y = 0.0; }
-    cu[n] = a;
-    cw[n] = b;
+  __shared__ cplx cf[3][128];
+  const int k = blockIdx.x, tid = threadIdx.x, N = d.N, S = d.S, nc = d.ncost;
+  const double wk = (d.ckeep && !d.ckeep[k]) ? 0.0 : ((k / d.Kz == 0) ? 1.0 : 2.0);
+  for (int e = tid; e < nc * N; e += NT) {
+    const int f = e / N, n = e - f * N;
+    cplx a = X[(size_t)k * S + e];
+    if (k == 0) a.y = 0.0;
+    cf[f][n] = a;
   }
   __syncthreads();
   double part = 0.0;
   for (int s = tid; s < S; s += NT) {
     cplx v = czero();
-    if (s < 2 * N) {
-      const cplx* c = (s < N) ? cu : cw;
-      const int m = (s < N) ? s : s - N;
+    if (s < nc * N) {
+      const int f = s / N, m = s - f * N;
+      const cplx* c = cf[f];
       double gr = 0.0, gi = 0.0;
       for (int n = 0; n < N; ++n) {
         const double G = d.gram[m * N + n];
@@ -1101,7 +1111,7 @@ __global__ void __launch_bounds__(NT) rbc_cost(RbcDev d, const cplx* X, cplx* Xb
         gi += G * c[n].y;
       }
       part += c[m].x * gr + c[m].y * gi;   // Re(conj(c_m) (G c)_m)
-      v = cmk(d.Lx * wk * gr, d.Lx * wk * gi);
+      v = cmk(d.cost_scale * wk * gr, d.cost_scale * wk * gi);
       if (k == 0) v.y = 0.0;
     }
     Xb[(size_t)k * S + s] = v;
@@ -1112,7 +1122,7 @@ __global__ void __launch_bounds__(NT) rbc_cost(RbcDev d, const cplx* X, cplx* Xb
     if (tid < o) red[tid] += red[tid + o];
     __syncthreads();
   }
-  if (tid == 0) Jpart[k] = 0.5 * d.Lx * wk * red[0];
+  if (tid == 0) Jpart[k] = 0.5 * d.cost_scale * wk * red[0];
 }
 
 __global__ void sum_parts(const double* part, int n, double* out) {
@@ -1178,10 +1188,10 @@ struct RbcHostBands {
 };
 
 // ABI-slot dense M_k, L_k (complex), written from the formulation of the header comment.
-static void rbc_assemble(const sps_desc& desc, int k, Cmat& M, Cmat& L) {
-  const int N = desc.nz;
-  const double kx = 2.0 * M_PI * k / desc.lx, k2 = kx * kx;
-  const double nu = std::pow(desc.param0 / desc.param1, -0.5), ka = std::pow(desc.param0 * desc.param1, -0.5);
+// M and L of one mode: horizontal wavenumber kx (the mean mode when `mean`), viscosity nu,
+// diffusivity ka of the third field, coupling cp of that field into the w rows.
+static void rbc_assemble(int N, double kx, double nu, double ka, double cp, bool mean, Cmat& M, Cmat& L) {
+  const double k2 = kx * kx;
   const std::vector<double> S0 = op_S0(N), S1 = op_S1(N);
   const std::vector<double> S10 = matmul(S1, S0, N);
   const std::vector<double> D0 = op_D(N, 1.0, true), D1 = op_D(N, 2.0, false);
@@ -1207,7 +1217,7 @@ static void rbc_assemble(const sps_desc& desc, int k, Cmat& M, Cmat& L) {
       const double s10 = S10[(size_t)i * N + j];
       if (s10 != 0.0) {
         L.add(U + i, P + j, 0.0, kx * s10);   // i kx S10 p in x-momentum
-        L.add(W + i, B + j, -s10);            // -b in z-momentum
+        if (cp != 0.0) L.add(W + i, B + j, -cp * s10);   // -b in z-momentum
       }
       const double sd = 2.0 * S1D0[(size_t)i * N + j];
       if (sd != 0.0) L.add(W + i, P + j, sd);   // dp/dz in z-momentum
@@ -1222,7 +1232,7 @@ static void rbc_assemble(const sps_desc& desc, int k, Cmat& M, Cmat& L) {
       L.add(T + 2 * f, f * N + m, (m & 1) ? -1.0 : 1.0);   // value at z = 0
       L.add(T + 2 * f + 1, f * N + m, 1.0);                // value at z = 1
     }
-  if (k == 0) {
+  if (mean) {
     L.add(P + 0, T + 6, 1.0);
     for (int m = 0; m < N; m += 2) L.add(T + 6, P + m, 1.0 / (1.0 - (double)m * m));
   } else {
@@ -1231,8 +1241,10 @@ static void rbc_assemble(const sps_desc& desc, int k, Cmat& M, Cmat& L) {
 }
 
 
-void rbc_host_bands(const sps_desc& desc, RbcHostBands& hb) {
-  const int N = desc.nz, S = 4 * N + 7, K = desc.nx / 2;
+// Real-ified banded M and L of every mode (mode k has wavenumber kx[k]; mode 0 is the mean mode).
+// Modes with equal wavenumbers share their assembly.
+static void host_bands(int N, const std::vector<double>& kxs, double nu, double ka, double cp, RbcHostBands& hb) {
+  const int S = 4 * N + 7, K = (int)kxs.size();
   // phases and recombination
   std::vector<signed char> rowph(S, 0), colph(S, 0);
   for (int i = 0; i < N; ++i) rowph[i] = 1;
@@ -1292,11 +1304,19 @@ void rbc_host_bands(const sps_desc& desc, RbcHostBands& hb) {
       }
     }
   };
+  std::map<double, int> seen;
   for (int k = 0; k < K; ++k) {
+    auto it = (k == 0) ? seen.end() : seen.find(kxs[k]);
+    if (it != seen.end()) {
+      bm[k] = bm[it->second];
+      bl[k] = bl[it->second];
+      continue;
+    }
     Cmat M(S), L(S);
-    rbc_assemble(desc, k, M, L);
+    rbc_assemble(N, kxs[k], nu, ka, cp, k == 0, M, L);
     transform(M, bm[k]);
     transform(L, bl[k]);
+    if (k > 0) seen[kxs[k]] = k;
   }
   const int bw = kl + ku + 1;
   hb.kl = kl;
@@ -1314,6 +1334,13 @@ void rbc_host_bands(const sps_desc& desc, RbcHostBands& hb) {
   hb.rowph = rowph;
   hb.colph = colph;
   hb.rho = rho;
+}
+
+void rbc_host_bands(const sps_desc& desc, RbcHostBands& hb) {
+  std::vector<double> kx(desc.nx / 2);
+  for (int k = 0; k < desc.nx / 2; ++k) kx[k] = 2.0 * M_PI * k / desc.lx;
+  host_bands(desc.nz, kx, std::pow(desc.param0 / desc.param1, -0.5), std::pow(desc.param0 * desc.param1, -0.5), 1.0,
+             hb);
 }
 
 class RbcProblem : public ProblemImpl {
@@ -1334,6 +1361,71 @@ class RbcProblem : public ProblemImpl {
     SPS_REQUIRE(fft_plan(desc.nx, &dv_.px1), "nx must factor into 2 and 3");
     nu_ = std::pow(desc.param0 / desc.param1, -0.5);
     ka_ = std::pow(desc.param0 * desc.param1, -0.5);
+    dt_ = desc.dt;
+    kxs_.resize(K_);
+    for (int k = 0; k < K_; ++k) kxs_[k] = 2.0 * M_PI * k / desc.lx;
+    cp_ = 1.0;
+    bc0_ = 1.0;
+    cost_scale_ = desc.lx;
+    Kz_ = 1;
+    ncost_ = 2;
+    init();
+  }
+
+  // 3D plane Couette flow (perturbation of U = y between walls y = -1, 1 moving with -1, 1):
+  // the per-mode Stokes systems of the frame scaled to unit wall distance (y' = (y + 1)/2,
+  // x' = x/2, z' = z/2, t' = t/2: nu' = 1/(2 Re), dt' = dt/2, U = 2y' - 1) in the variables
+  // (u_par, v, u_perp, p) of the wave-vector frame, with no buoyancy coupling and homogeneous
+  // walls; the explicit term from the plane kernels of cou.hip.
+  RbcProblem(const CouetteSpec& c, hipStream_t s) {
+    stream = s;
+    SPS_REQUIRE(c.nx >= 4 && c.nx % 2 == 0 && c.nz >= 4 && c.nz % 2 == 0, "nx and nz must be even and >= 4");
+    SPS_REQUIRE(c.ny >= 8 && c.ny <= 128 && c.ny % 2 == 0, "ny must be even in [8, 128]");
+    SPS_REQUIRE(c.lx > 0 && c.lz > 0 && c.re > 0, "bad periods or Reynolds number");
+    SPS_REQUIRE(c.dt > 0 && c.checkpoint_every >= 1 && c.max_steps >= 1, "bad dt / checkpoint / max_steps");
+    desc_ = sps_desc{};
+    desc_.equation = SPS_COUETTE3D;
+    desc_.scheme = SPS_RK222;
+    desc_.nx = c.nx;
+    desc_.nz = c.ny;
+    desc_.lx = c.lx;
+    desc_.dealias = 1.5;
+    desc_.dt = c.dt;
+    desc_.checkpoint_every = c.checkpoint_every;
+    desc_.max_steps = c.max_steps;
+    cou_ = true;
+    const int Kx = c.nx / 2;
+    K_ = Kx * c.nz;
+    N_ = c.ny;
+    S_ = 4 * N_ + 7;
+    Ngx_ = 3 * c.nx / 2;
+    Ngz_ = 3 * N_ / 2;
+    SPS_REQUIRE(fft_plan(Ngx_, &dv_.px) && fft_plan(c.nx, &dv_.px1), "nx and 3 nx / 2 must factor into 2 and 3");
+    nu_ = ka_ = 1.0 / (2.0 * c.re);
+    dt_ = 0.5 * c.dt;
+    const double lx = 0.5 * c.lx, lz = 0.5 * c.lz;
+    kxs_.resize(K_);
+    ckeep_.resize(K_);
+    for (int m = 0; m < Kx; ++m)
+      for (int n = 0; n < c.nz; ++n) {
+        const int ns = (n < c.nz / 2) ? n : n - c.nz;
+        kxs_[m * c.nz + n] = std::hypot(2.0 * M_PI * m / lx, 2.0 * M_PI * ns / lz);
+        ckeep_[m * c.nz + n] = (n != c.nz / 2);
+      }
+    cp_ = 0.0;
+    bc0_ = 0.0;
+    cost_scale_ = 2.0 * c.lx * c.lz;
+    Kz_ = c.nz;
+    ncost_ = 3;
+    std::vector<double> unode(Ngz_);
+    for (int j = 0; j < Ngz_; ++j)
+      unode[j] = -(double)cosl(3.14159265358979323846264338327950288L * (2 * j + 1) / (2.0L * Ngz_));
+    CouetteGeom g{Kx, c.nz, Ngx_, 3 * c.nz / 2, Ngz_, lx, lz, unode.data(), 2.0};
+    planes_.reset(new CouettePlanes(g, stream));
+    init();
+  }
+
+  void init() {
     build_tables();
     build_bands();
     alloc_work();
@@ -1356,7 +1448,7 @@ class RbcProblem : public ProblemImpl {
   void factor() override {
     if (factored_) return;
     const double g = 1.0 - 1.0 / std::sqrt(2.0);
-    hipLaunchKernelGGL(rbc_factor, dim3(K_), dim3(NT), factor_lds(), stream, dv_, BM_, BL_, 1.0, desc_.dt * g, ops_);
+    hipLaunchKernelGGL(rbc_factor, dim3(K_), dim3(NT), factor_lds(), stream, dv_, BM_, BL_, 1.0, dt_ * g, ops_);
     SPS_CHECK_LAUNCH();
     factored_ = true;
   }
@@ -1420,6 +1512,7 @@ class RbcProblem : public ProblemImpl {
   }
 
   void initial_state(const double* grid, double* X) override {
+    if (cou_) throw Error(SPS_E_UNSUPPORTED, "Couette states are given as coefficients");
     SPS_REQUIRE(grid && X, "null argument");
     hipLaunchKernelGGL(rbc_init_x, dim3(N_), dim3(NT), 2 * fpad_size(desc_.nx) * sizeof(cplx), stream, dv_, grid, itmp_);
     SPS_CHECK_LAUNCH();
@@ -1428,6 +1521,7 @@ class RbcProblem : public ProblemImpl {
   }
 
   void initial_state_adjoint(const double* Xbar, double* grid) override {
+    if (cou_) throw Error(SPS_E_UNSUPPORTED, "Couette states are given as coefficients");
     SPS_REQUIRE(grid && Xbar, "null argument");
     hipLaunchKernelGGL(rbc_init_adj_z, dim3(K_), dim3(NT), 0, stream, dv_, reinterpret_cast<const cplx*>(Xbar), itmp_);
     SPS_CHECK_LAUNCH();
@@ -1556,7 +1650,7 @@ class RbcProblem : public ProblemImpl {
     a.nl = nl_;
     a.F0 = F0_;
     a.zg = zg;
-    a.dt = desc_.dt;
+    a.dt = dt_;
     a.g = 1.0 - 1.0 / std::sqrt(2.0);
     a.dl = 1.0 - 1.0 / (2.0 * a.g);
     a.mode = mode;
@@ -1568,6 +1662,10 @@ class RbcProblem : public ProblemImpl {
     SPS_CHECK_LAUNCH();
   }
   void launch_xf(const cplx* zg, hipStream_t s = nullptr) {
+    if (planes_) {
+      planes_->forward(zg, nl_, s ? s : stream);
+      return;
+    }
     XfArgs a{zg, nl_};
     hipLaunchKernelGGL(rbc_xfwd, dim3(Ngz_), dim3(NTX), xf_lds(), s ? s : stream, dv_, a);
     SPS_CHECK_LAUNCH();
@@ -1580,7 +1678,7 @@ class RbcProblem : public ProblemImpl {
     a.acc = acc_;
     a.Ybuf = Ybuf_;
     a.nlbar = nlbar_;
-    a.dt = desc_.dt;
+    a.dt = dt_;
     a.g = 1.0 - 1.0 / std::sqrt(2.0);
     a.dl = 1.0 - 1.0 / (2.0 * a.g);
     a.flags = flags;
@@ -1591,6 +1689,10 @@ class RbcProblem : public ProblemImpl {
     SPS_CHECK_LAUNCH();
   }
   void launch_xa(const cplx* zg) {
+    if (planes_) {
+      planes_->vjp(nlbar_, zg, zbar_, stream);
+      return;
+    }
     XaArgs a{nlbar_, zg, zbar_};
     hipLaunchKernelGGL(rbc_xadj, dim3(Ngz_), dim3(NTX), xa_lds(), stream, dv_, a);
     SPS_CHECK_LAUNCH();
@@ -1683,8 +1785,6 @@ class RbcProblem : public ProblemImpl {
         c[m] = (double)cosl((long double)m * 3.14159265358979323846264338327950288L / (2.0L * Ng));
       return c;
     };
-    std::vector<double> kx(K);
-    for (int k = 0; k < K; ++k) kx[k] = 2.0 * M_PI * k / desc_.lx;
     std::vector<double> gram((size_t)N * N);
     auto I = [](int j) { return (j % 2 == 0) ? 2.0 / (1.0 - (double)j * j) : 0.0; };
     for (int m = 0; m < N; ++m)
@@ -1699,7 +1799,13 @@ class RbcProblem : public ProblemImpl {
     dv_.Lx = desc_.lx;
     dv_.nu = nu_;
     dv_.ka = ka_;
-    dv_.kx = arena_.upload(kx, stream);
+    dv_.kx = arena_.upload(kxs_, stream);
+    dv_.cp = cp_;
+    dv_.bc0 = bc0_;
+    dv_.cost_scale = cost_scale_;
+    dv_.Kz = Kz_;
+    dv_.ncost = ncost_;
+    dv_.ckeep = ckeep_.empty() ? nullptr : arena_.upload(ckeep_, stream);
     dv_.cosz = arena_.upload(costab(Ngz), stream);
     dv_.cosz1 = arena_.upload(costab(Nz1), stream);
     dv_.twx = arena_.upload(twiddles(Ngx_), stream);
@@ -1712,7 +1818,7 @@ class RbcProblem : public ProblemImpl {
 
   void build_bands() {
     RbcHostBands hb;
-    rbc_host_bands(desc_, hb);
+    host_bands(N_, kxs_, nu_, ka_, cp_, hb);
     kl_ = hb.kl;
     ku_ = hb.ku;
     SPS_REQUIRE(kl_ + SPS_BLK <= SPS_TW && SPS_BLK + kl_ + ku_ <= SPS_GW, "band too wide for the block solver");
@@ -1773,9 +1879,12 @@ class RbcProblem : public ProblemImpl {
     seglen_ = std::min(ce, desc_.max_steps);
     seg_ = arena_.alloc<cplx>((size_t)2 * seglen_ * 2 * zsize_);
     const size_t fac_lds = factor_lds();
-    const std::pair<const void*, size_t> lds[] = {{(const void*)rbc_kfwd, kf_lds()}, {(const void*)rbc_kadj, ka_lds()},
-                                                  {(const void*)rbc_xfwd, xf_lds()}, {(const void*)rbc_xadj, xa_lds()},
-                                                  {(const void*)rbc_factor, fac_lds}};
+    std::vector<std::pair<const void*, size_t>> lds = {
+        {(const void*)rbc_kfwd, kf_lds()}, {(const void*)rbc_kadj, ka_lds()}, {(const void*)rbc_factor, fac_lds}};
+    if (!cou_) {
+      lds.push_back({(const void*)rbc_xfwd, xf_lds()});
+      lds.push_back({(const void*)rbc_xadj, xa_lds()});
+    }
     for (const auto& fl : lds) {
       SPS_REQUIRE(fl.second <= 160 * 1024, "problem too large for LDS");
       SPS_HIP(hipFuncSetAttribute(fl.first, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fl.second));
@@ -1785,7 +1894,12 @@ class RbcProblem : public ProblemImpl {
 
   sps_desc desc_;
   int K_, N_, S_, Ngx_, Ngz_, kl_ = 0, ku_ = 0;
-  double nu_, ka_;
+  double nu_, ka_, dt_ = 0.0, cp_ = 1.0, bc0_ = 1.0, cost_scale_ = 1.0;
+  int Kz_ = 1, ncost_ = 2;
+  bool cou_ = false;
+  std::vector<double> kxs_;
+  std::vector<unsigned char> ckeep_;
+  std::unique_ptr<CouettePlanes> planes_;
   RbcDev dv_{};
   DevArena arena_;
   double *BM_ = nullptr, *BL_ = nullptr, *ops_ = nullptr, *Jpart_ = nullptr;
@@ -1805,6 +1919,7 @@ class RbcProblem : public ProblemImpl {
 }  // namespace
 
 ProblemImpl* make_rbc(const sps_desc& d, hipStream_t s) { return new RbcProblem(d, s); }
+ProblemImpl* make_couette(const CouetteSpec& c, hipStream_t s) { return new RbcProblem(c, s); }
 
 }  // namespace sps
 

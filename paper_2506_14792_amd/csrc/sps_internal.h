@@ -139,6 +139,12 @@ ProblemImpl* make_ks(const sps_desc& d, hipStream_t s);
 ProblemImpl* make_sh_batch(int batch, const int* n, const double* r, double lx, double dt, int max_steps,
                            hipStream_t s);
 void sh_tuning(ProblemImpl* p, int* col_tile, int* row_tile, int* blocks, int* threads, double* tuned_ms);
+struct CouetteSpec {
+  int nx, ny, nz;
+  double lx, lz, re, dt;
+  int checkpoint_every, max_steps;
+};
+ProblemImpl* make_couette(const CouetteSpec& c, hipStream_t s);
 ProblemImpl* make_kolmo(int batch, int N, double Re, double drag, double dt, int max_steps, int closure,
                         int keep_history, hipStream_t s);
 void kolmo_set_params(ProblemImpl* p, const double* theta);

@@ -61,6 +61,9 @@ def lib():
         "sps_sh_tuning": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                          ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                          ctypes.POINTER(ctypes.c_double)]),
+        "sps_build_couette": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, _P,
+                                             ctypes.POINTER(_P)]),
         "sps_build_kolmo": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                            ctypes.c_double, ctypes.c_int,
                                            ctypes.c_int, ctypes.c_int, _P, ctypes.POINTER(_P)]),
@@ -234,6 +237,28 @@ class ShBatch(Problem):
         _check(lib().sps_sh_tuning(self._h, ct, rt, ctypes.byref(b), ctypes.byref(t), ctypes.byref(ms)))
         return {"col_tile": list(ct), "row_pairs": list(rt), "blocks": b.value, "threads": t.value,
                 "step_ms": ms.value}
+
+
+class Couette(Problem):
+    """3D plane Couette flow (nx x ny x nz: Fourier x Chebyshev x Fourier, periods lx, lz, walls
+    y = -1, 1 moving with -1, 1, Reynolds number Re), RK222 step dt with checkpoints; states per
+    mode k = m nz + n in the layout (u_par, v, u_perp, p, taus) of the library's header."""
+
+    def __init__(self, nx, ny, nz, lx=4.0 * np.pi, lz=2.0 * np.pi, Re=400.0, dt=0.01, checkpoint_every=100,
+                 max_steps=1, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self._stream = stream
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.K = (self.nx // 2) * self.nz
+        h = _P()
+        _check(lib().sps_build_couette(self.nx, self.ny, self.nz, float(lx), float(lz), float(Re), float(dt),
+                                       int(checkpoint_every), int(max_steps), ctypes.c_void_p(stream.cuda_stream),
+                                       ctypes.byref(h)))
+        self._h = h
+        self.n = int(lib().sps_state_size(h))
+        self.tape_id = 0
 
 
 class Kolmogorov(Problem):
