@@ -53,12 +53,12 @@ def measured_traffic():
     return t.get("hbm_bytes_per_launch")
 
 
-def stage_kernel_bytes(nx, nz):
+def stage_kernel_bytes(nx, nz, K=None):
     """Algorithmic HBM bytes of one launch of the per-wavenumber forward stage kernel
     (average of the two RK222 stages): each operand streamed once.
     Per wavenumber: LU factors (n*kl multipliers + n*(kl+ku+1) U entries + n pivots),
     state in/out, nonlinear terms in, stage-0 F out/in, six z-grid fields out."""
-    K, N = nx // 2, nz
+    K, N = (nx // 2 if K is None else K), nz
     S = 4 * N + 7
     Ngz = 3 * N // 2
     kl, ku = 7, 20
@@ -206,6 +206,61 @@ def sh_timing(reps=2):
             "oracle_cpu_gradient_s_extrapolated": ocpu}
 
 
+COU_CFG = dict(nx=128, ny=64, nz=64, Lx=4.0 * np.pi, Lz=2.0 * np.pi, Re=400.0, dt=0.01, nsteps=2000,
+               checkpoint_every=100, seed=0, energy=1e-6)
+
+
+def couette_timing():
+    """Differentiation configuration: 3D plane Couette flow 128 x 64 x 64 (Fourier x Chebyshev x
+    Fourier, Lx = 4 pi, Lz = 2 pi, walls y = -1, 1 moving -1, 1), Re = 400, RK222 dt = 0.01 to T = 20
+    (2000 steps), checkpoints every 100; the gradient of the energy gain E(T)/E(0) of a seeded
+    divergence-free perturbation of energy 1e-6 through the torch.autograd Functions (Step with
+    checkpoint-and-recompute, Cost).  Reports the gradient time and the per-mode stage kernel
+    (4096 systems of 263 unknowns: the banded solves in the HBM regime) against the roofline:
+    algorithmic bytes per launch as for the 2D kernel, times 4096 systems."""
+    import torch
+    import workloads as wl
+    import paper_2506_14792_amd as sps
+    from paper_2506_14792_amd import autograd as sa
+    c = COU_CFG
+    n = c["nsteps"]
+    G = sps.Couette(c["nx"], c["ny"], c["nz"], c["Lx"], c["Lz"], Re=c["Re"], dt=c["dt"],
+                    checkpoint_every=c["checkpoint_every"], max_steps=n)
+    uvw = wl.couette_perturbation(seed=c["seed"], Nx=c["nx"], Ny=c["ny"], Nz=c["nz"], Lx=c["Lx"], Lz=c["Lz"],
+                                  energy=c["energy"])
+    x0 = torch.from_numpy(G.state_from_velocity(uvw)).cuda()
+
+    def one():
+        x = x0.clone().requires_grad_(True)
+        J = sa.cost(sa.step(x, G, n), G) / sa.cost(x, G)
+        (g,) = torch.autograd.grad(J, x)
+        return J, g
+
+    G.factor()
+    one()
+    G.sync()
+    G.timer_enable(0, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, g = one()
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    G.sync()
+    launches, kern_ms = G.timer_read()
+    G.timer_enable(0, False)
+    K = (c["nx"] // 2) * c["nz"]
+    bytes_launch = stage_kernel_bytes(0, c["ny"], K=K)
+    avg = kern_ms / max(launches, 1)
+    achieved = bytes_launch / (avg * 1e-3) / 1e9
+    return {"workload": "plane Couette 3D 128x64x64 (Fourier x Chebyshev x Fourier), Re=400, RK222 dt=0.01, "
+                        "2000 steps, checkpoint every 100, energy-gain gradient through torch.autograd",
+            "gpu_gradient_s": t, "timesteps_per_s": 3 * n / t, "forward_adjoint_timesteps_per_s": 2 * n / t,
+            "energy_gain": float(J.item()), "gradient_norm": float(g.norm().item()),
+            "stage_kernel": {"kernel": "rbc_kfwd on 4096 Couette modes (transforms in y, RHS, banded LU solve)",
+                             "bytes_per_launch": bytes_launch, "avg_launch_ms": avg, "launches_timed": launches,
+                             "achieved_GBps": achieved, "frac": achieved / HBM_PEAK_GBS}}
+
+
 KOL_CFG = dict(n_fine=512, factor=8, Re=1000.0, drag=0.1, dt=0.002, rollout=200, ntrain=4, ntest=2,
                spinup=16000, nsnap=600, batch=16, iters=40, lr=1e-3, seed=100)
 
@@ -300,7 +355,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--copy-calibration", action="store_true")
-    ap.add_argument("--only", choices=["ks", "sh", "closure"], default=None,
+    ap.add_argument("--only", choices=["ks", "sh", "closure", "couette"], default=None,
                     help="run one secondary configuration alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -313,7 +368,7 @@ def main():
     if args.only:
         import torch
         torch.cuda.set_device(0)
-        fn = {"ks": ks_timing, "sh": sh_timing, "closure": kolmo_timing}[args.only]
+        fn = {"ks": ks_timing, "sh": sh_timing, "closure": kolmo_timing, "couette": couette_timing}[args.only]
         print(json.dumps({args.only: fn()}))
         return
 
@@ -388,6 +443,7 @@ def main():
     ks = ks_timing()
     sh = sh_timing()
     kol = kolmo_timing()
+    cou = couette_timing()
     cpu = None if args.no_cpu else cpu_baseline(args.cpu_steps)
     out = {
         "metric": METRIC,
@@ -420,6 +476,7 @@ def main():
         "ks_config": ks,
         "sh_batched_config": sh,
         "closure_config": kol,
+        "couette_autograd_config": cou,
         "J": J.item(),
     }
     print(json.dumps(out))

@@ -259,6 +259,26 @@ class Couette(Problem):
         self._h = h
         self.n = int(lib().sps_state_size(h))
         self.tape_id = 0
+        self.lx, self.lz = float(lx), float(lz)
+
+    def state_from_velocity(self, c):
+        """Input preparation on the host: (K, 3, ny) complex Chebyshev coefficients of (u, v, w)
+        per mode -> a float64 state in the library layout (u_par, v, u_perp; p and taus zero)."""
+        K, N = self.K, self.ny
+        c = np.asarray(c).reshape(K, 3, N)
+        m = np.repeat(np.arange(self.nx // 2), self.nz)
+        n = np.tile(np.arange(self.nz), self.nx // 2)
+        kx = 2.0 * np.pi * m / self.lx
+        kz = 2.0 * np.pi * np.where(n < self.nz // 2, n, n - self.nz) / self.lz
+        kh = np.hypot(kx, kz)
+        safe = np.where(kh > 0, kh, 1.0)
+        ex = np.where(kh > 0, kx / safe, 1.0)[:, None]
+        ez = np.where(kh > 0, kz / safe, 0.0)[:, None]
+        X = np.zeros((K, 4 * N + 7), complex)
+        X[:, :N] = ex * c[:, 0] + ez * c[:, 2]
+        X[:, N:2 * N] = c[:, 1]
+        X[:, 2 * N:3 * N] = -ez * c[:, 0] + ex * c[:, 2]
+        return np.ascontiguousarray(X).view(np.float64).ravel()
 
 
 class Kolmogorov(Problem):
