@@ -40,89 +40,93 @@ __host__ __device__ inline int blk_ops_size(int n) {
   return ((blk_count(n) * (SPS_TW * SPS_TS + SPS_BLK * SPS_GS) + 3) / 4) * 4;
 }
 
-// x = A^{-1} b for one real vector b (element x at b[2*x], n + SPS_PAD entries, zero tail), one wave.
-__device__ inline void blk_solve_part(const double* ops, int nblk, double* b) {
+// The four sweeps over a range of blocks [t0, t1), with the operators of that range at T (T
+// blocks t0 .. t1-1) or G (G blocks t0 .. t1-1): forward L sweep (t ascending) and U sweep
+// (t descending), transposed U^T sweep (t ascending) and L^T sweep (t descending).  One wave.
+// L sweep: output r = lane/2 (32 lanes), half h = lane&1 sums columns 8h .. 8h+7
+__device__ inline void blk_L_range(const double* T, int t0, int t1, double* b) {
   const int lane = lane_id();
-  const double* T = ops;
-  const double* G = ops + nblk * SPS_TW * SPS_TS;
-  // L sweep: output r = lane/2 (32 lanes), half h = lane&1 sums columns 8h .. 8h+7
-  {
-    const int r = (lane >> 1) & (SPS_TW - 1), h = lane & 1;
-    for (int t = 0; t < nblk; ++t) {
-      const double* v = b + 2 * (t * SPS_BLK + 8 * h);
-      const double* Tr = T + (t * SPS_TW + r) * SPS_TS + 8 * h;
-      double a0 = 0.0, a1 = 0.0;
+  const int r = (lane >> 1) & (SPS_TW - 1), h = lane & 1;
+  for (int t = t0; t < t1; ++t) {
+    const double* v = b + 2 * (t * SPS_BLK + 8 * h);
+    const double* Tr = T + ((t - t0) * SPS_TW + r) * SPS_TS + 8 * h;
+    double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-      for (int c = 0; c < 8; c += 2) {
-        a0 = fma(Tr[c], v[2 * (c)], a0);
-        a1 = fma(Tr[c + 1], v[2 * (c + 1)], a1);
-      }
-      double s = a0 + a1;
-      s += dpp_xor1(s);
-      if (lane < 2 * SPS_TW && h == 0) b[2 * (t * SPS_BLK + r)] = s;
+    for (int c = 0; c < 8; c += 2) {
+      a0 = fma(Tr[c], v[2 * (c)], a0);
+      a1 = fma(Tr[c + 1], v[2 * (c + 1)], a1);
     }
-  }
-  // U sweep: output i = lane/4 (32 lanes), quarter q = lane&3 sums columns 9q .. 9q+8
-  {
-    const int i = (lane >> 2) & (SPS_BLK - 1), q = lane & 3;
-    for (int t = nblk - 1; t >= 0; --t) {
-      const double* v = b + 2 * (t * SPS_BLK + 9 * q);
-      const double* Gr = G + (t * SPS_BLK + i) * SPS_GS + 9 * q;
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-#pragma unroll
-      for (int c = 0; c < 9; c += 3) {
-        a0 = fma(Gr[c], v[2 * (c)], a0);
-        a1 = fma(Gr[c + 1], v[2 * (c + 1)], a1);
-        a2 = fma(Gr[c + 2], v[2 * (c + 2)], a2);
-      }
-      double s = (a0 + a1) + a2;
-      s += dpp_xor1(s);
-      s += dpp_xor2(s);
-      if (lane < 4 * SPS_BLK && q == 0) b[2 * (t * SPS_BLK + i)] = s;
-    }
+    double s = a0 + a1;
+    s += dpp_xor1(s);
+    if (lane < 2 * SPS_TW && h == 0) b[2 * (t * SPS_BLK + r)] = s;
   }
 }
-
+// U sweep: output i = lane/4 (32 lanes), quarter q = lane&3 sums columns 9q .. 9q+8
+__device__ inline void blk_U_range(const double* G, int t0, int t1, double* b) {
+  const int lane = lane_id();
+  const int i = (lane >> 2) & (SPS_BLK - 1), q = lane & 3;
+  for (int t = t1 - 1; t >= t0; --t) {
+    const double* v = b + 2 * (t * SPS_BLK + 9 * q);
+    const double* Gr = G + ((t - t0) * SPS_BLK + i) * SPS_GS + 9 * q;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 9; c += 3) {
+      a0 = fma(Gr[c], v[2 * (c)], a0);
+      a1 = fma(Gr[c + 1], v[2 * (c + 1)], a1);
+      a2 = fma(Gr[c + 2], v[2 * (c + 2)], a2);
+    }
+    double s = (a0 + a1) + a2;
+    s += dpp_xor1(s);
+    s += dpp_xor2(s);
+    if (lane < 4 * SPS_BLK && q == 0) b[2 * (t * SPS_BLK + i)] = s;
+  }
+}
+// U^T sweep: output c = lane (36 lanes) sums the BLK rows of its column
+__device__ inline void blk_Ut_range(const double* G, int t0, int t1, double* b) {
+  const int lane = lane_id();
+  const int c = (lane < SPS_GW) ? lane : SPS_GW - 1;
+  for (int t = t0; t < t1; ++t) {
+    const double* v = b + 2 * (t * SPS_BLK);
+    const double* Gc = G + (t - t0) * SPS_BLK * SPS_GS + c;
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+    for (int i = 0; i < SPS_BLK; i += 2) {
+      a0 = fma(Gc[i * SPS_GS], v[2 * (i)], a0);
+      a1 = fma(Gc[(i + 1) * SPS_GS], v[2 * (i + 1)], a1);
+    }
+    const double keep = (c >= SPS_BLK) ? v[2 * (c)] : 0.0;
+    if (lane < SPS_GW) b[2 * (t * SPS_BLK + c)] = keep + (a0 + a1);
+  }
+}
+// L^T sweep: output c = lane/2 (32 lanes), half h sums rows 8h .. 8h+7 of column c
+__device__ inline void blk_Lt_range(const double* T, int t0, int t1, double* b) {
+  const int lane = lane_id();
+  const int c = (lane >> 1) & (SPS_TW - 1), h = lane & 1;
+  for (int t = t1 - 1; t >= t0; --t) {
+    const double* v = b + 2 * (t * SPS_BLK + 8 * h);
+    const double* Tc = T + ((t - t0) * SPS_TW + 8 * h) * SPS_TS + c;
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+    for (int r = 0; r < 8; r += 2) {
+      a0 = fma(Tc[r * SPS_TS], v[2 * (r)], a0);
+      a1 = fma(Tc[(r + 1) * SPS_TS], v[2 * (r + 1)], a1);
+    }
+    double s = a0 + a1;
+    s += dpp_xor1(s);
+    if (lane < 2 * SPS_TW && h == 0) b[2 * (t * SPS_BLK + c)] = s;
+  }
+}
+// x = A^{-1} b for one real vector b (element x at b[2*x], n + SPS_PAD entries, zero tail), one
+// wave, all operators at ops.
+__device__ inline void blk_solve_part(const double* ops, int nblk, double* b) {
+  blk_L_range(ops, 0, nblk, b);
+  blk_U_range(ops + nblk * SPS_TW * SPS_TS, 0, nblk, b);
+}
 // x = A^{-T} b for one real vector b (element x at b[2*x], zero tail), one wave.
 __device__ inline void blk_solve_t_part(const double* ops, int nblk, double* b) {
-  const int lane = lane_id();
-  const double* T = ops;
-  const double* G = ops + nblk * SPS_TW * SPS_TS;
-  // U^T sweep: output c = lane (36 lanes) sums the BLK rows of its column
-  {
-    const int c = (lane < SPS_GW) ? lane : SPS_GW - 1;
-    for (int t = 0; t < nblk; ++t) {
-      const double* v = b + 2 * (t * SPS_BLK);
-      const double* Gc = G + t * SPS_BLK * SPS_GS + c;
-      double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-      for (int i = 0; i < SPS_BLK; i += 2) {
-        a0 = fma(Gc[i * SPS_GS], v[2 * (i)], a0);
-        a1 = fma(Gc[(i + 1) * SPS_GS], v[2 * (i + 1)], a1);
-      }
-      const double keep = (c >= SPS_BLK) ? v[2 * (c)] : 0.0;
-      if (lane < SPS_GW) b[2 * (t * SPS_BLK + c)] = keep + (a0 + a1);
-    }
-  }
-  // L^T sweep: output c = lane/2 (32 lanes), half h sums rows 8h .. 8h+7 of column c
-  {
-    const int c = (lane >> 1) & (SPS_TW - 1), h = lane & 1;
-    for (int t = nblk - 1; t >= 0; --t) {
-      const double* v = b + 2 * (t * SPS_BLK + 8 * h);
-      const double* Tc = T + (t * SPS_TW + 8 * h) * SPS_TS + c;
-      double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-      for (int r = 0; r < 8; r += 2) {
-        a0 = fma(Tc[r * SPS_TS], v[2 * (r)], a0);
-        a1 = fma(Tc[(r + 1) * SPS_TS], v[2 * (r + 1)], a1);
-      }
-      double s = a0 + a1;
-      s += dpp_xor1(s);
-      if (lane < 2 * SPS_TW && h == 0) b[2 * (t * SPS_BLK + c)] = s;
-    }
-  }
+  blk_Ut_range(ops + nblk * SPS_TW * SPS_TS, 0, nblk, b);
+  blk_Lt_range(ops, 0, nblk, b);
 }
-
 // One system's block operators are brought into LDS in two steps so that their memory
 // latency overlaps other work: ops_issue() starts all global loads of this thread's share
 // into registers, ops_store() writes them into LDS once the destination is free.

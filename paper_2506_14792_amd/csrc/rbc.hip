@@ -492,6 +492,66 @@ __device__ void rbc_solve_staged(const RbcDev& d, const OpsRegs& regs, double* o
   __syncthreads();
 }
 
+// The same solve with the block operators streamed from global memory through two LDS buffers
+// of SPS_CHUNK blocks: waves 0 and 1 run the sweeps over chunk q while the other waves copy
+// chunk q + 1 (for launches with many more systems than CUs: no register prefetch and a small
+// LDS footprint, so several blocks share a CU).  Block-wide; buf holds 2 * SOLVE_CHUNK_D doubles.
+constexpr int SPS_CHUNK = 8;
+constexpr int SOLVE_CHUNK_D = SPS_CHUNK * SPS_BLK * SPS_GS;   // >= SPS_CHUNK * SPS_TW * SPS_TS
+__device__ void rbc_solve_streamed(const RbcDev& d, const double* gops, double* buf, cplx* vA, bool transposed) {
+  const int nblk = blk_count(d.n), nch = (nblk + SPS_CHUNK - 1) / SPS_CHUNK, Q = 2 * nch;
+  const double* Tg = gops;
+  const double* Gg = gops + nblk * SPS_TW * SPS_TS;
+  const int tid = threadIdx.x, wave = tid >> 6;
+  // chunk q: the first sweep (L, or U^T) runs over ascending chunks, the second (U, or L^T)
+  // over descending ones; the forward solve reads T then G, the transposed G then T
+  auto range = [&](int q, int* t0, int* t1, bool* useT) {
+    const bool first = q < nch;
+    const int c = first ? q : 2 * nch - 1 - q;
+    *t0 = c * SPS_CHUNK;
+    *t1 = min(nblk, *t0 + SPS_CHUNK);
+    *useT = (first != transposed);
+  };
+  auto copy = [&](int q, double* dst, int i0, int step) {
+    int t0, t1;
+    bool useT;
+    range(q, &t0, &t1, &useT);
+    const int per = useT ? SPS_TW * SPS_TS : SPS_BLK * SPS_GS;
+    const double2* src = reinterpret_cast<const double2*>((useT ? Tg : Gg) + (size_t)t0 * per);
+    double2* d2 = reinterpret_cast<double2*>(dst);
+    const int h = (t1 - t0) * per / 2;
+    for (int e = i0; e < h; e += step) d2[e] = src[e];
+  };
+  copy(0, buf, tid, blockDim.x);
+  __syncthreads();
+  for (int q = 0; q < Q; ++q) {
+    double* cur = buf + (q & 1) * SOLVE_CHUNK_D;
+    if (wave >= 2) {
+      if (q + 1 < Q) copy(q + 1, buf + ((q + 1) & 1) * SOLVE_CHUNK_D, tid - 2 * SPS_WAVE, blockDim.x - 2 * SPS_WAVE);
+    } else {
+      int t0, t1;
+      bool useT;
+      range(q, &t0, &t1, &useT);
+      double* b = reinterpret_cast<double*>(vA) + wave;
+      if (!transposed) {
+        if (useT) blk_L_range(cur, t0, t1, b);
+        else blk_U_range(cur, t0, t1, b);
+      } else {
+        if (useT) blk_Lt_range(cur, t0, t1, b);
+        else blk_Ut_range(cur, t0, t1, b);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <bool STREAM>
+__device__ __forceinline__ void rbc_solve(const RbcDev& d, int k, const OpsRegs& regs, double* lds, cplx* vA,
+                                          bool transposed) {
+  if (STREAM) rbc_solve_streamed(d, d.ops + (size_t)k * d.opsize, lds, vA, transposed);
+  else rbc_solve_staged(d, regs, lds, vA, transposed);
+}
+
 // ---------------------------------------------------------------------------- per-wavenumber forward kernel
 enum KfMode { KF_ZGRID = 0, KF_STAGE1 = 1, KF_STAGE2 = 2, KF_EVALF = 3, KF_SOLVE = 4 };
 
@@ -509,6 +569,7 @@ struct KfArgs {
 // LDS: vA, vB (S complex each) persist; the rest is a union reused by the phases
 // (transforms and right-hand side | block operators of the solve | output transforms).
 // One entry of every length-S vector per thread (S + SPS_PAD <= NTK).
+template <bool STREAM>
 __global__ void __launch_bounds__(NTK) rbc_kfwd(RbcDev d, KfArgs a) {
   extern __shared__ double smem_d[];
   cplx* sm = reinterpret_cast<cplx*>(smem_d);
@@ -542,7 +603,7 @@ __global__ void __launch_bounds__(NTK) rbc_kfwd(RbcDev d, KfArgs a) {
   OpsRegs opsr;
   MapRegs mr;
   if (stage || mode == KF_SOLVE) {
-    ops_issue(d.ops + (size_t)k * d.opsize, d.opsize, opsr);
+    if (!STREAM) ops_issue(d.ops + (size_t)k * d.opsize, d.opsize, opsr);
     load_maps(d, mr);
   }
   if (stage) {
@@ -625,7 +686,7 @@ __global__ void __launch_bounds__(NTK) rbc_kfwd(RbcDev d, KfArgs a) {
     __syncthreads();
   } else {
     rbc_gather(d, mr, rr, vA);
-    rbc_solve_staged(d, opsr, reinterpret_cast<double*>(un), vA, false);
+    rbc_solve<STREAM>(d, k, opsr, reinterpret_cast<double*>(un), vA, false);
     rbc_scatter(d, mr, vA, vB, vA);   // vA <- new state (ABI slots)
     if (tid < S) {
       const cplx v = vA[tid];
@@ -898,6 +959,7 @@ __device__ void g_to_nlbar(const RbcDev& d, const KaArgs& a, int k, const double
 
 // LDS: vA, vB (S complex each) persist; the rest is a union of phase buffers and the
 // staged block operators.  One entry of every length-S vector per thread.
+template <bool STREAM>
 __global__ void __launch_bounds__(NTK) rbc_kadj(RbcDev d, KaArgs a) {
   extern __shared__ double smem_d[];
   cplx* sm = reinterpret_cast<cplx*>(smem_d);
@@ -934,7 +996,7 @@ __global__ void __launch_bounds__(NTK) rbc_kadj(RbcDev d, KaArgs a) {
   OpsRegs opsr;
   MapRegs mr;
   if (fl & (KA_A | KA_B | KA_SOLVE_T)) {
-    ops_issue(d.ops + (size_t)k * d.opsize, d.opsize, opsr);
+    if (!STREAM) ops_issue(d.ops + (size_t)k * d.opsize, d.opsize, opsr);
     load_maps(d, mr);
   }
   if (tid < 4 * Ngz) ct[tid] = cosr;
@@ -942,7 +1004,7 @@ __global__ void __launch_bounds__(NTK) rbc_kadj(RbcDev d, KaArgs a) {
     if (sl) xbar[tid] = xin;
     __syncthreads();
     rbc_gather_h(d, mr, xbar, vA);
-    rbc_solve_staged(d, opsr, ops, vA, true);
+    rbc_solve<STREAM>(d, k, opsr, ops, vA, true);
     rbc_scatter_h(d, mr, vA, vB);
     if (sl) a.Xb_out[ks] = vB[tid];
     return;
@@ -968,7 +1030,7 @@ __global__ void __launch_bounds__(NTK) rbc_kadj(RbcDev d, KaArgs a) {
   if (fl & KA_A) {
     // Y2 = A^{-H} xbar;  F cotangent of the stage-1 state: dt (1 - delta) Y2
     rbc_gather_h(d, mr, xbar, vA);
-    rbc_solve_staged(d, opsr, ops, vA, true);
+    rbc_solve<STREAM>(d, k, opsr, ops, vA, true);
     rbc_scatter_h(d, mr, vA, vB);
     if (tid < 4 * Ngz) ct[tid] = cosr;
     if (sl) {
@@ -992,7 +1054,7 @@ __global__ void __launch_bounds__(NTK) rbc_kadj(RbcDev d, KaArgs a) {
     }
     __syncthreads();
     rbc_gather_h(d, mr, xbar, vA);
-    rbc_solve_staged(d, opsr, ops, vA, true);
+    rbc_solve<STREAM>(d, k, opsr, ops, vA, true);
     rbc_scatter_h(d, mr, vA, vB);     // vB = Y1
     if (tid < 4 * Ngz) ct[tid] = cosr;
     if (sl) {
@@ -1426,6 +1488,7 @@ class RbcProblem : public ProblemImpl {
   }
 
   void init() {
+    stream_solve_ = K_ > 1024;
     build_tables();
     build_bands();
     alloc_work();
@@ -1579,7 +1642,16 @@ class RbcProblem : public ProblemImpl {
  private:
   // ----------------------------------------------------------------- launches
   size_t factor_lds() const { return (size_t)(2 * kl_ + ku_ + 1) * S_ * sizeof(double) + sizeof(int) * S_; }
-  size_t ops_bytes() const { return sizeof(double) * (size_t)blk_ops_size(S_); }
+  // staged solves hold a system's block operators in LDS; streamed ones two chunk buffers
+  size_t ops_bytes() const {
+    return stream_solve_ ? sizeof(double) * 2 * (size_t)SOLVE_CHUNK_D : sizeof(double) * (size_t)blk_ops_size(S_);
+  }
+  // launches with many more systems than CUs stream the operators (several blocks per CU);
+  // smaller ones stage them whole (one block per CU, shortest dependent chain)
+  typedef void (*KfFn)(RbcDev, KfArgs);
+  typedef void (*KaFn)(RbcDev, KaArgs);
+  KfFn kfwd_fn() const { return stream_solve_ ? rbc_kfwd<true> : rbc_kfwd<false>; }
+  KaFn kadj_fn() const { return stream_solve_ ? rbc_kadj<true> : rbc_kadj<false>; }
   size_t kf_lds() const {
     const size_t pre = sizeof(cplx) * (3 * S_ + 6 * half_nodes(Ngz_) + 6 * N_) + sizeof(double) * 4 * Ngz_;
     const size_t post = sizeof(double) * 4 * Ngz_ + sizeof(cplx) * 3 * N_;
@@ -1656,9 +1728,9 @@ class RbcProblem : public ProblemImpl {
     a.mode = mode;
     hipEvent_t e0, e1;
     if ((mode == KF_STAGE1 || mode == KF_STAGE2) && s == stream && !capturing_ && timer_.take(&e0, &e1))
-      hipExtLaunchKernelGGL(rbc_kfwd, dim3(K_), dim3(NTK), kf_lds(), s, e0, e1, 0, dv_, a);
+      hipExtLaunchKernelGGL(kfwd_fn(), dim3(K_), dim3(NTK), kf_lds(), s, e0, e1, 0, dv_, a);
     else
-      hipLaunchKernelGGL(rbc_kfwd, dim3(K_), dim3(NTK), kf_lds(), s, dv_, a);
+      hipLaunchKernelGGL(kfwd_fn(), dim3(K_), dim3(NTK), kf_lds(), s, dv_, a);
     SPS_CHECK_LAUNCH();
   }
   void launch_xf(const cplx* zg, hipStream_t s = nullptr) {
@@ -1685,7 +1757,7 @@ class RbcProblem : public ProblemImpl {
     return a;
   }
   void launch_ka(const KaArgs& a) {
-    hipLaunchKernelGGL(rbc_kadj, dim3(K_), dim3(NTK), ka_lds(), stream, dv_, a);
+    hipLaunchKernelGGL(kadj_fn(), dim3(K_), dim3(NTK), ka_lds(), stream, dv_, a);
     SPS_CHECK_LAUNCH();
   }
   void launch_xa(const cplx* zg) {
@@ -1880,7 +1952,7 @@ class RbcProblem : public ProblemImpl {
     seg_ = arena_.alloc<cplx>((size_t)2 * seglen_ * 2 * zsize_);
     const size_t fac_lds = factor_lds();
     std::vector<std::pair<const void*, size_t>> lds = {
-        {(const void*)rbc_kfwd, kf_lds()}, {(const void*)rbc_kadj, ka_lds()}, {(const void*)rbc_factor, fac_lds}};
+        {(const void*)kfwd_fn(), kf_lds()}, {(const void*)kadj_fn(), ka_lds()}, {(const void*)rbc_factor, fac_lds}};
     if (!cou_) {
       lds.push_back({(const void*)rbc_xfwd, xf_lds()});
       lds.push_back({(const void*)rbc_xadj, xa_lds()});
@@ -1896,7 +1968,7 @@ class RbcProblem : public ProblemImpl {
   int K_, N_, S_, Ngx_, Ngz_, kl_ = 0, ku_ = 0;
   double nu_, ka_, dt_ = 0.0, cp_ = 1.0, bc0_ = 1.0, cost_scale_ = 1.0;
   int Kz_ = 1, ncost_ = 2;
-  bool cou_ = false;
+  bool cou_ = false, stream_solve_ = false;
   std::vector<double> kxs_;
   std::vector<unsigned char> ckeep_;
   std::unique_ptr<CouettePlanes> planes_;

@@ -74,6 +74,8 @@ def state(P, seed, energy):
 
 
 CFGS = [dict(Nx=8, Ny=12, Nz=8, Lx=4.0 * np.pi, Lz=2.0 * np.pi), dict(Nx=24, Ny=16, Nz=12, Lx=3.0, Lz=2.5)]
+# more than 1024 modes: the per-mode kernels stream their block operators through LDS
+BIG = dict(Nx=64, Ny=16, Nz=48, Lx=4.0 * np.pi, Lz=2.0 * np.pi)
 
 
 @pytest.mark.parametrize("cfg", CFGS, ids=["8x12x8", "24x16x12"])
@@ -95,7 +97,7 @@ def test_couette_explicit_term_and_solve(cfg):
     assert ef <= 1e-11 and ev <= 1e-11
 
 
-@pytest.mark.parametrize("cfg", CFGS, ids=["8x12x8", "24x16x12"])
+@pytest.mark.parametrize("cfg", CFGS + [BIG], ids=["8x12x8", "24x16x12", "64x16x48-streamed"])
 def test_couette_forward_and_gradient(cfg):
     print(f"couette gradient {cfg}", flush=True)
     P = Couette(Re=400.0, **cfg)
