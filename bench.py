@@ -355,6 +355,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--skip-extra", action="store_true",
+                    help="only the headline configuration (for counter and trace runs)")
     ap.add_argument("--only", choices=["ks", "sh", "closure", "couette"], default=None,
                     help="run one secondary configuration alone and print its JSON (for profiling)")
     args = ap.parse_args()
@@ -440,10 +442,12 @@ def main():
     G.sync()
     graph_sec = (t7 - t6) / args.steps
     traffic = measured_traffic()
-    ks = ks_timing()
-    sh = sh_timing()
-    kol = kolmo_timing()
-    cou = couette_timing()
+    ks = sh = kol = cou = None
+    if not args.skip_extra:
+        ks = ks_timing()
+        sh = sh_timing()
+        kol = kolmo_timing()
+        cou = couette_timing()
     cpu = None if args.no_cpu else cpu_baseline(args.cpu_steps)
     out = {
         "metric": METRIC,
