@@ -135,7 +135,24 @@ def test_kolmo_snapshots_and_ring_history():
             assert rel(got, ref) <= 1e-11
 
 
-@pytest.mark.parametrize("N", [32, 96], ids=["32", "96"])
+def test_kolmo_fine_512_steps_full_size():
+    """The fine solver of the closure configuration at its full size (512^2 modes, 768^2 padded
+    grid, drag 0.1, step 0.00025, three-state ring): three steps against the oracle."""
+    print("kolmo fine 512", flush=True)
+    N, dt, n = 512, 0.00025, 3
+    c0 = workloads.kolmo_vorticity(seed=4, N=N, batch=1)
+    G = sps.Kolmogorov(1, N, Re=1000.0, dt=dt, max_steps=1, keep_history=False, drag=0.1)
+    X0 = to_dev(list(c0))
+    XN = torch.zeros_like(X0)
+    G.forward(X0, n, XN=XN)
+    P = Kolmogorov(N, Re=1000.0, drag=0.1)
+    ref, _ = imex.sbdf_forward(P, c0[0].reshape(-1, 1), dt, n)
+    e = rel(from_dev(XN, 1, N)[0], ref.reshape(N, N // 2))
+    print(f"  XN rel {e:.2e}", flush=True)
+    assert e <= 1e-11
+
+
+@pytest.mark.parametrize("N", [32, 64, 96], ids=["32", "64", "96"])
 def test_kolmo_closure_rollout(N):
     print(f"kolmo closure N={N}", flush=True)
     B, dt, n = 2, 0.01, 3
