@@ -53,6 +53,13 @@ __device__ __forceinline__ int nb(int p, int t, int H, int W) {
   return yy * W + xx;
 }
 __device__ __forceinline__ int nb_t(int p, int t, int H, int W) { return nb(p, 8 - t, H, W); }   // (y - dy, x - dx)
+// neighbour (y + dy, x + dx) of the pixel at row y, column x (periodic)
+__device__ __forceinline__ int nb_yx(int y, int x, int dy, int dx, int H, int W) {
+  int yy = y + dy, xx = x + dx;
+  yy += (yy < 0) ? H : (yy >= H ? -H : 0);
+  xx += (xx < 0) ? W : (xx >= W ? -W : 0);
+  return yy * W + xx;
+}
 __device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_df(float z) {
   return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
@@ -89,12 +96,25 @@ __global__ void __launch_bounds__(NTC) cnn_l1(CnnDev d, const double* x) {
 #pragma unroll
   for (int t = 0; t < 9; ++t) v[t] = (float)(__bf16)(float)x[(long long)b * HW + nb(p, t, d.H, d.W)];
   d.a0[g] = (__bf16)v[4];
-  for (int c = 0; c < CH; ++c) {
-    float z = d.b1[c];
+  // a pixel's 32 channels are contiguous: 16-byte stores
+  float4* zo = reinterpret_cast<float4*>(d.z1 + (long long)g * CH);
+  bf16x8* ao = reinterpret_cast<bf16x8*>(d.a1 + (long long)g * CH);
 #pragma unroll
-    for (int t = 0; t < 9; ++t) z = fmaf(d.w1[c * 9 + t], v[t], z);
-    d.z1[(long long)g * CH + c] = z;
-    d.a1[(long long)g * CH + c] = (__bf16)gelu_f(z);
+  for (int c8 = 0; c8 < CH; c8 += 8) {
+    float z[8];
+    bf16x8 a;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int c = c8 + j;
+      float acc = d.b1[c];
+#pragma unroll
+      for (int t = 0; t < 9; ++t) acc = fmaf(d.w1[c * 9 + t], v[t], acc);
+      z[j] = acc;
+      a[j] = (__bf16)gelu_f(acc);
+    }
+    zo[c8 / 4] = make_float4(z[0], z[1], z[2], z[3]);
+    zo[c8 / 4 + 1] = make_float4(z[4], z[5], z[6], z[7]);
+    ao[c8 / 8] = a;
   }
 }
 
@@ -139,9 +159,13 @@ __global__ void __launch_bounds__(NTC) cnn_l3(CnnDev d, double* y, double scale,
   const int b = g / HW, p = g - b * HW;
   float s = d.b3[0];
   for (int t = 0; t < 9; ++t) {
-    const __bf16* a = d.a2 + ((long long)b * HW + nb(p, t, d.H, d.W)) * CH;
+    const bf16x8* a8 = reinterpret_cast<const bf16x8*>(d.a2 + ((long long)b * HW + nb(p, t, d.H, d.W)) * CH);
 #pragma unroll
-    for (int c = 0; c < CH; ++c) s = fmaf(d.w3[c * 9 + t], (float)a[c], s);
+    for (int c8 = 0; c8 < CH / 8; ++c8) {
+      const bf16x8 a = a8[c8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) s = fmaf(d.w3[(c8 * 8 + j) * 9 + t], (float)a[j], s);
+    }
   }
   const double v = scale * (double)s;
   y[g] = accumulate ? y[g] + v : v;
@@ -157,12 +181,22 @@ __global__ void __launch_bounds__(NTC) cnn_l3_back(CnnDev d, const double* yb) {
   float ys[9];
 #pragma unroll
   for (int t = 0; t < 9; ++t) ys[t] = (float)yb[(long long)b * HW + nb_t(p, t, d.H, d.W)];
-  for (int c = 0; c < CH; ++c) {
-    float s = 0.f;
+  const float4* zi = reinterpret_cast<const float4*>(d.z2 + (long long)g * CH);
+  float4* go = reinterpret_cast<float4*>(d.g2 + (long long)g * CH);
 #pragma unroll
-    for (int t = 0; t < 9; ++t) s = fmaf(d.w3[c * 9 + t], ys[t], s);
-    const long long o = (long long)g * CH + c;
-    d.g2[o] = s * gelu_df(d.z2[o]);
+  for (int c4 = 0; c4 < CH / 4; ++c4) {
+    const float4 z = zi[c4];
+    const float zz[4] = {z.x, z.y, z.z, z.w};
+    float r[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = 4 * c4 + j;
+      float s = 0.f;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) s = fmaf(d.w3[c * 9 + t], ys[t], s);
+      r[j] = s * gelu_df(zz[j]);
+    }
+    go[c4] = make_float4(r[0], r[1], r[2], r[3]);
   }
 }
 
@@ -181,11 +215,18 @@ __global__ void __launch_bounds__(NTC) cnn_l2_back_input(CnnDev d) {
   const float* G = d.g2 + (long long)b * HW * CH;
   f32x16 acc = {};
   for (int t = 0; t < 9; ++t) {
-    const float* Gt = G + (long long)nb_t(p0 + row, t, d.H, d.W) * CH;
-#pragma unroll 4
-    for (int c2 = 0; c2 < CH; c2 += 2) {
-      const int co = c2 + half;
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(Gt[co], w[(t * CH + co) * CH + row], acc, 0, 0, 0);
+    // 16-byte loads: lane (pixel row, half) holds channels 8j + 4 half .. 8j + 4 half + 3, and
+    // each of the four MFMAs pairs channel 8j + m (half 0) with 8j + 4 + m (half 1)
+    const float4* Gt = reinterpret_cast<const float4*>(G + (long long)nb_t(p0 + row, t, d.H, d.W) * CH);
+#pragma unroll
+    for (int j = 0; j < CH / 8; ++j) {
+      const float4 q = Gt[2 * j + half];
+      const float qa[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int co = 8 * j + 4 * half + m;
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(qa[m], w[(t * CH + co) * CH + row], acc, 0, 0, 0);
+      }
     }
   }
 #pragma unroll
@@ -209,16 +250,27 @@ __global__ void __launch_bounds__(256) cnn_l2_back_weight(CnnDev d, double* acc2
   const int total = d.B * HW;
   const int row = lane & 31, half = lane >> 5;
   f32x16 acc = {};
+  // this lane's pixel q = q0 + k + half, tracked as (image, row, column) without divisions
+  const int dy = t / 3 - 1, dx = t % 3 - 1;
+  int qi = min(q0 + half, total - 1);
+  int bq = qi / HW, yq = (qi - bq * HW) / d.W, xq = qi - bq * HW - yq * d.W;
 #pragma unroll 8
   for (int k = 0; k < W2_CHUNK / 4; k += 2) {
     const int q = q0 + k + half;
     float av = 0.f, bv = 0.f;
     if (q < total) {
-      const int b = q / HW, p = q - b * HW;
       av = d.g2[(long long)q * CH + row];
-      bv = (float)d.a1[((long long)b * HW + nb(p, t, d.H, d.W)) * CH + row];
+      bv = (float)d.a1[((long long)bq * HW + nb_yx(yq, xq, dy, dx, d.H, d.W)) * CH + row];
     }
     acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+    xq += 2;
+    if (xq >= d.W) {
+      xq -= d.W;
+      if (++yq == d.H) {
+        yq = 0;
+        ++bq;
+      }
+    }
   }
   if (wv > 0) {
 #pragma unroll
@@ -244,58 +296,85 @@ __global__ void __launch_bounds__(NTC) cnn_l1_back_input(CnnDev d, double* xb, d
   const int b = g / HW, p = g - b * HW;
   float s = 0.f;
   for (int t = 0; t < 9; ++t) {
-    const float* G = d.g1 + ((long long)b * HW + nb_t(p, t, d.H, d.W)) * CH;
+    const float4* G = reinterpret_cast<const float4*>(d.g1 + ((long long)b * HW + nb_t(p, t, d.H, d.W)) * CH);
 #pragma unroll
-    for (int c = 0; c < CH; ++c) s = fmaf(d.w1[c * 9 + t], G[c], s);
+    for (int c4 = 0; c4 < CH / 4; ++c4) {
+      const float4 q = G[c4];
+      s = fmaf(d.w1[(4 * c4 + 0) * 9 + t], q.x, s);
+      s = fmaf(d.w1[(4 * c4 + 1) * 9 + t], q.y, s);
+      s = fmaf(d.w1[(4 * c4 + 2) * 9 + t], q.z, s);
+      s = fmaf(d.w1[(4 * c4 + 3) * 9 + t], q.w, s);
+    }
   }
   const double v = xscale * (double)s;
   xb[g] = accumulate ? xb[g] + v : v;
 }
 
-// the small parameter gradients (dw1, db1, dw3, db3, db2) of one chunk of SW_CHUNK pixels: one
-// thread per parameter sums over the chunk's pixels in order; written to (add == 0) or added to
-// the FP64 accumulator acc1[chunk][SMALL] (one owner per slot).  SMALL layout: dw1 [c][t],
-// db1 [c], dw3 [c][t], db3, db2 [c].
+// the small parameter gradients (dw1, db1, dw3, db3, db2) of one chunk of SW_CHUNK pixels: a
+// thread per (4 channels, tap) or per 4 channels (biases) sums over the chunk's pixels in order
+// with 16-byte loads of the channel vectors; written to (add == 0) or added to the FP64
+// accumulator acc1[chunk][SMALL] (one owner per slot).  SMALL layout: dw1 [c][t], db1 [c],
+// dw3 [c][t], db3, db2 [c].
 constexpr int SMALL = NP1 + CH + NP3 + 1 + CH;
-constexpr int SW_CHUNK = 128;
-constexpr int SW_THREADS = NP1 + CH;   // 288 (c, t) pairs + 32 channels
+constexpr int SW_CHUNK = 64;
+constexpr int SW_THREADS = 128;   // 72 weight threads, 8 bias threads
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void acc_store(double* slot, float v, int add) { *slot = add ? *slot + (double)v : (double)v; }
 __global__ void __launch_bounds__(SW_THREADS) cnn_small_weight(CnnDev d, const double* yb, double* acc1, int add) {
   const int HW = d.H * d.W, total = d.B * HW, tid = threadIdx.x;
   const int q0 = blockIdx.x * SW_CHUNK, q1 = min(q0 + SW_CHUNK, total);
   double* o = acc1 + (long long)blockIdx.x * SMALL;
-  int b = q0 / HW, p = q0 - b * HW;
-  if (tid < NP1) {
-    const int c = tid & 31, t = tid >> 5;
-    float s1 = 0.f, s3 = 0.f;
+  int b = q0 / HW, y = (q0 - b * HW) / d.W, x = q0 - b * HW - y * d.W;
+  if (tid < 72) {
+    const int c4 = tid & 7, t = tid >> 3, dy = t / 3 - 1, dx = t % 3 - 1;
+    float s1[4] = {0.f, 0.f, 0.f, 0.f}, s3[4] = {0.f, 0.f, 0.f, 0.f};
     for (int q = q0; q < q1; ++q) {
-      const long long nq = (long long)b * HW + nb(p, t, d.H, d.W);
-      s1 = fmaf(d.g1[(long long)q * CH + c], (float)d.a0[nq], s1);
-      s3 = fmaf((float)yb[q], (float)d.a2[nq * CH + c], s3);
-      if (++p == HW) {
-        p = 0;
-        ++b;
+      const long long nq = (long long)b * HW + nb_yx(y, x, dy, dx, d.H, d.W);
+      const float4 g = *reinterpret_cast<const float4*>(d.g1 + (long long)q * CH + 4 * c4);
+      const bf16x4 a2 = *reinterpret_cast<const bf16x4*>(d.a2 + nq * CH + 4 * c4);
+      const float a0 = (float)d.a0[nq], yv = (float)yb[q];
+      s1[0] = fmaf(g.x, a0, s1[0]);
+      s1[1] = fmaf(g.y, a0, s1[1]);
+      s1[2] = fmaf(g.z, a0, s1[2]);
+      s1[3] = fmaf(g.w, a0, s1[3]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) s3[j] = fmaf(yv, (float)a2[j], s3[j]);
+      if (++x == d.W) {
+        x = 0;
+        if (++y == d.H) {
+          y = 0;
+          ++b;
+        }
       }
     }
-    double* s1p = o + c * 9 + t;
-    double* s3p = o + NP1 + CH + c * 9 + t;
-    *s1p = add ? *s1p + (double)s1 : (double)s1;
-    *s3p = add ? *s3p + (double)s3 : (double)s3;
-  } else {
-    const int c = tid - NP1;
-    float sb1 = 0.f, sb2 = 0.f, sb3 = 0.f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = 4 * c4 + j;
+      acc_store(o + c * 9 + t, s1[j], add);
+      acc_store(o + NP1 + CH + c * 9 + t, s3[j], add);
+    }
+  } else if (tid < 80) {
+    const int c4 = tid - 72;
+    float sb1[4] = {0.f, 0.f, 0.f, 0.f}, sb2[4] = {0.f, 0.f, 0.f, 0.f}, sb3 = 0.f;
     for (int q = q0; q < q1; ++q) {
-      sb1 += d.g1[(long long)q * CH + c];
-      sb2 += d.g2[(long long)q * CH + c];
-      if (c == 0) sb3 += (float)yb[q];
+      const float4 g1 = *reinterpret_cast<const float4*>(d.g1 + (long long)q * CH + 4 * c4);
+      const float4 g2 = *reinterpret_cast<const float4*>(d.g2 + (long long)q * CH + 4 * c4);
+      sb1[0] += g1.x;
+      sb1[1] += g1.y;
+      sb1[2] += g1.z;
+      sb1[3] += g1.w;
+      sb2[0] += g2.x;
+      sb2[1] += g2.y;
+      sb2[2] += g2.z;
+      sb2[3] += g2.w;
+      if (c4 == 0) sb3 += (float)yb[q];
     }
-    double* p1 = o + NP1 + c;
-    double* p2 = o + NP1 + CH + NP3 + 1 + c;
-    *p1 = add ? *p1 + (double)sb1 : (double)sb1;
-    *p2 = add ? *p2 + (double)sb2 : (double)sb2;
-    if (c == 0) {
-      double* p3 = o + NP1 + CH + NP3;
-      *p3 = add ? *p3 + (double)sb3 : (double)sb3;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      acc_store(o + NP1 + 4 * c4 + j, sb1[j], add);
+      acc_store(o + NP1 + CH + NP3 + 1 + 4 * c4 + j, sb2[j], add);
     }
+    if (c4 == 0) acc_store(o + NP1 + CH + NP3, sb3, add);
   }
 }
 
