@@ -211,6 +211,7 @@ struct KolCol {
   cplx* out;         // K_EVALF: F; K_VJP: Xbar; K_ADJ (k = 0): dJ/dX_0; K_STEP (n = nsteps): X_N (nullable)
   cplx* snap;        // K_STEP: filtered snapshots (nullable)
   int snap_every, Nc;
+  int* err;          // sticky flags: bit 1 non-finite state
 };
 
 __device__ __forceinline__ long long hidx(const KolCol& a, int k, long long st) {
@@ -279,6 +280,7 @@ __global__ void __launch_bounds__(NTK) kol_cols_fwd(KolDev d, KolCol a, int tc, 
       }
       a.Fr[((n - 1) & 1) * st + si] = F;
       a.H[hidx(a, n, st) + si] = xn;
+      if (!(isfinite(xn.x) && isfinite(xn.y))) atomicOr(a.err, 2);
       if (n == a.nsteps && a.out) a.out[si] = xn;
       if (a.snap && n % a.snap_every == 0) {
         // spectral truncation to the Nc x Nc modes of the coarse grid
@@ -420,6 +422,8 @@ class KolProblem : public ProblemImpl {
     d_.tw = arena_.upload(tw, stream);
     d_.twoff = arena_.upload(off, stream);
     st_ = (long long)B_ * Nh_ * N_;
+    err_ = arena_.alloc<int>(1);
+    SPS_HIP(hipMemsetAsync(err_, 0, sizeof(int), stream));
     const int nh = keep_history ? max_steps + 1 : 3;
     H_ = arena_.alloc<cplx>((size_t)nh * st_);
     Fr_ = arena_.alloc<cplx>(2 * st_);
@@ -591,7 +595,13 @@ class KolProblem : public ProblemImpl {
     *l = 0;
     *ms = 0;
   }
-  int device_error() override { return 0; }
+  int device_error() override {
+    int h = 0;
+    SPS_HIP(hipMemcpyAsync(&h, err_, sizeof(int), hipMemcpyDeviceToHost, stream));
+    SPS_HIP(hipStreamSynchronize(stream));
+    if (h) SPS_HIP(hipMemsetAsync(err_, 0, sizeof(int), stream));
+    return h;
+  }
 
  private:
   long long hslot(int k) const { return hring_ ? k % hring_ : k; }
@@ -620,6 +630,7 @@ class KolProblem : public ProblemImpl {
     a.Yn = Yn_;
     a.Ln = Ln_;
     a.Gk = Gk_;
+    a.err = err_;
     return a;
   }
   void launch_cols(const KolCol& a) {
@@ -686,6 +697,7 @@ class KolProblem : public ProblemImpl {
   KolDev d_{};
   DevArena arena_;
   std::unique_ptr<Cnn> net_;
+  int* err_ = nullptr;
   cplx *H_, *Fr_, *Yn_, *Ln_, *Gk_, *Xw_, *Z4_, *Zg_, *W_, *Zc_ = nullptr, *Zgc_ = nullptr, *Wc_ = nullptr;
   double *og_ = nullptr, *yg_ = nullptr, *xg_ = nullptr, *theta_ = nullptr;
 };

@@ -178,6 +178,25 @@ def test_kolmo_closure_rollout(N):
         print(f"  F: max err {dF:.2e}  bound {2.0 ** -5 * S.max():.2e}  closure max {clo:.2e}", flush=True)
         assert clo > 1e-3 * np.max(np.abs(Fg[b]))          # the closure is not negligible
         assert dF <= 2.0 ** -5 * S.max() + 1e-11 * np.max(np.abs(Fg[b]))
+    # one VJP of F with the closure: state cotangent (eval_F_vjp) and parameter cotangent
+    # (param_vjp, summed over the batch), within the network's cotangent bound
+    Yb = workloads.kolmo_vorticity(seed=30, N=N, batch=B)
+    Yb[:, 0, 0] = 0.5   # a mean component, so that the output bias has a nonzero cotangent
+    Xb = torch.zeros_like(X0)
+    G.eval_F_vjp(X0, to_dev(list(Yb)), Xb)
+    pb = torch.zeros_like(theta)
+    G.param_vjp(X0, to_dev(list(Yb)), pb)
+    Xbg, pref = from_dev(Xb, B, N), None
+    for b in range(B):
+        xo, po = P.F_vjp(c0[b].reshape(-1, 1), Yb[b].reshape(-1, 1), with_params=True)
+        e = np.abs(Xbg[b] - xo.reshape(N, N // 2)) / np.max(np.abs(xo))
+        print(f"  F_vjp: max {e.max():.2e} median {np.median(e):.2e}", flush=True)
+        assert e.max() <= 2.0 ** -7 and np.median(e) <= 2.0 ** -13
+        pref = po if pref is None else pref + po
+    tp, to = cl.unflatten(pb.cpu().numpy()), cl.unflatten(pref)
+    for k in cl.PARAM_ORDER:
+        e = np.abs(tp[k] - to[k]) / np.max(np.abs(to[k]))
+        assert e.max() <= 2.0 ** -7 and np.median(e) <= 2.0 ** -13, ("param_vjp", k)
     targets = torch.cat([to_dev(list(t)) for t in tg])
     XN = torch.zeros_like(X0)
     J = torch.zeros(B, dtype=torch.float64, device="cuda")
@@ -203,3 +222,17 @@ def test_kolmo_closure_rollout(N):
         e = np.abs(tp[k] - to[k]) / np.max(np.abs(to[k]))
         print(f"  d/d{k}: max {e.max():.2e} median {np.median(e):.2e}", flush=True)
         assert e.max() <= 2.0 ** -7 and np.median(e) <= 2.0 ** -13, k
+
+
+def test_blow_up_is_reported_by_sync():
+    """Without drag the forced flow at Re = 1000 accelerates until the explicit advection of
+    SBDF2 goes unstable (the oracle does the same near t = 2.2 at 64^2, dt = 0.01): the run
+    completes, the step kernel sets the sticky non-finite flag and sps_sync reports it."""
+    print("kolmo non-finite flag", flush=True)
+    G = sps.Kolmogorov(1, 64, Re=1000.0, dt=0.01, max_steps=1, keep_history=False, drag=0.0)
+    X0 = to_dev(list(workloads.kolmo_vorticity(seed=100, N=64, batch=1, amp=0.1)))
+    XN = torch.zeros_like(X0)
+    G.forward(X0, 300, XN=XN)
+    with pytest.raises(sps.SpsError) as ei:
+        G.sync()
+    assert ei.value.code == -5 and not torch.isfinite(XN).all()

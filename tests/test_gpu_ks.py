@@ -102,3 +102,20 @@ def test_ks_step_then_adjoint_step_large_amplitude():
     assert rel(from_dev(dJ, P.K), g_ref) < TOL
     with pytest.raises(sps.SpsError):
         G.adjoint_step(dJ, nsteps - 1)
+
+
+def test_nonfinite_state_is_reported_by_sync():
+    """A forward run that overflows (KS with dt = 10 and an O(1) initial state: the explicit term
+    grows without bound) completes without a fault; the kernels set the sticky non-finite flag and
+    the next sps_sync reports SPS_E_NONFINITE, once."""
+    print("ks non-finite flag", flush=True)
+    P = KS()
+    G = sps.Problem(sps.KS1D, 64, 0, P.Lx, 0.0, 0.0, 1.5, 10.0, 1, 200)
+    c0 = wl.ks_c0(seed=3, amp=5.0)
+    X = torch.from_numpy(np.ascontiguousarray(c0).view(np.float64).ravel().copy()).cuda()
+    G.step(X, 200)
+    with pytest.raises(sps.SpsError) as ei:
+        G.sync()
+    assert ei.value.code == -5
+    assert not torch.isfinite(X).all()
+    G.sync()   # the flag is cleared once reported
