@@ -97,7 +97,7 @@ __global__ void __launch_bounds__(NTK) kol_cols_inv(KolDev d, const cplx* X, int
     b0[fpad(j * G + row)] = v;
   }
   __syncthreads();
-  const cplx* o = lds_fft(b0, b1, d.plans[plan], tw, +1, tcn, G, tid, NTK);
+  const cplx* o = lds_fft_inline(b0, b1, d.plans[plan], tw, +1, tcn, G, tid, NTK);
   cplx* Zb = Z + ((long long)b * nf + f) * G * Nh + c0;
   for (int e = tid; e < tcn * G; e += NTK) {
     const int y = e / tcn, j = e - y * tcn;
@@ -154,7 +154,7 @@ __global__ void __launch_bounds__(NT) kol_rows(KolDev d, int mode, int G, int pl
   }
   __syncthreads();
   const FftPlan& P = d.plans[plan];
-  cplx* h = (mode == R_FWD_GRID) ? b0 : lds_fft(b0, b1, P, tw, +1, nin, G, tid, NT);
+  cplx* h = (mode == R_FWD_GRID) ? b0 : lds_fft_inline(b0, b1, P, tw, +1, nin, G, tid, NT);
   if (mode == R_GRID) {
     double* r0 = grid + ((long long)b * G + y0) * G;
     for (int x = tid; x < G; x += NT) {
@@ -184,13 +184,52 @@ __global__ void __launch_bounds__(NT) kol_rows(KolDev d, int mode, int G, int pl
     __syncthreads();
   }
   cplx* o2 = (o == b0) ? b1 : b0;
-  const cplx* r = lds_fft(o, o2, P, tw, -1, nout, G, tid, NT);
+  const cplx* r = lds_fft_inline(o, o2, P, tw, -1, nout, G, tid, NT);
   // unpack the two real rows' half spectra: Y_y = (Z_m + conj Z_-m) / 2, Y_y+1 = (Z_m - conj Z_-m) / 2i
   for (int e = tid; e < nout * 2 * Nh; e += NT) {
     const int f = e / (2 * Nh), rr = e - f * 2 * Nh, yy = rr / Nh, m = rr - yy * Nh;
     const cplx zm = r[fpad(f * G + m)], zq = r[fpad(f * G + (m == 0 ? 0 : G - m))];
     const cplx v = yy ? cmk(0.5 * (zm.y + zq.y), -0.5 * (zm.x - zq.x)) : cmk(0.5 * (zm.x + zq.x), 0.5 * (zm.y - zq.y));
     W[(((long long)b * nout + f) * G + y0 + yy) * Nh + m] = v;
+  }
+}
+
+// The advection product of one row pair in two passes of two fields each (u, omega_x, then
+// v, omega_y), so that long rows fit two blocks per CU: LDS twiddles(G) + 2 fpad_size(2 G) +
+// fpad_size(G).  Same result as kol_rows in mode R_ADV up to the order of the two products.
+template <int NT>
+__global__ void __launch_bounds__(NT) kol_rows_adv2(KolDev d, int G, int plan, const cplx* Z4, cplx* W) {
+  extern __shared__ double smem_d[];
+  const int b = blockIdx.y, y0 = 2 * blockIdx.x, Nh = d.Nh, tid = threadIdx.x;
+  cplx* tw = reinterpret_cast<cplx*>(smem_d);
+  cplx* b0 = tw + G;
+  cplx* b1 = b0 + fpad_size(2 * G);
+  cplx* pr = b1 + fpad_size(2 * G);
+  const cplx* g = d.tw + d.twoff[plan];
+  for (int e = tid; e < G; e += NT) tw[e] = g[e];
+  const FftPlan& P = d.plans[plan];
+  for (int pass = 0; pass < 2; ++pass) {
+    // pass 0: fields 0 (u) and 2 (omega_x); pass 1: fields 1 (v) and 3 (omega_y)
+    for (int e = tid; e < 2 * G; e += NT) {
+      const int q = e / G, x = e - q * G, f = pass + 2 * q;
+      const cplx* U = Z4 + (((long long)b * 4 + f) * G + y0) * Nh;
+      b0[fpad(e)] = kol_pack(U, U + Nh, x, G, Nh, 1.0);
+    }
+    __syncthreads();
+    const cplx* h = lds_fft_inline(b0, b1, P, tw, +1, 2, G, tid, NT);
+    for (int x = tid; x < G; x += NT) {
+      const cplx a = h[fpad(x)], c = h[fpad(G + x)];
+      const cplx p = cmk(-(a.x * c.x), -(a.y * c.y));
+      pr[fpad(x)] = pass ? cmk(pr[fpad(x)].x + p.x, pr[fpad(x)].y + p.y) : p;
+    }
+    __syncthreads();
+  }
+  const cplx* r = lds_fft_inline(pr, b0, P, tw, -1, 1, G, tid, NT);
+  for (int e = tid; e < 2 * Nh; e += NT) {
+    const int yy = e / Nh, m = e - yy * Nh;
+    const cplx zm = r[fpad(m)], zq = r[fpad(m == 0 ? 0 : G - m)];
+    const cplx v = yy ? cmk(0.5 * (zm.y + zq.y), -0.5 * (zm.x - zq.x)) : cmk(0.5 * (zm.x + zq.x), 0.5 * (zm.y - zq.y));
+    W[((long long)b * G + y0 + yy) * Nh + m] = v;
   }
 }
 
@@ -246,8 +285,8 @@ __global__ void __launch_bounds__(NTK) kol_cols_fwd(KolDev d, KolCol a, int tc, 
       c0b[fpad(j * N + y)] = a.Wc[((long long)b * N + y) * Nh + c0 + j];
     }
   __syncthreads();
-  const cplx* res = (nW > 0) ? lds_fft(b0, b1, d.plans[d.pNg], twg, -1, nW * tcn, Ng, tid, NTK) : nullptr;
-  const cplx* rc = clo ? lds_fft(c0b, c1b, d.plans[d.pN], twn, -1, tcn, N, tid, NTK) : nullptr;
+  const cplx* res = (nW > 0) ? lds_fft_inline(b0, b1, d.plans[d.pNg], twg, -1, nW * tcn, Ng, tid, NTK) : nullptr;
+  const cplx* rc = clo ? lds_fft_inline(c0b, c1b, d.plans[d.pN], twn, -1, tcn, N, tid, NTK) : nullptr;
   const long long st = (long long)d.B * Nh * N, io = (long long)b * Nh * N;
   const double ng2 = 1.0 / ((double)Ng * Ng), n2 = 1.0 / ((double)N * N);
   for (int e = tid; e < tcn * N; e += NTK) {
@@ -457,7 +496,7 @@ class KolProblem : public ProblemImpl {
     const size_t il = std::max(inv_lds(Ng_, tc_ig_), inv_lds(N_, tc_in_));
     SPS_REQUIRE(rl <= kLdsMax && il <= kLdsMax && fwd_lds(tc_f_) <= kLdsMax, "size too large for the Kolmogorov kernels");
     for (const void* k : {(const void*)kol_cols_inv, (const void*)kol_rows<256>, (const void*)kol_rows<512>,
-                          (const void*)kol_cols_fwd})
+                          (const void*)kol_rows_adv2<512>, (const void*)kol_cols_fwd})
       SPS_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax));
     SPS_HIP(hipStreamSynchronize(stream));
   }
@@ -647,6 +686,12 @@ class KolProblem : public ProblemImpl {
   }
   void rows(int mode, int G, int plan, const cplx* Z4, const cplx* Zg, double* grid, const double* gin, cplx* W,
             double wscale, double gscale) {
+    if (mode == R_ADV && G >= 384) {
+      const size_t l2 = sizeof(cplx) * (G + 2 * (size_t)fpad_size(2 * G) + fpad_size(G));
+      hipLaunchKernelGGL(kol_rows_adv2<512>, dim3(G / 2, B_), dim3(512), l2, stream, d_, G, plan, Z4, W);
+      SPS_CHECK_LAUNCH();
+      return;
+    }
     // rows of 384 points or more: 512 threads, so that a CU holding one block (LDS) still has
     // eight waves
     const size_t lds = sizeof(cplx) * (G + 2 * (size_t)rcap_);

@@ -146,8 +146,8 @@ __device__ __forceinline__ void stockham_pass(const cplx* __restrict__ src, cplx
 // Batched in-LDS FFT of nbatch sequences (stride bstride, indices padded by fpad) held in
 // buf0; buf1 is scratch of the same size.  Returns the buffer holding the result.  Contains
 // __syncthreads(); must be called by every thread of the block.
-__device__ inline cplx* lds_fft(cplx* buf0, cplx* buf1, const FftPlan& p, const cplx* tw, int sign,
-                                int nbatch, int bstride, int tid, int nthreads) {
+__device__ __forceinline__ cplx* lds_fft_inline(cplx* buf0, cplx* buf1, const FftPlan& p, const cplx* tw, int sign,
+                                                int nbatch, int bstride, int tid, int nthreads) {
   cplx* src = buf0;
   cplx* dst = buf1;
   for (int s = 0; s < p.nst; ++s) {
@@ -164,6 +164,14 @@ __device__ inline cplx* lds_fft(cplx* buf0, cplx* buf1, const FftPlan& p, const 
     dst = t;
   }
   return src;
+}
+
+// The same FFT as an ordinary (inlining left to the compiler) function: kernels with several
+// FFT call sites may keep one out-of-line copy; lds_fft_inline forces a copy per call site,
+// which lets register allocation see each call's radix mix.
+__device__ inline cplx* lds_fft(cplx* buf0, cplx* buf1, const FftPlan& p, const cplx* tw, int sign, int nbatch,
+                                int bstride, int tid, int nthreads) {
+  return lds_fft_inline(buf0, buf1, p, tw, sign, nbatch, bstride, tid, nthreads);
 }
 
 // ---------------------------------------------------------------------------- lanes
