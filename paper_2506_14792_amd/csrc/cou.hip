@@ -34,9 +34,8 @@
 namespace sps {
 namespace {
 
-constexpr int NTC = 256;
 constexpr size_t kCouLdsMax = 160 * 1024;
-constexpr size_t kCouLdsBudget = 80 * 1024;
+constexpr size_t kCouLdsBudget = 40 * 1024;
 
 struct CouDev {
   int Kx, Nz, K, Ngx, Ngz, Ngy;
@@ -87,6 +86,85 @@ __device__ __forceinline__ cplx cou_pack(const cplx* U, const cplx* V, int x, in
   }
   return czero();
 }
+// ---------------------------------------------------------------------------- in-place FFT
+// The plane kernels run the mixed-radix Stockham passes in place in one LDS buffer: a thread
+// loads and transforms all of its butterflies of a pass into registers, the block
+// synchronizes, and the results go to their Stockham positions.  One buffer instead of a
+// ping-pong pair lets two or three blocks share a CU.  A pass of radix R holds up to MB
+// butterflies per thread, so a block of nt threads transforms up to 6 nt points
+// (nbatch * n <= 6 nt, checked on the host).
+// HALF: tw holds only the first n/2 twiddles (w^(m + n/2) = -w^m for even n).
+template <int R, int MB, bool HALF>
+__device__ __forceinline__ void ip_pass(cplx* buf, const FftPlan& p, int s, const cplx* __restrict__ tw, int sign,
+                                        int nbatch, int bstride, int tid, int nt) {
+  const int nR = p.n / R, Ns = p.ns[s], tst = p.tst[s];
+  const unsigned mnr = p.mag_nr[s], mns = p.mag_ns[s];
+  const int total = nbatch * nR;
+  cplx v[MB][R];
+  int dst[MB];
+#pragma unroll
+  for (int b = 0; b < MB; ++b) {
+    const int it = tid + b * nt;
+    dst[b] = -1;
+    if (it < total) {
+      const int q = fdiv(it, mnr);
+      const int j = it - q * nR;
+      const int jh = fdiv(j, mns);
+      const int k = j - jh * Ns;
+      const int t = k * tst;
+      const int base = q * bstride;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        cplx x = buf[fpad(base + j + r * nR)];
+        if (r > 0) {
+          const int ti = r * t;
+          cplx w;
+          if (HALF) {
+            const int hn = p.n >> 1;
+            if (ti < hn) {
+              w = tw[ti];
+            } else {
+              const cplx u = tw[ti - hn];
+              w = cmk(-u.x, -u.y);
+            }
+          } else {
+            w = tw[ti];
+          }
+          if (sign > 0) w = cconj(w);
+          x = cmul(x, w);
+        }
+        v[b][r] = x;
+      }
+      dft_small<R>(v[b], sign);
+      dst[b] = base + jh * Ns * R + k;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < MB; ++b)
+    if (dst[b] >= 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[fpad(dst[b] + r * Ns)] = v[b][r];
+    }
+  __syncthreads();
+}
+
+// nbatch sequences of length p.n at buf + q * bstride (padded indices), transformed in place;
+// ends synchronized.  Every thread of the block calls it.
+template <bool HALF = false>
+__device__ __forceinline__ void ip_fft(cplx* buf, const FftPlan& p, const cplx* tw, int sign, int nbatch, int bstride,
+                                       int tid, int nt) {
+  for (int s = 0; s < p.nst; ++s) {
+    switch (p.radix[s]) {
+      case 8: ip_pass<8, 1, HALF>(buf, p, s, tw, sign, nbatch, bstride, tid, nt); break;
+      case 6: ip_pass<6, 1, HALF>(buf, p, s, tw, sign, nbatch, bstride, tid, nt); break;
+      case 4: ip_pass<4, 2, HALF>(buf, p, s, tw, sign, nbatch, bstride, tid, nt); break;
+      case 3: ip_pass<3, 2, HALF>(buf, p, s, tw, sign, nbatch, bstride, tid, nt); break;
+      default: ip_pass<2, 3, HALF>(buf, p, s, tw, sign, nbatch, bstride, tid, nt); break;
+    }
+  }
+}
+
 // half spectrum of row yy (0 or 1) of a packed forward DFT r of two real rows
 __device__ __forceinline__ cplx cou_unpack(const cplx* r, int base, int m, int G, int yy) {
   const cplx zm = r[fpad(base + m)], zq = r[fpad(base + (m == 0 ? 0 : G - m))];
@@ -96,7 +174,8 @@ __device__ __forceinline__ cplx cou_unpack(const cplx* r, int base, int m, int G
 // ---------------------------------------------------------------------------- A: z inverse
 // Grid (x-mode tiles, 3 components, Ngy).  Component g (u, v, w) writes fields g, 3 + g,
 // 6 + 2g, 7 + 2g of Z: the component, its y-derivative, i kx times it, i kz times it.
-__global__ void __launch_bounds__(NTC) cou_zinv(CouDev d, const cplx* zg, int tc, cplx* Z) {
+template <int NT>
+__global__ void __launch_bounds__(NT) cou_zinv(CouDev d, const cplx* zg, int tc, cplx* Z) {
   extern __shared__ double smem_d[];
   const int g = blockIdx.y, y = blockIdx.z, m0 = blockIdx.x * tc, tid = threadIdx.x;
   const int Nz = d.Nz, G = d.Ngz, K = d.K, Kx = d.Kx, Ngy = d.Ngy;
@@ -104,11 +183,10 @@ __global__ void __launch_bounds__(NTC) cou_zinv(CouDev d, const cplx* zg, int tc
   const int tcn = min(tc, Kx - m0);
   cplx* tw = reinterpret_cast<cplx*>(smem_d);
   cplx* b0 = tw + G;
-  cplx* b1 = b0 + fpad_size(4 * tc * G);
-  for (int e = tid; e < G; e += NTC) tw[e] = d.twz[e];
-  for (int e = tid; e < 4 * tcn * G; e += NTC) b0[fpad(e)] = czero();
+  for (int e = tid; e < G; e += NT) tw[e] = d.twz[e];
+  for (int e = tid; e < 4 * tcn * G; e += NT) b0[fpad(e)] = czero();
   __syncthreads();
-  for (int e = tid; e < tcn * Nz; e += NTC) {
+  for (int e = tid; e < tcn * Nz; e += NT) {
     const int j = e / Nz, n = e - j * Nz, m = m0 + j;
     const int row = cou_zrow(n, Nz, G);
     if (row < 0) continue;
@@ -135,9 +213,10 @@ __global__ void __launch_bounds__(NTC) cou_zinv(CouDev d, const cplx* zg, int tc
     b0[fpad((3 * tcn + j) * G + row)] = cscale(cmul_i(val), w.kz);
   }
   __syncthreads();
-  const cplx* o = lds_fft(b0, b1, d.pz, tw, +1, 4 * tcn, G, tid, NTC);
+  ip_fft(b0, d.pz, tw, +1, 4 * tcn, G, tid, NT);
+  const cplx* o = b0;
   const int fid[4] = {g, 3 + g, 6 + 2 * g, 7 + 2 * g};
-  for (int e = tid; e < 4 * G * tcn; e += NTC) {
+  for (int e = tid; e < 4 * G * tcn; e += NT) {
     const int q = e / (G * tcn), r = e - q * G * tcn, z = r / tcn, j = r - z * tcn;
     Z[(((long long)fid[q] * Ngy + y) * G + z) * Kx + m0 + j] = o[fpad((q * tcn + j) * G + z)];
   }
@@ -157,23 +236,22 @@ __device__ __forceinline__ Dens cou_dens(const double* f, double U, double dU) {
   return r;
 }
 
-// Grid (Ngz / 2, Ngy).  LDS twiddles(Ngx) + 2 cap, cap >= fpad_size(12 Ngx).
+// Grid (Ngz / 2, Ngy), 12 Ngx <= 6 NT.  LDS twiddles(Ngx) + fpad_size(12 Ngx).  The densities
+// of a grid point overwrite its u, v, w slots (one thread reads and writes each x).
 template <int NT>
-__global__ void __launch_bounds__(NT) cou_xrow(CouDev d, const cplx* Z, int cap, cplx* W) {
+__global__ void __launch_bounds__(NT) cou_xrow(CouDev d, const cplx* __restrict__ Z, cplx* __restrict__ W) {
   extern __shared__ double smem_d[];
   const int y = blockIdx.y, z0 = 2 * blockIdx.x, tid = threadIdx.x, G = d.Ngx, Kx = d.Kx, Ngy = d.Ngy, Gz = d.Ngz;
   cplx* tw = reinterpret_cast<cplx*>(smem_d);
-  cplx* b0 = tw + G;
-  cplx* b1 = b0 + cap;
+  cplx* h = tw + G;
   for (int e = tid; e < G; e += NT) tw[e] = d.twx[e];
   for (int e = tid; e < 12 * G; e += NT) {
     const int f = e / G, x = e - f * G;
     const cplx* U = Z + (((long long)f * Ngy + y) * Gz + z0) * Kx;
-    b0[fpad(e)] = cou_pack(U, U + Kx, x, G, Kx, 1.0);
+    h[fpad(e)] = cou_pack(U, U + Kx, x, G, Kx, 1.0);
   }
   __syncthreads();
-  cplx* h = lds_fft(b0, b1, d.px, tw, +1, 12, G, tid, NT);
-  cplx* o = (h == b0) ? b1 : b0;
+  ip_fft(h, d.px, tw, +1, 12, G, tid, NT);
   const double Uy = d.unode[y], dU = d.du;
   for (int x = tid; x < G; x += NT) {
     double fa[12], fb[12];
@@ -184,13 +262,13 @@ __global__ void __launch_bounds__(NT) cou_xrow(CouDev d, const cplx* Z, int cap,
       fb[i] = v.y;
     }
     const Dens a = cou_dens(fa, Uy, dU), b = cou_dens(fb, Uy, dU);
-    o[fpad(x)] = cmk(a.nu, b.nu);
-    o[fpad(G + x)] = cmk(a.nv, b.nv);
-    o[fpad(2 * G + x)] = cmk(a.nw, b.nw);
+    h[fpad(x)] = cmk(a.nu, b.nu);
+    h[fpad(G + x)] = cmk(a.nv, b.nv);
+    h[fpad(2 * G + x)] = cmk(a.nw, b.nw);
   }
   __syncthreads();
-  cplx* o2 = (o == b0) ? b1 : b0;
-  const cplx* r = lds_fft(o, o2, d.px, tw, -1, 3, G, tid, NT);
+  ip_fft(h, d.px, tw, -1, 3, G, tid, NT);
+  const cplx* r = h;
   for (int e = tid; e < 3 * 2 * Kx; e += NT) {
     const int f = e / (2 * Kx), rr = e - f * 2 * Kx, yy = rr / Kx, m = rr - yy * Kx;
     W[(((long long)f * Ngy + y) * Gz + z0 + yy) * Kx + m] = cou_unpack(r, f * G, m, G, yy);
@@ -199,7 +277,8 @@ __global__ void __launch_bounds__(NT) cou_xrow(CouDev d, const cplx* Z, int cap,
 
 // ---------------------------------------------------------------------------- C: z forward
 // Grid (x-mode tiles, Ngy).
-__global__ void __launch_bounds__(NTC) cou_zfwd(CouDev d, const cplx* W, int tc, cplx* nl) {
+template <int NT>
+__global__ void __launch_bounds__(NT) cou_zfwd(CouDev d, const cplx* W, int tc, cplx* nl) {
   extern __shared__ double smem_d[];
   const int y = blockIdx.y, m0 = blockIdx.x * tc, tid = threadIdx.x;
   const int Nz = d.Nz, G = d.Ngz, K = d.K, Kx = d.Kx, Ngy = d.Ngy;
@@ -207,16 +286,16 @@ __global__ void __launch_bounds__(NTC) cou_zfwd(CouDev d, const cplx* W, int tc,
   const int tcn = min(tc, Kx - m0);
   cplx* tw = reinterpret_cast<cplx*>(smem_d);
   cplx* b0 = tw + G;
-  cplx* b1 = b0 + fpad_size(3 * tc * G);
-  for (int e = tid; e < G; e += NTC) tw[e] = d.twz[e];
-  for (int e = tid; e < 3 * G * tcn; e += NTC) {
+  for (int e = tid; e < G; e += NT) tw[e] = d.twz[e];
+  for (int e = tid; e < 3 * G * tcn; e += NT) {
     const int f = e / (G * tcn), r = e - f * G * tcn, z = r / tcn, j = r - z * tcn;
     b0[fpad((f * tcn + j) * G + z)] = W[(((long long)f * Ngy + y) * G + z) * Kx + m0 + j];
   }
   __syncthreads();
-  const cplx* res = lds_fft(b0, b1, d.pz, tw, -1, 3 * tcn, G, tid, NTC);
+  ip_fft(b0, d.pz, tw, -1, 3 * tcn, G, tid, NT);
+  const cplx* res = b0;
   const double s = 1.0 / ((double)d.Ngx * G);
-  for (int e = tid; e < tcn * Nz; e += NTC) {
+  for (int e = tid; e < tcn * Nz; e += NT) {
     const int j = e / Nz, n = e - j * Nz, m = m0 + j;
     const long long k = (long long)m * Nz + n;
     const int row = cou_zrow(n, Nz, G);
@@ -237,7 +316,8 @@ __global__ void __launch_bounds__(NTC) cou_zfwd(CouDev d, const cplx* W, int tc,
 }
 
 // ---------------------------------------------------------------------------- C': transpose of C
-__global__ void __launch_bounds__(NTC) cou_zfwd_adj(CouDev d, const cplx* nlbar, int tc, cplx* Wb) {
+template <int NT>
+__global__ void __launch_bounds__(NT) cou_zfwd_adj(CouDev d, const cplx* nlbar, int tc, cplx* Wb) {
   extern __shared__ double smem_d[];
   const int y = blockIdx.y, m0 = blockIdx.x * tc, tid = threadIdx.x;
   const int Nz = d.Nz, G = d.Ngz, K = d.K, Kx = d.Kx, Ngy = d.Ngy;
@@ -245,12 +325,11 @@ __global__ void __launch_bounds__(NTC) cou_zfwd_adj(CouDev d, const cplx* nlbar,
   const int tcn = min(tc, Kx - m0);
   cplx* tw = reinterpret_cast<cplx*>(smem_d);
   cplx* b0 = tw + G;
-  cplx* b1 = b0 + fpad_size(3 * tc * G);
-  for (int e = tid; e < G; e += NTC) tw[e] = d.twz[e];
-  for (int e = tid; e < 3 * tcn * G; e += NTC) b0[fpad(e)] = czero();
+  for (int e = tid; e < G; e += NT) tw[e] = d.twz[e];
+  for (int e = tid; e < 3 * tcn * G; e += NT) b0[fpad(e)] = czero();
   __syncthreads();
   const double s = 1.0 / ((double)d.Ngx * G);
-  for (int e = tid; e < tcn * Nz; e += NTC) {
+  for (int e = tid; e < tcn * Nz; e += NT) {
     const int j = e / Nz, n = e - j * Nz, m = m0 + j;
     const int row = cou_zrow(n, Nz, G);
     if (row < 0) continue;
@@ -263,73 +342,68 @@ __global__ void __launch_bounds__(NTC) cou_zfwd_adj(CouDev d, const cplx* nlbar,
     b0[fpad((2 * tcn + j) * G + row)] = cscale(lin2(w.ez, a, w.ex, c), s);
   }
   __syncthreads();
-  const cplx* o = lds_fft(b0, b1, d.pz, tw, +1, 3 * tcn, G, tid, NTC);
-  for (int e = tid; e < 3 * G * tcn; e += NTC) {
+  ip_fft(b0, d.pz, tw, +1, 3 * tcn, G, tid, NT);
+  const cplx* o = b0;
+  for (int e = tid; e < 3 * G * tcn; e += NT) {
     const int f = e / (G * tcn), r = e - f * G * tcn, z = r / tcn, j = r - z * tcn;
     Wb[(((long long)f * Ngy + y) * G + z) * Kx + m0 + j] = o[fpad((f * tcn + j) * G + z)];
   }
 }
 
 // ---------------------------------------------------------------------------- B': transpose of B
-// Grid (Ngz / 2, Ngy).  LDS twiddles(Ngx) + 2 cap, cap >= fpad_size(15 Ngx).  The primal fields
-// Zp (12) and the density cotangents Wb (3, weight-1 modes) in; the 12 field cotangents out,
-// as x half spectra times w_m (the transpose of the inverse transform).
+// Grid (Ngz / 2, Ngy), 15 Ngx <= 6 NT.  LDS twiddles(Ngx / 2) + fpad_size(15 Ngx): three
+// 512-thread blocks share a CU at Ngx = 192.  The primal fields Zp (12) and
+// the density cotangents Wb (3, weight-1 modes) in; the 12 field cotangents out, as x half
+// spectra times w_m (the transpose of the inverse transform).  The cotangents of a grid point
+// overwrite its first 12 slots (one thread reads and writes each x).
 template <int NT>
-__global__ void __launch_bounds__(NT) cou_xrow_adj(CouDev d, const cplx* Zp, const cplx* Wb, int cap, cplx* Gb) {
+__global__ void __launch_bounds__(NT)
+cou_xrow_adj(CouDev d, const cplx* __restrict__ Zp, const cplx* __restrict__ Wb, cplx* __restrict__ Gb) {
   extern __shared__ double smem_d[];
   const int y = blockIdx.y, z0 = 2 * blockIdx.x, tid = threadIdx.x, G = d.Ngx, Kx = d.Kx, Ngy = d.Ngy, Gz = d.Ngz;
   cplx* tw = reinterpret_cast<cplx*>(smem_d);
-  cplx* b0 = tw + G;
-  cplx* b1 = b0 + cap;
-  for (int e = tid; e < G; e += NT) tw[e] = d.twx[e];
+  cplx* h = tw + G / 2;
+  cplx* o = h;
+  for (int e = tid; e < G / 2; e += NT) tw[e] = d.twx[e];
   for (int e = tid; e < 15 * G; e += NT) {
     const int f = e / G, x = e - f * G;
     const cplx* U = (f < 12) ? Zp + (((long long)f * Ngy + y) * Gz + z0) * Kx
                              : Wb + (((long long)(f - 12) * Ngy + y) * Gz + z0) * Kx;
-    b0[fpad(e)] = cou_pack(U, U + Kx, x, G, Kx, f < 12 ? 1.0 : 0.5);
+    h[fpad(e)] = cou_pack(U, U + Kx, x, G, Kx, f < 12 ? 1.0 : 0.5);
   }
   __syncthreads();
-  cplx* h = lds_fft(b0, b1, d.px, tw, +1, 15, G, tid, NT);
-  cplx* o = (h == b0) ? b1 : b0;
+  ip_fft<true>(h, d.px, tw, +1, 15, G, tid, NT);
   const double Uy = d.unode[y], dU = d.du;
   for (int x = tid; x < G; x += NT) {
-    double f[2][12], q[2][3], out[2][12];
-#pragma unroll
-    for (int i = 0; i < 12; ++i) {
-      const cplx v = h[fpad(i * G + x)];
-      f[0][i] = v.x;
-      f[1][i] = v.y;
-    }
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const cplx v = h[fpad((12 + i) * G + x)];
-      q[0][i] = v.x;
-      q[1][i] = v.y;
-    }
+    // the two packed rows (real and imaginary parts) one after the other, as doubles
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
-      const double* a = f[r];
-      const double nu = q[r][0], nv = q[r][1], nw = q[r][2];
-      const double adv = a[0] + Uy;
-      out[r][0] = -(nu * a[6] + nv * a[8] + nw * a[10]);
-      out[r][1] = -(nu * a[3] + nv * a[4] + nw * a[5]) - dU * nu;
-      out[r][2] = -(nu * a[7] + nv * a[9] + nw * a[11]);
-      out[r][3] = -nu * a[1];
-      out[r][4] = -nv * a[1];
-      out[r][5] = -nw * a[1];
-      out[r][6] = -nu * adv;
-      out[r][7] = -nu * a[2];
-      out[r][8] = -nv * adv;
-      out[r][9] = -nv * a[2];
-      out[r][10] = -nw * adv;
-      out[r][11] = -nw * a[2];
-    }
+      double* hd = reinterpret_cast<double*>(h) + r;
+      double a[12];
 #pragma unroll
-    for (int i = 0; i < 12; ++i) o[fpad(i * G + x)] = cmk(out[0][i], out[1][i]);
+      for (int i = 0; i < 12; ++i) a[i] = hd[2 * fpad(i * G + x)];
+      const double nu = hd[2 * fpad(12 * G + x)], nv = hd[2 * fpad(13 * G + x)], nw = hd[2 * fpad(14 * G + x)];
+      const double adv = a[0] + Uy;
+      double out[12];
+      out[0] = -(nu * a[6] + nv * a[8] + nw * a[10]);
+      out[1] = -(nu * a[3] + nv * a[4] + nw * a[5]) - dU * nu;
+      out[2] = -(nu * a[7] + nv * a[9] + nw * a[11]);
+      out[3] = -nu * a[1];
+      out[4] = -nv * a[1];
+      out[5] = -nw * a[1];
+      out[6] = -nu * adv;
+      out[7] = -nu * a[2];
+      out[8] = -nv * adv;
+      out[9] = -nv * a[2];
+      out[10] = -nw * adv;
+      out[11] = -nw * a[2];
+#pragma unroll
+      for (int i = 0; i < 12; ++i) hd[2 * fpad(i * G + x)] = out[i];
+    }
   }
   __syncthreads();
-  cplx* o2 = (o == b0) ? b1 : b0;
-  const cplx* r = lds_fft(o, o2, d.px, tw, -1, 12, G, tid, NT);
+  ip_fft<true>(o, d.px, tw, -1, 12, G, tid, NT);
+  const cplx* r = o;
   for (int e = tid; e < 12 * 2 * Kx; e += NT) {
     const int f = e / (2 * Kx), rr = e - f * 2 * Kx, yy = rr / Kx, m = rr - yy * Kx;
     const cplx v = cou_unpack(r, f * G, m, G, yy);
@@ -341,7 +415,8 @@ __global__ void __launch_bounds__(NT) cou_xrow_adj(CouDev d, const cplx* Zp, con
 // Grid (x-mode tiles, 2 groups, Ngy): group 0 the u and w fields (8: they mix in the rotation),
 // group 1 the v fields (4).  Forward z-FFTs of the field cotangents, the transposes of the
 // derivative factors and of the rotation, into zbar[6][Ngy][K].
-__global__ void __launch_bounds__(NTC) cou_zinv_adj(CouDev d, const cplx* Gb, int tc, cplx* zbar) {
+template <int NT>
+__global__ void __launch_bounds__(NT) cou_zinv_adj(CouDev d, const cplx* Gb, int tc, cplx* zbar) {
   extern __shared__ double smem_d[];
   const int grp = blockIdx.y, y = blockIdx.z, m0 = blockIdx.x * tc, tid = threadIdx.x;
   const int Nz = d.Nz, G = d.Ngz, K = d.K, Kx = d.Kx, Ngy = d.Ngy;
@@ -353,16 +428,16 @@ __global__ void __launch_bounds__(NTC) cou_zinv_adj(CouDev d, const cplx* Gb, in
   const int fid1[4] = {1, 4, 8, 9};
   cplx* tw = reinterpret_cast<cplx*>(smem_d);
   cplx* b0 = tw + G;
-  cplx* b1 = b0 + fpad_size(8 * tc * G);
-  for (int e = tid; e < G; e += NTC) tw[e] = d.twz[e];
-  for (int e = tid; e < nf * G * tcn; e += NTC) {
+  for (int e = tid; e < G; e += NT) tw[e] = d.twz[e];
+  for (int e = tid; e < nf * G * tcn; e += NT) {
     const int q = e / (G * tcn), r = e - q * G * tcn, z = r / tcn, j = r - z * tcn;
     const int f = grp == 0 ? fid0[q] : fid1[q];
     b0[fpad((q * tcn + j) * G + z)] = Gb[(((long long)f * Ngy + y) * G + z) * Kx + m0 + j];
   }
   __syncthreads();
-  const cplx* res = lds_fft(b0, b1, d.pz, tw, -1, nf * tcn, G, tid, NTC);
-  for (int e = tid; e < tcn * Nz; e += NTC) {
+  ip_fft(b0, d.pz, tw, -1, nf * tcn, G, tid, NT);
+  const cplx* res = b0;
+  for (int e = tid; e < tcn * Nz; e += NT) {
     const int j = e / Nz, n = e - j * Nz, m = m0 + j;
     const long long k = (long long)m * Nz + n;
     const int row = cou_zrow(n, Nz, G);
@@ -386,11 +461,35 @@ __global__ void __launch_bounds__(NTC) cou_zinv_adj(CouDev d, const cplx* Gb, in
   }
 }
 
-size_t col_lds(int G, int nf, int tc) { return sizeof(cplx) * (G + 2 * (size_t)fpad_size(nf * tc * G)); }
-int col_tile(int G, int nf, int Kx) {
-  int tc = 8;
-  while (tc > 1 && col_lds(G, nf, tc) > kCouLdsBudget) --tc;
-  return std::min(tc, Kx);
+// Launch shapes.  A block transforms in place at most 6 NT points (ip_fft); the column kernels
+// take x-mode tiles of tc columns of nf fields.  Blocks of 256 threads with at most kCouLdsBudget
+// bytes of LDS, so that several share a CU; 1024 threads where one column of nf fields needs
+// more.
+constexpr int kColSmall = 256, kColLarge = 1024;
+size_t lds_bytes(int G, int points) { return sizeof(cplx) * (G + (size_t)fpad_size(points)); }
+int pick_nt(int points) { return points <= 6 * 256 ? 256 : (points <= 6 * 512 ? 512 : 1024); }
+
+struct ColShape {
+  int nt = kColSmall, tc = 1;
+  size_t lds = 0;
+};
+ColShape col_shape(int G, int nf, int Kx) {
+  ColShape c;
+  c.nt = (nf * G <= 6 * kColSmall) ? kColSmall : kColLarge;
+  SPS_REQUIRE(nf * G <= 6 * c.nt, "padded z grid too large for the plane kernels");
+  int tc = std::min(8, Kx);
+  while (tc > 1 && (nf * tc * G > 6 * c.nt || lds_bytes(G, nf * tc * G) > kCouLdsBudget)) --tc;
+  c.tc = tc;
+  c.lds = lds_bytes(G, nf * tc * G);
+  SPS_REQUIRE(c.lds <= kCouLdsMax, "padded z grid too large for LDS");
+  return c;
+}
+
+template <typename F1, typename F2>
+void launch_col(const ColShape& c, F1 small, F2 large, dim3 grid, hipStream_t s) {
+  if (c.nt == kColSmall) small(grid, s);
+  else large(grid, s);
+  SPS_CHECK_LAUNCH();
 }
 
 }  // namespace
@@ -398,7 +497,9 @@ int col_tile(int G, int nf, int Kx) {
 struct CouettePlanes::Impl {
   CouDev d{};
   DevArena arena;
-  int tcA = 1, tcC = 1, tcA2 = 1, capB = 0, capB2 = 0;
+  ColShape A, C, A2;
+  int ntB = 256, ntB2 = 256;
+  size_t ldsB = 0, ldsB2 = 0;
   cplx *Zf = nullptr, *Wf = nullptr, *Zv = nullptr, *Wbv = nullptr, *Gv = nullptr;
 };
 
@@ -417,19 +518,24 @@ CouettePlanes::CouettePlanes(const CouetteGeom& g, hipStream_t s) : p_(new Impl)
   d.lz = g.lz;
   d.du = g.dunode;
   SPS_REQUIRE(fft_plan(g.Ngx, &d.px) && fft_plan(g.Ngz, &d.pz), "padded plane sizes must factor into 2 and 3");
+  SPS_REQUIRE(15 * g.Ngx <= 6 * 1024, "padded x grid too large for the plane kernels");
   d.unode = m.arena.upload(std::vector<double>(g.unode, g.unode + g.Ngy), s);
   d.twx = m.arena.upload(twiddles(g.Ngx), s);
   d.twz = m.arena.upload(twiddles(g.Ngz), s);
-  m.tcA = col_tile(g.Ngz, 4, g.Kx);
-  m.tcC = col_tile(g.Ngz, 3, g.Kx);
-  m.tcA2 = col_tile(g.Ngz, 8, g.Kx);
-  m.capB = fpad_size(12 * g.Ngx);
-  m.capB2 = fpad_size(15 * g.Ngx);
-  const size_t lb2 = sizeof(cplx) * (g.Ngx + 2 * (size_t)m.capB2);
-  SPS_REQUIRE(lb2 <= kCouLdsMax && col_lds(g.Ngz, 8, m.tcA2) <= kCouLdsMax, "plane sizes too large for LDS");
-  for (const void* k : {(const void*)cou_zinv, (const void*)cou_xrow<256>, (const void*)cou_xrow<512>,
-                        (const void*)cou_zfwd, (const void*)cou_zfwd_adj, (const void*)cou_xrow_adj<256>,
-                        (const void*)cou_xrow_adj<512>, (const void*)cou_zinv_adj})
+  m.A = col_shape(g.Ngz, 4, g.Kx);
+  m.C = col_shape(g.Ngz, 3, g.Kx);
+  m.A2 = col_shape(g.Ngz, 8, g.Kx);
+  m.ntB = pick_nt(12 * g.Ngx);
+  m.ntB2 = pick_nt(15 * g.Ngx);
+  m.ldsB = lds_bytes(g.Ngx, 12 * g.Ngx);
+  m.ldsB2 = lds_bytes(g.Ngx / 2, 15 * g.Ngx);
+  SPS_REQUIRE(m.ldsB2 <= kCouLdsMax, "padded x grid too large for LDS");
+  for (const void* k :
+       {(const void*)cou_zinv<kColSmall>, (const void*)cou_zinv<kColLarge>, (const void*)cou_zfwd<kColSmall>,
+        (const void*)cou_zfwd<kColLarge>, (const void*)cou_zfwd_adj<kColSmall>, (const void*)cou_zfwd_adj<kColLarge>,
+        (const void*)cou_zinv_adj<kColSmall>, (const void*)cou_zinv_adj<kColLarge>, (const void*)cou_xrow<256>,
+        (const void*)cou_xrow<512>, (const void*)cou_xrow<1024>, (const void*)cou_xrow_adj<256>,
+        (const void*)cou_xrow_adj<512>, (const void*)cou_xrow_adj<1024>})
     SPS_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCouLdsMax));
   const size_t plane = (size_t)g.Ngy * g.Ngz * g.Kx;
   m.Zf = m.arena.alloc<cplx>(12 * plane);
@@ -441,44 +547,71 @@ CouettePlanes::CouettePlanes(const CouetteGeom& g, hipStream_t s) : p_(new Impl)
 CouettePlanes::~CouettePlanes() = default;
 
 namespace {
-void launch_zinv(const CouDev& d, int tc, const cplx* zg, cplx* Z, hipStream_t s) {
-  hipLaunchKernelGGL(cou_zinv, dim3((d.Kx + tc - 1) / tc, 3, d.Ngy), dim3(NTC), col_lds(d.Ngz, 4, tc), s, d, zg, tc,
-                     Z);
-  SPS_CHECK_LAUNCH();
+// (x-mode tiles, groups, Ngy) for the kernels that read y from blockIdx.z (A, A'); (x-mode
+// tiles, Ngy) for C and C', which read it from blockIdx.y.
+dim3 col_grid(const CouDev& d, const ColShape& c, int groups) { return dim3((d.Kx + c.tc - 1) / c.tc, groups, d.Ngy); }
+dim3 col_grid_y(const CouDev& d, const ColShape& c) { return dim3((d.Kx + c.tc - 1) / c.tc, d.Ngy); }
+
+void launch_zinv(const CouDev& d, const ColShape& c, const cplx* zg, cplx* Z, hipStream_t s) {
+  launch_col(
+      c, [&](dim3 g, hipStream_t st) { hipLaunchKernelGGL(cou_zinv<kColSmall>, g, dim3(kColSmall), c.lds, st, d, zg, c.tc, Z); },
+      [&](dim3 g, hipStream_t st) { hipLaunchKernelGGL(cou_zinv<kColLarge>, g, dim3(kColLarge), c.lds, st, d, zg, c.tc, Z); },
+      col_grid(d, c, 3), s);
 }
+
 }  // namespace
 
 void CouettePlanes::forward(const double2* zg, double2* nl, hipStream_t s) {
   Impl& m = *p_;
   const CouDev& d = m.d;
-  launch_zinv(d, m.tcA, zg, m.Zf, s);
-  const size_t lb = sizeof(cplx) * (d.Ngx + 2 * (size_t)m.capB);
-  if (d.Ngx >= 96)
-    hipLaunchKernelGGL(cou_xrow<512>, dim3(d.Ngz / 2, d.Ngy), dim3(512), lb, s, d, m.Zf, m.capB, m.Wf);
+  launch_zinv(d, m.A, zg, m.Zf, s);
+  const dim3 gb(d.Ngz / 2, d.Ngy);
+  if (m.ntB == 256)
+    hipLaunchKernelGGL(cou_xrow<256>, gb, dim3(256), m.ldsB, s, d, m.Zf, m.Wf);
+  else if (m.ntB == 512)
+    hipLaunchKernelGGL(cou_xrow<512>, gb, dim3(512), m.ldsB, s, d, m.Zf, m.Wf);
   else
-    hipLaunchKernelGGL(cou_xrow<256>, dim3(d.Ngz / 2, d.Ngy), dim3(256), lb, s, d, m.Zf, m.capB, m.Wf);
+    hipLaunchKernelGGL(cou_xrow<1024>, gb, dim3(1024), m.ldsB, s, d, m.Zf, m.Wf);
   SPS_CHECK_LAUNCH();
-  hipLaunchKernelGGL(cou_zfwd, dim3((d.Kx + m.tcC - 1) / m.tcC, d.Ngy), dim3(NTC), col_lds(d.Ngz, 3, m.tcC), s, d,
-                     m.Wf, m.tcC, nl);
-  SPS_CHECK_LAUNCH();
+  const ColShape& c = m.C;
+  launch_col(
+      c, [&](dim3 g, hipStream_t st) { hipLaunchKernelGGL(cou_zfwd<kColSmall>, g, dim3(kColSmall), c.lds, st, d, m.Wf, c.tc, nl); },
+      [&](dim3 g, hipStream_t st) { hipLaunchKernelGGL(cou_zfwd<kColLarge>, g, dim3(kColLarge), c.lds, st, d, m.Wf, c.tc, nl); },
+      col_grid_y(d, c), s);
 }
 
 void CouettePlanes::vjp(const double2* nlbar, const double2* zg, double2* zbar, hipStream_t s) {
   Impl& m = *p_;
   const CouDev& d = m.d;
-  launch_zinv(d, m.tcA, zg, m.Zv, s);
-  hipLaunchKernelGGL(cou_zfwd_adj, dim3((d.Kx + m.tcC - 1) / m.tcC, d.Ngy), dim3(NTC), col_lds(d.Ngz, 3, m.tcC), s,
-                     d, nlbar, m.tcC, m.Wbv);
-  SPS_CHECK_LAUNCH();
-  const size_t lb = sizeof(cplx) * (d.Ngx + 2 * (size_t)m.capB2);
-  if (d.Ngx >= 96)
-    hipLaunchKernelGGL(cou_xrow_adj<512>, dim3(d.Ngz / 2, d.Ngy), dim3(512), lb, s, d, m.Zv, m.Wbv, m.capB2, m.Gv);
+  launch_zinv(d, m.A, zg, m.Zv, s);
+  const ColShape& c = m.C;
+  launch_col(
+      c,
+      [&](dim3 g, hipStream_t st) {
+        hipLaunchKernelGGL(cou_zfwd_adj<kColSmall>, g, dim3(kColSmall), c.lds, st, d, nlbar, c.tc, m.Wbv);
+      },
+      [&](dim3 g, hipStream_t st) {
+        hipLaunchKernelGGL(cou_zfwd_adj<kColLarge>, g, dim3(kColLarge), c.lds, st, d, nlbar, c.tc, m.Wbv);
+      },
+      col_grid_y(d, c), s);
+  const dim3 gb(d.Ngz / 2, d.Ngy);
+  if (m.ntB2 == 256)
+    hipLaunchKernelGGL(cou_xrow_adj<256>, gb, dim3(256), m.ldsB2, s, d, m.Zv, m.Wbv, m.Gv);
+  else if (m.ntB2 == 512)
+    hipLaunchKernelGGL(cou_xrow_adj<512>, gb, dim3(512), m.ldsB2, s, d, m.Zv, m.Wbv, m.Gv);
   else
-    hipLaunchKernelGGL(cou_xrow_adj<256>, dim3(d.Ngz / 2, d.Ngy), dim3(256), lb, s, d, m.Zv, m.Wbv, m.capB2, m.Gv);
+    hipLaunchKernelGGL(cou_xrow_adj<1024>, gb, dim3(1024), m.ldsB2, s, d, m.Zv, m.Wbv, m.Gv);
   SPS_CHECK_LAUNCH();
-  hipLaunchKernelGGL(cou_zinv_adj, dim3((d.Kx + m.tcA2 - 1) / m.tcA2, 2, d.Ngy), dim3(NTC), col_lds(d.Ngz, 8, m.tcA2),
-                     s, d, m.Gv, m.tcA2, zbar);
-  SPS_CHECK_LAUNCH();
+  const ColShape& a2 = m.A2;
+  launch_col(
+      a2,
+      [&](dim3 g, hipStream_t st) {
+        hipLaunchKernelGGL(cou_zinv_adj<kColSmall>, g, dim3(kColSmall), a2.lds, st, d, m.Gv, a2.tc, zbar);
+      },
+      [&](dim3 g, hipStream_t st) {
+        hipLaunchKernelGGL(cou_zinv_adj<kColLarge>, g, dim3(kColLarge), a2.lds, st, d, m.Gv, a2.tc, zbar);
+      },
+      col_grid(d, a2, 2), s);
 }
 
 }  // namespace sps
