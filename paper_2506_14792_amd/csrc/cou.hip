@@ -113,28 +113,23 @@ __device__ __forceinline__ void ip_pass(cplx* buf, const FftPlan& p, int s, cons
       const int k = j - jh * Ns;
       const int t = k * tst;
       const int base = q * bstride;
+      // all LDS reads of the butterfly first (one wait), then the twiddle products
+      cplx w[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        cplx x = buf[fpad(base + j + r * nR)];
-        if (r > 0) {
-          const int ti = r * t;
-          cplx w;
-          if (HALF) {
-            const int hn = p.n >> 1;
-            if (ti < hn) {
-              w = tw[ti];
-            } else {
-              const cplx u = tw[ti - hn];
-              w = cmk(-u.x, -u.y);
-            }
-          } else {
-            w = tw[ti];
-          }
-          if (sign > 0) w = cconj(w);
-          x = cmul(x, w);
+      for (int r = 0; r < R; ++r) v[b][r] = buf[fpad(base + j + r * nR)];
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const int ti = r * t;
+        if (HALF) {
+          const int hn = p.n >> 1;
+          const cplx u = tw[ti < hn ? ti : ti - hn];
+          w[r] = (ti < hn) ? u : cmk(-u.x, -u.y);
+        } else {
+          w[r] = tw[ti];
         }
-        v[b][r] = x;
       }
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], sign > 0 ? cconj(w[r]) : w[r]);
       dft_small<R>(v[b], sign);
       dst[b] = base + jh * Ns * R + k;
     }
