@@ -240,3 +240,31 @@ class RBC:
             c[0] = c[0].real
             Xb[:, self.sl(f)] = self.Lx * wk[:, None] * (c @ G.T)
         return Xb
+
+    # ------------------------------------------------------------------ linear boundary value problem
+    # Supplementary, "Linear boundary value problems": L X = F(p), adjoint state equation
+    # L^H Y = G through the same LU factors, then the VJP of F.  Here F(f) = M f + c: the steady
+    # state of the IVP without its explicit term, driven by body forces and a heat source f
+    # (the u, w, b blocks of a state-shaped array, T coefficients; other slots ignored) with the
+    # IVP's boundary data c.  Its solution is an admissible IVP initial state (no-slip,
+    # divergence-free, the IVP's buoyancy boundary values), the Cartesian counterpart of the
+    # paper's LBVP-then-IVP chain.
+
+    def lbvp_rhs(self, f):
+        R = self.Fconst.copy()
+        for name in ("u", "w", "b"):
+            R[:, self.sl(name)] += f[:, self.sl(name)] @ self.S10.T
+        return R
+
+    def lbvp_solve(self, f):
+        """X with L_k X_k = (M f + c)_k for every wavenumber k (dense LU, partial pivoting)."""
+        R = self.lbvp_rhs(f)
+        return np.stack([np.linalg.solve(self.L[k], R[k]) for k in range(self.K)])
+
+    def lbvp_adjoint(self, Xbar):
+        """fbar = M^H L^-H Xbar, the cotangent of f (p and tau slots zero)."""
+        Y = np.stack([np.linalg.solve(self.L[k].conj().T, Xbar[k]) for k in range(self.K)])
+        fb = np.zeros_like(Y)
+        for name in ("u", "w", "b"):
+            fb[:, self.sl(name)] = Y[:, self.sl(name)] @ self.S10
+        return fb
