@@ -215,6 +215,27 @@ int sps_eval_F_vjp(sps_problem *P, const double *X, const double *Fbar, double *
  * scheme's implicit matrix (RK222: M + dt*gamma*L; SBDF2: 3/(2dt) M + L). */
 int sps_solve(sps_problem *P, const double *R, double *X, int adjoint);
 
+/* Linear boundary value problem of the 2D problem's operator (Supplementary, "Linear boundary
+ * value problems"): L X = M f + c, the steady state of the IVP without its explicit term,
+ * driven by body forces and a heat source f, with the IVP's boundary data c (no-slip walls,
+ * b(0) = 1 and b(1) = 0 for the horizontal mean, the pressure gauge).  f and X are device
+ * arrays in the state layout; only the u, w, b coefficient blocks of f are read (T_n(2z-1)
+ * coefficients of the forcing of each equation), its p and tau slots are ignored.  X is the
+ * full solution (velocity, buoyancy, pressure, taus): an admissible initial state for
+ * sps_step / sps_gradient, so that an IVP cost can be differentiated through the LBVP.
+ * L is LU-factored per wavenumber on the first call (the blocked almost-banded factors of the
+ * IVP, a second set held by the problem until sps_destroy) and reused by every later call and
+ * by sps_lbvp_adjoint.  A zero pivot sets the sticky device flag (sps_sync returns
+ * SPS_E_SINGULAR).  SPS_E_UNSUPPORTED for problems other than SPS_RBC2D. */
+int sps_lbvp_solve(sps_problem *P, const double *f, double *X);
+
+/* Adjoint of sps_lbvp_solve: the adjoint state equation L^H Y = Xbar through the same
+ * factors, then the VJP of the right-hand side, fbar = M^H Y (u, w, b blocks; zero p and tau
+ * slots).  Xbar is the cotangent of X (for example dJ/dX_0 from sps_adjoint_step); fbar is the
+ * gradient with respect to the forcing coefficients in the real inner product of the state
+ * layout.  Device arrays; asynchronous like every call. */
+int sps_lbvp_adjoint(sps_problem *P, const double *Xbar, double *fbar);
+
 /* Kernel timing of one kernel class inside the library (HIP events around each launch on
  * the problem's stream).  kind: 0 = per-wavenumber forward stage kernel (transforms in z,
  * RHS assembly, banded solve).  sps_timer_read returns launches and total milliseconds

@@ -1,6 +1,7 @@
 """torch.autograd bindings of the library: the forward sweep and its discrete adjoint
 (equ:adjoint; the reverse sweep with checkpoint-and-recompute of the Supplementary's IVP
-adjoint), the initial transform of a grid field and the built-in cost.
+adjoint), the initial transform of a grid field, the boundary value problem of the operator
+and the built-in cost.
 
 States are float64 CUDA tensors in the library's state layout (complex coefficients as
 (re, im) pairs); cotangents use the real inner product of that layout, which is the
@@ -67,6 +68,28 @@ class Cost(torch.autograd.Function):
     def backward(ctx, gJ):
         (dJ,) = ctx.saved_tensors
         return dJ * gJ, None
+
+
+class Lbvp(torch.autograd.Function):
+    """X = L^-1 (M f + c), the boundary value problem of the operator (Supplementary, "Linear
+    boundary value problems"); backward is its adjoint, M^H L^-H through the same factors."""
+
+    @staticmethod
+    def forward(ctx, f, problem):
+        X = torch.zeros(problem.n, dtype=torch.float64, device=f.device)
+        problem.lbvp_solve(f.detach().contiguous(), X)
+        ctx.problem = problem
+        return X
+
+    @staticmethod
+    def backward(ctx, gX):
+        g = torch.zeros_like(gX)
+        ctx.problem.lbvp_adjoint(gX.detach().contiguous(), g)
+        return g, None
+
+
+def lbvp(f, problem):
+    return Lbvp.apply(f, problem)
 
 
 def step(X0, problem, nsteps):

@@ -162,6 +162,14 @@ int sps_solve(sps_problem* P, const double* R, double* X, int adjoint) {
   return guard(P, [&](sps::ProblemImpl& p) { p.solve(R, X, adjoint); });
 }
 
+int sps_lbvp_solve(sps_problem* P, const double* f, double* X) {
+  return guard(P, [&](sps::ProblemImpl& p) { p.lbvp_solve(f, X); });
+}
+
+int sps_lbvp_adjoint(sps_problem* P, const double* Xbar, double* fbar) {
+  return guard(P, [&](sps::ProblemImpl& p) { p.lbvp_adjoint(Xbar, fbar); });
+}
+
 int sps_timer_enable(sps_problem* P, int kind, int on) {
   return guard(P, [&](sps::ProblemImpl& p) { p.timer_enable(kind, on != 0); });
 }

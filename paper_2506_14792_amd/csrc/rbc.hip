@@ -1084,6 +1084,39 @@ __global__ void __launch_bounds__(NT) rbc_factor(RbcDev d, const double* BM, con
                     sh, spiv, ops + (size_t)k * d.opsize, d.err);
 }
 
+// ---------------------------------------------------------------------------- linear boundary value problem
+// L X = M f + c (Supplementary, "Linear boundary value problems"): the steady state of the IVP
+// without its explicit term, driven by the forcing f (u, w, b blocks of a state-shaped array)
+// with the IVP's boundary data c.  Right-hand side in equation-row slots: S10 f in the C2 rows
+// of u, w, b, zero continuity and gauge rows, b(0) = bc0 at k = 0.  One block per wavenumber.
+__global__ void __launch_bounds__(NT) rbc_lbvp_rhs(RbcDev d, const cplx* f, cplx* R) {
+  const int k = blockIdx.x, N = d.N, S = d.S;
+  const cplx* fk = f + (size_t)k * S;
+  for (int s = threadIdx.x; s < S; s += NT) {
+    cplx v = czero();
+    if (s < 3 * N) {
+      const int q = s / N, n = s - q * N;
+      v = s10_at(fk + q * N, n, N);
+    } else if (k == 0 && s == 4 * N + 4) {
+      v = cmk(d.bc0, 0.0);
+    }
+    R[(size_t)k * S + s] = v;
+  }
+}
+// The VJP of the right-hand side: fbar = M^H Y on the u, w, b blocks, zero in the other slots.
+__global__ void __launch_bounds__(NT) rbc_lbvp_rhs_adj(RbcDev d, const cplx* Y, cplx* fbar) {
+  const int k = blockIdx.x, N = d.N, S = d.S;
+  const cplx* yk = Y + (size_t)k * S;
+  for (int s = threadIdx.x; s < S; s += NT) {
+    cplx v = czero();
+    if (s < 3 * N) {
+      const int q = s / N, m = s - q * N;
+      v = s10t_at(yk + q * N, m, N);
+    }
+    fbar[(size_t)k * S + s] = v;
+  }
+}
+
 // ---------------------------------------------------------------------------- initial state and its adjoint
 // x pass: one block per scale-1 z node; b0 laid out [x][z].
 __global__ void __launch_bounds__(NT) rbc_init_x(RbcDev d, const double* grid, cplx* tmp) {
@@ -1625,6 +1658,57 @@ class RbcProblem : public ProblemImpl {
     }
   }
 
+  // Linear boundary value problem L X = M f + c: L factored once (the same blocked LU as the
+  // IVP's matrix, with a = 0, b = 1), the forward solve and the adjoint through those factors.
+  void lbvp_factor() {
+    if (lfactored_) return;
+    if (!lops_) {
+      lops_ = arena_.alloc<double>((size_t)K_ * dv_.opsize);
+      lrhs_ = arena_.alloc<cplx>((size_t)K_ * S_);
+    }
+    hipLaunchKernelGGL(rbc_factor, dim3(K_), dim3(NT), factor_lds(), stream, dv_, BM_, BL_, 0.0, 1.0, lops_);
+    SPS_CHECK_LAUNCH();
+    lfactored_ = true;
+  }
+
+  void lbvp_solve(const double* f, double* X) override {
+    if (cou_) throw Error(SPS_E_UNSUPPORTED, "the boundary value problem is built for the 2D problem");
+    SPS_REQUIRE(f && X, "null argument");
+    lbvp_factor();
+    hipLaunchKernelGGL(rbc_lbvp_rhs, dim3(K_), dim3(NT), 0, stream, dv_, reinterpret_cast<const cplx*>(f), lrhs_);
+    SPS_CHECK_LAUNCH();
+    RbcDev dl = dv_;
+    dl.ops = lops_;
+    KfArgs a{};
+    a.X0 = lrhs_;
+    a.X1 = nullptr;
+    a.Xout = reinterpret_cast<cplx*>(X);
+    a.nl = nl_;
+    a.F0 = F0_;
+    a.zg = nullptr;
+    a.dt = dt_;
+    a.g = 1.0 - 1.0 / std::sqrt(2.0);
+    a.dl = 1.0 - 1.0 / (2.0 * a.g);
+    a.mode = KF_SOLVE;
+    hipLaunchKernelGGL(kfwd_fn(), dim3(K_), dim3(NTK), kf_lds(), stream, dl, a);
+    SPS_CHECK_LAUNCH();
+  }
+
+  void lbvp_adjoint(const double* Xbar, double* fbar) override {
+    if (cou_) throw Error(SPS_E_UNSUPPORTED, "the boundary value problem is built for the 2D problem");
+    SPS_REQUIRE(Xbar && fbar, "null argument");
+    lbvp_factor();
+    RbcDev dl = dv_;
+    dl.ops = lops_;
+    KaArgs a = ka_args(KA_SOLVE_T);
+    a.Xb_in = reinterpret_cast<const cplx*>(Xbar);
+    a.Xb_out = lrhs_;
+    hipLaunchKernelGGL(kadj_fn(), dim3(K_), dim3(NTK), ka_lds(), stream, dl, a);
+    SPS_CHECK_LAUNCH();
+    hipLaunchKernelGGL(rbc_lbvp_rhs_adj, dim3(K_), dim3(NT), 0, stream, dv_, lrhs_, reinterpret_cast<cplx*>(fbar));
+    SPS_CHECK_LAUNCH();
+  }
+
   void timer_enable(int kind, bool on) override {
     SPS_REQUIRE(kind == 0, "unknown timer kind");
     timer_.enable(on);
@@ -1975,6 +2059,9 @@ class RbcProblem : public ProblemImpl {
   RbcDev dv_{};
   DevArena arena_;
   double *BM_ = nullptr, *BL_ = nullptr, *ops_ = nullptr, *Jpart_ = nullptr;
+  double* lops_ = nullptr;   // LU block operators of L alone (boundary value problem), built on first use
+  cplx* lrhs_ = nullptr;
+  bool lfactored_ = false;
   int *err_ = nullptr;
   cplx *X1_, *Xw_, *Xg_, *acc_, *Ybuf_, *F0_, *zgA_, *zbar_, *nl_, *nlbar_, *itmp_, *ckpt_, *seg_;
   size_t zsize_ = 0;

@@ -125,6 +125,12 @@ class ProblemImpl {
   virtual void eval_F(const double* X, double* F) = 0;
   virtual void eval_F_vjp(const double* X, const double* Fbar, double* Xbar) = 0;
   virtual void solve(const double* R, double* X, int adjoint) = 0;
+  virtual void lbvp_solve(const double*, double*) {
+    throw Error(SPS_E_UNSUPPORTED, "no boundary value problem for this equation");
+  }
+  virtual void lbvp_adjoint(const double*, double*) {
+    throw Error(SPS_E_UNSUPPORTED, "no boundary value problem for this equation");
+  }
   virtual void timer_enable(int kind, bool on) = 0;
   virtual void timer_read(long long* launches, double* ms) = 0;
   virtual int device_error() = 0;  // reads and clears the sticky device flag

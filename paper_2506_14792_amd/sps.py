@@ -53,6 +53,8 @@ def lib():
         "sps_eval_F": (ctypes.c_int, [_P, _D, _D]),
         "sps_eval_F_vjp": (ctypes.c_int, [_P, _D, _D, _D]),
         "sps_solve": (ctypes.c_int, [_P, _D, _D, ctypes.c_int]),
+        "sps_lbvp_solve": (ctypes.c_int, [_P, _D, _D]),
+        "sps_lbvp_adjoint": (ctypes.c_int, [_P, _D, _D]),
         "sps_timer_enable": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
         "sps_timer_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double)]),
         "sps_set_graph": (ctypes.c_int, [_P, ctypes.c_int]),
@@ -176,6 +178,14 @@ class Problem:
 
     def solve(self, R, X, adjoint=False):
         _check(lib().sps_solve(self._h, _ptr(R, self.n), _ptr(X, self.n), int(bool(adjoint))))
+
+    def lbvp_solve(self, f, X):
+        """X = L^-1 (M f + c): the boundary value problem of the operator (2D problem only)."""
+        _check(lib().sps_lbvp_solve(self._h, _ptr(f, self.n), _ptr(X, self.n)))
+
+    def lbvp_adjoint(self, Xbar, fbar):
+        """fbar = M^H L^-H Xbar: the cotangent of the forcing of lbvp_solve."""
+        _check(lib().sps_lbvp_adjoint(self._h, _ptr(Xbar, self.n), _ptr(fbar, self.n)))
 
     def timer_enable(self, kind=0, on=True):
         _check(lib().sps_timer_enable(self._h, kind, int(bool(on))))
