@@ -206,6 +206,72 @@ def sh_timing(reps=2):
             "oracle_cpu_gradient_s_extrapolated": ocpu}
 
 
+def lbvp_timing(reps=200):
+    """Boundary value problem of the headline operator (256 x 64, Lx = 4, Ra = 1e6, Pr = 1):
+    L X = M f + c with L factored once, the solve and the adjoint (L^H Y = Xbar through the same
+    factors, then M^H Y) per call, and the LBVP-then-IVP gradient: the seeded smooth forcing's
+    gradient of the kinetic energy after the 1000-step RK222 run (sps_lbvp_solve, sps_gradient,
+    sps_lbvp_adjoint) against the IVP gradient alone.  Algorithmic bytes of a solve: the LU
+    factors once (as counted for the stage kernel) plus the input, the right-hand side (out and
+    in) and the output, 4 S x 16 B per wavenumber."""
+    import torch
+    import workloads as wl
+    import paper_2506_14792_amd as sps
+    from oracle.rbc import RBC
+    c = CFG
+    n = c["nsteps"]
+    G = sps.Problem(sps.RBC2D, c["nx"], c["nz"], c["lx"], c["Ra"], c["Pr"], 1.5, c["dt"], c["checkpoint_every"], n)
+    fh = wl.rbc_forcing(seed=c["seed"], Nx=c["nx"], Nz=c["nz"])
+    f = torch.from_numpy(fh.view(np.float64).ravel().copy()).cuda()
+    X = torch.zeros(G.n, dtype=torch.float64, device="cuda")
+    fb = torch.zeros_like(X)
+    G.factor()
+    G.lbvp_solve(f, X)            # factors L on the first call
+    G.lbvp_adjoint(X, fb)
+    torch.cuda.synchronize()
+
+    def timed(fn, k):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / k
+
+    solve_s = timed(lambda: G.lbvp_solve(f, X), reps)
+    adj_s = timed(lambda: G.lbvp_adjoint(X, fb), reps)
+    K, S = c["nx"] // 2, 4 * c["nz"] + 7
+    kl, ku = 7, 20
+    bytes_solve = K * (S * (kl + kl + ku + 1) * 8 + S * 4 + 4 * S * 16)
+    g = torch.zeros_like(X)
+    J = torch.zeros(1, dtype=torch.float64, device="cuda")
+    G.lbvp_solve(f, X)
+    X0 = X.clone()
+    G.gradient(X0, n, None, g, J)
+
+    def chain():
+        G.lbvp_solve(f, X)
+        G.gradient(X, n, None, g, J)
+        G.lbvp_adjoint(g, fb)
+
+    ivp_s = timed(lambda: G.gradient(X0, n, None, g, J), 3)
+    chain_s = timed(chain, 3)
+    G.sync()
+    P = RBC(Nx=c["nx"], Nz=c["nz"], Lx=c["lx"], Ra=c["Ra"], Pr=c["Pr"])
+    t0 = time.perf_counter()
+    P.lbvp_adjoint(P.lbvp_solve(fh))
+    ocpu = time.perf_counter() - t0
+    return {"workload": "boundary value problem L X = M f + c of the Rayleigh-Benard operator, 256x64, Ra=1e6, "
+                        "Pr=1 (steady Stokes-Boussinesq with the IVP's walls), seeded smooth forcing; its solution "
+                        "starts the 1000-step RK222 run whose kinetic energy is differentiated w.r.t. the forcing",
+            "solve_ms": solve_s * 1e3, "adjoint_ms": adj_s * 1e3,
+            "bytes_per_solve": bytes_solve, "solve_hbm_GBps": bytes_solve / solve_s / 1e9,
+            "solve_hbm_frac": bytes_solve / solve_s / 1e9 / HBM_PEAK_GBS,
+            "ivp_gradient_s": ivp_s, "lbvp_ivp_gradient_s": chain_s, "J": J.item(),
+            "oracle_cpu_solve_plus_adjoint_s": ocpu,
+            "speedup_vs_oracle": ocpu / (solve_s + adj_s)}
+
+
 COU_CFG = dict(nx=128, ny=64, nz=64, Lx=4.0 * np.pi, Lz=2.0 * np.pi, Re=400.0, dt=0.01, nsteps=2000,
                checkpoint_every=100, seed=0, energy=1e-6)
 
@@ -357,7 +423,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--skip-extra", action="store_true",
                     help="only the headline configuration (for counter and trace runs)")
-    ap.add_argument("--only", choices=["ks", "sh", "closure", "couette"], default=None,
+    ap.add_argument("--only", choices=["ks", "sh", "closure", "couette", "lbvp"], default=None,
                     help="run one secondary configuration alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -370,7 +436,8 @@ def main():
     if args.only:
         import torch
         torch.cuda.set_device(0)
-        fn = {"ks": ks_timing, "sh": sh_timing, "closure": kolmo_timing, "couette": couette_timing}[args.only]
+        fn = {"ks": ks_timing, "sh": sh_timing, "closure": kolmo_timing, "couette": couette_timing,
+              "lbvp": lbvp_timing}[args.only]
         print(json.dumps({args.only: fn()}))
         return
 
@@ -442,8 +509,9 @@ def main():
     G.sync()
     graph_sec = (t7 - t6) / args.steps
     traffic = measured_traffic()
-    ks = sh = kol = cou = None
+    ks = sh = kol = cou = lbvp = None
     if not args.skip_extra:
+        lbvp = lbvp_timing()
         ks = ks_timing()
         sh = sh_timing()
         kol = kolmo_timing()
@@ -481,6 +549,7 @@ def main():
         "sh_batched_config": sh,
         "closure_config": kol,
         "couette_autograd_config": cou,
+        "lbvp_config": lbvp,
         "J": J.item(),
     }
     print(json.dumps(out))

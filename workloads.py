@@ -21,6 +21,19 @@ def rbc_b0(seed=0, Nx=256, Nz=64, amp=1e-3):
     return (1.0 - z)[None, :] + amp * xi * (4.0 * z * (1.0 - z))[None, :]
 
 
+def rbc_forcing(seed=0, Nx=256, Nz=64, amp=1e-5, nmodes=4):
+    """Forcing of the 2D boundary value problem in the state layout (K = Nx/2 wavenumbers,
+    S = 4 Nz + 7 slots): i.i.d. complex normal coefficients of size amp in the first nmodes
+    Chebyshev modes of the u, w, b blocks at every wavenumber (real at k = 0), zero elsewhere."""
+    rng = np.random.default_rng(seed)
+    K, S = Nx // 2, 4 * Nz + 7
+    f = np.zeros((K, S), dtype=complex)
+    for q in range(3):
+        f[:, q * Nz:q * Nz + nmodes] = amp * (rng.standard_normal((K, nmodes)) + 1j * rng.standard_normal((K, nmodes)))
+    f[0] = f[0].real
+    return f
+
+
 def ks_c0(seed=0, Nx=64, amp=1e-2):
     """Initial half-spectrum coefficients c_m = amp (1 + m)^-2 (xi + i eta), m < Nx/2,
     with a real mean mode; returned as an (Nx/2,) complex array."""
