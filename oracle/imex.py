@@ -148,15 +148,28 @@ def rk_adjoint(P, Xbar_N, history, dt, tableau=None):
 # ----------------------------------------------------------------------------- IMEX multistep (SBDF)
 
 
+# SBDF-k at a constant step (Wang & Ruuth 2008): the k-step backward difference for M dX/dt
+# (a_i dt, i = 0..k) and the k-th order extrapolation of F from the previous k steps (c_i,
+# i = 1..k); L is implicit at the new step only (b_0 = 1).
+SBDF_ROWS = {
+    1: ([1.0, -1.0], [1.0]),
+    2: ([1.5, -2.0, 0.5], [2.0, -1.0]),
+    3: ([11.0 / 6.0, -3.0, 1.5, -1.0 / 3.0], [3.0, -3.0, 1.0]),
+    4: ([25.0 / 12.0, -4.0, 3.0, -4.0 / 3.0, 0.25], [4.0, -6.0, 4.0, -1.0]),
+}
+
+
 def sbdf_coefficients(n, dt, order=2):
     """Coefficients (a_i, b_i, c_i) of step n (n = 1, 2, ...) of the multistep scheme
-    (a_0 M + b_0 L) X_n = sum_{i>=1} [c_i F(X_{n-i}) - (a_i M + b_i L) X_{n-i}],
-    SBDF2 reverting to SBDF1 on the first step (Wang & Ruuth 2008)."""
-    if order == 1 or n == 1:
-        return np.array([1.0 / dt, -1.0 / dt]), np.array([1.0, 0.0]), np.array([0.0, 1.0])
-    return (np.array([1.5 / dt, -2.0 / dt, 0.5 / dt]),
-            np.array([1.0, 0.0, 0.0]),
-            np.array([0.0, 2.0, -1.0]))
+    (a_0 M + b_0 L) X_n = sum_{i>=1} [c_i F(X_{n-i}) - (a_i M + b_i L) X_{n-i}] (equ:imex):
+    SBDF-order, reverting to SBDF-n while fewer than `order` previous steps exist."""
+    q = min(n, order)
+    al, be = SBDF_ROWS[q]
+    a = np.array(al) / dt
+    b = np.zeros(q + 1)
+    b[0] = 1.0
+    c = np.concatenate([[0.0], be])
+    return a, b, c
 
 
 def sbdf_forward(P, X0, dt, nsteps, order=2):

@@ -2,6 +2,7 @@
 nonlinearity, exact products against numpy's FFT on a fine grid, the inner-product
 test on F, Taylor remainders and brute-force finite differences."""
 import numpy as np
+import pytest
 
 from oracle import imex
 from oracle.ks import KS
@@ -41,37 +42,40 @@ def test_F_vjp_inner_product():
     assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
 
 
-def gradient(P, X0, dt, n):
-    XN, states = imex.sbdf_forward(P, X0, dt, n)
-    return P.energy(XN), imex.sbdf_adjoint(P, P.energy_grad(XN), states, dt)
+def gradient(P, X0, dt, n, order=2):
+    XN, states = imex.sbdf_forward(P, X0, dt, n, order=order)
+    return P.energy(XN), imex.sbdf_adjoint(P, P.energy_grad(XN), states, dt, order=order)
 
 
-def test_taylor_remainder_rate():
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_taylor_remainder_rate(order):
     P = KS()
     X0 = wl.ks_c0(seed=0)[:, None]
-    J, g = gradient(P, X0, 0.05, 200)
+    dt = 0.05
+    J, g = gradient(P, X0, dt, 200, order)
     d = wl.random_state(10, (P.K, 1))
     rem = []
     for e in (1e-4, 5e-5, 2.5e-5, 1.25e-5):
-        Je = P.energy(imex.sbdf_forward(P, X0 + e * d, 0.05, 200)[0])
+        Je = P.energy(imex.sbdf_forward(P, X0 + e * d, dt, 200, order=order)[0])
         rem.append(abs(Je - J - e * np.real(np.vdot(g, d))))
     rates = np.log2(np.array(rem[:-1]) / np.array(rem[1:]))
     assert np.all(np.abs(rates - 2.0) < 0.05), rates
 
 
-def test_brute_force_finite_differences_every_component():
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_brute_force_finite_differences_every_component(order):
     """8 modes x 10 steps: every real and imaginary component of the initial state."""
     P = KS(Nx=16, L=8.0)
     X0 = wl.ks_c0(seed=1, Nx=16, amp=0.5)[:, None]
     dt, n = 0.05, 10
-    J, g = gradient(P, X0, dt, n)
+    J, g = gradient(P, X0, dt, n, order)
     h = 1e-6
     for m in range(P.K):
         for part in (1.0, 1j):
             if m == 0 and part == 1j:
                 continue
             e = np.zeros_like(X0); e[m, 0] = h * part
-            fd = (P.energy(imex.sbdf_forward(P, X0 + e, dt, n)[0])
-                  - P.energy(imex.sbdf_forward(P, X0 - e, dt, n)[0])) / (2 * h)
+            fd = (P.energy(imex.sbdf_forward(P, X0 + e, dt, n, order=order)[0])
+                  - P.energy(imex.sbdf_forward(P, X0 - e, dt, n, order=order)[0])) / (2 * h)
             an = np.real(np.conj(part) * g[m, 0])
             assert abs(fd - an) <= 1e-7 * np.max(np.abs(g))

@@ -91,6 +91,52 @@ def test_heat_adjoint_closed_form():
     assert abs(g[0, 0] - G * G * X0[0, 0]) < 1e-15
 
 
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_sbdf_order_conditions_and_ramp(k):
+    """The steady row of SBDF-k is exact for polynomials in time of degree <= k: the backward
+    difference sum_j a_j X(t_n - j dt) = dX/dt(t_n) (sum_j a_j (-j)^p dt^(p-1) = p 0^(p-1)) and
+    the extrapolation sum_i c_i F(t_n - i dt) = F(t_n) for degree < k; the first k - 1 steps use
+    the lower-order rows (the scheme reverts while the history is short)."""
+    dt = 0.3
+    a, b, c = imex.sbdf_coefficients(k, dt, order=k)
+    j = np.arange(len(a))
+    assert len(a) == k + 1 and len(c) == k + 1 and b[0] == 1.0 and np.all(b[1:] == 0.0)
+    for p in range(k + 1):
+        target = 1.0 if p == 1 else 0.0
+        assert abs(np.sum(a * dt * (-j) ** p) - target) < 1e-13, (k, p)
+    for p in range(k):
+        target = 1.0 if p == 0 else 0.0
+        assert abs(np.sum(c[1:] * (-j[1:]) ** p) - target) < 1e-13, (k, p)
+    # one degree more is not exact (the order is k, not higher)
+    assert abs(np.sum(a * dt * (-j) ** (k + 1))) > 1e-3
+    for n in range(1, k):
+        an, bn, cn = imex.sbdf_coefficients(n, dt, order=k)
+        ar, br, cr = imex.sbdf_coefficients(n, dt, order=n)
+        assert np.array_equal(an, ar) and np.array_equal(cn, cr) and len(an) == n + 1
+
+
+@pytest.mark.parametrize("k", [3, 4])
+def test_sbdf_principal_root_converges_at_order_k_plus_1(k):
+    """For dX/dt = -lam X + mu X (lam implicit, mu explicit) the steady recurrence
+    (a_0 + lam) r^k = sum_i (c_i mu - a_i) r^(k-i) has a principal root r(h) with
+    |r(h) - exp((mu - lam) h)| = O(h^(k+1)) (local error of a k-th order scheme)."""
+    lam, mu = 1.7, 0.6
+    errs = []
+    hs = [0.08, 0.04, 0.02]
+    for h in hs:
+        a, b, c = imex.sbdf_coefficients(k, h, order=k)
+        poly = np.zeros(k + 1)
+        poly[0] = a[0] + lam
+        for i in range(1, k + 1):
+            poly[i] = a[i] - c[i] * mu
+        roots = np.roots(poly)
+        ex = np.exp((mu - lam) * h)
+        r = roots[np.argmin(np.abs(roots - ex))]
+        errs.append(abs(r - ex))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(np.abs(rates - (k + 1)) < 0.15), rates
+
+
 def random_linear(seed, K=3, S=4):
     rng = np.random.default_rng(seed)
     c = lambda: rng.standard_normal((K, S, S)) + 1j * rng.standard_normal((K, S, S))
@@ -98,7 +144,7 @@ def random_linear(seed, K=3, S=4):
     return Linear(M, 0.5 * c(), 0.3 * c())
 
 
-@pytest.mark.parametrize("stepper", ["rk", "sbdf"])
+@pytest.mark.parametrize("stepper", ["rk", "sbdf", "sbdf3", "sbdf4"])
 def test_linear_trajectory_inner_product(stepper):
     P = random_linear(5)
     rng = np.random.default_rng(6)
@@ -109,8 +155,9 @@ def test_linear_trajectory_inner_product(stepper):
         XN, hist = imex.rk_forward(P, X0, dt, n)
         Xb = imex.rk_adjoint(P, Yb, hist, dt)
     else:
-        XN, states = imex.sbdf_forward(P, X0, dt, n)
-        Xb = imex.sbdf_adjoint(P, Yb, states, dt)
+        order = {"sbdf": 2, "sbdf3": 3, "sbdf4": 4}[stepper]
+        XN, states = imex.sbdf_forward(P, X0, dt, n, order=order)
+        Xb = imex.sbdf_adjoint(P, Yb, states, dt, order=order)
     lhs = np.real(np.vdot(Yb, XN))
     rhs = np.real(np.vdot(Xb, X0))
     assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
