@@ -4,7 +4,7 @@
  * The library advances an initial-value problem written as
  *     M dX/dt + L X = F(X)                     (paper, Supplementary: Initial value problems)
  * with a sparse ultraspherical/tau discretization (paper: Sparse spectral methods),
- * an IMEX scheme (ARS(2,2,2) Runge-Kutta or SBDF2 multistep), and computes gradients by
+ * an IMEX scheme (ARS(2,2,2) Runge-Kutta or SBDF2-4 multistep), and computes gradients by
  * the adjoint-state method (paper: equ:adjoint and equ:efficient_gradient): a forward
  * sweep with checkpoints, a reverse sweep through transposed solves that reuse the LU
  * factors (paper, Methods: Linear system solves) and vector-Jacobian products of F
@@ -48,11 +48,11 @@ enum sps_status {
 };
 
 enum sps_equation { SPS_RBC2D = 1, SPS_KS1D = 2, SPS_SH2D = 3, SPS_COUETTE3D = 4 };
-enum sps_scheme { SPS_RK222 = 1, SPS_SBDF2 = 2 };
+enum sps_scheme { SPS_RK222 = 1, SPS_SBDF2 = 2, SPS_SBDF3 = 3, SPS_SBDF4 = 4 };
 
 typedef struct {
   int equation;          /* sps_equation */
-  int scheme;            /* sps_scheme; RBC uses SPS_RK222, KS uses SPS_SBDF2 */
+  int scheme;            /* sps_scheme; RBC uses SPS_RK222, KS one of SPS_SBDF2/3/4 */
   int nx;                /* Fourier grid points at scale 1 (K = nx/2 stored wavenumbers) */
   int nz;                /* Chebyshev modes N (RBC), ignored for KS */
   double lx;             /* Fourier period */
@@ -212,7 +212,8 @@ int sps_eval_F(sps_problem *P, const double *X, double *F);
 /* (dF/dX)^H Fbar at X. */
 int sps_eval_F_vjp(sps_problem *P, const double *X, const double *Fbar, double *Xbar);
 /* Solve A x = r (adjoint = 0) or A^H x = r (adjoint = 1) with the current factors of the
- * scheme's implicit matrix (RK222: M + dt*gamma*L; SBDF2: 3/(2dt) M + L). */
+ * scheme's implicit matrix (RK222: M + dt*gamma*L; SBDF-k: a_0 M + L with the steady a_0 = 3/2,
+ * 11/6, 25/12 over dt for k = 2, 3, 4). */
 int sps_solve(sps_problem *P, const double *R, double *X, int adjoint);
 
 /* Linear boundary value problem of the 2D problem's operator (Supplementary, "Linear boundary

@@ -2,8 +2,8 @@
 // in the IVP form M dX/dt + L X = F(X) (Supplementary, "Initial value problems") with one
 // unknown per stored Fourier mode m < K = nx/2: M = 1, L_m = -k_m^2 + k_m^4,
 // F = -1/2 d/dx(u^2) with the product on the 3/2 grid (Methods, dealiasing).  Timestepping is
-// SBDF2 with an SBDF1 first step (equ:imex); the reverse sweep is the multistep adjoint
-// recurrence (equ:IMEX_adjoint).  The implicit matrices are diagonal, so a whole sweep is
+// SBDF-k, k = 2, 3 or 4, reverting to SBDF-n on the first k - 1 steps (equ:imex); the reverse
+// sweep is the multistep adjoint recurrence (equ:IMEX_adjoint).  The implicit matrices are diagonal, so a whole sweep is
 // one block that loops over the steps (a persistent launch) and keeps the per-mode history
 // in registers; the states of the run are stored for the reverse sweep.
 #include <hip/hip_runtime.h>
@@ -26,13 +26,33 @@ struct KsDev {
   const cplx* ex;     // [Ng] exp(2 pi i t / Ng)
 };
 
-// Multistep coefficients of step n (equ:imex): (a0 M + L) X_n = sum_i c_i F_{n-i} - a_i M X_{n-i}.
+// Multistep coefficients of step n (equ:imex): (a_0 M + L) X_n = sum_i c_i F_{n-i} - a_i M X_{n-i},
+// i = 1..4 (zero beyond the order): SBDF-k at a constant step (the k-step backward difference
+// of M dX/dt and the k-th order extrapolation of F), SBDF-n while n < k.
+constexpr int KS_MAX_ORDER = 4;
 struct SbdfCoef {
-  double a0, a1, a2, c1, c2;
+  double a[KS_MAX_ORDER + 1];
+  double c[KS_MAX_ORDER + 1];   // c[0] unused
 };
-__device__ __forceinline__ SbdfCoef sbdf_coef(int n, double dt) {
-  if (n == 1) return {1.0 / dt, -1.0 / dt, 0.0, 1.0, 0.0};
-  return {1.5 / dt, -2.0 / dt, 0.5 / dt, 2.0, -1.0};
+__host__ __device__ __forceinline__ SbdfCoef sbdf_coef(int n, int order, double dt) {
+  const int q = n < order ? n : order;
+  SbdfCoef r;
+  for (int i = 0; i <= KS_MAX_ORDER; ++i) r.a[i] = r.c[i] = 0.0;
+  if (q <= 1) {
+    r.a[0] = 1.0; r.a[1] = -1.0;
+    r.c[1] = 1.0;
+  } else if (q == 2) {
+    r.a[0] = 1.5; r.a[1] = -2.0; r.a[2] = 0.5;
+    r.c[1] = 2.0; r.c[2] = -1.0;
+  } else if (q == 3) {
+    r.a[0] = 11.0 / 6.0; r.a[1] = -3.0; r.a[2] = 1.5; r.a[3] = -1.0 / 3.0;
+    r.c[1] = 3.0; r.c[2] = -3.0; r.c[3] = 1.0;
+  } else {
+    r.a[0] = 25.0 / 12.0; r.a[1] = -4.0; r.a[2] = 3.0; r.a[3] = -4.0 / 3.0; r.a[4] = 0.25;
+    r.c[1] = 4.0; r.c[2] = -6.0; r.c[3] = 4.0; r.c[4] = -1.0;
+  }
+  for (int i = 0; i <= KS_MAX_ORDER; ++i) r.a[i] = r.a[i] / dt;
+  return r;
 }
 
 // Grid values from half-spectrum coefficients (LDS), W = 2 for the real field
@@ -135,66 +155,83 @@ __device__ __forceinline__ KsLds ks_lds(const KsDev& d, double* smem) {
 }
 
 // Forward sweep: X (in: X_0, out: X_N), history H[n][K] of X_0 .. X_N.  One block.
-__global__ void __launch_bounds__(NTS) ks_forward(KsDev d, cplx* X, cplx* H, int nsteps, double dt, int* err) {
+__global__ void __launch_bounds__(NTS) ks_forward(KsDev d, cplx* X, cplx* H, int nsteps, int order, double dt,
+                                                 int* err) {
   extern __shared__ double smem_d[];
   const KsLds L = ks_lds(d, smem_d);
   const int m = threadIdx.x, K = d.K;
   const bool own = m < K;
   const double lin = own ? d.lin[m] : 0.0;
-  cplx x1 = own ? X[m] : czero(), x2 = czero(), f1 = czero(), f2 = czero();
+  // x[i] = X_{n-1-i}, f[i] = F(X_{n-1-i}) of this mode (zero before X_0)
+  cplx x[KS_MAX_ORDER], f[KS_MAX_ORDER];
+#pragma unroll
+  for (int i = 0; i < KS_MAX_ORDER; ++i) x[i] = f[i] = czero();
+  x[0] = own ? X[m] : czero();
   if (own) {
-    H[m] = x1;
-    L.c[m] = x1;
+    H[m] = x[0];
+    L.c[m] = x[0];
   }
   __syncthreads();
   ks_eval_F(d, L.ex, L.c, L.u, L.fo);
-  if (own) f1 = L.fo[m];
+  if (own) f[0] = L.fo[m];
   for (int n = 1; n <= nsteps; ++n) {
-    const SbdfCoef q = sbdf_coef(n, dt);
-    cplx rhs = cadd(cscale(f1, q.c1), cscale(f2, q.c2));
-    rhs = csub(rhs, cadd(cscale(x1, q.a1), cscale(x2, q.a2)));
-    const cplx xn = cscale(rhs, 1.0 / (q.a0 + lin));
+    const SbdfCoef q = sbdf_coef(n, order, dt);
+    cplx fs = czero(), xs = czero();
+#pragma unroll
+    for (int i = 1; i <= KS_MAX_ORDER; ++i) {
+      fs = cadd(fs, cscale(f[i - 1], q.c[i]));
+      xs = cadd(xs, cscale(x[i - 1], q.a[i]));
+    }
+    const cplx xn = cscale(csub(fs, xs), 1.0 / (q.a[0] + lin));
     if (own) {
       H[(size_t)n * K + m] = xn;
       L.c[m] = xn;
     }
-    x2 = x1;
-    x1 = xn;
-    f2 = f1;
+#pragma unroll
+    for (int i = KS_MAX_ORDER - 1; i > 0; --i) {
+      x[i] = x[i - 1];
+      f[i] = f[i - 1];
+    }
+    x[0] = xn;
     if (n < nsteps) {
       __syncthreads();
       ks_eval_F(d, L.ex, L.c, L.u, L.fo);
-      if (own) f1 = L.fo[m];
+      if (own) f[0] = L.fo[m];
     }
   }
   if (own) {
+    const cplx x1 = x[0];
     X[m] = x1;
     if (__any(!(isfinite(x1.x) && isfinite(x1.y))) && lane_id() == 0) atomicOr(err, 2);
   }
 }
 
 // Reverse sweep: Xbar (in: dJ/dX_N, out: dJ/dX_0) through the history H of the forward run.
-// The cotangent of X_{n-1} collects Y_n (step n, i = 1) and Y_{n+1} (step n+1, i = 2), so it
-// is complete once Y_n is known; F's VJP, linear in its cotangent, is applied once per state.
-__global__ void __launch_bounds__(NTS) ks_adjoint(KsDev d, cplx* Xbar, const cplx* H, int nsteps, double dt) {
+// The cotangent of X_{n-1} collects Y_{n-1+i} from steps n-1+i, i = 1..order (equ:IMEX_adjoint),
+// so it is complete once Y_n is known; F's VJP, linear in its cotangent, is applied once per
+// state.  Y of steps beyond nsteps are zero.
+__global__ void __launch_bounds__(NTS) ks_adjoint(KsDev d, cplx* Xbar, const cplx* H, int nsteps, int order,
+                                                 double dt) {
   extern __shared__ double smem_d[];
   const KsLds L = ks_lds(d, smem_d);
   const int m = threadIdx.x, K = d.K;
   const bool own = m < K;
   const double lin = own ? d.lin[m] : 0.0;
   cplx xb = own ? Xbar[m] : czero();   // cotangent of X_n (complete)
-  cplx ynext = czero();                // Y_{n+1}
+  cplx ys[KS_MAX_ORDER - 1];           // Y_{n+1}, Y_{n+2}, Y_{n+3}
+#pragma unroll
+  for (int i = 0; i < KS_MAX_ORDER - 1; ++i) ys[i] = czero();
   cplx hnext = (own && nsteps >= 1) ? H[(size_t)(nsteps - 1) * K + m] : czero();
   for (int n = nsteps; n >= 1; --n) {
-    const SbdfCoef q = sbdf_coef(n, dt);
-    const cplx y = cscale(xb, 1.0 / (q.a0 + lin));
-    const bool has_next = n + 1 <= nsteps;
-    const SbdfCoef qn = sbdf_coef(n + 1, dt);
-    cplx g = cscale(y, q.c1);
-    cplx lin_part = cscale(y, q.a1);
-    if (has_next) {
-      g = cadd(g, cscale(ynext, qn.c2));
-      lin_part = cadd(lin_part, cscale(ynext, qn.a2));
+    const SbdfCoef q = sbdf_coef(n, order, dt);
+    const cplx y = cscale(xb, 1.0 / (q.a[0] + lin));
+    cplx g = cscale(y, q.c[1]);
+    cplx lin_part = cscale(y, q.a[1]);
+#pragma unroll
+    for (int i = 2; i <= KS_MAX_ORDER; ++i) {
+      const SbdfCoef qi = sbdf_coef(n - 1 + i, order, dt);   // step n-1+i, its term i
+      g = cadd(g, cscale(ys[i - 2], qi.c[i]));
+      lin_part = cadd(lin_part, cscale(ys[i - 2], qi.a[i]));
     }
     const cplx hcur = hnext;
     if (own && n >= 2) hnext = H[(size_t)(n - 2) * K + m];   // next iteration's state, early
@@ -205,7 +242,9 @@ __global__ void __launch_bounds__(NTS) ks_adjoint(KsDev d, cplx* Xbar, const cpl
     __syncthreads();
     ks_F_vjp(d, L.ex, L.c, L.g, L.sb, L.u, L.fo);
     xb = own ? csub(L.fo[m], lin_part) : czero();
-    ynext = y;
+#pragma unroll
+    for (int i = KS_MAX_ORDER - 2; i > 0; --i) ys[i] = ys[i - 1];
+    ys[0] = y;
   }
   if (own) Xbar[m] = xb;
 }
@@ -246,17 +285,20 @@ __global__ void __launch_bounds__(NTS) ks_cost(KsDev d, const cplx* X, cplx* dJ,
   if (J && m == 0) J[0] = red[0];
 }
 
-// X = (1.5/dt M + L)^{-1} R, the SBDF2 matrix (real diagonal, so equal to its adjoint).
-__global__ void __launch_bounds__(NTS) ks_solve(KsDev d, const cplx* R, cplx* X, double dt) {
+// X = (a_0 M + L)^{-1} R with the steady SBDF-k a_0 (3/2, 11/6 or 25/12 over dt): the scheme's
+// matrix (real diagonal, so equal to its adjoint).
+__global__ void __launch_bounds__(NTS) ks_solve(KsDev d, const cplx* R, cplx* X, double a0) {
   const int m = threadIdx.x;
-  if (m < d.K) X[m] = cscale(R[m], 1.0 / (1.5 / dt + d.lin[m]));
+  if (m < d.K) X[m] = cscale(R[m], 1.0 / (a0 + d.lin[m]));
 }
 
 class KsProblem : public ProblemImpl {
  public:
   KsProblem(const sps_desc& desc, hipStream_t s) : desc_(desc) {
     stream = s;
-    SPS_REQUIRE(desc.scheme == SPS_SBDF2, "KS supports the SBDF2 scheme");
+    SPS_REQUIRE(desc.scheme == SPS_SBDF2 || desc.scheme == SPS_SBDF3 || desc.scheme == SPS_SBDF4,
+                "KS supports the SBDF2, SBDF3 and SBDF4 schemes");
+    order_ = desc.scheme - SPS_SBDF2 + 2;
     SPS_REQUIRE(desc.nx >= 4 && desc.nx % 2 == 0 && desc.nx / 2 <= NTS, "nx must be even, 4 <= nx <= 512");
     SPS_REQUIRE(desc.dealias == 1.5, "KS uses 3/2 dealiasing");
     SPS_REQUIRE(desc.lx > 0 && desc.dt > 0 && desc.max_steps >= 1, "bad lx / dt / max_steps");
@@ -297,7 +339,7 @@ class KsProblem : public ProblemImpl {
     SPS_REQUIRE(Xbar != nullptr, "Xbar is null");
     if (tape_steps_ != nsteps) throw Error(SPS_E_STATE, "adjoint_step: nsteps does not match the recorded forward run");
     hipLaunchKernelGGL(ks_adjoint, dim3(1), dim3(NTS), lds(), stream, dv_, reinterpret_cast<cplx*>(Xbar), H_, nsteps,
-                       desc_.dt);
+                       order_, desc_.dt);
     SPS_CHECK_LAUNCH();
   }
   void cost(const double* X, double* J, double* dJdX) override {
@@ -336,7 +378,7 @@ class KsProblem : public ProblemImpl {
   void solve(const double* R, double* X, int) override {
     SPS_REQUIRE(R && X, "null argument");
     hipLaunchKernelGGL(ks_solve, dim3(1), dim3(NTS), 0, stream, dv_, reinterpret_cast<const cplx*>(R),
-                       reinterpret_cast<cplx*>(X), desc_.dt);
+                       reinterpret_cast<cplx*>(X), sbdf_coef(order_, order_, desc_.dt).a[0]);
     SPS_CHECK_LAUNCH();
   }
   void timer_enable(int kind, bool on) override {
@@ -357,14 +399,15 @@ class KsProblem : public ProblemImpl {
   void forward(cplx* X, int nsteps) {
     hipEvent_t e0, e1;
     if (timer_.take(&e0, &e1))
-      hipExtLaunchKernelGGL(ks_forward, dim3(1), dim3(NTS), lds(), stream, e0, e1, 0, dv_, X, H_, nsteps, desc_.dt,
+      hipExtLaunchKernelGGL(ks_forward, dim3(1), dim3(NTS), lds(), stream, e0, e1, 0, dv_, X, H_, nsteps, order_, desc_.dt,
                             err_);
     else
-      hipLaunchKernelGGL(ks_forward, dim3(1), dim3(NTS), lds(), stream, dv_, X, H_, nsteps, desc_.dt, err_);
+      hipLaunchKernelGGL(ks_forward, dim3(1), dim3(NTS), lds(), stream, dv_, X, H_, nsteps, order_, desc_.dt, err_);
     SPS_CHECK_LAUNCH();
     tape_steps_ = nsteps;
   }
 
+  int order_ = 2;   // SBDF order (2, 3 or 4)
   sps_desc desc_;
   int K_ = 0, Ng_ = 0;
   KsDev dv_{};

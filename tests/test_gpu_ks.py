@@ -1,7 +1,7 @@
-"""GPU parity of the Kuramoto-Sivashinsky path (Fourier, SBDF2) against the FP64 oracle,
-called through the C ABI: F and its VJP, the diagonal solve, forward runs (the SBDF1 start
-alone, then SBDF2) and the full discrete-adjoint gradient of J = 1/2 ||u(T)||^2 at the
-64-mode, dt = 0.05, 200-step configuration.  Tolerance: 1e-11 in
+"""GPU parity of the Kuramoto-Sivashinsky path (Fourier, SBDF2, SBDF3, SBDF4) against the FP64
+oracle, called through the C ABI: F and its VJP, the diagonal solve, forward runs (the SBDF1
+start alone, then SBDF2; the start-up ramps of SBDF3/4) and the full discrete-adjoint gradient
+of J = 1/2 ||u(T)||^2 at the 64-mode, dt = 0.05, 200-step configuration.  Tolerance: 1e-11 in
 max|gpu - oracle| / max|oracle| per array."""
 import numpy as np
 import pytest
@@ -37,10 +37,11 @@ def rel(a, b):
     return np.max(np.abs(a - b)) / np.max(np.abs(b))
 
 
-def build(cfg, max_steps=1):
+def build(cfg, max_steps=1, order=2):
     nx, L, dt = cfg
     P = KS(Nx=nx, L=L)
-    G = sps.Problem(sps.KS1D, nx, 0, L, 0.0, 0.0, 1.5, dt, 1, max_steps)
+    scheme = {2: sps.SBDF2, 3: sps.SBDF3, 4: sps.SBDF4}[order]
+    G = sps.Problem(sps.KS1D, nx, 0, L, 0.0, 0.0, 1.5, dt, 1, max_steps, scheme=scheme)
     assert G.n == 2 * P.K
     return P, G
 
@@ -119,3 +120,51 @@ def test_nonfinite_state_is_reported_by_sync():
     assert ei.value.code == -5
     assert not torch.isfinite(X).all()
     G.sync()   # the flag is cleared once reported
+
+
+@pytest.mark.parametrize("order", [3, 4])
+@pytest.mark.parametrize("cfg,nsteps", [(SMALL, 1), (SMALL, 2), (SMALL, 3), (SMALL, 9), (FULL, 200)],
+                         ids=["n1", "n2", "n3", "small", "full"])
+def test_ks_higher_order_forward_and_gradient(cfg, nsteps, order):
+    """SBDF3 and SBDF4 with their start-up ramps (SBDF1, SBDF2, ... on the first steps): the
+    forward run, J and the discrete-adjoint gradient vs the oracle at the same order."""
+    print(f"KS SBDF{order} gradient {cfg} x {nsteps}", flush=True)
+    P, G = build(cfg, max_steps=nsteps, order=order)
+    X0 = wl.ks_c0(seed=15, Nx=cfg[0], amp=0.5)[:, None]
+    XN_ref, states = imex.sbdf_forward(P, X0, cfg[2], nsteps, order=order)
+    J_ref = P.energy(XN_ref)
+    g_ref = imex.sbdf_adjoint(P, P.energy_grad(XN_ref), states, cfg[2], order=order)
+    XN = torch.zeros(G.n, dtype=torch.float64, device="cuda")
+    gX = torch.zeros(G.n, dtype=torch.float64, device="cuda")
+    J = torch.zeros(1, dtype=torch.float64, device="cuda")
+    G.gradient(to_dev(X0), nsteps, XN, gX, J)
+    G.sync()
+    ex, eg = rel(from_dev(XN, P.K), XN_ref), rel(from_dev(gX, P.K), g_ref)
+    print(f"  XN rel {ex:.2e}  dJ/dX0 rel {eg:.2e}", flush=True)
+    assert ex < TOL and abs(J.item() - J_ref) < TOL * abs(J_ref) and eg < TOL
+
+
+@pytest.mark.parametrize("order", [3, 4])
+def test_ks_higher_order_step_adjoint_and_solve(order):
+    """O(1) amplitudes, 40 steps: step + adjoint_step vs the oracle; sps_solve applies the
+    steady SBDF-k matrix a_0 M + L."""
+    print(f"KS SBDF{order} step + adjoint_step + solve", flush=True)
+    cfg, nsteps = FULL, 40
+    P, G = build(cfg, max_steps=nsteps, order=order)
+    X0 = wl.ks_c0(seed=16, Nx=cfg[0], amp=2.0)[:, None]
+    X = to_dev(X0)
+    G.step(X, nsteps)
+    dJ = torch.zeros(G.n, dtype=torch.float64, device="cuda")
+    G.cost(X, None, dJ)
+    G.adjoint_step(dJ, nsteps)
+    G.sync()
+    XN_ref, states = imex.sbdf_forward(P, X0, cfg[2], nsteps, order=order)
+    g_ref = imex.sbdf_adjoint(P, P.energy_grad(XN_ref), states, cfg[2], order=order)
+    assert rel(from_dev(X, P.K), XN_ref) < TOL
+    assert rel(from_dev(dJ, P.K), g_ref) < TOL
+    a, b, c = imex.sbdf_coefficients(order, cfg[2], order=order)
+    R = wl.ks_c0(seed=17, Nx=cfg[0], amp=1.0)[:, None]
+    out = torch.zeros(G.n, dtype=torch.float64, device="cuda")
+    G.solve(to_dev(R), out)
+    G.sync()
+    assert rel(from_dev(out, P.K), imex.BlockLU(P.M, P.L, a[0], b[0]).solve(R)) < TOL
