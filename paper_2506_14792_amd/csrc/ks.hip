@@ -54,6 +54,18 @@ __host__ __device__ __forceinline__ SbdfCoef sbdf_coef(int n, int order, double 
   for (int i = 0; i <= KS_MAX_ORDER; ++i) r.a[i] = r.a[i] / dt;
   return r;
 }
+// The rows of a run, by q = min(n, order): built once on the host, passed by value.
+struct SbdfTable {
+  SbdfCoef row[KS_MAX_ORDER + 1];   // row[q], q = 1..order
+};
+SbdfTable sbdf_table(int order, double dt) {
+  SbdfTable t;
+  for (int q = 0; q <= KS_MAX_ORDER; ++q) t.row[q] = sbdf_coef(q < 1 ? 1 : q, order, dt);
+  return t;
+}
+__device__ __forceinline__ const SbdfCoef& sbdf_row(const SbdfTable& t, int n, int order) {
+  return t.row[n < order ? n : order];
+}
 
 // Grid values from half-spectrum coefficients (LDS), W = 2 for the real field
 // u_j = Re c_0 + 2 sum_{m>=1} Re(c_m e^{2 pi i j m / Ng}), W = 1 for the transposed forward
@@ -155,8 +167,8 @@ __device__ __forceinline__ KsLds ks_lds(const KsDev& d, double* smem) {
 }
 
 // Forward sweep: X (in: X_0, out: X_N), history H[n][K] of X_0 .. X_N.  One block.
-__global__ void __launch_bounds__(NTS) ks_forward(KsDev d, cplx* X, cplx* H, int nsteps, int order, double dt,
-                                                 int* err) {
+__global__ void __launch_bounds__(NTS) ks_forward(KsDev d, cplx* X, cplx* H, int nsteps, int order,
+                                                 SbdfTable tab, int* err) {
   extern __shared__ double smem_d[];
   const KsLds L = ks_lds(d, smem_d);
   const int m = threadIdx.x, K = d.K;
@@ -175,7 +187,7 @@ __global__ void __launch_bounds__(NTS) ks_forward(KsDev d, cplx* X, cplx* H, int
   ks_eval_F(d, L.ex, L.c, L.u, L.fo);
   if (own) f[0] = L.fo[m];
   for (int n = 1; n <= nsteps; ++n) {
-    const SbdfCoef q = sbdf_coef(n, order, dt);
+    const SbdfCoef& q = sbdf_row(tab, n, order);
     cplx fs = czero(), xs = czero();
 #pragma unroll
     for (int i = 1; i <= KS_MAX_ORDER; ++i) {
@@ -211,7 +223,7 @@ __global__ void __launch_bounds__(NTS) ks_forward(KsDev d, cplx* X, cplx* H, int
 // so it is complete once Y_n is known; F's VJP, linear in its cotangent, is applied once per
 // state.  Y of steps beyond nsteps are zero.
 __global__ void __launch_bounds__(NTS) ks_adjoint(KsDev d, cplx* Xbar, const cplx* H, int nsteps, int order,
-                                                 double dt) {
+                                                 SbdfTable tab) {
   extern __shared__ double smem_d[];
   const KsLds L = ks_lds(d, smem_d);
   const int m = threadIdx.x, K = d.K;
@@ -223,13 +235,13 @@ __global__ void __launch_bounds__(NTS) ks_adjoint(KsDev d, cplx* Xbar, const cpl
   for (int i = 0; i < KS_MAX_ORDER - 1; ++i) ys[i] = czero();
   cplx hnext = (own && nsteps >= 1) ? H[(size_t)(nsteps - 1) * K + m] : czero();
   for (int n = nsteps; n >= 1; --n) {
-    const SbdfCoef q = sbdf_coef(n, order, dt);
+    const SbdfCoef& q = sbdf_row(tab, n, order);
     const cplx y = cscale(xb, 1.0 / (q.a[0] + lin));
     cplx g = cscale(y, q.c[1]);
     cplx lin_part = cscale(y, q.a[1]);
 #pragma unroll
     for (int i = 2; i <= KS_MAX_ORDER; ++i) {
-      const SbdfCoef qi = sbdf_coef(n - 1 + i, order, dt);   // step n-1+i, its term i
+      const SbdfCoef& qi = sbdf_row(tab, n - 1 + i, order);   // step n-1+i, its term i
       g = cadd(g, cscale(ys[i - 2], qi.c[i]));
       lin_part = cadd(lin_part, cscale(ys[i - 2], qi.a[i]));
     }
@@ -339,7 +351,7 @@ class KsProblem : public ProblemImpl {
     SPS_REQUIRE(Xbar != nullptr, "Xbar is null");
     if (tape_steps_ != nsteps) throw Error(SPS_E_STATE, "adjoint_step: nsteps does not match the recorded forward run");
     hipLaunchKernelGGL(ks_adjoint, dim3(1), dim3(NTS), lds(), stream, dv_, reinterpret_cast<cplx*>(Xbar), H_, nsteps,
-                       order_, desc_.dt);
+                       order_, sbdf_table(order_, desc_.dt));
     SPS_CHECK_LAUNCH();
   }
   void cost(const double* X, double* J, double* dJdX) override {
@@ -399,10 +411,11 @@ class KsProblem : public ProblemImpl {
   void forward(cplx* X, int nsteps) {
     hipEvent_t e0, e1;
     if (timer_.take(&e0, &e1))
-      hipExtLaunchKernelGGL(ks_forward, dim3(1), dim3(NTS), lds(), stream, e0, e1, 0, dv_, X, H_, nsteps, order_, desc_.dt,
+      hipExtLaunchKernelGGL(ks_forward, dim3(1), dim3(NTS), lds(), stream, e0, e1, 0, dv_, X, H_, nsteps, order_, sbdf_table(order_, desc_.dt),
                             err_);
     else
-      hipLaunchKernelGGL(ks_forward, dim3(1), dim3(NTS), lds(), stream, dv_, X, H_, nsteps, order_, desc_.dt, err_);
+      hipLaunchKernelGGL(ks_forward, dim3(1), dim3(NTS), lds(), stream, dv_, X, H_, nsteps, order_,
+                         sbdf_table(order_, desc_.dt), err_);
     SPS_CHECK_LAUNCH();
     tape_steps_ = nsteps;
   }
