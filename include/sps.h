@@ -216,6 +216,30 @@ int sps_eval_F_vjp(sps_problem *P, const double *X, const double *Fbar, double *
  * 11/6, 25/12 over dt for k = 2, 3, 4). */
 int sps_solve(sps_problem *P, const double *R, double *X, int adjoint);
 
+/* Checkpointing of the RK222 sweeps (Supplementary, "Initial value problems": the reverse
+ * sweep needs every forward state, kept through a checkpoint schedule that trades storage for
+ * recomputation).  scheme SPS_CKPT_UNIFORM (the default): a stored state every
+ * checkpoint_every steps and the stage data of one segment, segments recomputed on a second
+ * stream while the adjoint of the next one runs.  scheme SPS_CKPT_BINOMIAL: `slots` >= 1 stored
+ * states (slot 0 holds X_0) placed by the binomial schedule of sps_checkpoint_schedule, which
+ * needs the fewest forward recomputations for that storage; sps_step runs its forward sweep,
+ * sps_adjoint_step and sps_gradient its reverse sweep, all on the problem's stream.  Gradients
+ * are the same as with the default schedule.  Device memory: `slots` states (K S complex
+ * values each), held until sps_destroy.  Drops recorded graphs and the recorded forward run
+ * (sps_adjoint_step needs a new sps_step).  The 2D and plane Couette problems;
+ * SPS_E_UNSUPPORTED otherwise. */
+enum sps_checkpointing { SPS_CKPT_UNIFORM = 0, SPS_CKPT_BINOMIAL = 1 };
+int sps_set_checkpointing(sps_problem *P, int scheme, int slots);
+
+/* The binomial schedule for nsteps steps and `slots` stored states (host arrays; no problem
+ * or device needed): phase 0 the forward sweep, phase 1 the reverse sweep.  Writes *count
+ * actions as (op, a, b) triples into actions (capacity: actions it can hold); op 1 = advance
+ * the working state from step a to step b, 2 = store the working state (step b) in slot a,
+ * 3 = load slot a (the state of step b) into the working state, 4 = run step a forward
+ * recording its stage data and then its adjoint.  The reverse sweep's op-4 actions visit
+ * steps nsteps-1 .. 0 in order.  SPS_E_ARG (with *count set) when capacity is too small. */
+int sps_checkpoint_schedule(int nsteps, int slots, int phase, int *actions, int capacity, int *count);
+
 /* Linear boundary value problem of the 2D problem's operator (Supplementary, "Linear boundary
  * value problems"): L X = M f + c, the steady state of the IVP without its explicit term,
  * driven by body forces and a heat source f, with the IVP's boundary data c (no-slip walls,

@@ -3,7 +3,9 @@
 
 #include <cmath>
 #include <string>
+#include <vector>
 
+#include "ckpt.h"
 #include "cnn.h"
 #include "fft_plan.h"
 #include "sps_internal.h"
@@ -160,6 +162,31 @@ int sps_eval_F_vjp(sps_problem* P, const double* X, const double* Fbar, double* 
 
 int sps_solve(sps_problem* P, const double* R, double* X, int adjoint) {
   return guard(P, [&](sps::ProblemImpl& p) { p.solve(R, X, adjoint); });
+}
+
+int sps_set_checkpointing(sps_problem* P, int scheme, int slots) {
+  return guard(P, [&](sps::ProblemImpl& p) { p.set_checkpointing(scheme, slots); });
+}
+
+int sps_checkpoint_schedule(int nsteps, int slots, int phase, int* actions, int capacity, int* count) {
+  if (!count) return fail(SPS_E_ARG, "null count");
+  *count = 0;
+  if (nsteps < 1 || slots < 1 || (phase != 0 && phase != 1)) return fail(SPS_E_ARG, "nsteps, slots >= 1 and phase 0 or 1");
+  try {
+    std::vector<sps::CkptAction> fwd, rev;
+    sps::binomial_schedule(nsteps, slots, fwd, rev);
+    const std::vector<sps::CkptAction>& v = phase == 0 ? fwd : rev;
+    *count = (int)v.size();
+    if (!actions || capacity < *count) return fail(SPS_E_ARG, "actions array too small");
+    for (size_t i = 0; i < v.size(); ++i) {
+      actions[3 * i] = v[i].op;
+      actions[3 * i + 1] = v[i].a;
+      actions[3 * i + 2] = v[i].b;
+    }
+  } catch (const std::exception& e) {
+    return fail(SPS_E_NOMEM, e.what());
+  }
+  return SPS_OK;
 }
 
 int sps_lbvp_solve(sps_problem* P, const double* f, double* X) {

@@ -38,6 +38,7 @@
 #include <vector>
 
 #include "band_lu.h"
+#include "ckpt.h"
 #include "cou.h"
 #include "sps_device.h"
 #include "sps_internal.h"
@@ -1868,6 +1869,10 @@ class RbcProblem : public ProblemImpl {
   }
 
   void forward(cplx* X, int nsteps) {
+    if (ckpt_mode_ == SPS_CKPT_BINOMIAL) {
+      forward_binomial(X, nsteps);
+      return;
+    }
     const int ce = desc_.checkpoint_every;
     const int nseg = (nsteps + ce - 1) / ce;
     const int last0 = (nseg - 1) * ce;   // first step of the last segment: recorded now
@@ -1897,6 +1902,10 @@ class RbcProblem : public ProblemImpl {
   // the forward sweep, (ii) the adjoint of seg after its recompute, (iii) the recompute into a
   // buffer after the adjoint that last read it; the caller's stream waits for all of it.
   void reverse(cplx* Xbar, int nsteps) {
+    if (ckpt_mode_ == SPS_CKPT_BINOMIAL) {
+      reverse_binomial(Xbar, nsteps);
+      return;
+    }
     const int ce = desc_.checkpoint_every;
     const int nseg = (nsteps + ce - 1) / ce;
     auto seglen = [&](int g) { return std::min(ce, nsteps - g * ce); };
@@ -1929,6 +1938,75 @@ class RbcProblem : public ProblemImpl {
     // join the auxiliary stream explicitly (it may have waited without launching, nseg = 1)
     SPS_HIP(hipEventRecord(ev_rec, aux_));
     SPS_HIP(hipStreamWaitEvent(stream, ev_rec, 0));
+  }
+
+  // ----------------------------------------------------------------- binomial checkpointing
+  // The schedule's actions on a working state (the caller's X in the forward sweep, Xw_ in the
+  // reverse sweep) and rv_slots_ stored states, all on the problem's stream.  A turn records the
+  // step's two stage-field sets in the first segment slot and runs the step's adjoint launches,
+  // exactly those of the segment sweep.
+  void set_checkpointing(int scheme, int slots) override {
+    SPS_REQUIRE(scheme == SPS_CKPT_UNIFORM || scheme == SPS_CKPT_BINOMIAL, "unknown checkpointing scheme");
+    if (scheme == SPS_CKPT_BINOMIAL) {
+      SPS_REQUIRE(slots >= 1 && slots <= desc_.max_steps + 1, "slots must be in [1, max_steps + 1]");
+      if (slots > rv_cap_) {
+        rv_ = arena_.alloc<cplx>((size_t)slots * K_ * S_);
+        rv_cap_ = slots;
+      }
+    }
+    drop_graphs();
+    ckpt_mode_ = scheme;
+    rv_slots_ = (scheme == SPS_CKPT_BINOMIAL) ? slots : 0;
+    rv_n_ = -1;
+    tape_steps_ = -1;
+  }
+  cplx* rvslot(int i) { return rv_ + (size_t)i * K_ * S_; }
+  void ensure_schedule(int nsteps) {
+    if (rv_n_ == nsteps) return;
+    binomial_schedule(nsteps, rv_slots_, rv_fwd_, rv_rev_);
+    rv_n_ = nsteps;
+  }
+  void copy_state(cplx* dst, const cplx* src) {
+    SPS_HIP(hipMemcpyAsync(dst, src, sizeof(cplx) * K_ * S_, hipMemcpyDeviceToDevice, stream));
+  }
+  void advance(cplx* X, int a, int b) {
+    launch_kf(KF_ZGRID, X, nullptr, nullptr, zgA_);
+    for (int n = a; n < b; ++n) rk_step(stream, X, zgA_, zgA_, (n + 1 < b) ? zgA_ : nullptr);
+  }
+  void forward_binomial(cplx* X, int nsteps) {
+    ensure_schedule(nsteps);
+    for (const CkptAction& c : rv_fwd_) {
+      if (c.op == CK_TAKESHOT) copy_state(rvslot(c.a), X);
+      else if (c.op == CK_ADVANCE) advance(X, c.a, c.b);
+    }
+    tape_steps_ = nsteps;
+  }
+  void reverse_binomial(cplx* Xbar, int nsteps) {
+    ensure_schedule(nsteps);
+    bool first = true;
+    for (const CkptAction& c : rv_rev_) {
+      switch (c.op) {
+        case CK_RESTORE: copy_state(Xw_, rvslot(c.a)); break;
+        case CK_TAKESHOT: copy_state(rvslot(c.a), Xw_); break;
+        case CK_ADVANCE: advance(Xw_, c.a, c.b); break;
+        case CK_YOUTURN: {
+          launch_kf(KF_ZGRID, Xw_, nullptr, nullptr, slot(0, 0, 0));
+          rk_step(stream, Xw_, slot(0, 0, 0), slot(0, 0, 1), nullptr);
+          KaArgs a = ka_args(first ? KA_A : (KA_C | KA_A));
+          a.Xb_in = Xbar;
+          launch_ka(a);
+          first = false;
+          launch_xa(slot(0, 0, 1));
+          launch_ka(ka_args(KA_B));
+          launch_xa(slot(0, 0, 0));
+          break;
+        }
+        default: throw Error(SPS_E_STATE, "bad checkpoint action");
+      }
+    }
+    KaArgs a = ka_args(KA_C);
+    a.Xb_out = Xbar;
+    launch_ka(a);
   }
 
   // ----------------------------------------------------------------- tables
@@ -2072,6 +2150,9 @@ class RbcProblem : public ProblemImpl {
   std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs_;
   bool factored_ = false;
   int tape_steps_ = -1;
+  int ckpt_mode_ = SPS_CKPT_UNIFORM, rv_slots_ = 0, rv_cap_ = 0, rv_n_ = -1;
+  cplx* rv_ = nullptr;   // binomial schedule's stored states
+  std::vector<CkptAction> rv_fwd_, rv_rev_;
   KernelTimer timer_;
 };
 

@@ -125,6 +125,9 @@ class ProblemImpl {
   virtual void eval_F(const double* X, double* F) = 0;
   virtual void eval_F_vjp(const double* X, const double* Fbar, double* Xbar) = 0;
   virtual void solve(const double* R, double* X, int adjoint) = 0;
+  virtual void set_checkpointing(int, int) {
+    throw Error(SPS_E_UNSUPPORTED, "checkpoint schedules are built for the RK222 problems");
+  }
   virtual void lbvp_solve(const double*, double*) {
     throw Error(SPS_E_UNSUPPORTED, "no boundary value problem for this equation");
   }

@@ -9,6 +9,7 @@ LIB_PATH = os.path.join(_HERE, "libsps.so")
 
 RBC2D, KS1D, SH2D = 1, 2, 3
 RK222, SBDF2, SBDF3, SBDF4 = 1, 2, 3, 4
+CKPT_UNIFORM, CKPT_BINOMIAL = 0, 1
 
 _STATUS = {0: "SPS_OK", -1: "SPS_E_ARG", -2: "SPS_E_NOMEM", -3: "SPS_E_HIP", -4: "SPS_E_SINGULAR",
            -5: "SPS_E_NONFINITE", -6: "SPS_E_STATE", -7: "SPS_E_UNSUPPORTED"}
@@ -53,6 +54,10 @@ def lib():
         "sps_eval_F": (ctypes.c_int, [_P, _D, _D]),
         "sps_eval_F_vjp": (ctypes.c_int, [_P, _D, _D, _D]),
         "sps_solve": (ctypes.c_int, [_P, _D, _D, ctypes.c_int]),
+        "sps_set_checkpointing": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
+        "sps_checkpoint_schedule": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                   ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                                   ctypes.POINTER(ctypes.c_int)]),
         "sps_lbvp_solve": (ctypes.c_int, [_P, _D, _D]),
         "sps_lbvp_adjoint": (ctypes.c_int, [_P, _D, _D]),
         "sps_timer_enable": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
@@ -118,6 +123,22 @@ def make_desc(equation, nx, nz=0, lx=1.0, param0=0.0, param1=0.0, dealias=1.5, d
     return SpsDesc(equation, scheme, nx, nz, lx, param0, param1, dealias, dt, checkpoint_every, max_steps)
 
 
+def checkpoint_schedule(nsteps, slots):
+    """The binomial checkpointing schedule as two lists of (op, a, b) actions, forward sweep and
+    reverse sweep (op 1 advance a -> b, 2 store step b in slot a, 3 load slot a (step b),
+    4 record step a and run its adjoint).  Host-only: no device is used."""
+    out = []
+    for phase in (0, 1):
+        count = ctypes.c_int(0)
+        rc = lib().sps_checkpoint_schedule(nsteps, slots, phase, None, 0, ctypes.byref(count))
+        if rc not in (0, -1) or count.value == 0:
+            _check(rc)
+        buf = (ctypes.c_int * (3 * count.value))()
+        _check(lib().sps_checkpoint_schedule(nsteps, slots, phase, buf, count.value, ctypes.byref(count)))
+        out.append([tuple(buf[3 * i:3 * i + 3]) for i in range(count.value)])
+    return out[0], out[1]
+
+
 class Problem:
     """A built problem on the current HIP stream (torch.cuda.current_stream())."""
 
@@ -178,6 +199,12 @@ class Problem:
 
     def solve(self, R, X, adjoint=False):
         _check(lib().sps_solve(self._h, _ptr(R, self.n), _ptr(X, self.n), int(bool(adjoint))))
+
+    def set_checkpointing(self, scheme, slots=0):
+        """CKPT_UNIFORM (checkpoints every checkpoint_every steps) or CKPT_BINOMIAL with `slots`
+        stored states; drops the recorded forward run."""
+        _check(lib().sps_set_checkpointing(self._h, int(scheme), int(slots)))
+        self.tape_id += 1
 
     def lbvp_solve(self, f, X):
         """X = L^-1 (M f + c): the boundary value problem of the operator (2D problem only)."""

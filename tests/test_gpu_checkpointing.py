@@ -1,0 +1,132 @@
+"""GPU checks of binomial checkpointing (sps_set_checkpointing): the gradient, the final state
+and J under the binomial schedule are bit-for-bit those of the default uniform schedule (the
+same kernels on the same inputs, only their order and the stored states differ) for several
+slot counts on the 2D problem, through sps_gradient, sps_step + sps_adjoint_step and graph
+replay, at 24x16 (also against the oracle, 1e-11) and at the full 256x64 / 1000-step
+configuration, and on plane Couette."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import imex
+from oracle.rbc import RBC
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2506_14792_amd as sps  # noqa: E402
+
+SMALL = (24, 16, 3.0, 1e5, 0.7, 2e-3)
+FULL = (256, 64, 4.0, 1e6, 1.0, 1e-3)
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(X):
+    return torch.from_numpy(np.ascontiguousarray(X).view(np.float64).ravel().copy()).cuda()
+
+
+def grad(G, X0, n):
+    XN = torch.zeros_like(X0)
+    g = torch.zeros_like(X0)
+    J = torch.zeros(1, dtype=torch.float64, device="cuda")
+    G.gradient(X0, n, XN, g, J)
+    G.sync()
+    return XN, g, J
+
+
+def small_problem(n, ce):
+    nx, nz, lx, Ra, Pr, dt = SMALL
+    P = RBC(Nx=nx, Nz=nz, Lx=lx, Ra=Ra, Pr=Pr)
+    G = sps.Problem(sps.RBC2D, nx, nz, lx, Ra, Pr, 1.5, dt, ce, n)
+    X0 = P.initial_state(wl.rbc_b0(seed=4, Nx=nx, Nz=nz, amp=0.2))
+    return P, G, X0
+
+
+def test_binomial_equals_uniform_small_and_oracle():
+    n, ce = 13, 4
+    note(f"binomial vs uniform, 24x16, {n} steps")
+    P, G, X0h = small_problem(n, ce)
+    X0 = to_dev(X0h)
+    ref = grad(G, X0, n)
+    for slots in (1, 2, 3, 5, n + 1):
+        G.set_checkpointing(sps.CKPT_BINOMIAL, slots)
+        got = grad(G, X0, n)
+        same = all(torch.equal(a, b) for a, b in zip(got, ref))
+        note(f"  slots {slots}: identical {same}")
+        assert same
+    G.set_checkpointing(sps.CKPT_UNIFORM)
+    assert all(torch.equal(a, b) for a, b in zip(grad(G, X0, n), ref))
+    XN, hist = imex.rk_forward(P, X0h, SMALL[5], n)
+    g_ref = imex.rk_adjoint(P, P.kinetic_energy_grad(XN), hist, SMALL[5])
+    g = ref[1].cpu().numpy().view(np.complex128).reshape(g_ref.shape)
+    assert np.max(np.abs(g - g_ref)) <= 1e-11 * np.max(np.abs(g_ref))
+
+
+def test_binomial_step_adjoint_step_and_graph():
+    n, ce = 11, 3
+    note("binomial step + adjoint_step, graph replay")
+    P, G, X0h = small_problem(n, ce)
+    X0 = to_dev(X0h)
+    ref = grad(G, X0, n)
+    G.set_checkpointing(sps.CKPT_BINOMIAL, 3)
+    X = X0.clone()
+    G.step(X, n)
+    dJ = torch.zeros_like(X)
+    G.cost(X, None, dJ)
+    G.adjoint_step(dJ, n)
+    G.sync()
+    assert torch.equal(X, ref[0]) and torch.equal(dJ, ref[1])
+    G.set_graph(True)
+    for rep in range(3):
+        got = grad(G, X0, n)
+        assert all(torch.equal(a, b) for a, b in zip(got, ref)), rep
+        torch.cuda.synchronize()
+    G.set_graph(False)
+    # switching the schedule drops the recorded run
+    G.set_checkpointing(sps.CKPT_UNIFORM)
+    with pytest.raises(sps.SpsError):
+        G.adjoint_step(dJ, n)
+
+
+def test_binomial_full_size():
+    note("binomial vs uniform, 256x64, 1000 steps, 10 slots")
+    nx, nz, lx, Ra, Pr, dt = FULL
+    n = 1000
+    G = sps.Problem(sps.RBC2D, nx, nz, lx, Ra, Pr, 1.5, dt, 50, n)
+    b0 = torch.from_numpy(wl.rbc_b0(seed=0, Nx=nx, Nz=nz).ravel().copy()).cuda()
+    X0 = torch.zeros(G.n, dtype=torch.float64, device="cuda")
+    G.initial_state(b0, X0)
+    ref = grad(G, X0, n)
+    G.set_checkpointing(sps.CKPT_BINOMIAL, 10)
+    got = grad(G, X0, n)
+    same = all(torch.equal(a, b) for a, b in zip(got, ref))
+    note(f"  J {got[2].item():.12e}  identical {same}")
+    assert same
+
+
+def test_binomial_couette():
+    note("binomial vs uniform, Couette 8x12x8")
+    n = 7
+    G = sps.Couette(8, 12, 8, Re=400.0, dt=0.01, checkpoint_every=2, max_steps=n)
+    uvw = wl.couette_perturbation(seed=3, Nx=8, Ny=12, Nz=8, energy=1e-3)
+    X0 = torch.from_numpy(G.state_from_velocity(uvw)).cuda()
+    ref = grad(G, X0, n)
+    G.set_checkpointing(sps.CKPT_BINOMIAL, 2)
+    got = grad(G, X0, n)
+    assert all(torch.equal(a, b) for a, b in zip(got, ref))
+
+
+def test_checkpointing_unsupported_for_multistep_problems():
+    G = sps.Problem(sps.KS1D, 64, 0, 32.0 * np.pi, 0.0, 0.0, 1.5, 0.05, 1, 4)
+    with pytest.raises(sps.SpsError) as e:
+        G.set_checkpointing(sps.CKPT_BINOMIAL, 2)
+    assert e.value.code == -7
