@@ -286,6 +286,52 @@ def lbvp_timing(reps=200):
             "speedup_vs_oracle": ocpu / (solve_s + adj_s)}
 
 
+def ckpt_timing(slot_counts=(5, 10, 20, 50)):
+    """Checkpoint schedules on the headline configuration (256 x 64, 1000 RK222 steps): the
+    eager gradient with the default schedule (a stored state every 50 steps, one segment's stage
+    fields recorded, segments recomputed on a second stream) against binomial checkpointing with
+    a few slot counts (all launches on one stream; the fewest recomputed steps for the storage).
+    Reports seconds per gradient, forward steps per gradient (schedule count: forward sweep,
+    recomputation and the recorded turns) and the device memory of the stored data."""
+    import torch
+    import workloads as wl
+    import paper_2506_14792_amd as sps
+    c = CFG
+    n = c["nsteps"]
+    G = sps.Problem(sps.RBC2D, c["nx"], c["nz"], c["lx"], c["Ra"], c["Pr"], 1.5, c["dt"], c["checkpoint_every"], n)
+    b0 = torch.from_numpy(wl.rbc_b0(seed=c["seed"], Nx=c["nx"], Nz=c["nz"]).ravel().copy()).cuda()
+    X0 = torch.zeros(G.n, dtype=torch.float64, device="cuda")
+    G.initial_state(b0, X0)
+    g = torch.zeros_like(X0)
+    J = torch.zeros(1, dtype=torch.float64, device="cuda")
+
+    def timed(k=2):
+        G.gradient(X0, n, None, g, J)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            G.gradient(X0, n, None, g, J)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / k
+
+    K, S, Ngz = c["nx"] // 2, 4 * c["nz"] + 7, 3 * c["nz"] // 2
+    state_mb = K * S * 16 / 1e6
+    stage_mb = 6 * Ngz * K * 16 / 1e6            # z-grid fields of one stage
+    ce = c["checkpoint_every"]   # the last segment is recorded by the forward sweep, not recomputed
+    out = {"workload": "Rayleigh-Benard 256x64, 1000 RK222 steps, gradient of the final kinetic energy",
+           "uniform": {"gradient_s": timed(), "forward_steps": 2 * n - ce,
+                       "stored_MB": (n // ce) * state_mb + 2 * ce * 2 * stage_mb}}
+    for slots in slot_counts:
+        G.set_checkpointing(sps.CKPT_BINOMIAL, slots)
+        fwd, rev = sps.checkpoint_schedule(n, slots)
+        steps = sum(b - a for op, a, b in fwd + rev if op == 1) + sum(1 for op, _, _ in rev if op == 4)
+        out[f"binomial_{slots}"] = {"gradient_s": timed(), "forward_steps": steps,
+                                    "stored_MB": slots * state_mb + 2 * stage_mb}
+    G.set_checkpointing(sps.CKPT_UNIFORM)
+    G.sync()
+    return out
+
+
 COU_CFG = dict(nx=128, ny=64, nz=64, Lx=4.0 * np.pi, Lz=2.0 * np.pi, Re=400.0, dt=0.01, nsteps=2000,
                checkpoint_every=100, seed=0, energy=1e-6)
 
@@ -437,7 +483,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--skip-extra", action="store_true",
                     help="only the headline configuration (for counter and trace runs)")
-    ap.add_argument("--only", choices=["ks", "sh", "closure", "couette", "lbvp"], default=None,
+    ap.add_argument("--only", choices=["ks", "sh", "closure", "couette", "lbvp", "ckpt"], default=None,
                     help="run one secondary configuration alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -451,7 +497,7 @@ def main():
         import torch
         torch.cuda.set_device(0)
         fn = {"ks": ks_timing, "sh": sh_timing, "closure": kolmo_timing, "couette": couette_timing,
-              "lbvp": lbvp_timing}[args.only]
+              "lbvp": lbvp_timing, "ckpt": ckpt_timing}[args.only]
         print(json.dumps({args.only: fn()}))
         return
 
@@ -523,9 +569,10 @@ def main():
     G.sync()
     graph_sec = (t7 - t6) / args.steps
     traffic = measured_traffic()
-    ks = sh = kol = cou = lbvp = None
+    ks = sh = kol = cou = lbvp = ckpt = None
     if not args.skip_extra:
         lbvp = lbvp_timing()
+        ckpt = ckpt_timing()
         ks = ks_timing()
         sh = sh_timing()
         kol = kolmo_timing()
@@ -564,6 +611,7 @@ def main():
         "closure_config": kol,
         "couette_autograd_config": cou,
         "lbvp_config": lbvp,
+        "checkpointing_config": ckpt,
         "J": J.item(),
     }
     print(json.dumps(out))
