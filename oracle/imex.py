@@ -172,13 +172,48 @@ def sbdf_coefficients(n, dt, order=2):
     return a, b, c
 
 
+def sbdf_variable_coefficients(h, n, order=2):
+    """Coefficients of step n for step sizes h (h[i] = t_{i+1} - t_i; step n advances from
+    t_{n-1} by h[n-1]), the variable-step form of the scheme of sbdf_coefficients (equ:imex:
+    coefficients that depend on the timestep, lower order while the history is short).  With
+    q = min(n, order) and the nodes tau_j = t_{n-j} - t_n, j = 0..q, the row is defined by its
+    order conditions: sum_j a_j tau_j^p = [p == 1] for p = 0..q (the backward difference of
+    dX/dt at t_n is exact for polynomials of degree q) and sum_{i>=1} c_i tau_i^p = [p == 0]
+    for p = 0..q-1 (F extrapolated to t_n exactly for degree q - 1), solved as Vandermonde
+    systems."""
+    q = min(n, order)
+    tau = np.zeros(q + 1)
+    for j in range(1, q + 1):
+        tau[j] = tau[j - 1] - h[n - j]
+    V = np.vander(tau, q + 1, increasing=True).T          # V[p, j] = tau_j^p
+    rhs = np.zeros(q + 1)
+    rhs[1] = 1.0
+    a = np.linalg.solve(V, rhs)
+    W = np.vander(tau[1:], q, increasing=True).T          # W[p, i] = tau_i^p
+    e0 = np.zeros(q)
+    e0[0] = 1.0
+    c = np.concatenate([[0.0], np.linalg.solve(W, e0)])
+    b = np.zeros(q + 1)
+    b[0] = 1.0
+    return a, b, c
+
+
+def _coefficients(n, dt, order):
+    """Row of step n: constant step (scalar dt) or the variable-step row (dt a sequence)."""
+    if np.ndim(dt) == 0:
+        return sbdf_coefficients(n, dt, order)
+    return sbdf_variable_coefficients(dt, n, order)
+
+
 def sbdf_forward(P, X0, dt, nsteps, order=2):
-    """Multistep IMEX forward run; returns X_N and all states [X_0, ..., X_N]."""
+    """Multistep IMEX forward run; returns X_N and all states [X_0, ..., X_N].  dt is the
+    constant step or the sequence of step sizes (one LU per distinct a_0, rebuilt when the
+    step changes)."""
     states = [np.array(X0, dtype=complex)]
     Fs = [P.F(states[0])]
     lus = {}
     for n in range(1, nsteps + 1):
-        a, b, c = sbdf_coefficients(n, dt, order)
+        a, b, c = _coefficients(n, dt, order)
         key = (a[0], b[0])
         if key not in lus:
             lus[key] = BlockLU(P.M, P.L, a[0], b[0])
@@ -202,7 +237,7 @@ def sbdf_adjoint(P, Xbar_N, states, dt, order=2):
     Xbar[N] = np.array(Xbar_N, dtype=complex)
     lus = {}
     for n in range(N, 0, -1):
-        a, b, c = sbdf_coefficients(n, dt, order)
+        a, b, c = _coefficients(n, dt, order)
         key = (a[0], b[0])
         if key not in lus:
             lus[key] = BlockLU(P.M, P.L, a[0], b[0])
@@ -228,7 +263,7 @@ def sbdf_adjoint_general(P, states, dt, Xbar_N=None, inject=None, param_vjp=Fals
     for n in range(N, 0, -1):
         if inject is not None and inject[n] is not None:
             Xbar[n] += inject[n]
-        a, b, c = sbdf_coefficients(n, dt, order)
+        a, b, c = _coefficients(n, dt, order)
         key = (a[0], b[0])
         if key not in lus:
             lus[key] = BlockLU(P.M, P.L, a[0], b[0])

@@ -79,3 +79,22 @@ def test_brute_force_finite_differences_every_component(order):
                   - P.energy(imex.sbdf_forward(P, X0 - e, dt, n, order=order)[0])) / (2 * h)
             an = np.real(np.conj(part) * g[m, 0])
             assert abs(fd - an) <= 1e-7 * np.max(np.abs(g))
+
+
+@pytest.mark.parametrize("order", [2, 3])
+def test_variable_step_taylor_remainder_rate(order):
+    """200 steps whose sizes vary by +-30 % around 0.05: the gradient's Taylor remainder falls at
+    second order."""
+    P = KS()
+    X0 = wl.ks_c0(seed=0)[:, None]
+    h = 0.05 * (1.0 + 0.3 * np.sin(np.arange(200) * 0.37))
+    XN, states = imex.sbdf_forward(P, X0, h, 200, order=order)
+    J = P.energy(XN)
+    g = imex.sbdf_adjoint(P, P.energy_grad(XN), states, h, order=order)
+    d = wl.random_state(10, (P.K, 1))
+    rem = []
+    for e in (1e-4, 5e-5, 2.5e-5, 1.25e-5):
+        Je = P.energy(imex.sbdf_forward(P, X0 + e * d, h, 200, order=order)[0])
+        rem.append(abs(Je - J - e * np.real(np.vdot(g, d))))
+    rates = np.log2(np.array(rem[:-1]) / np.array(rem[1:]))
+    assert np.all(np.abs(rates - 2.0) < 0.05), rates

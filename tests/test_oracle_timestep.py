@@ -137,6 +137,70 @@ def test_sbdf_principal_root_converges_at_order_k_plus_1(k):
     assert np.all(np.abs(rates - (k + 1)) < 0.15), rates
 
 
+def steps(n, h, amp=0.4, seed=None):
+    """A smoothly varying step sequence: h (1 + amp sin(2 pi i / n)), or i.i.d. factors in
+    [1 - amp, 1 + amp] when seed is given."""
+    if seed is None:
+        return h * (1.0 + amp * np.sin(2.0 * np.pi * np.arange(n) / n))
+    return h * (1.0 + amp * (2.0 * np.random.default_rng(seed).random(n) - 1.0))
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_variable_step_rows_reduce_to_the_constant_rows(k):
+    h = np.full(8, 0.07)
+    for n in range(1, 8):
+        a, b, c = imex.sbdf_variable_coefficients(h, n, k)
+        ar, br, cr = imex.sbdf_coefficients(n, 0.07, k)
+        assert np.allclose(a, ar, rtol=1e-13, atol=1e-13 * np.abs(ar).max())
+        assert np.allclose(c, cr, rtol=1e-13, atol=1e-13) and np.array_equal(b, br)
+
+
+def test_variable_step_sbdf2_closed_form():
+    """Variable-step SBDF2 with w = h_n / h_{n-1}: a_0 = (1 + 2w) / ((1 + w) h_n),
+    a_1 = -(1 + w) / h_n, a_2 = w^2 / ((1 + w) h_n), c_1 = 1 + w, c_2 = -w."""
+    h = steps(12, 0.05, seed=3)
+    for n in range(2, 12):
+        w = h[n - 1] / h[n - 2]
+        hn = h[n - 1]
+        a, b, c = imex.sbdf_variable_coefficients(h, n, 2)
+        ref_a = np.array([(1 + 2 * w) / ((1 + w) * hn), -(1 + w) / hn, w * w / ((1 + w) * hn)])
+        assert np.allclose(a, ref_a, rtol=1e-13)
+        assert np.allclose(c, [0.0, 1 + w, -w], rtol=1e-13)
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_variable_step_second_order_convergence(k):
+    """dX/dt = -lam X + mu X over [0, 1] on steps that grow linearly by a factor 2: the error to
+    the exponential falls at second order (SBDF3 is limited to second order by its SBDF1/SBDF2
+    start).  Rows built for constant steps are inconsistent on such steps by -(w - 1)/2 X' with
+    w the ratio of neighbouring steps, which on a monotone ramp does not average out: they
+    converge at first order, so this pins the variable-step rows."""
+    lam, mu, T = 2.0, 0.5, 1.0
+    errs = []
+    for n in (40, 80, 160):
+        h = 1.0 + np.arange(n) / n
+        h *= T / h.sum()
+        XN, _ = imex.sbdf_forward(scalar(lam, mu), np.ones((1, 1)), h, n, order=k)
+        errs.append(abs(XN[0, 0] - np.exp((mu - lam) * T)))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(np.abs(rates - 2.0) < 0.1), rates
+
+
+@pytest.mark.parametrize("k", [2, 3, 4])
+def test_variable_step_trajectory_inner_product(k):
+    P = random_linear(8)
+    rng = np.random.default_rng(9)
+    X0 = rng.standard_normal((3, 4)) + 1j * rng.standard_normal((3, 4))
+    Yb = rng.standard_normal((3, 4)) + 1j * rng.standard_normal((3, 4))
+    n = 12
+    h = steps(n, 0.05, seed=10)
+    XN, states = imex.sbdf_forward(P, X0, h, n, order=k)
+    Xb = imex.sbdf_adjoint(P, Yb, states, h, order=k)
+    lhs = np.real(np.vdot(Yb, XN))
+    rhs = np.real(np.vdot(Xb, X0))
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
 def random_linear(seed, K=3, S=4):
     rng = np.random.default_rng(seed)
     c = lambda: rng.standard_normal((K, S, S)) + 1j * rng.standard_normal((K, S, S))
