@@ -136,6 +136,17 @@ def ks_timing(reps=20):
         hs = (time.perf_counter() - t0) / reps
         Gh.sync()
         higher[name] = {"gpu_gradient_s": hs, "gpu_timesteps_per_s": 2 * c["nsteps"] / hs}
+    # SBDF2 on variable steps (a linear ramp of the step size from 0.67 dt to 1.33 dt)
+    G.set_timesteps(c["dt"] * (0.67 + 0.67 * np.arange(c["nsteps"]) / c["nsteps"]))
+    G.gradient(X0, c["nsteps"], None, g, None)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        G.gradient(X0, c["nsteps"], None, g, None)
+    torch.cuda.synchronize()
+    higher["sbdf2_variable_steps"] = {"gpu_gradient_s": (time.perf_counter() - t0) / reps}
+    G.set_timesteps(None)
+    G.sync()
     return {"workload": "Kuramoto-Sivashinsky 1D, 64 Fourier modes, L = 32 pi, SBDF2 dt = 0.05, 200 steps, "
                         "gradient of 1/2 ||u(T)||^2", "gpu_gradient_s": gpu_s, "oracle_cpu_gradient_s": cpu_s,
             "gpu_timesteps_per_s": 2 * c["nsteps"] / gpu_s, "higher_order": higher}

@@ -216,6 +216,18 @@ int sps_eval_F_vjp(sps_problem *P, const double *X, const double *Fbar, double *
  * 11/6, 25/12 over dt for k = 2, 3, 4). */
 int sps_solve(sps_problem *P, const double *R, double *X, int adjoint);
 
+/* Variable time steps of the multistep schemes (equ:imex: the coefficients of step n depend on
+ * the step sizes, lower order while the history is short).  dts: HOST array of n step sizes
+ * (dts[i] = t_{i+1} - t_i, positive), copied; later sps_step / sps_gradient runs of at most n
+ * steps take step i + 1 with dts[i], and sps_adjoint_step reverses them with the same rows.
+ * Step n's row is the SBDF-k of the problem's scheme on the non-uniform nodes t_n .. t_{n-q},
+ * q = min(n, k): a_j the derivative at t_n of the Lagrange basis polynomial of node t_{n-j}
+ * (backward difference of M dX/dt), c_i the value at t_n of the basis polynomial of t_{n-i}
+ * on t_{n-1} .. t_{n-q} (extrapolation of F); equal steps give the constant-step rows.
+ * dts = NULL or n = 0 returns to the constant step of the descriptor (sps_solve always uses
+ * it).  Drops the recorded forward run.  The KS problem; SPS_E_UNSUPPORTED otherwise. */
+int sps_set_timesteps(sps_problem *P, const double *dts, int n);
+
 /* Checkpointing of the RK222 sweeps (Supplementary, "Initial value problems": the reverse
  * sweep needs every forward state, kept through a checkpoint schedule that trades storage for
  * recomputation).  scheme SPS_CKPT_UNIFORM (the default): a stored state every

@@ -164,6 +164,10 @@ int sps_solve(sps_problem* P, const double* R, double* X, int adjoint) {
   return guard(P, [&](sps::ProblemImpl& p) { p.solve(R, X, adjoint); });
 }
 
+int sps_set_timesteps(sps_problem* P, const double* dts, int n) {
+  return guard(P, [&](sps::ProblemImpl& p) { p.set_timesteps(dts, n); });
+}
+
 int sps_set_checkpointing(sps_problem* P, int scheme, int slots) {
   return guard(P, [&](sps::ProblemImpl& p) { p.set_checkpointing(scheme, slots); });
 }

@@ -54,17 +54,36 @@ __host__ __device__ __forceinline__ SbdfCoef sbdf_coef(int n, int order, double 
   for (int i = 0; i <= KS_MAX_ORDER; ++i) r.a[i] = r.a[i] / dt;
   return r;
 }
-// The rows of a run, by q = min(n, order): built once on the host, passed by value.
-struct SbdfTable {
-  SbdfCoef row[KS_MAX_ORDER + 1];   // row[q], q = 1..order
-};
-SbdfTable sbdf_table(int order, double dt) {
-  SbdfTable t;
-  for (int q = 0; q <= KS_MAX_ORDER; ++q) t.row[q] = sbdf_coef(q < 1 ? 1 : q, order, dt);
-  return t;
-}
-__device__ __forceinline__ const SbdfCoef& sbdf_row(const SbdfTable& t, int n, int order) {
-  return t.row[n < order ? n : order];
+// Row of step n for step sizes h (h[i] = t_{i+1} - t_i; step n advances from t_{n-1} by
+// h[n-1]): with q = min(n, order) and the nodes tau_j = t_{n-j} - t_n, j = 0..q, a_j is the
+// derivative at tau = 0 of the Lagrange basis polynomial of node j on tau_0..tau_q (the
+// q-step backward difference of dX/dt at t_n) and c_i the value at 0 of the basis polynomial
+// of node i on tau_1..tau_q (extrapolation of F).  Equal steps give the rows of sbdf_coef.
+SbdfCoef sbdf_row_variable(const double* h, int n, int order) {
+  const int q = n < order ? n : order;
+  double tau[KS_MAX_ORDER + 1];
+  tau[0] = 0.0;
+  for (int j = 1; j <= q; ++j) tau[j] = tau[j - 1] - h[n - j];
+  SbdfCoef r;
+  for (int i = 0; i <= KS_MAX_ORDER; ++i) r.a[i] = r.c[i] = 0.0;
+  for (int j = 0; j <= q; ++j) {
+    double d = 0.0;
+    for (int k = 0; k <= q; ++k) {
+      if (k == j) continue;
+      double p = 1.0 / (tau[j] - tau[k]);
+      for (int m = 0; m <= q; ++m)
+        if (m != j && m != k) p *= (0.0 - tau[m]) / (tau[j] - tau[m]);
+      d += p;
+    }
+    r.a[j] = d;
+  }
+  for (int i = 1; i <= q; ++i) {
+    double p = 1.0;
+    for (int m = 1; m <= q; ++m)
+      if (m != i) p *= (0.0 - tau[m]) / (tau[i] - tau[m]);
+    r.c[i] = p;
+  }
+  return r;
 }
 
 // Grid values from half-spectrum coefficients (LDS), W = 2 for the real field
@@ -167,8 +186,9 @@ __device__ __forceinline__ KsLds ks_lds(const KsDev& d, double* smem) {
 }
 
 // Forward sweep: X (in: X_0, out: X_N), history H[n][K] of X_0 .. X_N.  One block.
-__global__ void __launch_bounds__(NTS) ks_forward(KsDev d, cplx* X, cplx* H, int nsteps, int order,
-                                                 SbdfTable tab, int* err) {
+// rows[n]: the coefficients of step n (device array, rows beyond the run zero)
+__global__ void __launch_bounds__(NTS) ks_forward(KsDev d, cplx* X, cplx* H, int nsteps, const SbdfCoef* rows,
+                                                 int* err) {
   extern __shared__ double smem_d[];
   const KsLds L = ks_lds(d, smem_d);
   const int m = threadIdx.x, K = d.K;
@@ -187,7 +207,7 @@ __global__ void __launch_bounds__(NTS) ks_forward(KsDev d, cplx* X, cplx* H, int
   ks_eval_F(d, L.ex, L.c, L.u, L.fo);
   if (own) f[0] = L.fo[m];
   for (int n = 1; n <= nsteps; ++n) {
-    const SbdfCoef& q = sbdf_row(tab, n, order);
+    const SbdfCoef q = rows[n];
     cplx fs = czero(), xs = czero();
 #pragma unroll
     for (int i = 1; i <= KS_MAX_ORDER; ++i) {
@@ -222,8 +242,8 @@ __global__ void __launch_bounds__(NTS) ks_forward(KsDev d, cplx* X, cplx* H, int
 // The cotangent of X_{n-1} collects Y_{n-1+i} from steps n-1+i, i = 1..order (equ:IMEX_adjoint),
 // so it is complete once Y_n is known; F's VJP, linear in its cotangent, is applied once per
 // state.  Y of steps beyond nsteps are zero.
-__global__ void __launch_bounds__(NTS) ks_adjoint(KsDev d, cplx* Xbar, const cplx* H, int nsteps, int order,
-                                                 SbdfTable tab) {
+__global__ void __launch_bounds__(NTS) ks_adjoint(KsDev d, cplx* Xbar, const cplx* H, int nsteps,
+                                                 const SbdfCoef* rows) {
   extern __shared__ double smem_d[];
   const KsLds L = ks_lds(d, smem_d);
   const int m = threadIdx.x, K = d.K;
@@ -235,13 +255,13 @@ __global__ void __launch_bounds__(NTS) ks_adjoint(KsDev d, cplx* Xbar, const cpl
   for (int i = 0; i < KS_MAX_ORDER - 1; ++i) ys[i] = czero();
   cplx hnext = (own && nsteps >= 1) ? H[(size_t)(nsteps - 1) * K + m] : czero();
   for (int n = nsteps; n >= 1; --n) {
-    const SbdfCoef& q = sbdf_row(tab, n, order);
+    const SbdfCoef q = rows[n];
     const cplx y = cscale(xb, 1.0 / (q.a[0] + lin));
     cplx g = cscale(y, q.c[1]);
     cplx lin_part = cscale(y, q.a[1]);
 #pragma unroll
     for (int i = 2; i <= KS_MAX_ORDER; ++i) {
-      const SbdfCoef& qi = sbdf_row(tab, n - 1 + i, order);   // step n-1+i, its term i
+      const SbdfCoef qi = rows[n - 1 + i];   // step n-1+i, its term i
       g = cadd(g, cscale(ys[i - 2], qi.c[i]));
       lin_part = cadd(lin_part, cscale(ys[i - 2], qi.a[i]));
     }
@@ -335,8 +355,38 @@ class KsProblem : public ProblemImpl {
     H_ = arena_.alloc<cplx>((size_t)(desc.max_steps + 1) * K_);
     Xw_ = arena_.alloc<cplx>(K_);
     err_ = arena_.alloc<int>(1);
+    nrows_ = desc.max_steps + KS_MAX_ORDER + 2;
+    rows_ = arena_.alloc<SbdfCoef>(nrows_);
     SPS_HIP(hipMemsetAsync(err_, 0, sizeof(int), stream));
+    upload_rows(0, nullptr);
+  }
+
+  // Rows of the run: the constant-step rows of desc.dt (dts null), or the variable-step rows of
+  // the step sizes dts[0..n-1]; rows past the last step are zero (the adjoint reads up to
+  // KS_MAX_ORDER - 1 of them, against zero cotangents).
+  void upload_rows(int n, const double* dts) {
+    hrows_.assign(nrows_, SbdfCoef{});
+    for (auto& r : hrows_)
+      for (int i = 0; i <= KS_MAX_ORDER; ++i) r.a[i] = r.c[i] = 0.0;
+    if (!dts) {
+      for (int m = 1; m <= desc_.max_steps; ++m) hrows_[m] = sbdf_coef(m, order_, desc_.dt);
+    } else {
+      for (int m = 1; m <= n; ++m) hrows_[m] = sbdf_row_variable(dts, m, order_);
+    }
+    SPS_HIP(hipMemcpyAsync(rows_, hrows_.data(), sizeof(SbdfCoef) * nrows_, hipMemcpyHostToDevice, stream));
     SPS_HIP(hipStreamSynchronize(stream));
+  }
+  void set_timesteps(const double* dts, int n) override {
+    if (!dts || n == 0) {
+      upload_rows(0, nullptr);
+      var_n_ = 0;
+    } else {
+      SPS_REQUIRE(n >= 1 && n <= desc_.max_steps, "the step sequence must have 1 .. max_steps entries");
+      for (int i = 0; i < n; ++i) SPS_REQUIRE(std::isfinite(dts[i]) && dts[i] > 0.0, "step sizes must be positive");
+      upload_rows(n, dts);
+      var_n_ = n;
+    }
+    tape_steps_ = -1;
   }
 
   long long state_size() const override { return 2LL * K_; }
@@ -344,14 +394,14 @@ class KsProblem : public ProblemImpl {
 
   void step(double* X, int nsteps) override {
     SPS_REQUIRE(X != nullptr, "X is null");
-    SPS_REQUIRE(nsteps >= 1 && nsteps <= desc_.max_steps, "nsteps out of range");
+    SPS_REQUIRE(nsteps >= 1 && nsteps <= (var_n_ ? var_n_ : desc_.max_steps), "nsteps out of range");
     forward(reinterpret_cast<cplx*>(X), nsteps);
   }
   void adjoint_step(double* Xbar, int nsteps) override {
     SPS_REQUIRE(Xbar != nullptr, "Xbar is null");
     if (tape_steps_ != nsteps) throw Error(SPS_E_STATE, "adjoint_step: nsteps does not match the recorded forward run");
     hipLaunchKernelGGL(ks_adjoint, dim3(1), dim3(NTS), lds(), stream, dv_, reinterpret_cast<cplx*>(Xbar), H_, nsteps,
-                       order_, sbdf_table(order_, desc_.dt));
+                       rows_);
     SPS_CHECK_LAUNCH();
   }
   void cost(const double* X, double* J, double* dJdX) override {
@@ -362,7 +412,7 @@ class KsProblem : public ProblemImpl {
   }
   void gradient(const double* X0, int nsteps, double* XN, double* dJdX0, double* J) override {
     SPS_REQUIRE(X0 && dJdX0, "null argument");
-    SPS_REQUIRE(nsteps >= 1 && nsteps <= desc_.max_steps, "nsteps out of range");
+    SPS_REQUIRE(nsteps >= 1 && nsteps <= (var_n_ ? var_n_ : desc_.max_steps), "nsteps out of range");
     SPS_HIP(hipMemcpyAsync(Xw_, X0, sizeof(cplx) * K_, hipMemcpyDeviceToDevice, stream));
     forward(Xw_, nsteps);
     if (XN) SPS_HIP(hipMemcpyAsync(XN, Xw_, sizeof(cplx) * K_, hipMemcpyDeviceToDevice, stream));
@@ -411,11 +461,10 @@ class KsProblem : public ProblemImpl {
   void forward(cplx* X, int nsteps) {
     hipEvent_t e0, e1;
     if (timer_.take(&e0, &e1))
-      hipExtLaunchKernelGGL(ks_forward, dim3(1), dim3(NTS), lds(), stream, e0, e1, 0, dv_, X, H_, nsteps, order_, sbdf_table(order_, desc_.dt),
+      hipExtLaunchKernelGGL(ks_forward, dim3(1), dim3(NTS), lds(), stream, e0, e1, 0, dv_, X, H_, nsteps, rows_,
                             err_);
     else
-      hipLaunchKernelGGL(ks_forward, dim3(1), dim3(NTS), lds(), stream, dv_, X, H_, nsteps, order_,
-                         sbdf_table(order_, desc_.dt), err_);
+      hipLaunchKernelGGL(ks_forward, dim3(1), dim3(NTS), lds(), stream, dv_, X, H_, nsteps, rows_, err_);
     SPS_CHECK_LAUNCH();
     tape_steps_ = nsteps;
   }
@@ -427,6 +476,9 @@ class KsProblem : public ProblemImpl {
   DevArena arena_;
   cplx *H_ = nullptr, *Xw_ = nullptr;
   int* err_ = nullptr;
+  SbdfCoef* rows_ = nullptr;          // [nrows_] coefficient rows of the steps (device)
+  std::vector<SbdfCoef> hrows_;       // their host copy
+  int nrows_ = 0, var_n_ = 0;         // var_n_ > 0: variable steps, runs of at most var_n_ steps
   int tape_steps_ = -1;
   KernelTimer timer_;
 };

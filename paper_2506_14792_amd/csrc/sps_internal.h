@@ -125,6 +125,9 @@ class ProblemImpl {
   virtual void eval_F(const double* X, double* F) = 0;
   virtual void eval_F_vjp(const double* X, const double* Fbar, double* Xbar) = 0;
   virtual void solve(const double* R, double* X, int adjoint) = 0;
+  virtual void set_timesteps(const double*, int) {
+    throw Error(SPS_E_UNSUPPORTED, "variable steps are built for the KS problem");
+  }
   virtual void set_checkpointing(int, int) {
     throw Error(SPS_E_UNSUPPORTED, "checkpoint schedules are built for the RK222 problems");
   }

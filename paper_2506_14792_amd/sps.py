@@ -54,6 +54,7 @@ def lib():
         "sps_eval_F": (ctypes.c_int, [_P, _D, _D]),
         "sps_eval_F_vjp": (ctypes.c_int, [_P, _D, _D, _D]),
         "sps_solve": (ctypes.c_int, [_P, _D, _D, ctypes.c_int]),
+        "sps_set_timesteps": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.c_int]),
         "sps_set_checkpointing": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
         "sps_checkpoint_schedule": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                                    ctypes.POINTER(ctypes.c_int), ctypes.c_int,
@@ -199,6 +200,16 @@ class Problem:
 
     def solve(self, R, X, adjoint=False):
         _check(lib().sps_solve(self._h, _ptr(R, self.n), _ptr(X, self.n), int(bool(adjoint))))
+
+    def set_timesteps(self, dts=None):
+        """Variable step sizes (a host sequence) for the following runs; None: the constant dt."""
+        if dts is None:
+            _check(lib().sps_set_timesteps(self._h, None, 0))
+        else:
+            import numpy as np
+            h = np.ascontiguousarray(dts, dtype=np.float64)
+            _check(lib().sps_set_timesteps(self._h, h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(h.size)))
+        self.tape_id += 1
 
     def set_checkpointing(self, scheme, slots=0):
         """CKPT_UNIFORM (checkpoints every checkpoint_every steps) or CKPT_BINOMIAL with `slots`

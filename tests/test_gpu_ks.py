@@ -168,3 +168,47 @@ def test_ks_higher_order_step_adjoint_and_solve(order):
     G.solve(to_dev(R), out)
     G.sync()
     assert rel(from_dev(out, P.K), imex.BlockLU(P.M, P.L, a[0], b[0]).solve(R)) < TOL
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+@pytest.mark.parametrize("kind", ["ramp", "random"])
+def test_ks_variable_steps_gradient(order, kind):
+    """Variable step sizes (sps_set_timesteps): 200 steps growing linearly by 2x around 0.05, or
+    i.i.d. within +-30 %: forward run, J and gradient vs the oracle's variable-step rows; then
+    the constant step again gives the constant-step run."""
+    print(f"KS SBDF{order} variable steps ({kind})", flush=True)
+    cfg, nsteps = FULL, 200
+    P, G = build(cfg, max_steps=nsteps, order=order)
+    if kind == "ramp":
+        h = 0.05 * (0.67 + 0.67 * np.arange(nsteps) / nsteps)
+    else:
+        h = 0.05 * (1.0 + 0.3 * (2.0 * np.random.default_rng(order).random(nsteps) - 1.0))
+    X0 = wl.ks_c0(seed=18, Nx=cfg[0], amp=0.5)[:, None]
+    XN_ref, states = imex.sbdf_forward(P, X0, h, nsteps, order=order)
+    g_ref = imex.sbdf_adjoint(P, P.energy_grad(XN_ref), states, h, order=order)
+    G.set_timesteps(h)
+    XN = torch.zeros(G.n, dtype=torch.float64, device="cuda")
+    gX = torch.zeros_like(XN)
+    J = torch.zeros(1, dtype=torch.float64, device="cuda")
+    G.gradient(to_dev(X0), nsteps, XN, gX, J)
+    G.sync()
+    ex, eg = rel(from_dev(XN, P.K), XN_ref), rel(from_dev(gX, P.K), g_ref)
+    print(f"  XN rel {ex:.2e}  dJ/dX0 rel {eg:.2e}", flush=True)
+    assert ex < TOL and eg < TOL and abs(J.item() - P.energy(XN_ref)) < TOL * P.energy(XN_ref)
+    G.set_timesteps(None)
+    G.gradient(to_dev(X0), nsteps, XN, gX, J)
+    G.sync()
+    XN_c, _ = imex.sbdf_forward(P, X0, cfg[2], nsteps, order=order)
+    assert rel(from_dev(XN, P.K), XN_c) < TOL
+
+
+def test_ks_variable_steps_arguments():
+    P, G = build(SMALL, max_steps=10)
+    with pytest.raises(sps.SpsError):
+        G.set_timesteps(np.full(11, 0.01))        # longer than max_steps
+    with pytest.raises(sps.SpsError):
+        G.set_timesteps(np.array([0.01, -0.01]))  # a negative step
+    G.set_timesteps(np.full(4, 0.01))
+    X = to_dev(wl.ks_c0(seed=1, Nx=SMALL[0])[:, None])
+    with pytest.raises(sps.SpsError):
+        G.step(X, 5)                               # more steps than sizes given
