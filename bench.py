@@ -338,6 +338,16 @@ def ckpt_timing(slot_counts=(5, 10, 20, 50)):
         steps = sum(b - a for op, a, b in fwd + rev if op == 1) + sum(1 for op, _, _ in rev if op == 4)
         out[f"binomial_{slots}"] = {"gradient_s": timed(), "forward_steps": steps,
                                     "stored_MB": slots * state_mb + 2 * stage_mb}
+    # two levels: segment starts (every 50 steps) in pinned host memory, binomial inside
+    for slots in (3, 8):
+        G.set_checkpointing(sps.CKPT_TWO_LEVEL, slots)
+        fs, rs = sps.checkpoint_schedule(ce, slots)
+        last = max(i for i, a in enumerate(fs) if a[0] == 2)
+        seg_steps = (sum(b - a for op, a, b in fs[:last + 1] if op == 1)
+                     + sum(b - a for op, a, b in rs if op == 1) + sum(1 for op, _, _ in rs if op == 4))
+        out[f"two_level_{slots}"] = {"gradient_s": timed(), "forward_steps": n + (n // ce) * seg_steps,
+                                     "stored_MB": slots * state_mb + 2 * stage_mb,
+                                     "host_stored_MB": (n // ce) * state_mb}
     G.set_checkpointing(sps.CKPT_UNIFORM)
     G.sync()
     return out

@@ -235,12 +235,16 @@ int sps_set_timesteps(sps_problem *P, const double *dts, int n);
  * stream while the adjoint of the next one runs.  scheme SPS_CKPT_BINOMIAL: `slots` >= 1 stored
  * states (slot 0 holds X_0) placed by the binomial schedule of sps_checkpoint_schedule, which
  * needs the fewest forward recomputations for that storage; sps_step runs its forward sweep,
- * sps_adjoint_step and sps_gradient its reverse sweep, all on the problem's stream.  Gradients
- * are the same as with the default schedule.  Device memory: `slots` states (K S complex
- * values each), held until sps_destroy.  Drops recorded graphs and the recorded forward run
+ * sps_adjoint_step and sps_gradient its reverse sweep, all on the problem's stream.  scheme
+ * SPS_CKPT_TWO_LEVEL: the state at the start of every segment of checkpoint_every steps is
+ * stored in pinned host memory by the forward sweep; the reverse sweep brings the segments
+ * back from the last and reverses each with the binomial schedule of its length on `slots`
+ * device states (sps_gradient then runs eagerly, also in graph mode).  Gradients are the same
+ * as with the default schedule.  Device memory: `slots` states (K S complex values each);
+ * host memory (two levels): ceil(max_steps / checkpoint_every) states; held until sps_destroy.  Drops recorded graphs and the recorded forward run
  * (sps_adjoint_step needs a new sps_step).  The 2D and plane Couette problems;
  * SPS_E_UNSUPPORTED otherwise. */
-enum sps_checkpointing { SPS_CKPT_UNIFORM = 0, SPS_CKPT_BINOMIAL = 1 };
+enum sps_checkpointing { SPS_CKPT_UNIFORM = 0, SPS_CKPT_BINOMIAL = 1, SPS_CKPT_TWO_LEVEL = 2 };
 int sps_set_checkpointing(sps_problem *P, int scheme, int slots);
 
 /* The binomial schedule for nsteps steps and `slots` stored states (host arrays; no problem

@@ -1533,6 +1533,7 @@ class RbcProblem : public ProblemImpl {
   }
   ~RbcProblem() override {
     drop_graphs();
+    if (host_ckpt_) (void)hipStreamSynchronize(stream);   // copies into pinned host memory
     if (cap_) (void)hipStreamDestroy(cap_);
     if (aux_) (void)hipStreamSynchronize(aux_);
     for (auto e : ev_)
@@ -1583,7 +1584,7 @@ class RbcProblem : public ProblemImpl {
     SPS_REQUIRE(X0 && dJdX0, "null argument");
     SPS_REQUIRE(nsteps >= 1 && nsteps <= desc_.max_steps, "nsteps out of range");
     factor();
-    if (graph_on_) {
+    if (graph_on_ && ckpt_mode_ != SPS_CKPT_TWO_LEVEL) {
       const GraphKey key{X0, XN, dJdX0, J, nsteps};
       for (const auto& g : graphs_)
         if (g.first == key) {
@@ -1873,6 +1874,10 @@ class RbcProblem : public ProblemImpl {
       forward_binomial(X, nsteps);
       return;
     }
+    if (ckpt_mode_ == SPS_CKPT_TWO_LEVEL) {
+      forward_two_level(X, nsteps);
+      return;
+    }
     const int ce = desc_.checkpoint_every;
     const int nseg = (nsteps + ce - 1) / ce;
     const int last0 = (nseg - 1) * ce;   // first step of the last segment: recorded now
@@ -1904,6 +1909,10 @@ class RbcProblem : public ProblemImpl {
   void reverse(cplx* Xbar, int nsteps) {
     if (ckpt_mode_ == SPS_CKPT_BINOMIAL) {
       reverse_binomial(Xbar, nsteps);
+      return;
+    }
+    if (ckpt_mode_ == SPS_CKPT_TWO_LEVEL) {
+      reverse_two_level(Xbar, nsteps);
       return;
     }
     const int ce = desc_.checkpoint_every;
@@ -1946,45 +1955,61 @@ class RbcProblem : public ProblemImpl {
   // step's two stage-field sets in the first segment slot and runs the step's adjoint launches,
   // exactly those of the segment sweep.
   void set_checkpointing(int scheme, int slots) override {
-    SPS_REQUIRE(scheme == SPS_CKPT_UNIFORM || scheme == SPS_CKPT_BINOMIAL, "unknown checkpointing scheme");
-    if (scheme == SPS_CKPT_BINOMIAL) {
+    SPS_REQUIRE(scheme == SPS_CKPT_UNIFORM || scheme == SPS_CKPT_BINOMIAL || scheme == SPS_CKPT_TWO_LEVEL,
+                "unknown checkpointing scheme");
+    if (scheme != SPS_CKPT_UNIFORM) {
       SPS_REQUIRE(slots >= 1 && slots <= desc_.max_steps + 1, "slots must be in [1, max_steps + 1]");
       if (slots > rv_cap_) {
         rv_ = arena_.alloc<cplx>((size_t)slots * K_ * S_);
         rv_cap_ = slots;
       }
     }
+    if (scheme == SPS_CKPT_TWO_LEVEL && !host_ckpt_) {
+      const int nseg = (desc_.max_steps + desc_.checkpoint_every - 1) / desc_.checkpoint_every;
+      void* p = nullptr;
+      SPS_HIP(hipHostMalloc(&p, sizeof(cplx) * K_ * S_ * (size_t)nseg, hipHostMallocDefault));
+      host_ckpt_.reset(reinterpret_cast<cplx*>(p));
+      if (!Xs_) Xs_ = arena_.alloc<cplx>((size_t)K_ * S_);
+    }
     drop_graphs();
     ckpt_mode_ = scheme;
-    rv_slots_ = (scheme == SPS_CKPT_BINOMIAL) ? slots : 0;
-    rv_n_ = -1;
+    rv_slots_ = (scheme == SPS_CKPT_UNIFORM) ? 0 : slots;
+    sched_.clear();
     tape_steps_ = -1;
   }
   cplx* rvslot(int i) { return rv_ + (size_t)i * K_ * S_; }
-  void ensure_schedule(int nsteps) {
-    if (rv_n_ == nsteps) return;
-    binomial_schedule(nsteps, rv_slots_, rv_fwd_, rv_rev_);
-    rv_n_ = nsteps;
+  // binomial schedule (forward and reverse actions) for a run of n steps with rv_slots_ slots
+  const std::pair<std::vector<CkptAction>, std::vector<CkptAction>>& schedule(int n) {
+    auto it = sched_.find(n);
+    if (it == sched_.end()) {
+      std::pair<std::vector<CkptAction>, std::vector<CkptAction>> v;
+      binomial_schedule(n, rv_slots_, v.first, v.second);
+      it = sched_.emplace(n, std::move(v)).first;
+    }
+    return it->second;
   }
   void copy_state(cplx* dst, const cplx* src) {
-    SPS_HIP(hipMemcpyAsync(dst, src, sizeof(cplx) * K_ * S_, hipMemcpyDeviceToDevice, stream));
+    SPS_HIP(hipMemcpyAsync(dst, src, sizeof(cplx) * K_ * S_, hipMemcpyDefault, stream));
   }
   void advance(cplx* X, int a, int b) {
     launch_kf(KF_ZGRID, X, nullptr, nullptr, zgA_);
     for (int n = a; n < b; ++n) rk_step(stream, X, zgA_, zgA_, (n + 1 < b) ? zgA_ : nullptr);
   }
-  void forward_binomial(cplx* X, int nsteps) {
-    ensure_schedule(nsteps);
-    for (const CkptAction& c : rv_fwd_) {
+  // forward actions of a schedule on the working state X (stored states in the slots); with
+  // to_end false, the advance past the last stored state (to the run's final state) is skipped
+  void run_forward_actions(cplx* X, const std::vector<CkptAction>& acts, bool to_end = true) {
+    size_t last = acts.size();
+    if (!to_end)
+      while (last > 0 && acts[last - 1].op != CK_TAKESHOT) --last;
+    for (size_t i = 0; i < last; ++i) {
+      const CkptAction& c = acts[i];
       if (c.op == CK_TAKESHOT) copy_state(rvslot(c.a), X);
       else if (c.op == CK_ADVANCE) advance(X, c.a, c.b);
     }
-    tape_steps_ = nsteps;
   }
-  void reverse_binomial(cplx* Xbar, int nsteps) {
-    ensure_schedule(nsteps);
-    bool first = true;
-    for (const CkptAction& c : rv_rev_) {
+  // reverse actions on the working state Xw_; `first`: no reverse step has run yet in this sweep
+  void run_reverse_actions(cplx* Xbar, const std::vector<CkptAction>& acts, bool& first) {
+    for (const CkptAction& c : acts) {
       switch (c.op) {
         case CK_RESTORE: copy_state(Xw_, rvslot(c.a)); break;
         case CK_TAKESHOT: copy_state(rvslot(c.a), Xw_); break;
@@ -2004,9 +2029,44 @@ class RbcProblem : public ProblemImpl {
         default: throw Error(SPS_E_STATE, "bad checkpoint action");
       }
     }
+  }
+  void finish_reverse(cplx* Xbar) {
     KaArgs a = ka_args(KA_C);
     a.Xb_out = Xbar;
     launch_ka(a);
+  }
+  void forward_binomial(cplx* X, int nsteps) {
+    run_forward_actions(X, schedule(nsteps).first);
+    tape_steps_ = nsteps;
+  }
+  void reverse_binomial(cplx* Xbar, int nsteps) {
+    bool first = true;
+    run_reverse_actions(Xbar, schedule(nsteps).second, first);
+    finish_reverse(Xbar);
+  }
+  // Two levels: the state at the start of every segment of checkpoint_every steps goes to
+  // pinned host memory during the forward sweep; the reverse sweep brings the segments back
+  // from the last, and reverses each with the binomial schedule of its length on the device
+  // slots (the segment's own forward actions first, then its turns).
+  int seg_len(int g, int nsteps) const { return std::min(desc_.checkpoint_every, nsteps - g * desc_.checkpoint_every); }
+  void forward_two_level(cplx* X, int nsteps) {
+    const int ce = desc_.checkpoint_every, nseg = (nsteps + ce - 1) / ce;
+    for (int g = 0; g < nseg; ++g) {
+      copy_state(host_ckpt_.get() + (size_t)g * K_ * S_, X);
+      advance(X, 0, seg_len(g, nsteps));
+    }
+    tape_steps_ = nsteps;
+  }
+  void reverse_two_level(cplx* Xbar, int nsteps) {
+    const int ce = desc_.checkpoint_every, nseg = (nsteps + ce - 1) / ce;
+    bool first = true;
+    for (int g = nseg - 1; g >= 0; --g) {
+      const auto& sc = schedule(seg_len(g, nsteps));
+      copy_state(Xs_, host_ckpt_.get() + (size_t)g * K_ * S_);
+      run_forward_actions(Xs_, sc.first, false);
+      run_reverse_actions(Xbar, sc.second, first);
+    }
+    finish_reverse(Xbar);
   }
 
   // ----------------------------------------------------------------- tables
@@ -2150,9 +2210,14 @@ class RbcProblem : public ProblemImpl {
   std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs_;
   bool factored_ = false;
   int tape_steps_ = -1;
-  int ckpt_mode_ = SPS_CKPT_UNIFORM, rv_slots_ = 0, rv_cap_ = 0, rv_n_ = -1;
+  int ckpt_mode_ = SPS_CKPT_UNIFORM, rv_slots_ = 0, rv_cap_ = 0;
   cplx* rv_ = nullptr;   // binomial schedule's stored states
-  std::vector<CkptAction> rv_fwd_, rv_rev_;
+  cplx* Xs_ = nullptr;   // working state of a two-level segment's forward actions
+  std::map<int, std::pair<std::vector<CkptAction>, std::vector<CkptAction>>> sched_;   // by run length
+  struct HostFree {
+    void operator()(cplx* p) const { (void)hipHostFree(p); }
+  };
+  std::unique_ptr<cplx, HostFree> host_ckpt_;   // two-level: segment start states in pinned host memory
   KernelTimer timer_;
 };
 

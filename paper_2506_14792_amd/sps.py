@@ -9,7 +9,7 @@ LIB_PATH = os.path.join(_HERE, "libsps.so")
 
 RBC2D, KS1D, SH2D = 1, 2, 3
 RK222, SBDF2, SBDF3, SBDF4 = 1, 2, 3, 4
-CKPT_UNIFORM, CKPT_BINOMIAL = 0, 1
+CKPT_UNIFORM, CKPT_BINOMIAL, CKPT_TWO_LEVEL = 0, 1, 2
 
 _STATUS = {0: "SPS_OK", -1: "SPS_E_ARG", -2: "SPS_E_NOMEM", -3: "SPS_E_HIP", -4: "SPS_E_SINGULAR",
            -5: "SPS_E_NONFINITE", -6: "SPS_E_STATE", -7: "SPS_E_UNSUPPORTED"}
@@ -212,8 +212,9 @@ class Problem:
         self.tape_id += 1
 
     def set_checkpointing(self, scheme, slots=0):
-        """CKPT_UNIFORM (checkpoints every checkpoint_every steps) or CKPT_BINOMIAL with `slots`
-        stored states; drops the recorded forward run."""
+        """CKPT_UNIFORM (checkpoints every checkpoint_every steps), CKPT_BINOMIAL with `slots`
+        stored states, or CKPT_TWO_LEVEL (segment starts in host memory, binomial inside a segment
+        on `slots` device states); drops the recorded forward run."""
         _check(lib().sps_set_checkpointing(self._h, int(scheme), int(slots)))
         self.tape_id += 1
 

@@ -1,5 +1,5 @@
-"""GPU checks of binomial checkpointing (sps_set_checkpointing): the gradient, the final state
-and J under the binomial schedule are bit-for-bit those of the default uniform schedule (the
+"""GPU checks of binomial and two-level checkpointing (sps_set_checkpointing): the gradient, the
+final state and J under these schedules are bit-for-bit those of the default uniform schedule (the
 same kernels on the same inputs, only their order and the stored states differ) for several
 slot counts on the 2D problem, through sps_gradient, sps_step + sps_adjoint_step and graph
 replay, at 24x16 (also against the oracle, 1e-11) and at the full 256x64 / 1000-step
@@ -130,3 +130,54 @@ def test_checkpointing_unsupported_for_multistep_problems():
     with pytest.raises(sps.SpsError) as e:
         G.set_checkpointing(sps.CKPT_BINOMIAL, 2)
     assert e.value.code == -7
+
+
+def test_two_level_equals_uniform():
+    """Segment starts in pinned host memory, binomial inside each segment on device slots:
+    24x16 with ragged segments (13 steps, segments of 4) for 1-3 slots and in graph mode (which
+    runs eagerly), and the full 256x64 / 1000-step configuration with 5 slots."""
+    n, ce = 13, 4
+    note(f"two-level vs uniform, 24x16, {n} steps")
+    P, G, X0h = small_problem(n, ce)
+    X0 = to_dev(X0h)
+    ref = grad(G, X0, n)
+    for slots in (1, 2, 3):
+        G.set_checkpointing(sps.CKPT_TWO_LEVEL, slots)
+        got = grad(G, X0, n)
+        same = all(torch.equal(a, b) for a, b in zip(got, ref))
+        note(f"  slots {slots}: identical {same}")
+        assert same
+    G.set_graph(True)
+    assert all(torch.equal(a, b) for a, b in zip(grad(G, X0, n), ref))
+    G.set_graph(False)
+    X = X0.clone()
+    G.step(X, n)
+    dJ = torch.zeros_like(X)
+    G.cost(X, None, dJ)
+    G.adjoint_step(dJ, n)
+    G.sync()
+    assert torch.equal(X, ref[0]) and torch.equal(dJ, ref[1])
+
+    note("two-level vs uniform, 256x64, 1000 steps, 5 slots")
+    nx, nz, lx, Ra, Pr, dt = FULL
+    nf = 1000
+    Gf = sps.Problem(sps.RBC2D, nx, nz, lx, Ra, Pr, 1.5, dt, 50, nf)
+    b0 = torch.from_numpy(wl.rbc_b0(seed=0, Nx=nx, Nz=nz).ravel().copy()).cuda()
+    Xf = torch.zeros(Gf.n, dtype=torch.float64, device="cuda")
+    Gf.initial_state(b0, Xf)
+    reff = grad(Gf, Xf, nf)
+    Gf.set_checkpointing(sps.CKPT_TWO_LEVEL, 5)
+    gotf = grad(Gf, Xf, nf)
+    same = all(torch.equal(a, b) for a, b in zip(gotf, reff))
+    note(f"  identical {same}")
+    assert same
+
+
+def test_two_level_couette():
+    n = 9
+    G = sps.Couette(8, 12, 8, Re=400.0, dt=0.01, checkpoint_every=4, max_steps=n)
+    uvw = wl.couette_perturbation(seed=5, Nx=8, Ny=12, Nz=8, energy=1e-3)
+    X0 = torch.from_numpy(G.state_from_velocity(uvw)).cuda()
+    ref = grad(G, X0, n)
+    G.set_checkpointing(sps.CKPT_TWO_LEVEL, 2)
+    assert all(torch.equal(a, b) for a, b in zip(grad(G, X0, n), ref))
