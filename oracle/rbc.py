@@ -268,3 +268,58 @@ class RBC:
         for name in ("u", "w", "b"):
             fb[:, self.sl(name)] = Y[:, self.sl(name)] @ self.S10
         return fb
+
+    # ------------------------------------------------------------------ linear stability (eigenvalue problem)
+    # Supplementary, "Eigenvalue problems": (lambda M + L) X = 0, the adjoint problem
+    # (conj(lambda) M^H + L^H) Y = 0, and the eigenvalue sensitivity equ:eigenvalue_sens,
+    # d lambda / dp = -<Y, (lambda dM/dp + dL/dp) X> / <Y, M X>.  The operator is that of a
+    # perturbation of the conduction state b0 = 1 - z, u = 0: the IVP's L plus the linearized
+    # advection of b0 by w (w db0/dz = -w), -S10 w in the b rows; lambda is the growth rate
+    # (perturbations ~ exp(lambda t)).  M does not depend on Ra or k.
+
+    def stability_operator(self):
+        Ls = self.L.copy()
+        for k in range(self.K):
+            Ls[k][self.sl("b"), self.sl("w")] -= self.S10
+        return Ls
+
+    def stability_eig(self, k, sigma):
+        """Eigenvalue of wavenumber k nearest sigma, with right and left (adjoint) eigenvectors,
+        from the dense generalized eigenproblem L X = -lambda M X (scipy; M singular, so the
+        infinite eigenvalues are dropped)."""
+        import scipy.linalg as sla
+        Ls = self.stability_operator()[k]
+        w, vl, vr = sla.eig(Ls, -self.M[k], left=True, right=True)
+        ok = np.isfinite(w)
+        i = np.flatnonzero(ok)[np.argmin(np.abs(w[ok] - sigma))]
+        return w[i], vr[:, i], vl[:, i]
+
+    def _L_with(self, k, nu=None, ka=None, kx=None):
+        saved = (self.nu, self.kappa, self.kx[k])
+        if nu is not None:
+            self.nu = nu
+        if ka is not None:
+            self.kappa = ka
+        if kx is not None:
+            self.kx[k] = kx
+        _, L, _ = self._build_matrices()
+        self.nu, self.kappa, self.kx[k] = saved
+        return L[k]
+
+    def stability_dL(self, k):
+        """dL/dRa and dL/dk of wavenumber k, exactly: L is affine in nu and kappa (differences
+        at unit and zero values), quadratic in k (a central difference is exact), and the
+        stability coupling depends on neither."""
+        Lnu = self._L_with(k, nu=1.0, ka=0.0) - self._L_with(k, nu=0.0, ka=0.0)
+        Lka = self._L_with(k, nu=0.0, ka=1.0) - self._L_with(k, nu=0.0, ka=0.0)
+        dnu = -0.5 * self.nu / self.Ra
+        dka = -0.5 * self.kappa / self.Ra
+        h = 0.5
+        dLk = (self._L_with(k, kx=self.kx[k] + h) - self._L_with(k, kx=self.kx[k] - h)) / (2 * h)
+        return dnu * Lnu + dka * Lka, dLk
+
+    def stability_sensitivity(self, k, lam, X, Y):
+        """(d lambda/dRa, d lambda/dk) by equ:eigenvalue_sens (dM/dp = 0)."""
+        dLRa, dLk = self.stability_dL(k)
+        den = np.vdot(Y, self.M[k] @ X)
+        return -np.vdot(Y, dLRa @ X) / den, -np.vdot(Y, dLk @ X) / den

@@ -1,0 +1,57 @@
+"""Pins of the oracle's eigenvalue problem and eigenvalue sensitivities (Supplementary,
+"Eigenvalue problems", equ:eigenvalue_sens) on the onset of Rayleigh-Benard convection between
+no-slip walls: Newton steps on the growth rate with the adjoint sensitivity converge to the
+textbook critical Rayleigh number 1707.762 at k = 3.1163 with a real leading eigenvalue
+(exchange of stabilities) and a neutral curve with zero slope there; the sensitivities equal
+central differences of the eigenvalues; the left eigenvector solves the adjoint problem."""
+import numpy as np
+
+from oracle.rbc import RBC
+
+KC, RAC = 3.1163, 1707.762
+
+
+def problem(Ra, k=KC, N=32):
+    return RBC(Nx=4, Nz=N, Lx=2.0 * np.pi / k, Ra=Ra, Pr=1.0)
+
+
+def growth(Ra, k=KC):
+    P = problem(Ra, k)
+    lam, X, Y = P.stability_eig(1, 0.0)
+    return P, lam, X, Y
+
+
+def test_newton_on_the_growth_rate_finds_the_textbook_onset():
+    Ra = 1500.0
+    for _ in range(8):
+        P, lam, X, Y = growth(Ra)
+        dRa, _ = P.stability_sensitivity(1, lam, X, Y)
+        Ra -= lam.real / dRa.real
+    P, lam, X, Y = growth(Ra)
+    assert abs(Ra - RAC) < 2e-3, Ra
+    assert abs(lam) < 1e-12 and abs(lam.imag) < 1e-12
+    # the critical wavenumber is the minimum of the neutral curve: dRa/dk = -(dl/dk)/(dl/dRa)
+    dRa, dk = P.stability_sensitivity(1, lam, X, Y)
+    assert abs(dk.real / dRa.real) < 0.1
+    P2, lam2, X2, Y2 = growth(Ra, k=2.5)
+    dRa2, dk2 = P2.stability_sensitivity(1, lam2, X2, Y2)
+    assert -dk2.real / dRa2.real < -100.0      # Ra rises steeply below k_c
+
+
+def test_sensitivities_equal_central_differences():
+    Ra, h = 1800.0, 0.5
+    P, lam, X, Y = growth(Ra, k=2.8)
+    dRa, dk = P.stability_sensitivity(1, lam, X, Y)
+    fd_Ra = (growth(Ra + h, k=2.8)[1] - growth(Ra - h, k=2.8)[1]) / (2 * h)
+    hk = 1e-4
+    fd_k = (growth(Ra, k=2.8 + hk)[1] - growth(Ra, k=2.8 - hk)[1]) / (2 * hk)
+    assert abs(dRa - fd_Ra) < 1e-6 * abs(dRa)
+    assert abs(dk - fd_k) < 1e-5 * abs(dk)
+
+
+def test_left_eigenvector_solves_the_adjoint_problem():
+    P, lam, X, Y = growth(3000.0, k=4.0)
+    Ls = P.stability_operator()[1]
+    r = (np.conj(lam) * P.M[1].conj().T + Ls.conj().T) @ Y
+    assert np.linalg.norm(r) < 1e-11 * np.linalg.norm(Ls) * np.linalg.norm(Y)
+    assert np.linalg.norm((lam * P.M[1] + Ls) @ X) < 1e-11 * np.linalg.norm(Ls) * np.linalg.norm(X)
