@@ -216,6 +216,21 @@ int sps_eval_F_vjp(sps_problem *P, const double *X, const double *Fbar, double *
  * 11/6, 25/12 over dt for k = 2, 3, 4). */
 int sps_solve(sps_problem *P, const double *R, double *X, int adjoint);
 
+/* Eigenvalue problem of the 2D problem's operator (Supplementary, "Eigenvalue problems"):
+ * linear stability of the conduction state b0 = 1 - z, u = 0, i.e. (lambda M + L_s) X = 0 per
+ * wavenumber with L_s the IVP's L plus the linearized advection of b0 (-S10 w in the b rows),
+ * lambda the growth rate.  For every wavenumber k of the problem at once: the eigenvalue
+ * nearest the real shift sigma by inverse iteration with A = sigma M + L_s (one blocked
+ * almost-banded LU per call, `iters` iterations), the adjoint eigenvector
+ * ((conj(lambda) M^H + L_s^H) Y = 0) by the same number of iterations through the transposed
+ * solves of the same factors, and the eigenvalue sensitivities of equ:eigenvalue_sens,
+ * d lambda/dp = -<Y, dL/dp X> / <Y, M X> for p = Ra (at fixed Pr) and p = k.  Device arrays:
+ * lam[K] complex; X and Y [K][S] complex in the state layout, unit Euclidean norm per
+ * wavenumber; dlam[K][2] complex (d/dRa, d/dk).  Convergence is linear in
+ * |lambda - sigma| / |lambda_2 - sigma|; the caller picks sigma and iters.  The stability bands
+ * and a third factor set are built on the first call.  SPS_E_UNSUPPORTED for other problems. */
+int sps_stability(sps_problem *P, double sigma, int iters, double *lam, double *X, double *Y, double *dlam);
+
 /* Variable time steps of the multistep schemes (equ:imex: the coefficients of step n depend on
  * the step sizes, lower order while the history is short).  dts: HOST array of n step sizes
  * (dts[i] = t_{i+1} - t_i, positive), copied; later sps_step / sps_gradient runs of at most n

@@ -164,6 +164,10 @@ int sps_solve(sps_problem* P, const double* R, double* X, int adjoint) {
   return guard(P, [&](sps::ProblemImpl& p) { p.solve(R, X, adjoint); });
 }
 
+int sps_stability(sps_problem* P, double sigma, int iters, double* lam, double* X, double* Y, double* dlam) {
+  return guard(P, [&](sps::ProblemImpl& p) { p.stability(sigma, iters, lam, X, Y, dlam); });
+}
+
 int sps_set_timesteps(sps_problem* P, const double* dts, int n) {
   return guard(P, [&](sps::ProblemImpl& p) { p.set_timesteps(dts, n); });
 }

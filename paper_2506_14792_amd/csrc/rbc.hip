@@ -1118,6 +1118,111 @@ __global__ void __launch_bounds__(NT) rbc_lbvp_rhs_adj(RbcDev d, const cplx* Y, 
   }
 }
 
+// ---------------------------------------------------------------------------- eigenvalue problem
+// Linear stability of the conduction state (Supplementary, "Eigenvalue problems"):
+// (lambda M + L_s) X = 0 per wavenumber, L_s the IVP's L with -S10 w in the b rows.  The
+// eigenvalue nearest a shift sigma comes from inverse iteration with A = sigma M + L_s:
+// y = A^-1 M x, mu = <x, y> for |x| = 1, lambda = sigma - 1/mu; the adjoint eigenvector
+// ((conj(lambda) M^H + L_s^H) Y = 0) from y = A^-H M^H x through the same factors.
+
+// R = M X: S10 on the u, w, b blocks, zero in the other slots.  One block per wavenumber.
+__global__ void __launch_bounds__(NT) rbc_apply_m(RbcDev d, const cplx* X, cplx* R) {
+  const int k = blockIdx.x, N = d.N, S = d.S;
+  const cplx* xk = X + (size_t)k * S;
+  for (int s = threadIdx.x; s < S; s += NT) {
+    cplx v = czero();
+    if (s < 3 * N) {
+      const int q = s / N, n = s - q * N;
+      v = s10_at(xk + q * N, n, N);
+    }
+    R[(size_t)k * S + s] = v;
+  }
+}
+
+// sum over the block of NT values per component (LDS tree); every thread gets the sums
+template <int C>
+__device__ __forceinline__ void block_sums(double (&v)[C], double (*red)[NT]) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int c = 0; c < C; ++c) red[c][tid] = v[c];
+  __syncthreads();
+  for (int h = NT / 2; h > 0; h >>= 1) {
+    if (tid < h)
+#pragma unroll
+      for (int c = 0; c < C; ++c) red[c][tid] += red[c][tid + h];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c) v[c] = red[c][0];
+}
+
+// One inverse-iteration update per wavenumber: mu = <x, y> (x has unit norm), x <- y / |y|,
+// lam = sigma - 1/mu (lam may be null).
+__global__ void __launch_bounds__(NT) rbc_evp_update(RbcDev d, cplx* x, const cplx* y, double sigma, cplx* lam) {
+  __shared__ double red[3][NT];
+  const int k = blockIdx.x, S = d.S;
+  cplx* xk = x + (size_t)k * S;
+  const cplx* yk = y + (size_t)k * S;
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int s = threadIdx.x; s < S; s += NT) {
+    const cplx a = xk[s], b = yk[s];
+    v[0] += a.x * b.x + a.y * b.y;   // Re conj(a) b
+    v[1] += a.x * b.y - a.y * b.x;   // Im conj(a) b
+    v[2] += b.x * b.x + b.y * b.y;
+  }
+  block_sums<3>(v, red);
+  const double inv = v[2] > 0.0 ? 1.0 / sqrt(v[2]) : 0.0;
+  for (int s = threadIdx.x; s < S; s += NT) xk[s] = cscale(yk[s], inv);
+  if (lam && threadIdx.x == 0) {
+    const double m2 = v[0] * v[0] + v[1] * v[1];
+    lam[k] = cmk(sigma - v[0] / m2, v[1] / m2);   // sigma - 1/mu
+  }
+}
+
+// Eigenvalue sensitivities (equ:eigenvalue_sens, dM/dp = 0): out[k] = (d lambda/dRa,
+// d lambda/dk) = -<Y, dL/dp X> / <Y, M X>, with dL/dRa = dnu dL/dnu + dka dL/dkappa (the
+// viscous and diffusive blocks and their lifted taus) and dL/dk (the k^2 terms, i k p in the
+// x-momentum rows, i k u in continuity).
+__global__ void __launch_bounds__(NT) rbc_evp_sens(RbcDev d, const cplx* X, const cplx* Y, double dnu, double dka,
+                                                   cplx* out) {
+  __shared__ double red[6][NT];
+  const int k = blockIdx.x, N = d.N, S = d.S;
+  const cplx* xk = X + (size_t)k * S;
+  const cplx* yk = Y + (size_t)k * S;
+  const double kx = d.kx[k], k2 = kx * kx;
+  double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // <Y,MX>, <Y,dL/dRa X>, <Y,dL/dk X> (re, im)
+  auto acc = [&](int c, cplx yv, cplx w) {
+    v[2 * c] += yv.x * w.x + yv.y * w.y;
+    v[2 * c + 1] += yv.x * w.y - yv.y * w.x;
+  };
+  for (int s = threadIdx.x; s < 4 * N; s += NT) {
+    const cplx yv = yk[s];
+    if (s < 3 * N) {
+      const int f = s / N, n = s - f * N;
+      const cplx* c = xk + f * N;
+      const double dif = (f == 2) ? d.ka : d.nu, ddif = (f == 2) ? dka : dnu;
+      const cplx sc = s10_at(c, n, N);
+      cplx dra = cscale(cadd(cscale(dzz_at(c, n, N), -1.0), cscale(sc, k2)), ddif);
+      if (n == N - 2) dra = csub(dra, cscale(xk[4 * N + f], 4.0 * ddif));
+      cplx dk = cscale(sc, 2.0 * kx * dif);
+      if (f == 0) dk = cadd(dk, cmul_i(s10_at(xk + 3 * N, n, N)));
+      acc(0, yv, sc);
+      acc(1, yv, dra);
+      acc(2, yv, dk);
+    } else {
+      const int n = s - 3 * N;
+      acc(2, yv, cmul_i(s0_at(xk, n, N)));
+    }
+  }
+  block_sums<6>(v, red);
+  if (threadIdx.x == 0) {
+    const double dr = v[0], di = v[1], m2 = dr * dr + di * di;
+    // -num / den
+    out[2 * k] = cmk(-(v[2] * dr + v[3] * di) / m2, -(v[3] * dr - v[2] * di) / m2);
+    out[2 * k + 1] = cmk(-(v[4] * dr + v[5] * di) / m2, -(v[5] * dr - v[4] * di) / m2);
+  }
+}
+
 // ---------------------------------------------------------------------------- initial state and its adjoint
 // x pass: one block per scale-1 z node; b0 laid out [x][z].
 __global__ void __launch_bounds__(NT) rbc_init_x(RbcDev d, const double* grid, cplx* tmp) {
@@ -1286,7 +1391,9 @@ struct RbcHostBands {
 // ABI-slot dense M_k, L_k (complex), written from the formulation of the header comment.
 // M and L of one mode: horizontal wavenumber kx (the mean mode when `mean`), viscosity nu,
 // diffusivity ka of the third field, coupling cp of that field into the w rows.
-static void rbc_assemble(int N, double kx, double nu, double ka, double cp, bool mean, Cmat& M, Cmat& L) {
+// cw: coupling of w into the b rows (-cw S10 w), the linearized advection of the conduction
+// profile in the stability operator (0 for the IVP).
+static void rbc_assemble(int N, double kx, double nu, double ka, double cp, double cw, bool mean, Cmat& M, Cmat& L) {
   const double k2 = kx * kx;
   const std::vector<double> S0 = op_S0(N), S1 = op_S1(N);
   const std::vector<double> S10 = matmul(S1, S0, N);
@@ -1314,6 +1421,7 @@ static void rbc_assemble(int N, double kx, double nu, double ka, double cp, bool
       if (s10 != 0.0) {
         L.add(U + i, P + j, 0.0, kx * s10);   // i kx S10 p in x-momentum
         if (cp != 0.0) L.add(W + i, B + j, -cp * s10);   // -b in z-momentum
+        if (cw != 0.0) L.add(B + i, W + j, -cw * s10);   // -w in the buoyancy rows (stability)
       }
       const double sd = 2.0 * S1D0[(size_t)i * N + j];
       if (sd != 0.0) L.add(W + i, P + j, sd);   // dp/dz in z-momentum
@@ -1339,7 +1447,8 @@ static void rbc_assemble(int N, double kx, double nu, double ka, double cp, bool
 
 // Real-ified banded M and L of every mode (mode k has wavenumber kx[k]; mode 0 is the mean mode).
 // Modes with equal wavenumbers share their assembly.
-static void host_bands(int N, const std::vector<double>& kxs, double nu, double ka, double cp, RbcHostBands& hb) {
+static void host_bands(int N, const std::vector<double>& kxs, double nu, double ka, double cp, RbcHostBands& hb,
+                       double cw = 0.0) {
   const int S = 4 * N + 7, K = (int)kxs.size();
   // phases and recombination
   std::vector<signed char> rowph(S, 0), colph(S, 0);
@@ -1409,7 +1518,7 @@ static void host_bands(int N, const std::vector<double>& kxs, double nu, double 
       continue;
     }
     Cmat M(S), L(S);
-    rbc_assemble(N, kxs[k], nu, ka, cp, k == 0, M, L);
+    rbc_assemble(N, kxs[k], nu, ka, cp, cw, k == 0, M, L);
     transform(M, bm[k]);
     transform(L, bl[k]);
     if (k > 0) seen[kxs[k]] = k;
@@ -1708,6 +1817,80 @@ class RbcProblem : public ProblemImpl {
     hipLaunchKernelGGL(kadj_fn(), dim3(K_), dim3(NTK), ka_lds(), stream, dl, a);
     SPS_CHECK_LAUNCH();
     hipLaunchKernelGGL(rbc_lbvp_rhs_adj, dim3(K_), dim3(NT), 0, stream, dv_, lrhs_, reinterpret_cast<cplx*>(fbar));
+    SPS_CHECK_LAUNCH();
+  }
+
+  // Eigenvalue problem of the conduction state's perturbations, every wavenumber at once: the
+  // stability bands (built on first use), one factorization of sigma M + L_s, `iters` inverse
+  // iterations for the right and for the left eigenvector through those factors, then the
+  // sensitivities.  lam[K], dlam[K][2] complex; X, Y [K][S] complex (unit norm); device arrays.
+  void stability(double sigma, int iters, double* lam, double* X, double* Y, double* dlam) override {
+    if (cou_) throw Error(SPS_E_UNSUPPORTED, "the eigenvalue problem is built for the 2D problem");
+    SPS_REQUIRE(lam && X && Y && dlam, "null argument");
+    SPS_REQUIRE(iters >= 1 && iters <= 10000, "iters must be in [1, 10000]");
+    if (!eops_) {
+      RbcHostBands hb;
+      host_bands(N_, kxs_, nu_, ka_, cp_, hb, 1.0);
+      SPS_REQUIRE(hb.kl + SPS_BLK <= SPS_TW && SPS_BLK + hb.kl + hb.ku <= SPS_GW,
+                  "stability band too wide for the block solver");
+      ekl_ = hb.kl;
+      eku_ = hb.ku;
+      eBM_ = arena_.upload(hb.BM, stream);
+      eBL_ = arena_.upload(hb.BL, stream);
+      eops_ = arena_.alloc<double>((size_t)K_ * dv_.opsize);
+      ework_ = arena_.alloc<cplx>((size_t)K_ * S_);
+      std::vector<cplx> x0((size_t)K_ * S_, make_double2(0.0, 0.0));
+      for (int k = 0; k < K_; ++k)
+        for (int s = 0; s < 3 * N_; ++s) x0[(size_t)k * S_ + s] = make_double2(1.0 / (1 + s % N_), 0.5 / (1 + s / N_));
+      estart_ = arena_.upload(x0, stream);
+      const size_t lds = (size_t)(2 * ekl_ + eku_ + 1) * S_ * sizeof(double) + sizeof(int) * S_;
+      SPS_REQUIRE(lds <= 160 * 1024, "problem too large for LDS");
+      if (lds > factor_lds())
+        SPS_HIP(hipFuncSetAttribute((const void*)rbc_factor, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    }
+    RbcDev de = dv_;
+    de.kl = ekl_;
+    de.ku = eku_;
+    de.uw = ekl_ + eku_ + 1;
+    de.ops = eops_;
+    const size_t lds = (size_t)(2 * ekl_ + eku_ + 1) * S_ * sizeof(double) + sizeof(int) * S_;
+    hipLaunchKernelGGL(rbc_factor, dim3(K_), dim3(NT), lds, stream, de, eBM_, eBL_, sigma, 1.0, eops_);
+    SPS_CHECK_LAUNCH();
+    cplx* x = reinterpret_cast<cplx*>(X);
+    cplx* y = reinterpret_cast<cplx*>(Y);
+    cplx* l = reinterpret_cast<cplx*>(lam);
+    // right eigenvector
+    copy_state(x, estart_);
+    for (int it = 0; it < iters; ++it) {
+      hipLaunchKernelGGL(rbc_apply_m, dim3(K_), dim3(NT), 0, stream, de, x, ework_);
+      SPS_CHECK_LAUNCH();
+      KfArgs a{};
+      a.X0 = ework_;
+      a.Xout = y;   // y is scratch until the left iteration
+      a.nl = nl_;
+      a.F0 = F0_;
+      a.mode = KF_SOLVE;
+      hipLaunchKernelGGL(kfwd_fn(), dim3(K_), dim3(NTK), kf_lds(), stream, de, a);
+      SPS_CHECK_LAUNCH();
+      hipLaunchKernelGGL(rbc_evp_update, dim3(K_), dim3(NT), 0, stream, de, x, y, sigma, l);
+      SPS_CHECK_LAUNCH();
+    }
+    // left (adjoint) eigenvector through the same factors
+    copy_state(y, estart_);
+    for (int it = 0; it < iters; ++it) {
+      hipLaunchKernelGGL(rbc_lbvp_rhs_adj, dim3(K_), dim3(NT), 0, stream, de, y, ework_);   // M^H y
+      SPS_CHECK_LAUNCH();
+      KaArgs a = ka_args(KA_SOLVE_T);
+      a.Xb_in = ework_;
+      a.Xb_out = Xw_;
+      hipLaunchKernelGGL(kadj_fn(), dim3(K_), dim3(NTK), ka_lds(), stream, de, a);
+      SPS_CHECK_LAUNCH();
+      hipLaunchKernelGGL(rbc_evp_update, dim3(K_), dim3(NT), 0, stream, de, y, Xw_, sigma, nullptr);
+      SPS_CHECK_LAUNCH();
+    }
+    const double Ra = desc_.param0;
+    hipLaunchKernelGGL(rbc_evp_sens, dim3(K_), dim3(NT), 0, stream, de, x, y, -0.5 * nu_ / Ra, -0.5 * ka_ / Ra,
+                       reinterpret_cast<cplx*>(dlam));
     SPS_CHECK_LAUNCH();
   }
 
@@ -2198,6 +2381,9 @@ class RbcProblem : public ProblemImpl {
   DevArena arena_;
   double *BM_ = nullptr, *BL_ = nullptr, *ops_ = nullptr, *Jpart_ = nullptr;
   double* lops_ = nullptr;   // LU block operators of L alone (boundary value problem), built on first use
+  double *eBM_ = nullptr, *eBL_ = nullptr, *eops_ = nullptr;   // stability operator bands and factors
+  cplx *ework_ = nullptr, *estart_ = nullptr;
+  int ekl_ = 0, eku_ = 0;
   cplx* lrhs_ = nullptr;
   bool lfactored_ = false;
   int *err_ = nullptr;

@@ -125,6 +125,9 @@ class ProblemImpl {
   virtual void eval_F(const double* X, double* F) = 0;
   virtual void eval_F_vjp(const double* X, const double* Fbar, double* Xbar) = 0;
   virtual void solve(const double* R, double* X, int adjoint) = 0;
+  virtual void stability(double, int, double*, double*, double*, double*) {
+    throw Error(SPS_E_UNSUPPORTED, "the eigenvalue problem is built for the 2D problem");
+  }
   virtual void set_timesteps(const double*, int) {
     throw Error(SPS_E_UNSUPPORTED, "variable steps are built for the KS problem");
   }

@@ -54,6 +54,7 @@ def lib():
         "sps_eval_F": (ctypes.c_int, [_P, _D, _D]),
         "sps_eval_F_vjp": (ctypes.c_int, [_P, _D, _D, _D]),
         "sps_solve": (ctypes.c_int, [_P, _D, _D, ctypes.c_int]),
+        "sps_stability": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int, _D, _D, _D, _D]),
         "sps_set_timesteps": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.c_int]),
         "sps_set_checkpointing": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
         "sps_checkpoint_schedule": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -200,6 +201,22 @@ class Problem:
 
     def solve(self, R, X, adjoint=False):
         _check(lib().sps_solve(self._h, _ptr(R, self.n), _ptr(X, self.n), int(bool(adjoint))))
+
+    def stability(self, sigma=0.0, iters=30):
+        """Growth rate nearest sigma of every wavenumber's perturbation of the conduction state,
+        right and left eigenvectors and (d lambda/dRa, d lambda/dk): complex CUDA tensors
+        lam [K], X [K, S], Y [K, S], dlam [K, 2] (2D problem)."""
+        import torch
+        K = self.n // (2 * (4 * self.desc.nz + 7))
+        S = 4 * self.desc.nz + 7
+        lam = torch.zeros(2 * K, dtype=torch.float64, device="cuda")
+        X = torch.zeros(self.n, dtype=torch.float64, device="cuda")
+        Y = torch.zeros_like(X)
+        dlam = torch.zeros(4 * K, dtype=torch.float64, device="cuda")
+        _check(lib().sps_stability(self._h, float(sigma), int(iters), _ptr(lam), _ptr(X, self.n), _ptr(Y, self.n),
+                                   _ptr(dlam)))
+        c = lambda t, *shape: torch.view_as_complex(t.view(*shape, 2))
+        return c(lam, K), c(X, K, S), c(Y, K, S), c(dlam, K, 2)
 
     def set_timesteps(self, dts=None):
         """Variable step sizes (a host sequence) for the following runs; None: the constant dt."""
