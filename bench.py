@@ -353,6 +353,49 @@ def ckpt_timing(slot_counts=(5, 10, 20, 50)):
     return out
 
 
+def stability_timing(iters=30):
+    """Eigenvalue problem of the conduction state's perturbations: (a) all 128 wavenumbers of the
+    headline operator (256 x 64, Ra = 1e6, Pr = 1) in one sps_stability call (one LU of
+    sigma M + L_s per wavenumber, `iters` inverse iterations for the right and the left
+    eigenvector, the sensitivities), against the oracle's dense generalized eigensolve (left
+    and right vectors, no sensitivities) of a sample of wavenumbers scaled to all 128; (b) the onset at k = 3.1163 (nz = 32) by Newton
+    steps on the growth rate with the adjoint sensitivity d lambda/dRa, from Ra = 1500."""
+    import torch
+    import paper_2506_14792_amd as sps
+    from oracle.rbc import RBC
+    c = CFG
+    G = sps.Problem(sps.RBC2D, c["nx"], c["nz"], c["lx"], c["Ra"], c["Pr"], 1.5, c["dt"], 1, 1)
+    G.stability(0.0, iters)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 5
+    for _ in range(reps):
+        lam, X, Y, dl = G.stability(0.0, iters)
+    torch.cuda.synchronize()
+    call_s = (time.perf_counter() - t0) / reps
+    G.sync()
+    P = RBC(Nx=c["nx"], Nz=c["nz"], Lx=c["lx"], Ra=c["Ra"], Pr=c["Pr"])
+    t0 = time.perf_counter()
+    sample = (1, 32, 64, 127)
+    for k in sample:
+        P.stability_eig(k, 0.0)   # dense generalized eigensolve with left and right vectors
+    ocpu = (time.perf_counter() - t0) * (c["nx"] // 2) / len(sample)
+    kc, Ra = 3.1163, 1500.0
+    t0 = time.perf_counter()
+    for it in range(5):
+        Gn = sps.Problem(sps.RBC2D, 8, 32, 2.0 * np.pi / kc, Ra, 1.0, 1.5, 1e-3, 1, 1)
+        lam_n, _, _, dl_n = Gn.stability(0.0, 40)
+        g, dg = lam_n[1].item(), dl_n[1, 0].item()
+        Ra -= g.real / dg.real
+    newton_s = time.perf_counter() - t0
+    return {"workload": "linear stability of the conduction state (eigenvalue nearest 0, right and adjoint "
+                        "eigenvectors, d lambda/dRa and d lambda/dk): 256x64 Ra=1e6 all 128 wavenumbers; onset by "
+                        "Newton at k=3.1163, nz=32",
+            "iterations": iters, "gpu_call_s": call_s, "gpu_us_per_wavenumber": call_s / (c["nx"] // 2) * 1e6,
+            "oracle_cpu_eig_s_all_wavenumbers_extrapolated": ocpu, "speedup_vs_oracle": ocpu / call_s,
+            "newton_onset_Ra": Ra, "newton_final_growth": g.real, "newton_5_solves_s": newton_s}
+
+
 COU_CFG = dict(nx=128, ny=64, nz=64, Lx=4.0 * np.pi, Lz=2.0 * np.pi, Re=400.0, dt=0.01, nsteps=2000,
                checkpoint_every=100, seed=0, energy=1e-6)
 
@@ -504,7 +547,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--skip-extra", action="store_true",
                     help="only the headline configuration (for counter and trace runs)")
-    ap.add_argument("--only", choices=["ks", "sh", "closure", "couette", "lbvp", "ckpt"], default=None,
+    ap.add_argument("--only", choices=["ks", "sh", "closure", "couette", "lbvp", "ckpt", "stability"], default=None,
                     help="run one secondary configuration alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -518,7 +561,7 @@ def main():
         import torch
         torch.cuda.set_device(0)
         fn = {"ks": ks_timing, "sh": sh_timing, "closure": kolmo_timing, "couette": couette_timing,
-              "lbvp": lbvp_timing, "ckpt": ckpt_timing}[args.only]
+              "lbvp": lbvp_timing, "ckpt": ckpt_timing, "stability": stability_timing}[args.only]
         print(json.dumps({args.only: fn()}))
         return
 
@@ -590,10 +633,11 @@ def main():
     G.sync()
     graph_sec = (t7 - t6) / args.steps
     traffic = measured_traffic()
-    ks = sh = kol = cou = lbvp = ckpt = None
+    ks = sh = kol = cou = lbvp = ckpt = stab = None
     if not args.skip_extra:
         lbvp = lbvp_timing()
         ckpt = ckpt_timing()
+        stab = stability_timing()
         ks = ks_timing()
         sh = sh_timing()
         kol = kolmo_timing()
@@ -633,6 +677,7 @@ def main():
         "couette_autograd_config": cou,
         "lbvp_config": lbvp,
         "checkpointing_config": ckpt,
+        "stability_config": stab,
         "J": J.item(),
     }
     print(json.dumps(out))
