@@ -96,7 +96,7 @@ KS_CFG = dict(nx=64, L=32.0 * np.pi, dt=0.05, nsteps=200, seed=0)
 
 
 def ks_timing(reps=20):
-    """The first configuration (1D Kuramoto-Sivashinsky, 64 modes, SBDF2 dt = 0.05, 200 steps,
+    """The 1D Kuramoto-Sivashinsky workload (64 modes, SBDF2 dt = 0.05, 200 steps,
     gradient of 1/2 ||u(T)||^2 w.r.t. the initial coefficients): GPU gradient time and the
     oracle's CPU seconds for the same gradient."""
     import torch
@@ -551,7 +551,7 @@ def main():
                     help="run one secondary configuration alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); the multi-GPU "
+        print(f"bench.py: this benchmark runs on exactly one GPU (asked for {args.gpus}); the multi-GPU "
               "sharding is a design note only", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:

@@ -5,7 +5,7 @@ TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
 The equations are written in the paper's IVP form M dX/dt + L X = F(X)
 (Supplementary, "Initial value problems"); the sparse ultraspherical
 discretization with tau terms follows "Sparse spectral methods".  Readings the
-paper leaves open (all listed in the design doc):
+paper leaves open:
 
 * free-fall units: nu = (Ra/Pr)^(-1/2), kappa = (Ra Pr)^(-1/2); buoyancy b with
   b(z=0) = 1, b(z=1) = 0 and no-slip walls u = w = 0;

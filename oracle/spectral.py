@@ -9,7 +9,7 @@ Paper passages followed:
 * Methods, "Spectral transforms": f_hat = T f, f = T^{-1} f_hat; the adjoint of a
   matrix transform is its Hermitian transpose.
 
-Readings where the paper is silent (listed in the design doc):
+Readings where the paper is silent:
 * Fourier: real data, half spectrum m = 0..K-1 stored (Nyquist dropped).
   backward  u_j = Re(c_0) + 2 Re sum_{m>=1} c_m exp(i k_m x_j),
   forward   c_m = (1/Ng) sum_j u_j exp(-i k_m x_j),   x_j = j L / Ng, k_m = 2 pi m / L.
