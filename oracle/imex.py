@@ -71,6 +71,23 @@ def ars222_tableau():
     return A, H
 
 
+def ars443_tableau():
+    """ARS(4,4,3) of Ascher, Ruuth & Spiteri (1997): three stages past the initial state plus
+    the final one, implicit diagonal 1/2 (one matrix serves every stage), third order, both
+    parts stiffly accurate (X_{n+1} is the last stage)."""
+    A = np.array([[0.0, 0.0, 0.0, 0.0, 0.0],
+                  [1.0 / 2.0, 0.0, 0.0, 0.0, 0.0],
+                  [11.0 / 18.0, 1.0 / 18.0, 0.0, 0.0, 0.0],
+                  [5.0 / 6.0, -5.0 / 6.0, 1.0 / 2.0, 0.0, 0.0],
+                  [1.0 / 4.0, 7.0 / 4.0, 3.0 / 4.0, -7.0 / 4.0, 0.0]])
+    H = np.array([[0.0, 0.0, 0.0, 0.0, 0.0],
+                  [0.0, 1.0 / 2.0, 0.0, 0.0, 0.0],
+                  [0.0, 1.0 / 6.0, 1.0 / 2.0, 0.0, 0.0],
+                  [0.0, -1.0 / 2.0, 1.0 / 2.0, 1.0 / 2.0, 0.0],
+                  [0.0, 3.0 / 2.0, -3.0 / 2.0, 1.0 / 2.0, 1.0 / 2.0]])
+    return A, H
+
+
 def rk_forward(P, X0, dt, nsteps, tableau=None):
     """IMEX RK: (M + dt H_ii L) X_{n,i} = M X_{n,0} + dt sum_{j<i} [A_ij F_{n,j} - H_ij L X_{n,j}].
 

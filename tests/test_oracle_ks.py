@@ -98,3 +98,34 @@ def test_variable_step_taylor_remainder_rate(order):
         rem.append(abs(Je - J - e * np.real(np.vdot(g, d))))
     rates = np.log2(np.array(rem[:-1]) / np.array(rem[1:]))
     assert np.all(np.abs(rates - 2.0) < 0.05), rates
+
+
+def test_rk443_gradient_taylor_rate_and_brute_force():
+    """KS with ARS(4,4,3): Taylor remainder rate 2 of the gradient (64 modes, 100 steps) and
+    brute-force central differences of every component (8 modes, 6 steps)."""
+    tab = imex.ars443_tableau()
+    P = KS()
+    X0 = wl.ks_c0(seed=0)[:, None]
+    XN, hist = imex.rk_forward(P, X0, 0.05, 100, tableau=tab)
+    J = P.energy(XN)
+    g = imex.rk_adjoint(P, P.energy_grad(XN), hist, 0.05, tableau=tab)
+    d = wl.random_state(10, (P.K, 1))
+    rem = []
+    for e in (1e-4, 5e-5, 2.5e-5):
+        Je = P.energy(imex.rk_forward(P, X0 + e * d, 0.05, 100, tableau=tab)[0])
+        rem.append(abs(Je - J - e * np.real(np.vdot(g, d))))
+    rates = np.log2(np.array(rem[:-1]) / np.array(rem[1:]))
+    assert np.all(np.abs(rates - 2.0) < 0.05), rates
+    P = KS(Nx=16, L=8.0)
+    X0 = wl.ks_c0(seed=1, Nx=16, amp=0.5)[:, None]
+    XN, hist = imex.rk_forward(P, X0, 0.05, 6, tableau=tab)
+    g = imex.rk_adjoint(P, P.energy_grad(XN), hist, 0.05, tableau=tab)
+    h = 1e-6
+    for m in range(P.K):
+        for part in (1.0, 1j):
+            if m == 0 and part == 1j:
+                continue
+            e = np.zeros_like(X0); e[m, 0] = h * part
+            fd = (P.energy(imex.rk_forward(P, X0 + e, 0.05, 6, tableau=tab)[0])
+                  - P.energy(imex.rk_forward(P, X0 - e, 0.05, 6, tableau=tab)[0])) / (2 * h)
+            assert abs(fd - np.real(np.conj(part) * g[m, 0])) <= 1e-7 * np.max(np.abs(g))

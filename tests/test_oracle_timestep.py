@@ -44,6 +44,35 @@ def test_rk222_explicit_part_is_second_order_taylor():
     assert abs(XN[0, 0] - (1 + z + z * z / 2) ** n) < 1e-13
 
 
+def test_ars443_third_order_conditions():
+    """ARS(4,4,3) as a pair of tableaus with weights b = last row (stiffly accurate): row sums
+    give the same abscissae c for both parts, and the order-3 conditions hold for each part
+    (sum b = 1, b.c = 1/2, b.c^2 = 1/3, b.A.c = 1/6) and for the coupling (b_E.A_I.c and
+    b_I.A_E.c = 1/6).  One more order (b.c^3 = 1/4 for both parts) does not hold."""
+    A, H = imex.ars443_tableau()
+    c = A.sum(axis=1)
+    assert np.allclose(H.sum(axis=1), c, atol=1e-15)
+    bE, bI = A[-1], H[-1]
+    for b, M in ((bE, A), (bI, H)):
+        assert abs(b.sum() - 1.0) < 1e-15
+        assert abs(b @ c - 0.5) < 1e-15
+        assert abs(b @ c ** 2 - 1.0 / 3.0) < 1e-15
+        assert abs(b @ M @ c - 1.0 / 6.0) < 1e-15
+    assert abs(bE @ H @ c - 1.0 / 6.0) < 1e-15 and abs(bI @ A @ c - 1.0 / 6.0) < 1e-15
+    assert abs(bE @ c ** 3 - 0.25) > 1e-3 or abs(bI @ c ** 3 - 0.25) > 1e-3
+    assert np.all(np.diag(H)[1:] == 0.5)
+
+
+def test_ars443_third_order_convergence():
+    lam, a, T = 2.0, 0.5, 1.0
+    errs = []
+    for n in (20, 40, 80):
+        XN, _ = imex.rk_forward(scalar(lam, a), np.ones((1, 1)), T / n, n, tableau=imex.ars443_tableau())
+        errs.append(abs(XN[0, 0] - np.exp((a - lam) * T)))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(np.abs(rates - 3.0) < 0.15), rates
+
+
 @pytest.mark.parametrize("stepper", ["rk", "sbdf"])
 def test_second_order_convergence_to_exponential(stepper):
     lam, a, T = 2.0, 0.5, 1.0
@@ -208,16 +237,17 @@ def random_linear(seed, K=3, S=4):
     return Linear(M, 0.5 * c(), 0.3 * c())
 
 
-@pytest.mark.parametrize("stepper", ["rk", "sbdf", "sbdf3", "sbdf4"])
+@pytest.mark.parametrize("stepper", ["rk", "rk443", "sbdf", "sbdf3", "sbdf4"])
 def test_linear_trajectory_inner_product(stepper):
     P = random_linear(5)
     rng = np.random.default_rng(6)
     X0 = rng.standard_normal((3, 4)) + 1j * rng.standard_normal((3, 4))
     Yb = rng.standard_normal((3, 4)) + 1j * rng.standard_normal((3, 4))
     dt, n = 0.05, 12
-    if stepper == "rk":
-        XN, hist = imex.rk_forward(P, X0, dt, n)
-        Xb = imex.rk_adjoint(P, Yb, hist, dt)
+    if stepper in ("rk", "rk443"):
+        tab = imex.ars443_tableau() if stepper == "rk443" else None
+        XN, hist = imex.rk_forward(P, X0, dt, n, tableau=tab)
+        Xb = imex.rk_adjoint(P, Yb, hist, dt, tableau=tab)
     else:
         order = {"sbdf": 2, "sbdf3": 3, "sbdf4": 4}[stepper]
         XN, states = imex.sbdf_forward(P, X0, dt, n, order=order)
