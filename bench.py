@@ -122,9 +122,9 @@ def ks_timing(reps=20):
     XN, states = imex.sbdf_forward(P, c0, c["dt"], c["nsteps"])
     imex.sbdf_adjoint(P, P.energy_grad(XN), states, c["dt"])
     cpu_s = time.perf_counter() - t0
-    # the same gradient with the higher-order multistep schemes
+    # the same gradient with the higher-order multistep schemes and the IMEX RK schemes
     higher = {}
-    for name, scheme in (("sbdf3", sps.SBDF3), ("sbdf4", sps.SBDF4)):
+    for name, scheme in (("sbdf3", sps.SBDF3), ("sbdf4", sps.SBDF4), ("rk222", sps.RK222), ("rk443", sps.RK443)):
         Gh = sps.Problem(sps.KS1D, c["nx"], 0, c["L"], 0.0, 0.0, 1.5, c["dt"], 1, c["nsteps"], scheme=scheme)
         gh = torch.zeros(Gh.n, dtype=torch.float64, device="cuda")
         Gh.gradient(X0, c["nsteps"], None, gh, None)

@@ -48,11 +48,11 @@ enum sps_status {
 };
 
 enum sps_equation { SPS_RBC2D = 1, SPS_KS1D = 2, SPS_SH2D = 3, SPS_COUETTE3D = 4 };
-enum sps_scheme { SPS_RK222 = 1, SPS_SBDF2 = 2, SPS_SBDF3 = 3, SPS_SBDF4 = 4 };
+enum sps_scheme { SPS_RK222 = 1, SPS_SBDF2 = 2, SPS_SBDF3 = 3, SPS_SBDF4 = 4, SPS_RK443 = 5 };
 
 typedef struct {
   int equation;          /* sps_equation */
-  int scheme;            /* sps_scheme; RBC uses SPS_RK222, KS one of SPS_SBDF2/3/4 */
+  int scheme;            /* sps_scheme; RBC uses SPS_RK222, KS any of them */
   int nx;                /* Fourier grid points at scale 1 (K = nx/2 stored wavenumbers) */
   int nz;                /* Chebyshev modes N (RBC), ignored for KS */
   double lx;             /* Fourier period */
@@ -212,8 +212,8 @@ int sps_eval_F(sps_problem *P, const double *X, double *F);
 /* (dF/dX)^H Fbar at X. */
 int sps_eval_F_vjp(sps_problem *P, const double *X, const double *Fbar, double *Xbar);
 /* Solve A x = r (adjoint = 0) or A^H x = r (adjoint = 1) with the current factors of the
- * scheme's implicit matrix (RK222: M + dt*gamma*L; SBDF-k: a_0 M + L with the steady a_0 = 3/2,
- * 11/6, 25/12 over dt for k = 2, 3, 4). */
+ * scheme's implicit matrix (RK222: M + dt*gamma*L; RK443: M + dt/2 L; SBDF-k: a_0 M + L with the
+ * steady a_0 = 3/2, 11/6, 25/12 over dt for k = 2, 3, 4). */
 int sps_solve(sps_problem *P, const double *R, double *X, int adjoint);
 
 /* Eigenvalue problem of the 2D problem's operator (Supplementary, "Eigenvalue problems"):
@@ -240,7 +240,8 @@ int sps_stability(sps_problem *P, double sigma, int iters, double *lam, double *
  * (backward difference of M dX/dt), c_i the value at t_n of the basis polynomial of t_{n-i}
  * on t_{n-1} .. t_{n-q} (extrapolation of F); equal steps give the constant-step rows.
  * dts = NULL or n = 0 returns to the constant step of the descriptor (sps_solve always uses
- * it).  Drops the recorded forward run.  The KS problem; SPS_E_UNSUPPORTED otherwise. */
+ * it).  Drops the recorded forward run.  The KS problem with an SBDF scheme; SPS_E_UNSUPPORTED
+ * otherwise. */
 int sps_set_timesteps(sps_problem *P, const double *dts, int n);
 
 /* Checkpointing of the RK222 sweeps (Supplementary, "Initial value problems": the reverse

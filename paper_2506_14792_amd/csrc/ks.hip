@@ -2,8 +2,10 @@
 // in the IVP form M dX/dt + L X = F(X) (Supplementary, "Initial value problems") with one
 // unknown per stored Fourier mode m < K = nx/2: M = 1, L_m = -k_m^2 + k_m^4,
 // F = -1/2 d/dx(u^2) with the product on the 3/2 grid (Methods, dealiasing).  Timestepping is
-// SBDF-k, k = 2, 3 or 4, reverting to SBDF-n on the first k - 1 steps (equ:imex); the reverse
-// sweep is the multistep adjoint recurrence (equ:IMEX_adjoint).  The implicit matrices are diagonal, so a whole sweep is
+// SBDF-k, k = 2, 3 or 4, reverting to SBDF-n on the first k - 1 steps (equ:imex), with the
+// multistep adjoint recurrence (equ:IMEX_adjoint) as reverse sweep, or the IMEX Runge-Kutta
+// schemes ARS(2,2,2) and ARS(4,4,3) with the RK adjoint equations (Supplementary, "Initial value
+// problems").  The implicit matrices are diagonal, so a whole sweep is
 // one block that loops over the steps (a persistent launch) and keeps the per-mode history
 // in registers; the states of the run are stored for the reverse sweep.
 #include <hip/hip_runtime.h>
@@ -168,6 +170,13 @@ __device__ void ks_F_vjp(const KsDev& d, const cplx* ex, const cplx* c, const cp
   __syncthreads();
 }
 
+// IMEX RK tableau with S implicit stages past the initial one: explicit part A and implicit
+// part H, (S+1) x (S+1), lower triangular, row i giving stage i; X_{n+1} is stage S.
+struct RkTab {
+  double A[5][5];
+  double H[5][5];
+};
+
 // LDS of every KS kernel: ex (Ng), c, g, sb, fo (K each), u (Ng doubles)
 struct KsLds {
   cplx *ex, *c, *g, *sb, *fo;
@@ -281,6 +290,104 @@ __global__ void __launch_bounds__(NTS) ks_adjoint(KsDev d, cplx* Xbar, const cpl
   if (own) Xbar[m] = xb;
 }
 
+// RK forward sweep, S stages: X (in: X_0, out: X_N); the stage states X_{n,0..S-1} of step n at
+// H[(n S + i) K] for the reverse sweep.  Stage i solves
+// (1 + dt H_ii L_m) X_{n,i} = X_{n,0} + dt sum_{j<i} (A_ij F_{n,j} - H_ij L_m X_{n,j}) per mode
+// (M = 1); F of stage S is not needed (column S of A is zero).  One block; the stage values of
+// this thread's mode stay in registers.
+template <int S>
+__global__ void __launch_bounds__(NTS) ks_forward_rk(KsDev d, cplx* X, cplx* H, int nsteps, RkTab tab, double dt,
+                                                    int* err) {
+  extern __shared__ double smem_d[];
+  const KsLds L = ks_lds(d, smem_d);
+  const int m = threadIdx.x, K = d.K;
+  const bool own = m < K;
+  const double lin = own ? d.lin[m] : 0.0;
+  double inv[S + 1];
+#pragma unroll
+  for (int i = 1; i <= S; ++i) inv[i] = 1.0 / (1.0 + dt * tab.H[i][i] * lin);
+  cplx x0 = own ? X[m] : czero();
+  for (int n = 0; n < nsteps; ++n) {
+    cplx xs[S + 1], fs[S];
+    xs[0] = x0;
+#pragma unroll
+    for (int i = 0; i <= S; ++i) {
+      if (i > 0) {
+        cplx r = xs[0];
+#pragma unroll
+        for (int j = 0; j < i; ++j) {
+          r = cadd(r, cscale(fs[j], dt * tab.A[i][j]));
+          r = csub(r, cscale(xs[j], dt * tab.H[i][j] * lin));
+        }
+        xs[i] = cscale(r, inv[i]);
+      }
+      if (i < S) {
+        if (own) {
+          H[((size_t)n * S + i) * K + m] = xs[i];
+          L.c[m] = xs[i];
+        }
+        __syncthreads();
+        ks_eval_F(d, L.ex, L.c, L.u, L.fo);
+        fs[i] = own ? L.fo[m] : czero();
+      }
+    }
+    x0 = xs[S];
+  }
+  if (own) {
+    X[m] = x0;
+    if (__any(!(isfinite(x0.x) && isfinite(x0.y))) && lane_id() == 0) atomicOr(err, 2);
+  }
+}
+
+// RK reverse sweep: Xbar (in: dJ/dX_N, out: dJ/dX_0) through the stage states of the forward
+// run.  Per step, from the cotangent Yn of X_{n+1} (M = 1, L real diagonal, so each implicit
+// matrix is its own adjoint):
+//   Y_S = Yn / (1 + dt H_SS L),
+//   Y_i = [dF(X_{n,i})^H (dt sum_{j>i} A_ji Y_j) - dt L sum_{j>i} H_ji Y_j] / (1 + dt H_ii L),
+//   cotangent of X_n = sum_{j>=1} Y_j + dF(X_{n,0})^H (dt sum_j A_j0 Y_j) - dt L sum_j H_j0 Y_j.
+template <int S>
+__global__ void __launch_bounds__(NTS) ks_adjoint_rk(KsDev d, cplx* Xbar, const cplx* H, int nsteps, RkTab tab,
+                                                    double dt) {
+  extern __shared__ double smem_d[];
+  const KsLds L = ks_lds(d, smem_d);
+  const int m = threadIdx.x, K = d.K;
+  const bool own = m < K;
+  const double lin = own ? d.lin[m] : 0.0;
+  double inv[S + 1];
+#pragma unroll
+  for (int i = 1; i <= S; ++i) inv[i] = 1.0 / (1.0 + dt * tab.H[i][i] * lin);
+  cplx yn = own ? Xbar[m] : czero();
+  for (int n = nsteps - 1; n >= 0; --n) {
+    cplx ys[S + 1];
+    ys[S] = cscale(yn, inv[S]);
+#pragma unroll
+    for (int i = S - 1; i >= 0; --i) {
+      cplx g = czero(), lp = czero();
+#pragma unroll
+      for (int j = i + 1; j <= S; ++j) {
+        g = cadd(g, cscale(ys[j], dt * tab.A[j][i]));
+        lp = cadd(lp, cscale(ys[j], dt * tab.H[j][i] * lin));
+      }
+      if (own) {
+        L.c[m] = H[((size_t)n * S + i) * K + m];
+        L.g[m] = g;
+      }
+      __syncthreads();
+      ks_F_vjp(d, L.ex, L.c, L.g, L.sb, L.u, L.fo);
+      const cplx v = own ? L.fo[m] : czero();
+      if (i > 0) {
+        ys[i] = cscale(csub(v, lp), inv[i]);
+      } else {
+        cplx sum = czero();
+#pragma unroll
+        for (int j = 1; j <= S; ++j) sum = cadd(sum, ys[j]);
+        yn = csub(cadd(sum, v), lp);
+      }
+    }
+  }
+  if (own) Xbar[m] = yn;
+}
+
 // F or its VJP at one state (one block).
 __global__ void __launch_bounds__(NTS) ks_eval(KsDev d, const cplx* X, const cplx* G, cplx* out) {
   extern __shared__ double smem_d[];
@@ -317,20 +424,51 @@ __global__ void __launch_bounds__(NTS) ks_cost(KsDev d, const cplx* X, cplx* dJ,
   if (J && m == 0) J[0] = red[0];
 }
 
-// X = (a_0 M + L)^{-1} R with the steady SBDF-k a_0 (3/2, 11/6 or 25/12 over dt): the scheme's
-// matrix (real diagonal, so equal to its adjoint).
-__global__ void __launch_bounds__(NTS) ks_solve(KsDev d, const cplx* R, cplx* X, double a0) {
+// X = (a_0 M + b L)^{-1} R: the scheme's implicit matrix, a_0 the steady SBDF-k a_0 (3/2, 11/6
+// or 25/12 over dt) with b = 1, or a_0 = 1 and b = dt gamma for the RK schemes (real diagonal,
+// so equal to its adjoint).
+__global__ void __launch_bounds__(NTS) ks_solve(KsDev d, const cplx* R, cplx* X, double a0, double b) {
   const int m = threadIdx.x;
-  if (m < d.K) X[m] = cscale(R[m], 1.0 / (a0 + d.lin[m]));
+  if (m < d.K) X[m] = cscale(R[m], 1.0 / (a0 + b * d.lin[m]));
+}
+
+// ARS(2,2,2) (gamma = 1 - 1/sqrt 2, delta = 1 - 1/(2 gamma)) and ARS(4,4,3) of Ascher, Ruuth &
+// Spiteri (1997).
+RkTab rk_tableau(int scheme, int* stages) {
+  RkTab t;
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j < 5; ++j) t.A[i][j] = t.H[i][j] = 0.0;
+  if (scheme == SPS_RK222) {
+    const double g = 1.0 - 1.0 / std::sqrt(2.0), dl = 1.0 - 1.0 / (2.0 * g);
+    t.A[1][0] = g;
+    t.A[2][0] = dl; t.A[2][1] = 1.0 - dl;
+    t.H[1][1] = g;
+    t.H[2][1] = 1.0 - g; t.H[2][2] = g;
+    *stages = 2;
+  } else {
+    t.A[1][0] = 0.5;
+    t.A[2][0] = 11.0 / 18.0; t.A[2][1] = 1.0 / 18.0;
+    t.A[3][0] = 5.0 / 6.0; t.A[3][1] = -5.0 / 6.0; t.A[3][2] = 0.5;
+    t.A[4][0] = 0.25; t.A[4][1] = 1.75; t.A[4][2] = 0.75; t.A[4][3] = -1.75;
+    t.H[1][1] = 0.5;
+    t.H[2][1] = 1.0 / 6.0; t.H[2][2] = 0.5;
+    t.H[3][1] = -0.5; t.H[3][2] = 0.5; t.H[3][3] = 0.5;
+    t.H[4][1] = 1.5; t.H[4][2] = -1.5; t.H[4][3] = 0.5; t.H[4][4] = 0.5;
+    *stages = 4;
+  }
+  return t;
 }
 
 class KsProblem : public ProblemImpl {
  public:
   KsProblem(const sps_desc& desc, hipStream_t s) : desc_(desc) {
     stream = s;
-    SPS_REQUIRE(desc.scheme == SPS_SBDF2 || desc.scheme == SPS_SBDF3 || desc.scheme == SPS_SBDF4,
-                "KS supports the SBDF2, SBDF3 and SBDF4 schemes");
-    order_ = desc.scheme - SPS_SBDF2 + 2;
+    SPS_REQUIRE(desc.scheme == SPS_SBDF2 || desc.scheme == SPS_SBDF3 || desc.scheme == SPS_SBDF4 ||
+                    desc.scheme == SPS_RK222 || desc.scheme == SPS_RK443,
+                "KS supports the SBDF2, SBDF3, SBDF4, RK222 and RK443 schemes");
+    rk_ = desc.scheme == SPS_RK222 || desc.scheme == SPS_RK443;
+    if (rk_) tab_ = rk_tableau(desc.scheme, &stages_);
+    else order_ = desc.scheme - SPS_SBDF2 + 2;
     SPS_REQUIRE(desc.nx >= 4 && desc.nx % 2 == 0 && desc.nx / 2 <= NTS, "nx must be even, 4 <= nx <= 512");
     SPS_REQUIRE(desc.dealias == 1.5, "KS uses 3/2 dealiasing");
     SPS_REQUIRE(desc.lx > 0 && desc.dt > 0 && desc.max_steps >= 1, "bad lx / dt / max_steps");
@@ -352,7 +490,8 @@ class KsProblem : public ProblemImpl {
     dv_.kx = arena_.upload(kx, stream);
     dv_.lin = arena_.upload(lin, stream);
     dv_.ex = arena_.upload(ex, stream);
-    H_ = arena_.alloc<cplx>((size_t)(desc.max_steps + 1) * K_);
+    // history: X_0 .. X_N (SBDF) or the stage states X_{n,0..S-1} of every step (RK)
+    H_ = arena_.alloc<cplx>((size_t)(rk_ ? (size_t)desc.max_steps * stages_ : desc.max_steps + 1) * K_);
     Xw_ = arena_.alloc<cplx>(K_);
     err_ = arena_.alloc<int>(1);
     nrows_ = desc.max_steps + KS_MAX_ORDER + 2;
@@ -377,6 +516,7 @@ class KsProblem : public ProblemImpl {
     SPS_HIP(hipStreamSynchronize(stream));
   }
   void set_timesteps(const double* dts, int n) override {
+    if (rk_) throw Error(SPS_E_UNSUPPORTED, "variable steps are given for the multistep schemes");
     if (!dts || n == 0) {
       upload_rows(0, nullptr);
       var_n_ = 0;
@@ -400,8 +540,13 @@ class KsProblem : public ProblemImpl {
   void adjoint_step(double* Xbar, int nsteps) override {
     SPS_REQUIRE(Xbar != nullptr, "Xbar is null");
     if (tape_steps_ != nsteps) throw Error(SPS_E_STATE, "adjoint_step: nsteps does not match the recorded forward run");
-    hipLaunchKernelGGL(ks_adjoint, dim3(1), dim3(NTS), lds(), stream, dv_, reinterpret_cast<cplx*>(Xbar), H_, nsteps,
-                       rows_);
+    cplx* xb = reinterpret_cast<cplx*>(Xbar);
+    if (!rk_)
+      hipLaunchKernelGGL(ks_adjoint, dim3(1), dim3(NTS), lds(), stream, dv_, xb, H_, nsteps, rows_);
+    else if (stages_ == 2)
+      hipLaunchKernelGGL(ks_adjoint_rk<2>, dim3(1), dim3(NTS), lds(), stream, dv_, xb, H_, nsteps, tab_, desc_.dt);
+    else
+      hipLaunchKernelGGL(ks_adjoint_rk<4>, dim3(1), dim3(NTS), lds(), stream, dv_, xb, H_, nsteps, tab_, desc_.dt);
     SPS_CHECK_LAUNCH();
   }
   void cost(const double* X, double* J, double* dJdX) override {
@@ -439,8 +584,10 @@ class KsProblem : public ProblemImpl {
   }
   void solve(const double* R, double* X, int) override {
     SPS_REQUIRE(R && X, "null argument");
+    const double a0 = rk_ ? 1.0 : sbdf_coef(order_, order_, desc_.dt).a[0];
+    const double b = rk_ ? desc_.dt * tab_.H[1][1] : 1.0;
     hipLaunchKernelGGL(ks_solve, dim3(1), dim3(NTS), 0, stream, dv_, reinterpret_cast<const cplx*>(R),
-                       reinterpret_cast<cplx*>(X), sbdf_coef(order_, order_, desc_.dt).a[0]);
+                       reinterpret_cast<cplx*>(X), a0, b);
     SPS_CHECK_LAUNCH();
   }
   void timer_enable(int kind, bool on) override {
@@ -458,18 +605,27 @@ class KsProblem : public ProblemImpl {
 
  private:
   size_t lds() const { return sizeof(cplx) * (Ng_ + 4 * K_) + sizeof(double) * Ng_; }
-  void forward(cplx* X, int nsteps) {
+  // one-block sweep launch, bracketed by the timer's events while it records
+  template <typename... P, typename... A>
+  void launch_timed(void (*kern)(P...), A... args) {
     hipEvent_t e0, e1;
     if (timer_.take(&e0, &e1))
-      hipExtLaunchKernelGGL(ks_forward, dim3(1), dim3(NTS), lds(), stream, e0, e1, 0, dv_, X, H_, nsteps, rows_,
-                            err_);
+      hipExtLaunchKernelGGL(kern, dim3(1), dim3(NTS), lds(), stream, e0, e1, 0, args...);
     else
-      hipLaunchKernelGGL(ks_forward, dim3(1), dim3(NTS), lds(), stream, dv_, X, H_, nsteps, rows_, err_);
+      hipLaunchKernelGGL(kern, dim3(1), dim3(NTS), lds(), stream, args...);
+  }
+  void forward(cplx* X, int nsteps) {
+    if (!rk_) launch_timed(ks_forward, dv_, X, H_, nsteps, static_cast<const SbdfCoef*>(rows_), err_);
+    else if (stages_ == 2) launch_timed(ks_forward_rk<2>, dv_, X, H_, nsteps, tab_, desc_.dt, err_);
+    else launch_timed(ks_forward_rk<4>, dv_, X, H_, nsteps, tab_, desc_.dt, err_);
     SPS_CHECK_LAUNCH();
     tape_steps_ = nsteps;
   }
 
   int order_ = 2;   // SBDF order (2, 3 or 4)
+  bool rk_ = false;  // an IMEX RK scheme: tab_ with stages_ stages
+  int stages_ = 0;
+  RkTab tab_{};
   sps_desc desc_;
   int K_ = 0, Ng_ = 0;
   KsDev dv_{};

@@ -8,7 +8,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsps.so")
 
 RBC2D, KS1D, SH2D = 1, 2, 3
-RK222, SBDF2, SBDF3, SBDF4 = 1, 2, 3, 4
+RK222, SBDF2, SBDF3, SBDF4, RK443 = 1, 2, 3, 4, 5
 CKPT_UNIFORM, CKPT_BINOMIAL, CKPT_TWO_LEVEL = 0, 1, 2
 
 _STATUS = {0: "SPS_OK", -1: "SPS_E_ARG", -2: "SPS_E_NOMEM", -3: "SPS_E_HIP", -4: "SPS_E_SINGULAR",

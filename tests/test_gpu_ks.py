@@ -1,8 +1,8 @@
-"""GPU parity of the Kuramoto-Sivashinsky path (Fourier, SBDF2, SBDF3, SBDF4) against the FP64
-oracle, called through the C ABI: F and its VJP, the diagonal solve, forward runs (the SBDF1
-start alone, then SBDF2; the start-up ramps of SBDF3/4) and the full discrete-adjoint gradient
-of J = 1/2 ||u(T)||^2 at the 64-mode, dt = 0.05, 200-step configuration.  Tolerance: 1e-11 in
-max|gpu - oracle| / max|oracle| per array."""
+"""GPU parity of the Kuramoto-Sivashinsky path (Fourier; SBDF2, SBDF3, SBDF4, RK222, RK443)
+against the FP64 oracle, called through the C ABI: F and its VJP, the diagonal solve, forward
+runs (the SBDF1 start alone, then SBDF2; the start-up ramps of SBDF3/4; one and several RK
+steps) and the full discrete-adjoint gradient of J = 1/2 ||u(T)||^2 at the 64-mode, dt = 0.05,
+200-step configuration.  Tolerance: 1e-11 in max|gpu - oracle| / max|oracle| per array."""
 import numpy as np
 import pytest
 
@@ -212,3 +212,64 @@ def test_ks_variable_steps_arguments():
     X = to_dev(wl.ks_c0(seed=1, Nx=SMALL[0])[:, None])
     with pytest.raises(sps.SpsError):
         G.step(X, 5)                               # more steps than sizes given
+
+
+RK_SCHEMES = {"rk222": (None, 1), "rk443": (imex.ars443_tableau, 5)}
+
+
+def rk_problem(cfg, nsteps, name):
+    nx, L, dt = cfg
+    P = KS(Nx=nx, L=L)
+    G = sps.Problem(sps.KS1D, nx, 0, L, 0.0, 0.0, 1.5, dt, 1, nsteps, scheme=RK_SCHEMES[name][1])
+    tab = RK_SCHEMES[name][0]
+    return P, G, (tab() if tab else None)
+
+
+@pytest.mark.parametrize("name", ["rk222", "rk443"])
+@pytest.mark.parametrize("cfg,nsteps", [(SMALL, 1), (SMALL, 7), (FULL, 200)], ids=["one", "small", "full"])
+def test_ks_rk_forward_and_gradient(cfg, nsteps, name):
+    """IMEX RK on KS: forward run, J and the gradient through the RK adjoint equations vs the
+    oracle's RK sweeps with the same tableau."""
+    print(f"KS {name} gradient {cfg} x {nsteps}", flush=True)
+    P, G, tab = rk_problem(cfg, nsteps, name)
+    X0 = wl.ks_c0(seed=19, Nx=cfg[0], amp=0.5)[:, None]
+    XN_ref, hist = imex.rk_forward(P, X0, cfg[2], nsteps, tableau=tab)
+    J_ref = P.energy(XN_ref)
+    g_ref = imex.rk_adjoint(P, P.energy_grad(XN_ref), hist, cfg[2], tableau=tab)
+    XN = torch.zeros(G.n, dtype=torch.float64, device="cuda")
+    gX = torch.zeros_like(XN)
+    J = torch.zeros(1, dtype=torch.float64, device="cuda")
+    G.gradient(to_dev(X0), nsteps, XN, gX, J)
+    G.sync()
+    ex, eg = rel(from_dev(XN, P.K), XN_ref), rel(from_dev(gX, P.K), g_ref)
+    print(f"  XN rel {ex:.2e}  dJ/dX0 rel {eg:.2e}", flush=True)
+    assert ex < TOL and abs(J.item() - J_ref) < TOL * abs(J_ref) and eg < TOL
+
+
+@pytest.mark.parametrize("name", ["rk222", "rk443"])
+def test_ks_rk_step_adjoint_and_solve(name):
+    """O(1) amplitudes, 40 steps: step + adjoint_step vs the oracle; sps_solve applies
+    M + dt gamma L; variable steps are refused for the RK schemes."""
+    print(f"KS {name} step + adjoint_step + solve", flush=True)
+    cfg, nsteps = FULL, 40
+    P, G, tab = rk_problem(cfg, nsteps, name)
+    X0 = wl.ks_c0(seed=20, Nx=cfg[0], amp=2.0)[:, None]
+    X = to_dev(X0)
+    G.step(X, nsteps)
+    dJ = torch.zeros(G.n, dtype=torch.float64, device="cuda")
+    G.cost(X, None, dJ)
+    G.adjoint_step(dJ, nsteps)
+    G.sync()
+    XN_ref, hist = imex.rk_forward(P, X0, cfg[2], nsteps, tableau=tab)
+    g_ref = imex.rk_adjoint(P, P.energy_grad(XN_ref), hist, cfg[2], tableau=tab)
+    assert rel(from_dev(X, P.K), XN_ref) < TOL
+    assert rel(from_dev(dJ, P.K), g_ref) < TOL
+    H = (tab if tab is not None else imex.ars222_tableau())[1]
+    R = wl.ks_c0(seed=21, Nx=cfg[0], amp=1.0)[:, None]
+    out = torch.zeros(G.n, dtype=torch.float64, device="cuda")
+    G.solve(to_dev(R), out)
+    G.sync()
+    assert rel(from_dev(out, P.K), imex.BlockLU(P.M, P.L, 1.0, cfg[2] * H[1, 1]).solve(R)) < TOL
+    with pytest.raises(sps.SpsError) as e:
+        G.set_timesteps(np.full(4, 0.01))
+    assert e.value.code == -7
