@@ -294,6 +294,40 @@ class RBC:
         i = np.flatnonzero(ok)[np.argmin(np.abs(w[ok] - sigma))]
         return w[i], vr[:, i], vl[:, i]
 
+    def stability_arnoldi(self, k, sigma, v0, m):
+        """Several eigenvalues nearest the real shift sigma at once (Supplementary, "Eigenvalue
+        problems": shift-invert about a target with a Krylov eigensolver): m steps of Arnoldi on
+        B = (sigma M + L_s)^-1 M from the start vector v0, each new vector orthogonalized by
+        classical Gram-Schmidt applied twice, then the eigenpairs (nu, y) of the m x m
+        Hessenberg matrix.  B X = nu X turns into (lambda M + L_s) X = 0 with
+        lambda = sigma - 1/nu.  Returns, ordered by decreasing |nu| (nearest sigma first): lambda,
+        the Ritz vectors V_m y (unit norm) as columns, the residuals |h_{m+1,m}| |e_m^T y| of the
+        pairs of B (y of unit norm), and the Arnoldi basis V (S x (m+1)) and matrix
+        Hbar ((m+1) x m)."""
+        import scipy.linalg as sla
+        A = sigma * self.M[k] + self.stability_operator()[k]
+        lu = sla.lu_factor(A)
+        S = A.shape[0]
+        V = np.zeros((S, m + 1), dtype=complex)
+        Hbar = np.zeros((m + 1, m), dtype=complex)
+        V[:, 0] = v0 / np.linalg.norm(v0)
+        for j in range(m):
+            w = sla.lu_solve(lu, self.M[k] @ V[:, j])
+            for _ in range(2):
+                h = V[:, :j + 1].conj().T @ w
+                w = w - V[:, :j + 1] @ h
+                Hbar[:j + 1, j] += h
+            Hbar[j + 1, j] = np.linalg.norm(w)
+            V[:, j + 1] = w / Hbar[j + 1, j]
+        nu, Y = np.linalg.eig(Hbar[:m, :])
+        order = np.argsort(-np.abs(nu), kind="stable")
+        nu, Y = nu[order], Y[:, order]
+        Y = Y / np.linalg.norm(Y, axis=0)
+        X = V[:, :m] @ Y
+        X = X / np.linalg.norm(X, axis=0)
+        res = np.abs(Hbar[m, m - 1]) * np.abs(Y[m - 1, :])
+        return sigma - 1.0 / nu, X, res, V, Hbar
+
     def _L_with(self, k, nu=None, ka=None, kx=None):
         saved = (self.nu, self.kappa, self.kx[k])
         if nu is not None:

@@ -3,7 +3,10 @@
 no-slip walls: Newton steps on the growth rate with the adjoint sensitivity converge to the
 textbook critical Rayleigh number 1707.762 at k = 3.1163 with a real leading eigenvalue
 (exchange of stabilities) and a neutral curve with zero slope there; the sensitivities equal
-central differences of the eigenvalues; the left eigenvector solves the adjoint problem."""
+central differences of the eigenvalues; the left eigenvector solves the adjoint problem.
+The shift-invert Arnoldi: the Arnoldi relation and orthonormal basis, its converged Ritz
+values equal the dense generalized eigenvalues nearest the shift in the same order, its Ritz
+vectors solve the pencil, and its leading value at the onset has zero growth rate."""
 import numpy as np
 
 from oracle.rbc import RBC
@@ -55,3 +58,52 @@ def test_left_eigenvector_solves_the_adjoint_problem():
     r = (np.conj(lam) * P.M[1].conj().T + Ls.conj().T) @ Y
     assert np.linalg.norm(r) < 1e-11 * np.linalg.norm(Ls) * np.linalg.norm(Y)
     assert np.linalg.norm((lam * P.M[1] + Ls) @ X) < 1e-11 * np.linalg.norm(Ls) * np.linalg.norm(X)
+
+
+def dense_nearest(P, k, sigma, count):
+    import scipy.linalg as sla
+    w = sla.eig(P.stability_operator()[k], -P.M[k], right=False)
+    w = w[np.isfinite(w)]
+    return w[np.argsort(np.abs(w - sigma), kind="stable")][:count]
+
+
+def test_arnoldi_relation_and_orthonormal_basis():
+    import workloads as wl
+    P = problem(3000.0, k=2.5, N=16)
+    m, sigma = 12, 0.5
+    v0 = wl.random_state(7, (P.K, P.M[1].shape[0]))[1]
+    lam, X, res, V, Hbar = P.stability_arnoldi(1, sigma, v0, m)
+    B = np.linalg.solve(sigma * P.M[1] + P.stability_operator()[1], P.M[1])
+    assert np.linalg.norm(B @ V[:, :m] - V @ Hbar) < 1e-12 * np.linalg.norm(B)
+    assert np.linalg.norm(V.conj().T @ V - np.eye(m + 1)) < 1e-13
+    assert np.allclose(np.tril(Hbar, -2), 0.0) and np.all(np.diag(Hbar, -1).real > 0)
+    assert np.allclose(V[:, 0], v0 / np.linalg.norm(v0))
+
+
+def test_arnoldi_ritz_values_are_the_eigenvalues_nearest_the_shift():
+    import workloads as wl
+    for Ra, k, sigma in ((5000.0, 3.0, 0.05), (3000.0, 2.5, -0.3)):
+        P = problem(Ra, k=k, N=24)
+        v0 = wl.random_state(8, (P.K, P.M[1].shape[0]))[1]
+        lam, X, res, V, Hbar = P.stability_arnoldi(1, sigma, v0, 30)
+        nu = 1.0 / (sigma - lam)
+        conv = res < 1e-10 * np.abs(nu)
+        nconv = int(np.argmin(conv)) if not conv.all() else len(conv)
+        assert nconv >= 4, res
+        ref = dense_nearest(P, 1, sigma, nconv)
+        assert np.max(np.abs(lam[:nconv] - ref) / np.maximum(np.abs(ref), 1.0)) < 1e-9
+        Ls, M = P.stability_operator()[1], P.M[1]
+        for i in range(nconv):
+            r = (lam[i] * M + Ls) @ X[:, i]
+            assert np.linalg.norm(r) < 1e-7 * np.linalg.norm(Ls)
+
+
+def test_arnoldi_leading_value_at_the_onset_has_zero_growth():
+    import workloads as wl
+    P = problem(RAC, k=KC, N=32)
+    v0 = wl.random_state(9, (P.K, P.M[1].shape[0]))[1]
+    lam, X, res, V, Hbar = P.stability_arnoldi(1, 0.0, v0, 20)
+    assert abs(lam[0]) < 1e-6 and abs(lam[0].imag) < 1e-12
+    lr, Xr, _ = P.stability_eig(1, 0.0)
+    assert abs(lam[0] - lr) < 1e-12
+    assert abs(abs(np.vdot(X[:, 0], Xr)) / np.linalg.norm(Xr) - 1.0) < 1e-10
