@@ -44,7 +44,8 @@ enum sps_status {
   SPS_E_SINGULAR = -4,     /* zero pivot in the LU factorization */
   SPS_E_NONFINITE = -5,    /* a state became NaN or infinite */
   SPS_E_STATE = -6,        /* call out of order (e.g. adjoint without a recorded forward run) */
-  SPS_E_UNSUPPORTED = -7
+  SPS_E_UNSUPPORTED = -7,
+  SPS_E_NOCONV = -8        /* an eigenvalue iteration did not converge (reported by sps_sync) */
 };
 
 enum sps_equation { SPS_RBC2D = 1, SPS_KS1D = 2, SPS_SH2D = 3, SPS_COUETTE3D = 4 };
@@ -230,6 +231,25 @@ int sps_solve(sps_problem *P, const double *R, double *X, int adjoint);
  * |lambda - sigma| / |lambda_2 - sigma|; the caller picks sigma and iters.  The stability bands
  * and a third factor set are built on the first call.  SPS_E_UNSUPPORTED for other problems. */
 int sps_stability(sps_problem *P, double sigma, int iters, double *lam, double *X, double *Y, double *dlam);
+
+/* Several eigenvalues nearest the real shift sigma per wavenumber of the same stability problem
+ * (Supplementary, "Eigenvalue problems": shift-invert about a target with a Krylov eigensolver):
+ * m Arnoldi steps on B = (sigma M + L_s)^-1 M through one blocked LU of sigma M + L_s, each
+ * new vector orthogonalized by classical Gram-Schmidt applied twice, then the eigenpairs
+ * (nu, y) of the m x m Hessenberg matrix by shifted QR steps on the device, and
+ * lambda = sigma - 1/nu.  2 <= m <= min(64, 3 nz), 1 <= nev <= m.  Device arrays:
+ *   v0   (nullable) [K][S] complex start vectors in the state layout (any norm); NULL uses a
+ *        fixed start vector;
+ *   lam  [K][nev] complex: the nev eigenvalues with the largest |nu| (nearest sigma), in
+ *        that order;
+ *   X    (nullable) [K][nev][S] complex Ritz vectors V_m y, unit Euclidean norm;
+ *   res  (nullable) [K][nev] doubles: the residuals |h_{m+1,m}| |e_m^T y| (|y| = 1) of the
+ *        pairs of B; a pair has converged when res is small against |nu|;
+ *   H    (nullable) [K][m+1][m] complex: the Arnoldi matrix, row-major.
+ * The 2D problem; SPS_E_UNSUPPORTED otherwise.  A QR iteration that does not converge in
+ * 30 m steps sets a flag that the next sps_sync() reports as SPS_E_NOCONV. */
+int sps_stability_arnoldi(sps_problem *P, double sigma, int m, int nev, const double *v0, double *lam, double *X,
+                          double *res, double *H);
 
 /* Variable time steps of the multistep schemes (equ:imex: the coefficients of step n depend on
  * the step sizes, lower order while the history is short).  dts: HOST array of n step sizes

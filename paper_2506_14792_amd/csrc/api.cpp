@@ -168,6 +168,11 @@ int sps_stability(sps_problem* P, double sigma, int iters, double* lam, double* 
   return guard(P, [&](sps::ProblemImpl& p) { p.stability(sigma, iters, lam, X, Y, dlam); });
 }
 
+int sps_stability_arnoldi(sps_problem* P, double sigma, int m, int nev, const double* v0, double* lam, double* X,
+                          double* res, double* H) {
+  return guard(P, [&](sps::ProblemImpl& p) { p.stability_arnoldi(sigma, m, nev, v0, lam, X, res, H); });
+}
+
 int sps_set_timesteps(sps_problem* P, const double* dts, int n) {
   return guard(P, [&](sps::ProblemImpl& p) { p.set_timesteps(dts, n); });
 }
@@ -345,6 +350,7 @@ int sps_sync(sps_problem* P) {
   if (rc != SPS_OK) return rc;
   if (flag & 1) return fail(SPS_E_SINGULAR, "zero pivot in the LU factorization");
   if (flag & 2) return fail(SPS_E_NONFINITE, "state became non-finite");
+  if (flag & 4) return fail(SPS_E_NOCONV, "an eigenvalue iteration did not converge");
   return SPS_OK;
 }
 

@@ -1223,6 +1223,258 @@ __global__ void __launch_bounds__(NT) rbc_evp_sens(RbcDev d, const cplx* X, cons
   }
 }
 
+// ---------------------------------------------------------------------------- shift-invert Arnoldi
+// Several eigenvalues nearest a real shift per wavenumber (Supplementary, "Eigenvalue
+// problems": a Krylov eigensolver on the shift-inverted pencil).  m Arnoldi steps on
+// B = (sigma M + L_s)^-1 M through the factors of the inverse iteration: v_{j+1} h_{j+1,j} =
+// B v_j - sum_{i<=j} h_ij v_i, the h_ij by classical Gram-Schmidt applied twice.  Basis V laid
+// out vector-major, [m+1][K][S] (vector j of every wavenumber is a state); Hessenberg matrices
+// Hb [K][(m+1) m], row-major.
+constexpr int ARN_MAX_M = 64;
+constexpr int ARN_CH = 4;   // inner products reduced together
+
+// Orthogonalizes w = V_{j+1} (in place, one block per wavenumber) against V_0..V_j and
+// normalizes it, filling column j of Hb; j = -1 normalizes the start vector V_0.
+__global__ void __launch_bounds__(NT) rbc_arnoldi_orth(RbcDev d, cplx* V, cplx* Hb, int j, int m) {
+  extern __shared__ double smem_d[];
+  __shared__ double red[2 * ARN_CH][NT];
+  __shared__ cplx hs[ARN_MAX_M];
+  cplx* w = reinterpret_cast<cplx*>(smem_d);
+  const int k = blockIdx.x, K = d.K, S = d.S, tid = threadIdx.x;
+  auto vec = [&](int i) { return V + ((size_t)i * K + k) * S; };
+  cplx* Hk = Hb + (size_t)k * (m + 1) * m;
+  cplx* wg = vec(j + 1);
+  for (int s = tid; s < S; s += NT) w[s] = wg[s];
+  __syncthreads();
+  for (int pass = 0; pass < 2 && j >= 0; ++pass) {
+    for (int i0 = 0; i0 <= j; i0 += ARN_CH) {
+      double v[2 * ARN_CH];
+#pragma unroll
+      for (int c = 0; c < 2 * ARN_CH; ++c) v[c] = 0.0;
+      for (int s = tid; s < S; s += NT) {
+        const cplx b = w[s];
+#pragma unroll
+        for (int c = 0; c < ARN_CH; ++c)
+          if (i0 + c <= j) {
+            const cplx a = vec(i0 + c)[s];
+            v[2 * c] += a.x * b.x + a.y * b.y;       // Re conj(a) b
+            v[2 * c + 1] += a.x * b.y - a.y * b.x;   // Im conj(a) b
+          }
+      }
+      block_sums<2 * ARN_CH>(v, red);
+      if (tid == 0)
+#pragma unroll
+        for (int c = 0; c < ARN_CH; ++c)
+          if (i0 + c <= j) hs[i0 + c] = cmk(v[2 * c], v[2 * c + 1]);
+      __syncthreads();   // red is reused by the next reduction; hs complete
+    }
+    for (int s = tid; s < S; s += NT) {
+      cplx r = w[s];
+      for (int i = 0; i <= j; ++i) r = csub(r, cmul(hs[i], vec(i)[s]));
+      w[s] = r;
+    }
+    if (tid <= j) Hk[(size_t)tid * m + j] = pass == 0 ? hs[tid] : cadd(Hk[(size_t)tid * m + j], hs[tid]);
+    __syncthreads();
+  }
+  double v[1] = {0.0};
+  for (int s = tid; s < S; s += NT) v[0] += w[s].x * w[s].x + w[s].y * w[s].y;
+  block_sums<1>(v, red);
+  const double h = sqrt(v[0]);
+  const double inv = h > 0.0 ? 1.0 / h : 0.0;
+  for (int s = tid; s < S; s += NT) wg[s] = cscale(w[s], inv);
+  if (j >= 0 && tid == 0) Hk[(size_t)(j + 1) * m + j] = cmk(h, 0.0);
+  for (int i = j + 2 + tid; j >= 0 && i <= m; i += NT) Hk[(size_t)i * m + j] = czero();   // below the subdiagonal
+}
+
+__device__ __forceinline__ double cabs_d(cplx a) { return hypot(a.x, a.y); }
+__device__ __forceinline__ cplx cdiv(cplx a, cplx b) {
+  const double q = 1.0 / (b.x * b.x + b.y * b.y);
+  return cmk((a.x * b.x + a.y * b.y) * q, (a.y * b.x - a.x * b.y) * q);
+}
+__device__ __forceinline__ cplx csqrt_d(cplx z) {
+  const double r = hypot(z.x, z.y);
+  if (r == 0.0) return czero();
+  const double t = sqrt(0.5 * (r + fabs(z.x)));
+  return z.x >= 0.0 ? cmk(t, z.y / (2.0 * t)) : cmk(fabs(z.y) / (2.0 * t), copysign(t, z.y));
+}
+
+// Eigenpairs of the m x m Hessenberg matrix of every wavenumber (one wave per wavenumber):
+// complex Schur form H = Z T Z^H by shifted QR steps (Givens rotations, Wilkinson shift from
+// the trailing 2 x 2 of the active block, an exceptional shift every 10 steps without
+// deflation, deflation where |h_{l,l-1}| <= ulp (|h_ll| + |h_{l-1,l-1}|)), eigenvectors of T
+// by back substitution, y = Z z normalized.  Out, per wavenumber, the nev pairs of largest
+// |nu| (nearest the shift) in that order: lam = sigma - 1/nu, the residual |h_{m+1,m}| |y_m|
+// (res, nullable) and y (Ysel [K][nev][m]).  Zw: [K][2][m][m] work.  No convergence within
+// 30 m steps sets bit 4 of d.err.
+constexpr int ARN_NT = 64;
+__global__ void __launch_bounds__(ARN_NT) rbc_hess_eig(RbcDev d, const cplx* Hb, int m, int nev, double sigma,
+                                                        cplx* lam, double* res, cplx* Ysel, cplx* Zw) {
+  extern __shared__ double smem_d[];
+  const int k = blockIdx.x, t = threadIdx.x, n = m;
+  cplx* H = reinterpret_cast<cplx*>(smem_d);
+  cplx* Z = H + n * n;
+  cplx* cs = Z + n * n;        // [2n] rotations of one QR step
+  cplx* nu = cs + 2 * n;       // [n]
+  double* rs = reinterpret_cast<double*>(nu + n);   // [n]
+  int* sel = reinterpret_cast<int*>(rs + n);        // [n]
+  const cplx* Hk = Hb + (size_t)k * (m + 1) * m;
+  for (int e = t; e < n * n; e += ARN_NT) {
+    const int i = e / n, j = e - i * n;
+    H[e] = (i <= j + 1) ? Hk[(size_t)i * m + j] : czero();
+    Z[e] = cmk(i == j ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  double anorm = 0.0;
+  for (int e = 0; e < n * n; ++e) anorm = fmax(anorm, cabs_d(H[e]));
+  const double ulp = 2.220446049250313e-16;
+  const double smlnum = fmax(anorm * ulp, 1e-300);
+  int hi = n - 1, its = 0, total = 0;
+  bool fail = false;
+  while (hi > 0) {
+    int l = hi;
+    for (; l > 0; --l) {
+      const double sub = cabs_d(H[l * n + l - 1]);
+      double tst = cabs_d(H[(l - 1) * n + l - 1]) + cabs_d(H[l * n + l]);
+      if (tst == 0.0) tst = anorm;
+      if (sub <= ulp * tst || sub <= smlnum) break;
+    }
+    __syncthreads();
+    if (l > 0 && t == 0) H[l * n + l - 1] = czero();
+    __syncthreads();
+    if (l == hi) {
+      --hi;
+      its = 0;
+      continue;
+    }
+    if (++total > 30 * n) {
+      fail = true;
+      break;
+    }
+    ++its;
+    cplx mu;
+    const cplx dd = H[hi * n + hi];
+    if (its % 10 == 0) {
+      mu = cmk(dd.x + 0.75 * cabs_d(H[hi * n + hi - 1]), dd.y);
+    } else {
+      const cplx a = H[(hi - 1) * n + hi - 1], b = H[(hi - 1) * n + hi], c = H[hi * n + hi - 1];
+      const cplx half = cscale(csub(a, dd), 0.5), mid = cscale(cadd(a, dd), 0.5);
+      const cplx disc = csqrt_d(cadd(cmul(half, half), cmul(b, c)));
+      const cplx m1 = cadd(mid, disc), m2 = csub(mid, disc);
+      mu = cabs_d(csub(m1, dd)) <= cabs_d(csub(m2, dd)) ? m1 : m2;
+    }
+    __syncthreads();
+    for (int i = l + t; i <= hi; i += ARN_NT) H[i * n + i] = csub(H[i * n + i], mu);
+    __syncthreads();
+    // H - mu I = Q R: G_kk zeroes h_{kk+1,kk}, G = [[conj c, conj s], [-s, c]]
+    for (int kk = l; kk < hi; ++kk) {
+      const cplx x = H[kk * n + kk], y = H[(kk + 1) * n + kk];
+      const double r = hypot(cabs_d(x), cabs_d(y));
+      const cplx c = r > 0.0 ? cscale(x, 1.0 / r) : cmk(1.0, 0.0);
+      const cplx sg = r > 0.0 ? cscale(y, 1.0 / r) : czero();
+      __syncthreads();
+      for (int j = kk + t; j < n; j += ARN_NT) {
+        const cplx a = H[kk * n + j], b = H[(kk + 1) * n + j];
+        H[kk * n + j] = cadd(cmul(cconj(c), a), cmul(cconj(sg), b));
+        H[(kk + 1) * n + j] = csub(cmul(c, b), cmul(sg, a));
+      }
+      if (t == 0) {
+        cs[2 * (kk - l)] = c;
+        cs[2 * (kk - l) + 1] = sg;
+      }
+      __syncthreads();
+    }
+    // R Q + mu I, Z Q: columns kk, kk+1 times G^H = [[c, -conj s], [s, conj c]]
+    for (int kk = l; kk < hi; ++kk) {
+      const cplx c = cs[2 * (kk - l)], sg = cs[2 * (kk - l) + 1];
+      for (int i = t; i <= kk + 1; i += ARN_NT) {
+        const cplx a = H[i * n + kk], b = H[i * n + kk + 1];
+        H[i * n + kk] = cadd(cmul(a, c), cmul(b, sg));
+        H[i * n + kk + 1] = csub(cmul(b, cconj(c)), cmul(a, cconj(sg)));
+      }
+      for (int i = t; i < n; i += ARN_NT) {
+        const cplx a = Z[i * n + kk], b = Z[i * n + kk + 1];
+        Z[i * n + kk] = cadd(cmul(a, c), cmul(b, sg));
+        Z[i * n + kk + 1] = csub(cmul(b, cconj(c)), cmul(a, cconj(sg)));
+      }
+      __syncthreads();
+    }
+    for (int i = l + t; i <= hi; i += ARN_NT) H[i * n + i] = cadd(H[i * n + i], mu);
+    __syncthreads();
+  }
+  if (fail && t == 0) atomicOr(d.err, 4);
+  // eigenvector i of T (lane i), then y = Z z
+  cplx* zk = Zw + (size_t)k * 2 * n * n;
+  const double hsub = cabs_d(Hk[(size_t)m * m + m - 1]);
+  for (int i = t; i < n; i += ARN_NT) {
+    cplx* z = zk + (size_t)i * n;
+    cplx* y = zk + (size_t)(n + i) * n;
+    const cplx ti = H[i * n + i];
+    for (int j = 0; j < n; ++j) z[j] = cmk(j == i ? 1.0 : 0.0, 0.0);
+    for (int j = i - 1; j >= 0; --j) {
+      cplx acc = czero();
+      for (int q = j + 1; q <= i; ++q) acc = cadd(acc, cmul(H[j * n + q], z[q]));
+      cplx den = csub(H[j * n + j], ti);
+      if (cabs_d(den) < smlnum) den = cmk(smlnum, 0.0);
+      z[j] = cscale(cdiv(acc, den), -1.0);
+    }
+    double nrm = 0.0;
+    for (int r = 0; r < n; ++r) {
+      cplx acc = czero();
+      for (int q = 0; q <= i; ++q) acc = cadd(acc, cmul(Z[r * n + q], z[q]));
+      y[r] = acc;
+      nrm += acc.x * acc.x + acc.y * acc.y;
+    }
+    const double inv = 1.0 / sqrt(nrm);
+    for (int r = 0; r < n; ++r) y[r] = cscale(y[r], inv);
+    nu[i] = ti;
+    rs[i] = hsub * cabs_d(y[n - 1]);
+  }
+  __syncthreads();
+  if (t == 0) {
+    for (int r = 0; r < nev; ++r) {
+      int best = -1;
+      double bv = -1.0;
+      for (int i = 0; i < n; ++i) {
+        bool used = false;
+        for (int q = 0; q < r; ++q) used = used || sel[q] == i;
+        const double a = cabs_d(nu[i]);
+        if (!used && a > bv) {
+          bv = a;
+          best = i;
+        }
+      }
+      sel[r] = best;
+    }
+  }
+  __syncthreads();
+  for (int r = t; r < nev; r += ARN_NT) {
+    const int i = sel[r];
+    const cplx inv_nu = cdiv(cmk(1.0, 0.0), nu[i]);
+    lam[(size_t)k * nev + r] = cmk(sigma - inv_nu.x, -inv_nu.y);
+    if (res) res[(size_t)k * nev + r] = rs[i];
+    const cplx* y = zk + (size_t)(n + i) * n;
+    for (int q = 0; q < n; ++q) Ysel[((size_t)k * nev + r) * m + q] = y[q];
+  }
+}
+
+// Ritz vectors X[k][r] = V_m y_r (unit norm), one block per (wavenumber, pair).
+__global__ void __launch_bounds__(NT) rbc_ritz(RbcDev d, const cplx* V, const cplx* Ysel, int m, int nev, cplx* X) {
+  __shared__ double red[1][NT];
+  const int k = blockIdx.x, r = blockIdx.y, K = d.K, S = d.S, tid = threadIdx.x;
+  const cplx* y = Ysel + ((size_t)k * nev + r) * m;
+  cplx* xo = X + ((size_t)k * nev + r) * S;
+  double v[1] = {0.0};
+  for (int s = tid; s < S; s += NT) {
+    cplx acc = czero();
+    for (int i = 0; i < m; ++i) acc = cadd(acc, cmul(V[((size_t)i * K + k) * S + s], y[i]));
+    xo[s] = acc;
+    v[0] += acc.x * acc.x + acc.y * acc.y;
+  }
+  block_sums<1>(v, red);
+  const double inv = v[0] > 0.0 ? 1.0 / sqrt(v[0]) : 0.0;
+  for (int s = tid; s < S; s += NT) xo[s] = cscale(xo[s], inv);
+}
+
 // ---------------------------------------------------------------------------- initial state and its adjoint
 // x pass: one block per scale-1 z node; b0 laid out [x][z].
 __global__ void __launch_bounds__(NT) rbc_init_x(RbcDev d, const double* grid, cplx* tmp) {
@@ -1824,10 +2076,9 @@ class RbcProblem : public ProblemImpl {
   // stability bands (built on first use), one factorization of sigma M + L_s, `iters` inverse
   // iterations for the right and for the left eigenvector through those factors, then the
   // sensitivities.  lam[K], dlam[K][2] complex; X, Y [K][S] complex (unit norm); device arrays.
-  void stability(double sigma, int iters, double* lam, double* X, double* Y, double* dlam) override {
-    if (cou_) throw Error(SPS_E_UNSUPPORTED, "the eigenvalue problem is built for the 2D problem");
-    SPS_REQUIRE(lam && X && Y && dlam, "null argument");
-    SPS_REQUIRE(iters >= 1 && iters <= 10000, "iters must be in [1, 10000]");
+  // Bands, factor storage and default start vector of the stability operator (first call),
+  // then the factors of sigma M + L_s; returns the descriptor with that band.
+  RbcDev evp_setup(double sigma) {
     if (!eops_) {
       RbcHostBands hb;
       host_bands(N_, kxs_, nu_, ka_, cp_, hb, 1.0);
@@ -1856,22 +2107,34 @@ class RbcProblem : public ProblemImpl {
     const size_t lds = (size_t)(2 * ekl_ + eku_ + 1) * S_ * sizeof(double) + sizeof(int) * S_;
     hipLaunchKernelGGL(rbc_factor, dim3(K_), dim3(NT), lds, stream, de, eBM_, eBL_, sigma, 1.0, eops_);
     SPS_CHECK_LAUNCH();
+    return de;
+  }
+  // y = (sigma M + L_s)^-1 M x for every wavenumber through the factors of evp_setup
+  void evp_apply(const RbcDev& de, const cplx* x, cplx* y) {
+    hipLaunchKernelGGL(rbc_apply_m, dim3(K_), dim3(NT), 0, stream, de, x, ework_);
+    SPS_CHECK_LAUNCH();
+    KfArgs a{};
+    a.X0 = ework_;
+    a.Xout = y;
+    a.nl = nl_;
+    a.F0 = F0_;
+    a.mode = KF_SOLVE;
+    hipLaunchKernelGGL(kfwd_fn(), dim3(K_), dim3(NTK), kf_lds(), stream, de, a);
+    SPS_CHECK_LAUNCH();
+  }
+
+  void stability(double sigma, int iters, double* lam, double* X, double* Y, double* dlam) override {
+    if (cou_) throw Error(SPS_E_UNSUPPORTED, "the eigenvalue problem is built for the 2D problem");
+    SPS_REQUIRE(lam && X && Y && dlam, "null argument");
+    SPS_REQUIRE(iters >= 1 && iters <= 10000, "iters must be in [1, 10000]");
+    const RbcDev de = evp_setup(sigma);
     cplx* x = reinterpret_cast<cplx*>(X);
     cplx* y = reinterpret_cast<cplx*>(Y);
     cplx* l = reinterpret_cast<cplx*>(lam);
     // right eigenvector
     copy_state(x, estart_);
     for (int it = 0; it < iters; ++it) {
-      hipLaunchKernelGGL(rbc_apply_m, dim3(K_), dim3(NT), 0, stream, de, x, ework_);
-      SPS_CHECK_LAUNCH();
-      KfArgs a{};
-      a.X0 = ework_;
-      a.Xout = y;   // y is scratch until the left iteration
-      a.nl = nl_;
-      a.F0 = F0_;
-      a.mode = KF_SOLVE;
-      hipLaunchKernelGGL(kfwd_fn(), dim3(K_), dim3(NTK), kf_lds(), stream, de, a);
-      SPS_CHECK_LAUNCH();
+      evp_apply(de, x, y);   // y is scratch until the left iteration
       hipLaunchKernelGGL(rbc_evp_update, dim3(K_), dim3(NT), 0, stream, de, x, y, sigma, l);
       SPS_CHECK_LAUNCH();
     }
@@ -1892,6 +2155,46 @@ class RbcProblem : public ProblemImpl {
     hipLaunchKernelGGL(rbc_evp_sens, dim3(K_), dim3(NT), 0, stream, de, x, y, -0.5 * nu_ / Ra, -0.5 * ka_ / Ra,
                        reinterpret_cast<cplx*>(dlam));
     SPS_CHECK_LAUNCH();
+  }
+
+  void stability_arnoldi(double sigma, int m, int nev, const double* v0, double* lam, double* X, double* res,
+                         double* Hout) override {
+    if (cou_) throw Error(SPS_E_UNSUPPORTED, "the eigenvalue problem is built for the 2D problem");
+    SPS_REQUIRE(lam != nullptr, "lam is null");
+    SPS_REQUIRE(m >= 2 && m <= ARN_MAX_M, "m must be in [2, 64]");
+    SPS_REQUIRE(nev >= 1 && nev <= m, "nev must be in [1, m]");
+    SPS_REQUIRE(m <= 3 * N_, "m must not exceed the rank of M (3 nz)");
+    const RbcDev de = evp_setup(sigma);
+    if (!aV_) {
+      aV_ = arena_.alloc<cplx>((size_t)(ARN_MAX_M + 1) * K_ * S_);
+      aH_ = arena_.alloc<cplx>((size_t)K_ * (ARN_MAX_M + 1) * ARN_MAX_M);
+      aZ_ = arena_.alloc<cplx>((size_t)K_ * 2 * ARN_MAX_M * ARN_MAX_M);
+      aY_ = arena_.alloc<cplx>((size_t)K_ * ARN_MAX_M * ARN_MAX_M);
+      SPS_HIP(hipFuncSetAttribute((const void*)rbc_hess_eig, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)hess_lds(ARN_MAX_M)));
+    }
+    auto vec = [&](int i) { return aV_ + (size_t)i * K_ * S_; };
+    copy_state(vec(0), v0 ? reinterpret_cast<const cplx*>(v0) : estart_);
+    const size_t wl = sizeof(cplx) * S_;
+    hipLaunchKernelGGL(rbc_arnoldi_orth, dim3(K_), dim3(NT), wl, stream, de, aV_, aH_, -1, m);
+    SPS_CHECK_LAUNCH();
+    for (int j = 0; j < m; ++j) {
+      evp_apply(de, vec(j), vec(j + 1));
+      hipLaunchKernelGGL(rbc_arnoldi_orth, dim3(K_), dim3(NT), wl, stream, de, aV_, aH_, j, m);
+      SPS_CHECK_LAUNCH();
+    }
+    if (Hout)
+      SPS_HIP(hipMemcpyAsync(Hout, aH_, sizeof(cplx) * K_ * (m + 1) * m, hipMemcpyDeviceToDevice, stream));
+    hipLaunchKernelGGL(rbc_hess_eig, dim3(K_), dim3(ARN_NT), hess_lds(m), stream, de, aH_, m, nev, sigma,
+                       reinterpret_cast<cplx*>(lam), res, aY_, aZ_);
+    SPS_CHECK_LAUNCH();
+    if (X) {
+      hipLaunchKernelGGL(rbc_ritz, dim3(K_, nev), dim3(NT), 0, stream, de, aV_, aY_, m, nev, reinterpret_cast<cplx*>(X));
+      SPS_CHECK_LAUNCH();
+    }
+  }
+  static size_t hess_lds(int m) {
+    return sizeof(cplx) * ((size_t)2 * m * m + 3 * m) + sizeof(double) * m + sizeof(int) * m;
   }
 
   void timer_enable(int kind, bool on) override {
@@ -2382,6 +2685,7 @@ class RbcProblem : public ProblemImpl {
   double *BM_ = nullptr, *BL_ = nullptr, *ops_ = nullptr, *Jpart_ = nullptr;
   double* lops_ = nullptr;   // LU block operators of L alone (boundary value problem), built on first use
   double *eBM_ = nullptr, *eBL_ = nullptr, *eops_ = nullptr;   // stability operator bands and factors
+  cplx *aV_ = nullptr, *aH_ = nullptr, *aZ_ = nullptr, *aY_ = nullptr;   // Arnoldi basis, Hessenberg, work
   cplx *ework_ = nullptr, *estart_ = nullptr;
   int ekl_ = 0, eku_ = 0;
   cplx* lrhs_ = nullptr;

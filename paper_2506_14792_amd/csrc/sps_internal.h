@@ -128,6 +128,9 @@ class ProblemImpl {
   virtual void stability(double, int, double*, double*, double*, double*) {
     throw Error(SPS_E_UNSUPPORTED, "the eigenvalue problem is built for the 2D problem");
   }
+  virtual void stability_arnoldi(double, int, int, const double*, double*, double*, double*, double*) {
+    throw Error(SPS_E_UNSUPPORTED, "the eigenvalue problem is built for the 2D problem");
+  }
   virtual void set_timesteps(const double*, int) {
     throw Error(SPS_E_UNSUPPORTED, "variable steps are built for the KS problem");
   }

@@ -55,6 +55,8 @@ def lib():
         "sps_eval_F_vjp": (ctypes.c_int, [_P, _D, _D, _D]),
         "sps_solve": (ctypes.c_int, [_P, _D, _D, ctypes.c_int]),
         "sps_stability": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int, _D, _D, _D, _D]),
+        "sps_stability_arnoldi": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int, ctypes.c_int, _D, _D, _D, _D,
+                                                 _D]),
         "sps_set_timesteps": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.c_int]),
         "sps_set_checkpointing": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int]),
         "sps_checkpoint_schedule": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -217,6 +219,27 @@ class Problem:
                                    _ptr(dlam)))
         c = lambda t, *shape: torch.view_as_complex(t.view(*shape, 2))
         return c(lam, K), c(X, K, S), c(Y, K, S), c(dlam, K, 2)
+
+    def stability_arnoldi(self, sigma=0.0, m=24, nev=4, v0=None, want_vectors=True, want_H=False):
+        """The nev eigenvalues nearest sigma of every wavenumber by shift-invert Arnoldi with m
+        steps: complex CUDA tensors lam [K, nev], X [K, nev, S] (or None), residuals res
+        [K, nev] (float64) and the Arnoldi matrices H [K, m+1, m] (or None).  v0: complex
+        [K, S] start vectors (CUDA), None for the fixed start (2D problem)."""
+        import torch
+        S = 4 * self.desc.nz + 7
+        K = self.n // (2 * S)
+        lam = torch.zeros(2 * K * nev, dtype=torch.float64, device="cuda")
+        res = torch.zeros(K * nev, dtype=torch.float64, device="cuda")
+        X = torch.zeros(2 * K * nev * S, dtype=torch.float64, device="cuda") if want_vectors else None
+        H = torch.zeros(2 * K * (m + 1) * m, dtype=torch.float64, device="cuda") if want_H else None
+        v = None
+        if v0 is not None:
+            v = torch.view_as_real(v0.to(torch.complex128).contiguous()).reshape(-1)
+            assert v.numel() == self.n and v.is_cuda
+        _check(lib().sps_stability_arnoldi(self._h, float(sigma), int(m), int(nev), _ptr(v), _ptr(lam), _ptr(X),
+                                           _ptr(res), _ptr(H)))
+        c = lambda t, *shape: None if t is None else torch.view_as_complex(t.view(*shape, 2))
+        return c(lam, K, nev), c(X, K, nev, S), res.view(K, nev), c(H, K, m + 1, m)
 
     def set_timesteps(self, dts=None):
         """Variable step sizes (a host sequence) for the following runs; None: the constant dt."""
