@@ -251,6 +251,17 @@ int sps_stability(sps_problem *P, double sigma, int iters, double *lam, double *
 int sps_stability_arnoldi(sps_problem *P, double sigma, int m, int nev, const double *v0, double *lam, double *X,
                           double *res, double *H);
 
+/* A new constant step dt > 0 for the following runs (a step-size change between segments of a
+ * run, as an adaptive step controller makes it; equ:imex: the implicit matrices depend on dt).
+ * The 2D problem and plane Couette refactor every wavenumber's M + dt gamma L at once (one
+ * blocked LU per wavenumber on the problem's stream); KS takes the new dt in its SBDF rows
+ * (unless variable steps are set) or RK stage coefficients.  Drops the recorded forward run and
+ * captured graphs: the reverse sweep of a segment runs with that segment's step, so a gradient
+ * through a run with step changes reverses the segments one by one, each after sps_set_dt of
+ * its own step and a recomputation of its forward sweep.  sps_solve then uses the new matrix.
+ * SPS_E_ARG for dt <= 0 or not finite; SPS_E_UNSUPPORTED for the batched problems. */
+int sps_set_dt(sps_problem *P, double dt);
+
 /* Variable time steps of the multistep schemes (equ:imex: the coefficients of step n depend on
  * the step sizes, lower order while the history is short).  dts: HOST array of n step sizes
  * (dts[i] = t_{i+1} - t_i, positive), copied; later sps_step / sps_gradient runs of at most n

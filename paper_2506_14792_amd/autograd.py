@@ -36,6 +36,35 @@ class Step(torch.autograd.Function):
         return g, None, None
 
 
+class StepSegments(torch.autograd.Function):
+    """X_N over segments of constant step: for each (dt, nsteps) in turn, sps_set_dt(dt) (the
+    implicit matrices refactored) and nsteps steps.  Backward reverses the segments from the
+    last: each is set to its own step again, its forward sweep recomputed from the segment's
+    stored initial state and reversed by sps_adjoint_step.  The problem is left at the first
+    segment's step after backward and at the last one's after forward."""
+
+    @staticmethod
+    def forward(ctx, X0, problem, segments):
+        X = X0.detach().contiguous().clone()
+        starts = []
+        for dt, n in segments:
+            starts.append(X.clone())
+            problem.set_dt(dt)
+            problem.step(X, n)
+        ctx.problem, ctx.segments, ctx.starts = problem, list(segments), starts
+        return X
+
+    @staticmethod
+    def backward(ctx, gX):
+        P = ctx.problem
+        g = gX.detach().contiguous().clone()
+        for (dt, n), X in zip(reversed(ctx.segments), reversed(ctx.starts)):
+            P.set_dt(dt)
+            P.step(X.clone(), n)
+            P.adjoint_step(g, n)
+        return g, None, None
+
+
 class InitialState(torch.autograd.Function):
     """X_0 = T(grid): the scale-1 grid field into the state (e.g. the initial buoyancy)."""
 
@@ -94,6 +123,10 @@ def lbvp(f, problem):
 
 def step(X0, problem, nsteps):
     return Step.apply(X0, problem, nsteps)
+
+
+def step_segments(X0, problem, segments):
+    return StepSegments.apply(X0, problem, segments)
 
 
 def initial_state(grid, problem):

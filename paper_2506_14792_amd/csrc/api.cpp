@@ -173,6 +173,10 @@ int sps_stability_arnoldi(sps_problem* P, double sigma, int m, int nev, const do
   return guard(P, [&](sps::ProblemImpl& p) { p.stability_arnoldi(sigma, m, nev, v0, lam, X, res, H); });
 }
 
+int sps_set_dt(sps_problem* P, double dt) {
+  return guard(P, [&](sps::ProblemImpl& p) { p.set_dt(dt); });
+}
+
 int sps_set_timesteps(sps_problem* P, const double* dts, int n) {
   return guard(P, [&](sps::ProblemImpl& p) { p.set_timesteps(dts, n); });
 }

@@ -515,6 +515,14 @@ class KsProblem : public ProblemImpl {
     SPS_HIP(hipMemcpyAsync(rows_, hrows_.data(), sizeof(SbdfCoef) * nrows_, hipMemcpyHostToDevice, stream));
     SPS_HIP(hipStreamSynchronize(stream));
   }
+  // A new constant step: the SBDF rows of the constant step (unless variable steps are set) or
+  // the RK stage coefficients take it; the recorded run is dropped.
+  void set_dt(double dt) override {
+    SPS_REQUIRE(std::isfinite(dt) && dt > 0.0, "dt must be positive");
+    desc_.dt = dt;
+    if (!rk_ && var_n_ == 0) upload_rows(0, nullptr);
+    tape_steps_ = -1;
+  }
   void set_timesteps(const double* dts, int n) override {
     if (rk_) throw Error(SPS_E_UNSUPPORTED, "variable steps are given for the multistep schemes");
     if (!dts || n == 0) {

@@ -1912,6 +1912,19 @@ class RbcProblem : public ProblemImpl {
     factored_ = true;
   }
 
+  // A new step for the following runs: the RK222 matrices M + dt gamma L of every wavenumber are
+  // refactored at once (in the scaled frame for plane Couette); recorded runs and captured
+  // graphs are dropped.
+  void set_dt(double dt) override {
+    SPS_REQUIRE(std::isfinite(dt) && dt > 0.0, "dt must be positive");
+    drop_graphs();
+    desc_.dt = dt;
+    dt_ = cou_ ? 0.5 * dt : dt;
+    factored_ = false;
+    tape_steps_ = -1;
+    factor();
+  }
+
   void step(double* X, int nsteps) override {
     SPS_REQUIRE(X != nullptr, "X is null");
     SPS_REQUIRE(nsteps >= 1 && nsteps <= desc_.max_steps, "nsteps out of range");

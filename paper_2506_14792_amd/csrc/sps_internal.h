@@ -131,6 +131,7 @@ class ProblemImpl {
   virtual void stability_arnoldi(double, int, int, const double*, double*, double*, double*, double*) {
     throw Error(SPS_E_UNSUPPORTED, "the eigenvalue problem is built for the 2D problem");
   }
+  virtual void set_dt(double) { throw Error(SPS_E_UNSUPPORTED, "the step is fixed for this problem"); }
   virtual void set_timesteps(const double*, int) {
     throw Error(SPS_E_UNSUPPORTED, "variable steps are built for the KS problem");
   }
