@@ -297,6 +297,60 @@ def lbvp_timing(reps=200):
             "speedup_vs_oracle": ocpu / (solve_s + adj_s)}
 
 
+def dtchange_timing(reps=3):
+    """Step-size changes on the headline configuration (256 x 64): the cost of sps_set_dt (the
+    RK222 matrices M + dt gamma L of all 128 wavenumbers refactored), and the gradient of a
+    1000-step run in four segments of 250 steps at dt = 1.0, 1.2, 0.9, 1.1 x 1e-3 through
+    torch.autograd (StepSegments: forward with a refactorization per segment; backward sets each
+    segment's step again, recomputes its forward sweep and reverses it) beside the gradient of
+    1000 steps at one step."""
+    import torch
+    import workloads as wl
+    import paper_2506_14792_amd as sps
+    from paper_2506_14792_amd import autograd as sa
+    c = CFG
+    G = sps.Problem(sps.RBC2D, c["nx"], c["nz"], c["lx"], c["Ra"], c["Pr"], 1.5, c["dt"], c["checkpoint_every"], 250)
+    b0 = torch.from_numpy(wl.rbc_b0(seed=c["seed"], Nx=c["nx"], Nz=c["nz"]).ravel().copy()).cuda()
+    X0 = torch.zeros(G.n, dtype=torch.float64, device="cuda")
+    G.initial_state(b0, X0)
+    G.set_dt(1.1e-3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(20):
+        G.set_dt(1e-3 if i % 2 == 0 else 1.2e-3)
+    torch.cuda.synchronize()
+    set_dt_s = (time.perf_counter() - t0) / 20
+    segs = [(1.0e-3, 250), (1.2e-3, 250), (0.9e-3, 250), (1.1e-3, 250)]
+
+    def seg_grad():
+        X = X0.clone().requires_grad_(True)
+        J = sa.cost(sa.step_segments(X, G, segs), G)
+        return torch.autograd.grad(J, X)[0]
+
+    seg_grad()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        seg_grad()
+    torch.cuda.synchronize()
+    seg_s = (time.perf_counter() - t0) / reps
+    G.sync()
+    G1 = sps.Problem(sps.RBC2D, c["nx"], c["nz"], c["lx"], c["Ra"], c["Pr"], 1.5, c["dt"], c["checkpoint_every"], 1000)
+    g = torch.zeros_like(X0)
+    G1.gradient(X0, 1000, None, g, None)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        G1.gradient(X0, 1000, None, g, None)
+    torch.cuda.synchronize()
+    one_s = (time.perf_counter() - t0) / reps
+    G1.sync()
+    return {"workload": "256x64 RK222, step changes: sps_set_dt (refactor of 128 wavenumbers' M + dt gamma L); "
+                        "gradient of 1000 steps in 4 segments of different dt through autograd",
+            "set_dt_ms": set_dt_s * 1e3, "segmented_gradient_s": seg_s, "single_step_gradient_s": one_s,
+            "segmented_over_single": seg_s / one_s}
+
+
 def ckpt_timing(slot_counts=(5, 10, 20, 50)):
     """Checkpoint schedules on the headline configuration (256 x 64, 1000 RK222 steps): the
     eager gradient with the default schedule (a stored state every 50 steps, one segment's stage
@@ -571,7 +625,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--skip-extra", action="store_true",
                     help="only the headline configuration (for counter and trace runs)")
-    ap.add_argument("--only", choices=["ks", "sh", "closure", "couette", "lbvp", "ckpt", "stability"], default=None,
+    ap.add_argument("--only", choices=["ks", "sh", "closure", "couette", "lbvp", "ckpt", "stability", "dtchange"],
+                    default=None,
                     help="run one secondary configuration alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -585,7 +640,8 @@ def main():
         import torch
         torch.cuda.set_device(0)
         fn = {"ks": ks_timing, "sh": sh_timing, "closure": kolmo_timing, "couette": couette_timing,
-              "lbvp": lbvp_timing, "ckpt": ckpt_timing, "stability": stability_timing}[args.only]
+              "lbvp": lbvp_timing, "ckpt": ckpt_timing, "stability": stability_timing,
+              "dtchange": dtchange_timing}[args.only]
         print(json.dumps({args.only: fn()}))
         return
 
@@ -657,10 +713,11 @@ def main():
     G.sync()
     graph_sec = (t7 - t6) / args.steps
     traffic = measured_traffic()
-    ks = sh = kol = cou = lbvp = ckpt = stab = None
+    ks = sh = kol = cou = lbvp = ckpt = stab = dtc = None
     if not args.skip_extra:
         lbvp = lbvp_timing()
         ckpt = ckpt_timing()
+        dtc = dtchange_timing()
         stab = stability_timing()
         ks = ks_timing()
         sh = sh_timing()
@@ -701,6 +758,7 @@ def main():
         "couette_autograd_config": cou,
         "lbvp_config": lbvp,
         "checkpointing_config": ckpt,
+        "step_change_config": dtc,
         "stability_config": stab,
         "J": J.item(),
     }
