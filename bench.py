@@ -352,7 +352,8 @@ def dtchange_timing(reps=3):
 
 
 def ckpt_timing(slot_counts=(5, 10, 20, 50)):
-    """Checkpoint schedules on the headline configuration (256 x 64, 1000 RK222 steps): the
+    """Checkpoint schedules on the headline configuration (256 x 64, 1000 RK222 steps; two levels
+    with the outer level in host memory or in a file): the
     eager gradient with the default schedule (a stored state every 50 steps, one segment's stage
     fields recorded, segments recomputed on a second stream) against binomial checkpointing with
     a few slot counts (all launches on one stream; the fewest recomputed steps for the storage).
@@ -402,6 +403,14 @@ def ckpt_timing(slot_counts=(5, 10, 20, 50)):
         out[f"two_level_{slots}"] = {"gradient_s": timed(), "forward_steps": n + (n // ce) * seg_steps,
                                      "stored_MB": slots * state_mb + 2 * stage_mb,
                                      "host_stored_MB": (n // ce) * state_mb}
+    # the disk level: the same segment starts in a file instead of host memory (8 slots)
+    import tempfile
+    with tempfile.TemporaryDirectory() as tmp:
+        G.set_checkpointing(sps.CKPT_TWO_LEVEL, 8)
+        G.set_checkpoint_file(os.path.join(tmp, "segment_starts.bin"))
+        out["two_level_8_disk"] = {"gradient_s": timed(), "file_MB": (n // ce) * state_mb,
+                                   "stored_MB": 8 * state_mb + 2 * stage_mb + 2 * state_mb}
+        G.set_checkpoint_file(None)
     G.set_checkpointing(sps.CKPT_UNIFORM)
     G.sync()
     return out

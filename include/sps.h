@@ -45,7 +45,8 @@ enum sps_status {
   SPS_E_NONFINITE = -5,    /* a state became NaN or infinite */
   SPS_E_STATE = -6,        /* call out of order (e.g. adjoint without a recorded forward run) */
   SPS_E_UNSUPPORTED = -7,
-  SPS_E_NOCONV = -8        /* an eigenvalue iteration did not converge (reported by sps_sync) */
+  SPS_E_NOCONV = -8,       /* an eigenvalue iteration did not converge (reported by sps_sync) */
+  SPS_E_IO = -9            /* the checkpoint file could not be created, written or read */
 };
 
 enum sps_equation { SPS_RBC2D = 1, SPS_KS1D = 2, SPS_SH2D = 3, SPS_COUETTE3D = 4 };
@@ -293,6 +294,18 @@ int sps_set_timesteps(sps_problem *P, const double *dts, int n);
  * SPS_E_UNSUPPORTED otherwise. */
 enum sps_checkpointing { SPS_CKPT_UNIFORM = 0, SPS_CKPT_BINOMIAL = 1, SPS_CKPT_TWO_LEVEL = 2 };
 int sps_set_checkpointing(sps_problem *P, int scheme, int slots);
+
+/* Disk level of the SPS_CKPT_TWO_LEVEL schedule (Supplementary, "Initial value problems": stored
+ * states on slower, larger storage when a run outgrows device and host memory).  path != NULL:
+ * the state at the start of every segment goes to this file (created or truncated, owner-only
+ * permissions, removed when the problem is destroyed or another path is set) instead of pinned
+ * host memory, staged through two pinned buffers of one state each: the forward sweep writes
+ * segment g's start once its device-to-host copy is done, while later segments run; the reverse
+ * sweep reads segment g's start while segment g+1 is reversed.  The host thread waits on
+ * those copies, so sps_step and sps_gradient return after the sweep's last file access.
+ * path = NULL returns to pinned host memory.  Drops the recorded forward run.  File errors
+ * return SPS_E_IO.  The 2D problem and plane Couette; SPS_E_UNSUPPORTED otherwise. */
+int sps_set_checkpoint_file(sps_problem *P, const char *path);
 
 /* The binomial schedule for nsteps steps and `slots` stored states (host arrays; no problem
  * or device needed): phase 0 the forward sweep, phase 1 the reverse sweep.  Writes *count

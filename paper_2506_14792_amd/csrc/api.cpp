@@ -185,6 +185,10 @@ int sps_set_checkpointing(sps_problem* P, int scheme, int slots) {
   return guard(P, [&](sps::ProblemImpl& p) { p.set_checkpointing(scheme, slots); });
 }
 
+int sps_set_checkpoint_file(sps_problem* P, const char* path) {
+  return guard(P, [&](sps::ProblemImpl& p) { p.set_checkpoint_file(path); });
+}
+
 int sps_checkpoint_schedule(int nsteps, int slots, int phase, int* actions, int capacity, int* count) {
   if (!count) return fail(SPS_E_ARG, "null count");
   *count = 0;

@@ -29,12 +29,15 @@
 // B = D_r A D_c R is then a real banded matrix (kl = 7, ku = 20 at N = 64) factored by
 // banded LU with partial pivoting.  A x = r is solved as B y = D_r r, x = D_c R y, and
 // A^H z = g as B^T w = R^T D_c^H g, z = D_r^H w, through the same factors.
+#include <fcntl.h>
 #include <math.h>
+#include <unistd.h>
 
 #include <algorithm>
 #include <cstring>
 #include <map>
 #include <memory>
+#include <string>
 #include <vector>
 
 #include "band_lu.h"
@@ -1895,6 +1898,9 @@ class RbcProblem : public ProblemImpl {
   ~RbcProblem() override {
     drop_graphs();
     if (host_ckpt_) (void)hipStreamSynchronize(stream);   // copies into pinned host memory
+    close_ckpt_file();
+    for (auto e : ckev_)
+      if (e) (void)hipEventDestroy(e);
     if (cap_) (void)hipStreamDestroy(cap_);
     if (aux_) (void)hipStreamSynchronize(aux_);
     for (auto e : ev_)
@@ -2463,11 +2469,8 @@ class RbcProblem : public ProblemImpl {
         rv_cap_ = slots;
       }
     }
-    if (scheme == SPS_CKPT_TWO_LEVEL && !host_ckpt_) {
-      const int nseg = (desc_.max_steps + desc_.checkpoint_every - 1) / desc_.checkpoint_every;
-      void* p = nullptr;
-      SPS_HIP(hipHostMalloc(&p, sizeof(cplx) * K_ * S_ * (size_t)nseg, hipHostMallocDefault));
-      host_ckpt_.reset(reinterpret_cast<cplx*>(p));
+    if (scheme == SPS_CKPT_TWO_LEVEL) {
+      if (ckfd_ < 0) alloc_host_ckpt();
       if (!Xs_) Xs_ = arena_.alloc<cplx>((size_t)K_ * S_);
     }
     drop_graphs();
@@ -2550,23 +2553,110 @@ class RbcProblem : public ProblemImpl {
   int seg_len(int g, int nsteps) const { return std::min(desc_.checkpoint_every, nsteps - g * desc_.checkpoint_every); }
   void forward_two_level(cplx* X, int nsteps) {
     const int ce = desc_.checkpoint_every, nseg = (nsteps + ce - 1) / ce;
-    for (int g = 0; g < nseg; ++g) {
-      copy_state(host_ckpt_.get() + (size_t)g * K_ * S_, X);
-      advance(X, 0, seg_len(g, nsteps));
+    if (ckfd_ >= 0) {
+      forward_disk(X, nsteps, nseg);
+    } else {
+      for (int g = 0; g < nseg; ++g) {
+        copy_state(host_ckpt_.get() + (size_t)g * K_ * S_, X);
+        advance(X, 0, seg_len(g, nsteps));
+      }
     }
     tape_steps_ = nsteps;
   }
   void reverse_two_level(cplx* Xbar, int nsteps) {
     const int ce = desc_.checkpoint_every, nseg = (nsteps + ce - 1) / ce;
     bool first = true;
+    int pend[2] = {0, 0};   // disk level: a host-to-device copy from staging buffer b in flight
     for (int g = nseg - 1; g >= 0; --g) {
       const auto& sc = schedule(seg_len(g, nsteps));
-      copy_state(Xs_, host_ckpt_.get() + (size_t)g * K_ * S_);
+      if (ckfd_ >= 0) {
+        const int b = g & 1;
+        if (pend[b]) SPS_HIP(hipEventSynchronize(ckev_[b]));
+        file_io(false, b, g);
+        copy_state(Xs_, ckstage_.get() + (size_t)b * K_ * S_);
+        SPS_HIP(hipEventRecord(ckev_[b], stream));
+        pend[b] = 1;
+      } else {
+        copy_state(Xs_, host_ckpt_.get() + (size_t)g * K_ * S_);
+      }
       run_forward_actions(Xs_, sc.first, false);
       run_reverse_actions(Xbar, sc.second, first);
     }
     finish_reverse(Xbar);
   }
+  // Disk level: segment starts staged through two pinned buffers; the write of segment g's
+  // start waits for its device-to-host copy (an event) while later segments run.
+  void forward_disk(cplx* X, int nsteps, int nseg) {
+    int pend[2] = {-1, -1};
+    auto flush = [&](int b) {
+      if (pend[b] < 0) return;
+      SPS_HIP(hipEventSynchronize(ckev_[b]));
+      file_io(true, b, pend[b]);
+      pend[b] = -1;
+    };
+    for (int g = 0; g < nseg; ++g) {
+      const int b = g & 1;
+      flush(b);
+      copy_state(ckstage_.get() + (size_t)b * K_ * S_, X);
+      SPS_HIP(hipEventRecord(ckev_[b], stream));
+      pend[b] = g;
+      advance(X, 0, seg_len(g, nsteps));
+    }
+    flush(0);
+    flush(1);
+  }
+  void file_io(bool write, int b, int g) {
+    const size_t bytes = sizeof(cplx) * K_ * S_;
+    char* p = reinterpret_cast<char*>(ckstage_.get() + (size_t)b * K_ * S_);
+    const off_t off = (off_t)g * (off_t)bytes;
+    size_t done = 0;
+    while (done < bytes) {
+      const ssize_t r = write ? pwrite(ckfd_, p + done, bytes - done, off + (off_t)done)
+                              : pread(ckfd_, p + done, bytes - done, off + (off_t)done);
+      if (r <= 0) throw Error(SPS_E_IO, write ? "checkpoint file write failed" : "checkpoint file read failed");
+      done += (size_t)r;
+    }
+  }
+  void alloc_host_ckpt() {
+    if (host_ckpt_) return;
+    const int nseg = (desc_.max_steps + desc_.checkpoint_every - 1) / desc_.checkpoint_every;
+    void* p = nullptr;
+    SPS_HIP(hipHostMalloc(&p, sizeof(cplx) * K_ * S_ * (size_t)nseg, hipHostMallocDefault));
+    host_ckpt_.reset(reinterpret_cast<cplx*>(p));
+  }
+  void close_ckpt_file() {
+    if (ckfd_ < 0) return;
+    (void)hipStreamSynchronize(stream);
+    (void)close(ckfd_);
+    (void)unlink(ckpath_.c_str());
+    ckfd_ = -1;
+    ckpath_.clear();
+  }
+
+ public:
+  void set_checkpoint_file(const char* path) override {
+    drop_graphs();
+    close_ckpt_file();
+    tape_steps_ = -1;
+    if (!path) {
+      if (ckpt_mode_ == SPS_CKPT_TWO_LEVEL) alloc_host_ckpt();
+      return;
+    }
+    SPS_REQUIRE(path[0] != '\0', "empty checkpoint file path");
+    const int fd = open(path, O_RDWR | O_CREAT | O_TRUNC, 0600);
+    if (fd < 0) throw Error(SPS_E_IO, std::string("cannot create the checkpoint file ") + path);
+    ckfd_ = fd;
+    ckpath_ = path;
+    if (!ckstage_) {
+      void* p = nullptr;
+      SPS_HIP(hipHostMalloc(&p, sizeof(cplx) * K_ * S_ * 2, hipHostMallocDefault));
+      ckstage_.reset(reinterpret_cast<cplx*>(p));
+      for (auto& e : ckev_) SPS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    host_ckpt_.reset();
+  }
+
+ private:
 
   // ----------------------------------------------------------------- tables
   void build_tables() {
@@ -2721,6 +2811,10 @@ class RbcProblem : public ProblemImpl {
     void operator()(cplx* p) const { (void)hipHostFree(p); }
   };
   std::unique_ptr<cplx, HostFree> host_ckpt_;   // two-level: segment start states in pinned host memory
+  std::unique_ptr<cplx, HostFree> ckstage_;     // disk level: two pinned staging buffers
+  hipEvent_t ckev_[2] = {nullptr, nullptr};
+  int ckfd_ = -1;                               // disk level: the checkpoint file, or -1
+  std::string ckpath_;
   KernelTimer timer_;
 };
 

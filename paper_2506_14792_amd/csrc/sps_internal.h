@@ -138,6 +138,9 @@ class ProblemImpl {
   virtual void set_checkpointing(int, int) {
     throw Error(SPS_E_UNSUPPORTED, "checkpoint schedules are built for the RK222 problems");
   }
+  virtual void set_checkpoint_file(const char*) {
+    throw Error(SPS_E_UNSUPPORTED, "checkpoint schedules are built for the RK222 problems");
+  }
   virtual void lbvp_solve(const double*, double*) {
     throw Error(SPS_E_UNSUPPORTED, "no boundary value problem for this equation");
   }

@@ -55,6 +55,7 @@ def lib():
         "sps_eval_F_vjp": (ctypes.c_int, [_P, _D, _D, _D]),
         "sps_solve": (ctypes.c_int, [_P, _D, _D, ctypes.c_int]),
         "sps_set_dt": (ctypes.c_int, [_P, ctypes.c_double]),
+        "sps_set_checkpoint_file": (ctypes.c_int, [_P, ctypes.c_char_p]),
         "sps_stability": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int, _D, _D, _D, _D]),
         "sps_stability_arnoldi": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int, ctypes.c_int, _D, _D, _D, _D,
                                                  _D]),
@@ -241,6 +242,12 @@ class Problem:
                                            _ptr(res), _ptr(H)))
         c = lambda t, *shape: None if t is None else torch.view_as_complex(t.view(*shape, 2))
         return c(lam, K, nev), c(X, K, nev, S), res.view(K, nev), c(H, K, m + 1, m)
+
+    def set_checkpoint_file(self, path):
+        """Disk level of CKPT_TWO_LEVEL: segment starts in this file (created, removed with the
+        problem); None returns to pinned host memory."""
+        _check(lib().sps_set_checkpoint_file(self._h, None if path is None else str(path).encode()))
+        self.tape_id += 1
 
     def set_dt(self, dt):
         """A new constant step for the following runs (refactors the implicit matrices; drops the

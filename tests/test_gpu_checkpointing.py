@@ -181,3 +181,68 @@ def test_two_level_couette():
     ref = grad(G, X0, n)
     G.set_checkpointing(sps.CKPT_TWO_LEVEL, 2)
     assert all(torch.equal(a, b) for a, b in zip(grad(G, X0, n), ref))
+
+
+def test_disk_level_equals_uniform(tmp_path):
+    """Disk level (sps_set_checkpoint_file): the segment starts of the two-level schedule in a
+    file, staged through pinned buffers: bit-identical gradients at 24x16 (ragged segments, 1-3
+    slots, step + adjoint_step) and at 256x64 x 1000 steps with 5 slots; the file holds one state
+    per segment and is removed with the problem; NULL returns to host memory; an uncreatable path
+    gives SPS_E_IO."""
+    import gc
+    import os
+    n, ce = 13, 4
+    note(f"disk level vs uniform, 24x16, {n} steps")
+    P, G, X0h = small_problem(n, ce)
+    X0 = to_dev(X0h)
+    ref = grad(G, X0, n)
+    path = tmp_path / "ckpt_small.bin"
+    G.set_checkpointing(sps.CKPT_TWO_LEVEL, 2)
+    G.set_checkpoint_file(path)
+    for slots in (1, 2, 3):
+        G.set_checkpointing(sps.CKPT_TWO_LEVEL, slots)
+        got = grad(G, X0, n)
+        same = all(torch.equal(a, b) for a, b in zip(got, ref))
+        note(f"  slots {slots}: identical {same}")
+        assert same
+    nseg = (n + ce - 1) // ce
+    assert os.path.getsize(path) == nseg * G.n * 8
+    X = X0.clone()
+    G.step(X, n)
+    dJ = torch.zeros_like(X)
+    G.cost(X, None, dJ)
+    G.adjoint_step(dJ, n)
+    G.sync()
+    assert torch.equal(X, ref[0]) and torch.equal(dJ, ref[1])
+    G.set_checkpoint_file(None)
+    assert not path.exists()
+    assert all(torch.equal(a, b) for a, b in zip(grad(G, X0, n), ref))
+    with pytest.raises(sps.SpsError) as e:
+        G.set_checkpoint_file(tmp_path / "missing_dir" / "ckpt.bin")
+    assert e.value.code == -9
+
+    note("disk level vs uniform, 256x64, 1000 steps, 5 slots")
+    nx, nz, lx, Ra, Pr, dt = FULL
+    nf = 1000
+    Gf = sps.Problem(sps.RBC2D, nx, nz, lx, Ra, Pr, 1.5, dt, 50, nf)
+    b0 = torch.from_numpy(wl.rbc_b0(seed=0, Nx=nx, Nz=nz).ravel().copy()).cuda()
+    Xf = torch.zeros(Gf.n, dtype=torch.float64, device="cuda")
+    Gf.initial_state(b0, Xf)
+    reff = grad(Gf, Xf, nf)
+    big = tmp_path / "ckpt_full.bin"
+    Gf.set_checkpointing(sps.CKPT_TWO_LEVEL, 5)
+    Gf.set_checkpoint_file(big)
+    gotf = grad(Gf, Xf, nf)
+    same = all(torch.equal(a, b) for a, b in zip(gotf, reff))
+    note(f"  identical {same}, file {os.path.getsize(big)} bytes")
+    assert same and os.path.getsize(big) == 20 * Gf.n * 8
+    del Gf
+    gc.collect()
+    assert not big.exists()
+
+
+def test_disk_level_unsupported_for_multistep_problems(tmp_path):
+    G = sps.Problem(sps.KS1D, 64, 0, 32.0 * np.pi, 0.0, 0.0, 1.5, 0.05, 1, 4)
+    with pytest.raises(sps.SpsError) as e:
+        G.set_checkpoint_file(tmp_path / "x.bin")
+    assert e.value.code == -7
