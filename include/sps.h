@@ -271,9 +271,10 @@ int sps_set_dt(sps_problem *P, double dt);
  * q = min(n, k): a_j the derivative at t_n of the Lagrange basis polynomial of node t_{n-j}
  * (backward difference of M dX/dt), c_i the value at t_n of the basis polynomial of t_{n-i}
  * on t_{n-1} .. t_{n-q} (extrapolation of F); equal steps give the constant-step rows.
+ * With the RK schemes step i + 1 uses dts[i] in its stage coefficients (the implicit matrices
+ * are diagonal, so nothing is refactored).
  * dts = NULL or n = 0 returns to the constant step of the descriptor (sps_solve always uses
- * it).  Drops the recorded forward run.  The KS problem with an SBDF scheme; SPS_E_UNSUPPORTED
- * otherwise. */
+ * it).  Drops the recorded forward run.  The KS problem; SPS_E_UNSUPPORTED otherwise. */
 int sps_set_timesteps(sps_problem *P, const double *dts, int n);
 
 /* Checkpointing of the RK222 sweeps (Supplementary, "Initial value problems": the reverse

@@ -290,24 +290,28 @@ __global__ void __launch_bounds__(NTS) ks_adjoint(KsDev d, cplx* Xbar, const cpl
   if (own) Xbar[m] = xb;
 }
 
-// RK forward sweep, S stages: X (in: X_0, out: X_N); the stage states X_{n,0..S-1} of step n at
+// RK forward sweep, S stages, step dt0 or dts[n] for step n + 1 (dts: device array, nullable):
+// X (in: X_0, out: X_N); the stage states X_{n,0..S-1} of step n at
 // H[(n S + i) K] for the reverse sweep.  Stage i solves
 // (1 + dt H_ii L_m) X_{n,i} = X_{n,0} + dt sum_{j<i} (A_ij F_{n,j} - H_ij L_m X_{n,j}) per mode
 // (M = 1); F of stage S is not needed (column S of A is zero).  One block; the stage values of
 // this thread's mode stay in registers.
 template <int S>
-__global__ void __launch_bounds__(NTS) ks_forward_rk(KsDev d, cplx* X, cplx* H, int nsteps, RkTab tab, double dt,
-                                                    int* err) {
+__global__ void __launch_bounds__(NTS) ks_forward_rk(KsDev d, cplx* X, cplx* H, int nsteps, RkTab tab, double dt0,
+                                                    const double* dts, int* err) {
   extern __shared__ double smem_d[];
   const KsLds L = ks_lds(d, smem_d);
   const int m = threadIdx.x, K = d.K;
   const bool own = m < K;
   const double lin = own ? d.lin[m] : 0.0;
   double inv[S + 1];
-#pragma unroll
-  for (int i = 1; i <= S; ++i) inv[i] = 1.0 / (1.0 + dt * tab.H[i][i] * lin);
   cplx x0 = own ? X[m] : czero();
   for (int n = 0; n < nsteps; ++n) {
+    const double dt = dts ? dts[n] : dt0;   // step n + 1 advances by dts[n]
+    if (n == 0 || dts) {
+#pragma unroll
+      for (int i = 1; i <= S; ++i) inv[i] = 1.0 / (1.0 + dt * tab.H[i][i] * lin);
+    }
     cplx xs[S + 1], fs[S];
     xs[0] = x0;
 #pragma unroll
@@ -347,17 +351,20 @@ __global__ void __launch_bounds__(NTS) ks_forward_rk(KsDev d, cplx* X, cplx* H, 
 //   cotangent of X_n = sum_{j>=1} Y_j + dF(X_{n,0})^H (dt sum_j A_j0 Y_j) - dt L sum_j H_j0 Y_j.
 template <int S>
 __global__ void __launch_bounds__(NTS) ks_adjoint_rk(KsDev d, cplx* Xbar, const cplx* H, int nsteps, RkTab tab,
-                                                    double dt) {
+                                                    double dt0, const double* dts) {
   extern __shared__ double smem_d[];
   const KsLds L = ks_lds(d, smem_d);
   const int m = threadIdx.x, K = d.K;
   const bool own = m < K;
   const double lin = own ? d.lin[m] : 0.0;
   double inv[S + 1];
-#pragma unroll
-  for (int i = 1; i <= S; ++i) inv[i] = 1.0 / (1.0 + dt * tab.H[i][i] * lin);
   cplx yn = own ? Xbar[m] : czero();
   for (int n = nsteps - 1; n >= 0; --n) {
+    const double dt = dts ? dts[n] : dt0;
+    if (n == nsteps - 1 || dts) {
+#pragma unroll
+      for (int i = 1; i <= S; ++i) inv[i] = 1.0 / (1.0 + dt * tab.H[i][i] * lin);
+    }
     cplx ys[S + 1];
     ys[S] = cscale(yn, inv[S]);
 #pragma unroll
@@ -524,7 +531,20 @@ class KsProblem : public ProblemImpl {
     tape_steps_ = -1;
   }
   void set_timesteps(const double* dts, int n) override {
-    if (rk_) throw Error(SPS_E_UNSUPPORTED, "variable steps are given for the multistep schemes");
+    if (rk_) {
+      if (!dts || n == 0) {
+        var_n_ = 0;
+      } else {
+        SPS_REQUIRE(n >= 1 && n <= desc_.max_steps, "the step sequence must have 1 .. max_steps entries");
+        for (int i = 0; i < n; ++i) SPS_REQUIRE(std::isfinite(dts[i]) && dts[i] > 0.0, "step sizes must be positive");
+        if (!dts_) dts_ = arena_.alloc<double>(desc_.max_steps);
+        SPS_HIP(hipMemcpyAsync(dts_, dts, sizeof(double) * n, hipMemcpyHostToDevice, stream));
+        SPS_HIP(hipStreamSynchronize(stream));
+        var_n_ = n;
+      }
+      tape_steps_ = -1;
+      return;
+    }
     if (!dts || n == 0) {
       upload_rows(0, nullptr);
       var_n_ = 0;
@@ -552,9 +572,11 @@ class KsProblem : public ProblemImpl {
     if (!rk_)
       hipLaunchKernelGGL(ks_adjoint, dim3(1), dim3(NTS), lds(), stream, dv_, xb, H_, nsteps, rows_);
     else if (stages_ == 2)
-      hipLaunchKernelGGL(ks_adjoint_rk<2>, dim3(1), dim3(NTS), lds(), stream, dv_, xb, H_, nsteps, tab_, desc_.dt);
+      hipLaunchKernelGGL(ks_adjoint_rk<2>, dim3(1), dim3(NTS), lds(), stream, dv_, xb, H_, nsteps, tab_, desc_.dt,
+                         rk_dts());
     else
-      hipLaunchKernelGGL(ks_adjoint_rk<4>, dim3(1), dim3(NTS), lds(), stream, dv_, xb, H_, nsteps, tab_, desc_.dt);
+      hipLaunchKernelGGL(ks_adjoint_rk<4>, dim3(1), dim3(NTS), lds(), stream, dv_, xb, H_, nsteps, tab_, desc_.dt,
+                         rk_dts());
     SPS_CHECK_LAUNCH();
   }
   void cost(const double* X, double* J, double* dJdX) override {
@@ -613,6 +635,7 @@ class KsProblem : public ProblemImpl {
 
  private:
   size_t lds() const { return sizeof(cplx) * (Ng_ + 4 * K_) + sizeof(double) * Ng_; }
+  const double* rk_dts() const { return var_n_ ? dts_ : nullptr; }
   // one-block sweep launch, bracketed by the timer's events while it records
   template <typename... P, typename... A>
   void launch_timed(void (*kern)(P...), A... args) {
@@ -624,8 +647,8 @@ class KsProblem : public ProblemImpl {
   }
   void forward(cplx* X, int nsteps) {
     if (!rk_) launch_timed(ks_forward, dv_, X, H_, nsteps, static_cast<const SbdfCoef*>(rows_), err_);
-    else if (stages_ == 2) launch_timed(ks_forward_rk<2>, dv_, X, H_, nsteps, tab_, desc_.dt, err_);
-    else launch_timed(ks_forward_rk<4>, dv_, X, H_, nsteps, tab_, desc_.dt, err_);
+    else if (stages_ == 2) launch_timed(ks_forward_rk<2>, dv_, X, H_, nsteps, tab_, desc_.dt, rk_dts(), err_);
+    else launch_timed(ks_forward_rk<4>, dv_, X, H_, nsteps, tab_, desc_.dt, rk_dts(), err_);
     SPS_CHECK_LAUNCH();
     tape_steps_ = nsteps;
   }
@@ -634,6 +657,7 @@ class KsProblem : public ProblemImpl {
   bool rk_ = false;  // an IMEX RK scheme: tab_ with stages_ stages
   int stages_ = 0;
   RkTab tab_{};
+  double* dts_ = nullptr;   // RK on variable steps: the step sizes (device, max_steps entries)
   sps_desc desc_;
   int K_ = 0, Ng_ = 0;
   KsDev dv_{};

@@ -249,7 +249,7 @@ def test_ks_rk_forward_and_gradient(cfg, nsteps, name):
 @pytest.mark.parametrize("name", ["rk222", "rk443"])
 def test_ks_rk_step_adjoint_and_solve(name):
     """O(1) amplitudes, 40 steps: step + adjoint_step vs the oracle; sps_solve applies
-    M + dt gamma L; variable steps are refused for the RK schemes."""
+    M + dt gamma L."""
     print(f"KS {name} step + adjoint_step + solve", flush=True)
     cfg, nsteps = FULL, 40
     P, G, tab = rk_problem(cfg, nsteps, name)
@@ -270,6 +270,39 @@ def test_ks_rk_step_adjoint_and_solve(name):
     G.solve(to_dev(R), out)
     G.sync()
     assert rel(from_dev(out, P.K), imex.BlockLU(P.M, P.L, 1.0, cfg[2] * H[1, 1]).solve(R)) < TOL
-    with pytest.raises(sps.SpsError) as e:
-        G.set_timesteps(np.full(4, 0.01))
-    assert e.value.code == -7
+
+
+@pytest.mark.parametrize("name", ["rk222", "rk443"])
+def test_ks_rk_variable_steps(name):
+    """RK on variable steps (sps_set_timesteps): 200 steps on a linear ramp of step sizes from
+    0.67 to 1.33 x 0.05; the oracle chains single RK steps of those sizes and reverses them in
+    turn.  Back to the constant step afterwards."""
+    print(f"KS {name} variable steps", flush=True)
+    cfg, nsteps = FULL, 200
+    P, G, tab = rk_problem(cfg, nsteps, name)
+    h = 0.05 * (0.67 + 0.67 * np.arange(nsteps) / nsteps)
+    X0 = wl.ks_c0(seed=23, Nx=cfg[0], amp=0.5)[:, None]
+    X, hists = X0, []
+    for i in range(nsteps):
+        X, hi = imex.rk_forward(P, X, h[i], 1, tableau=tab)
+        hists.append(hi)
+    XN_ref = X
+    g_ref = P.energy_grad(XN_ref)
+    for i in reversed(range(nsteps)):
+        g_ref = imex.rk_adjoint(P, g_ref, hists[i], h[i], tableau=tab)
+    G.set_timesteps(h)
+    XN = torch.zeros(G.n, dtype=torch.float64, device="cuda")
+    gX = torch.zeros_like(XN)
+    J = torch.zeros(1, dtype=torch.float64, device="cuda")
+    G.gradient(to_dev(X0), nsteps, XN, gX, J)
+    G.sync()
+    ex, eg = rel(from_dev(XN, P.K), XN_ref), rel(from_dev(gX, P.K), g_ref)
+    print(f"  XN rel {ex:.2e}  dJ/dX0 rel {eg:.2e}", flush=True)
+    assert ex < TOL and eg < TOL
+    with pytest.raises(sps.SpsError):
+        G.step(to_dev(X0), nsteps + 1)
+    G.set_timesteps(None)
+    G.gradient(to_dev(X0), nsteps, XN, gX, J)
+    G.sync()
+    XN_c, _ = imex.rk_forward(P, X0, cfg[2], nsteps, tableau=tab)
+    assert rel(from_dev(XN, P.K), XN_c) < TOL
