@@ -1234,13 +1234,39 @@ __global__ void __launch_bounds__(NT) rbc_evp_sens(RbcDev d, const cplx* X, cons
 // out vector-major, [m+1][K][S] (vector j of every wavenumber is a state); Hessenberg matrices
 // Hb [K][(m+1) m], row-major.
 constexpr int ARN_MAX_M = 64;
-constexpr int ARN_CH = 4;   // inner products reduced together
+constexpr int ARN_CH = 8;   // inner products reduced together
+
+// Sums of C values over the block (NT / 64 waves): each wave sums by xor shuffles, then the
+// waves' partial sums meet in LDS (red: [C][NT / 64]); every thread gets the sums.  A barrier
+// must separate two uses of red.
+template <int C>
+__device__ __forceinline__ void block_sums_w(double (&v)[C], double (*red)[NT / 64]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    double x = v[c];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    v[c] = x;
+  }
+  if (lane == 0)
+#pragma unroll
+    for (int c = 0; c < C; ++c) red[c][w] = v[c];
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    double x = 0.0;
+#pragma unroll
+    for (int q = 0; q < NT / 64; ++q) x += red[c][q];
+    v[c] = x;
+  }
+}
 
 // Orthogonalizes w = V_{j+1} (in place, one block per wavenumber) against V_0..V_j and
 // normalizes it, filling column j of Hb; j = -1 normalizes the start vector V_0.
 __global__ void __launch_bounds__(NT) rbc_arnoldi_orth(RbcDev d, cplx* V, cplx* Hb, int j, int m) {
   extern __shared__ double smem_d[];
-  __shared__ double red[2 * ARN_CH][NT];
+  __shared__ double red[2 * ARN_CH][NT / 64];
   __shared__ cplx hs[ARN_MAX_M];
   cplx* w = reinterpret_cast<cplx*>(smem_d);
   const int k = blockIdx.x, K = d.K, S = d.S, tid = threadIdx.x;
@@ -1264,7 +1290,7 @@ __global__ void __launch_bounds__(NT) rbc_arnoldi_orth(RbcDev d, cplx* V, cplx* 
             v[2 * c + 1] += a.x * b.y - a.y * b.x;   // Im conj(a) b
           }
       }
-      block_sums<2 * ARN_CH>(v, red);
+      block_sums_w<2 * ARN_CH>(v, red);
       if (tid == 0)
 #pragma unroll
         for (int c = 0; c < ARN_CH; ++c)
@@ -1281,7 +1307,7 @@ __global__ void __launch_bounds__(NT) rbc_arnoldi_orth(RbcDev d, cplx* V, cplx* 
   }
   double v[1] = {0.0};
   for (int s = tid; s < S; s += NT) v[0] += w[s].x * w[s].x + w[s].y * w[s].y;
-  block_sums<1>(v, red);
+  block_sums_w<1>(v, red);
   const double h = sqrt(v[0]);
   const double inv = h > 0.0 ? 1.0 / h : 0.0;
   for (int s = tid; s < S; s += NT) wg[s] = cscale(w[s], inv);
@@ -1290,6 +1316,7 @@ __global__ void __launch_bounds__(NT) rbc_arnoldi_orth(RbcDev d, cplx* V, cplx* 
 }
 
 __device__ __forceinline__ double cabs_d(cplx a) { return hypot(a.x, a.y); }
+__device__ __forceinline__ double cabs1(cplx a) { return fabs(a.x) + fabs(a.y); }   // |re| + |im|
 __device__ __forceinline__ cplx cdiv(cplx a, cplx b) {
   const double q = 1.0 / (b.x * b.x + b.y * b.y);
   return cmk((a.x * b.x + a.y * b.y) * q, (a.y * b.x - a.x * b.y) * q);
@@ -1304,14 +1331,20 @@ __device__ __forceinline__ cplx csqrt_d(cplx z) {
 // Eigenpairs of the m x m Hessenberg matrix of every wavenumber (one wave per wavenumber):
 // complex Schur form H = Z T Z^H by shifted QR steps (Givens rotations, Wilkinson shift from
 // the trailing 2 x 2 of the active block, an exceptional shift every 10 steps without
-// deflation, deflation where |h_{l,l-1}| <= ulp (|h_ll| + |h_{l-1,l-1}|)), eigenvectors of T
+// deflation, deflation where |h_{l,l-1}| <= ulp (|h_ll| + |h_{l-1,l-1}|) with |z| measured as
+// |re z| + |im z|), eigenvectors of T
 // by back substitution, y = Z z normalized.  Out, per wavenumber, the nev pairs of largest
 // |nu| (nearest the shift) in that order: lam = sigma - 1/nu, the residual |h_{m+1,m}| |y_m|
-// (res, nullable) and y (Ysel [K][nev][m]).  Zw: [K][2][m][m] work.  No convergence within
-// 30 m steps sets bit 4 of d.err.
+// (res, nullable) and y (Ysel [K][nev][m]).  Zw: [K][2][m][m] work in global memory, or, with
+// zlds, the same 2 m^2 entries after sel in LDS.  No convergence within 30 m steps sets bit 4
+// of d.err.
 constexpr int ARN_NT = 64;
+// offset (in complex entries) of the eigenvector work arrays in rbc_hess_eig's LDS: after H, Z,
+// rotations and nu (2 n^2 + 3 n entries), residuals (n doubles) and selection (n ints), rounded
+// up to a whole entry
+__host__ __device__ inline int hess_zoff(int n) { return 2 * n * n + 3 * n + (8 * n + 4 * n + 15) / 16; }
 __global__ void __launch_bounds__(ARN_NT) rbc_hess_eig(RbcDev d, const cplx* Hb, int m, int nev, double sigma,
-                                                        cplx* lam, double* res, cplx* Ysel, cplx* Zw) {
+                                                        cplx* lam, double* res, cplx* Ysel, cplx* Zw, int zlds) {
   extern __shared__ double smem_d[];
   const int k = blockIdx.x, t = threadIdx.x, n = m;
   cplx* H = reinterpret_cast<cplx*>(smem_d);
@@ -1328,7 +1361,7 @@ __global__ void __launch_bounds__(ARN_NT) rbc_hess_eig(RbcDev d, const cplx* Hb,
   }
   __syncthreads();
   double anorm = 0.0;
-  for (int e = 0; e < n * n; ++e) anorm = fmax(anorm, cabs_d(H[e]));
+  for (int e = 0; e < n * n; ++e) anorm = fmax(anorm, cabs1(H[e]));
   const double ulp = 2.220446049250313e-16;
   const double smlnum = fmax(anorm * ulp, 1e-300);
   int hi = n - 1, its = 0, total = 0;
@@ -1336,8 +1369,8 @@ __global__ void __launch_bounds__(ARN_NT) rbc_hess_eig(RbcDev d, const cplx* Hb,
   while (hi > 0) {
     int l = hi;
     for (; l > 0; --l) {
-      const double sub = cabs_d(H[l * n + l - 1]);
-      double tst = cabs_d(H[(l - 1) * n + l - 1]) + cabs_d(H[l * n + l]);
+      const double sub = cabs1(H[l * n + l - 1]);
+      double tst = cabs1(H[(l - 1) * n + l - 1]) + cabs1(H[l * n + l]);
       if (tst == 0.0) tst = anorm;
       if (sub <= ulp * tst || sub <= smlnum) break;
     }
@@ -1371,9 +1404,10 @@ __global__ void __launch_bounds__(ARN_NT) rbc_hess_eig(RbcDev d, const cplx* Hb,
     // H - mu I = Q R: G_kk zeroes h_{kk+1,kk}, G = [[conj c, conj s], [-s, c]]
     for (int kk = l; kk < hi; ++kk) {
       const cplx x = H[kk * n + kk], y = H[(kk + 1) * n + kk];
-      const double r = hypot(cabs_d(x), cabs_d(y));
-      const cplx c = r > 0.0 ? cscale(x, 1.0 / r) : cmk(1.0, 0.0);
-      const cplx sg = r > 0.0 ? cscale(y, 1.0 / r) : czero();
+      const double r2 = x.x * x.x + x.y * x.y + y.x * y.x + y.y * y.y;
+      const double ir = r2 > 0.0 ? 1.0 / sqrt(r2) : 0.0;
+      const cplx c = r2 > 0.0 ? cscale(x, ir) : cmk(1.0, 0.0);
+      const cplx sg = cscale(y, ir);
       __syncthreads();
       for (int j = kk + t; j < n; j += ARN_NT) {
         const cplx a = H[kk * n + j], b = H[(kk + 1) * n + j];
@@ -1405,32 +1439,33 @@ __global__ void __launch_bounds__(ARN_NT) rbc_hess_eig(RbcDev d, const cplx* Hb,
     __syncthreads();
   }
   if (fail && t == 0) atomicOr(d.err, 4);
-  // eigenvector i of T (lane i), then y = Z z
-  cplx* zk = Zw + (size_t)k * 2 * n * n;
+  // eigenvector i of T (lane i), then y = Z z; entry j of vector i at [j n + i] (z) and
+  // [(n + j) n + i] (y), so the lanes of a wave touch neighbouring entries
+  cplx* zk = zlds ? reinterpret_cast<cplx*>(smem_d) + hess_zoff(n) : Zw + (size_t)k * 2 * n * n;
   const double hsub = cabs_d(Hk[(size_t)m * m + m - 1]);
   for (int i = t; i < n; i += ARN_NT) {
-    cplx* z = zk + (size_t)i * n;
-    cplx* y = zk + (size_t)(n + i) * n;
+    cplx* z = zk + i;
+    cplx* y = zk + (size_t)n * n + i;
     const cplx ti = H[i * n + i];
-    for (int j = 0; j < n; ++j) z[j] = cmk(j == i ? 1.0 : 0.0, 0.0);
+    for (int j = 0; j < n; ++j) z[(size_t)j * n] = cmk(j == i ? 1.0 : 0.0, 0.0);
     for (int j = i - 1; j >= 0; --j) {
       cplx acc = czero();
-      for (int q = j + 1; q <= i; ++q) acc = cadd(acc, cmul(H[j * n + q], z[q]));
+      for (int q = j + 1; q <= i; ++q) acc = cadd(acc, cmul(H[j * n + q], z[(size_t)q * n]));
       cplx den = csub(H[j * n + j], ti);
       if (cabs_d(den) < smlnum) den = cmk(smlnum, 0.0);
-      z[j] = cscale(cdiv(acc, den), -1.0);
+      z[(size_t)j * n] = cscale(cdiv(acc, den), -1.0);
     }
     double nrm = 0.0;
     for (int r = 0; r < n; ++r) {
       cplx acc = czero();
-      for (int q = 0; q <= i; ++q) acc = cadd(acc, cmul(Z[r * n + q], z[q]));
-      y[r] = acc;
+      for (int q = 0; q <= i; ++q) acc = cadd(acc, cmul(Z[r * n + q], z[(size_t)q * n]));
+      y[(size_t)r * n] = acc;
       nrm += acc.x * acc.x + acc.y * acc.y;
     }
     const double inv = 1.0 / sqrt(nrm);
-    for (int r = 0; r < n; ++r) y[r] = cscale(y[r], inv);
+    for (int r = 0; r < n; ++r) y[(size_t)r * n] = cscale(y[(size_t)r * n], inv);
     nu[i] = ti;
-    rs[i] = hsub * cabs_d(y[n - 1]);
+    rs[i] = hsub * cabs_d(y[(size_t)(n - 1) * n]);
   }
   __syncthreads();
   if (t == 0) {
@@ -1455,8 +1490,8 @@ __global__ void __launch_bounds__(ARN_NT) rbc_hess_eig(RbcDev d, const cplx* Hb,
     const cplx inv_nu = cdiv(cmk(1.0, 0.0), nu[i]);
     lam[(size_t)k * nev + r] = cmk(sigma - inv_nu.x, -inv_nu.y);
     if (res) res[(size_t)k * nev + r] = rs[i];
-    const cplx* y = zk + (size_t)(n + i) * n;
-    for (int q = 0; q < n; ++q) Ysel[((size_t)k * nev + r) * m + q] = y[q];
+    const cplx* y = zk + (size_t)n * n + i;
+    for (int q = 0; q < n; ++q) Ysel[((size_t)k * nev + r) * m + q] = y[(size_t)q * n];
   }
 }
 
@@ -2190,7 +2225,7 @@ class RbcProblem : public ProblemImpl {
       aZ_ = arena_.alloc<cplx>((size_t)K_ * 2 * ARN_MAX_M * ARN_MAX_M);
       aY_ = arena_.alloc<cplx>((size_t)K_ * ARN_MAX_M * ARN_MAX_M);
       SPS_HIP(hipFuncSetAttribute((const void*)rbc_hess_eig, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)hess_lds(ARN_MAX_M)));
+                                  (int)kHessLdsMax));
     }
     auto vec = [&](int i) { return aV_ + (size_t)i * K_ * S_; };
     copy_state(vec(0), v0 ? reinterpret_cast<const cplx*>(v0) : estart_);
@@ -2204,17 +2239,21 @@ class RbcProblem : public ProblemImpl {
     }
     if (Hout)
       SPS_HIP(hipMemcpyAsync(Hout, aH_, sizeof(cplx) * K_ * (m + 1) * m, hipMemcpyDeviceToDevice, stream));
-    hipLaunchKernelGGL(rbc_hess_eig, dim3(K_), dim3(ARN_NT), hess_lds(m), stream, de, aH_, m, nev, sigma,
-                       reinterpret_cast<cplx*>(lam), res, aY_, aZ_);
+    const int zlds = hess_lds(m, true) <= kHessLdsMax ? 1 : 0;
+    hipLaunchKernelGGL(rbc_hess_eig, dim3(K_), dim3(ARN_NT), hess_lds(m, zlds != 0), stream, de, aH_, m, nev, sigma,
+                       reinterpret_cast<cplx*>(lam), res, aY_, aZ_, zlds);
     SPS_CHECK_LAUNCH();
     if (X) {
       hipLaunchKernelGGL(rbc_ritz, dim3(K_, nev), dim3(NT), 0, stream, de, aV_, aY_, m, nev, reinterpret_cast<cplx*>(X));
       SPS_CHECK_LAUNCH();
     }
   }
-  static size_t hess_lds(int m) {
-    return sizeof(cplx) * ((size_t)2 * m * m + 3 * m) + sizeof(double) * m + sizeof(int) * m;
+  // LDS of rbc_hess_eig: H, Z, rotations, nu, residuals, selection, and with zlds the
+  // eigenvector work arrays
+  static size_t hess_lds(int m, bool zlds) {
+    return sizeof(cplx) * ((size_t)hess_zoff(m) + (zlds ? (size_t)2 * m * m : 0));
   }
+  static constexpr size_t kHessLdsMax = 160 * 1024;
 
   void timer_enable(int kind, bool on) override {
     SPS_REQUIRE(kind == 0, "unknown timer kind");
@@ -2566,7 +2605,9 @@ class RbcProblem : public ProblemImpl {
   void reverse_two_level(cplx* Xbar, int nsteps) {
     const int ce = desc_.checkpoint_every, nseg = (nsteps + ce - 1) / ce;
     bool first = true;
-    int pend[2] = {0, 0};   // disk level: a host-to-device copy from staging buffer b in flight
+    // disk level: a host-to-device copy from staging buffer b may be in flight (also from an
+    // earlier reverse sweep of the same run; waiting on an event never recorded returns at once)
+    int pend[2] = {1, 1};
     for (int g = nseg - 1; g >= 0; --g) {
       const auto& sc = schedule(seg_len(g, nsteps));
       if (ckfd_ >= 0) {
@@ -2636,6 +2677,7 @@ class RbcProblem : public ProblemImpl {
  public:
   void set_checkpoint_file(const char* path) override {
     drop_graphs();
+    SPS_HIP(hipStreamSynchronize(stream));   // copies into the host level may be in flight
     close_ckpt_file();
     tape_steps_ = -1;
     if (!path) {

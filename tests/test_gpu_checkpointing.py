@@ -212,8 +212,11 @@ def test_disk_level_equals_uniform(tmp_path):
     dJ = torch.zeros_like(X)
     G.cost(X, None, dJ)
     G.adjoint_step(dJ, n)
+    dJ2 = torch.zeros_like(X)   # a second reverse sweep of the same recorded run
+    G.cost(X, None, dJ2)
+    G.adjoint_step(dJ2, n)
     G.sync()
-    assert torch.equal(X, ref[0]) and torch.equal(dJ, ref[1])
+    assert torch.equal(X, ref[0]) and torch.equal(dJ, ref[1]) and torch.equal(dJ2, ref[1])
     G.set_checkpoint_file(None)
     assert not path.exists()
     assert all(torch.equal(a, b) for a, b in zip(grad(G, X0, n), ref))
