@@ -90,51 +90,59 @@ SbdfCoef sbdf_row_variable(const double* h, int n, int order) {
 
 // Grid values from half-spectrum coefficients (LDS), W = 2 for the real field
 // u_j = Re c_0 + 2 sum_{m>=1} Re(c_m e^{2 pi i j m / Ng}), W = 1 for the transposed forward
-// transform (unweighted).  Two series at once (b may be null).  Block-wide, no barrier.
+// transform (unweighted).  Two series at once (b may be null).  Two lanes (an aligned pair,
+// h = 0, 1) per grid point, lane h summing the modes m = 1 + h, 3 + h, ...; both lanes of the
+// pair return the values.  Block-wide, no barrier.
 __device__ __forceinline__ void ks_grid_point(const KsDev& d, const cplx* ex, const cplx* a, double Wa,
-                                              const cplx* b, double Wb, int j, double& ua, double& ub) {
-  int t = 0;
+                                              const cplx* b, double Wb, int j, int h, double& ua, double& ub) {
+  const int Ng = d.Ng;
+  int t = (int)(((long long)(1 + h) * j) % Ng);
+  const int st = (2 * j) % Ng;
   double sa = 0.0, sb = 0.0;
-  for (int m = 1; m < d.K; ++m) {
-    t += j;
-    if (t >= d.Ng) t -= d.Ng;
+  for (int m = 1 + h; m < d.K; m += 2) {
     const cplx e = ex[t];
     sa = fma(a[m].x, e.x, fma(-a[m].y, e.y, sa));
     if (b) sb = fma(b[m].x, e.x, fma(-b[m].y, e.y, sb));
+    t += st;
+    if (t >= Ng) t -= Ng;
   }
+  sa = group_sum<2>(sa);
+  if (b) sb = group_sum<2>(sb);
   ua = a[0].x + Wa * sa;
   ub = b ? b[0].x + Wb * sb : 0.0;
 }
 
-// sum_j v_j e^{-2 pi i j m / Ng} over the grid, four lanes (an aligned quad) per mode; every
-// lane of the quad returns the sum.
+// sum_j v_j e^{-2 pi i j m / Ng} over the grid, eight lanes (an aligned group, h = 0..7) per
+// mode; every lane of the group returns the sum.
+constexpr int KS_MG = 8;
 __device__ __forceinline__ cplx ks_mode_sum(const KsDev& d, const cplx* ex, const double* v, int m, int h) {
   const int Ng = d.Ng;
   int t = (h * m) % Ng;
-  const int st = (4 * m) % Ng;
+  const int st = (KS_MG * m) % Ng;
   double sr = 0.0, si = 0.0;
-  for (int j = h; j < Ng; j += 4) {
+  for (int j = h; j < Ng; j += KS_MG) {
     const cplx e = ex[t];
     sr = fma(v[j], e.x, sr);
     si = fma(-v[j], e.y, si);
     t += st;
     if (t >= Ng) t -= Ng;
   }
-  return group_sum<4>(cmk(sr, si));
+  return group_sum<KS_MG>(cmk(sr, si));
 }
 
 // F(X) for X in LDS c; result fo[m] (LDS).  u: Ng doubles scratch.  Starts after a barrier
 // that made c visible; ends with a barrier.
 __device__ void ks_eval_F(const KsDev& d, const cplx* ex, const cplx* c, double* u, cplx* fo) {
-  for (int j = threadIdx.x; j < d.Ng; j += NTS) {
+  for (int e = threadIdx.x; e < 2 * d.Ng; e += NTS) {
+    const int j = e >> 1;
     double v, unused;
-    ks_grid_point(d, ex, c, 2.0, nullptr, 0.0, j, v, unused);
-    u[j] = v * v;
+    ks_grid_point(d, ex, c, 2.0, nullptr, 0.0, j, e & 1, v, unused);
+    if ((e & 1) == 0) u[j] = v * v;
   }
   __syncthreads();
   const double inv = 1.0 / d.Ng;
-  for (int e = threadIdx.x; e < 4 * d.K; e += NTS) {
-    const int m = e >> 2, h = e & 3;
+  for (int e = threadIdx.x; e < KS_MG * d.K; e += NTS) {
+    const int m = e / KS_MG, h = e % KS_MG;
     const cplx s = ks_mode_sum(d, ex, u, m, h);
     const double k = d.kx[m];
     // -1/2 i k (s / Ng)
@@ -156,14 +164,15 @@ __device__ void ks_F_vjp(const KsDev& d, const cplx* ex, const cplx* c, const cp
   }
   __syncthreads();
   const double inv = 1.0 / d.Ng;
-  for (int j = tid; j < d.Ng; j += NTS) {
+  for (int e = tid; e < 2 * d.Ng; e += NTS) {
+    const int j = e >> 1;
     double uj, rj;
-    ks_grid_point(d, ex, c, 2.0, sb, 1.0, j, uj, rj);
-    u[j] = 2.0 * uj * rj * inv;
+    ks_grid_point(d, ex, c, 2.0, sb, 1.0, j, e & 1, uj, rj);
+    if ((e & 1) == 0) u[j] = 2.0 * uj * rj * inv;
   }
   __syncthreads();
-  for (int e = tid; e < 4 * d.K; e += NTS) {
-    const int m = e >> 2, h = e & 3;
+  for (int e = tid; e < KS_MG * d.K; e += NTS) {
+    const int m = e / KS_MG, h = e % KS_MG;
     const cplx s = ks_mode_sum(d, ex, u, m, h);
     if (h == 0) xo[m] = cscale(s, m == 0 ? 1.0 : 2.0);
   }
