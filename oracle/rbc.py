@@ -294,6 +294,23 @@ class RBC:
         i = np.flatnonzero(ok)[np.argmin(np.abs(w[ok] - sigma))]
         return w[i], vr[:, i], vl[:, i]
 
+    def stability_vector_sensitivity(self, k, lam, X, Y):
+        """Eigenvector sensitivities (equ:eigenvector_sens, dM/dp = 0): for p = Ra and p = k the
+        solution z of (lambda M + L_s) z = -(M dlambda/dp + dL/dp) X with <X, z> = 0, which is
+        unique because the right-hand side is orthogonal to the adjoint eigenvector Y.  Solved
+        as the consistent stacked system [lambda M + L_s; X^H] z = [rhs; 0] (least squares, exact
+        here).  Returns the two vectors as columns."""
+        A = lam * self.M[k] + self.stability_operator()[k]
+        dRa, dk = self.stability_sensitivity(k, lam, X, Y)
+        dLRa, dLk = self.stability_dL(k)
+        out = []
+        for dl, dL in ((dRa, dLRa), (dk, dLk)):
+            rhs = -(dl * (self.M[k] @ X) + dL @ X)
+            Ab = np.vstack([A, X.conj()[None, :]])
+            z = np.linalg.lstsq(Ab, np.concatenate([rhs, [0.0]]), rcond=None)[0]
+            out.append(z)
+        return np.stack(out, axis=1)
+
     def stability_arnoldi(self, k, sigma, v0, m):
         """Several eigenvalues nearest the real shift sigma at once (Supplementary, "Eigenvalue
         problems": shift-invert about a target with a Krylov eigensolver): m steps of Arnoldi on

@@ -107,3 +107,35 @@ def test_arnoldi_leading_value_at_the_onset_has_zero_growth():
     lr, Xr, _ = P.stability_eig(1, 0.0)
     assert abs(lam[0] - lr) < 1e-12
     assert abs(abs(np.vdot(X[:, 0], Xr)) / np.linalg.norm(Xr) - 1.0) < 1e-10
+
+
+def normalized_eig(P, k, sigma, X0):
+    """Eigenvector nearest sigma scaled so that <X0, X> = <X0, X0>."""
+    lam, X, _ = P.stability_eig(k, sigma)
+    return lam, X * (np.vdot(X0, X0) / np.vdot(X0, X))
+
+
+def test_eigenvector_sensitivity_equals_central_differences():
+    """equ:eigenvector_sens with <X, dX/dp> = 0 is the derivative of the eigenvector normalized by
+    <X(p0), X(p)> = <X(p0), X(p0)>: central differences in Ra and in k agree, and z solves the
+    singular equation with a right-hand side orthogonal to Y."""
+    Ra, kx, h, hk = 1800.0, 2.8, 0.5, 1e-4
+    P, lam, X, Y = growth(Ra, k=kx)
+    X = X / np.linalg.norm(X)
+    Z = P.stability_vector_sensitivity(1, lam, X, Y)
+    A = lam * P.M[1] + P.stability_operator()[1]
+    dRa, dk = P.stability_sensitivity(1, lam, X, Y)
+    dLRa, dLk = P.stability_dL(1)
+    for i, (dl, dL) in enumerate(((dRa, dLRa), (dk, dLk))):
+        rhs = -(dl * (P.M[1] @ X) + dL @ X)
+        assert abs(np.vdot(Y, rhs)) < 1e-10 * np.linalg.norm(Y) * np.linalg.norm(rhs)
+        assert np.linalg.norm(A @ Z[:, i] - rhs) < 1e-9 * np.linalg.norm(rhs)
+        assert abs(np.vdot(X, Z[:, i])) < 1e-12 * np.linalg.norm(Z[:, i])
+    Xp = normalized_eig(problem(Ra + h, k=kx), 1, lam.real, X)[1]
+    Xm = normalized_eig(problem(Ra - h, k=kx), 1, lam.real, X)[1]
+    fd = (Xp - Xm) / (2 * h)
+    assert np.linalg.norm(fd - Z[:, 0]) < 1e-5 * np.linalg.norm(Z[:, 0])
+    Xp = normalized_eig(problem(Ra, k=kx + hk), 1, lam.real, X)[1]
+    Xm = normalized_eig(problem(Ra, k=kx - hk), 1, lam.real, X)[1]
+    fd = (Xp - Xm) / (2 * hk)
+    assert np.linalg.norm(fd - Z[:, 1]) < 1e-5 * np.linalg.norm(Z[:, 1])
