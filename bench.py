@@ -422,7 +422,8 @@ def stability_timing(iters=30):
     sigma M + L_s per wavenumber, `iters` inverse iterations for the right and the left
     eigenvector, the sensitivities), against the oracle's dense generalized eigensolve (left
     and right vectors, no sensitivities) of a sample of wavenumbers scaled to all 128; (b) the onset at k = 3.1163 (nz = 32) by Newton
-    steps on the growth rate with the adjoint sensitivity d lambda/dRa, from Ra = 1500; (c) the
+    steps on the growth rate with the adjoint sensitivity d lambda/dRa, from Ra = 1500; the
+    eigenvector sensitivities dX/dRa and dX/dk of all 128 wavenumbers (20 iterations); (c) the
     shift-invert Arnoldi on the same 128 wavenumbers (m = 32 steps, the 8 eigenvalues nearest 0
     with Ritz vectors and residuals), against the oracle's Arnoldi on a sample scaled to all
     128, with the count of converged pairs (residual below 1e-10 |nu|)."""
@@ -454,6 +455,15 @@ def stability_timing(iters=30):
         g, dg = lam_n[1].item(), dl_n[1, 0].item()
         Ra -= g.real / dg.real
     newton_s = time.perf_counter() - t0
+    # eigenvector sensitivities of all 128 wavenumbers (20 projected iterations per parameter)
+    G.stability_vector_sens(0.0, lam, X, Y, dl, iters=20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        G.stability_vector_sens(0.0, lam, X, Y, dl, iters=20)
+    torch.cuda.synchronize()
+    vsens_s = (time.perf_counter() - t0) / reps
+    G.sync()
     # (c) Arnoldi, several eigenvalues per shift
     m, nev = 32, 8
     G.stability_arnoldi(0.0, m=m, nev=nev)
@@ -480,7 +490,7 @@ def stability_timing(iters=30):
             "iterations": iters, "gpu_call_s": call_s, "gpu_us_per_wavenumber": call_s / (c["nx"] // 2) * 1e6,
             "oracle_cpu_eig_s_all_wavenumbers_extrapolated": ocpu, "speedup_vs_oracle": ocpu / call_s,
             "newton_onset_Ra": Ra, "newton_final_growth": g.real, "newton_5_solves_s": newton_s,
-            "arnoldi": arnoldi}
+            "eigenvector_sensitivities_s": vsens_s, "arnoldi": arnoldi}
 
 
 COU_CFG = dict(nx=128, ny=64, nz=64, Lx=4.0 * np.pi, Lz=2.0 * np.pi, Re=400.0, dt=0.01, nsteps=2000,

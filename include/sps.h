@@ -233,6 +233,20 @@ int sps_solve(sps_problem *P, const double *R, double *X, int adjoint);
  * and a third factor set are built on the first call.  SPS_E_UNSUPPORTED for other problems. */
 int sps_stability(sps_problem *P, double sigma, int iters, double *lam, double *X, double *Y, double *dlam);
 
+/* Eigenvector sensitivities (Supplementary, "Eigenvalue problems", equ:eigenvector_sens with
+ * dM/dp = 0): for p = Ra (at fixed Pr) and p = k, per wavenumber, the solution z of
+ * (lambda M + L_s) z = -(dlambda/dp M + dL/dp) X with <X, z> = 0 (unique, the right-hand side
+ * being orthogonal to Y).  lam, X, Y, dlam: the outputs of sps_stability with the same sigma
+ * (device arrays, read only).  z is found through one blocked LU of sigma M + L_s by `iters`
+ * iterations z <- P (sigma M + L_s)^-1 (r - (lambda - sigma) M z), P the spectral projector
+ * I - X (Y^H M .)/(Y^H M X), then z's component along X is removed; each iteration contracts
+ * the error by |lambda - sigma| / min_j |lambda_j - sigma| (the other eigenvalues lambda_j of the
+ * wavenumber), so a shift near the eigenvalue converges in a few iterations.  dX: device
+ * array [2][K][S] complex (p-major: dX/dRa of every wavenumber, then dX/dk).  The 2D problem;
+ * SPS_E_UNSUPPORTED otherwise. */
+int sps_stability_vector_sens(sps_problem *P, double sigma, int iters, const double *lam, const double *X,
+                              const double *Y, const double *dlam, double *dX);
+
 /* Several eigenvalues nearest the real shift sigma per wavenumber of the same stability problem
  * (Supplementary, "Eigenvalue problems": shift-invert about a target with a Krylov eigensolver):
  * m Arnoldi steps on B = (sigma M + L_s)^-1 M through one blocked LU of sigma M + L_s, each

@@ -168,6 +168,11 @@ int sps_stability(sps_problem* P, double sigma, int iters, double* lam, double* 
   return guard(P, [&](sps::ProblemImpl& p) { p.stability(sigma, iters, lam, X, Y, dlam); });
 }
 
+int sps_stability_vector_sens(sps_problem* P, double sigma, int iters, const double* lam, const double* X,
+                              const double* Y, const double* dlam, double* dX) {
+  return guard(P, [&](sps::ProblemImpl& p) { p.stability_vector_sens(sigma, iters, lam, X, Y, dlam, dX); });
+}
+
 int sps_stability_arnoldi(sps_problem* P, double sigma, int m, int nev, const double* v0, double* lam, double* X,
                           double* res, double* H) {
   return guard(P, [&](sps::ProblemImpl& p) { p.stability_arnoldi(sigma, m, nev, v0, lam, X, res, H); });

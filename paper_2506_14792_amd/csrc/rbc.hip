@@ -1226,6 +1226,77 @@ __global__ void __launch_bounds__(NT) rbc_evp_sens(RbcDev d, const cplx* X, cons
   }
 }
 
+// Eigenvector sensitivities (equ:eigenvector_sens, dM/dp = 0): z with (lambda M + L_s) z = r,
+// r = -(dlambda/dp M + dL/dp) X, and <X, z> = 0, through the factors of A = sigma M + L_s:
+// z <- P A^-1 (r - (lambda - sigma) M z), P = I - X (Y^H M .) / (Y^H M X) the spectral projector
+// that removes the eigenvector (M^H Y is proportional to the left eigenvector of A^-1 M, and
+// Y^H r = 0 makes the fixed point a solution); the iteration contracts by
+// |lambda - sigma| / min_j |lambda_j - sigma| over the other eigenvalues.  Finally z loses its
+// component along X.
+
+// R = -(dlam[k][p] M X + dL/dp X) per wavenumber, p = 0 (Ra, via dnu and dka) or 1 (k); the
+// rows as in rbc_evp_sens.
+__global__ void __launch_bounds__(NT) rbc_evp_dlx(RbcDev d, const cplx* X, const cplx* dlam, int p, double dnu,
+                                                  double dka, cplx* R) {
+  const int k = blockIdx.x, N = d.N, S = d.S;
+  const cplx* xk = X + (size_t)k * S;
+  const double kx = d.kx[k], k2 = kx * kx;
+  const cplx dl = dlam[2 * k + p];
+  for (int s = threadIdx.x; s < S; s += NT) {
+    cplx v = czero();
+    if (s < 3 * N) {
+      const int f = s / N, n = s - f * N;
+      const cplx* c = xk + f * N;
+      const double dif = (f == 2) ? d.ka : d.nu, ddif = (f == 2) ? dka : dnu;
+      const cplx sc = s10_at(c, n, N);
+      if (p == 0) {
+        v = cscale(cadd(cscale(dzz_at(c, n, N), -1.0), cscale(sc, k2)), ddif);
+        if (n == N - 2) v = csub(v, cscale(xk[4 * N + f], 4.0 * ddif));
+      } else {
+        v = cscale(sc, 2.0 * kx * dif);
+        if (f == 0) v = cadd(v, cmul_i(s10_at(xk + 3 * N, n, N)));
+      }
+      v = cadd(v, cmul(dl, sc));
+    } else if (s < 4 * N && p == 1) {
+      v = cmul_i(s0_at(xk, s - 3 * N, N));
+    }
+    R[(size_t)k * S + s] = cscale(v, -1.0);
+  }
+}
+
+// W = R - (lam[k] - sigma) MZ per wavenumber.
+__global__ void __launch_bounds__(NT) rbc_vs_combine(RbcDev d, const cplx* R, const cplx* MZ, const cplx* lam,
+                                                     double sigma, cplx* W) {
+  const int k = blockIdx.x, S = d.S;
+  const cplx c = cmk(lam[k].x - sigma, lam[k].y);
+  for (int s = threadIdx.x; s < S; s += NT) {
+    const size_t e = (size_t)k * S + s;
+    W[e] = csub(R[e], cmul(c, MZ[e]));
+  }
+}
+
+// Z -= X <Q, Z> / <Q, X> per wavenumber (complex inner products <a, b> = sum conj(a) b): the
+// spectral projection with Q = M^H Y, or the orthogonal one with Q = X.
+__global__ void __launch_bounds__(NT) rbc_vs_project(RbcDev d, cplx* Z, const cplx* X, const cplx* Q) {
+  __shared__ double red[4][NT];
+  const int k = blockIdx.x, S = d.S;
+  cplx* zk = Z + (size_t)k * S;
+  const cplx* xk = X + (size_t)k * S;
+  const cplx* qk = Q + (size_t)k * S;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int s = threadIdx.x; s < S; s += NT) {
+    const cplx q = qk[s], z = zk[s], x = xk[s];
+    v[0] += q.x * z.x + q.y * z.y;
+    v[1] += q.x * z.y - q.y * z.x;
+    v[2] += q.x * x.x + q.y * x.y;
+    v[3] += q.x * x.y - q.y * x.x;
+  }
+  block_sums<4>(v, red);
+  const double m2 = v[2] * v[2] + v[3] * v[3];
+  const cplx a = m2 > 0.0 ? cmk((v[0] * v[2] + v[1] * v[3]) / m2, (v[1] * v[2] - v[0] * v[3]) / m2) : czero();
+  for (int s = threadIdx.x; s < S; s += NT) zk[s] = csub(zk[s], cmul(a, xk[s]));
+}
+
 // ---------------------------------------------------------------------------- shift-invert Arnoldi
 // Several eigenvalues nearest a real shift per wavenumber (Supplementary, "Eigenvalue
 // problems": a Krylov eigensolver on the shift-inverted pencil).  m Arnoldi steps on
@@ -2167,8 +2238,12 @@ class RbcProblem : public ProblemImpl {
   void evp_apply(const RbcDev& de, const cplx* x, cplx* y) {
     hipLaunchKernelGGL(rbc_apply_m, dim3(K_), dim3(NT), 0, stream, de, x, ework_);
     SPS_CHECK_LAUNCH();
+    evp_solve(de, ework_, y);
+  }
+  // y = (sigma M + L_s)^-1 r
+  void evp_solve(const RbcDev& de, const cplx* r, cplx* y) {
     KfArgs a{};
-    a.X0 = ework_;
+    a.X0 = r;
     a.Xout = y;
     a.nl = nl_;
     a.F0 = F0_;
@@ -2209,6 +2284,44 @@ class RbcProblem : public ProblemImpl {
     hipLaunchKernelGGL(rbc_evp_sens, dim3(K_), dim3(NT), 0, stream, de, x, y, -0.5 * nu_ / Ra, -0.5 * ka_ / Ra,
                        reinterpret_cast<cplx*>(dlam));
     SPS_CHECK_LAUNCH();
+  }
+
+  void stability_vector_sens(double sigma, int iters, const double* lam, const double* X, const double* Y,
+                             const double* dlam, double* dX) override {
+    if (cou_) throw Error(SPS_E_UNSUPPORTED, "the eigenvalue problem is built for the 2D problem");
+    SPS_REQUIRE(lam && X && Y && dlam && dX, "null argument");
+    SPS_REQUIRE(iters >= 1 && iters <= 10000, "iters must be in [1, 10000]");
+    const RbcDev de = evp_setup(sigma);
+    if (!vsR_) {
+      vsR_ = arena_.alloc<cplx>((size_t)K_ * S_);
+      vsW_ = arena_.alloc<cplx>((size_t)K_ * S_);
+      vsQ_ = arena_.alloc<cplx>((size_t)K_ * S_);
+    }
+    const cplx* x = reinterpret_cast<const cplx*>(X);
+    const cplx* l = reinterpret_cast<const cplx*>(lam);
+    hipLaunchKernelGGL(rbc_lbvp_rhs_adj, dim3(K_), dim3(NT), 0, stream, de, reinterpret_cast<const cplx*>(Y), vsQ_);
+    SPS_CHECK_LAUNCH();   // Q = M^H Y
+    const double Ra = desc_.param0;
+    for (int p = 0; p < 2; ++p) {
+      cplx* z = reinterpret_cast<cplx*>(dX) + (size_t)p * K_ * S_;
+      hipLaunchKernelGGL(rbc_evp_dlx, dim3(K_), dim3(NT), 0, stream, de, x, reinterpret_cast<const cplx*>(dlam), p,
+                         -0.5 * nu_ / Ra, -0.5 * ka_ / Ra, vsR_);
+      SPS_CHECK_LAUNCH();
+      evp_solve(de, vsR_, z);
+      hipLaunchKernelGGL(rbc_vs_project, dim3(K_), dim3(NT), 0, stream, de, z, x, vsQ_);
+      SPS_CHECK_LAUNCH();
+      for (int it = 1; it < iters; ++it) {
+        hipLaunchKernelGGL(rbc_apply_m, dim3(K_), dim3(NT), 0, stream, de, z, ework_);
+        SPS_CHECK_LAUNCH();
+        hipLaunchKernelGGL(rbc_vs_combine, dim3(K_), dim3(NT), 0, stream, de, vsR_, ework_, l, sigma, vsW_);
+        SPS_CHECK_LAUNCH();
+        evp_solve(de, vsW_, z);
+        hipLaunchKernelGGL(rbc_vs_project, dim3(K_), dim3(NT), 0, stream, de, z, x, vsQ_);
+        SPS_CHECK_LAUNCH();
+      }
+      hipLaunchKernelGGL(rbc_vs_project, dim3(K_), dim3(NT), 0, stream, de, z, x, x);
+      SPS_CHECK_LAUNCH();
+    }
   }
 
   void stability_arnoldi(double sigma, int m, int nev, const double* v0, double* lam, double* X, double* res,
@@ -2831,6 +2944,7 @@ class RbcProblem : public ProblemImpl {
   double* lops_ = nullptr;   // LU block operators of L alone (boundary value problem), built on first use
   double *eBM_ = nullptr, *eBL_ = nullptr, *eops_ = nullptr;   // stability operator bands and factors
   cplx *aV_ = nullptr, *aH_ = nullptr, *aZ_ = nullptr, *aY_ = nullptr;   // Arnoldi basis, Hessenberg, work
+  cplx *vsR_ = nullptr, *vsW_ = nullptr, *vsQ_ = nullptr;   // eigenvector sensitivities: rhs, work, M^H Y
   cplx *ework_ = nullptr, *estart_ = nullptr;
   int ekl_ = 0, eku_ = 0;
   cplx* lrhs_ = nullptr;

@@ -128,6 +128,10 @@ class ProblemImpl {
   virtual void stability(double, int, double*, double*, double*, double*) {
     throw Error(SPS_E_UNSUPPORTED, "the eigenvalue problem is built for the 2D problem");
   }
+  virtual void stability_vector_sens(double, int, const double*, const double*, const double*, const double*,
+                                     double*) {
+    throw Error(SPS_E_UNSUPPORTED, "the eigenvalue problem is built for the 2D problem");
+  }
   virtual void stability_arnoldi(double, int, int, const double*, double*, double*, double*, double*) {
     throw Error(SPS_E_UNSUPPORTED, "the eigenvalue problem is built for the 2D problem");
   }

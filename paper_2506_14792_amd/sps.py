@@ -57,6 +57,7 @@ def lib():
         "sps_set_dt": (ctypes.c_int, [_P, ctypes.c_double]),
         "sps_set_checkpoint_file": (ctypes.c_int, [_P, ctypes.c_char_p]),
         "sps_stability": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int, _D, _D, _D, _D]),
+        "sps_stability_vector_sens": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int, _D, _D, _D, _D, _D]),
         "sps_stability_arnoldi": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int, ctypes.c_int, _D, _D, _D, _D,
                                                  _D]),
         "sps_set_timesteps": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.c_int]),
@@ -221,6 +222,18 @@ class Problem:
                                    _ptr(dlam)))
         c = lambda t, *shape: torch.view_as_complex(t.view(*shape, 2))
         return c(lam, K), c(X, K, S), c(Y, K, S), c(dlam, K, 2)
+
+    def stability_vector_sens(self, sigma, lam, X, Y, dlam, iters=20):
+        """Eigenvector sensitivities dX/dRa and dX/dk (<X, dX> = 0) from the outputs of
+        stability(sigma): complex CUDA tensor [2, K, S]."""
+        import torch
+        S = 4 * self.desc.nz + 7
+        K = self.n // (2 * S)
+        dX = torch.zeros(2 * self.n, dtype=torch.float64, device="cuda")
+        args = [torch.view_as_real(t.to(torch.complex128).contiguous()).reshape(-1) for t in (lam, X, Y, dlam)]
+        _check(lib().sps_stability_vector_sens(self._h, float(sigma), int(iters), *[_ptr(a) for a in args],
+                                               _ptr(dX)))
+        return torch.view_as_complex(dX.view(2, K, S, 2))
 
     def stability_arnoldi(self, sigma=0.0, m=24, nev=4, v0=None, want_vectors=True, want_H=False):
         """The nev eigenvalues nearest sigma of every wavenumber by shift-invert Arnoldi with m

@@ -167,3 +167,34 @@ def test_arnoldi_arguments():
     with pytest.raises(sps.SpsError) as e:
         Gk.stability_arnoldi(0.0, m=8, nev=2)
     assert e.value.code == -7
+
+
+@pytest.mark.parametrize("Ra,sigma", [(RAC, 0.0), (5000.0, 0.27)], ids=["onset", "unstable"])
+def test_eigenvector_sensitivities_vs_oracle(Ra, sigma):
+    """equ:eigenvector_sens on the GPU (sps_stability_vector_sens, 60 projected iterations
+    through the factors of sigma M + L_s) against the oracle's direct solution of the singular
+    system with the same eigenvector X (the GPU's, so both use one normalization), on every
+    wavenumber whose contraction factor |lambda - sigma| / min_j |lambda_j - sigma| (dense
+    eigenvalues) is below 1/2."""
+    import scipy.linalg as sla
+    note(f"eigenvector sensitivities Ra = {Ra}, sigma = {sigma}")
+    P, G = build(Ra)
+    lam, X, Y, dl = G.stability(sigma, iters=60)
+    dX = G.stability_vector_sens(sigma, lam, X, Y, dl, iters=60)
+    G.sync()
+    lam, X, dX = lam.cpu().numpy(), X.cpu().numpy(), dX.cpu().numpy()
+    checked = 0
+    for k in range(1, P.K):
+        w = sla.eig(P.stability_operator()[k], -P.M[k], right=False)
+        w = np.sort_complex(w[np.isfinite(w)])
+        i0 = np.argmin(np.abs(w - lam[k]))
+        q = abs(lam[k] - sigma) / np.min(np.abs(np.delete(w, i0) - sigma))
+        lr, _, Yr = P.stability_eig(k, sigma)
+        Z = P.stability_vector_sensitivity(k, lr, X[k], Yr)
+        e = [np.linalg.norm(dX[p, k] - Z[:, p]) / np.linalg.norm(Z[:, p]) for p in range(2)]
+        note(f"  k {k}: contraction {q:.2e}, dX/dRa rel {e[0]:.1e}, dX/dk rel {e[1]:.1e}, "
+             f"<X, dX> {abs(np.vdot(X[k], dX[0, k])):.1e}")
+        if q < 0.5:
+            assert max(e) < 1e-9
+            checked += 1
+    assert checked >= 1
