@@ -403,6 +403,12 @@ def ckpt_timing(slot_counts=(5, 10, 20, 50)):
         out[f"two_level_{slots}"] = {"gradient_s": timed(), "forward_steps": n + (n // ce) * seg_steps,
                                      "stored_MB": slots * state_mb + 2 * stage_mb,
                                      "host_stored_MB": (n // ce) * state_mb}
+    # nested: 4 outer (host) states for the 20 segment starts, 8 device slots
+    G.set_checkpointing(sps.CKPT_TWO_LEVEL, 8)
+    G.set_outer_slots(4)
+    out["nested_4_outer_8_device"] = {"gradient_s": timed(), "host_stored_MB": 4 * state_mb,
+                                      "stored_MB": 8 * state_mb + 2 * stage_mb}
+    G.set_outer_slots(0)
     # the disk level: the same segment starts in a file instead of host memory (8 slots)
     import tempfile
     with tempfile.TemporaryDirectory() as tmp:

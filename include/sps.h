@@ -304,7 +304,10 @@ int sps_set_timesteps(sps_problem *P, const double *dts, int n);
  * back from the last and reverses each with the binomial schedule of its length on `slots`
  * device states (sps_gradient then runs eagerly, also in graph mode).  Gradients are the same
  * as with the default schedule.  Device memory: `slots` states (K S complex values each);
- * host memory (two levels): ceil(max_steps / checkpoint_every) states; held until sps_destroy.  Drops recorded graphs and the recorded forward run
+ * host memory (two levels): ceil(max_steps / checkpoint_every) states, or the outer slot count
+ * of sps_set_outer_slots when smaller; held until sps_destroy.  With SPS_CKPT_BINOMIAL the reverse
+ * sweep reuses the snapshot slots, so a recorded run is reversed once (a second
+ * sps_adjoint_step returns SPS_E_STATE).  Drops recorded graphs and the recorded forward run
  * (sps_adjoint_step needs a new sps_step).  The 2D and plane Couette problems;
  * SPS_E_UNSUPPORTED otherwise. */
 enum sps_checkpointing { SPS_CKPT_UNIFORM = 0, SPS_CKPT_BINOMIAL = 1, SPS_CKPT_TWO_LEVEL = 2 };
@@ -321,6 +324,20 @@ int sps_set_checkpointing(sps_problem *P, int scheme, int slots);
  * path = NULL returns to pinned host memory.  Drops the recorded forward run.  File errors
  * return SPS_E_IO.  The 2D problem and plane Couette; SPS_E_UNSUPPORTED otherwise. */
 int sps_set_checkpoint_file(sps_problem *P, const char *path);
+
+/* Number of outer-level states (pinned host memory, or the checkpoint file) of the
+ * SPS_CKPT_TWO_LEVEL schedule.  0 (the default): one per segment of checkpoint_every steps.
+ * 1 <= slots < the number of segments of a run: nested binomial checkpointing (Supplementary,
+ * "Initial value problems": multi-level schedules that trade storage on each level for
+ * recomputation) - the segment starts are placed on the outer slots by the binomial schedule
+ * over segments (slot 0 holds X_0; segments are recomputed from earlier stored starts), and
+ * each segment is reversed with the binomial schedule of its length on the device slots.  With
+ * a file the outer accesses are synchronous (each waits for its copy).  Gradients are
+ * bit-identical to the other schedules.  As with SPS_CKPT_BINOMIAL, the reverse sweep reuses
+ * the stored states, so a recorded run is reversed once (a second sps_adjoint_step returns
+ * SPS_E_STATE).  Drops the recorded forward run.  The 2D problem and
+ * plane Couette; SPS_E_UNSUPPORTED otherwise. */
+int sps_set_outer_slots(sps_problem *P, int slots);
 
 /* The binomial schedule for nsteps steps and `slots` stored states (host arrays; no problem
  * or device needed): phase 0 the forward sweep, phase 1 the reverse sweep.  Writes *count

@@ -190,6 +190,10 @@ int sps_set_checkpointing(sps_problem* P, int scheme, int slots) {
   return guard(P, [&](sps::ProblemImpl& p) { p.set_checkpointing(scheme, slots); });
 }
 
+int sps_set_outer_slots(sps_problem* P, int slots) {
+  return guard(P, [&](sps::ProblemImpl& p) { p.set_outer_slots(slots); });
+}
+
 int sps_set_checkpoint_file(sps_problem* P, const char* path) {
   return guard(P, [&](sps::ProblemImpl& p) { p.set_checkpoint_file(path); });
 }

@@ -2075,12 +2075,12 @@ class RbcProblem : public ProblemImpl {
       for (const auto& g : graphs_)
         if (g.first == key) {
           SPS_HIP(hipGraphLaunch(g.second, stream));
-          tape_steps_ = nsteps;
+          tape_steps_ = ckpt_mode_ == SPS_CKPT_BINOMIAL ? -1 : nsteps;
           return;
         }
       graphs_.emplace_back(key, capture_gradient(X0, nsteps, XN, dJdX0, J));
       SPS_HIP(hipGraphLaunch(graphs_.back().second, stream));
-      tape_steps_ = nsteps;
+      tape_steps_ = ckpt_mode_ == SPS_CKPT_BINOMIAL ? -1 : nsteps;
       return;
     }
     gradient_launches(X0, nsteps, XN, dJdX0, J);
@@ -2697,15 +2697,83 @@ class RbcProblem : public ProblemImpl {
     bool first = true;
     run_reverse_actions(Xbar, schedule(nsteps).second, first);
     finish_reverse(Xbar);
+    tape_steps_ = -1;   // the reverse sweep reused the snapshot slots: the run is reversed once
   }
   // Two levels: the state at the start of every segment of checkpoint_every steps goes to
   // pinned host memory during the forward sweep; the reverse sweep brings the segments back
   // from the last, and reverses each with the binomial schedule of its length on the device
   // slots (the segment's own forward actions first, then its turns).
   int seg_len(int g, int nsteps) const { return std::min(desc_.checkpoint_every, nsteps - g * desc_.checkpoint_every); }
+  // Nested schedule (outer slots fewer than the segments): the segment starts are placed by the
+  // binomial schedule over segments on the outer slots; each outer turn reverses its segment
+  // with the binomial schedule of the segment on the device slots.
+  bool nested(int nseg) const { return outer_slots_ > 0 && outer_slots_ < nseg; }
+  int seg_start(int g, int nsteps) const { return std::min(g * desc_.checkpoint_every, nsteps); }
+  const std::pair<std::vector<CkptAction>, std::vector<CkptAction>>& outer_schedule(int nseg) {
+    auto it = osched_.find(nseg);
+    if (it == osched_.end()) {
+      std::pair<std::vector<CkptAction>, std::vector<CkptAction>> sc;
+      binomial_schedule(nseg, outer_slots_, sc.first, sc.second);
+      it = osched_.emplace(nseg, std::move(sc)).first;
+    }
+    return it->second;
+  }
+  // outer slot i <-> device state (host memory: stream-ordered copies; file: staged through
+  // buffer 0 with the stream synchronized around each file access)
+  void outer_store(int i, const cplx* src) {
+    if (ckfd_ < 0) {
+      copy_state(host_ckpt_.get() + (size_t)i * K_ * S_, src);
+      return;
+    }
+    copy_state(ckstage_.get(), src);
+    SPS_HIP(hipStreamSynchronize(stream));
+    file_io(true, 0, i);
+  }
+  void outer_load(int i, cplx* dst) {
+    if (ckfd_ < 0) {
+      copy_state(dst, host_ckpt_.get() + (size_t)i * K_ * S_);
+      return;
+    }
+    SPS_HIP(hipStreamSynchronize(stream));   // staging buffer 0 free
+    file_io(false, 0, i);
+    copy_state(dst, ckstage_.get());
+  }
+  void forward_nested(cplx* X, int nsteps, int nseg) {
+    for (const CkptAction& c : outer_schedule(nseg).first) {
+      if (c.op == CK_TAKESHOT) outer_store(c.a, X);
+      else if (c.op == CK_ADVANCE) advance(X, seg_start(c.a, nsteps), seg_start(c.b, nsteps));
+    }
+    if (ckfd_ >= 0) SPS_HIP(hipStreamSynchronize(stream));
+  }
+  void reverse_nested(cplx* Xbar, int nsteps, int nseg) {
+    if (!Xo_) Xo_ = arena_.alloc<cplx>((size_t)K_ * S_);
+    bool first = true;
+    for (const CkptAction& c : outer_schedule(nseg).second) {
+      switch (c.op) {
+        case CK_RESTORE: outer_load(c.a, Xo_); break;
+        case CK_TAKESHOT: outer_store(c.a, Xo_); break;
+        case CK_ADVANCE: advance(Xo_, seg_start(c.a, nsteps), seg_start(c.b, nsteps)); break;
+        case CK_YOUTURN: {
+          // the working state holds the start of segment c.a; the schedule restores before
+          // it uses the working state again
+          const auto& sc = schedule(seg_len(c.a, nsteps));
+          copy_state(Xs_, Xo_);
+          run_forward_actions(Xs_, sc.first, false);
+          run_reverse_actions(Xbar, sc.second, first);
+          break;
+        }
+        default: throw Error(SPS_E_STATE, "bad checkpoint action");
+      }
+    }
+    finish_reverse(Xbar);
+    tape_steps_ = -1;   // the outer slots were reused: the run is reversed once
+  }
+
   void forward_two_level(cplx* X, int nsteps) {
     const int ce = desc_.checkpoint_every, nseg = (nsteps + ce - 1) / ce;
-    if (ckfd_ >= 0) {
+    if (nested(nseg)) {
+      forward_nested(X, nsteps, nseg);
+    } else if (ckfd_ >= 0) {
       forward_disk(X, nsteps, nseg);
     } else {
       for (int g = 0; g < nseg; ++g) {
@@ -2717,6 +2785,10 @@ class RbcProblem : public ProblemImpl {
   }
   void reverse_two_level(cplx* Xbar, int nsteps) {
     const int ce = desc_.checkpoint_every, nseg = (nsteps + ce - 1) / ce;
+    if (nested(nseg)) {
+      reverse_nested(Xbar, nsteps, nseg);
+      return;
+    }
     bool first = true;
     // disk level: a host-to-device copy from staging buffer b may be in flight (also from an
     // earlier reverse sweep of the same run; waiting on an event never recorded returns at once)
@@ -2771,12 +2843,18 @@ class RbcProblem : public ProblemImpl {
       done += (size_t)r;
     }
   }
+  // pinned host states of the outer level: one per segment of the longest run, or the outer
+  // slot count when that is smaller
   void alloc_host_ckpt() {
-    if (host_ckpt_) return;
     const int nseg = (desc_.max_steps + desc_.checkpoint_every - 1) / desc_.checkpoint_every;
+    const int need = outer_slots_ > 0 ? std::min(outer_slots_, nseg) : nseg;
+    if (host_ckpt_ && host_cap_ >= need) return;
+    if (host_ckpt_) SPS_HIP(hipStreamSynchronize(stream));
+    host_ckpt_.reset();
     void* p = nullptr;
-    SPS_HIP(hipHostMalloc(&p, sizeof(cplx) * K_ * S_ * (size_t)nseg, hipHostMallocDefault));
+    SPS_HIP(hipHostMalloc(&p, sizeof(cplx) * K_ * S_ * (size_t)need, hipHostMallocDefault));
     host_ckpt_.reset(reinterpret_cast<cplx*>(p));
+    host_cap_ = need;
   }
   void close_ckpt_file() {
     if (ckfd_ < 0) return;
@@ -2809,6 +2887,16 @@ class RbcProblem : public ProblemImpl {
       for (auto& e : ckev_) SPS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     }
     host_ckpt_.reset();
+    host_cap_ = 0;
+  }
+  void set_outer_slots(int slots) override {
+    SPS_REQUIRE(slots >= 0, "outer slots must be >= 0");
+    drop_graphs();
+    SPS_HIP(hipStreamSynchronize(stream));
+    outer_slots_ = slots;
+    osched_.clear();
+    tape_steps_ = -1;
+    if (ckpt_mode_ == SPS_CKPT_TWO_LEVEL && ckfd_ < 0) alloc_host_ckpt();
   }
 
  private:
@@ -2968,6 +3056,10 @@ class RbcProblem : public ProblemImpl {
   };
   std::unique_ptr<cplx, HostFree> host_ckpt_;   // two-level: segment start states in pinned host memory
   std::unique_ptr<cplx, HostFree> ckstage_;     // disk level: two pinned staging buffers
+  int host_cap_ = 0;                            // states held by host_ckpt_
+  int outer_slots_ = 0;                         // outer-level slots (0: one per segment)
+  std::map<int, std::pair<std::vector<CkptAction>, std::vector<CkptAction>>> osched_;
+  cplx* Xo_ = nullptr;                          // working state of the nested outer schedule
   hipEvent_t ckev_[2] = {nullptr, nullptr};
   int ckfd_ = -1;                               // disk level: the checkpoint file, or -1
   std::string ckpath_;

@@ -56,6 +56,7 @@ def lib():
         "sps_solve": (ctypes.c_int, [_P, _D, _D, ctypes.c_int]),
         "sps_set_dt": (ctypes.c_int, [_P, ctypes.c_double]),
         "sps_set_checkpoint_file": (ctypes.c_int, [_P, ctypes.c_char_p]),
+        "sps_set_outer_slots": (ctypes.c_int, [_P, ctypes.c_int]),
         "sps_stability": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int, _D, _D, _D, _D]),
         "sps_stability_vector_sens": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int, _D, _D, _D, _D, _D]),
         "sps_stability_arnoldi": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int, ctypes.c_int, _D, _D, _D, _D,
@@ -255,6 +256,11 @@ class Problem:
                                            _ptr(res), _ptr(H)))
         c = lambda t, *shape: None if t is None else torch.view_as_complex(t.view(*shape, 2))
         return c(lam, K, nev), c(X, K, nev, S), res.view(K, nev), c(H, K, m + 1, m)
+
+    def set_outer_slots(self, slots):
+        """Outer-level states of CKPT_TWO_LEVEL (0: one per segment; fewer: nested binomial)."""
+        _check(lib().sps_set_outer_slots(self._h, int(slots)))
+        self.tape_id += 1
 
     def set_checkpoint_file(self, path):
         """Disk level of CKPT_TWO_LEVEL: segment starts in this file (created, removed with the

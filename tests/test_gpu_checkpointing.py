@@ -85,6 +85,9 @@ def test_binomial_step_adjoint_step_and_graph():
     G.adjoint_step(dJ, n)
     G.sync()
     assert torch.equal(X, ref[0]) and torch.equal(dJ, ref[1])
+    with pytest.raises(sps.SpsError) as e:   # the snapshot slots were reused by the reverse sweep
+        G.adjoint_step(dJ, n)
+    assert e.value.code == -6
     G.set_graph(True)
     for rep in range(3):
         got = grad(G, X0, n)
@@ -249,3 +252,61 @@ def test_disk_level_unsupported_for_multistep_problems(tmp_path):
     with pytest.raises(sps.SpsError) as e:
         G.set_checkpoint_file(tmp_path / "x.bin")
     assert e.value.code == -7
+
+
+def test_nested_outer_slots_equal_uniform(tmp_path):
+    """Nested binomial checkpointing (sps_set_outer_slots below the segment count): segment
+    starts placed on 1-6 outer slots by the binomial schedule over segments, each segment
+    reversed on 1-2 device slots; bit-identical gradients at 24x16 (13 steps in 7 segments of 2)
+    in host memory and in a file (with step + adjoint_step; a second reverse sweep of the run is
+    refused), and at 256x64 x 1000 steps (20
+    segments on 4 outer and 5 device slots, host memory and file)."""
+    n, ce = 13, 2
+    note(f"nested two-level vs uniform, 24x16, {n} steps, segments of {ce}")
+    P, G, X0h = small_problem(n, ce)
+    X0 = to_dev(X0h)
+    ref = grad(G, X0, n)
+    for slots in (1, 2):
+        G.set_checkpointing(sps.CKPT_TWO_LEVEL, slots)
+        for outer in (1, 2, 3, 6):
+            G.set_outer_slots(outer)
+            got = grad(G, X0, n)
+            same = all(torch.equal(a, b) for a, b in zip(got, ref))
+            note(f"  device slots {slots}, outer slots {outer}: identical {same}")
+            assert same
+    G.set_checkpoint_file(tmp_path / "nested_small.bin")
+    for outer in (1, 3):
+        G.set_outer_slots(outer)
+        assert all(torch.equal(a, b) for a, b in zip(grad(G, X0, n), ref)), outer
+    X = X0.clone()
+    G.step(X, n)
+    dJ = torch.zeros_like(X)
+    G.cost(X, None, dJ)
+    G.adjoint_step(dJ, n)
+    G.sync()
+    assert torch.equal(X, ref[0]) and torch.equal(dJ, ref[1])
+    with pytest.raises(sps.SpsError) as e:   # the outer slots were reused by the reverse sweep
+        G.adjoint_step(dJ, n)
+    assert e.value.code == -6
+    G.set_checkpoint_file(None)
+    G.set_outer_slots(0)
+    assert all(torch.equal(a, b) for a, b in zip(grad(G, X0, n), ref))
+    with pytest.raises(sps.SpsError) as e:
+        G.set_outer_slots(-1)
+    assert e.value.code == -1
+
+    note("nested two-level vs uniform, 256x64, 1000 steps, 4 outer and 5 device slots")
+    nx, nz, lx, Ra, Pr, dt = FULL
+    nf = 1000
+    Gf = sps.Problem(sps.RBC2D, nx, nz, lx, Ra, Pr, 1.5, dt, 50, nf)
+    b0 = torch.from_numpy(wl.rbc_b0(seed=0, Nx=nx, Nz=nz).ravel().copy()).cuda()
+    Xf = torch.zeros(Gf.n, dtype=torch.float64, device="cuda")
+    Gf.initial_state(b0, Xf)
+    reff = grad(Gf, Xf, nf)
+    Gf.set_checkpointing(sps.CKPT_TWO_LEVEL, 5)
+    Gf.set_outer_slots(4)
+    same = all(torch.equal(a, b) for a, b in zip(grad(Gf, Xf, nf), reff))
+    Gf.set_checkpoint_file(tmp_path / "nested_full.bin")
+    same_file = all(torch.equal(a, b) for a, b in zip(grad(Gf, Xf, nf), reff))
+    note(f"  identical: host {same}, file {same_file}")
+    assert same and same_file
