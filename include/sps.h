@@ -274,7 +274,8 @@ int sps_stability_arnoldi(sps_problem *P, double sigma, int m, int nev, const do
  * captured graphs: the reverse sweep of a segment runs with that segment's step, so a gradient
  * through a run with step changes reverses the segments one by one, each after sps_set_dt of
  * its own step and a recomputation of its forward sweep.  sps_solve then uses the new matrix.
- * SPS_E_ARG for dt <= 0 or not finite; SPS_E_UNSUPPORTED for the batched problems. */
+ * The batched Swift-Hohenberg and Kolmogorov problems take it in their SBDF2 coefficients (their
+ * implicit operators are diagonal).  SPS_E_ARG for dt <= 0 or not finite. */
 int sps_set_dt(sps_problem *P, double dt);
 
 /* Variable time steps of the multistep schemes (equ:imex: the coefficients of step n depend on

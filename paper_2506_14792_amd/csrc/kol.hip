@@ -502,6 +502,13 @@ class KolProblem : public ProblemImpl {
   }
 
   long long state_size() const override { return 2 * st_; }
+  // a new step for the following runs: the SBDF2 coefficients take it (diagonal implicit
+  // operator); drops the recorded run
+  void set_dt(double dt) override {
+    SPS_REQUIRE(std::isfinite(dt) && dt > 0.0, "dt must be positive");
+    d_.dt = dt;
+    tape_ = -1;
+  }
   void factor() override {}
 
   void set_params(const double* theta) {

@@ -619,6 +619,14 @@ class ShProblem : public ProblemImpl {
   }
 
   long long state_size() const override { return 2 * state_cplx_; }
+  // a new step for the following runs: the SBDF2 coefficients take it (the implicit operator is
+  // diagonal, nothing is factored); drops the recorded run
+  void set_dt(double dt) override {
+    SPS_REQUIRE(std::isfinite(dt) && dt > 0.0, "dt must be positive");
+    dt_ = dt;
+    dv_.dt = dt;
+    tape_steps_ = -1;
+  }
   void factor() override {}
 
   void step(double* X, int nsteps) override {

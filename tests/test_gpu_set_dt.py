@@ -5,7 +5,8 @@ two segments with different steps, and the gradient through it by torch.autograd
 its forward sweep), match the oracle's chained RK222 sweeps and adjoints (1e-11) at 24x16 and
 the full 256x64 configuration (Taylor remainder rate 2 there); returning to a step gives runs
 bit-identical to a problem built with it, for the 2D problem and plane Couette; KS takes the new
-step in its SBDF rows and RK stages."""
+step in its SBDF rows and RK stages; the batched Swift-Hohenberg and Kolmogorov problems in their
+SBDF2 coefficients."""
 import sys
 
 import numpy as np
@@ -178,8 +179,42 @@ def test_set_dt_arguments():
         with pytest.raises(sps.SpsError) as e:
             G.set_dt(bad)
         assert e.value.code == -1
-    sizes, rs, _ = wl.sh_batch(seed=0, batch=2, sizes=(64,))
-    B = sps.ShBatch(sizes, rs, 16.0 * np.pi, 0.02, max_steps=2)
-    with pytest.raises(sps.SpsError) as e:
-        B.set_dt(0.01)
-    assert e.value.code == -7
+
+
+def test_batched_problems_set_dt():
+    """The batched Swift-Hohenberg and Kolmogorov problems after sps_set_dt match problems built
+    with the new step: SH gradients within 1e-12 (the two builds may tune different tiles),
+    Kolmogorov forward runs and reverse sweeps bit-identical."""
+    note("set_dt on the batched problems")
+    sizes, rs, u0 = wl.sh_batch(seed=0, batch=3, sizes=(64, 96))
+    grid = torch.from_numpy(np.concatenate([u.ravel() for u in u0])).cuda()
+    outs = []
+    for dt0 in (0.02, 0.01):
+        B = sps.ShBatch(sizes, rs, 16.0 * np.pi, dt0, max_steps=20)
+        if dt0 != 0.01:
+            B.set_dt(0.01)
+        X0 = torch.zeros(B.n, dtype=torch.float64, device="cuda")
+        B.initial_state(grid, X0)
+        g = torch.zeros_like(X0)
+        XN = torch.zeros_like(X0)
+        J = torch.zeros(len(sizes), dtype=torch.float64, device="cuda")
+        B.gradient(X0, 20, XN, g, J)
+        B.sync()
+        outs.append((XN, g, J))
+    for a, b in zip(*outs):
+        assert (a - b).abs().max().item() <= 1e-12 * b.abs().max().item()
+    c0 = wl.kolmo_vorticity(seed=1, N=16, batch=2)
+    Yb = wl.kolmo_vorticity(seed=5, N=16, batch=2)
+    res = []
+    for dt0 in (0.02, 0.005):
+        G = sps.Kolmogorov(2, 16, Re=1000.0, dt=dt0, max_steps=8, closure=False, keep_history=True)
+        if dt0 != 0.005:
+            G.set_dt(0.005)
+        # device layout X[b][m][iy] from the coefficient arrays c[iy, m]
+        X = torch.from_numpy(np.concatenate([np.ascontiguousarray(c.T).view(np.float64).ravel() for c in c0])).cuda()
+        G.step(X, 8)
+        Xb = torch.from_numpy(np.concatenate([np.ascontiguousarray(c.T).view(np.float64).ravel() for c in Yb])).cuda()
+        G.adjoint_step(Xb, 8)
+        G.sync()
+        res.append((X, Xb))
+    assert all(torch.equal(a, b) for a, b in zip(*res))
