@@ -176,13 +176,20 @@ def test_two_level_equals_uniform():
     assert same
 
 
-def test_two_level_couette():
+def test_two_level_couette(tmp_path):
+    """Plane Couette: two levels in host memory, nested on 2 outer slots, and both in a file."""
     n = 9
-    G = sps.Couette(8, 12, 8, Re=400.0, dt=0.01, checkpoint_every=4, max_steps=n)
+    G = sps.Couette(8, 12, 8, Re=400.0, dt=0.01, checkpoint_every=2, max_steps=n)
     uvw = wl.couette_perturbation(seed=5, Nx=8, Ny=12, Nz=8, energy=1e-3)
     X0 = torch.from_numpy(G.state_from_velocity(uvw)).cuda()
     ref = grad(G, X0, n)
     G.set_checkpointing(sps.CKPT_TWO_LEVEL, 2)
+    assert all(torch.equal(a, b) for a, b in zip(grad(G, X0, n), ref))
+    G.set_outer_slots(2)
+    assert all(torch.equal(a, b) for a, b in zip(grad(G, X0, n), ref))
+    G.set_checkpoint_file(tmp_path / "couette.bin")
+    assert all(torch.equal(a, b) for a, b in zip(grad(G, X0, n), ref))
+    G.set_outer_slots(0)
     assert all(torch.equal(a, b) for a, b in zip(grad(G, X0, n), ref))
 
 
