@@ -136,6 +136,14 @@ def test_arnoldi_vs_oracle(Ra, k, sigma, m):
     arnoldi_case(P, G, sigma, m, 6, seed=31, ks=range(1, P.K))
 
 
+def test_arnoldi_large_m_global_work_arrays():
+    """m = 56: the Hessenberg kernel's eigenvector work arrays no longer fit in LDS beside H and
+    Z (m >= 50) and live in global memory; same checks as the smaller cases."""
+    note("arnoldi m = 56")
+    P, G = build(5000.0, nz=32, lx=2.0 * np.pi / 3.0)
+    arnoldi_case(P, G, 0.05, 56, 6, seed=34, ks=range(1, P.K))
+
+
 def test_arnoldi_onset_and_inverse_iteration():
     note("arnoldi at the onset")
     P, G = build(RAC)
