@@ -218,3 +218,29 @@ def test_batched_problems_set_dt():
         G.sync()
         res.append((X, Xb))
     assert all(torch.equal(a, b) for a, b in zip(*res))
+
+
+def test_ks_step_segments_autograd():
+    """KS with RK443 in two segments of different steps (0.05 x 40, then 0.03 x 60) through
+    torch.autograd (StepSegments, Cost) against the oracle's chained RK443 sweeps and adjoints."""
+    note("KS rk443 step segments through autograd")
+    P = KS()
+    tab = imex.ars443_tableau()
+    G = sps.Problem(sps.KS1D, 64, 0, P.Lx, 0.0, 0.0, 1.5, 0.05, 1, 60, scheme=sps.RK443)
+    segs = [(0.05, 40), (0.03, 60)]
+    X0h = wl.ks_c0(seed=24, amp=0.5)[:, None]
+    X, hists = X0h, []
+    for dt, n in segs:
+        X, h = imex.rk_forward(P, X, dt, n, tableau=tab)
+        hists.append((dt, h))
+    g_ref = P.energy_grad(X)
+    J_ref = P.energy(X)
+    for dt, h in reversed(hists):
+        g_ref = imex.rk_adjoint(P, g_ref, h, dt, tableau=tab)
+    X0 = to_dev(X0h).requires_grad_(True)
+    J = sa.cost(sa.step_segments(X0, G, segs), G)
+    (g,) = torch.autograd.grad(J, X0)
+    G.sync()
+    eg = rel(from_dev(g, g_ref.shape), g_ref)
+    note(f"  J rel {abs(J.item() - J_ref) / J_ref:.1e}, dJ/dX0 rel {eg:.1e}")
+    assert abs(J.item() - J_ref) < TOL * J_ref and eg < TOL
