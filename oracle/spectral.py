@@ -36,24 +36,30 @@ def fourier_wavenumbers(K, L):
     return 2.0 * np.pi * np.arange(K) / L
 
 
+def grid_phase(m, Ng):
+    """exp(i k_m x_j) on the grid x_j = j L / Ng, as a (len(j) = Ng) x len(m) array, for integer
+    (possibly negative) mode numbers m.  Since k_m x_j = 2 pi m j / Ng, the angle is reduced
+    exactly in integers first (m j mod Ng), so every entry is correct to the rounding of one
+    cosine and sine, independent of L and of the sizes of m and j."""
+    j = np.arange(Ng)
+    r = np.mod(np.outer(j, np.asarray(m, dtype=np.int64)), Ng)
+    return np.exp(2j * np.pi * r / Ng)
+
+
 def fourier_backward_matrix(K, Ng, L):
     """Complex matrix B (Ng x K) such that the real grid values are u = Re(B @ c).
 
     B[j, m] = w_m exp(i k_m x_j) with w_0 = 1 and w_m = 2 for m >= 1, so that
     u_j = Re(c_0) + 2 Re sum_{m>=1} c_m exp(i k_m x_j).
     """
-    x = fourier_grid(Ng, L)
-    k = fourier_wavenumbers(K, L)
     w = np.full(K, 2.0)
     w[0] = 1.0
-    return w[None, :] * np.exp(1j * np.outer(x, k))
+    return w[None, :] * grid_phase(np.arange(K), Ng)
 
 
 def fourier_forward_matrix(K, Ng, L):
     """Complex matrix F (K x Ng): c_m = (1/Ng) sum_j u_j exp(-i k_m x_j) (truncating)."""
-    x = fourier_grid(Ng, L)
-    k = fourier_wavenumbers(K, L)
-    return np.exp(-1j * np.outer(k, x)) / Ng
+    return np.conj(grid_phase(np.arange(K), Ng)).T / Ng
 
 
 def fourier_backward(c, B):
@@ -90,18 +96,16 @@ def complex_fourier_modes(Nc):
 
 def complex_fourier_backward_matrix(Nc, Ng, L):
     """(Ng x Nc): u_j = sum_m c_m exp(i k_m x_j); the Nyquist slot (m = -Nc/2) is not used."""
-    m = complex_fourier_modes(Nc).astype(float)
+    m = complex_fourier_modes(Nc)
     keep = (np.abs(m) < Nc // 2).astype(float)
-    x = fourier_grid(Ng, L)
-    return keep[None, :] * np.exp(1j * np.outer(x, 2.0 * np.pi * m / L))
+    return keep[None, :] * grid_phase(m, Ng)
 
 
 def complex_fourier_forward_matrix(Nc, Ng, L):
     """(Nc x Ng): c_m = (1/Ng) sum_j u_j exp(-i k_m x_j), Nyquist slot set to zero."""
-    m = complex_fourier_modes(Nc).astype(float)
+    m = complex_fourier_modes(Nc)
     keep = (np.abs(m) < Nc // 2).astype(float)
-    x = fourier_grid(Ng, L)
-    return keep[:, None] * np.exp(-1j * np.outer(2.0 * np.pi * m / L, x)) / Ng
+    return keep[:, None] * np.conj(grid_phase(m, Ng)).T / Ng
 
 
 # ----------------------------------------------------------------------------- Chebyshev
@@ -119,14 +123,25 @@ def chebyshev_T(nmax, x):
     return np.cos(np.outer(th, np.arange(nmax)))
 
 
+def chebyshev_T_nodes(nmax, Ng):
+    """T[j, n] = T_n(x_j) at the ascending Gauss nodes x_j = -cos(pi (j + 1/2) / Ng):
+    T_n(x_j) = cos(n arccos x_j) = cos(pi n (2 (Ng - j) - 1) / (2 Ng)), with the angle reduced
+    exactly in integers (mod 4 Ng) so that every entry is correct to the rounding of one cosine
+    (cos(n arccos x_j) of the rounded node loses about n ulps of the angle)."""
+    j = np.arange(Ng)
+    n = np.arange(nmax, dtype=np.int64)
+    M = np.mod(np.outer(2 * (Ng - j) - 1, n), 4 * Ng)
+    return np.cos(np.pi * M / (2.0 * Ng))
+
+
 def chebyshev_backward_matrix(N, Ng):
     """(Ng x N): f_j = sum_n a_n T_n(x_j) on the Gauss nodes."""
-    return chebyshev_T(N, chebyshev_nodes(Ng))
+    return chebyshev_T_nodes(N, Ng)
 
 
 def chebyshev_forward_matrix(N, Ng):
     """(N x Ng): a_n = (2 - delta_{n0}) / Ng * sum_j f_j T_n(x_j), truncated to n < N."""
-    T = chebyshev_T(N, chebyshev_nodes(Ng))
+    T = chebyshev_T_nodes(N, Ng)
     c = np.full(N, 2.0)
     c[0] = 1.0
     return (c[:, None] * T.T) / Ng
