@@ -122,7 +122,7 @@ def rk_forward(P, X0, dt, nsteps, tableau=None):
     return X, history
 
 
-def rk_adjoint(P, Xbar_N, history, dt, tableau=None):
+def rk_adjoint(P, Xbar_N, history, dt, tableau=None, dLs=None, XN=None):
     """Reverse sweep of the IMEX RK scheme (Supplementary, RK adjoint equations).
 
     With Y_{n+1,0} the cotangent of X_{n+1} = X_{n,s}:
@@ -130,6 +130,13 @@ def rk_adjoint(P, Xbar_N, history, dt, tableau=None):
       (M + dt H_ii L)^H Y_{n,i} = sum_{j>i} dt (A_ji dF_{n,i} - H_ji L)^H Y_{n,j},  0 < i < s
       Y_{n,0} = sum_{j>=1} (M^H + dt [A_j0 dF_{n,0} - H_j0 L]^H) Y_{n,j}
     and Y_{n,0} is the cotangent of X_n.  Returns dJ/dX_0 = Y_{0,0}.
+
+    Parameter gradients (equ:efficient_gradient): with dLs a list of per-wavenumber blocks
+    dL/dp (one (K, S, S) array per parameter p of L) and XN the final state, also returns
+    dJ/dp = -sum_n sum_{i>=1} <Y_{n,i}, dR_{n,i}/dp>, the residual of stage i being
+    R_{n,i} = (M + dt H_ii L) X_{n,i} - M X_{n,0} - dt sum_{j<i} [A_ij F_{n,j} - H_ij L X_{n,j}],
+    so dR_{n,i}/dp = dt sum_{j<=i} H_ij (dL/dp) X_{n,j} with X_{n,s} = X_{n+1}; <a, b> is the
+    real inner product Re(a^H b) of the state layout.  Result: (dJ/dX_0, array of dJ/dp).
     """
     A, H = tableau if tableau is not None else ars222_tableau()
     s = A.shape[0] - 1
@@ -138,6 +145,8 @@ def rk_adjoint(P, Xbar_N, history, dt, tableau=None):
         if H[i, i] not in lus:
             lus[H[i, i]] = BlockLU(P.M, P.L, 1.0, dt * H[i, i])
     Ynext = np.array(Xbar_N, dtype=complex)
+    grads = np.zeros(0 if dLs is None else len(dLs))
+    Xend = None if dLs is None else np.array(XN, dtype=complex)
     for Xs in reversed(history):
         Y = [None] * (s + 1)
         Y[s] = lus[H[s, s]].solve_adjoint(Ynext)
@@ -158,7 +167,19 @@ def rk_adjoint(P, Xbar_N, history, dt, tableau=None):
             if H[j, 0] != 0.0:
                 Y0 -= dt * H[j, 0] * apply_blocks_H(P.L, Y[j])
         Y0 += P.F_vjp(Xs[0], Fcot)
+        if dLs is not None:
+            stages = list(Xs) + [Xend]
+            for q, dL in enumerate(dLs):
+                for i in range(1, s + 1):
+                    r = np.zeros_like(Ynext)
+                    for j in range(i + 1):
+                        if H[i, j] != 0.0:
+                            r += dt * H[i, j] * apply_blocks(dL, stages[j])
+                    grads[q] -= np.real(np.vdot(Y[i], r))
+            Xend = Xs[0]
         Ynext = Y0
+    if dLs is not None:
+        return Ynext, grads
     return Ynext
 
 

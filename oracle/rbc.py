@@ -357,6 +357,18 @@ class RBC:
         self.nu, self.kappa, self.kx[k] = saved
         return L[k]
 
+    def param_dL(self):
+        """dL/dRa and dL/dPr of every wavenumber, (K, S, S) each, exactly: L is affine in
+        nu = (Ra/Pr)^(-1/2) and kappa = (Ra Pr)^(-1/2) (differences at unit and zero values), and
+        dnu/dRa = -nu/(2 Ra), dnu/dPr = nu/(2 Pr), dkappa/dRa = -kappa/(2 Ra),
+        dkappa/dPr = -kappa/(2 Pr).  M and F do not depend on Ra or Pr."""
+        Lnu = np.array([self._L_with(k, nu=1.0, ka=0.0) - self._L_with(k, nu=0.0, ka=0.0) for k in range(self.K)])
+        Lka = np.array([self._L_with(k, nu=0.0, ka=1.0) - self._L_with(k, nu=0.0, ka=0.0) for k in range(self.K)])
+        nu, ka = self.nu, self.kappa
+        dRa = (-0.5 * nu / self.Ra) * Lnu + (-0.5 * ka / self.Ra) * Lka
+        dPr = (0.5 * nu / self.Pr) * Lnu + (-0.5 * ka / self.Pr) * Lka
+        return [dRa, dPr]
+
     def stability_dL(self, k):
         """dL/dRa and dL/dk of wavenumber k, exactly: L is affine in nu and kappa (differences
         at unit and zero values), quadratic in k (a central difference is exact), and the

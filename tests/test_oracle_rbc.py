@@ -182,3 +182,32 @@ def test_brute_force_finite_differences_every_component():
         Jm = P.kinetic_energy(imex.rk_forward(P, P.initial_state(b0 - e), dt, n)[0])
         fd[idx] = (Jp - Jm) / (2 * h)
     assert np.max(np.abs(fd - g)) <= 1e-7 * np.max(np.abs(g))
+
+
+def test_parameter_gradient_against_central_differences():
+    """dJ/dRa and dJ/dPr of the kinetic energy after a few RK222 steps from the reverse sweep's
+    stage adjoints (equ:efficient_gradient: minus the adjoints against the parameter derivative
+    of each stage residual) against brute-force central differences of the whole forward run in
+    Ra and in Pr (Richardson-extrapolated steps of 1e-3 and 5e-4 relative), on a tiny grid."""
+    import workloads as wl
+    from oracle import imex
+    Ra, Pr, dt, n = 1e5, 0.7, 2e-3, 3
+
+    def run(ra, pr):
+        P = RBC(Nx=8, Nz=8, Lx=3.0, Ra=ra, Pr=pr)
+        X0 = P.initial_state(wl.rbc_b0(seed=3, Nx=8, Nz=8, amp=0.3))
+        XN, hist = imex.rk_forward(P, X0, dt, n)
+        return P, XN, hist
+
+    P, XN, hist = run(Ra, Pr)
+    _, gp = imex.rk_adjoint(P, P.kinetic_energy_grad(XN), hist, dt, dLs=P.param_dL(), XN=XN)
+
+    def J(ra, pr):
+        Q, XQ, _ = run(ra, pr)
+        return Q.kinetic_energy(XQ)
+
+    for q, (dra, dpr) in enumerate(((Ra, 0.0), (0.0, Pr))):
+        def cd(h):
+            return (J(Ra + h * dra, Pr + h * dpr) - J(Ra - h * dra, Pr - h * dpr)) / (2 * h * (dra + dpr))
+        fd = (4 * cd(5e-4) - cd(1e-3)) / 3.0
+        assert abs(fd - gp[q]) <= 1e-8 * abs(gp[q]), (q, fd, gp[q])
