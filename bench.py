@@ -73,23 +73,48 @@ def stage_kernel_bytes(nx, nz, K=None):
     return K * 0.5 * (stage1 + stage2)
 
 
-def cpu_baseline(nsteps=60):
+def host_cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo) and its logical CPU count."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def cpu_baseline(nsteps=60, nsteps_single=10):
     """The oracle (numpy/scipy FP64) on a bounded sample: nsteps forward + nsteps adjoint
-    steps of the same 256 x 64 problem from the same b0."""
-    from threadpoolctl import threadpool_info
+    steps of the same 256 x 64 problem from the same b0, with the BLAS thread pool at its
+    default size (all host cores) and, for nsteps_single + nsteps_single steps, on one thread."""
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import imex
     from oracle.rbc import RBC
     import workloads as wl
     P = RBC(Nx=CFG["nx"], Nz=CFG["nz"], Lx=CFG["lx"], Ra=CFG["Ra"], Pr=CFG["Pr"])
     X0 = P.initial_state(wl.rbc_b0(seed=CFG["seed"], Nx=CFG["nx"], Nz=CFG["nz"]))
-    t0 = time.perf_counter()
-    XN, hist = imex.rk_forward(P, X0, CFG["dt"], nsteps)
-    imex.rk_adjoint(P, P.kinetic_energy_grad(XN), hist, CFG["dt"])
-    t = time.perf_counter() - t0
+
+    def run(n):
+        t0 = time.perf_counter()
+        XN, hist = imex.rk_forward(P, X0, CFG["dt"], n)
+        imex.rk_adjoint(P, P.kinetic_energy_grad(XN), hist, CFG["dt"])
+        return time.perf_counter() - t0
+
+    t = run(nsteps)
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    with threadpool_limits(limits=1):
+        t1 = run(nsteps_single)
+    model, ncpu = host_cpu_model()
     return {"value": 2 * nsteps / t, "unit": "timesteps/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{nsteps} forward + {nsteps} adjoint RK222 steps at 256x64 (dense LU, matrix transforms), "
-                      f"{t:.1f} s; host has {os.cpu_count()} logical CPUs"}
+                      f"{t:.1f} s on {threads} BLAS threads; host: {ncpu} logical CPUs, {model}",
+            "single_thread": {"value": 2 * nsteps_single / t1, "unit": "timesteps/s", "cores": 1,
+                              "sample": f"{nsteps_single} forward + {nsteps_single} adjoint steps, {t1:.1f} s"},
+            "host_cpu_model": model, "host_logical_cpus": ncpu}
 
 
 KS_CFG = dict(nx=64, L=32.0 * np.pi, dt=0.05, nsteps=200, seed=0)
@@ -213,6 +238,11 @@ def sh_timing(reps=2):
         torch.cuda.synchronize()
         plain += counts[n] * (time.perf_counter() - t1)
         G1.sync()
+        G1.close()
+    tuning = G.tuning()
+    # every library handle is closed before the function returns, so nothing of the library is
+    # left for interpreter teardown
+    G.close()
     # oracle sample
     ocpu = 0.0
     for n in sorted(counts):
@@ -226,7 +256,7 @@ def sh_timing(reps=2):
                         "L = 16 pi, 2x padding, SBDF2 dt = 0.02, 500 steps, gradient of the summed energies",
             "gpu_gradient_s": batch_s, "gpu_instance_timesteps_per_s": 2 * c["nsteps"] * len(sizes) / batch_s,
             "hbm_achieved_GBps": bytes_grad / batch_s / 1e9, "hbm_frac": bytes_grad / batch_s / 1e9 / HBM_PEAK_GBS,
-            "algorithmic_bytes_per_gradient": bytes_grad, "tuning": G.tuning(),
+            "algorithmic_bytes_per_gradient": bytes_grad, "tuning": tuning,
             "plain_launch_gradient_s": plain, "batched_speedup_vs_plain": plain / batch_s,
             "oracle_cpu_gradient_s_extrapolated": ocpu}
 
@@ -573,7 +603,6 @@ def kolmo_timing():
     import workloads as wl
     import paper_2506_14792_amd as sps
     from paper_2506_14792_amd import closure_train as ct
-    from oracle import closure as cl
     c = KOL_CFG
     nf, fac, nc = c["n_fine"], c["factor"], c["n_fine"] // c["factor"]
     nb = c["ntrain"] + c["ntest"]
@@ -590,7 +619,7 @@ def kolmo_timing():
     # coarse steps with and without the closure (forward runs of B windows, no history)
     picks = [(s, b % c["ntrain"]) for b, s in enumerate(range(0, B * 10, 10))]
     Xc, _ = ct.gather_windows(Str, picks, n)
-    theta0 = torch.from_numpy(cl.flatten(cl.init_params(seed=0, C=32, scale=1.0))).cuda()
+    theta0 = torch.from_numpy(wl.closure_theta(seed=0, C=32, scale=1.0)).cuda()
     step_ms = {}
     for name, clo in (("plain", False), ("closure", True)):
         G = sps.Kolmogorov(B, nc, Re=c["Re"], dt=c["dt"], max_steps=1, closure=clo, keep_history=False,

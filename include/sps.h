@@ -193,11 +193,23 @@ int sps_adjoint_step(sps_problem *P, double *Xbar, int nsteps);
  * J_out: device pointer to one double; dJdX: cotangent in state layout. */
 int sps_cost(sps_problem *P, const double *X, double *J_out, double *dJdX);
 
-/* Full gradient: X0 -> forward nsteps with checkpoints -> J and dJ/dX_N -> reverse sweep.
- * Outputs XN (final state), dJdX0 (state layout) and J_out (one double); any output may
- * be NULL except dJdX0. */
-int sps_gradient(sps_problem *P, const double *X0, int nsteps, double *XN, double *dJdX0,
-                 double *J_out);
+/* Full gradient (paper: equ:adjoint and equ:efficient_gradient): X0 -> forward nsteps with
+ * checkpoints -> the final-time cotangent -> reverse sweep -> dJ/dX0.
+ *  dJdXN (nullable, input): the cotangent of the final state from an upstream vector-Jacobian
+ *        product (Supplementary, Initial value problems: the final-time condition of the adjoint
+ *        comes from the cost's VJP, which may belong to a larger computation); the reverse sweep
+ *        starts there.  NULL: the built-in cost of the problem (sps_cost) and its gradient.
+ *  XN (nullable, output): the final state.
+ *  dJdX0 (output, required): the gradient with respect to the initial state, state layout.  It
+ *        may be the same array as dJdXN (read first, then overwritten).
+ *  dJdtheta (nullable, output): the gradient with respect to the problem's parameters (the
+ *        efficient-gradient identity: minus the sum over steps of the adjoint variables against
+ *        the parameter derivative of each stage's residual).  Problems without parameter
+ *        gradients return SPS_E_UNSUPPORTED when it is not NULL.
+ *  J_out (nullable, output, one double): the built-in cost; must be NULL when dJdXN is given
+ *        (SPS_E_ARG). */
+int sps_gradient(sps_problem *P, const double *X0, int nsteps, const double *dJdXN, double *XN, double *dJdX0,
+                 double *dJdtheta, double *J_out);
 
 /* Initial state from scale-1 grid values (paper, Methods: Spectral transforms, forward
  * transform f_hat = T f).  RBC: grid is b0[x][z], nx * nz doubles; the state gets b and

@@ -72,17 +72,9 @@ def conv3_adjoint_weight(a, g):
 
 
 def init_params(seed=0, C=32, scale=1.0):
-    """He-style initial weights (the network starts as a small perturbation of F)."""
-    rng = np.random.default_rng(seed)
-    p = {
-        "w1": rng.standard_normal((C, 1, 3, 3)) * math.sqrt(2.0 / 9.0) * scale,
-        "b1": np.zeros(C),
-        "w2": rng.standard_normal((C, C, 3, 3)) * math.sqrt(2.0 / (9.0 * C)) * scale,
-        "b2": np.zeros(C),
-        "w3": rng.standard_normal((1, C, 3, 3)) * math.sqrt(1.0 / (9.0 * C)) * scale * 1e-2,
-        "b3": np.zeros(1),
-    }
-    return p
+    """Seeded initial weights (random draws only, from the shared input generators)."""
+    import workloads
+    return workloads.closure_params(seed, C, scale)
 
 
 def forward(p, x, bf=True):

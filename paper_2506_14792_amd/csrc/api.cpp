@@ -140,8 +140,12 @@ int sps_cost(sps_problem* P, const double* X, double* J_out, double* dJdX) {
   return guard(P, [&](sps::ProblemImpl& p) { p.cost(X, J_out, dJdX); });
 }
 
-int sps_gradient(sps_problem* P, const double* X0, int nsteps, double* XN, double* dJdX0, double* J_out) {
-  return guard(P, [&](sps::ProblemImpl& p) { p.gradient(X0, nsteps, XN, dJdX0, J_out); });
+int sps_gradient(sps_problem* P, const double* X0, int nsteps, const double* dJdXN, double* XN, double* dJdX0,
+                 double* dJdtheta, double* J_out) {
+  return guard(P, [&](sps::ProblemImpl& p) {
+    SPS_REQUIRE(!(dJdXN && J_out), "J_out is the built-in cost: pass NULL with an upstream cotangent dJdXN");
+    p.gradient(X0, nsteps, dJdXN, XN, dJdX0, dJdtheta, J_out);
+  });
 }
 
 int sps_initial_state(sps_problem* P, const double* grid, double* X) {

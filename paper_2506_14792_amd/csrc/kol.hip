@@ -608,7 +608,7 @@ class KolProblem : public ProblemImpl {
   void cost(const double*, double*, double*) override {
     throw Error(SPS_E_UNSUPPORTED, "the Kolmogorov problem's objective is the rollout loss");
   }
-  void gradient(const double*, int, double*, double*, double*) override {
+  void gradient(const double*, int, const double*, double*, double*, double*, double*) override {
     throw Error(SPS_E_UNSUPPORTED, "use the rollout call of the Kolmogorov problem");
   }
   void initial_state(const double*, double*) override {

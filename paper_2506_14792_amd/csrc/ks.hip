@@ -594,13 +594,19 @@ class KsProblem : public ProblemImpl {
                        reinterpret_cast<cplx*>(dJdX), J);
     SPS_CHECK_LAUNCH();
   }
-  void gradient(const double* X0, int nsteps, double* XN, double* dJdX0, double* J) override {
+  void gradient(const double* X0, int nsteps, const double* dJdXN, double* XN, double* dJdX0, double* dJdtheta,
+                double* J) override {
     SPS_REQUIRE(X0 && dJdX0, "null argument");
+    if (dJdtheta) throw Error(SPS_E_UNSUPPORTED, "the KS problem has no parameters to differentiate");
     SPS_REQUIRE(nsteps >= 1 && nsteps <= (var_n_ ? var_n_ : desc_.max_steps), "nsteps out of range");
     SPS_HIP(hipMemcpyAsync(Xw_, X0, sizeof(cplx) * K_, hipMemcpyDeviceToDevice, stream));
     forward(Xw_, nsteps);
     if (XN) SPS_HIP(hipMemcpyAsync(XN, Xw_, sizeof(cplx) * K_, hipMemcpyDeviceToDevice, stream));
-    cost(reinterpret_cast<const double*>(Xw_), J, dJdX0);
+    if (dJdXN) {
+      if (dJdXN != dJdX0) SPS_HIP(hipMemcpyAsync(dJdX0, dJdXN, sizeof(cplx) * K_, hipMemcpyDeviceToDevice, stream));
+    } else {
+      cost(reinterpret_cast<const double*>(Xw_), J, dJdX0);
+    }
     adjoint_step(dJdX0, nsteps);
   }
   void initial_state(const double*, double*) override {

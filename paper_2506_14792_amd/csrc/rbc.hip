@@ -45,8 +45,10 @@
 #include "cou.h"
 #include "sps_device.h"
 #include "sps_internal.h"
+#include "wave_fft.h"
 
 namespace sps {
+
 namespace {
 
 constexpr int NT = 256;   // threads per block of the grid-row, factor and set-up kernels
@@ -877,6 +879,172 @@ __global__ void __launch_bounds__(NTX) rbc_xadj(RbcDev d, XaArgs a) {
     // x-derivative transposed: conj(i kx) = -i kx
     const cplx dxt = cscale(cmul_mi(Ad), kx);
     cplx base = (f == 0) ? A0 : (f == 1 ? B0 : czero());
+    a.zbar[((size_t)f * Ngz + j) * K + m] = cadd(base, dxt);
+    a.zbar[((size_t)(3 + f) * Ngz + j) * K + m] = Bd;
+  }
+}
+
+// Grid-row kernels with one wavefront per length-Ngx FFT (Ngx = 64 R1, R1 = 3 or 6, i.e. nx = 128
+// or 256): the same transforms and products as rbc_xfwd / rbc_xadj, with the FFTs of wave_fft.h
+// (registers, two in-wave LDS exchanges, no block barrier inside a transform).  Each wave packs
+// its pair of real rows (Hermitian packing of two half spectra, read straight from global
+// memory), the inverse FFTs leave the grid rows in the permuted layout, the products are formed
+// in that layout, and the forward FFTs return natural-order spectra for the truncation.
+template <int R1>
+struct WaveRow {
+  static constexpr int N = 64 * R1;      // Ngx
+  static constexpr int K = N / 3;        // kept modes
+  static constexpr int SC = (N + (N >> 3) + 1 + 1) & ~1;   // fpad_size(N), rounded to even
+};
+
+// Natural-layout entries a[q] = packed spectrum at m = l + 64 q of the pair (U, V): U the
+// x-spectrum of field fu (times i kx when du), V that of field fv (none when fv < 0), modes
+// m >= 1 scaled by sc.  src: [fields][Ngz][K] at row j.
+template <int R1>
+__device__ __forceinline__ void pack_pair_row(const RbcDev& d, const cplx* src, int j, int fu, bool du, int fv,
+                                              double scl, cplx (&a)[R1]) {
+  constexpr int N = WaveRow<R1>::N, K = WaveRow<R1>::K;
+  const int l = lane_id(), Ngz = d.Ngz;
+  const cplx* U = src + ((size_t)fu * Ngz + j) * K;
+  const cplx* V = fv >= 0 ? src + ((size_t)fv * Ngz + j) * K : nullptr;
+#pragma unroll
+  for (int q = 0; q < R1; ++q) {
+    const int m = l + 64 * q;
+    const bool lowm = m < K, highm = m > N - K;
+    const int sidx = lowm ? m : (highm ? N - m : 0);
+    cplx u = czero(), v = czero();
+    if (lowm || highm) {
+      u = U[sidx];
+      if (du) u = cscale(cmul_i(u), d.kx[sidx]);
+      if (V) v = V[sidx];
+    }
+    cplx r;
+    if (m == 0) r = cmk(u.x, v.x);
+    else if (lowm) r = cscale(cmk(u.x - v.y, u.y + v.x), scl);
+    else if (highm) r = cscale(cmk(u.x + v.y, v.x - u.y), scl);
+    else r = czero();
+    a[q] = r;
+  }
+}
+
+template <int R1>
+__global__ void __launch_bounds__(256) rbc_xfwd_w(RbcDev d, XfArgs a) {
+  using W = WaveRow<R1>;
+  constexpr int N = W::N, K = W::K, SC = W::SC;
+  extern __shared__ double smem_d[];
+  cplx* tw = reinterpret_cast<cplx*>(smem_d);   // N
+  cplx* scr = tw + N;                            // 4 x SC
+  cplx* G = scr + 4 * SC;                        // 4 x 8 x 64 grid rows (permuted layout)
+  const int j = blockIdx.x, tid = threadIdx.x, wv = tid >> 6, l = lane_id();
+  cplx* sc = scr + wv * SC;
+  // pair wv: (u, w), (ux, uz), (wx, wz), (bx, bz)
+  cplx av[R1];
+  pack_pair_row<R1>(d, a.zg, j, wv == 0 ? 0 : wv - 1, wv > 0, wv == 0 ? 1 : wv + 2, 1.0, av);
+  for (int e = tid; e < N; e += 256) tw[e] = d.twx[e];
+  __syncthreads();
+  cplx pv[8];
+  wfft_a_to_p<R1, +1>(av, pv, sc, tw);
+  if (l < 8 * R1) {
+#pragma unroll
+    for (int h = 0; h < 8; ++h) G[(wv * 8 + h) * 64 + l] = pv[h];
+  }
+  __syncthreads();
+  if (wv >= 2) return;
+  if (l < 8 * R1) {
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+      const cplx uw = G[(0 * 8 + h) * 64 + l];
+      if (wv == 0) {
+        const cplx ud = G[(1 * 8 + h) * 64 + l], wd = G[(2 * 8 + h) * 64 + l];
+        pv[h] = cmk(-(uw.x * ud.x + uw.y * ud.y), -(uw.x * wd.x + uw.y * wd.y));   // N_u, N_w
+      } else {
+        const cplx bd = G[(3 * 8 + h) * 64 + l];
+        pv[h] = cmk(-(uw.x * bd.x + uw.y * bd.y), 0.0);                            // N_b
+      }
+    }
+  }
+  wfft_p_to_a<R1, -1>(pv, av, sc, tw);
+#pragma unroll
+  for (int q = 0; q < R1; ++q) sc[fpad(q * 64 + l)] = av[q];
+  wave_lds_sync();
+  constexpr double inv = 1.0 / N;
+  const int Ngz = d.Ngz;
+#pragma unroll
+  for (int t = 0; t < (K + 63) / 64; ++t) {
+    const int m = l + 64 * t;
+    if (m >= K) break;
+    const cplx zm = sc[fpad(m)], zq = sc[fpad(m == 0 ? 0 : N - m)];
+    if (wv == 0) {
+      a.nl[((size_t)0 * Ngz + j) * K + m] = cscale(cmk(0.5 * (zm.x + zq.x), 0.5 * (zm.y - zq.y)), inv);
+      a.nl[((size_t)1 * Ngz + j) * K + m] = cscale(cmk(0.5 * (zm.y + zq.y), -0.5 * (zm.x - zq.x)), inv);
+    } else {
+      a.nl[((size_t)2 * Ngz + j) * K + m] = cscale(cmk(0.5 * (zm.x + zq.x), 0.5 * (zm.y - zq.y)), inv);
+    }
+  }
+}
+
+template <int R1>
+__global__ void __launch_bounds__(384) rbc_xadj_w(RbcDev d, XaArgs a) {
+  using W = WaveRow<R1>;
+  constexpr int N = W::N, K = W::K, SC = W::SC;
+  extern __shared__ double smem_d[];
+  cplx* tw = reinterpret_cast<cplx*>(smem_d);   // N
+  cplx* scr = tw + N;                            // 6 x SC
+  cplx* G = scr + 6 * SC;                        // 6 x 8 x 64 grid rows (permuted layout)
+  const int j = blockIdx.x, tid = threadIdx.x, wv = tid >> 6, l = lane_id();
+  cplx* sc = scr + wv * SC;
+  // pairs: (u, w), (ux, uz), (wx, wz), (bx, bz), (Nu_bar, Nw_bar) and (Nb_bar, 0) with halved
+  // weights of the modes m >= 1 (the transposed forward transform of a real row)
+  cplx av[R1];
+  if (wv < 4) pack_pair_row<R1>(d, a.zg, j, wv == 0 ? 0 : wv - 1, wv > 0, wv == 0 ? 1 : wv + 2, 1.0, av);
+  else pack_pair_row<R1>(d, a.nlbar, j, wv == 4 ? 0 : 2, false, wv == 4 ? 1 : -1, 0.5, av);
+  for (int e = tid; e < N; e += 384) tw[e] = d.twx[e];
+  __syncthreads();
+  cplx pv[8];
+  wfft_a_to_p<R1, +1>(av, pv, sc, tw);
+  if (l < 8 * R1) {
+#pragma unroll
+    for (int h = 0; h < 8; ++h) G[(wv * 8 + h) * 64 + l] = pv[h];
+  }
+  __syncthreads();
+  if (wv < 4) {
+    if (l < 8 * R1) {
+      constexpr double inv = 1.0 / N;
+#pragma unroll
+      for (int h = 0; h < 8; ++h) {
+        const cplx nb = G[(4 * 8 + h) * 64 + l];
+        const double Nub = nb.x * inv, Nwb = nb.y * inv, Nbb = G[(5 * 8 + h) * 64 + l].x * inv;
+        if (wv == 0) {
+          const cplx ud = G[(1 * 8 + h) * 64 + l], wd = G[(2 * 8 + h) * 64 + l], bd = G[(3 * 8 + h) * 64 + l];
+          pv[h] = cmk(-(Nub * ud.x + Nwb * wd.x + Nbb * bd.x), -(Nub * ud.y + Nwb * wd.y + Nbb * bd.y));
+        } else {
+          const cplx uw = G[(0 * 8 + h) * 64 + l];
+          const double c = (wv == 1) ? Nub : (wv == 2 ? Nwb : Nbb);
+          pv[h] = cmk(-c * uw.x, -c * uw.y);   // (x-derivative bar, z-derivative bar) of u, w or b
+        }
+      }
+    }
+    wfft_p_to_a<R1, -1>(pv, av, sc, tw);
+#pragma unroll
+    for (int q = 0; q < R1; ++q) sc[fpad(q * 64 + l)] = av[q];
+  }
+  __syncthreads();
+  // unpack A_m = (Z_m + conj Z_-m)/2, B_m = (Z_m - conj Z_-m)/(2i), weight 1 at m = 0, 2 else
+  const int Ngz = d.Ngz;
+  for (int e = tid; e < 3 * K; e += 384) {
+    const int f = e / K, m = e - f * K;
+    const double wgt = (m == 0) ? 1.0 : 2.0;
+    auto unpack = [&](int q, cplx& A, cplx& B) {
+      const cplx* Z = scr + q * SC;
+      const cplx zm = Z[fpad(m)], zq = Z[fpad(m == 0 ? 0 : N - m)];
+      A = cscale(cmk(0.5 * (zm.x + zq.x), 0.5 * (zm.y - zq.y)), wgt);
+      B = cscale(cmk(0.5 * (zm.y + zq.y), -0.5 * (zm.x - zq.x)), wgt);
+    };
+    cplx A0, B0, Ad, Bd;
+    unpack(0, A0, B0);
+    unpack(1 + f, Ad, Bd);
+    const cplx dxt = cscale(cmul_mi(Ad), d.kx[m]);
+    const cplx base = (f == 0) ? A0 : (f == 1 ? B0 : czero());
     a.zbar[((size_t)f * Ngz + j) * K + m] = cadd(base, dxt);
     a.zbar[((size_t)(3 + f) * Ngz + j) * K + m] = Bd;
   }
@@ -2066,32 +2234,45 @@ class RbcProblem : public ProblemImpl {
     graph_on_ = on;
   }
 
-  void gradient(const double* X0, int nsteps, double* XN, double* dJdX0, double* J) override {
+  void gradient(const double* X0, int nsteps, const double* dJdXN, double* XN, double* dJdX0, double* dJdtheta,
+                double* J) override {
     SPS_REQUIRE(X0 && dJdX0, "null argument");
     SPS_REQUIRE(nsteps >= 1 && nsteps <= desc_.max_steps, "nsteps out of range");
+    if (dJdtheta) throw Error(SPS_E_UNSUPPORTED, "parameter gradients are not available for this problem");
     factor();
     if (graph_on_ && ckpt_mode_ != SPS_CKPT_TWO_LEVEL) {
-      const GraphKey key{X0, XN, dJdX0, J, nsteps};
+      const GraphKey key{X0, dJdXN, XN, dJdX0, J, nsteps};
       for (const auto& g : graphs_)
         if (g.first == key) {
           SPS_HIP(hipGraphLaunch(g.second, stream));
-          tape_steps_ = ckpt_mode_ == SPS_CKPT_BINOMIAL ? -1 : nsteps;
+          after_graph_gradient(nsteps);
           return;
         }
-      graphs_.emplace_back(key, capture_gradient(X0, nsteps, XN, dJdX0, J));
+      graphs_.emplace_back(key, capture_gradient(X0, nsteps, dJdXN, XN, dJdX0, J));
       SPS_HIP(hipGraphLaunch(graphs_.back().second, stream));
-      tape_steps_ = ckpt_mode_ == SPS_CKPT_BINOMIAL ? -1 : nsteps;
+      after_graph_gradient(nsteps);
       return;
     }
-    gradient_launches(X0, nsteps, XN, dJdX0, J);
+    gradient_launches(X0, nsteps, dJdXN, XN, dJdX0, J);
+  }
+
+  // the recorded-run state a replayed gradient leaves (as its eager launches would)
+  void after_graph_gradient(int nsteps) {
+    tape_steps_ = ckpt_mode_ == SPS_CKPT_BINOMIAL ? -1 : nsteps;
+    const int ce = desc_.checkpoint_every;
+    last_seg_ok_ = (nsteps + ce - 1) / ce < 3;
   }
 
   // the launch sequence of one gradient on `stream` (and the auxiliary stream)
-  void gradient_launches(const double* X0, int nsteps, double* XN, double* dJdX0, double* J) {
+  void gradient_launches(const double* X0, int nsteps, const double* dJdXN, double* XN, double* dJdX0, double* J) {
     SPS_HIP(hipMemcpyAsync(Xg_, X0, sizeof(cplx) * K_ * S_, hipMemcpyDeviceToDevice, stream));
     forward(Xg_, nsteps);
     if (XN) SPS_HIP(hipMemcpyAsync(XN, Xg_, sizeof(cplx) * K_ * S_, hipMemcpyDeviceToDevice, stream));
-    cost(reinterpret_cast<const double*>(Xg_), J, dJdX0);
+    if (dJdXN) {
+      if (dJdXN != dJdX0) SPS_HIP(hipMemcpyAsync(dJdX0, dJdXN, sizeof(cplx) * K_ * S_, hipMemcpyDeviceToDevice, stream));
+    } else {
+      cost(reinterpret_cast<const double*>(Xg_), J, dJdX0);
+    }
     reverse(reinterpret_cast<cplx*>(dJdX0), nsteps);
   }
 
@@ -2410,17 +2591,18 @@ class RbcProblem : public ProblemImpl {
 
   // ----------------------------------------------------------------- graphs
   struct GraphKey {
-    const double* X0;
+    const double *X0, *dJN;
     double *XN, *dJ, *J;
     int nsteps;
     bool operator==(const GraphKey& o) const {
-      return X0 == o.X0 && XN == o.XN && dJ == o.dJ && J == o.J && nsteps == o.nsteps;
+      return X0 == o.X0 && dJN == o.dJN && XN == o.XN && dJ == o.dJ && J == o.J && nsteps == o.nsteps;
     }
   };
   // Record one gradient into a graph: the launches go to a private capture stream (the
   // caller's stream may be the legacy null stream, which cannot be captured); the
   // auxiliary stream joins the capture through the events of the reverse sweep.
-  hipGraphExec_t capture_gradient(const double* X0, int nsteps, double* XN, double* dJdX0, double* J) {
+  hipGraphExec_t capture_gradient(const double* X0, int nsteps, const double* dJdXN, double* XN, double* dJdX0,
+                                  double* J) {
     if (!cap_) SPS_HIP(hipStreamCreateWithFlags(&cap_, hipStreamNonBlocking));
     hipStream_t user = stream;
     stream = cap_;
@@ -2428,7 +2610,7 @@ class RbcProblem : public ProblemImpl {
     hipGraph_t graph = nullptr;
     SPS_HIP(hipStreamBeginCapture(cap_, hipStreamCaptureModeThreadLocal));
     try {
-      gradient_launches(X0, nsteps, XN, dJdX0, J);
+      gradient_launches(X0, nsteps, dJdXN, XN, dJdX0, J);
     } catch (...) {
       (void)hipStreamEndCapture(cap_, &graph);
       if (graph) (void)hipGraphDestroy(graph);
@@ -2481,10 +2663,19 @@ class RbcProblem : public ProblemImpl {
       planes_->forward(zg, nl_, s ? s : stream);
       return;
     }
-    XfArgs a{zg, nl_};
-    hipLaunchKernelGGL(rbc_xfwd, dim3(Ngz_), dim3(NTX), xf_lds(), s ? s : stream, dv_, a);
+    launch_xf_rows(zg, nl_, s ? s : stream);
+  }
+  // the grid-row forward kernel: one wave per FFT where the row length is 64 R1 (R1 = 3, 6)
+  void launch_xf_rows(const cplx* zg, cplx* nl, hipStream_t s) {
+    XfArgs a{zg, nl};
+    if (wave_r1_ == 6) hipLaunchKernelGGL(rbc_xfwd_w<6>, dim3(Ngz_), dim3(256), xfw_lds(), s, dv_, a);
+    else if (wave_r1_ == 3) hipLaunchKernelGGL(rbc_xfwd_w<3>, dim3(Ngz_), dim3(256), xfw_lds(), s, dv_, a);
+    else hipLaunchKernelGGL(rbc_xfwd, dim3(Ngz_), dim3(NTX), xf_lds(), s, dv_, a);
     SPS_CHECK_LAUNCH();
   }
+  size_t xfw_lds() const { return sizeof(cplx) * (Ngx_ + 4 * wave_sc() + 4 * 512); }
+  size_t xaw_lds() const { return sizeof(cplx) * (Ngx_ + 6 * wave_sc() + 6 * 512); }
+  int wave_sc() const { return wave_r1_ == 6 ? WaveRow<6>::SC : WaveRow<3>::SC; }
   KaArgs ka_args(int flags) {
     KaArgs a;
     a.zbar = zbar_;
@@ -2509,7 +2700,9 @@ class RbcProblem : public ProblemImpl {
       return;
     }
     XaArgs a{nlbar_, zg, zbar_};
-    hipLaunchKernelGGL(rbc_xadj, dim3(Ngz_), dim3(NTX), xa_lds(), stream, dv_, a);
+    if (wave_r1_ == 6) hipLaunchKernelGGL(rbc_xadj_w<6>, dim3(Ngz_), dim3(384), xaw_lds(), stream, dv_, a);
+    else if (wave_r1_ == 3) hipLaunchKernelGGL(rbc_xadj_w<3>, dim3(Ngz_), dim3(384), xaw_lds(), stream, dv_, a);
+    else hipLaunchKernelGGL(rbc_xadj, dim3(Ngz_), dim3(NTX), xa_lds(), stream, dv_, a);
     SPS_CHECK_LAUNCH();
   }
 
@@ -2548,6 +2741,7 @@ class RbcProblem : public ProblemImpl {
       rk_step(stream, X, zpos(n, 0), zpos(n, 1), (n + 1 < nsteps) ? zpos(n + 1, 0) : nullptr);
     }
     tape_steps_ = nsteps;
+    last_seg_ok_ = true;
   }
 
   // re-run segment seg from its checkpoint on stream s into segment buffer seg & 1
@@ -2576,6 +2770,10 @@ class RbcProblem : public ProblemImpl {
     const int nseg = (nsteps + ce - 1) / ce;
     auto seglen = [&](int g) { return std::min(ce, nsteps - g * ce); };
     hipEvent_t ev_fwd = ev_[0], ev_rec = ev_[1], ev_adj = ev_[2];
+    // A second reverse sweep of the same run: with three or more segments the previous sweep's
+    // recompute of segment nseg-3 overwrote the buffer that held the last segment's stage
+    // fields (both use buffer (nseg-1)&1), so the last segment is recomputed first.
+    if (!last_seg_ok_) recompute(nseg - 1, seglen(nseg - 1), stream);
     SPS_HIP(hipEventRecord(ev_fwd, stream));
     SPS_HIP(hipStreamWaitEvent(aux_, ev_fwd, 0));
     bool first = true;
@@ -2598,6 +2796,7 @@ class RbcProblem : public ProblemImpl {
       }
       SPS_HIP(hipEventRecord(ev_adj, stream));
     }
+    last_seg_ok_ = nseg < 3;
     KaArgs a = ka_args(KA_C);
     a.Xb_out = Xbar;
     launch_ka(a);
@@ -3008,8 +3207,17 @@ class RbcProblem : public ProblemImpl {
     std::vector<std::pair<const void*, size_t>> lds = {
         {(const void*)kfwd_fn(), kf_lds()}, {(const void*)kadj_fn(), ka_lds()}, {(const void*)rbc_factor, fac_lds}};
     if (!cou_) {
-      lds.push_back({(const void*)rbc_xfwd, xf_lds()});
-      lds.push_back({(const void*)rbc_xadj, xa_lds()});
+      wave_r1_ = (Ngx_ == 384) ? 6 : (Ngx_ == 192 ? 3 : 0);
+      if (wave_r1_ == 6) {
+        lds.push_back({(const void*)rbc_xfwd_w<6>, xfw_lds()});
+        lds.push_back({(const void*)rbc_xadj_w<6>, xaw_lds()});
+      } else if (wave_r1_ == 3) {
+        lds.push_back({(const void*)rbc_xfwd_w<3>, xfw_lds()});
+        lds.push_back({(const void*)rbc_xadj_w<3>, xaw_lds()});
+      } else {
+        lds.push_back({(const void*)rbc_xfwd, xf_lds()});
+        lds.push_back({(const void*)rbc_xadj, xa_lds()});
+      }
     }
     for (const auto& fl : lds) {
       SPS_REQUIRE(fl.second <= 160 * 1024, "problem too large for LDS");
@@ -3023,6 +3231,7 @@ class RbcProblem : public ProblemImpl {
   double nu_, ka_, dt_ = 0.0, cp_ = 1.0, bc0_ = 1.0, cost_scale_ = 1.0;
   int Kz_ = 1, ncost_ = 2;
   bool cou_ = false, stream_solve_ = false;
+  int wave_r1_ = 0;   // grid rows of 64 wave_r1_ points use the one-wave-per-FFT kernels
   std::vector<double> kxs_;
   std::vector<unsigned char> ckeep_;
   std::unique_ptr<CouettePlanes> planes_;
@@ -3047,6 +3256,7 @@ class RbcProblem : public ProblemImpl {
   std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs_;
   bool factored_ = false;
   int tape_steps_ = -1;
+  bool last_seg_ok_ = true;   // uniform schedule: the last segment's stage fields are in their buffer
   int ckpt_mode_ = SPS_CKPT_UNIFORM, rv_slots_ = 0, rv_cap_ = 0;
   cplx* rv_ = nullptr;   // binomial schedule's stored states
   cplx* Xs_ = nullptr;   // working state of a two-level segment's forward actions

@@ -653,11 +653,15 @@ class ShProblem : public ProblemImpl {
     ShRun a{RUN_COST, max_steps_ + 1, nullptr, nullptr, nullptr, nullptr, J, reinterpret_cast<cplx*>(dJdX)};
     run(a);
   }
-  void gradient(const double* X0, int nsteps, double* XN, double* dJdX0, double* J) override {
+  void gradient(const double* X0, int nsteps, const double* dJdXN, double* XN, double* dJdX0, double* dJdtheta,
+                double* J) override {
     SPS_REQUIRE(X0 && dJdX0, "null argument");
     SPS_REQUIRE(nsteps >= 1 && nsteps <= max_steps_, "nsteps out of range");
-    ShRun a{RUN_FWD | RUN_COST | RUN_ADJ, nsteps, reinterpret_cast<const cplx*>(X0), reinterpret_cast<cplx*>(XN),
-            nullptr, reinterpret_cast<cplx*>(dJdX0), J, nullptr};
+    if (dJdtheta) throw Error(SPS_E_UNSUPPORTED, "the Swift-Hohenberg batch has no parameter gradients");
+    // an upstream cotangent replaces the cost phase: the reverse sweep starts from dJdXN
+    ShRun a{dJdXN ? (RUN_FWD | RUN_ADJ) : (RUN_FWD | RUN_COST | RUN_ADJ), nsteps, reinterpret_cast<const cplx*>(X0),
+            reinterpret_cast<cplx*>(XN), reinterpret_cast<const cplx*>(dJdXN), reinterpret_cast<cplx*>(dJdX0), J,
+            nullptr};
     run(a);
     tape_steps_ = nsteps;
   }
@@ -867,9 +871,17 @@ class ShProblem : public ProblemImpl {
     double best = 1e30;
     int best_tc[4] = {1, 1, 1, 1}, best_trp[4] = {1, 1, 1, 1}, best_blocks = cus_, best_nt = 256;
     const int nsteps = std::min(4, max_steps_);
-    hipEvent_t e0, e1;
-    SPS_HIP(hipEventCreate(&e0));
-    SPS_HIP(hipEventCreate(&e1));
+    // the timing events are destroyed on every exit from the tuner, also by an exception
+    struct Events {
+      hipEvent_t e[2] = {nullptr, nullptr};
+      ~Events() {
+        for (hipEvent_t x : e)
+          if (x) (void)hipEventDestroy(x);
+      }
+    } ev;
+    SPS_HIP(hipEventCreate(&ev.e[0]));
+    SPS_HIP(hipEventCreate(&ev.e[1]));
+    hipEvent_t e0 = ev.e[0], e1 = ev.e[1];
     for (int nt : cand_nt)
       for (int bc : cand)
         for (int br : cand)
@@ -902,8 +914,6 @@ class ShProblem : public ProblemImpl {
               best_nt = nt;
             }
           }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     SPS_REQUIRE(best < 1e29, "no tile configuration fits this batch");
     schedule(best_tc, best_trp, best_blocks, best_nt);
     std::copy(best_tc, best_tc + 4, tc_by_size_);

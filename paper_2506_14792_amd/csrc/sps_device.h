@@ -1,5 +1,5 @@
 // Device helpers shared by the gfx950 kernels: complex FP64 arithmetic, a batched
-// mixed-radix (2/3/4) Stockham FFT staged through LDS, and wave64 lane utilities.
+// mixed-radix (2/3/4/6/8) Stockham FFT staged through LDS, and wave64 lane utilities.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -21,7 +21,7 @@ __device__ __forceinline__ cplx cmul_mi(cplx a) { return cmk(a.y, -a.x); }     /
 __device__ __forceinline__ cplx czero() { return cmk(0.0, 0.0); }
 
 // ---------------------------------------------------------------------------- FFT plan
-// n = product of radices; every radix is 2, 3 or 4.  Twiddles tw[t] = exp(-2 pi i t / n).
+// n = product of radices; every radix is 2, 3, 4, 6 or 8.  Twiddles tw[t] = exp(-2 pi i t / n).
 #include "fft_plan.h"
 
 // Radix-R DFT in registers: v_k <- sum_r v_r w^(r k), w = exp(sign 2 pi i / R)

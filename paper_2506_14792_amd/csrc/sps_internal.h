@@ -119,7 +119,11 @@ class ProblemImpl {
   virtual void step(double* X, int nsteps) = 0;
   virtual void adjoint_step(double* Xbar, int nsteps) = 0;
   virtual void cost(const double* X, double* J, double* dJdX) = 0;
-  virtual void gradient(const double* X0, int nsteps, double* XN, double* dJdX0, double* J) = 0;
+  // dJdXN (nullable): the cotangent of the final state from the caller (the reverse sweep starts
+  // there; J must then be null); null: the built-in cost J and its gradient.  dJdtheta (nullable):
+  // the gradient with respect to the problem's parameters, where the problem has them.
+  virtual void gradient(const double* X0, int nsteps, const double* dJdXN, double* XN, double* dJdX0,
+                        double* dJdtheta, double* J) = 0;
   virtual void initial_state(const double* grid, double* X) = 0;
   virtual void initial_state_adjoint(const double* Xbar, double* grid) = 0;
   virtual void eval_F(const double* X, double* F) = 0;

@@ -12,7 +12,8 @@ RK222, SBDF2, SBDF3, SBDF4, RK443 = 1, 2, 3, 4, 5
 CKPT_UNIFORM, CKPT_BINOMIAL, CKPT_TWO_LEVEL = 0, 1, 2
 
 _STATUS = {0: "SPS_OK", -1: "SPS_E_ARG", -2: "SPS_E_NOMEM", -3: "SPS_E_HIP", -4: "SPS_E_SINGULAR",
-           -5: "SPS_E_NONFINITE", -6: "SPS_E_STATE", -7: "SPS_E_UNSUPPORTED"}
+           -5: "SPS_E_NONFINITE", -6: "SPS_E_STATE", -7: "SPS_E_UNSUPPORTED", -8: "SPS_E_NOCONV",
+           -9: "SPS_E_IO"}
 
 
 class SpsDesc(ctypes.Structure):
@@ -48,7 +49,7 @@ def lib():
         "sps_step": (ctypes.c_int, [_P, _D, ctypes.c_int]),
         "sps_adjoint_step": (ctypes.c_int, [_P, _D, ctypes.c_int]),
         "sps_cost": (ctypes.c_int, [_P, _D, _D, _D]),
-        "sps_gradient": (ctypes.c_int, [_P, _D, ctypes.c_int, _D, _D, _D]),
+        "sps_gradient": (ctypes.c_int, [_P, _D, ctypes.c_int, _D, _D, _D, _D, _D]),
         "sps_initial_state": (ctypes.c_int, [_P, _D, _D]),
         "sps_initial_state_adjoint": (ctypes.c_int, [_P, _D, _D]),
         "sps_eval_F": (ctypes.c_int, [_P, _D, _D]),
@@ -188,10 +189,13 @@ class Problem:
     def cost(self, X, J, dJdX):
         _check(lib().sps_cost(self._h, _ptr(X, self.n), _ptr(J, 1), _ptr(dJdX, self.n)))
 
-    def gradient(self, X0, nsteps, XN, dJdX0, J):
+    # number of parameters of dJdtheta (problems with parameter gradients set it)
+    nparam_grad = 0
+
+    def gradient(self, X0, nsteps, XN, dJdX0, J, dJdXN=None, dJdtheta=None):
         self.tape_id += 1
-        _check(lib().sps_gradient(self._h, _ptr(X0, self.n), nsteps, _ptr(XN, self.n), _ptr(dJdX0, self.n),
-                                  _ptr(J, 1)))
+        _check(lib().sps_gradient(self._h, _ptr(X0, self.n), nsteps, _ptr(dJdXN, self.n), _ptr(XN, self.n),
+                                  _ptr(dJdX0, self.n), _ptr(dJdtheta, self.nparam_grad or None), _ptr(J, 1)))
 
     def initial_state(self, grid, X):
         _check(lib().sps_initial_state(self._h, _ptr(grid), _ptr(X, self.n)))
@@ -339,10 +343,10 @@ class ShBatch(Problem):
     def cost(self, X, J, dJdX):
         _check(lib().sps_cost(self._h, _ptr(X, self.n), _ptr(J, self.batch), _ptr(dJdX, self.n)))
 
-    def gradient(self, X0, nsteps, XN, dJdX0, J):
+    def gradient(self, X0, nsteps, XN, dJdX0, J, dJdXN=None):
         self.tape_id += 1
-        _check(lib().sps_gradient(self._h, _ptr(X0, self.n), nsteps, _ptr(XN, self.n), _ptr(dJdX0, self.n),
-                                  _ptr(J, self.batch)))
+        _check(lib().sps_gradient(self._h, _ptr(X0, self.n), nsteps, _ptr(dJdXN, self.n), _ptr(XN, self.n),
+                                  _ptr(dJdX0, self.n), None, _ptr(J, self.batch)))
 
     def initial_state(self, grid, X):
         _check(lib().sps_initial_state(self._h, _ptr(grid, self.grid_size), _ptr(X, self.n)))

@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 from oracle import closure as cl
+import workloads
 
 pytestmark = pytest.mark.gpu
 
@@ -25,7 +26,7 @@ import paper_2506_14792_amd as sps  # noqa: E402
 
 def params(seed):
     rng = np.random.default_rng(seed)
-    p = cl.init_params(seed=seed, C=32, scale=1.0)
+    p = workloads.closure_params(seed=seed, C=32, scale=1.0)
     p["w3"] = p["w3"] * 100.0
     for k in ("b1", "b2", "b3"):
         p[k] = 0.2 * rng.standard_normal(p[k].shape)

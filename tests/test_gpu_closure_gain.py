@@ -34,7 +34,7 @@ def test_trained_closure_beats_no_closure():
     Str, Ste = S[:, :ntrain].contiguous(), S[:, ntrain:].contiguous()
     picks = [(s, b) for s in range(0, 401, 100) for b in range(ntest)]
     J_plain = ct.rollout_losses(Ste, picks, n, NC, RE, DRAG, DT, None)
-    theta0 = torch.from_numpy(cl.flatten(cl.init_params(seed=0, C=32, scale=1.0))).cuda()
+    theta0 = torch.from_numpy(workloads.closure_theta(seed=0, C=32, scale=1.0)).cuda()
     print("closure gain: training", flush=True)
     theta, losses = ct.train(Str, theta0, n, NC, RE, DRAG, DT, batch=8, iters=40, lr=1e-3,
                              starts=list(range(0, 401, 10)), seed=0)

@@ -1,5 +1,6 @@
-"""3D plane Couette flow on the GPU against the FP64 oracle (relative error <= 1e-11 of the largest
-magnitude per array), and the full 128 x 64 x 64 configuration's gradient against central
+"""3D plane Couette flow on the GPU against the FP64 oracle (error <= 1e-11 of each field's own
+largest entry: u_par, v, u_perp, p and the taus, the mean mode and the other modes apart, see
+tests/parity.py), and the full 128 x 64 x 64 configuration's gradient against central
 differences of the GPU's own forward runs.
 
 The library stores each mode's horizontal velocity in the frame of its wave vector,
@@ -13,6 +14,7 @@ import pytest
 import workloads as wl
 from oracle import imex
 from oracle.couette import Couette
+from parity import check_fields
 
 pytestmark = pytest.mark.gpu
 
@@ -64,6 +66,13 @@ def rel(a, b):
     return np.max(np.abs(a - b)) / np.max(np.abs(b))
 
 
+NAMES = ("u_par", "v", "u_perp", "p")
+
+
+def fields(got, ref, P, what, tol=1e-11):
+    return check_fields(got, ref, P.N, tol, what=what, names=NAMES)
+
+
 def state(P, seed, energy):
     c = wl.couette_perturbation(seed=seed, Nx=P.Nx, Ny=P.N, Nz=P.Nz, Lx=P.Lx, Lz=P.Lz, energy=energy,
                                 mmax=min(4, P.Kx), nmax=min(4, P.Nz // 2))
@@ -88,13 +97,12 @@ def test_couette_explicit_term_and_solve(cfg):
     X[:, 3 * P.N:] = 0.0
     F = torch.zeros(G.n, dtype=torch.float64, device="cuda")
     G.eval_F(dev(to_lib(P, X)), F)
-    ef = rel(host(F, P), to_lib(P, 2.0 * P.F(X)))
+    ef = fields(host(F, P), to_lib(P, 2.0 * P.F(X)), P, "F")
     Yb = wl.random_state(3, (P.K, P.S), real_first_row=False)
     Xb = torch.zeros_like(F)
     G.eval_F_vjp(dev(to_lib(P, X)), dev(to_lib(P, Yb, 1.0)), Xb)
-    ev = rel(host(Xb, P)[:, :3 * P.N], to_lib(P, 2.0 * P.F_vjp(X, Yb), 1.0)[:, :3 * P.N])
+    ev = fields(host(Xb, P)[:, :3 * P.N], to_lib(P, 2.0 * P.F_vjp(X, Yb), 1.0)[:, :3 * P.N], P, "F vjp")
     print(f"  F rel {ef:.2e}  F_vjp rel {ev:.2e}", flush=True)
-    assert ef <= 1e-11 and ev <= 1e-11
 
 
 @pytest.mark.parametrize("cfg", CFGS + [BIG], ids=["8x12x8", "24x16x12", "64x16x48-streamed"])
@@ -114,19 +122,19 @@ def test_couette_forward_and_gradient(cfg):
     J = torch.zeros(1, dtype=torch.float64, device="cuda")
     G.gradient(Xd, n, XNg, g, J)
     G.sync()
-    ex = rel(host(XNg, P), to_lib(P, XN))
-    eg = rel(host(g, P), to_lib(P, go, 1.0))
+    ex = fields(host(XNg, P), to_lib(P, XN), P, "X_N")
+    eg = fields(host(g, P), to_lib(P, go, 1.0), P, "dJ/dX0")
     eJ = abs(J.item() - Jo) / Jo
     print(f"  XN rel {ex:.2e}  J rel {eJ:.2e}  dJ/dX0 rel {eg:.2e}", flush=True)
-    assert ex <= 1e-11 and eJ <= 1e-11 and eg <= 1e-11
+    assert eJ <= 1e-11
     # the forward sweep alone, then the adjoint of the recorded run with an external cotangent
     X = Xd.clone()
     G.step(X, n)
     Xbar = dev(to_lib(P, P.energy_grad(XN), 1.0))
     G.adjoint_step(Xbar, n)
     G.sync()
-    assert rel(host(X, P), to_lib(P, XN)) <= 1e-11
-    assert rel(host(Xbar, P), to_lib(P, go, 1.0)) <= 1e-11
+    fields(host(X, P), to_lib(P, XN), P, "step X_N")
+    fields(host(Xbar, P), to_lib(P, go, 1.0), P, "adjoint_step dJ/dX0")
 
 
 def test_couette_full_size_gradient_central_differences():
@@ -193,9 +201,9 @@ def test_couette_energy_gain_through_autograd():
     E0, ET = P.energy(X0), P.energy(XN)
     gT = imex.rk_adjoint(P, P.energy_grad(XN), hist, dt)
     gref = gT / E0 - (ET / E0 ** 2) * P.energy_grad(X0)
-    eg = rel(host(g, P), to_lib(P, gref, 1.0))
+    eg = fields(host(g, P), to_lib(P, gref, 1.0), P, "gain gradient")
     print(f"  gain {J.item():.10f} vs {ET / E0:.10f}  gradient rel {eg:.2e}", flush=True)
-    assert abs(J.item() - ET / E0) <= 1e-11 * ET / E0 and eg <= 1e-11
+    assert abs(J.item() - ET / E0) <= 1e-11 * ET / E0
     d = dev(to_lib(P, state(P, 12, 1e-6)))
     eps = 1e-3
     with torch.no_grad():

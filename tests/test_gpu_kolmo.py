@@ -51,7 +51,7 @@ def rel(a, b):
 
 def params(seed):
     rng = np.random.default_rng(seed)
-    p = cl.init_params(seed=seed, C=32, scale=1.0)
+    p = workloads.closure_params(seed=seed, C=32, scale=1.0)
     p["w3"] = p["w3"] * 30.0
     for k in ("b1", "b2", "b3"):
         p[k] = 0.1 * rng.standard_normal(p[k].shape)

@@ -3,8 +3,9 @@
 the solve and the adjoint at three sizes, the LBVP-then-IVP gradient (sps_lbvp_solve,
 sps_gradient, sps_lbvp_adjoint) against the oracle's chain, and the same chain at the full
 256 x 64 configuration through torch.autograd against central differences of GPU runs.
-Tolerance: 1e-11 in max|gpu - oracle| / max|oracle| per array (L is conditioned at about 1e5
-at 256 x 64)."""
+Tolerance: 1e-11 of each field's own largest entry (u, w, b, p and the taus, the k = 0 row
+and the rows k >= 1 apart, the solution with the conduction state subtracted; tests/parity.py)
+(L is conditioned at about 1e5 at 256 x 64)."""
 import sys
 
 import numpy as np
@@ -13,6 +14,7 @@ import pytest
 import workloads as wl
 from oracle import imex
 from oracle.rbc import RBC
+from parity import check_fields
 
 pytestmark = pytest.mark.gpu
 
@@ -79,12 +81,12 @@ def test_lbvp_solve_and_adjoint(cfg):
     G.lbvp_solve(to_dev(f), X)
     G.lbvp_adjoint(to_dev(Xb), fb)
     G.sync()
-    ex = rel(from_dev(X, shape), P.lbvp_solve(f))
+    base = P.lbvp_solve(np.zeros(shape, complex))
+    ex = check_fields(from_dev(X, shape), P.lbvp_solve(f), P.Nz, TOL, base=base, what="LBVP X")
     ref = P.lbvp_adjoint(Xb)
     got = from_dev(fb, shape)
-    ea = rel(got, ref)
+    ea = check_fields(got[:, :3 * P.N], ref[:, :3 * P.N], P.Nz, TOL, what="LBVP fbar")
     note(f"  X rel {ex:.2e}  fbar rel {ea:.2e}")
-    assert ex <= TOL and ea <= TOL
     assert np.abs(got[:, 3 * P.N:]).max() == 0.0
     # a second call reuses the factors and gives the same result bit for bit
     X2 = torch.zeros_like(X)
@@ -114,9 +116,9 @@ def test_lbvp_then_ivp_gradient_against_oracle():
     G.lbvp_adjoint(g, fb)
     G.sync()
     eJ = abs(J.item() - Jo) / Jo
-    ef = rel(from_dev(fb, shape), fbo)
+    ef = check_fields(from_dev(fb, shape)[:, :3 * P.N], fbo[:, :3 * P.N], P.Nz, TOL, what="dJ/df")
     note(f"  J {J.item():.6e} rel {eJ:.2e}  dJ/df rel {ef:.2e}")
-    assert eJ <= TOL and ef <= TOL
+    assert eJ <= TOL
 
 
 def test_lbvp_chain_full_size_autograd_central_differences():

@@ -4,6 +4,8 @@ This module draws random numbers and lays them out on the problem's grid points;
 it holds none of the solver's arithmetic (no transforms, operators or timesteps).
 All generators use numpy's PCG64 (numpy.random.default_rng(seed)) in FP64.
 """
+import math
+
 import numpy as np
 
 
@@ -148,3 +150,29 @@ def couette_perturbation(seed=0, Nx=128, Ny=64, Nz=64, Lx=4.0 * np.pi, Lz=2.0 * 
             integ = C.chebint(sq)
             e += 0.5 * Lx * Lz * wm * (C.chebval(1.0, integ) - C.chebval(-1.0, integ))
     return out * np.sqrt(energy / e)
+
+
+CLOSURE_PARAM_ORDER = ("w1", "b1", "w2", "b2", "w3", "b3")
+
+
+def closure_params(seed=0, C=32, scale=1.0):
+    """Seeded initial weights of the closure network (3x3 convolutions 1 -> C -> C -> 1):
+    He-style normal draws for w1 and w2, a last layer 1e-2 smaller so that the network starts
+    as a small perturbation of the explicit term, zero biases.  Returns a dict of arrays with
+    the shapes w1 (C, 1, 3, 3), b1 (C,), w2 (C, C, 3, 3), b2 (C,), w3 (1, C, 3, 3), b3 (1,)."""
+    rng = np.random.default_rng(seed)
+    return {
+        "w1": rng.standard_normal((C, 1, 3, 3)) * math.sqrt(2.0 / 9.0) * scale,
+        "b1": np.zeros(C),
+        "w2": rng.standard_normal((C, C, 3, 3)) * math.sqrt(2.0 / (9.0 * C)) * scale,
+        "b2": np.zeros(C),
+        "w3": rng.standard_normal((1, C, 3, 3)) * math.sqrt(1.0 / (9.0 * C)) * scale * 1e-2,
+        "b3": np.zeros(1),
+    }
+
+
+def closure_theta(seed=0, C=32, scale=1.0):
+    """closure_params as one FP64 vector in the library's parameter order (w1, b1, w2, b2, w3,
+    b3, each row-major)."""
+    p = closure_params(seed, C, scale)
+    return np.concatenate([np.asarray(p[k], dtype=np.float64).ravel() for k in CLOSURE_PARAM_ORDER])
