@@ -225,6 +225,18 @@ int sps_initial_state_adjoint(sps_problem *P, const double *Xbar, double *grid_b
 int sps_eval_F(sps_problem *P, const double *X, double *F);
 /* (dF/dX)^H Fbar at X. */
 int sps_eval_F_vjp(sps_problem *P, const double *X, const double *Fbar, double *Xbar);
+/* sps_eval_F for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same result, bit for bit, with
+ * the intermediates (x-spectral z-grid fields and nonlinear terms, 9 * K * Ngz complex values,
+ * Ngz = 3 nz / 2) in the library's static scratch of 2 MiB per GPU instead of the problem's
+ * workspace.  The call allocates nothing (no hipMalloc, no events): it launches three kernels on
+ * the problem's stream.  The scratch is looked up once per device (the device current when the
+ * problem was built) on the first call and held until the process ends; every call on a GPU
+ * shares it, so calls that overlap on one GPU (several streams or host threads) race and must be
+ * serialized by the caller.  SPS_E_ARG when the problem needs more than the 2 MiB (nx = 256,
+ * nz = 64 needs 1.77 MB; nx = 324, nz = 64 is refused); SPS_E_UNSUPPORTED for problems other
+ * than SPS_RBC2D. */
+int sps_eval_F_noalloc(sps_problem *P, const double *X, double *F);
 /* Solve A x = r (adjoint = 0) or A^H x = r (adjoint = 1) with the current factors of the
  * scheme's implicit matrix (RK222: M + dt*gamma*L; RK443: M + dt/2 L; SBDF-k: a_0 M + L with the
  * steady a_0 = 3/2, 11/6, 25/12 over dt for k = 2, 3, 4). */

@@ -160,6 +160,10 @@ int sps_eval_F(sps_problem* P, const double* X, double* F) {
   return guard(P, [&](sps::ProblemImpl& p) { p.eval_F(X, F); });
 }
 
+int sps_eval_F_noalloc(sps_problem* P, const double* X, double* F) {
+  return guard(P, [&](sps::ProblemImpl& p) { p.eval_F_noalloc(X, F); });
+}
+
 int sps_eval_F_vjp(sps_problem* P, const double* X, const double* Fbar, double* Xbar) {
   return guard(P, [&](sps::ProblemImpl& p) { p.eval_F_vjp(X, Fbar, Xbar); });
 }

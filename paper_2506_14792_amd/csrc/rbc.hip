@@ -37,6 +37,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -47,7 +48,34 @@
 #include "sps_internal.h"
 #include "wave_fft.h"
 
+// Scratch of the allocation-free explicit-term evaluation (sps_eval_F_noalloc): the x-spectral
+// z-grid fields and the nonlinear terms of one evaluation.  One copy per GPU that the library
+// runs on, held until the process ends.  Host code never passes this name to a kernel (on the
+// host it is a stand-in, not a device address); it uses the per-device address from
+// hipGetSymbolAddress (sps::scratch_address).
+constexpr size_t SPS_SCRATCH_BYTES = size_t(2) << 20;
+static __device__ __align__(256) double scratch[SPS_SCRATCH_BYTES / sizeof(double)];
+
 namespace sps {
+
+// Device address of `scratch` on device dev, looked up once per device with that device current.
+static double* scratch_address(int dev) {
+  static std::mutex mu;
+  static std::map<int, double*> addr;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(dev);
+  if (it != addr.end()) return it->second;
+  int cur = -1;
+  SPS_HIP(hipGetDevice(&cur));
+  if (cur != dev) SPS_HIP(hipSetDevice(dev));
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (cur != dev) SPS_HIP(hipSetDevice(cur));
+  if (e != hipSuccess || ptr == nullptr)
+    throw Error(SPS_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  addr.emplace(dev, static_cast<double*>(ptr));
+  return static_cast<double*>(ptr);
+}
 
 namespace {
 
@@ -2103,6 +2131,7 @@ class RbcProblem : public ProblemImpl {
     cost_scale_ = desc.lx;
     Kz_ = 1;
     ncost_ = 2;
+    SPS_HIP(hipGetDevice(&device_));
     init();
   }
 
@@ -2299,6 +2328,40 @@ class RbcProblem : public ProblemImpl {
     launch_kf(KF_ZGRID, reinterpret_cast<const cplx*>(X), nullptr, nullptr, zgA_);
     launch_xf(zgA_);
     launch_kf(KF_EVALF, nullptr, nullptr, reinterpret_cast<cplx*>(F), nullptr);
+  }
+
+  // eval_F with its intermediates in the library's static per-device scratch: no device
+  // allocation, no timer events, three launches on the problem's stream.  Calls that overlap
+  // on one GPU share the scratch and race.
+  void eval_F_noalloc(const double* X, double* F) override {
+    if (cou_) throw Error(SPS_E_UNSUPPORTED, "the allocation-free evaluation is built for the 2D problem");
+    SPS_REQUIRE(X && F, "null argument");
+    const size_t need = (size_t)9 * Ngz_ * K_ * sizeof(cplx);
+    if (need > SPS_SCRATCH_BYTES)
+      throw Error(SPS_E_ARG, "eval_F_noalloc: the problem needs " + std::to_string(need) +
+                                 " bytes of scratch, more than the library's " + std::to_string(SPS_SCRATCH_BYTES));
+    cplx* zg = reinterpret_cast<cplx*>(scratch_address(device_));
+    cplx* nl = zg + (size_t)6 * Ngz_ * K_;
+    KfArgs a;
+    a.X0 = reinterpret_cast<const cplx*>(X);
+    a.X1 = nullptr;
+    a.Xout = nullptr;
+    a.nl = nl;
+    a.F0 = nullptr;
+    a.zg = zg;
+    a.dt = dt_;
+    a.g = 1.0 - 1.0 / std::sqrt(2.0);
+    a.dl = 1.0 - 1.0 / (2.0 * a.g);
+    a.mode = KF_ZGRID;
+    hipLaunchKernelGGL(kfwd_fn(), dim3(K_), dim3(NTK), kf_lds(), stream, dv_, a);
+    SPS_CHECK_LAUNCH();
+    launch_xf_rows(zg, nl, stream);
+    a.X0 = nullptr;
+    a.Xout = reinterpret_cast<cplx*>(F);
+    a.zg = nullptr;
+    a.mode = KF_EVALF;
+    hipLaunchKernelGGL(kfwd_fn(), dim3(K_), dim3(NTK), kf_lds(), stream, dv_, a);
+    SPS_CHECK_LAUNCH();
   }
 
   void eval_F_vjp(const double* X, const double* Fbar, double* Xbar) override {
@@ -3255,6 +3318,7 @@ class RbcProblem : public ProblemImpl {
   bool graph_on_ = false, capturing_ = false;
   std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs_;
   bool factored_ = false;
+  int device_ = 0;   // the device current when the problem was built
   int tape_steps_ = -1;
   bool last_seg_ok_ = true;   // uniform schedule: the last segment's stage fields are in their buffer
   int ckpt_mode_ = SPS_CKPT_UNIFORM, rv_slots_ = 0, rv_cap_ = 0;

@@ -128,6 +128,9 @@ class ProblemImpl {
   virtual void initial_state_adjoint(const double* Xbar, double* grid) = 0;
   virtual void eval_F(const double* X, double* F) = 0;
   virtual void eval_F_vjp(const double* X, const double* Fbar, double* Xbar) = 0;
+  virtual void eval_F_noalloc(const double*, double*) {
+    throw Error(SPS_E_UNSUPPORTED, "the allocation-free evaluation is built for the 2D problem");
+  }
   virtual void solve(const double* R, double* X, int adjoint) = 0;
   virtual void stability(double, int, double*, double*, double*, double*) {
     throw Error(SPS_E_UNSUPPORTED, "the eigenvalue problem is built for the 2D problem");

@@ -54,6 +54,7 @@ def lib():
         "sps_initial_state_adjoint": (ctypes.c_int, [_P, _D, _D]),
         "sps_eval_F": (ctypes.c_int, [_P, _D, _D]),
         "sps_eval_F_vjp": (ctypes.c_int, [_P, _D, _D, _D]),
+        "sps_eval_F_noalloc": (ctypes.c_int, [_P, _D, _D]),
         "sps_solve": (ctypes.c_int, [_P, _D, _D, ctypes.c_int]),
         "sps_set_dt": (ctypes.c_int, [_P, ctypes.c_double]),
         "sps_set_checkpoint_file": (ctypes.c_int, [_P, ctypes.c_char_p]),
@@ -205,6 +206,9 @@ class Problem:
 
     def eval_F(self, X, F):
         _check(lib().sps_eval_F(self._h, _ptr(X, self.n), _ptr(F, self.n)))
+
+    def eval_F_noalloc(self, X, F):
+        _check(lib().sps_eval_F_noalloc(self._h, _ptr(X, self.n), _ptr(F, self.n)))
 
     def eval_F_vjp(self, X, Fbar, Xbar):
         _check(lib().sps_eval_F_vjp(self._h, _ptr(X, self.n), _ptr(Fbar, self.n), _ptr(Xbar, self.n)))
