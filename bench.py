@@ -551,7 +551,7 @@ def couette_timing():
                     checkpoint_every=c["checkpoint_every"], max_steps=n)
     uvw = wl.couette_perturbation(seed=c["seed"], Nx=c["nx"], Ny=c["ny"], Nz=c["nz"], Lx=c["Lx"], Lz=c["Lz"],
                                   energy=c["energy"])
-    x0 = torch.from_numpy(G.state_from_velocity(uvw)).cuda()
+    x0 = G.state_from_velocity(uvw)
 
     def one():
         x = x0.clone().requires_grad_(True)
@@ -668,6 +668,22 @@ def copy_calibration(nbytes=1 << 28, reps=5):
     print(json.dumps({"copy_calibration_bytes_per_dispatch": nbytes, "reps": reps}))
 
 
+def kernel_bytes(nx, nz):
+    """Algorithmic HBM bytes per launch of each stage kernel of the 2D problem (each operand
+    streamed once; factors in banded form): the per-wavenumber forward kernel (average of the
+    two RK222 stages, stage_kernel_bytes), the per-wavenumber adjoint kernel (factors, the six
+    z-grid cotangent columns, two state-size vectors in, one out, the nonlinear-term cotangents
+    out), and the grid-row kernels (forward: 6 spectra in, 3 out per row; adjoint: 6 primal
+    spectra and 3 cotangents in, 6 cotangents out per row)."""
+    K, N = nx // 2, nz
+    S, Ngz = 4 * N + 7, 3 * N // 2
+    kl, ku = 7, 20
+    factors = S * (kl + kl + ku + 1) * 8 + S * 4
+    kadj = K * (factors + 6 * Ngz * 16 + 2 * S * 16 + S * 16 + 3 * Ngz * 16)
+    return {"rbc_kfwd": stage_kernel_bytes(nx, nz), "rbc_kadj": kadj,
+            "rbc_xfwd": Ngz * 9 * K * 16, "rbc_xadj": Ngz * 15 * K * 16}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -749,11 +765,27 @@ def main():
     torch.cuda.synchronize()
     t5 = time.perf_counter()
     G.sync()
+    # the other stage kernels, one eager gradient each with the timer on that kernel class
+    per_kernel = {}
+    kb = kernel_bytes(c["nx"], c["nz"])
+    for kind, name in ((1, "rbc_kadj"), (2, "rbc_xfwd"), (3, "rbc_xadj")):
+        G.timer_enable(kind, True)
+        one_gradient()
+        torch.cuda.synchronize()
+        nk, msk = G.timer_read()
+        G.timer_enable(kind, False)
+        avg = msk / max(nk, 1)
+        per_kernel[name] = {"bytes_per_launch": kb[name], "avg_launch_ms": avg, "launches_timed": nk,
+                            "achieved_GBps": kb[name] / (avg * 1e-3) / 1e9,
+                            "frac": kb[name] / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS}
     sec = (t1 - t0) / args.steps
     grads_per_s = 1.0 / sec
     bytes_launch = stage_kernel_bytes(c["nx"], c["nz"])
     avg_ms = kern_ms / max(launches, 1)
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    per_kernel = dict({"rbc_kfwd": {"bytes_per_launch": bytes_launch, "avg_launch_ms": avg_ms,
+                                    "launches_timed": launches, "achieved_GBps": achieved,
+                                    "frac": achieved / HBM_PEAK_GBS}}, **per_kernel)
     # the same gradients with the launch sequence recorded once as a HIP graph and replayed
     G.set_graph(True)
     one_gradient()
@@ -804,7 +836,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "rbc_kfwd (RK222 stage: z-transforms, RHS, banded LU solve)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "bytes_per_launch": bytes_launch, "avg_launch_ms": avg_ms,
-                     "launches_timed": launches},
+                     "launches_timed": launches, "per_kernel": per_kernel},
         "cpu_baseline": cpu,
         "ks_config": ks,
         "sh_batched_config": sh,

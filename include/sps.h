@@ -30,6 +30,8 @@
 #ifndef SPS_H
 #define SPS_H
 
+#include <stddef.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -65,6 +67,17 @@ typedef struct {
   int checkpoint_every;  /* steps between stored checkpoints in the forward sweep */
   int max_steps;         /* largest nsteps accepted by sps_step / sps_gradient */
 } sps_desc;
+
+/* The caller's device allocator (for example a framework's caching allocator), used for every
+ * device allocation of the problems and networks built after the call: alloc_fn(bytes, ctx)
+ * returns a device pointer (NULL: the build fails with SPS_E_NOMEM), free_fn(ptr, ctx) returns
+ * it.  A handle allocates at build time (and on the first use of a feature that needs more
+ * memory: a second factor set, checkpoint slots, the parameter gradient's records), never per
+ * step; it frees its blocks in sps_destroy, after the device has finished the work that used
+ * them, through the functions that allocated them.  alloc_fn = free_fn = NULL returns to
+ * hipMalloc / hipFree.  Process-wide; set it while no other thread builds a problem.  SPS_E_ARG
+ * if only one function is given. */
+int sps_set_allocator(void *(*alloc_fn)(size_t bytes, void *ctx), void (*free_fn)(void *ptr, void *ctx), void *ctx);
 
 /* Build a problem: assembles the banded operators and transform tables on the host,
  * allocates device workspace and the checkpoint store (paper, Supplementary: Initial
@@ -116,6 +129,18 @@ int sps_sh_tuning(const sps_problem *P, int *col_tile, int *row_tile, int *block
  * sps_initial_state[_adjoint] return SPS_E_UNSUPPORTED (states are given as coefficients). */
 int sps_build_couette(int nx, int ny, int nz, double lx, double lz, double re, double dt, int checkpoint_every,
                       int max_steps, void *hip_stream, sps_problem **out);
+
+/* Plane Couette states (or cotangents) between the physical layout and the library's.
+ * Physical layout per mode (S = 4 ny + 7 complex slots): u, v, w, p (ny Chebyshev coefficients
+ * each), then the taus of the unscaled equations: first-order tau of u, v, w, second-order tau
+ * of u, v, w, tau_p.  Library layout: the one described for sps_build_couette (u_par, v, u_perp
+ * and the taus in the frame of the mode's wave vector, taus twice the unscaled ones).  to_library
+ * != 0 maps physical -> library, else library -> physical.  cotangent != 0 treats the arrays as
+ * cotangents (gradients) of states: the rotation is orthogonal, so velocities rotate alike, and
+ * the tau slots scale by the inverse factor.  in and out are device arrays of sps_state_size()
+ * doubles and must not overlap.  Asynchronous on the problem's stream.  SPS_E_UNSUPPORTED for
+ * other problems. */
+int sps_couette_frame(sps_problem *P, const double *in, double *out, int to_library, int cotangent);
 
 /* Batched 2D Kolmogorov flow in vorticity form on [0, 2 pi)^2, periodic:
  * omega_t + u . grad omega = nu Laplacian omega - drag omega - 4 cos 4y (+ closure),
@@ -203,9 +228,13 @@ int sps_cost(sps_problem *P, const double *X, double *J_out, double *dJdX);
  *  dJdX0 (output, required): the gradient with respect to the initial state, state layout.  It
  *        may be the same array as dJdXN (read first, then overwritten).
  *  dJdtheta (nullable, output): the gradient with respect to the problem's parameters (the
- *        efficient-gradient identity: minus the sum over steps of the adjoint variables against
- *        the parameter derivative of each stage's residual).  Problems without parameter
- *        gradients return SPS_E_UNSUPPORTED when it is not NULL.
+ *        efficient-gradient identity: minus the sum over steps and stages of the stage adjoints
+ *        against the parameter derivative of each stage's residual).  The 2D problem: two
+ *        doubles, dJ/dRa and dJ/dPr (L depends on them through nu = (Ra/Pr)^(-1/2) and
+ *        kappa = (Ra Pr)^(-1/2); M and F do not), with the uniform checkpoint schedule (the
+ *        recorded segments also keep each step's stage states: 2 states per step of a segment,
+ *        allocated on the first such call).  Other problems and schedules return
+ *        SPS_E_UNSUPPORTED when it is not NULL.
  *  J_out (nullable, output, one double): the built-in cost; must be NULL when dJdXN is given
  *        (SPS_E_ARG). */
 int sps_gradient(sps_problem *P, const double *X0, int nsteps, const double *dJdXN, double *XN, double *dJdX0,
@@ -394,10 +423,14 @@ int sps_lbvp_solve(sps_problem *P, const double *f, double *X);
  * layout.  Device arrays; asynchronous like every call. */
 int sps_lbvp_adjoint(sps_problem *P, const double *Xbar, double *fbar);
 
-/* Kernel timing of one kernel class inside the library (HIP events around each launch on
- * the problem's stream).  kind: 0 = per-wavenumber forward stage kernel (transforms in z,
- * RHS assembly, banded solve).  sps_timer_read returns launches and total milliseconds
- * since sps_timer_enable and resets the counters. */
+/* Kernel timing of one kernel class inside the library (HIP events stamped by each launch's
+ * dispatch on the problem's stream; launches on the auxiliary stream and inside graph capture
+ * are not timed).  kind: 0 = per-wavenumber forward stage kernel (transforms in z, RHS
+ * assembly, banded solve), 1 = per-wavenumber adjoint stage kernel (transposed solve, adjoint
+ * transforms), 2 = grid-row forward kernel (x transforms and products), 3 = grid-row adjoint
+ * kernel (their VJP); the 2D problem takes all four, other problems kind 0 where they have a
+ * timer.  One kind is followed at a time.  sps_timer_read returns launches and total
+ * milliseconds since sps_timer_enable and resets the counters. */
 int sps_timer_enable(sps_problem *P, int kind, int on);
 int sps_timer_read(sps_problem *P, long long *launches, double *total_ms);
 

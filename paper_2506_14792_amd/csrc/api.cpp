@@ -55,6 +55,11 @@ int cnn_guard(sps_cnn* C, F&& f) {
 
 namespace sps {
 
+AllocHooks& alloc_hooks() {
+  static AllocHooks h;
+  return h;
+}
+
 std::vector<double2> twiddles(int n) {
   std::vector<double2> t(n);
   const long double tau = 6.28318530717958647692528676655900577L;
@@ -101,6 +106,16 @@ bool fft_plan(int n, FftPlan* p) {
 }  // namespace sps
 
 extern "C" {
+
+int sps_set_allocator(void* (*alloc_fn)(size_t, void*), void (*free_fn)(void*, void*), void* ctx) {
+  if ((alloc_fn == nullptr) != (free_fn == nullptr))
+    return fail(SPS_E_ARG, "sps_set_allocator: give both functions or neither");
+  sps::AllocHooks& h = sps::alloc_hooks();
+  h.alloc = alloc_fn;
+  h.free = free_fn;
+  h.ctx = alloc_fn ? ctx : nullptr;
+  return SPS_OK;
+}
 
 int sps_build_problem(const sps_desc* desc, void* hip_stream, sps_problem** out) {
   if (!desc || !out) return fail(SPS_E_ARG, "null argument");
@@ -158,6 +173,10 @@ int sps_initial_state_adjoint(sps_problem* P, const double* Xbar, double* grid_b
 
 int sps_eval_F(sps_problem* P, const double* X, double* F) {
   return guard(P, [&](sps::ProblemImpl& p) { p.eval_F(X, F); });
+}
+
+int sps_couette_frame(sps_problem* P, const double* in, double* out, int to_library, int cotangent) {
+  return guard(P, [&](sps::ProblemImpl& p) { p.couette_frame(in, out, to_library, cotangent); });
 }
 
 int sps_eval_F_noalloc(sps_problem* P, const double* X, double* F) {

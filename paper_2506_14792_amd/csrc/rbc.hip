@@ -596,6 +596,7 @@ struct KfArgs {
   const cplx* nl;     // [3][Ngz][K] nonlinear terms in x-spectral, z-grid form
   cplx* F0;           // [K][3][N] S10 N-hat of stage 0
   cplx* zg;           // [6][Ngz][K] output x-spectral z-grid fields (may be null)
+  cplx* Xsave;        // second copy of the stage's new state (may be null)
   double dt, g, dl;   // dt, gamma, delta
   int mode;
 };
@@ -725,6 +726,7 @@ __global__ void __launch_bounds__(NTK) rbc_kfwd(RbcDev d, KfArgs a) {
     if (tid < S) {
       const cplx v = vA[tid];
       a.Xout[(size_t)k * S + tid] = v;
+      if (a.Xsave) a.Xsave[(size_t)k * S + tid] = v;
       if (mode == KF_STAGE2 && __any(!(isfinite(v.x) && isfinite(v.y))) && lane_id() == 0) atomicOr(d.err, 2);
     }
   }
@@ -1088,9 +1090,60 @@ struct KaArgs {
   cplx* acc;          // [K][S] M^H (Y1 + Y2)
   cplx* Ybuf;         // [K][S] Y2
   cplx* nlbar;        // [3][Ngz][K]
+  const cplx* Xs1;    // parameter gradient (KA_B, may be null): the step's stage-1 state
+  const cplx* Xs2;    //   and its new state
+  double* pacc;       //   [K][2] accumulated dJ/dnu, dJ/dkappa of each wavenumber
   double dt, g, dl;
   int flags;
 };
+
+// Row s < 3N of (dL/dp) X for p = nu (u, w rows) or kappa (b rows): the viscous or diffusive
+// operator -(DZZ - kx^2 S10) of the row's field and its lifted first-order tau.
+__device__ __forceinline__ cplx dl_row(const RbcDev& d, int k, const cplx* X, int s) {
+  const int N = d.N, f = s / N, n = s - f * N;
+  const double kx = d.kx[k];
+  const cplx* c = X + f * N;
+  cplx v = cadd(cscale(dzz_at(c, n, N), -1.0), cscale(s10_at(c, n, N), kx * kx));
+  if (n == N - 2) v = csub(v, cscale(X[4 * N + f], 4.0));
+  return v;
+}
+
+// pacc[k] += -dt (<Y2, dL (g X2 + (1 - g) X1)> + g <Y1, dL X1>) for dL = dL/dnu, dL/dkappa: the
+// stage residuals' parameter derivatives against the stage adjoints (equ:efficient_gradient).
+// Y1, Y2, X1, X2 in LDS (ABI slots); red: 2 * (NTK / 64) doubles.  Block-wide.
+__device__ void param_accumulate(const RbcDev& d, const KaArgs& a, int k, const cplx* Y1, const cplx* Y2,
+                                 const cplx* X1, const cplx* X2, double* red) {
+  const int tid = threadIdx.x, N = d.N;
+  double cn = 0.0, ck = 0.0;
+  if (tid < 3 * N) {
+    const cplx l1 = dl_row(d, k, X1, tid), l2 = dl_row(d, k, X2, tid);
+    const double g = a.g;
+    const cplx t2 = cadd(cscale(l2, g), cscale(l1, 1.0 - g));
+    const cplx y1 = Y1[tid], y2 = Y2[tid];
+    const double v = (y2.x * t2.x + y2.y * t2.y) + g * (y1.x * l1.x + y1.y * l1.y);
+    if (tid < 2 * N) cn = v;
+    else ck = v;
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    cn += __shfl_xor(cn, o);
+    ck += __shfl_xor(ck, o);
+  }
+  const int wv = tid >> 6;
+  if ((tid & 63) == 0) {
+    red[2 * wv] = cn;
+    red[2 * wv + 1] = ck;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double sn = 0.0, sk = 0.0;
+    for (int w = 0; w < NTK / 64; ++w) {
+      sn += red[2 * w];
+      sk += red[2 * w + 1];
+    }
+    a.pacc[2 * k] -= a.dt * sn;
+    a.pacc[2 * k + 1] -= a.dt * sk;
+  }
+}
 
 // The zbar entries of mirror pair (f, j) = (tid / Hc, tid % Hc), f < 6, read by each thread at
 // kernel start (6 Hc <= NTK).
@@ -1185,12 +1238,18 @@ __global__ void __launch_bounds__(NTK) rbc_kadj(RbcDev d, KaArgs a) {
   cplx* p_t = y2;                                       // S  (Y1 + Y2)
   cplx* p_g = pqz;                                      // S  cotangent of F
   cplx* p_nh = p_g + S;                                 // 3*N
+  cplx* p_x1 = p_nh + 3 * N;                            // S  (parameter gradient: X1, X2)
+  cplx* p_x2 = p_x1 + S;                                // S
+  double* p_red = reinterpret_cast<double*>(p_x2 + S);  // 2 * NTK / 64
 
   // global reads in the order they are needed, the block operators last
   const bool in_x = (fl & (KA_SOLVE_T | KA_G)) || ((fl & KA_A) && !(fl & KA_C));
   const cplx xin = (in_x && sl) ? a.Xb_in[ks] : czero();
   const cplx accv = ((fl & KA_C) && a.acc && sl) ? a.acc[ks] : czero();
   const cplx y2v = ((fl & KA_B) && sl) ? a.Ybuf[ks] : czero();
+  const bool par = (fl & KA_B) && a.pacc;
+  const cplx x1v = (par && sl) ? a.Xs1[ks] : czero();
+  const cplx x2v = (par && sl) ? a.Xs2[ks] : czero();
   const ZbarPair zp = load_zbar_pair(d, a, k, (fl & (KA_C | KA_B)) != 0);
   const double cosr = (tid < 4 * Ngz) ? d.cosz[tid] : 0.0;
   OpsRegs opsr;
@@ -1260,8 +1319,13 @@ __global__ void __launch_bounds__(NTK) rbc_kadj(RbcDev d, KaArgs a) {
     if (sl) {
       p_y2[tid] = y2v;
       p_t[tid] = cadd(vB[tid], y2v);
+      if (par) {
+        p_x1[tid] = x1v;
+        p_x2[tid] = x2v;
+      }
     }
     __syncthreads();
+    if (par) param_accumulate(d, a, k, vB, p_y2, p_x1, p_x2, p_red);
     if (sl) {
       const MLRow t = mlt_col(d, k, p_t, tid);
       a.acc[ks] = t.m;
@@ -1883,6 +1947,64 @@ __global__ void __launch_bounds__(NT) rbc_cost(RbcDev d, const cplx* X, cplx* Xb
   if (tid == 0) Jpart[k] = 0.5 * d.cost_scale * wk * red[0];
 }
 
+// Plane Couette states between the physical layout (u, v, w, p; taus of u, v, w first order,
+// then second order, then tau_p) and the library's (u_par, v, u_perp, p; the same taus in the
+// wave-vector frame, scaled to unit wall distance).  e[k] = (kx, kz) / |(kx, kz)| of mode k
+// ((1, 0) at the mean mode).  One thread per (mode, index): index n < N takes the four
+// coefficients of mode n, index N + t the first-order (t = 0) or second-order (t = 1) taus, or
+// tau_p (t = 2).  to_lib: rotate into the frame and multiply the taus by tscale; else rotate
+// back and divide them by tscale.
+__global__ void cou_frame(int K, int N, const double2* e, const cplx* in, cplx* out, int to_lib, double tscale) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int S = 4 * N + 7, per = N + 3;
+  if (i >= K * per) return;
+  const int k = i / per, idx = i - k * per;
+  const double ex = e[k].x, ez = e[k].y;
+  const cplx* a = in + (size_t)k * S;
+  cplx* o = out + (size_t)k * S;
+  auto rot = [&](int s0, int s2, double sc) {
+    const cplx u = a[s0], w = a[s2];
+    if (to_lib) {
+      o[s0] = cscale(cadd(cscale(u, ex), cscale(w, ez)), sc);
+      o[s2] = cscale(cadd(cscale(u, -ez), cscale(w, ex)), sc);
+    } else {
+      o[s0] = cscale(cadd(cscale(u, ex), cscale(w, -ez)), sc);
+      o[s2] = cscale(cadd(cscale(u, ez), cscale(w, ex)), sc);
+    }
+  };
+  const double ts = to_lib ? tscale : 1.0 / tscale;
+  if (idx < N) {
+    rot(idx, 2 * N + idx, 1.0);
+    o[N + idx] = a[N + idx];
+    o[3 * N + idx] = a[3 * N + idx];
+  } else if (idx < N + 2) {
+    const int b = 4 * N + 3 * (idx - N);
+    rot(b, b + 2, ts);
+    o[b + 1] = cscale(a[b + 1], ts);
+  } else {
+    o[4 * N + 6] = cscale(a[4 * N + 6], ts);
+  }
+}
+
+__global__ void fill_zero(double* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+// out[0] = dJ/dRa, out[1] = dJ/dPr from the per-wavenumber dJ/dnu, dJ/dkappa (summed over k in
+// order by one thread, so the result does not depend on scheduling) and the chain-rule factors.
+__global__ void rbc_param_finish(const double* pacc, int K, double nu_ra, double ka_ra, double nu_pr, double ka_pr,
+                                 double* out) {
+  if (threadIdx.x != 0) return;
+  double sn = 0.0, sk = 0.0;
+  for (int k = 0; k < K; ++k) {
+    sn += pacc[2 * k];
+    sk += pacc[2 * k + 1];
+  }
+  out[0] = nu_ra * sn + ka_ra * sk;
+  out[1] = nu_pr * sn + ka_pr * sk;
+}
+
 __global__ void sum_parts(const double* part, int n, double* out) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     double s = 0.0;
@@ -2185,6 +2307,14 @@ class RbcProblem : public ProblemImpl {
       unode[j] = -(double)cosl(3.14159265358979323846264338327950288L * (2 * j + 1) / (2.0L * Ngz_));
     CouetteGeom g{Kx, c.nz, Ngx_, 3 * c.nz / 2, Ngz_, lx, lz, unode.data(), 2.0};
     planes_.reset(new CouettePlanes(g, stream));
+    std::vector<double2> fr(K_);
+    for (int m = 0; m < Kx; ++m)
+      for (int n = 0; n < c.nz; ++n) {
+        const int ns = (n < c.nz / 2) ? n : n - c.nz;
+        const double kx = 2.0 * M_PI * m / c.lx, kz = 2.0 * M_PI * ns / c.lz, kh = std::hypot(kx, kz);
+        fr[m * c.nz + n] = kh > 0.0 ? make_double2(kx / kh, kz / kh) : make_double2(1.0, 0.0);
+      }
+    frame_ = arena_.upload(fr, stream);
     init();
   }
 
@@ -2241,6 +2371,18 @@ class RbcProblem : public ProblemImpl {
     forward(reinterpret_cast<cplx*>(X), nsteps);
   }
 
+  // plane Couette: physical (u, v, w) layout <-> the library's wave-vector frame; a state's taus
+  // are twice the physical ones in the library (unit wall distance), a cotangent's half
+  void couette_frame(const double* in, double* out, int to_lib, int cotangent) override {
+    if (!cou_) throw Error(SPS_E_UNSUPPORTED, "the frame conversion is for plane Couette states");
+    SPS_REQUIRE(in && out, "null argument");
+    const int n = K_ * (N_ + 3);
+    hipLaunchKernelGGL(cou_frame, dim3((n + NT - 1) / NT), dim3(NT), 0, stream, K_, N_, frame_,
+                       reinterpret_cast<const cplx*>(in), reinterpret_cast<cplx*>(out), to_lib ? 1 : 0,
+                       cotangent ? 0.5 : 2.0);
+    SPS_CHECK_LAUNCH();
+  }
+
   void adjoint_step(double* Xbar, int nsteps) override {
     SPS_REQUIRE(Xbar != nullptr, "Xbar is null");
     if (tape_steps_ != nsteps) throw Error(SPS_E_STATE, "adjoint_step: nsteps does not match the recorded forward run");
@@ -2267,22 +2409,30 @@ class RbcProblem : public ProblemImpl {
                 double* J) override {
     SPS_REQUIRE(X0 && dJdX0, "null argument");
     SPS_REQUIRE(nsteps >= 1 && nsteps <= desc_.max_steps, "nsteps out of range");
-    if (dJdtheta) throw Error(SPS_E_UNSUPPORTED, "parameter gradients are not available for this problem");
+    if (dJdtheta) {
+      if (cou_) throw Error(SPS_E_UNSUPPORTED, "parameter gradients are built for the 2D problem");
+      if (ckpt_mode_ != SPS_CKPT_UNIFORM)
+        throw Error(SPS_E_UNSUPPORTED, "parameter gradients need the uniform checkpoint schedule");
+      if (!sst_) {
+        sst_ = arena_.alloc<cplx>((size_t)2 * seglen_ * 2 * K_ * S_);
+        pacc_ = arena_.alloc<double>((size_t)2 * K_);
+      }
+    }
     factor();
     if (graph_on_ && ckpt_mode_ != SPS_CKPT_TWO_LEVEL) {
-      const GraphKey key{X0, dJdXN, XN, dJdX0, J, nsteps};
+      const GraphKey key{X0, dJdXN, XN, dJdX0, dJdtheta, J, nsteps};
       for (const auto& g : graphs_)
         if (g.first == key) {
           SPS_HIP(hipGraphLaunch(g.second, stream));
           after_graph_gradient(nsteps);
           return;
         }
-      graphs_.emplace_back(key, capture_gradient(X0, nsteps, dJdXN, XN, dJdX0, J));
+      graphs_.emplace_back(key, capture_gradient(X0, nsteps, dJdXN, XN, dJdX0, dJdtheta, J));
       SPS_HIP(hipGraphLaunch(graphs_.back().second, stream));
       after_graph_gradient(nsteps);
       return;
     }
-    gradient_launches(X0, nsteps, dJdXN, XN, dJdX0, J);
+    gradient_launches(X0, nsteps, dJdXN, XN, dJdX0, dJdtheta, J);
   }
 
   // the recorded-run state a replayed gradient leaves (as its eager launches would)
@@ -2293,7 +2443,16 @@ class RbcProblem : public ProblemImpl {
   }
 
   // the launch sequence of one gradient on `stream` (and the auxiliary stream)
-  void gradient_launches(const double* X0, int nsteps, const double* dJdXN, double* XN, double* dJdX0, double* J) {
+  void gradient_launches(const double* X0, int nsteps, const double* dJdXN, double* XN, double* dJdX0,
+                         double* dJdtheta, double* J) {
+    // the parameter gradient records the stage states of every recorded step and accumulates
+    // over the reverse sweep; it is on for this gradient only
+    param_on_ = dJdtheta != nullptr;
+    theta_out_ = dJdtheta;
+    struct Off {
+      RbcProblem* p;
+      ~Off() { p->param_on_ = false; p->theta_out_ = nullptr; }
+    } off{this};
     SPS_HIP(hipMemcpyAsync(Xg_, X0, sizeof(cplx) * K_ * S_, hipMemcpyDeviceToDevice, stream));
     forward(Xg_, nsteps);
     if (XN) SPS_HIP(hipMemcpyAsync(XN, Xg_, sizeof(cplx) * K_ * S_, hipMemcpyDeviceToDevice, stream));
@@ -2342,7 +2501,7 @@ class RbcProblem : public ProblemImpl {
                                  " bytes of scratch, more than the library's " + std::to_string(SPS_SCRATCH_BYTES));
     cplx* zg = reinterpret_cast<cplx*>(scratch_address(device_));
     cplx* nl = zg + (size_t)6 * Ngz_ * K_;
-    KfArgs a;
+    KfArgs a{};
     a.X0 = reinterpret_cast<const cplx*>(X);
     a.X1 = nullptr;
     a.Xout = nullptr;
@@ -2613,8 +2772,13 @@ class RbcProblem : public ProblemImpl {
   static constexpr size_t kHessLdsMax = 160 * 1024;
 
   void timer_enable(int kind, bool on) override {
-    SPS_REQUIRE(kind == 0, "unknown timer kind");
+    SPS_REQUIRE(kind >= 0 && kind <= 3, "unknown timer kind");
+    timer_kind_ = kind;
     timer_.enable(on);
+  }
+  // the timer's event pair for a launch of kernel class `kind` on stream s, if it is timed
+  bool timed(int kind, hipStream_t s, hipEvent_t* e0, hipEvent_t* e1) {
+    return kind == timer_kind_ && s == stream && !capturing_ && timer_.take(e0, e1);
   }
   void timer_read(long long* launches, double* ms) override { timer_.read(launches, ms); }
 
@@ -2646,7 +2810,7 @@ class RbcProblem : public ProblemImpl {
   }
   size_t ka_lds() const {
     const size_t pre = sizeof(double) * 4 * Ngz_ + sizeof(cplx) * (2 * S_ + 12 * half_nodes(Ngz_) + 9 * N_);
-    const size_t post = sizeof(double) * 4 * Ngz_ + sizeof(cplx) * (3 * S_ + 3 * N_);
+    const size_t post = sizeof(double) * (4 * Ngz_ + 2 * NTK / 64) + sizeof(cplx) * (5 * S_ + 3 * N_);
     return sizeof(cplx) * (2 * S_ + SPS_PAD) + std::max({pre, post, ops_bytes()});
   }
   size_t xf_lds() const { return sizeof(cplx) * (9 * K_ + 2 * fpad_size(4 * Ngx_) + Ngx_); }
@@ -2655,17 +2819,17 @@ class RbcProblem : public ProblemImpl {
   // ----------------------------------------------------------------- graphs
   struct GraphKey {
     const double *X0, *dJN;
-    double *XN, *dJ, *J;
+    double *XN, *dJ, *th, *J;
     int nsteps;
     bool operator==(const GraphKey& o) const {
-      return X0 == o.X0 && dJN == o.dJN && XN == o.XN && dJ == o.dJ && J == o.J && nsteps == o.nsteps;
+      return X0 == o.X0 && dJN == o.dJN && XN == o.XN && dJ == o.dJ && th == o.th && J == o.J && nsteps == o.nsteps;
     }
   };
   // Record one gradient into a graph: the launches go to a private capture stream (the
   // caller's stream may be the legacy null stream, which cannot be captured); the
   // auxiliary stream joins the capture through the events of the reverse sweep.
   hipGraphExec_t capture_gradient(const double* X0, int nsteps, const double* dJdXN, double* XN, double* dJdX0,
-                                  double* J) {
+                                  double* dJdtheta, double* J) {
     if (!cap_) SPS_HIP(hipStreamCreateWithFlags(&cap_, hipStreamNonBlocking));
     hipStream_t user = stream;
     stream = cap_;
@@ -2673,7 +2837,7 @@ class RbcProblem : public ProblemImpl {
     hipGraph_t graph = nullptr;
     SPS_HIP(hipStreamBeginCapture(cap_, hipStreamCaptureModeThreadLocal));
     try {
-      gradient_launches(X0, nsteps, dJdXN, XN, dJdX0, J);
+      gradient_launches(X0, nsteps, dJdXN, XN, dJdX0, dJdtheta, J);
     } catch (...) {
       (void)hipStreamEndCapture(cap_, &graph);
       if (graph) (void)hipGraphDestroy(graph);
@@ -2702,7 +2866,8 @@ class RbcProblem : public ProblemImpl {
   }
   // stage launches on the caller's stream are timed (on the auxiliary stream a launch may share
   // the chip with the adjoint sweep)
-  void launch_kf_on(hipStream_t s, int mode, const cplx* X0, const cplx* X1, cplx* Xout, cplx* zg) {
+  void launch_kf_on(hipStream_t s, int mode, const cplx* X0, const cplx* X1, cplx* Xout, cplx* zg,
+                    cplx* save = nullptr) {
     KfArgs a;
     a.X0 = X0;
     a.X1 = X1;
@@ -2710,12 +2875,13 @@ class RbcProblem : public ProblemImpl {
     a.nl = nl_;
     a.F0 = F0_;
     a.zg = zg;
+    a.Xsave = save;
     a.dt = dt_;
     a.g = 1.0 - 1.0 / std::sqrt(2.0);
     a.dl = 1.0 - 1.0 / (2.0 * a.g);
     a.mode = mode;
     hipEvent_t e0, e1;
-    if ((mode == KF_STAGE1 || mode == KF_STAGE2) && s == stream && !capturing_ && timer_.take(&e0, &e1))
+    if ((mode == KF_STAGE1 || mode == KF_STAGE2) && timed(0, s, &e0, &e1))
       hipExtLaunchKernelGGL(kfwd_fn(), dim3(K_), dim3(NTK), kf_lds(), s, e0, e1, 0, dv_, a);
     else
       hipLaunchKernelGGL(kfwd_fn(), dim3(K_), dim3(NTK), kf_lds(), s, dv_, a);
@@ -2731,9 +2897,11 @@ class RbcProblem : public ProblemImpl {
   // the grid-row forward kernel: one wave per FFT where the row length is 64 R1 (R1 = 3, 6)
   void launch_xf_rows(const cplx* zg, cplx* nl, hipStream_t s) {
     XfArgs a{zg, nl};
-    if (wave_r1_ == 6) hipLaunchKernelGGL(rbc_xfwd_w<6>, dim3(Ngz_), dim3(256), xfw_lds(), s, dv_, a);
-    else if (wave_r1_ == 3) hipLaunchKernelGGL(rbc_xfwd_w<3>, dim3(Ngz_), dim3(256), xfw_lds(), s, dv_, a);
-    else hipLaunchKernelGGL(rbc_xfwd, dim3(Ngz_), dim3(NTX), xf_lds(), s, dv_, a);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const bool t = timed(2, s, &e0, &e1);
+    if (wave_r1_ == 6) hipExtLaunchKernelGGL(rbc_xfwd_w<6>, dim3(Ngz_), dim3(256), xfw_lds(), s, t ? e0 : nullptr, t ? e1 : nullptr, 0, dv_, a);
+    else if (wave_r1_ == 3) hipExtLaunchKernelGGL(rbc_xfwd_w<3>, dim3(Ngz_), dim3(256), xfw_lds(), s, t ? e0 : nullptr, t ? e1 : nullptr, 0, dv_, a);
+    else hipExtLaunchKernelGGL(rbc_xfwd, dim3(Ngz_), dim3(NTX), xf_lds(), s, t ? e0 : nullptr, t ? e1 : nullptr, 0, dv_, a);
     SPS_CHECK_LAUNCH();
   }
   size_t xfw_lds() const { return sizeof(cplx) * (Ngx_ + 4 * wave_sc() + 4 * 512); }
@@ -2747,6 +2915,9 @@ class RbcProblem : public ProblemImpl {
     a.acc = acc_;
     a.Ybuf = Ybuf_;
     a.nlbar = nlbar_;
+    a.Xs1 = nullptr;
+    a.Xs2 = nullptr;
+    a.pacc = nullptr;
     a.dt = dt_;
     a.g = 1.0 - 1.0 / std::sqrt(2.0);
     a.dl = 1.0 - 1.0 / (2.0 * a.g);
@@ -2754,7 +2925,11 @@ class RbcProblem : public ProblemImpl {
     return a;
   }
   void launch_ka(const KaArgs& a) {
-    hipLaunchKernelGGL(kadj_fn(), dim3(K_), dim3(NTK), ka_lds(), stream, dv_, a);
+    hipEvent_t e0, e1;
+    if ((a.flags & (KA_A | KA_B)) && !(a.flags & KA_SOLVE_T) && timed(1, stream, &e0, &e1))
+      hipExtLaunchKernelGGL(kadj_fn(), dim3(K_), dim3(NTK), ka_lds(), stream, e0, e1, 0, dv_, a);
+    else
+      hipLaunchKernelGGL(kadj_fn(), dim3(K_), dim3(NTK), ka_lds(), stream, dv_, a);
     SPS_CHECK_LAUNCH();
   }
   void launch_xa(const cplx* zg) {
@@ -2763,9 +2938,12 @@ class RbcProblem : public ProblemImpl {
       return;
     }
     XaArgs a{nlbar_, zg, zbar_};
-    if (wave_r1_ == 6) hipLaunchKernelGGL(rbc_xadj_w<6>, dim3(Ngz_), dim3(384), xaw_lds(), stream, dv_, a);
-    else if (wave_r1_ == 3) hipLaunchKernelGGL(rbc_xadj_w<3>, dim3(Ngz_), dim3(384), xaw_lds(), stream, dv_, a);
-    else hipLaunchKernelGGL(rbc_xadj, dim3(Ngz_), dim3(NTX), xa_lds(), stream, dv_, a);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const bool t = timed(3, stream, &e0, &e1);
+    if (!t) e0 = e1 = nullptr;
+    if (wave_r1_ == 6) hipExtLaunchKernelGGL(rbc_xadj_w<6>, dim3(Ngz_), dim3(384), xaw_lds(), stream, e0, e1, 0, dv_, a);
+    else if (wave_r1_ == 3) hipExtLaunchKernelGGL(rbc_xadj_w<3>, dim3(Ngz_), dim3(384), xaw_lds(), stream, e0, e1, 0, dv_, a);
+    else hipExtLaunchKernelGGL(rbc_xadj, dim3(Ngz_), dim3(NTX), xa_lds(), stream, e0, e1, 0, dv_, a);
     SPS_CHECK_LAUNCH();
   }
 
@@ -2775,12 +2953,17 @@ class RbcProblem : public ProblemImpl {
 
   // One RK222 step from X (in place) on stream s.  zin: x-spectral z-grid fields of X;
   // zs1: where stage 1 writes its fields; zout: where the new state's fields go (or null).
-  void rk_step(hipStream_t s, cplx* X, const cplx* zin, cplx* zs1, cplx* zout) {
+  // save1, save2 (nullable): where the stage-1 state and the new state are also stored (the
+  // parameter gradient's records).
+  void rk_step(hipStream_t s, cplx* X, const cplx* zin, cplx* zs1, cplx* zout, cplx* save1 = nullptr,
+               cplx* save2 = nullptr) {
     launch_xf(zin, s);
-    launch_kf_on(s, KF_STAGE1, X, nullptr, X1_, zs1);
+    launch_kf_on(s, KF_STAGE1, X, nullptr, X1_, zs1, save1);
     launch_xf(zs1, s);
-    launch_kf_on(s, KF_STAGE2, X, X1_, X, zout);
+    launch_kf_on(s, KF_STAGE2, X, X1_, X, zout, save2);
   }
+  // state records of the parameter gradient: two buffers of (stage-1 state, new state) per step
+  cplx* sslot(int buf, int s, int q) { return sst_ + (((size_t)buf * seglen_ + s) * 2 + q) * K_ * S_; }
 
   void forward(cplx* X, int nsteps) {
     if (ckpt_mode_ == SPS_CKPT_BINOMIAL) {
@@ -2798,10 +2981,11 @@ class RbcProblem : public ProblemImpl {
     // fields of step n, stage q: a single rolling buffer (kernels are stream ordered) or,
     // inside the last segment, the segment store read back by the reverse sweep
     auto zpos = [&](int n, int q) { return (n >= last0) ? slot(lb, n - last0, q) : zgA_; };
+    auto spos = [&](int n, int q) { return (param_on_ && n >= last0) ? sslot(lb, n - last0, q) : nullptr; };
     launch_kf(KF_ZGRID, X, nullptr, nullptr, zpos(0, 0));
     for (int n = 0; n < nsteps; ++n) {
       if (n % ce == 0) SPS_HIP(hipMemcpyAsync(ckpt(n / ce), X, sizeof(cplx) * K_ * S_, hipMemcpyDeviceToDevice, stream));
-      rk_step(stream, X, zpos(n, 0), zpos(n, 1), (n + 1 < nsteps) ? zpos(n + 1, 0) : nullptr);
+      rk_step(stream, X, zpos(n, 0), zpos(n, 1), (n + 1 < nsteps) ? zpos(n + 1, 0) : nullptr, spos(n, 0), spos(n, 1));
     }
     tape_steps_ = nsteps;
     last_seg_ok_ = true;
@@ -2812,7 +2996,9 @@ class RbcProblem : public ProblemImpl {
     const int b = seg & 1;
     SPS_HIP(hipMemcpyAsync(Xw_, ckpt(seg), sizeof(cplx) * K_ * S_, hipMemcpyDeviceToDevice, s));
     launch_kf_on(s, KF_ZGRID, Xw_, nullptr, nullptr, slot(b, 0, 0));
-    for (int j = 0; j < len; ++j) rk_step(s, Xw_, slot(b, j, 0), slot(b, j, 1), (j + 1 < len) ? slot(b, j + 1, 0) : nullptr);
+    for (int j = 0; j < len; ++j)
+      rk_step(s, Xw_, slot(b, j, 0), slot(b, j, 1), (j + 1 < len) ? slot(b, j + 1, 0) : nullptr,
+              param_on_ ? sslot(b, j, 0) : nullptr, param_on_ ? sslot(b, j, 1) : nullptr);
   }
 
   // Reverse sweep.  The recompute of segment seg-1 (auxiliary stream, scratch X1_, Xw_, nl_, F0_,
@@ -2837,6 +3023,10 @@ class RbcProblem : public ProblemImpl {
     // recompute of segment nseg-3 overwrote the buffer that held the last segment's stage
     // fields (both use buffer (nseg-1)&1), so the last segment is recomputed first.
     if (!last_seg_ok_) recompute(nseg - 1, seglen(nseg - 1), stream);
+    if (param_on_) {
+      hipLaunchKernelGGL(fill_zero, dim3((2 * K_ + NT - 1) / NT), dim3(NT), 0, stream, pacc_, 2 * K_);
+      SPS_CHECK_LAUNCH();
+    }
     SPS_HIP(hipEventRecord(ev_fwd, stream));
     SPS_HIP(hipStreamWaitEvent(aux_, ev_fwd, 0));
     bool first = true;
@@ -2854,7 +3044,13 @@ class RbcProblem : public ProblemImpl {
         launch_ka(a);
         first = false;
         launch_xa(slot(b, j, 1));
-        launch_ka(ka_args(KA_B));
+        KaArgs ab = ka_args(KA_B);
+        if (param_on_) {
+          ab.Xs1 = sslot(b, j, 0);
+          ab.Xs2 = sslot(b, j, 1);
+          ab.pacc = pacc_;
+        }
+        launch_ka(ab);
         launch_xa(slot(b, j, 0));
       }
       SPS_HIP(hipEventRecord(ev_adj, stream));
@@ -2863,6 +3059,13 @@ class RbcProblem : public ProblemImpl {
     KaArgs a = ka_args(KA_C);
     a.Xb_out = Xbar;
     launch_ka(a);
+    if (param_on_) {
+      // dJ/dRa and dJ/dPr from dJ/dnu and dJ/dkappa: nu = (Ra/Pr)^(-1/2), kappa = (Ra Pr)^(-1/2)
+      const double Ra = desc_.param0, Pr = desc_.param1;
+      hipLaunchKernelGGL(rbc_param_finish, dim3(1), dim3(64), 0, stream, pacc_, K_, -0.5 * nu_ / Ra,
+                         -0.5 * ka_ / Ra, 0.5 * nu_ / Pr, -0.5 * ka_ / Pr, theta_out_);
+      SPS_CHECK_LAUNCH();
+    }
     // join the auxiliary stream explicitly (it may have waited without launching, nseg = 1)
     SPS_HIP(hipEventRecord(ev_rec, aux_));
     SPS_HIP(hipStreamWaitEvent(stream, ev_rec, 0));
@@ -3294,7 +3497,8 @@ class RbcProblem : public ProblemImpl {
   double nu_, ka_, dt_ = 0.0, cp_ = 1.0, bc0_ = 1.0, cost_scale_ = 1.0;
   int Kz_ = 1, ncost_ = 2;
   bool cou_ = false, stream_solve_ = false;
-  int wave_r1_ = 0;   // grid rows of 64 wave_r1_ points use the one-wave-per-FFT kernels
+  int wave_r1_ = 0;
+  const double2* frame_ = nullptr;   // plane Couette: unit wave vector of each mode   // grid rows of 64 wave_r1_ points use the one-wave-per-FFT kernels
   std::vector<double> kxs_;
   std::vector<unsigned char> ckeep_;
   std::unique_ptr<CouettePlanes> planes_;
@@ -3320,7 +3524,11 @@ class RbcProblem : public ProblemImpl {
   bool factored_ = false;
   int device_ = 0;   // the device current when the problem was built
   int tape_steps_ = -1;
-  bool last_seg_ok_ = true;   // uniform schedule: the last segment's stage fields are in their buffer
+  bool last_seg_ok_ = true;
+  bool param_on_ = false;          // this gradient also accumulates dJ/dRa, dJ/dPr
+  double* theta_out_ = nullptr;    // where they go
+  cplx* sst_ = nullptr;            // state records of the parameter gradient (sslot)
+  double* pacc_ = nullptr;         // [K][2] per-wavenumber dJ/dnu, dJ/dkappa   // uniform schedule: the last segment's stage fields are in their buffer
   int ckpt_mode_ = SPS_CKPT_UNIFORM, rv_slots_ = 0, rv_cap_ = 0;
   cplx* rv_ = nullptr;   // binomial schedule's stored states
   cplx* Xs_ = nullptr;   // working state of a two-level segment's forward actions
@@ -3338,6 +3546,7 @@ class RbcProblem : public ProblemImpl {
   int ckfd_ = -1;                               // disk level: the checkpoint file, or -1
   std::string ckpath_;
   KernelTimer timer_;
+  int timer_kind_ = 0;   // kernel class the timer follows (0 kfwd, 1 kadj, 2 x rows, 3 x rows adjoint)
 };
 
 }  // namespace

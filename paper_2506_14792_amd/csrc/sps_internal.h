@@ -30,19 +30,44 @@ struct Error : std::runtime_error {
     if (!(cond)) throw ::sps::Error(SPS_E_ARG, (msg));          \
   } while (0)
 
-// Device allocation owned by a problem; freed in the destructor.
+// The caller's device allocator (sps_set_allocator), process-wide; null functions: hipMalloc.
+struct AllocHooks {
+  void* (*alloc)(size_t, void*) = nullptr;
+  void (*free)(void*, void*) = nullptr;
+  void* ctx = nullptr;
+};
+AllocHooks& alloc_hooks();
+
+// Device allocation owned by a problem; freed in the destructor (through the allocator that
+// made each block).
 class DevArena {
  public:
   ~DevArena() {
-    for (void* p : ptrs_) (void)hipFree(p);
+    // hipFree waits for the device; a caller's free may not, so the work that used its blocks
+    // is finished first
+    bool hooked = false;
+    for (const Block& b : blocks_) hooked = hooked || b.free != nullptr;
+    if (hooked) (void)hipDeviceSynchronize();
+    for (const Block& b : blocks_) {
+      if (b.free) b.free(b.p, b.ctx);
+      else (void)hipFree(b.p);
+    }
   }
   template <typename T>
   T* alloc(size_t count) {
     void* p = nullptr;
     if (count == 0) count = 1;
-    if (hipMalloc(&p, count * sizeof(T)) != hipSuccess)
-      throw Error(SPS_E_NOMEM, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed");
-    ptrs_.push_back(p);
+    const size_t bytes = count * sizeof(T);
+    const AllocHooks h = alloc_hooks();
+    if (h.alloc) {
+      p = h.alloc(bytes, h.ctx);
+      if (!p) throw Error(SPS_E_NOMEM, "the caller's allocator returned no block of " + std::to_string(bytes) + " bytes");
+      blocks_.push_back({p, h.free, h.ctx});
+    } else {
+      if (hipMalloc(&p, bytes) != hipSuccess)
+        throw Error(SPS_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+      blocks_.push_back({p, nullptr, nullptr});
+    }
     return static_cast<T*>(p);
   }
   template <typename T>
@@ -54,7 +79,12 @@ class DevArena {
   }
 
  private:
-  std::vector<void*> ptrs_;
+  struct Block {
+    void* p;
+    void (*free)(void*, void*);
+    void* ctx;
+  };
+  std::vector<Block> blocks_;
 };
 
 // HIP-event timing of one kernel class: launches are bracketed by events from a pool
@@ -128,6 +158,9 @@ class ProblemImpl {
   virtual void initial_state_adjoint(const double* Xbar, double* grid) = 0;
   virtual void eval_F(const double* X, double* F) = 0;
   virtual void eval_F_vjp(const double* X, const double* Fbar, double* Xbar) = 0;
+  virtual void couette_frame(const double*, double*, int, int) {
+    throw Error(SPS_E_UNSUPPORTED, "the frame conversion is for plane Couette states");
+  }
   virtual void eval_F_noalloc(const double*, double*) {
     throw Error(SPS_E_UNSUPPORTED, "the allocation-free evaluation is built for the 2D problem");
   }

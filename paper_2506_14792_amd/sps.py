@@ -32,6 +32,9 @@ class SpsError(RuntimeError):
 _lib = None
 _P = ctypes.c_void_p
 _D = ctypes.c_void_p  # device double*
+_ALLOC_T = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_T = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+_alloc_refs = None   # the callbacks handed to the library (kept alive while installed)
 
 
 def lib():
@@ -43,6 +46,7 @@ def lib():
         raise RuntimeError(f"{LIB_PATH} is missing; build it with paper_2506_14792_amd/build.py")
     L = ctypes.CDLL(LIB_PATH)
     sig = {
+        "sps_set_allocator": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
         "sps_build_problem": (ctypes.c_int, [ctypes.POINTER(SpsDesc), _P, ctypes.POINTER(_P)]),
         "sps_state_size": (ctypes.c_longlong, [_P]),
         "sps_factor": (ctypes.c_int, [_P]),
@@ -55,6 +59,7 @@ def lib():
         "sps_eval_F": (ctypes.c_int, [_P, _D, _D]),
         "sps_eval_F_vjp": (ctypes.c_int, [_P, _D, _D, _D]),
         "sps_eval_F_noalloc": (ctypes.c_int, [_P, _D, _D]),
+        "sps_couette_frame": (ctypes.c_int, [_P, _D, _D, ctypes.c_int, ctypes.c_int]),
         "sps_solve": (ctypes.c_int, [_P, _D, _D, ctypes.c_int]),
         "sps_set_dt": (ctypes.c_int, [_P, ctypes.c_double]),
         "sps_set_checkpoint_file": (ctypes.c_int, [_P, ctypes.c_char_p]),
@@ -109,6 +114,32 @@ def lib():
     return L
 
 
+def use_torch_allocator(on=True):
+    """Device memory of the problems built from now on comes from torch's caching allocator
+    (sps_set_allocator with callbacks into torch.cuda.caching_allocator_alloc / _delete);
+    on=False returns to hipMalloc."""
+    global _alloc_refs
+    if not on:
+        _check(lib().sps_set_allocator(None, None, None))
+        _alloc_refs = None
+        return
+    import torch
+    dev = torch.cuda.current_device()
+
+    def alloc(nbytes, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), dev)
+        except Exception:   # out of memory: the library reports SPS_E_NOMEM
+            return None
+
+    def free(ptr, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    refs = (_ALLOC_T(alloc), _FREE_T(free))
+    _check(lib().sps_set_allocator(ctypes.cast(refs[0], ctypes.c_void_p), ctypes.cast(refs[1], ctypes.c_void_p), None))
+    _alloc_refs = refs
+
+
 def _check(rc):
     if rc != 0:
         raise SpsError(rc, lib().sps_last_error().decode())
@@ -152,6 +183,8 @@ def checkpoint_schedule(nsteps, slots):
 class Problem:
     """A built problem on the current HIP stream (torch.cuda.current_stream())."""
 
+    nparam_grad = 0   # length of dJdtheta (0: the problem has no parameter gradient)
+
     def __init__(self, equation, nx, nz=0, lx=1.0, param0=0.0, param1=0.0, dealias=1.5, dt=1e-3,
                  checkpoint_every=1, max_steps=1, scheme=None, stream=None):
         import torch
@@ -164,6 +197,8 @@ class Problem:
         self._h = h
         self.n = int(lib().sps_state_size(h))
         self.tape_id = 0   # advanced by every forward sweep; a reverse sweep needs the latest one
+        # the 2D problem's parameter gradient: (dJ/dRa, dJ/dPr)
+        self.nparam_grad = 2 if equation == RBC2D else 0
 
     def close(self):
         if getattr(self, "_h", None):
@@ -190,9 +225,6 @@ class Problem:
     def cost(self, X, J, dJdX):
         _check(lib().sps_cost(self._h, _ptr(X, self.n), _ptr(J, 1), _ptr(dJdX, self.n)))
 
-    # number of parameters of dJdtheta (problems with parameter gradients set it)
-    nparam_grad = 0
-
     def gradient(self, X0, nsteps, XN, dJdX0, J, dJdXN=None, dJdtheta=None):
         self.tape_id += 1
         _check(lib().sps_gradient(self._h, _ptr(X0, self.n), nsteps, _ptr(dJdXN, self.n), _ptr(XN, self.n),
@@ -206,6 +238,12 @@ class Problem:
 
     def eval_F(self, X, F):
         _check(lib().sps_eval_F(self._h, _ptr(X, self.n), _ptr(F, self.n)))
+
+    def frame(self, X, out, to_library=True, cotangent=False):
+        """Physical (u, v, w, p, taus) <-> library (u_par, v, u_perp, p, scaled taus) layout of a
+        state or of a cotangent (sps_couette_frame), device tensors of n doubles."""
+        _check(lib().sps_couette_frame(self._h, _ptr(X, self.n), _ptr(out, self.n), int(bool(to_library)),
+                                       int(bool(cotangent))))
 
     def eval_F_noalloc(self, X, F):
         _check(lib().sps_eval_F_noalloc(self._h, _ptr(X, self.n), _ptr(F, self.n)))
@@ -391,24 +429,18 @@ class Couette(Problem):
         self.tape_id = 0
         self.lx, self.lz = float(lx), float(lz)
 
-    def state_from_velocity(self, c):
-        """Input preparation on the host: (K, 3, ny) complex Chebyshev coefficients of (u, v, w)
-        per mode -> a float64 state in the library layout (u_par, v, u_perp; p and taus zero)."""
+    def state_from_velocity(self, c, cotangent=False):
+        """(K, 3, ny) complex Chebyshev coefficients of (u, v, w) per mode (host) -> a device state
+        in the library layout (p and taus zero): the coefficients are placed into the physical
+        layout on the host and rotated into the library's frame by sps_couette_frame."""
+        import torch
         K, N = self.K, self.ny
-        c = np.asarray(c).reshape(K, 3, N)
-        m = np.repeat(np.arange(self.nx // 2), self.nz)
-        n = np.tile(np.arange(self.nz), self.nx // 2)
-        kx = 2.0 * np.pi * m / self.lx
-        kz = 2.0 * np.pi * np.where(n < self.nz // 2, n, n - self.nz) / self.lz
-        kh = np.hypot(kx, kz)
-        safe = np.where(kh > 0, kh, 1.0)
-        ex = np.where(kh > 0, kx / safe, 1.0)[:, None]
-        ez = np.where(kh > 0, kz / safe, 0.0)[:, None]
         X = np.zeros((K, 4 * N + 7), complex)
-        X[:, :N] = ex * c[:, 0] + ez * c[:, 2]
-        X[:, N:2 * N] = c[:, 1]
-        X[:, 2 * N:3 * N] = -ez * c[:, 0] + ex * c[:, 2]
-        return np.ascontiguousarray(X).view(np.float64).ravel()
+        X[:, :3 * N] = np.asarray(c).reshape(K, 3 * N)
+        phys = torch.from_numpy(np.ascontiguousarray(X).view(np.float64).ravel().copy()).cuda()
+        out = torch.empty_like(phys)
+        self.frame(phys, out, True, cotangent)
+        return out
 
 
 class Kolmogorov(Problem):

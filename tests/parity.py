@@ -59,6 +59,7 @@ def field_errors(got, ref, N, base=None, names=FIELD_NAMES):
     ref = np.asarray(ref)
     assert got.shape == ref.shape, (got.shape, ref.shape)
     bg = np.zeros(len(FIELD_NAMES))
+    full = ref   # the whole state (background included): the scale of the solve's rounding
     if base is not None:
         base = np.asarray(base)
         for f in range(len(FIELD_NAMES)):
@@ -75,8 +76,8 @@ def field_errors(got, ref, N, base=None, names=FIELD_NAMES):
             continue
         d = np.max(np.abs(g - r))
         m = np.max(np.abs(r))
-        if fi is None:   # taus: relative to the state of their wavenumbers
-            m = max(m, np.max(np.abs(ref[rows, :])))
+        if fi is None:   # taus: relative to the whole state of their wavenumbers
+            m = max(m, np.max(np.abs(full[rows, :])))
         if scale == 0.0:
             res[label] = (d, "abs", d)
         elif m > ZERO_GROUP * scale:

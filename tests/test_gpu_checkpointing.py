@@ -121,7 +121,7 @@ def test_binomial_couette():
     n = 7
     G = sps.Couette(8, 12, 8, Re=400.0, dt=0.01, checkpoint_every=2, max_steps=n)
     uvw = wl.couette_perturbation(seed=3, Nx=8, Ny=12, Nz=8, energy=1e-3)
-    X0 = torch.from_numpy(G.state_from_velocity(uvw)).cuda()
+    X0 = G.state_from_velocity(uvw)
     ref = grad(G, X0, n)
     G.set_checkpointing(sps.CKPT_BINOMIAL, 2)
     got = grad(G, X0, n)
@@ -181,7 +181,7 @@ def test_two_level_couette(tmp_path):
     n = 9
     G = sps.Couette(8, 12, 8, Re=400.0, dt=0.01, checkpoint_every=2, max_steps=n)
     uvw = wl.couette_perturbation(seed=5, Nx=8, Ny=12, Nz=8, energy=1e-3)
-    X0 = torch.from_numpy(G.state_from_velocity(uvw)).cuda()
+    X0 = G.state_from_velocity(uvw)
     ref = grad(G, X0, n)
     G.set_checkpointing(sps.CKPT_TWO_LEVEL, 2)
     assert all(torch.equal(a, b) for a, b in zip(grad(G, X0, n), ref))

@@ -1,19 +1,21 @@
 """The closure network on the GPU (bf16 weights and activations, FP32 accumulation, MFMA for
 the 32 -> 32 layer) against the FP64 oracle that emulates the same bf16 roundings.
 
-Bound.  Both sides round the same values to bf16; they differ by FP32 versus FP64
-accumulation (at most K 2^-24 of the sum of magnitudes, K = 288 terms) and by an occasional
-activation that lands on the other side of a bf16 rounding boundary (one bf16 ulp, 2^-8 of
-that activation).  Per output pixel, with S_p = sum |w3| |a2| over the pixel's 3x3 x 32
-inputs (the magnitude the output is a sum of), the test requires
-max_p |y_gpu - y_oracle| / S_p <= 2^-5 (a few flips, amplified once by a layer) and the median
-<= 2^-13.  Cotangents (FP32 on the GPU, FP64 in the oracle) of the input and of every parameter
-array: max error <= 2^-7 and median <= 2^-13 relative to the array's largest magnitude."""
+Bound.  Every output pixel, input-cotangent pixel and parameter-cotangent entry is held to an
+element-wise bound derived from the two implementations' arithmetic (tests/closure_bound.py):
+FP32 accumulation of K terms (K u times the sum of magnitudes, u = 2^-24, with a factor 2),
+FP32 GELU evaluation, and one bf16 spacing for exactly those activations whose oracle value
+lies within the propagated difference of a bf16 rounding boundary (a possible flip), carried
+through the following layers by the absolute weights.  A pixel with no nearby boundary is thus
+held at the accumulation level (about 3e-5 of its sum of magnitudes), and a wrong tap anywhere,
+the periodic border included, shows at once; the border rows and columns are also reported on
+their own."""
 import numpy as np
 import pytest
 
 from oracle import closure as cl
 import workloads
+from closure_bound import forward_bound, vjp_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -54,26 +56,37 @@ def test_closure_net_forward_and_vjp(shape):
     net.vjp(xd, torch.from_numpy(yb.ravel().copy()).cuda(), xb, tb)   # theta_bar accumulates
     torch.cuda.synchronize()
     y, xb, tb = y.cpu().numpy().reshape(B, H, W), xb.cpu().numpy().reshape(B, H, W), tb.cpu().numpy() / 2
-    yr, xr, tr = [], [], None
-    ratios = []
+    ry, rx, tr, tbound = [], [], None, None
+    border = np.zeros((H, W), bool)
+    border[[0, -1], :] = True
+    border[:, [0, -1]] = True
+    flips = [0, 0]
     for i in range(B):
-        yo, cache = cl.forward(p, x[i], bf=True)
-        a2, w3 = cache[4], cache[7]
-        S = cl.conv3(np.abs(a2), np.abs(w3), np.zeros(1))[0]
-        ratios.append(np.abs(y[i] - yo) / S)
+        yo, by, cache, dl = forward_bound(p, x[i])
+        flips[0] += dl["flips1"]
+        flips[1] += dl["flips2"]
+        ry.append(np.abs(y[i] - yo) / by)
         xo, po = cl.vjp(p, x[i], yb[i], bf=True)
-        xr.append(xo)
+        bx, bp = vjp_bound(p, x[i], yb[i], cache, dl)
+        rx.append(np.abs(xb[i] - xo) / bx)
         f = cl.flatten(po)
+        g = cl.flatten(bp)
         tr = f if tr is None else tr + f
-    ratios = np.concatenate([r.ravel() for r in ratios])
-    print(f"forward: max {ratios.max():.3e} median {np.median(ratios):.3e} of S_p", flush=True)
-    assert ratios.max() <= 2.0 ** -5 and np.median(ratios) <= 2.0 ** -13
-    ex = np.abs(xb - np.stack(xr)) / np.max(np.abs(xr))
-    print(f"input cotangent: max {ex.max():.3e} median {np.median(ex):.3e}", flush=True)
-    assert ex.max() <= 2.0 ** -7 and np.median(ex) <= 2.0 ** -13
-    tp = cl.unflatten(tb)
-    to = cl.unflatten(tr)
+        tbound = g if tbound is None else tbound + g
+    ry, rx = np.stack(ry), np.stack(rx)
+    print(f"possible bf16 flips: layer 1 {flips[0]}, layer 2 {flips[1]} of {B * H * W * 32} activations each",
+          flush=True)
+    print(f"forward: max |dy| / bound {ry.max():.3f} (border {ry[:, border].max():.3f})", flush=True)
+    print(f"input cotangent: max |dx| / bound {rx.max():.3f} (border {rx[:, border].max():.3f})", flush=True)
+    assert ry.max() <= 1.0 and rx.max() <= 1.0
+    # and the bulk: median errors far below the bounds' rounding level
+    xr = np.stack([cl.vjp(p, x[i], yb[i], bf=True)[0] for i in range(B)])
+    ex = np.abs(xb - xr) / np.max(np.abs(xr))
+    print(f"input cotangent: median {np.median(ex):.2e} of the largest", flush=True)
+    assert np.median(ex) <= 2.0 ** -13
+    tp, to, tbd = cl.unflatten(tb), cl.unflatten(tr), cl.unflatten(tbound)
     for k in cl.PARAM_ORDER:
+        r = np.abs(tp[k] - to[k]) / tbd[k]
         e = np.abs(tp[k] - to[k]) / np.max(np.abs(to[k]))
-        print(f"{k}: max {e.max():.3e} median {np.median(e):.3e}", flush=True)
-        assert e.max() <= 2.0 ** -7 and np.median(e) <= 2.0 ** -13, k
+        print(f"{k}: max |d| / bound {r.max():.3f}, median {np.median(e):.2e} of the largest", flush=True)
+        assert r.max() <= 1.0 and np.median(e) <= 2.0 ** -13, k

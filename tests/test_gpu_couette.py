@@ -211,3 +211,30 @@ def test_couette_energy_gain_through_autograd():
     an = float(torch.dot(g, d).item())
     print(f"  central difference {fd:.10e}  gradient {an:.10e}", flush=True)
     assert abs(fd - an) <= 1e-6 * abs(an)
+
+
+def test_couette_frame_conversion_through_the_abi():
+    """sps_couette_frame against the test's own rotation (to_lib): states (taus doubled) and
+    cotangents (taus halved) into the library's frame, and back (round trip to rounding)."""
+    print("couette frame conversion", flush=True)
+    cfg = CFGS[1]
+    P = Couette(Re=400.0, **cfg)
+    G = sps.Couette(cfg["Nx"], cfg["Ny"], cfg["Nz"], cfg["Lx"], cfg["Lz"], Re=400.0, dt=0.01, checkpoint_every=1,
+                    max_steps=1)
+    X = wl.random_state(40, (P.K, P.S), real_first_row=False)
+    out = torch.zeros(G.n, dtype=torch.float64, device="cuda")
+    back = torch.zeros_like(out)
+    for cot, ts in ((False, 2.0), (True, 0.5)):
+        G.frame(dev(X), out, to_library=True, cotangent=cot)
+        G.frame(out, back, to_library=False, cotangent=cot)
+        G.sync()
+        ref = to_lib(P, X, ts)
+        e1 = np.max(np.abs(host(out, P) - ref)) / np.max(np.abs(ref))
+        e2 = np.max(np.abs(host(back, P) - X)) / np.max(np.abs(X))
+        print(f"  cotangent={cot}: to library {e1:.1e}, round trip {e2:.1e}", flush=True)
+        assert e1 <= 1e-15 and e2 <= 1e-15
+    R = sps.Problem(sps.RBC2D, 16, 12, 4.0, 1e6, 1.0, 1.5, 1e-3, 1, 1)
+    Z = torch.zeros(R.n, dtype=torch.float64, device="cuda")
+    with pytest.raises(sps.SpsError) as e:
+        R.frame(Z, Z.clone())
+    assert e.value.code == -7

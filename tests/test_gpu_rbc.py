@@ -242,3 +242,69 @@ def test_gradient_with_an_upstream_cotangent():
     with pytest.raises(sps.SpsError) as e:
         G.gradient(to_dev(X0), nsteps, None, g, J, dJdXN=to_dev(seed))
     assert e.value.code == -1
+
+
+@pytest.mark.parametrize("cfg,nsteps,ce", [(SMALL, 7, 3), (FULL, 6, 4)], ids=["small", "full"])
+def test_parameter_gradient(cfg, nsteps, ce):
+    """dJdtheta = (dJ/dRa, dJ/dPr) from the same gradient call (equ:efficient_gradient: the stage
+    residuals' derivatives in Ra and Pr against the stage adjoints, summed over the reverse sweep)
+    against the oracle's, with three segments of checkpoints (the first sweep's state records
+    reused by the recompute), in graph mode too; dJ/dX0 is unchanged by asking for it."""
+    note(f"parameter gradient {cfg} x {nsteps} ce={ce}")
+    P, G = build(cfg, ce=ce, max_steps=nsteps)
+    X0 = P.initial_state(wl.rbc_b0(seed=14, Nx=cfg[0], Nz=cfg[1], amp=0.1))
+    XN_ref, hist = imex.rk_forward(P, X0, cfg[5], nsteps)
+    g_ref, th_ref = imex.rk_adjoint(P, P.kinetic_energy_grad(XN_ref), hist, cfg[5], dLs=P.param_dL(), XN=XN_ref)
+    g = torch.zeros(G.n, dtype=torch.float64, device="cuda")
+    g0 = torch.zeros_like(g)
+    th = torch.zeros(2, dtype=torch.float64, device="cuda")
+    x0 = to_dev(X0)
+    G.gradient(x0, nsteps, None, g0, None)
+    G.gradient(x0, nsteps, None, g, None, dJdtheta=th)
+    G.sync()
+    assert torch.equal(g, g0)
+    t = th.cpu().numpy()
+    e = np.abs(t - th_ref) / np.abs(th_ref)
+    note(f"  dJ/dRa {t[0]:.15e} vs {th_ref[0]:.15e} ({e[0]:.1e}); dJ/dPr {t[1]:.15e} vs {th_ref[1]:.15e} ({e[1]:.1e})")
+    assert np.all(e <= TOL)
+    G.set_graph(True)
+    th2 = torch.zeros_like(th)
+    for _ in range(2):   # record, then replay
+        G.gradient(x0, nsteps, None, g, None, dJdtheta=th2)
+        G.sync()
+        assert torch.equal(th2, th)
+    G.set_graph(False)
+    G.set_checkpointing(1, 3)   # binomial: refused
+    with pytest.raises(sps.SpsError) as ex:
+        G.gradient(x0, nsteps, None, g, None, dJdtheta=th)
+    assert ex.value.code == -7
+
+
+def test_caller_allocator():
+    """Problems built with torch's caching allocator installed (sps_set_allocator) take their
+    device memory from it (torch's allocated bytes grow by the problem's workspace and shrink
+    back after sps_destroy) and compute the same gradient bit for bit."""
+    note("caller allocator")
+    cfg, nsteps = SMALL, 5
+    P = RBC(Nx=cfg[0], Nz=cfg[1], Lx=cfg[2], Ra=cfg[3], Pr=cfg[4])
+    X0 = to_dev(P.initial_state(wl.rbc_b0(seed=15, Nx=cfg[0], Nz=cfg[1], amp=0.1)))
+    _, G = build(cfg, ce=2, max_steps=nsteps)
+    g_ref = torch.zeros(G.n, dtype=torch.float64, device="cuda")
+    G.gradient(X0, nsteps, None, g_ref, None)
+    G.sync()
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    sps.use_torch_allocator(True)
+    try:
+        _, H = build(cfg, ce=2, max_steps=nsteps)
+    finally:
+        sps.use_torch_allocator(False)
+    grown = torch.cuda.memory_allocated() - before
+    g = torch.zeros_like(g_ref)
+    H.gradient(X0, nsteps, None, g, None)
+    H.sync()
+    assert torch.equal(g, g_ref)
+    H.close()
+    torch.cuda.synchronize()
+    note(f"  workspace from torch's allocator: {grown / 1e6:.2f} MB, returned: {torch.cuda.memory_allocated() == before}")
+    assert grown > 1e5 and torch.cuda.memory_allocated() == before

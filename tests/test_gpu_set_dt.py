@@ -114,7 +114,7 @@ def test_return_to_a_step_is_bit_identical_to_a_fresh_problem():
     Gc = sps.Couette(8, 12, 8, Re=400.0, dt=0.01, checkpoint_every=2, max_steps=5)
     Gc2 = sps.Couette(8, 12, 8, Re=400.0, dt=0.015, checkpoint_every=2, max_steps=5)
     uvw = wl.couette_perturbation(seed=3, Nx=8, Ny=12, Nz=8, energy=1e-3)
-    X0 = torch.from_numpy(Gc.state_from_velocity(uvw)).cuda()
+    X0 = Gc.state_from_velocity(uvw)
     Gc.set_dt(0.015)
     res = []
     for H in (Gc, Gc2):

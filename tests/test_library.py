@@ -78,3 +78,16 @@ def test_host_bands_match_oracle_operators(nx, nz, lx, Ra, Pr):
             assert np.abs(T.real - B).max() <= 1e-14 * np.abs(T).max(), (k, which)
     if nz == 64:
         assert (hb["kl"], hb["ku"]) == (7, 20)
+
+
+def test_set_allocator_arguments():
+    """sps_set_allocator takes both functions or neither (no device needed)."""
+    L = sps.lib()
+    from paper_2506_14792_amd.sps import _ALLOC_T, _FREE_T
+    fa = _ALLOC_T(lambda n, c: None)
+    ff = _FREE_T(lambda p, c: None)
+    a, f = ctypes.cast(fa, ctypes.c_void_p), ctypes.cast(ff, ctypes.c_void_p)
+    assert L.sps_set_allocator(a, None, None) == -1
+    assert L.sps_set_allocator(None, f, None) == -1
+    assert L.sps_set_allocator(a, f, None) == 0
+    assert L.sps_set_allocator(None, None, None) == 0
