@@ -668,6 +668,60 @@ def copy_calibration(nbytes=1 << 28, reps=5):
     print(json.dumps({"copy_calibration_bytes_per_dispatch": nbytes, "reps": reps}))
 
 
+RBC_BATCH_CFG = dict(batch=64, nx=256, nz=64, lx=4.0, Pr=1.0, ra_min=5e5, ra_max=2e6, dt=1e-3, nsteps=100,
+                     checkpoint_every=50, seed=100)
+
+
+def rbc_batch_timing(reps=2):
+    """A batch of 64 instances of the 256 x 64 problem with Rayleigh numbers drawn uniformly from
+    [5e5, 2e6] (seeded; each instance has its own factors, 9.6 MB of banded LU factors, i.e.
+    615 MB for the batch), RK222 dt = 1e-3, a 100-step gradient with checkpoints every 50: every
+    stage launch covers all instances (8192 per-wavenumber systems, 6144 grid rows).  Reports
+    instance timesteps per second and, per stage kernel, the algorithmic bytes of a launch (64
+    times the single problem's, the factors counted per instance), the live average launch time
+    (HIP events on the launch stream, eager gradients) and the fraction of 8 TB/s."""
+    import torch
+    import paper_2506_14792_amd as sps
+    import workloads as wl
+    c = RBC_BATCH_CFG
+    B, n = c["batch"], c["nsteps"]
+    ras = list(np.random.default_rng(c["seed"]).uniform(c["ra_min"], c["ra_max"], size=B))
+    G = sps.RbcBatch(ras, c["nx"], c["nz"], c["lx"], c["Pr"], dt=c["dt"], checkpoint_every=c["checkpoint_every"],
+                     max_steps=n)
+    grid = torch.from_numpy(np.concatenate([wl.rbc_b0(seed=c["seed"] + b, Nx=c["nx"], Nz=c["nz"]).ravel()
+                                            for b in range(B)])).cuda()
+    X0 = torch.zeros(G.n, dtype=torch.float64, device="cuda")
+    g = torch.zeros_like(X0)
+    J = torch.zeros(B, dtype=torch.float64, device="cuda")
+    G.initial_state(grid, X0)
+    G.gradient(X0, n, None, g, J)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        G.gradient(X0, n, None, g, J)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / reps
+    kb = kernel_bytes(c["nx"], c["nz"])
+    per = {}
+    for kind, name in ((0, "rbc_kfwd"), (1, "rbc_kadj"), (2, "rbc_xfwd"), (3, "rbc_xadj")):
+        G.timer_enable(kind, True)
+        G.gradient(X0, n, None, g, J)
+        torch.cuda.synchronize()
+        nk, ms = G.timer_read()
+        G.timer_enable(kind, False)
+        avg = ms / max(nk, 1)
+        byt = B * kb[name]
+        per[name] = {"bytes_per_launch": byt, "avg_launch_ms": avg, "launches_timed": nk,
+                     "achieved_GBps": byt / (avg * 1e-3) / 1e9, "frac": byt / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    G.sync()
+    finite = bool(torch.isfinite(g).all().item())
+    G.close()
+    return {"workload": "batch of 64 Rayleigh-Benard 256x64 instances, Ra uniform in [5e5, 2e6] (seeded), Pr=1, "
+                        "RK222 dt=1e-3, 100-step gradient, checkpoints every 50, one launch per stage for all instances",
+            "batch": B, "gpu_gradient_s": sec, "instance_timesteps_per_s": 2 * n * B / sec,
+            "gradients_per_s_per_instance": B / sec, "per_kernel": per, "finite": finite}
+
+
 def kernel_bytes(nx, nz):
     """Algorithmic HBM bytes per launch of each stage kernel of the 2D problem (each operand
     streamed once; factors in banded form): the per-wavenumber forward kernel (average of the
@@ -695,7 +749,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--skip-extra", action="store_true",
                     help="only the headline configuration (for counter and trace runs)")
-    ap.add_argument("--only", choices=["ks", "sh", "closure", "couette", "lbvp", "ckpt", "stability", "dtchange"],
+    ap.add_argument("--only", choices=["ks", "sh", "closure", "couette", "lbvp", "ckpt", "stability", "dtchange",
+                                       "rbcbatch"],
                     default=None,
                     help="run one secondary configuration alone and print its JSON (for profiling)")
     args = ap.parse_args()
@@ -711,7 +766,7 @@ def main():
         torch.cuda.set_device(0)
         fn = {"ks": ks_timing, "sh": sh_timing, "closure": kolmo_timing, "couette": couette_timing,
               "lbvp": lbvp_timing, "ckpt": ckpt_timing, "stability": stability_timing,
-              "dtchange": dtchange_timing}[args.only]
+              "dtchange": dtchange_timing, "rbcbatch": rbc_batch_timing}[args.only]
         print(json.dumps({args.only: fn()}))
         return
 
@@ -799,8 +854,9 @@ def main():
     G.sync()
     graph_sec = (t7 - t6) / args.steps
     traffic = measured_traffic()
-    ks = sh = kol = cou = lbvp = ckpt = stab = dtc = None
+    ks = sh = kol = cou = lbvp = ckpt = stab = dtc = rbatch = None
     if not args.skip_extra:
+        rbatch = rbc_batch_timing()
         lbvp = lbvp_timing()
         ckpt = ckpt_timing()
         dtc = dtchange_timing()
@@ -838,6 +894,7 @@ def main():
                      "traffic": traffic, "bytes_per_launch": bytes_launch, "avg_launch_ms": avg_ms,
                      "launches_timed": launches, "per_kernel": per_kernel},
         "cpu_baseline": cpu,
+        "rbc_batched_config": rbatch,
         "ks_config": ks,
         "sh_batched_config": sh,
         "closure_config": kol,

@@ -4,7 +4,7 @@
  * The library advances an initial-value problem written as
  *     M dX/dt + L X = F(X)                     (paper, Supplementary: Initial value problems)
  * with a sparse ultraspherical/tau discretization (paper: Sparse spectral methods),
- * an IMEX scheme (ARS(2,2,2) Runge-Kutta or SBDF2-4 multistep), and computes gradients by
+ * an IMEX scheme (ARS(2,2,2) or ARS(4,4,3) Runge-Kutta, SBDF2-4 multistep), and computes gradients by
  * the adjoint-state method (paper: equ:adjoint and equ:efficient_gradient): a forward
  * sweep with checkpoints, a reverse sweep through transposed solves that reuse the LU
  * factors (paper, Methods: Linear system solves) and vector-Jacobian products of F
@@ -56,7 +56,7 @@ enum sps_scheme { SPS_RK222 = 1, SPS_SBDF2 = 2, SPS_SBDF3 = 3, SPS_SBDF4 = 4, SP
 
 typedef struct {
   int equation;          /* sps_equation */
-  int scheme;            /* sps_scheme; RBC uses SPS_RK222, KS any of them */
+  int scheme;            /* sps_scheme; RBC: SPS_RK222 or SPS_RK443, KS any of them */
   int nx;                /* Fourier grid points at scale 1 (K = nx/2 stored wavenumbers) */
   int nz;                /* Chebyshev modes N (RBC), ignored for KS */
   double lx;             /* Fourier period */
@@ -84,6 +84,20 @@ int sps_set_allocator(void *(*alloc_fn)(size_t bytes, void *ctx), void (*free_fn
  * value problems; checkpointing).  hip_stream may be NULL (the null stream).
  * Returns SPS_E_ARG for unsupported sizes.  *out owns all device memory it allocates. */
 int sps_build_problem(const sps_desc *desc, void *hip_stream, sps_problem **out);
+
+/* A batch of `batch` independent instances of the 2D problem of desc (equation SPS_RBC2D, RK222 or RK443)
+ * that differ in their Rayleigh number: ra (host array of batch values, copied; NULL: desc's
+ * param0 for every instance), Prandtl number, sizes and step from desc.  Every instance has its
+ * own LU factors (L depends on Ra through nu and kappa), and every stage launch of the sweeps
+ * covers all instances (the per-wavenumber kernels run batch x K systems, the grid-row kernels
+ * batch x Ngz rows).  Layouts: states and cotangents hold the instances in order (batch blocks of
+ * the single-problem layout, sps_state_size() = batch K S 2 doubles); grid arrays of
+ * sps_initial_state[_adjoint] hold batch (nx x nz) grids; sps_cost's and sps_gradient's J have
+ * one value per instance, and the gradient is that of their sum.  sps_step, sps_adjoint_step,
+ * sps_gradient (uniform checkpoints, graph mode included; no dJdtheta), sps_cost,
+ * sps_initial_state[_adjoint], sps_factor, sps_set_dt, sps_set_graph and the timers work as for
+ * one problem; the other entry points return SPS_E_UNSUPPORTED for a batch. */
+int sps_build_rbc_batch(const sps_desc *desc, int batch, const double *ra, void *hip_stream, sps_problem **out);
 
 /* Batched 2D Swift-Hohenberg problems u_t = r u - (1 + Laplacian)^2 u - u^3 on [0, lx)^2,
  * periodic (IVP form of the Supplementary, "Initial value problems": M = 1,
@@ -345,7 +359,7 @@ int sps_set_dt(sps_problem *P, double dt);
  * it).  Drops the recorded forward run.  The KS problem; SPS_E_UNSUPPORTED otherwise. */
 int sps_set_timesteps(sps_problem *P, const double *dts, int n);
 
-/* Checkpointing of the RK222 sweeps (Supplementary, "Initial value problems": the reverse
+/* Checkpointing of the Runge-Kutta sweeps (Supplementary, "Initial value problems": the reverse
  * sweep needs every forward state, kept through a checkpoint schedule that trades storage for
  * recomputation).  scheme SPS_CKPT_UNIFORM (the default): a stored state every
  * checkpoint_every steps and the stage data of one segment, segments recomputed on a second

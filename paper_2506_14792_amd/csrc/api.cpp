@@ -137,6 +137,22 @@ int sps_build_problem(const sps_desc* desc, void* hip_stream, sps_problem** out)
   }
 }
 
+int sps_build_rbc_batch(const sps_desc* desc, int batch, const double* ra, void* hip_stream, sps_problem** out) {
+  if (!desc || !out) return fail(SPS_E_ARG, "null argument");
+  *out = nullptr;
+  if (desc->equation != SPS_RBC2D) return fail(SPS_E_ARG, "batches are built for the 2D problem");
+  if (batch < 1) return fail(SPS_E_ARG, "batch must be positive");
+  try {
+    sps::ProblemImpl* impl = sps::make_rbc_batch(*desc, batch, ra, reinterpret_cast<hipStream_t>(hip_stream));
+    *out = new sps_problem{impl};
+    return SPS_OK;
+  } catch (const sps::Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::exception& e) {
+    return fail(SPS_E_HIP, e.what());
+  }
+}
+
 long long sps_state_size(const sps_problem* P) { return (P && P->impl) ? P->impl->state_size() : -1; }
 
 int sps_factor(sps_problem* P) {

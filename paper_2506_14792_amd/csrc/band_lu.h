@@ -159,9 +159,14 @@ __device__ __forceinline__ void ops_store(const OpsRegs& r, int count, double* d
 // band[i*(kl+ku+1) + (c - i + kl)] = A[i][c], combined as a*BM + b*BL.
 // LDS layout (LAPACK band with fill rows): ab[c*ldab + (kv + i - c)] = A[i][c],
 // ldab = 2kl + ku + 1, kv = kl + ku.
+// With BLnu and BLka given, the L band is BL + nu BLnu + ka BLka (an operator affine in two
+// parameters, here the diffusivities of one instance of a batch).
 __device__ inline void band_factor_block(const double* __restrict__ BM, const double* __restrict__ BL,
                                          double a, double bcoef, int n, int kl, int ku, double* ab,
-                                         int* sh, int* spiv, double* OPS, int* err) {
+                                         int* sh, int* spiv, double* OPS, int* err,
+                                         const double* __restrict__ BLnu = nullptr,
+                                         const double* __restrict__ BLka = nullptr, double nu = 0.0,
+                                         double ka = 0.0) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int ldab = 2 * kl + ku + 1, kv = kl + ku, bw = kl + ku + 1, uw = kl + ku + 1;
   for (int e = tid; e < n * ldab; e += nt) ab[e] = 0.0;
@@ -169,7 +174,10 @@ __device__ inline void band_factor_block(const double* __restrict__ BM, const do
   for (int e = tid; e < n * bw; e += nt) {
     const int i = e / bw, d = e - i * bw;
     const int c = i + d - kl;
-    if (c >= 0 && c < n) ab[c * ldab + (kv + i - c)] = a * BM[e] + bcoef * BL[e];
+    if (c >= 0 && c < n) {
+      const double l = BLnu ? BL[e] + nu * BLnu[e] + ka * BLka[e] : BL[e];
+      ab[c * ldab + (kv + i - c)] = a * BM[e] + bcoef * l;
+    }
   }
   __syncthreads();
   for (int j = 0; j < n; ++j) {

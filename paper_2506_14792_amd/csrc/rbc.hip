@@ -1,5 +1,5 @@
-// 2D Rayleigh-Benard convection, Fourier (x) x Chebyshev (z), RK222 IMEX, and its
-// discrete adjoint on gfx950.
+// 2D Rayleigh-Benard convection, Fourier (x) x Chebyshev (z), IMEX Runge-Kutta (ARS(2,2,2)
+// or ARS(4,4,3)), and its discrete adjoint on gfx950.
 //
 // Equations (paper, Supplementary: Initial value problems) in the form
 // M dX/dt + L X = F(X) with the ultraspherical/tau discretization (paper: Sparse spectral
@@ -9,7 +9,7 @@
 // coefficients, continuity in C1, boundary rows u(0), u(1), w(0), w(1), b(0), b(1), and
 // the pressure gauge int p dz = 0 (k = 0) or tau_p = 0 (k != 0).
 //
-// Device data flow of one RK222 stage:
+// Device data flow of one Runge-Kutta stage:
 //   grid-row kernel (one block per Gauss node z_j): inverse real FFTs of the 8 fields
 //     (u, w, ux, uz, wx, wz, bx, bz) from their x-spectra at z_j, products
 //     N = -(u.grad)(u, w, b), forward real FFTs, truncation  -> nl[3][Ngz][K]
@@ -111,10 +111,30 @@ struct RbcDev {
   const int* sflag;     // colph[i] (slot i)
   const double* gram;   // [N][N] int_0^1 T_m T_n dz
   const double* intw;   // [N] int_0^1 T_m(2z-1) dz
-  const double* ops;    // [K][opsize] block operators of the LU factors (T blocks, then G blocks)
+  const double* ops;    // [B][K][opsize] block operators of the LU factors (T blocks, then G blocks)
   int opsize;
   int* err;             // bit 0 singular pivot, bit 1 non-finite state
+  // A batch of B instances of the problem (blockIdx.y = instance) that differ in their
+  // Rayleigh number: per-instance nu and kappa (null for a single problem), factors and arrays
+  // at instance strides.
+  int B;
+  const double* nub;    // [B]
+  const double* kab;    // [B]
 };
+
+// Instance b's view of the problem: its diffusivities and its factors.
+__device__ __forceinline__ void rbc_inst(RbcDev& d, int b) {
+  if (d.nub) {
+    d.nu = d.nub[b];
+    d.ka = d.kab[b];
+  }
+  d.ops += (size_t)b * d.K * d.opsize;
+}
+// p + b * stride for a non-null per-instance array
+template <typename T>
+__device__ __forceinline__ T* inst_ptr(T* p, int b, size_t stride) {
+  return p ? p + (size_t)b * stride : p;
+}
 
 // ---------------------------------------------------------------------------- operators
 // Sparse ultraspherical operators on [0,1] applied to length-N coefficient arrays in LDS.
@@ -587,17 +607,75 @@ __device__ __forceinline__ void rbc_solve(const RbcDev& d, int k, const OpsRegs&
 }
 
 // ---------------------------------------------------------------------------- per-wavenumber forward kernel
-enum KfMode { KF_ZGRID = 0, KF_STAGE1 = 1, KF_STAGE2 = 2, KF_EVALF = 3, KF_SOLVE = 4 };
+enum KfMode { KF_ZGRID = 0, KF_STAGE = 1, KF_EVALF = 3, KF_SOLVE = 4 };
 
+// Implicit stages of the largest IMEX Runge-Kutta tableau the stage kernels take (ARS(4,4,3)).
+constexpr int RK_MAXS = 4;
+
+// The IMEX Runge-Kutta schemes of Ascher, Ruuth & Spiteri (1997) the 2D problem runs: explicit
+// tableau A and implicit tableau H over stages 0 .. s, stage 0 the step's initial state.  Both
+// have H's first column zero and one implicit diagonal value (one factorization of M + dt H_ii L
+// serves every stage), and are stiffly accurate (the new state is the last stage).
+struct RkTab {
+  int s = 0;
+  double A[RK_MAXS + 1][RK_MAXS + 1] = {};
+  double H[RK_MAXS + 1][RK_MAXS + 1] = {};
+};
+inline RkTab rk_tableau(int scheme) {
+  RkTab t;
+  if (scheme == SPS_RK222) {
+    // ARS(2,2,2): gamma = 1 - 1/sqrt(2), delta = 1 - 1/(2 gamma)
+    const double g = 1.0 - 1.0 / std::sqrt(2.0), dl = 1.0 - 1.0 / (2.0 * g);
+    t.s = 2;
+    t.A[1][0] = g;
+    t.A[2][0] = dl;
+    t.A[2][1] = 1.0 - dl;
+    t.H[1][1] = g;
+    t.H[2][1] = 1.0 - g;
+    t.H[2][2] = g;
+  } else if (scheme == SPS_RK443) {
+    // ARS(4,4,3): third order, implicit diagonal 1/2
+    const double A[5][5] = {{0, 0, 0, 0, 0},
+                            {1.0 / 2, 0, 0, 0, 0},
+                            {11.0 / 18, 1.0 / 18, 0, 0, 0},
+                            {5.0 / 6, -5.0 / 6, 1.0 / 2, 0, 0},
+                            {1.0 / 4, 7.0 / 4, 3.0 / 4, -7.0 / 4, 0}};
+    const double H[5][5] = {{0, 0, 0, 0, 0},
+                            {0, 1.0 / 2, 0, 0, 0},
+                            {0, 1.0 / 6, 1.0 / 2, 0, 0},
+                            {0, -1.0 / 2, 1.0 / 2, 1.0 / 2, 0},
+                            {0, 3.0 / 2, -3.0 / 2, 1.0 / 2, 1.0 / 2}};
+    t.s = 4;
+    for (int i = 0; i < 5; ++i)
+      for (int j = 0; j < 5; ++j) {
+        t.A[i][j] = A[i][j];
+        t.H[i][j] = H[i][j];
+      }
+  }
+  return t;
+}
+
+// Stage i of an IMEX Runge-Kutta step (Supplementary, "Initial value problems"; equ:imex):
+//   (M + dt H_ii L) X_i = M X_0 + dt sum_{j<i} [A_ij F(X_j) - H_ij L X_j].
+// The kernel that solves for X_i evaluates F(X_{i-1}) from the nonlinear terms of X_{i-1}'s
+// grid fields and reads the earlier stages' states and F from their buffers.  H's first column
+// is zero (stage 0 is explicit), so the implicit sum runs over j >= 1.
 struct KfArgs {
   const cplx* X0;     // stage-0 state (ABI layout)
-  const cplx* X1;     // stage-1 state
-  cplx* Xout;         // new state (or F for KF_EVALF)
+  const cplx* Xst;    // stage states X_1 .. X_{s-1}: X_j at Xst + (j - 1) sstr
+  cplx* Xout;         // the stage's state (or F for KF_EVALF)
   const cplx* nl;     // [3][Ngz][K] nonlinear terms in x-spectral, z-grid form
-  cplx* F0;           // [K][3][N] S10 N-hat of stage 0
+  cplx* Fst;          // S10 N-hat of stages 0 .. s-2, [K][3][N] each: F_j at Fst + j fstr
   cplx* zg;           // [6][Ngz][K] output x-spectral z-grid fields (may be null)
   cplx* Xsave;        // second copy of the stage's new state (may be null)
-  double dt, g, dl;   // dt, gamma, delta
+  size_t sstr, fstr;  // stage-slot strides of Xst and Fst (complex entries, all instances)
+  double dt;
+  double fa[RK_MAXS]; // A_ij, j < i (zero beyond)
+  double lh[RK_MAXS]; // H_ij, j < i (lh[0] = 0; zero beyond)
+  double fself;       // A_{i,i-1}: the weight of the F evaluated in this launch
+  double asum;        // sum_j A_ij: the weight of F's boundary data
+  int stage, nst;     // i (1 .. s) and s
+  int lx;             // some H_ij (j < i) is nonzero
   int mode;
 };
 
@@ -606,6 +684,20 @@ struct KfArgs {
 // One entry of every length-S vector per thread (S + SPS_PAD <= NTK).
 template <bool STREAM>
 __global__ void __launch_bounds__(NTK) rbc_kfwd(RbcDev d, KfArgs a) {
+  if (blockIdx.y) {
+    const int b = blockIdx.y;
+    const size_t st = (size_t)d.K * d.S, zs = (size_t)d.Ngz * d.K;
+    rbc_inst(d, b);
+    a.X0 = inst_ptr(a.X0, b, st);
+    a.Xst = inst_ptr(a.Xst, b, st);
+    a.Xout = inst_ptr(a.Xout, b, st);
+    a.Xsave = inst_ptr(a.Xsave, b, st);
+    a.nl = inst_ptr(a.nl, b, 3 * zs);
+    a.zg = inst_ptr(a.zg, b, 6 * zs);
+    a.Fst = inst_ptr(a.Fst, b, (size_t)d.K * 3 * d.N);
+  } else if (d.nub) {
+    rbc_inst(d, 0);
+  }
   extern __shared__ double smem_d[];
   cplx* sm = reinterpret_cast<cplx*>(smem_d);
   const int k = blockIdx.x, tid = threadIdx.x;
@@ -616,20 +708,33 @@ __global__ void __launch_bounds__(NTK) rbc_kfwd(RbcDev d, KfArgs a) {
   cplx* un = vB + S;            // union
   // phase A views
   cplx* xa = un;                // S : stage-0 state
-  cplx* xb = xa + S;            // S : stage-1 state
+  cplx* xb = xa + S;            // S : sum_j H_ij X_j of the earlier stages
   cplx* rr = xb + S;            // S : right-hand side (equation slots)
   cplx* pq = rr + S;            // 6*Hc mirror sums of the three nonlinear terms
   cplx* nh = pq + 6 * Hc;       // 3*N  N-hat
   cplx* fr = nh + 3 * N;        // 3*N  S10 N-hat
   double* ct = reinterpret_cast<double*>(fr + 3 * N);   // 4*Ngz cosines
-  const bool stage = (mode == KF_STAGE1 || mode == KF_STAGE2);
+  const bool stage = mode == KF_STAGE;
   const bool nonlin = stage || mode == KF_EVALF;
+  const int si = a.stage;
 
-  // Global reads, in the order they are needed: state, stage-0 F, the mirror pair of the
-  // nonlinear terms and one cosine per thread first, then the block operators (needed last).
+  // Global reads, in the order they are needed: the states and earlier F (combined as they
+  // arrive), the mirror pair of the nonlinear terms and one cosine per thread first, then the
+  // block operators (needed last).
   const cplx x0 = (mode != KF_EVALF && tid < S) ? a.X0[(size_t)k * S + tid] : czero();
-  const cplx x1 = (mode == KF_STAGE2 && tid < S) ? a.X1[(size_t)k * S + tid] : czero();
-  const cplx f0v = (mode == KF_STAGE2 && tid < 3 * N) ? a.F0[(size_t)k * 3 * N + tid] : czero();
+  // (loops over the tableau's fixed size, so that the coefficients are read at constant
+  // indices; the host zeroes them beyond the stage)
+  cplx xc = czero(), fc = czero();
+  if (stage) {
+#pragma unroll
+    for (int j = 1; j < RK_MAXS; ++j)
+      if (j < si && a.lh[j] != 0.0 && tid < S)
+        xc = cadd(xc, cscale(a.Xst[(size_t)(j - 1) * a.sstr + (size_t)k * S + tid], a.lh[j]));
+#pragma unroll
+    for (int j = 0; j + 1 < RK_MAXS; ++j)
+      if (j + 1 < si && a.fa[j] != 0.0 && tid < 3 * N)
+        fc = cadd(fc, cscale(a.Fst[(size_t)j * a.fstr + (size_t)k * 3 * N + tid], a.fa[j]));
+  }
   const int pf = tid / Hc, pj = tid - pf * Hc, pjm = Ngz - 1 - pj;
   const bool pl = nonlin && tid < 3 * Hc;
   const cplx nvj = pl ? a.nl[((size_t)pf * Ngz + pj) * K + k] : czero();
@@ -644,9 +749,9 @@ __global__ void __launch_bounds__(NTK) rbc_kfwd(RbcDev d, KfArgs a) {
   if (stage) {
     if (tid < S) {
       xa[tid] = x0;
-      xb[tid] = x1;
+      xb[tid] = xc;
     }
-    if (tid < 3 * N) vB[tid] = f0v;   // stage-0 F (stage 2); vB is free until the solve
+    if (tid < 3 * N) vB[tid] = fc;    // sum_{j < i-1} A_ij F_j; vB is free until the solve
   }
   const cplx* f0s = vB;
   if (nonlin) {
@@ -678,38 +783,25 @@ __global__ void __launch_bounds__(NTK) rbc_kfwd(RbcDev d, KfArgs a) {
       }
       return;
     }
-    if (mode == KF_STAGE1 && tid < 3 * N) a.F0[(size_t)k * 3 * N + tid] = fr[tid];
+    // F of stage i-1, kept for the later stages
+    if (stage && si < a.nst && tid < 3 * N) a.Fst[(size_t)(si - 1) * a.fstr + (size_t)k * 3 * N + tid] = fr[tid];
   }
   if (stage) {
-    const double dt = a.dt, g = a.g, dl = a.dl;
+    const double dt = a.dt, fl = a.fself;
     if (tid < 4 * N) {
       const int s = tid;
       const MLRow r0 = ml_row(d, k, xa, s);
-      const cplx f0 = (s < 3 * N) ? ((mode == KF_STAGE1) ? fr[s] : f0s[s]) : czero();
-      cplx rhs;
-      if (mode == KF_STAGE1) {
-        rhs = cadd(r0.m, cscale(f0, dt * g));
-      } else {
-        const cplx f1 = (s < 3 * N) ? fr[s] : czero();
-        const MLRow r1 = ml_row(d, k, xb, s);
-        cplx comb = cadd(cscale(f0, dl), cscale(f1, 1.0 - dl));
-        comb = csub(comb, cscale(r1.l, 1.0 - g));
-        rhs = cadd(r0.m, cscale(comb, dt));
-      }
-      rr[s] = rhs;
+      cplx comb = (s < 3 * N) ? cadd(f0s[s], cscale(fr[s], fl)) : czero();
+      if (a.lx) comb = csub(comb, ml_row(d, k, xb, s).l);
+      rr[s] = cadd(r0.m, cscale(comb, dt));
     } else if (tid < 4 * N + 28) {
-      // boundary and gauge rows: M is zero there and F holds the boundary data (b = 1 at
-      // z = 0 for k = 0), so stage 1 gives dt g F and stage 2 dt (F - (1 - g) L X1)
+      // boundary and gauge rows: M is zero there and every stage's F holds the boundary data
+      // (b = 1 at z = 0 for k = 0), so the row is dt (sum_j A_ij F - L sum_j H_ij X_j)
       const int q = (tid - 4 * N) >> 2, h = tid & 3;
       const double fbc = (k == 0 && q == 4) ? d.bc0 : 0.0;
-      cplx rhs;
-      if (mode == KF_STAGE1) {
-        rhs = cmk(dt * g * fbc, 0.0);
-      } else {
-        const cplx lx = l_bc_row(d, k, xb, q, h);
-        rhs = cscale(csub(cmk(fbc, 0.0), cscale(lx, 1.0 - g)), dt);
-      }
-      if (h == 0) rr[4 * N + q] = rhs;
+      cplx v = cmk(a.asum * fbc, 0.0);
+      if (a.lx) v = csub(v, l_bc_row(d, k, xb, q, h));
+      if (h == 0) rr[4 * N + q] = cscale(v, dt);
     }
     __syncthreads();
   } else if (mode == KF_SOLVE) {
@@ -727,7 +819,7 @@ __global__ void __launch_bounds__(NTK) rbc_kfwd(RbcDev d, KfArgs a) {
       const cplx v = vA[tid];
       a.Xout[(size_t)k * S + tid] = v;
       if (a.Xsave) a.Xsave[(size_t)k * S + tid] = v;
-      if (mode == KF_STAGE2 && __any(!(isfinite(v.x) && isfinite(v.y))) && lane_id() == 0) atomicOr(d.err, 2);
+      if (stage && si == a.nst && __any(!(isfinite(v.x) && isfinite(v.y))) && lane_id() == 0) atomicOr(d.err, 2);
     }
   }
   if (a.zg == nullptr || mode == KF_SOLVE) return;
@@ -776,6 +868,11 @@ struct XfArgs {
 };
 
 __global__ void __launch_bounds__(NTX) rbc_xfwd(RbcDev d, XfArgs a) {
+  if (blockIdx.y) {
+    const size_t zs = (size_t)d.Ngz * d.K;
+    a.zg = inst_ptr(a.zg, blockIdx.y, 6 * zs);
+    a.nl = inst_ptr(a.nl, blockIdx.y, 3 * zs);
+  }
   extern __shared__ double smem_d[];
   cplx* sm = reinterpret_cast<cplx*>(smem_d);
   const int j = blockIdx.x, tid = threadIdx.x;
@@ -841,6 +938,12 @@ struct XaArgs {
 };
 
 __global__ void __launch_bounds__(NTX) rbc_xadj(RbcDev d, XaArgs a) {
+  if (blockIdx.y) {
+    const size_t zs = (size_t)d.Ngz * d.K;
+    a.nlbar = inst_ptr(a.nlbar, blockIdx.y, 3 * zs);
+    a.zg = inst_ptr(a.zg, blockIdx.y, 6 * zs);
+    a.zbar = inst_ptr(a.zbar, blockIdx.y, 6 * zs);
+  }
   extern __shared__ double smem_d[];
   cplx* sm = reinterpret_cast<cplx*>(smem_d);
   const int j = blockIdx.x, tid = threadIdx.x;
@@ -959,6 +1062,11 @@ __device__ __forceinline__ void pack_pair_row(const RbcDev& d, const cplx* src, 
 
 template <int R1>
 __global__ void __launch_bounds__(256) rbc_xfwd_w(RbcDev d, XfArgs a) {
+  if (blockIdx.y) {
+    const size_t zs = (size_t)d.Ngz * d.K;
+    a.zg = inst_ptr(a.zg, blockIdx.y, 6 * zs);
+    a.nl = inst_ptr(a.nl, blockIdx.y, 3 * zs);
+  }
   using W = WaveRow<R1>;
   constexpr int N = W::N, K = W::K, SC = W::SC;
   extern __shared__ double smem_d[];
@@ -1015,6 +1123,12 @@ __global__ void __launch_bounds__(256) rbc_xfwd_w(RbcDev d, XfArgs a) {
 
 template <int R1>
 __global__ void __launch_bounds__(384) rbc_xadj_w(RbcDev d, XaArgs a) {
+  if (blockIdx.y) {
+    const size_t zs = (size_t)d.Ngz * d.K;
+    a.nlbar = inst_ptr(a.nlbar, blockIdx.y, 3 * zs);
+    a.zg = inst_ptr(a.zg, blockIdx.y, 6 * zs);
+    a.zbar = inst_ptr(a.zbar, blockIdx.y, 6 * zs);
+  }
   using W = WaveRow<R1>;
   constexpr int N = W::N, K = W::K, SC = W::SC;
   extern __shared__ double smem_d[];
@@ -1083,17 +1197,29 @@ __global__ void __launch_bounds__(384) rbc_xadj_w(RbcDev d, XaArgs a) {
 // ---------------------------------------------------------------------------- per-wavenumber adjoint kernel
 enum KaFlags { KA_C = 1, KA_A = 2, KA_B = 4, KA_G = 8, KA_SOLVE_T = 16 };
 
+// Reverse of stage m of an IMEX Runge-Kutta step (Supplementary, RK adjoint equations), with
+// Y_j the stage adjoints:
+//   (M + dt H_mm L)^H Y_m = dF(X_m)^H (dt sum_{j>m} A_jm Y_j) - dt L^H sum_{j>m} H_jm Y_j
+// (for m = s the right-hand side is the cotangent of the step's new state), and the step's
+// initial-state cotangent M^H sum_j Y_j + dF(X_0)^H (dt sum_j A_j0 Y_j) (H's first column is
+// zero).  The kernel of stage m (KA_A for m = s, KA_B below) solves for Y_m, hands the
+// cotangent dt sum_{j>=m} A_{j,m-1} Y_j of F(X_{m-1}) to the grid-row adjoint, and (m = 1)
+// forms M^H sum_j Y_j for the KA_C step that adds the last F-VJP.
 struct KaArgs {
   const cplx* zbar;   // [6][Ngz][K]
   const cplx* Xb_in;  // cotangent of the step's final state (KA_A without KA_C) or F-bar (KA_G) or rhs (KA_SOLVE_T)
   cplx* Xb_out;       // cotangent of the step's initial state (KA_C) or solution (KA_SOLVE_T)
-  cplx* acc;          // [K][S] M^H (Y1 + Y2)
-  cplx* Ybuf;         // [K][S] Y2
+  cplx* acc;          // [K][S] M^H (Y_1 + ... + Y_s)
+  cplx* Ybuf;         // stage adjoints Y_2 .. Y_s, [K][S] each: Y_j at Ybuf + (j - 2) sstr
   cplx* nlbar;        // [3][Ngz][K]
-  const cplx* Xs1;    // parameter gradient (KA_B, may be null): the step's stage-1 state
-  const cplx* Xs2;    //   and its new state
+  const cplx* Xm;     // parameter gradient (may be null): the stage state X_m (X_s: the step's new state)
   double* pacc;       //   [K][2] accumulated dJ/dnu, dJ/dkappa of each wavenumber
-  double dt, g, dl;
+  size_t sstr;        // stage-slot stride of Ybuf (complex entries, all instances)
+  double dt;
+  double hc[RK_MAXS + 1];   // H_jm, j = m+1 .. s (zero elsewhere)
+  double fc[RK_MAXS + 1];   // A_{j,m-1}, j = m+1 .. s (zero elsewhere)
+  double hself, fself;      // H_mm and A_{m,m-1}
+  int stage, nst;           // m and s
   int flags;
 };
 
@@ -1108,19 +1234,17 @@ __device__ __forceinline__ cplx dl_row(const RbcDev& d, int k, const cplx* X, in
   return v;
 }
 
-// pacc[k] += -dt (<Y2, dL (g X2 + (1 - g) X1)> + g <Y1, dL X1>) for dL = dL/dnu, dL/dkappa: the
-// stage residuals' parameter derivatives against the stage adjoints (equ:efficient_gradient).
-// Y1, Y2, X1, X2 in LDS (ABI slots); red: 2 * (NTK / 64) doubles.  Block-wide.
-__device__ void param_accumulate(const RbcDev& d, const KaArgs& a, int k, const cplx* Y1, const cplx* Y2,
-                                 const cplx* X1, const cplx* X2, double* red) {
+// pacc[k] += -dt <W_m, dL X_m> for dL = dL/dnu, dL/dkappa and W_m = sum_{j>=m} H_jm Y_j: stage
+// m's share of -sum_i <Y_i, dR_i/dp>, the stage residuals' parameter derivatives
+// dR_i/dp = dt sum_{j<=i} H_ij dL X_j against the stage adjoints (equ:efficient_gradient),
+// regrouped by state.  w: this thread's entry of W_m; Xm in LDS (ABI slots); red: 2 * (NTK / 64)
+// doubles.  Block-wide.
+__device__ void param_accumulate(const RbcDev& d, const KaArgs& a, int k, cplx w, const cplx* Xm, double* red) {
   const int tid = threadIdx.x, N = d.N;
   double cn = 0.0, ck = 0.0;
   if (tid < 3 * N) {
-    const cplx l1 = dl_row(d, k, X1, tid), l2 = dl_row(d, k, X2, tid);
-    const double g = a.g;
-    const cplx t2 = cadd(cscale(l2, g), cscale(l1, 1.0 - g));
-    const cplx y1 = Y1[tid], y2 = Y2[tid];
-    const double v = (y2.x * t2.x + y2.y * t2.y) + g * (y1.x * l1.x + y1.y * l1.y);
+    const cplx l = dl_row(d, k, Xm, tid);
+    const double v = w.x * l.x + w.y * l.y;
     if (tid < 2 * N) cn = v;
     else ck = v;
   }
@@ -1214,12 +1338,27 @@ __device__ void g_to_nlbar(const RbcDev& d, const KaArgs& a, int k, const double
 // staged block operators.  One entry of every length-S vector per thread.
 template <bool STREAM>
 __global__ void __launch_bounds__(NTK) rbc_kadj(RbcDev d, KaArgs a) {
+  if (blockIdx.y) {
+    const int b = blockIdx.y;
+    const size_t st = (size_t)d.K * d.S, zs = (size_t)d.Ngz * d.K;
+    rbc_inst(d, b);
+    a.zbar = inst_ptr(a.zbar, b, 6 * zs);
+    a.nlbar = inst_ptr(a.nlbar, b, 3 * zs);
+    a.Xb_in = inst_ptr(a.Xb_in, b, st);
+    a.Xb_out = inst_ptr(a.Xb_out, b, st);
+    a.acc = inst_ptr(a.acc, b, st);
+    a.Ybuf = inst_ptr(a.Ybuf, b, st);
+    a.Xm = inst_ptr(a.Xm, b, st);
+  } else if (d.nub) {
+    rbc_inst(d, 0);
+  }
   extern __shared__ double smem_d[];
   cplx* sm = reinterpret_cast<cplx*>(smem_d);
   const int k = blockIdx.x, tid = threadIdx.x;
   const int N = d.N, S = d.S, Ngz = d.Ngz, Hc = half_nodes(Ngz);
   const int fl = a.flags;
-  const double dt = a.dt, g = a.g, dl = a.dl;
+  const double dt = a.dt;
+  const int m = a.stage;
   const bool sl = tid < S;
   const size_t ks = (size_t)k * S + tid;
   cplx* vA = sm;                // S + SPS_PAD : solver-order vector
@@ -1234,22 +1373,33 @@ __global__ void __launch_bounds__(NTK) rbc_kadj(RbcDev d, KaArgs a) {
   cplx* cb = pqz + 12 * Hc;                             // 6*N
   cplx* vv = cb + 6 * N;                                // 3*N
   // views after the solve
-  cplx* p_y2 = xbar;                                    // S
   cplx* p_t = y2;                                       // S  (Y1 + Y2)
   cplx* p_g = pqz;                                      // S  cotangent of F
   cplx* p_nh = p_g + S;                                 // 3*N
-  cplx* p_x1 = p_nh + 3 * N;                            // S  (parameter gradient: X1, X2)
-  cplx* p_x2 = p_x1 + S;                                // S
-  double* p_red = reinterpret_cast<double*>(p_x2 + S);  // 2 * NTK / 64
+  cplx* p_x = p_nh + 3 * N;                             // S  (parameter gradient: X_m)
+  double* p_red = reinterpret_cast<double*>(p_x + S);   // 2 * NTK / 64
 
   // global reads in the order they are needed, the block operators last
   const bool in_x = (fl & (KA_SOLVE_T | KA_G)) || ((fl & KA_A) && !(fl & KA_C));
   const cplx xin = (in_x && sl) ? a.Xb_in[ks] : czero();
   const cplx accv = ((fl & KA_C) && a.acc && sl) ? a.acc[ks] : czero();
-  const cplx y2v = ((fl & KA_B) && sl) ? a.Ybuf[ks] : czero();
-  const bool par = (fl & KA_B) && a.pacc;
-  const cplx x1v = (par && sl) ? a.Xs1[ks] : czero();
-  const cplx x2v = (par && sl) ? a.Xs2[ks] : czero();
+  // the later stages' adjoints, combined as they arrive: yc = sum_{j>m} H_jm Y_j (implicit
+  // coupling), fs = sum_{j>m} A_{j,m-1} Y_j (F cotangent of stage m-1), ys = sum_{j>m} Y_j
+  // (a loop over the tableau's fixed size: coefficients at constant indices)
+  cplx yc = czero(), fs = czero(), ys = czero();
+  if ((fl & KA_B) && sl) {
+#pragma unroll
+    for (int j = 2; j <= RK_MAXS; ++j) {
+      if (j > m && j <= a.nst) {
+        const cplx y = a.Ybuf[(size_t)(j - 2) * a.sstr + ks];
+        yc = cadd(yc, cscale(y, a.hc[j]));
+        fs = cadd(fs, cscale(y, a.fc[j]));
+        ys = cadd(ys, y);
+      }
+    }
+  }
+  const bool par = (fl & (KA_A | KA_B)) && a.pacc;
+  const cplx xmv = (par && sl) ? a.Xm[ks] : czero();
   const ZbarPair zp = load_zbar_pair(d, a, k, (fl & (KA_C | KA_B)) != 0);
   const double cosr = (tid < 4 * Ngz) ? d.cosz[tid] : 0.0;
   OpsRegs opsr;
@@ -1286,66 +1436,53 @@ __global__ void __launch_bounds__(NTK) rbc_kadj(RbcDev d, KaArgs a) {
     if (sl) xbar[tid] = xin;
     __syncthreads();
   }
-  if (fl & KA_A) {
-    // Y2 = A^{-H} xbar;  F cotangent of the stage-1 state: dt (1 - delta) Y2
-    rbc_gather_h(d, mr, xbar, vA);
-    rbc_solve<STREAM>(d, k, opsr, ops, vA, true);
-    rbc_scatter_h(d, mr, vA, vB);
-    if (tid < 4 * Ngz) ct[tid] = cosr;
-    if (sl) {
-      a.Ybuf[ks] = vB[tid];
-      p_g[tid] = cscale(vB[tid], dt * (1.0 - dl));
-    }
-    __syncthreads();
-    g_to_nlbar(d, a, k, ct, p_g, p_nh);
-    return;
-  }
   if (fl & KA_B) {
+    // xbar_m = F-VJP part - dt L^H sum_{j>m} H_jm Y_j
     zbar_to_coeffs(d, zp, ct, pqz, cb, vv);
-    if (sl) y2[tid] = y2v;
+    if (sl) y2[tid] = yc;
     __syncthreads();
-    // xbar_1 = F-VJP part - dt (1 - gamma) L^H Y2
     if (sl) {
       const MLRow t = mlt_col(d, k, y2, tid);
-      cplx v = cscale(t.l, -dt * (1.0 - g));
+      cplx v = cscale(t.l, -dt);
       if (tid < 3 * N) v = cadd(v, vv[tid]);
       xbar[tid] = v;
     }
     __syncthreads();
-    rbc_gather_h(d, mr, xbar, vA);
-    rbc_solve<STREAM>(d, k, opsr, ops, vA, true);
-    rbc_scatter_h(d, mr, vA, vB);     // vB = Y1
-    if (tid < 4 * Ngz) ct[tid] = cosr;
-    if (sl) {
-      p_y2[tid] = y2v;
-      p_t[tid] = cadd(vB[tid], y2v);
-      if (par) {
-        p_x1[tid] = x1v;
-        p_x2[tid] = x2v;
-      }
-    }
-    __syncthreads();
-    if (par) param_accumulate(d, a, k, vB, p_y2, p_x1, p_x2, p_red);
-    if (sl) {
-      const MLRow t = mlt_col(d, k, p_t, tid);
-      a.acc[ks] = t.m;
-      p_g[tid] = cadd(cscale(p_y2[tid], dt * dl), cscale(vB[tid], dt * g));
-    }
-    __syncthreads();
-    g_to_nlbar(d, a, k, ct, p_g, p_nh);
   }
+  // Y_m = (M + dt H_mm L)^{-H} xbar
+  rbc_gather_h(d, mr, xbar, vA);
+  rbc_solve<STREAM>(d, k, opsr, ops, vA, true);
+  rbc_scatter_h(d, mr, vA, vB);       // vB = Y_m
+  if (tid < 4 * Ngz) ct[tid] = cosr;
+  const cplx ym = sl ? vB[tid] : czero();
+  if (sl) {
+    if (m >= 2) a.Ybuf[(size_t)(m - 2) * a.sstr + ks] = ym;
+    if (m == 1) p_t[tid] = cadd(ys, ym);
+    if (par) p_x[tid] = xmv;
+    // F cotangent of stage m-1: dt sum_{j>=m} A_{j,m-1} Y_j
+    p_g[tid] = cscale(cadd(fs, cscale(ym, a.fself)), dt);
+  }
+  __syncthreads();
+  if (par) param_accumulate(d, a, k, cadd(yc, cscale(ym, a.hself)), p_x, p_red);
+  if (m == 1 && sl) a.acc[ks] = mlt_col(d, k, p_t, tid).m;
+  g_to_nlbar(d, a, k, ct, p_g, p_nh);
 }
 
 // ---------------------------------------------------------------------------- factor
+// A batch (BLnu != null): instance blockIdx.y factors a M + b (BL + nu BLnu + kappa BLka) with
+// its own nu and kappa (L is affine in them) into its own operators.
 __global__ void __launch_bounds__(NT) rbc_factor(RbcDev d, const double* BM, const double* BL, double am,
-                                                 double bl, double* ops) {
+                                                 double bl, double* ops, const double* BLnu = nullptr,
+                                                 const double* BLka = nullptr) {
   extern __shared__ double smem_d[];
   __shared__ int sh[4];
-  const int k = blockIdx.x;
-  const size_t bw = d.kl + d.ku + 1;
+  const int k = blockIdx.x, b = blockIdx.y;
+  const size_t bw = d.kl + d.ku + 1, ko = (size_t)k * d.n * bw;
   int* spiv = reinterpret_cast<int*>(smem_d + (size_t)d.n * (2 * d.kl + d.ku + 1));
-  band_factor_block(BM + (size_t)k * d.n * bw, BL + (size_t)k * d.n * bw, am, bl, d.n, d.kl, d.ku, smem_d,
-                    sh, spiv, ops + (size_t)k * d.opsize, d.err);
+  const double nu = d.nub ? d.nub[b] : 0.0, ka = d.kab ? d.kab[b] : 0.0;
+  band_factor_block(BM + ko, BL + ko, am, bl, d.n, d.kl, d.ku, smem_d, sh, spiv,
+                    ops + ((size_t)b * d.K + k) * d.opsize, d.err, BLnu ? BLnu + ko : nullptr,
+                    BLka ? BLka + ko : nullptr, nu, ka);
 }
 
 // ---------------------------------------------------------------------------- linear boundary value problem
@@ -1850,6 +1987,8 @@ __global__ void __launch_bounds__(NT) rbc_init_x(RbcDev d, const double* grid, c
   extern __shared__ double smem_d[];
   cplx* sm = reinterpret_cast<cplx*>(smem_d);
   const int zi = blockIdx.x, tid = threadIdx.x, n = d.Nx1, K = d.K;
+  grid += (size_t)blockIdx.y * n * d.Nz1;
+  tmp += (size_t)blockIdx.y * d.Nz1 * K;
   cplx* b0 = sm;
   cplx* b1 = sm + fpad_size(n);
   for (int x = tid; x < n; x += NT) b0[fpad(x)] = cmk(grid[(size_t)x * d.Nz1 + zi], 0.0);
@@ -1862,6 +2001,8 @@ __global__ void __launch_bounds__(NT) rbc_init_z(RbcDev d, const cplx* tmp, cplx
   __shared__ double ct[4 * 256];
   __shared__ cplx col[256];
   const int k = blockIdx.x, tid = threadIdx.x, N = d.N, S = d.S, K = d.K, Nz1 = d.Nz1;
+  tmp += (size_t)blockIdx.y * Nz1 * K;
+  X += (size_t)blockIdx.y * K * S;
   stage_cos(d.cosz1, ct, Nz1);
   for (int z = tid; z < Nz1; z += NT) col[z] = tmp[(size_t)z * K + k];
   __syncthreads();
@@ -1879,6 +2020,8 @@ __global__ void __launch_bounds__(NT) rbc_init_adj_z(RbcDev d, const cplx* Xb, c
   __shared__ double ct[4 * 256];
   __shared__ cplx cw[128];
   const int k = blockIdx.x, tid = threadIdx.x, N = d.N, S = d.S, K = d.K, Nz1 = d.Nz1;
+  Xb += (size_t)blockIdx.y * K * S;
+  tmp += (size_t)blockIdx.y * Nz1 * K;
   stage_cos(d.cosz1, ct, Nz1);
   for (int n = tid; n < N; n += NT) cw[n] = cscale(Xb[(size_t)k * S + 2 * N + n], (n == 0 ? 1.0 : 2.0) / Nz1);
   __syncthreads();
@@ -1889,6 +2032,8 @@ __global__ void __launch_bounds__(NT) rbc_init_adj_x(RbcDev d, const cplx* tmp, 
   extern __shared__ double smem_d[];
   cplx* sm = reinterpret_cast<cplx*>(smem_d);
   const int zi = blockIdx.x, tid = threadIdx.x, n = d.Nx1, K = d.K;
+  tmp += (size_t)blockIdx.y * d.Nz1 * K;
+  gbar += (size_t)blockIdx.y * n * d.Nz1;
   cplx* b0 = sm;
   cplx* b1 = sm + fpad_size(n);
   const cplx* t = tmp + (size_t)zi * K;
@@ -1912,6 +2057,9 @@ __global__ void __launch_bounds__(NT) rbc_cost(RbcDev d, const cplx* X, cplx* Xb
   __shared__ double red[NT];
   __shared__ cplx cf[3][128];
   const int k = blockIdx.x, tid = threadIdx.x, N = d.N, S = d.S, nc = d.ncost;
+  X += (size_t)blockIdx.y * d.K * S;
+  Xb += (size_t)blockIdx.y * d.K * S;
+  Jpart += (size_t)blockIdx.y * d.K;
   const double wk = (d.ckeep && !d.ckeep[k]) ? 0.0 : ((k / d.Kz == 0) ? 1.0 : 2.0);
   for (int e = tid; e < nc * N; e += NT) {
     const int f = e / N, n = e - f * N;
@@ -2005,11 +2153,13 @@ __global__ void rbc_param_finish(const double* pacc, int K, double nu_ra, double
   out[1] = nu_pr * sn + ka_pr * sk;
 }
 
+// out[b] = sum of part[b][0..n) in order; one block per instance b
 __global__ void sum_parts(const double* part, int n, double* out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
+  if (threadIdx.x == 0) {
+    const double* p = part + (size_t)blockIdx.x * n;
     double s = 0.0;
-    for (int i = 0; i < n; ++i) s += part[i];
-    *out = s;
+    for (int i = 0; i < n; ++i) s += p[i];
+    out[blockIdx.x] = s;
   }
 }
 
@@ -2127,7 +2277,7 @@ static void rbc_assemble(int N, double kx, double nu, double ka, double cp, doub
 // Real-ified banded M and L of every mode (mode k has wavenumber kx[k]; mode 0 is the mean mode).
 // Modes with equal wavenumbers share their assembly.
 static void host_bands(int N, const std::vector<double>& kxs, double nu, double ka, double cp, RbcHostBands& hb,
-                       double cw = 0.0) {
+                       double cw = 0.0, int force_kl = -1, int force_ku = -1) {
   const int S = 4 * N + 7, K = (int)kxs.size();
   // phases and recombination
   std::vector<signed char> rowph(S, 0), colph(S, 0);
@@ -2202,6 +2352,11 @@ static void host_bands(int N, const std::vector<double>& kxs, double nu, double 
     transform(L, bl[k]);
     if (k > 0) seen[kxs[k]] = k;
   }
+  if (force_kl >= 0) {   // the band of another operator of the same family (a batch's common layout)
+    SPS_REQUIRE(kl <= force_kl && ku <= force_ku, "operator band wider than the batch's common band");
+    kl = force_kl;
+    ku = force_ku;
+  }
   const int bw = kl + ku + 1;
   hb.kl = kl;
   hb.ku = ku;
@@ -2229,9 +2384,18 @@ void rbc_host_bands(const sps_desc& desc, RbcHostBands& hb) {
 
 class RbcProblem : public ProblemImpl {
  public:
-  RbcProblem(const sps_desc& desc, hipStream_t s) : desc_(desc) {
+  // ra (batch > 1 or ra given): a batch of instances of the problem with Rayleigh numbers ra[b]
+  // and the descriptor's other parameters; each instance has its own factors.
+  RbcProblem(const sps_desc& desc, hipStream_t s, int batch = 1, const double* ra = nullptr) : desc_(desc) {
     stream = s;
-    SPS_REQUIRE(desc.scheme == SPS_RK222, "RBC supports the RK222 scheme");
+    SPS_REQUIRE(batch >= 1 && batch <= 4096, "batch must be in [1, 4096]");
+    B_ = batch;
+    if (ra) {
+      rab_.assign(ra, ra + batch);
+      for (double r : rab_) SPS_REQUIRE(std::isfinite(r) && r > 0.0, "Rayleigh numbers must be positive");
+    }
+    SPS_REQUIRE(desc.scheme == SPS_RK222 || desc.scheme == SPS_RK443, "RBC supports the RK222 and RK443 schemes");
+    tab_ = rk_tableau(desc.scheme);
     SPS_REQUIRE(desc.nx >= 8 && desc.nx % 2 == 0, "nx must be even and >= 8");
     SPS_REQUIRE(desc.nz >= 8 && desc.nz <= 128 && desc.nz % 2 == 0, "nz must be even in [8, 128]");
     SPS_REQUIRE(desc.dealias == 1.5, "RBC uses 3/2 dealiasing");
@@ -2271,6 +2435,7 @@ class RbcProblem : public ProblemImpl {
     desc_ = sps_desc{};
     desc_.equation = SPS_COUETTE3D;
     desc_.scheme = SPS_RK222;
+    tab_ = rk_tableau(SPS_RK222);
     desc_.nx = c.nx;
     desc_.nz = c.ny;
     desc_.lx = c.lx;
@@ -2319,7 +2484,8 @@ class RbcProblem : public ProblemImpl {
   }
 
   void init() {
-    stream_solve_ = K_ > 1024;
+    dv_.B = B_;
+    stream_solve_ = (long long)K_ * B_ > 1024;
     build_tables();
     build_bands();
     alloc_work();
@@ -2341,17 +2507,22 @@ class RbcProblem : public ProblemImpl {
     if (aux_) (void)hipStreamDestroy(aux_);
   }
 
-  long long state_size() const override { return (long long)K_ * S_ * 2; }
+  long long state_size() const override { return (long long)B_ * K_ * S_ * 2; }
+  size_t st() const { return (size_t)B_ * K_ * S_; }   // complex entries of a state (all instances)
+  void no_batch(const char* what) const {
+    if (B_ > 1 || !rab_.empty()) throw Error(SPS_E_UNSUPPORTED, std::string(what) + " is not built for batches");
+  }
 
+  // M + dt H_ii L (the implicit diagonal is one value for every stage)
   void factor() override {
     if (factored_) return;
-    const double g = 1.0 - 1.0 / std::sqrt(2.0);
-    hipLaunchKernelGGL(rbc_factor, dim3(K_), dim3(NT), factor_lds(), stream, dv_, BM_, BL_, 1.0, dt_ * g, ops_);
+    hipLaunchKernelGGL(rbc_factor, dim3(K_, B_), dim3(NT), factor_lds(), stream, dv_, BM_, BL_, 1.0,
+                       dt_ * tab_.H[1][1], ops_, BLnu_, BLka_);
     SPS_CHECK_LAUNCH();
     factored_ = true;
   }
 
-  // A new step for the following runs: the RK222 matrices M + dt gamma L of every wavenumber are
+  // A new step for the following runs: the matrices M + dt H_ii L of every wavenumber are
   // refactored at once (in the scaled frame for plane Couette); recorded runs and captured
   // graphs are dropped.
   void set_dt(double dt) override {
@@ -2391,11 +2562,11 @@ class RbcProblem : public ProblemImpl {
 
   void cost(const double* X, double* J, double* dJdX) override {
     SPS_REQUIRE(X && dJdX, "null argument");
-    hipLaunchKernelGGL(rbc_cost, dim3(K_), dim3(NT), 0, stream, dv_, reinterpret_cast<const cplx*>(X),
+    hipLaunchKernelGGL(rbc_cost, dim3(K_, B_), dim3(NT), 0, stream, dv_, reinterpret_cast<const cplx*>(X),
                        reinterpret_cast<cplx*>(dJdX), Jpart_);
     SPS_CHECK_LAUNCH();
     if (J) {
-      hipLaunchKernelGGL(sum_parts, dim3(1), dim3(64), 0, stream, Jpart_, K_, J);
+      hipLaunchKernelGGL(sum_parts, dim3(B_), dim3(64), 0, stream, Jpart_, K_, J);
       SPS_CHECK_LAUNCH();
     }
   }
@@ -2410,11 +2581,12 @@ class RbcProblem : public ProblemImpl {
     SPS_REQUIRE(X0 && dJdX0, "null argument");
     SPS_REQUIRE(nsteps >= 1 && nsteps <= desc_.max_steps, "nsteps out of range");
     if (dJdtheta) {
+      no_batch("the parameter gradient");
       if (cou_) throw Error(SPS_E_UNSUPPORTED, "parameter gradients are built for the 2D problem");
       if (ckpt_mode_ != SPS_CKPT_UNIFORM)
         throw Error(SPS_E_UNSUPPORTED, "parameter gradients need the uniform checkpoint schedule");
       if (!sst_) {
-        sst_ = arena_.alloc<cplx>((size_t)2 * seglen_ * 2 * K_ * S_);
+        sst_ = arena_.alloc<cplx>((size_t)2 * seglen_ * tab_.s * K_ * S_);
         pacc_ = arena_.alloc<double>((size_t)2 * K_);
       }
     }
@@ -2453,11 +2625,11 @@ class RbcProblem : public ProblemImpl {
       RbcProblem* p;
       ~Off() { p->param_on_ = false; p->theta_out_ = nullptr; }
     } off{this};
-    SPS_HIP(hipMemcpyAsync(Xg_, X0, sizeof(cplx) * K_ * S_, hipMemcpyDeviceToDevice, stream));
+    SPS_HIP(hipMemcpyAsync(Xg_, X0, sizeof(cplx) * st(), hipMemcpyDeviceToDevice, stream));
     forward(Xg_, nsteps);
-    if (XN) SPS_HIP(hipMemcpyAsync(XN, Xg_, sizeof(cplx) * K_ * S_, hipMemcpyDeviceToDevice, stream));
+    if (XN) SPS_HIP(hipMemcpyAsync(XN, Xg_, sizeof(cplx) * st(), hipMemcpyDeviceToDevice, stream));
     if (dJdXN) {
-      if (dJdXN != dJdX0) SPS_HIP(hipMemcpyAsync(dJdX0, dJdXN, sizeof(cplx) * K_ * S_, hipMemcpyDeviceToDevice, stream));
+      if (dJdXN != dJdX0) SPS_HIP(hipMemcpyAsync(dJdX0, dJdXN, sizeof(cplx) * st(), hipMemcpyDeviceToDevice, stream));
     } else {
       cost(reinterpret_cast<const double*>(Xg_), J, dJdX0);
     }
@@ -2467,32 +2639,37 @@ class RbcProblem : public ProblemImpl {
   void initial_state(const double* grid, double* X) override {
     if (cou_) throw Error(SPS_E_UNSUPPORTED, "Couette states are given as coefficients");
     SPS_REQUIRE(grid && X, "null argument");
-    hipLaunchKernelGGL(rbc_init_x, dim3(N_), dim3(NT), 2 * fpad_size(desc_.nx) * sizeof(cplx), stream, dv_, grid, itmp_);
+    hipLaunchKernelGGL(rbc_init_x, dim3(N_, B_), dim3(NT), 2 * fpad_size(desc_.nx) * sizeof(cplx), stream, dv_, grid,
+                       itmp_);
     SPS_CHECK_LAUNCH();
-    hipLaunchKernelGGL(rbc_init_z, dim3(K_), dim3(NT), 0, stream, dv_, itmp_, reinterpret_cast<cplx*>(X));
+    hipLaunchKernelGGL(rbc_init_z, dim3(K_, B_), dim3(NT), 0, stream, dv_, itmp_, reinterpret_cast<cplx*>(X));
     SPS_CHECK_LAUNCH();
   }
 
   void initial_state_adjoint(const double* Xbar, double* grid) override {
     if (cou_) throw Error(SPS_E_UNSUPPORTED, "Couette states are given as coefficients");
     SPS_REQUIRE(grid && Xbar, "null argument");
-    hipLaunchKernelGGL(rbc_init_adj_z, dim3(K_), dim3(NT), 0, stream, dv_, reinterpret_cast<const cplx*>(Xbar), itmp_);
+    hipLaunchKernelGGL(rbc_init_adj_z, dim3(K_, B_), dim3(NT), 0, stream, dv_, reinterpret_cast<const cplx*>(Xbar),
+                       itmp_);
     SPS_CHECK_LAUNCH();
-    hipLaunchKernelGGL(rbc_init_adj_x, dim3(N_), dim3(NT), 2 * fpad_size(desc_.nx) * sizeof(cplx), stream, dv_, itmp_, grid);
+    hipLaunchKernelGGL(rbc_init_adj_x, dim3(N_, B_), dim3(NT), 2 * fpad_size(desc_.nx) * sizeof(cplx), stream, dv_,
+                       itmp_, grid);
     SPS_CHECK_LAUNCH();
   }
 
   void eval_F(const double* X, double* F) override {
+    no_batch("this evaluation");
     SPS_REQUIRE(X && F, "null argument");
-    launch_kf(KF_ZGRID, reinterpret_cast<const cplx*>(X), nullptr, nullptr, zgA_);
+    launch_kf(KF_ZGRID, reinterpret_cast<const cplx*>(X), nullptr, zgA_);
     launch_xf(zgA_);
-    launch_kf(KF_EVALF, nullptr, nullptr, reinterpret_cast<cplx*>(F), nullptr);
+    launch_kf(KF_EVALF, nullptr, reinterpret_cast<cplx*>(F), nullptr);
   }
 
   // eval_F with its intermediates in the library's static per-device scratch: no device
   // allocation, no timer events, three launches on the problem's stream.  Calls that overlap
   // on one GPU share the scratch and race.
   void eval_F_noalloc(const double* X, double* F) override {
+    no_batch("the allocation-free evaluation");
     if (cou_) throw Error(SPS_E_UNSUPPORTED, "the allocation-free evaluation is built for the 2D problem");
     SPS_REQUIRE(X && F, "null argument");
     const size_t need = (size_t)9 * Ngz_ * K_ * sizeof(cplx);
@@ -2503,14 +2680,9 @@ class RbcProblem : public ProblemImpl {
     cplx* nl = zg + (size_t)6 * Ngz_ * K_;
     KfArgs a{};
     a.X0 = reinterpret_cast<const cplx*>(X);
-    a.X1 = nullptr;
-    a.Xout = nullptr;
     a.nl = nl;
-    a.F0 = nullptr;
     a.zg = zg;
     a.dt = dt_;
-    a.g = 1.0 - 1.0 / std::sqrt(2.0);
-    a.dl = 1.0 - 1.0 / (2.0 * a.g);
     a.mode = KF_ZGRID;
     hipLaunchKernelGGL(kfwd_fn(), dim3(K_), dim3(NTK), kf_lds(), stream, dv_, a);
     SPS_CHECK_LAUNCH();
@@ -2524,8 +2696,9 @@ class RbcProblem : public ProblemImpl {
   }
 
   void eval_F_vjp(const double* X, const double* Fbar, double* Xbar) override {
+    no_batch("this evaluation");
     SPS_REQUIRE(X && Fbar && Xbar, "null argument");
-    launch_kf(KF_ZGRID, reinterpret_cast<const cplx*>(X), nullptr, nullptr, zgA_);
+    launch_kf(KF_ZGRID, reinterpret_cast<const cplx*>(X), nullptr, zgA_);
     KaArgs a = ka_args(KA_G);
     a.Xb_in = reinterpret_cast<const cplx*>(Fbar);
     launch_ka(a);
@@ -2537,10 +2710,11 @@ class RbcProblem : public ProblemImpl {
   }
 
   void solve(const double* R, double* X, int adjoint) override {
+    no_batch("this evaluation");
     SPS_REQUIRE(R && X, "null argument");
     factor();
     if (!adjoint) {
-      launch_kf(KF_SOLVE, reinterpret_cast<const cplx*>(R), nullptr, reinterpret_cast<cplx*>(X), nullptr);
+      launch_kf(KF_SOLVE, reinterpret_cast<const cplx*>(R), reinterpret_cast<cplx*>(X), nullptr);
     } else {
       KaArgs a = ka_args(KA_SOLVE_T);
       a.Xb_in = reinterpret_cast<const cplx*>(R);
@@ -2563,6 +2737,7 @@ class RbcProblem : public ProblemImpl {
   }
 
   void lbvp_solve(const double* f, double* X) override {
+    no_batch("the boundary value problem");
     if (cou_) throw Error(SPS_E_UNSUPPORTED, "the boundary value problem is built for the 2D problem");
     SPS_REQUIRE(f && X, "null argument");
     lbvp_factor();
@@ -2570,22 +2745,15 @@ class RbcProblem : public ProblemImpl {
     SPS_CHECK_LAUNCH();
     RbcDev dl = dv_;
     dl.ops = lops_;
-    KfArgs a{};
+    KfArgs a = kf_args(KF_SOLVE);
     a.X0 = lrhs_;
-    a.X1 = nullptr;
     a.Xout = reinterpret_cast<cplx*>(X);
-    a.nl = nl_;
-    a.F0 = F0_;
-    a.zg = nullptr;
-    a.dt = dt_;
-    a.g = 1.0 - 1.0 / std::sqrt(2.0);
-    a.dl = 1.0 - 1.0 / (2.0 * a.g);
-    a.mode = KF_SOLVE;
     hipLaunchKernelGGL(kfwd_fn(), dim3(K_), dim3(NTK), kf_lds(), stream, dl, a);
     SPS_CHECK_LAUNCH();
   }
 
   void lbvp_adjoint(const double* Xbar, double* fbar) override {
+    no_batch("the boundary value problem");
     if (cou_) throw Error(SPS_E_UNSUPPORTED, "the boundary value problem is built for the 2D problem");
     SPS_REQUIRE(Xbar && fbar, "null argument");
     lbvp_factor();
@@ -2645,17 +2813,15 @@ class RbcProblem : public ProblemImpl {
   }
   // y = (sigma M + L_s)^-1 r
   void evp_solve(const RbcDev& de, const cplx* r, cplx* y) {
-    KfArgs a{};
+    KfArgs a = kf_args(KF_SOLVE);
     a.X0 = r;
     a.Xout = y;
-    a.nl = nl_;
-    a.F0 = F0_;
-    a.mode = KF_SOLVE;
     hipLaunchKernelGGL(kfwd_fn(), dim3(K_), dim3(NTK), kf_lds(), stream, de, a);
     SPS_CHECK_LAUNCH();
   }
 
   void stability(double sigma, int iters, double* lam, double* X, double* Y, double* dlam) override {
+    no_batch("the eigenvalue problem");
     if (cou_) throw Error(SPS_E_UNSUPPORTED, "the eigenvalue problem is built for the 2D problem");
     SPS_REQUIRE(lam && X && Y && dlam, "null argument");
     SPS_REQUIRE(iters >= 1 && iters <= 10000, "iters must be in [1, 10000]");
@@ -2691,6 +2857,7 @@ class RbcProblem : public ProblemImpl {
 
   void stability_vector_sens(double sigma, int iters, const double* lam, const double* X, const double* Y,
                              const double* dlam, double* dX) override {
+    no_batch("the eigenvalue problem");
     if (cou_) throw Error(SPS_E_UNSUPPORTED, "the eigenvalue problem is built for the 2D problem");
     SPS_REQUIRE(lam && X && Y && dlam && dX, "null argument");
     SPS_REQUIRE(iters >= 1 && iters <= 10000, "iters must be in [1, 10000]");
@@ -2729,6 +2896,7 @@ class RbcProblem : public ProblemImpl {
 
   void stability_arnoldi(double sigma, int m, int nev, const double* v0, double* lam, double* X, double* res,
                          double* Hout) override {
+    no_batch("the eigenvalue problem");
     if (cou_) throw Error(SPS_E_UNSUPPORTED, "the eigenvalue problem is built for the 2D problem");
     SPS_REQUIRE(lam != nullptr, "lam is null");
     SPS_REQUIRE(m >= 2 && m <= ARN_MAX_M, "m must be in [2, 64]");
@@ -2861,30 +3029,54 @@ class RbcProblem : public ProblemImpl {
     graphs_.clear();
   }
 
-  void launch_kf(int mode, const cplx* X0, const cplx* X1, cplx* Xout, cplx* zg) {
-    launch_kf_on(stream, mode, X0, X1, Xout, zg);
+  // a non-stage launch of the forward kernel (grid fields, F, a solve)
+  void launch_kf(int mode, const cplx* X0, cplx* Xout, cplx* zg) { launch_kf_on(stream, mode, X0, Xout, zg); }
+  void launch_kf_on(hipStream_t s, int mode, const cplx* X0, cplx* Xout, cplx* zg) {
+    KfArgs a = kf_args(mode);
+    a.X0 = X0;
+    a.Xout = Xout;
+    a.zg = zg;
+    launch_kf_args(s, a);
+  }
+  KfArgs kf_args(int mode) const {
+    KfArgs a{};
+    a.Xst = Xst_;
+    a.Fst = Fst_;
+    a.nl = nl_;
+    a.sstr = st();
+    a.fstr = (size_t)B_ * K_ * 3 * N_;
+    a.dt = dt_;
+    a.nst = tab_.s;
+    a.mode = mode;
+    return a;
+  }
+  // stage i (1 .. s) of a step from X: the stage's state goes to its slot of Xst_ (i < s) or
+  // back into X (i = s, the new state); zg: where its grid fields go (nullable); save: a second
+  // copy of its state (nullable)
+  void launch_stage(hipStream_t s, int i, cplx* X, cplx* zg, cplx* save) {
+    KfArgs a = kf_args(KF_STAGE);
+    a.X0 = X;
+    a.Xout = (i < tab_.s) ? Xst_ + (size_t)(i - 1) * st() : X;
+    a.zg = zg;
+    a.Xsave = save;
+    a.stage = i;
+    for (int j = 0; j < i; ++j) {
+      a.fa[j] = tab_.A[i][j];
+      a.lh[j] = tab_.H[i][j];
+      a.asum += tab_.A[i][j];
+      if (tab_.H[i][j] != 0.0) a.lx = 1;
+    }
+    a.fself = tab_.A[i][i - 1];
+    launch_kf_args(s, a);
   }
   // stage launches on the caller's stream are timed (on the auxiliary stream a launch may share
   // the chip with the adjoint sweep)
-  void launch_kf_on(hipStream_t s, int mode, const cplx* X0, const cplx* X1, cplx* Xout, cplx* zg,
-                    cplx* save = nullptr) {
-    KfArgs a;
-    a.X0 = X0;
-    a.X1 = X1;
-    a.Xout = Xout;
-    a.nl = nl_;
-    a.F0 = F0_;
-    a.zg = zg;
-    a.Xsave = save;
-    a.dt = dt_;
-    a.g = 1.0 - 1.0 / std::sqrt(2.0);
-    a.dl = 1.0 - 1.0 / (2.0 * a.g);
-    a.mode = mode;
+  void launch_kf_args(hipStream_t s, const KfArgs& a) {
     hipEvent_t e0, e1;
-    if ((mode == KF_STAGE1 || mode == KF_STAGE2) && timed(0, s, &e0, &e1))
-      hipExtLaunchKernelGGL(kfwd_fn(), dim3(K_), dim3(NTK), kf_lds(), s, e0, e1, 0, dv_, a);
+    if (a.mode == KF_STAGE && timed(0, s, &e0, &e1))
+      hipExtLaunchKernelGGL(kfwd_fn(), dim3(K_, B_), dim3(NTK), kf_lds(), s, e0, e1, 0, dv_, a);
     else
-      hipLaunchKernelGGL(kfwd_fn(), dim3(K_), dim3(NTK), kf_lds(), s, dv_, a);
+      hipLaunchKernelGGL(kfwd_fn(), dim3(K_, B_), dim3(NTK), kf_lds(), s, dv_, a);
     SPS_CHECK_LAUNCH();
   }
   void launch_xf(const cplx* zg, hipStream_t s = nullptr) {
@@ -2899,37 +3091,43 @@ class RbcProblem : public ProblemImpl {
     XfArgs a{zg, nl};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const bool t = timed(2, s, &e0, &e1);
-    if (wave_r1_ == 6) hipExtLaunchKernelGGL(rbc_xfwd_w<6>, dim3(Ngz_), dim3(256), xfw_lds(), s, t ? e0 : nullptr, t ? e1 : nullptr, 0, dv_, a);
-    else if (wave_r1_ == 3) hipExtLaunchKernelGGL(rbc_xfwd_w<3>, dim3(Ngz_), dim3(256), xfw_lds(), s, t ? e0 : nullptr, t ? e1 : nullptr, 0, dv_, a);
-    else hipExtLaunchKernelGGL(rbc_xfwd, dim3(Ngz_), dim3(NTX), xf_lds(), s, t ? e0 : nullptr, t ? e1 : nullptr, 0, dv_, a);
+    const dim3 g(Ngz_, B_);
+    if (wave_r1_ == 6) hipExtLaunchKernelGGL(rbc_xfwd_w<6>, g, dim3(256), xfw_lds(), s, t ? e0 : nullptr, t ? e1 : nullptr, 0, dv_, a);
+    else if (wave_r1_ == 3) hipExtLaunchKernelGGL(rbc_xfwd_w<3>, g, dim3(256), xfw_lds(), s, t ? e0 : nullptr, t ? e1 : nullptr, 0, dv_, a);
+    else hipExtLaunchKernelGGL(rbc_xfwd, g, dim3(NTX), xf_lds(), s, t ? e0 : nullptr, t ? e1 : nullptr, 0, dv_, a);
     SPS_CHECK_LAUNCH();
   }
   size_t xfw_lds() const { return sizeof(cplx) * (Ngx_ + 4 * wave_sc() + 4 * 512); }
   size_t xaw_lds() const { return sizeof(cplx) * (Ngx_ + 6 * wave_sc() + 6 * 512); }
   int wave_sc() const { return wave_r1_ == 6 ? WaveRow<6>::SC : WaveRow<3>::SC; }
-  KaArgs ka_args(int flags) {
-    KaArgs a;
+  // adjoint kernel arguments; stage m (1 .. s) for the stage reverses KA_A (m = s) and KA_B
+  KaArgs ka_args(int flags, int m = 0) {
+    KaArgs a{};
     a.zbar = zbar_;
-    a.Xb_in = nullptr;
-    a.Xb_out = nullptr;
     a.acc = acc_;
     a.Ybuf = Ybuf_;
     a.nlbar = nlbar_;
-    a.Xs1 = nullptr;
-    a.Xs2 = nullptr;
-    a.pacc = nullptr;
+    a.sstr = st();
     a.dt = dt_;
-    a.g = 1.0 - 1.0 / std::sqrt(2.0);
-    a.dl = 1.0 - 1.0 / (2.0 * a.g);
+    a.stage = m;
+    a.nst = tab_.s;
+    if (m >= 1) {
+      for (int j = m + 1; j <= tab_.s; ++j) {
+        a.hc[j] = tab_.H[j][m];
+        a.fc[j] = tab_.A[j][m - 1];
+      }
+      a.hself = tab_.H[m][m];
+      a.fself = tab_.A[m][m - 1];
+    }
     a.flags = flags;
     return a;
   }
   void launch_ka(const KaArgs& a) {
     hipEvent_t e0, e1;
     if ((a.flags & (KA_A | KA_B)) && !(a.flags & KA_SOLVE_T) && timed(1, stream, &e0, &e1))
-      hipExtLaunchKernelGGL(kadj_fn(), dim3(K_), dim3(NTK), ka_lds(), stream, e0, e1, 0, dv_, a);
+      hipExtLaunchKernelGGL(kadj_fn(), dim3(K_, B_), dim3(NTK), ka_lds(), stream, e0, e1, 0, dv_, a);
     else
-      hipLaunchKernelGGL(kadj_fn(), dim3(K_), dim3(NTK), ka_lds(), stream, dv_, a);
+      hipLaunchKernelGGL(kadj_fn(), dim3(K_, B_), dim3(NTK), ka_lds(), stream, dv_, a);
     SPS_CHECK_LAUNCH();
   }
   void launch_xa(const cplx* zg) {
@@ -2941,29 +3139,56 @@ class RbcProblem : public ProblemImpl {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const bool t = timed(3, stream, &e0, &e1);
     if (!t) e0 = e1 = nullptr;
-    if (wave_r1_ == 6) hipExtLaunchKernelGGL(rbc_xadj_w<6>, dim3(Ngz_), dim3(384), xaw_lds(), stream, e0, e1, 0, dv_, a);
-    else if (wave_r1_ == 3) hipExtLaunchKernelGGL(rbc_xadj_w<3>, dim3(Ngz_), dim3(384), xaw_lds(), stream, e0, e1, 0, dv_, a);
-    else hipExtLaunchKernelGGL(rbc_xadj, dim3(Ngz_), dim3(NTX), xa_lds(), stream, e0, e1, 0, dv_, a);
+    const dim3 g(Ngz_, B_);
+    if (wave_r1_ == 6) hipExtLaunchKernelGGL(rbc_xadj_w<6>, g, dim3(384), xaw_lds(), stream, e0, e1, 0, dv_, a);
+    else if (wave_r1_ == 3) hipExtLaunchKernelGGL(rbc_xadj_w<3>, g, dim3(384), xaw_lds(), stream, e0, e1, 0, dv_, a);
+    else hipExtLaunchKernelGGL(rbc_xadj, g, dim3(NTX), xa_lds(), stream, e0, e1, 0, dv_, a);
     SPS_CHECK_LAUNCH();
   }
 
-  // segment store: two buffers of z-grid fields (step s, stage q), used by alternate segments
-  cplx* slot(int buf, int s, int stage) { return seg_ + (((size_t)buf * seglen_ + s) * 2 + stage) * zsize_; }
-  cplx* ckpt(int c) { return ckpt_ + (size_t)c * K_ * S_; }
-
-  // One RK222 step from X (in place) on stream s.  zin: x-spectral z-grid fields of X;
-  // zs1: where stage 1 writes its fields; zout: where the new state's fields go (or null).
-  // save1, save2 (nullable): where the stage-1 state and the new state are also stored (the
-  // parameter gradient's records).
-  void rk_step(hipStream_t s, cplx* X, const cplx* zin, cplx* zs1, cplx* zout, cplx* save1 = nullptr,
-               cplx* save2 = nullptr) {
-    launch_xf(zin, s);
-    launch_kf_on(s, KF_STAGE1, X, nullptr, X1_, zs1, save1);
-    launch_xf(zs1, s);
-    launch_kf_on(s, KF_STAGE2, X, X1_, X, zout, save2);
+  // segment store: two buffers of z-grid fields (step s, stage q < s_stages: the fields of the
+  // states F is evaluated at), used by alternate segments
+  cplx* slot(int buf, int s, int stage) {
+    return seg_ + (((size_t)buf * seglen_ + s) * tab_.s + stage) * zsize_;
   }
-  // state records of the parameter gradient: two buffers of (stage-1 state, new state) per step
-  cplx* sslot(int buf, int s, int q) { return sst_ + (((size_t)buf * seglen_ + s) * 2 + q) * K_ * S_; }
+  cplx* ckpt(int c) { return ckpt_ + (size_t)c * st(); }
+
+  // One IMEX RK step from X (in place) on stream st.  z(q), q < s: the x-spectral z-grid fields
+  // of stage q's state (z(0): those of X, given; the stages write the others); zout: where the
+  // new state's fields go (or null).  sv(q) (nullable): where stage q+1's state is also stored
+  // (the parameter gradient's records; sv(s-1) is the new state).
+  template <class ZF, class SF>
+  void rk_step(hipStream_t st, cplx* X, ZF z, cplx* zout, SF sv) {
+    const int s = tab_.s;
+    for (int i = 1; i <= s; ++i) {
+      launch_xf(z(i - 1), st);
+      launch_stage(st, i, X, (i < s) ? z(i) : zout, sv(i - 1));
+    }
+  }
+  static cplx* no_save(int) { return nullptr; }
+  // state records of the parameter gradient: two buffers of the s stage states per step
+  cplx* sslot(int buf, int s, int q) { return sst_ + (((size_t)buf * seglen_ + s) * tab_.s + q) * K_ * S_; }
+
+  // The adjoint launches of one step: its stages in reverse, each followed by the grid-row
+  // adjoint of the F it differentiates.  z(q): the fields of stage q's state recorded by the
+  // step's forward run; sv(q): stage q+1's state (parameter gradient only).  `first`: no step
+  // has been reversed yet in this sweep (Xbar is the cotangent of the step's new state);
+  // otherwise the stage-s kernel first completes the later step's initial-state cotangent.
+  template <class ZF, class SF>
+  void reverse_step(cplx* Xbar, bool& first, ZF z, SF sv) {
+    const int s = tab_.s;
+    for (int m = s; m >= 1; --m) {
+      KaArgs a = ka_args(m == s ? (first ? KA_A : (KA_C | KA_A)) : KA_B, m);
+      if (m == s) a.Xb_in = Xbar;
+      if (param_on_) {
+        a.Xm = sv(m - 1);
+        a.pacc = pacc_;
+      }
+      launch_ka(a);
+      first = false;
+      launch_xa(z(m - 1));
+    }
+  }
 
   void forward(cplx* X, int nsteps) {
     if (ckpt_mode_ == SPS_CKPT_BINOMIAL) {
@@ -2982,10 +3207,11 @@ class RbcProblem : public ProblemImpl {
     // inside the last segment, the segment store read back by the reverse sweep
     auto zpos = [&](int n, int q) { return (n >= last0) ? slot(lb, n - last0, q) : zgA_; };
     auto spos = [&](int n, int q) { return (param_on_ && n >= last0) ? sslot(lb, n - last0, q) : nullptr; };
-    launch_kf(KF_ZGRID, X, nullptr, nullptr, zpos(0, 0));
+    launch_kf(KF_ZGRID, X, nullptr, zpos(0, 0));
     for (int n = 0; n < nsteps; ++n) {
-      if (n % ce == 0) SPS_HIP(hipMemcpyAsync(ckpt(n / ce), X, sizeof(cplx) * K_ * S_, hipMemcpyDeviceToDevice, stream));
-      rk_step(stream, X, zpos(n, 0), zpos(n, 1), (n + 1 < nsteps) ? zpos(n + 1, 0) : nullptr, spos(n, 0), spos(n, 1));
+      if (n % ce == 0) SPS_HIP(hipMemcpyAsync(ckpt(n / ce), X, sizeof(cplx) * st(), hipMemcpyDeviceToDevice, stream));
+      rk_step(stream, X, [&](int q) { return zpos(n, q); }, (n + 1 < nsteps) ? zpos(n + 1, 0) : nullptr,
+              [&](int q) { return spos(n, q); });
     }
     tape_steps_ = nsteps;
     last_seg_ok_ = true;
@@ -2994,14 +3220,14 @@ class RbcProblem : public ProblemImpl {
   // re-run segment seg from its checkpoint on stream s into segment buffer seg & 1
   void recompute(int seg, int len, hipStream_t s) {
     const int b = seg & 1;
-    SPS_HIP(hipMemcpyAsync(Xw_, ckpt(seg), sizeof(cplx) * K_ * S_, hipMemcpyDeviceToDevice, s));
-    launch_kf_on(s, KF_ZGRID, Xw_, nullptr, nullptr, slot(b, 0, 0));
+    SPS_HIP(hipMemcpyAsync(Xw_, ckpt(seg), sizeof(cplx) * st(), hipMemcpyDeviceToDevice, s));
+    launch_kf_on(s, KF_ZGRID, Xw_, nullptr, slot(b, 0, 0));
     for (int j = 0; j < len; ++j)
-      rk_step(s, Xw_, slot(b, j, 0), slot(b, j, 1), (j + 1 < len) ? slot(b, j + 1, 0) : nullptr,
-              param_on_ ? sslot(b, j, 0) : nullptr, param_on_ ? sslot(b, j, 1) : nullptr);
+      rk_step(s, Xw_, [&](int q) { return slot(b, j, q); }, (j + 1 < len) ? slot(b, j + 1, 0) : nullptr,
+              [&](int q) { return param_on_ ? sslot(b, j, q) : nullptr; });
   }
 
-  // Reverse sweep.  The recompute of segment seg-1 (auxiliary stream, scratch X1_, Xw_, nl_, F0_,
+  // Reverse sweep.  The recompute of segment seg-1 (auxiliary stream, scratch Xst_, Xw_, nl_, Fst_,
   // segment buffer (seg-1)&1) overlaps the adjoint of segment seg (caller's stream, scratch
   // acc_, Ybuf_, nlbar_, zbar_, segment buffer seg&1).  Events order (i) every recompute after
   // the forward sweep, (ii) the adjoint of seg after its recompute, (iii) the recompute into a
@@ -3038,21 +3264,8 @@ class RbcProblem : public ProblemImpl {
         recompute(seg - 1, seglen(seg - 1), aux_);
         SPS_HIP(hipEventRecord(ev_rec, aux_));
       }
-      for (int j = len - 1; j >= 0; --j) {
-        KaArgs a = ka_args(first ? KA_A : (KA_C | KA_A));
-        a.Xb_in = Xbar;
-        launch_ka(a);
-        first = false;
-        launch_xa(slot(b, j, 1));
-        KaArgs ab = ka_args(KA_B);
-        if (param_on_) {
-          ab.Xs1 = sslot(b, j, 0);
-          ab.Xs2 = sslot(b, j, 1);
-          ab.pacc = pacc_;
-        }
-        launch_ka(ab);
-        launch_xa(slot(b, j, 0));
-      }
+      for (int j = len - 1; j >= 0; --j)
+        reverse_step(Xbar, first, [&](int q) { return slot(b, j, q); }, [&](int q) { return sslot(b, j, q); });
       SPS_HIP(hipEventRecord(ev_adj, stream));
     }
     last_seg_ok_ = nseg < 3;
@@ -3077,6 +3290,7 @@ class RbcProblem : public ProblemImpl {
   // step's two stage-field sets in the first segment slot and runs the step's adjoint launches,
   // exactly those of the segment sweep.
   void set_checkpointing(int scheme, int slots) override {
+    if (scheme != SPS_CKPT_UNIFORM) no_batch("this checkpoint schedule");
     SPS_REQUIRE(scheme == SPS_CKPT_UNIFORM || scheme == SPS_CKPT_BINOMIAL || scheme == SPS_CKPT_TWO_LEVEL,
                 "unknown checkpointing scheme");
     if (scheme != SPS_CKPT_UNIFORM) {
@@ -3111,8 +3325,8 @@ class RbcProblem : public ProblemImpl {
     SPS_HIP(hipMemcpyAsync(dst, src, sizeof(cplx) * K_ * S_, hipMemcpyDefault, stream));
   }
   void advance(cplx* X, int a, int b) {
-    launch_kf(KF_ZGRID, X, nullptr, nullptr, zgA_);
-    for (int n = a; n < b; ++n) rk_step(stream, X, zgA_, zgA_, (n + 1 < b) ? zgA_ : nullptr);
+    launch_kf(KF_ZGRID, X, nullptr, zgA_);
+    for (int n = a; n < b; ++n) rk_step(stream, X, [&](int) { return zgA_; }, (n + 1 < b) ? zgA_ : nullptr, no_save);
   }
   // forward actions of a schedule on the working state X (stored states in the slots); with
   // to_end false, the advance past the last stored state (to the run's final state) is skipped
@@ -3134,15 +3348,10 @@ class RbcProblem : public ProblemImpl {
         case CK_TAKESHOT: copy_state(rvslot(c.a), Xw_); break;
         case CK_ADVANCE: advance(Xw_, c.a, c.b); break;
         case CK_YOUTURN: {
-          launch_kf(KF_ZGRID, Xw_, nullptr, nullptr, slot(0, 0, 0));
-          rk_step(stream, Xw_, slot(0, 0, 0), slot(0, 0, 1), nullptr);
-          KaArgs a = ka_args(first ? KA_A : (KA_C | KA_A));
-          a.Xb_in = Xbar;
-          launch_ka(a);
-          first = false;
-          launch_xa(slot(0, 0, 1));
-          launch_ka(ka_args(KA_B));
-          launch_xa(slot(0, 0, 0));
+          auto z = [&](int q) { return slot(0, 0, q); };
+          launch_kf(KF_ZGRID, Xw_, nullptr, slot(0, 0, 0));
+          rk_step(stream, Xw_, z, nullptr, no_save);
+          reverse_step(Xbar, first, z, no_save);
           break;
         }
         default: throw Error(SPS_E_STATE, "bad checkpoint action");
@@ -3332,6 +3541,7 @@ class RbcProblem : public ProblemImpl {
 
  public:
   void set_checkpoint_file(const char* path) override {
+    no_batch("the disk checkpoint level");
     drop_graphs();
     SPS_HIP(hipStreamSynchronize(stream));   // copies into the host level may be in flight
     close_ckpt_file();
@@ -3355,6 +3565,7 @@ class RbcProblem : public ProblemImpl {
     host_cap_ = 0;
   }
   void set_outer_slots(int slots) override {
+    no_batch("the nested checkpoint schedule");
     SPS_REQUIRE(slots >= 0, "outer slots must be >= 0");
     drop_graphs();
     SPS_HIP(hipStreamSynchronize(stream));
@@ -3412,6 +3623,27 @@ class RbcProblem : public ProblemImpl {
     host_bands(N_, kxs_, nu_, ka_, cp_, hb);
     kl_ = hb.kl;
     ku_ = hb.ku;
+    if (!rab_.empty()) {
+      // a batch: L = L0 + nu Lnu + kappa Lka on the common band, per-instance nu and kappa
+      RbcHostBands h0, hn, hk;
+      host_bands(N_, kxs_, 0.0, 0.0, cp_, h0, 0.0, kl_, ku_);
+      host_bands(N_, kxs_, 1.0, 0.0, cp_, hn, 0.0, kl_, ku_);
+      host_bands(N_, kxs_, 0.0, 1.0, cp_, hk, 0.0, kl_, ku_);
+      for (size_t e = 0; e < hn.BL.size(); ++e) {
+        hn.BL[e] -= h0.BL[e];
+        hk.BL[e] -= h0.BL[e];
+      }
+      hb.BL = h0.BL;
+      BLnu_ = arena_.upload(hn.BL, stream);
+      BLka_ = arena_.upload(hk.BL, stream);
+      std::vector<double> nub(B_), kab(B_);
+      for (int b = 0; b < B_; ++b) {
+        nub[b] = std::pow(rab_[b] / desc_.param1, -0.5);
+        kab[b] = std::pow(rab_[b] * desc_.param1, -0.5);
+      }
+      dv_.nub = arena_.upload(nub, stream);
+      dv_.kab = arena_.upload(kab, stream);
+    }
     SPS_REQUIRE(kl_ + SPS_BLK <= SPS_TW && SPS_BLK + kl_ + ku_ <= SPS_GW, "band too wide for the block solver");
     SPS_REQUIRE(blk_ops_size(S_) <= 2 * SPS_OPS_REG * NTK, "nz too large for the staged block solver");
     SPS_REQUIRE(S_ + SPS_PAD <= NTK && 4 * N_ + 28 <= NTK && 4 * Ngz_ <= NTK && 6 * half_nodes(Ngz_) <= NTK,
@@ -3444,31 +3676,32 @@ class RbcProblem : public ProblemImpl {
   }
 
   void alloc_work() {
-    const size_t st = (size_t)K_ * S_;
-    zsize_ = (size_t)6 * Ngz_ * K_;
+    const size_t st = (size_t)B_ * K_ * S_;
+    zsize_ = (size_t)B_ * 6 * Ngz_ * K_;
     dv_.opsize = blk_ops_size(S_);
-    ops_ = arena_.alloc<double>((size_t)K_ * dv_.opsize);
+    ops_ = arena_.alloc<double>((size_t)B_ * K_ * dv_.opsize);
     dv_.ops = ops_;
     err_ = arena_.alloc<int>(1);
     SPS_HIP(hipMemsetAsync(err_, 0, sizeof(int), stream));
     dv_.err = err_;
-    X1_ = arena_.alloc<cplx>(st);
+    const int ns = tab_.s;
+    Xst_ = arena_.alloc<cplx>((size_t)(ns - 1) * st);
     Xw_ = arena_.alloc<cplx>(st);
     Xg_ = arena_.alloc<cplx>(st);
     acc_ = arena_.alloc<cplx>(st);
-    Ybuf_ = arena_.alloc<cplx>(st);
-    F0_ = arena_.alloc<cplx>((size_t)K_ * 3 * N_);
+    Ybuf_ = arena_.alloc<cplx>((size_t)(ns - 1) * st);
+    Fst_ = arena_.alloc<cplx>((size_t)(ns - 1) * B_ * K_ * 3 * N_);
     zgA_ = arena_.alloc<cplx>(zsize_);
     zbar_ = arena_.alloc<cplx>(zsize_);
-    nl_ = arena_.alloc<cplx>((size_t)3 * Ngz_ * K_);
-    nlbar_ = arena_.alloc<cplx>((size_t)3 * Ngz_ * K_);
-    itmp_ = arena_.alloc<cplx>((size_t)desc_.nz * K_);
-    Jpart_ = arena_.alloc<double>(K_);
+    nl_ = arena_.alloc<cplx>((size_t)B_ * 3 * Ngz_ * K_);
+    nlbar_ = arena_.alloc<cplx>((size_t)B_ * 3 * Ngz_ * K_);
+    itmp_ = arena_.alloc<cplx>((size_t)B_ * desc_.nz * K_);
+    Jpart_ = arena_.alloc<double>((size_t)B_ * K_);
     const int ce = desc_.checkpoint_every;
     const int nck = (desc_.max_steps + ce - 1) / ce;
     ckpt_ = arena_.alloc<cplx>((size_t)nck * st);
     seglen_ = std::min(ce, desc_.max_steps);
-    seg_ = arena_.alloc<cplx>((size_t)2 * seglen_ * 2 * zsize_);
+    seg_ = arena_.alloc<cplx>((size_t)2 * seglen_ * ns * zsize_);
     const size_t fac_lds = factor_lds();
     std::vector<std::pair<const void*, size_t>> lds = {
         {(const void*)kfwd_fn(), kf_lds()}, {(const void*)kadj_fn(), ka_lds()}, {(const void*)rbc_factor, fac_lds}};
@@ -3498,6 +3731,9 @@ class RbcProblem : public ProblemImpl {
   int Kz_ = 1, ncost_ = 2;
   bool cou_ = false, stream_solve_ = false;
   int wave_r1_ = 0;
+  int B_ = 1;                        // instances of a batch
+  std::vector<double> rab_;          // a batch's Rayleigh numbers (empty: a single problem)
+  const double *BLnu_ = nullptr, *BLka_ = nullptr;   // a batch's nu and kappa parts of L
   const double2* frame_ = nullptr;   // plane Couette: unit wave vector of each mode   // grid rows of 64 wave_r1_ points use the one-wave-per-FFT kernels
   std::vector<double> kxs_;
   std::vector<unsigned char> ckeep_;
@@ -3514,7 +3750,8 @@ class RbcProblem : public ProblemImpl {
   cplx* lrhs_ = nullptr;
   bool lfactored_ = false;
   int *err_ = nullptr;
-  cplx *X1_, *Xw_, *Xg_, *acc_, *Ybuf_, *F0_, *zgA_, *zbar_, *nl_, *nlbar_, *itmp_, *ckpt_, *seg_;
+  RkTab tab_;                        // the step's IMEX Runge-Kutta tableau
+  cplx *Xst_, *Xw_, *Xg_, *acc_, *Ybuf_, *Fst_, *zgA_, *zbar_, *nl_, *nlbar_, *itmp_, *ckpt_, *seg_;
   size_t zsize_ = 0;
   int seglen_ = 0;
   hipStream_t aux_ = nullptr, cap_ = nullptr;
@@ -3552,6 +3789,11 @@ class RbcProblem : public ProblemImpl {
 }  // namespace
 
 ProblemImpl* make_rbc(const sps_desc& d, hipStream_t s) { return new RbcProblem(d, s); }
+ProblemImpl* make_rbc_batch(const sps_desc& d, int batch, const double* ra, hipStream_t s) {
+  std::vector<double> r(batch > 0 ? batch : 0, d.param0);
+  if (ra) r.assign(ra, ra + batch);
+  return new RbcProblem(d, s, batch, r.data());
+}
 ProblemImpl* make_couette(const CouetteSpec& c, hipStream_t s) { return new RbcProblem(c, s); }
 
 }  // namespace sps

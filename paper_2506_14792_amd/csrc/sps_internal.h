@@ -204,6 +204,7 @@ class ProblemImpl {
 };
 
 ProblemImpl* make_rbc(const sps_desc& d, hipStream_t s);
+ProblemImpl* make_rbc_batch(const sps_desc& d, int batch, const double* ra, hipStream_t s);
 ProblemImpl* make_ks(const sps_desc& d, hipStream_t s);
 ProblemImpl* make_sh_batch(int batch, const int* n, const double* r, double lx, double dt, int max_steps,
                            hipStream_t s);

@@ -48,6 +48,8 @@ def lib():
     sig = {
         "sps_set_allocator": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
         "sps_build_problem": (ctypes.c_int, [ctypes.POINTER(SpsDesc), _P, ctypes.POINTER(_P)]),
+        "sps_build_rbc_batch": (ctypes.c_int, [ctypes.POINTER(SpsDesc), ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                               _P, ctypes.POINTER(_P)]),
         "sps_state_size": (ctypes.c_longlong, [_P]),
         "sps_factor": (ctypes.c_int, [_P]),
         "sps_step": (ctypes.c_int, [_P, _D, ctypes.c_int]),
@@ -359,6 +361,41 @@ class Problem:
 
     def sync(self):
         _check(lib().sps_sync(self._h))
+
+
+class RbcBatch(Problem):
+    """A batch of 2D problems (nx x nz, Lx, Pr, dt, checkpoints and max_steps shared) with one
+    Rayleigh number per instance; states, grids and J hold the instances in order."""
+
+    def __init__(self, ra, nx, nz, lx, Pr, dt=1e-3, checkpoint_every=1, max_steps=1, scheme=RK222, stream=None):
+        import torch
+        self.batch = len(ra)
+        self.desc = make_desc(RBC2D, nx, nz, lx, float(ra[0]), Pr, 1.5, dt, checkpoint_every, max_steps, scheme)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self._stream = stream
+        arr = (ctypes.c_double * self.batch)(*[float(v) for v in ra])
+        h = _P()
+        _check(lib().sps_build_rbc_batch(ctypes.byref(self.desc), self.batch, arr, ctypes.c_void_p(stream.cuda_stream),
+                                         ctypes.byref(h)))
+        self._h = h
+        self.n = int(lib().sps_state_size(h))
+        self.tape_id = 0
+        self.grid_size = self.batch * nx * nz
+
+    def cost(self, X, J, dJdX):
+        _check(lib().sps_cost(self._h, _ptr(X, self.n), _ptr(J, self.batch), _ptr(dJdX, self.n)))
+
+    def gradient(self, X0, nsteps, XN, dJdX0, J, dJdXN=None):
+        self.tape_id += 1
+        _check(lib().sps_gradient(self._h, _ptr(X0, self.n), nsteps, _ptr(dJdXN, self.n), _ptr(XN, self.n),
+                                  _ptr(dJdX0, self.n), None, _ptr(J, self.batch)))
+
+    def initial_state(self, grid, X):
+        _check(lib().sps_initial_state(self._h, _ptr(grid, self.grid_size), _ptr(X, self.n)))
+
+    def initial_state_adjoint(self, Xbar, grid_bar):
+        _check(lib().sps_initial_state_adjoint(self._h, _ptr(Xbar, self.n), _ptr(grid_bar, self.grid_size)))
 
 
 class ShBatch(Problem):

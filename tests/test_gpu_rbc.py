@@ -290,6 +290,7 @@ def test_caller_allocator():
     X0 = to_dev(P.initial_state(wl.rbc_b0(seed=15, Nx=cfg[0], Nz=cfg[1], amp=0.1)))
     _, G = build(cfg, ce=2, max_steps=nsteps)
     g_ref = torch.zeros(G.n, dtype=torch.float64, device="cuda")
+    g = torch.zeros_like(g_ref)
     G.gradient(X0, nsteps, None, g_ref, None)
     G.sync()
     torch.cuda.synchronize()
@@ -300,7 +301,6 @@ def test_caller_allocator():
     finally:
         sps.use_torch_allocator(False)
     grown = torch.cuda.memory_allocated() - before
-    g = torch.zeros_like(g_ref)
     H.gradient(X0, nsteps, None, g, None)
     H.sync()
     assert torch.equal(g, g_ref)

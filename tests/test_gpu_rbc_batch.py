@@ -1,0 +1,110 @@
+"""A batch of 2D problems with one Rayleigh number per instance (sps_build_rbc_batch: every
+instance its own factors, every stage launch over all instances) against the FP64 oracle,
+instance by instance, field by field (tests/parity.py): the forward run, J and the gradient at
+24x16 (three instances, ragged checkpoint segments) and at the full 256x64 size (two
+instances); an instance's results do not depend on the other instances of its batch; calls
+outside the batch's scope are refused."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import imex
+from oracle.rbc import RBC
+import workloads as wl
+from parity import check_fields
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2506_14792_amd as sps  # noqa: E402
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def cat_states(Xs):
+    return torch.from_numpy(np.concatenate([np.ascontiguousarray(X).view(np.float64).ravel() for X in Xs])).cuda()
+
+
+def split(t, B, shape):
+    return t.cpu().numpy().view(np.complex128).reshape((B,) + shape)
+
+
+@pytest.mark.parametrize("nx,nz,lx,Pr,dt,ras,nsteps,ce", [
+    (24, 16, 3.0, 0.7, 2e-3, (1e5, 3e4, 2e5), 5, 2),
+    (256, 64, 4.0, 1.0, 1e-3, (1e6, 5e5), 3, 2),
+], ids=["24x16x3", "256x64x2"])
+def test_batch_against_oracle(nx, nz, lx, Pr, dt, ras, nsteps, ce):
+    note(f"batch {nx}x{nz} Ra {ras} x {nsteps} steps ce={ce}")
+    B = len(ras)
+    G = sps.RbcBatch(list(ras), nx, nz, lx, Pr, dt=dt, checkpoint_every=ce, max_steps=nsteps)
+    Ps = [RBC(Nx=nx, Nz=nz, Lx=lx, Ra=r, Pr=Pr) for r in ras]
+    grids = [wl.rbc_b0(seed=30 + b, Nx=nx, Nz=nz, amp=0.1) for b in range(B)]
+    X0 = torch.zeros(G.n, dtype=torch.float64, device="cuda")
+    G.initial_state(torch.from_numpy(np.concatenate([g.ravel() for g in grids])).cuda(), X0)
+    XN = torch.zeros_like(X0)
+    g = torch.zeros_like(X0)
+    J = torch.zeros(B, dtype=torch.float64, device="cuda")
+    G.gradient(X0, nsteps, XN, g, J)
+    gb = torch.zeros(B * nx * nz, dtype=torch.float64, device="cuda")
+    G.initial_state_adjoint(g, gb)
+    G.sync()
+    shape = (nx // 2, 4 * nz + 7)
+    X0h, XNh, gh = split(X0, B, shape), split(XN, B, shape), split(g, B, shape)
+    gbh = gb.cpu().numpy().reshape(B, nx, nz)
+    for b, P in enumerate(Ps):
+        X0r = P.initial_state(grids[b])
+        base = P.lbvp_solve(np.zeros(shape, complex))
+        check_fields(X0h[b], X0r, nz, TOL, base=base, what=f"instance {b} X0")
+        XNr, hist = imex.rk_forward(P, X0r, dt, nsteps)
+        Jr = P.kinetic_energy(XNr)
+        gr = imex.rk_adjoint(P, P.kinetic_energy_grad(XNr), hist, dt)
+        check_fields(XNh[b], XNr, nz, TOL, base=base, what=f"instance {b} X_N")
+        check_fields(gh[b], gr, nz, TOL, what=f"instance {b} dJ/dX0")
+        eJ = abs(J[b].item() - Jr) / abs(Jr)
+        egb = np.max(np.abs(gbh[b] - P.initial_state_adjoint(gr))) / np.max(np.abs(P.initial_state_adjoint(gr)))
+        note(f"  instance {b} (Ra {ras[b]:.0e}): J rel {eJ:.1e}, grid gradient rel {egb:.1e}")
+        assert eJ <= TOL and egb <= TOL
+
+
+def test_instances_are_independent_and_scope():
+    """Instance 1 of a batch of three gives the same bits as that instance in a batch of one; the
+    step / adjoint_step pair equals the gradient; unsupported calls are refused."""
+    note("batch independence")
+    ras = (1e5, 3e4, 2e5)
+    nx, nz, lx, Pr, dt, n = 24, 16, 3.0, 0.7, 2e-3, 5
+    G3 = sps.RbcBatch(list(ras), nx, nz, lx, Pr, dt=dt, checkpoint_every=2, max_steps=n)
+    G1 = sps.RbcBatch([ras[1]], nx, nz, lx, Pr, dt=dt, checkpoint_every=2, max_steps=n)
+    Ps = [RBC(Nx=nx, Nz=nz, Lx=lx, Ra=r, Pr=Pr) for r in ras]
+    Xs = [P.initial_state(wl.rbc_b0(seed=40 + b, Nx=nx, Nz=nz, amp=0.1)) for b, P in enumerate(Ps)]
+    X3, X1 = cat_states(Xs), cat_states([Xs[1]])
+    g3, g1 = torch.zeros_like(X3), torch.zeros_like(X1)
+    G3.gradient(X3, n, None, g3, None)
+    G1.gradient(X1, n, None, g1, None)
+    G3.sync()
+    G1.sync()
+    m = G1.n
+    assert torch.equal(g3[m:2 * m], g1)
+    # step + cost + adjoint_step
+    X = X3.clone()
+    G3.step(X, n)
+    seed = torch.zeros_like(X)
+    G3.cost(X, None, seed)
+    G3.adjoint_step(seed, n)
+    G3.sync()
+    assert torch.equal(seed, g3)
+    out = torch.zeros_like(X3)
+    with pytest.raises(sps.SpsError) as e:
+        G3.eval_F(X3, out)
+    assert e.value.code == -7
+    with pytest.raises(sps.SpsError) as e:
+        G3.set_checkpointing(1, 3)
+    assert e.value.code == -7
