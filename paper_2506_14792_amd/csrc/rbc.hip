@@ -46,6 +46,7 @@
 #include "cou.h"
 #include "sps_device.h"
 #include "sps_internal.h"
+#include "ultra_ops.h"
 #include "wave_fft.h"
 
 // Scratch of the allocation-free explicit-term evaluation (sps_eval_F_noalloc): the x-spectral
@@ -2161,51 +2162,6 @@ __global__ void sum_parts(const double* part, int n, double* out) {
     for (int i = 0; i < n; ++i) s += p[i];
     out[blockIdx.x] = s;
   }
-}
-
-// ---------------------------------------------------------------------------- host: operators
-struct Cmat {
-  int n;
-  std::vector<double2> a;
-  explicit Cmat(int n_) : n(n_), a((size_t)n_ * n_, make_double2(0.0, 0.0)) {}
-  double2& at(int i, int j) { return a[(size_t)i * n + j]; }
-  void add(int i, int j, double re, double im = 0.0) {
-    at(i, j).x += re;
-    at(i, j).y += im;
-  }
-};
-
-// Dense N x N matrices of the ultraspherical operators (column n = image of basis n).
-static std::vector<double> op_S0(int N) {
-  std::vector<double> S((size_t)N * N, 0.0);
-  for (int n = 0; n < N; ++n) {
-    S[(size_t)n * N + n] = (n == 0) ? 1.0 : 0.5;
-    if (n >= 2) S[(size_t)(n - 2) * N + n] = -0.5;
-  }
-  return S;
-}
-static std::vector<double> op_S1(int N) {
-  std::vector<double> S((size_t)N * N, 0.0);
-  for (int n = 0; n < N; ++n) {
-    S[(size_t)n * N + n] = 1.0 / (n + 1);
-    if (n >= 2) S[(size_t)(n - 2) * N + n] = -1.0 / (n + 1);
-  }
-  return S;
-}
-static std::vector<double> op_D(int N, double v, bool scaled_by_index) {  // D[n-1][n]
-  std::vector<double> D((size_t)N * N, 0.0);
-  for (int n = 1; n < N; ++n) D[(size_t)(n - 1) * N + n] = scaled_by_index ? v * n : v;
-  return D;
-}
-static std::vector<double> matmul(const std::vector<double>& A, const std::vector<double>& B, int N) {
-  std::vector<double> C((size_t)N * N, 0.0);
-  for (int i = 0; i < N; ++i)
-    for (int k = 0; k < N; ++k) {
-      const double a = A[(size_t)i * N + k];
-      if (a == 0.0) continue;
-      for (int j = 0; j < N; ++j) C[(size_t)i * N + j] += a * B[(size_t)k * N + j];
-    }
-  return C;
 }
 
 // ---------------------------------------------------------------------------- host: banded systems
