@@ -722,6 +722,66 @@ def rbc_batch_timing(reps=2):
             "gradients_per_s_per_instance": B / sec, "per_kernel": per, "finite": finite}
 
 
+def poiseuille_timing():
+    """Plane Poiseuille stability (the neutral-curve example), nz = 128 (S = 389): (a) the onset at
+    alpha = 1.02056 by Newton in Re from Re = 5000 in one launch (factorization, 20 inverse
+    iterations for each of the right and left eigenvectors and the sensitivities per Newton step),
+    against the oracle's dense eigensolves with left vectors for the same Newton steps; (b) a batch
+    of 128 neutral points in one launch: Newton in Re from Re = 5000 at 128 wavenumbers from 0.9
+    to 1.09 (both branches near the onset); (c) 20 continuation steps along the curve from the
+    onset, one launch each."""
+    import torch
+    import paper_2506_14792_amd as sps
+    from oracle.poiseuille import Poiseuille
+    nz = 128
+    z = lambda n: torch.zeros(n, dtype=torch.float64, device="cuda")
+    G = sps.PoiseuilleStability(nz, 128)
+    lam, dl, info = z(2), z(4), z(3)
+    G.solve([(1.02056, 5000.0, -0.27j)], lam, dl, info, iters=20, mode=G.NEWTON_RE, tol=1e-12, maxit=12)
+    G.sync()
+    t0 = time.perf_counter()
+    reps = 5
+    for _ in range(reps):
+        G.solve([(1.02056, 5000.0, -0.27j)], lam, dl, info, iters=20, mode=G.NEWTON_RE, tol=1e-12, maxit=12)
+    G.sync()
+    onset_s = (time.perf_counter() - t0) / reps
+    a0, Re0, solves0 = info.cpu().numpy()
+    P = Poiseuille(nz)
+    t0 = time.perf_counter()
+    Re_o, _, solves_o, _ = P.neutral_Re(1.02056, 5000.0, -0.27j, tol=1e-12)
+    onset_cpu = time.perf_counter() - t0
+    alphas = np.linspace(0.9, 1.09, 128)
+    pars = [(al, 5000.0, -0.264j * al) for al in alphas]
+    lb, db, ib = z(2 * 128), z(4 * 128), z(3 * 128)
+    G.solve(pars, lb, db, ib, iters=20, mode=G.NEWTON_RE, tol=1e-12, maxit=15)
+    G.sync()
+    t0 = time.perf_counter()
+    G.solve(pars, lb, db, ib, iters=20, mode=G.NEWTON_RE, tol=1e-12, maxit=15)
+    G.sync()
+    batch_s = time.perf_counter() - t0
+    grow = np.abs(lb.cpu().numpy()[0::2])
+    inf = ib.cpu().numpy().reshape(128, 3)
+    a, Re, sg = float(a0), float(Re0), complex(*lam.cpu().numpy())
+    t0 = time.perf_counter()
+    steps = []
+    for _ in range(20):
+        G.solve([(a, Re, sg, 0.1)], lam, dl, info, iters=20, mode=G.CONTINUE, tol=1e-12, maxit=12)
+        G.sync()
+        a, Re, nsol = info.cpu().numpy()
+        sg = complex(*lam.cpu().numpy())
+        steps.append(int(nsol))
+    cont_s = time.perf_counter() - t0
+    G.close()
+    return {"workload": "plane Poiseuille stability, nz=128 (389 unknowns, complex band kl=11, ku=19)",
+            "onset": {"Re_c": float(Re0), "alpha_c": 1.02056, "eigenvalue_solves": int(solves0), "gpu_s": onset_s,
+                      "oracle_Re_c": Re_o, "oracle_solves": solves_o, "oracle_cpu_s": onset_cpu},
+            "batch_neutral_points": {"points": 128, "gpu_s": batch_s, "max_abs_growth": float(grow.max()),
+                                     "mean_solves": float(inf[:, 2].mean()),
+                                     "Re_range": [float(inf[:, 1].min()), float(inf[:, 1].max())]},
+            "continuation": {"steps": 20, "ds": 0.1, "gpu_s": cont_s, "mean_solves": float(np.mean(steps)),
+                             "end": [float(a), float(Re)]}}
+
+
 def kernel_bytes(nx, nz):
     """Algorithmic HBM bytes per launch of each stage kernel of the 2D problem (each operand
     streamed once; factors in banded form): the per-wavenumber forward kernel (average of the
@@ -750,7 +810,7 @@ def main():
     ap.add_argument("--skip-extra", action="store_true",
                     help="only the headline configuration (for counter and trace runs)")
     ap.add_argument("--only", choices=["ks", "sh", "closure", "couette", "lbvp", "ckpt", "stability", "dtchange",
-                                       "rbcbatch"],
+                                       "rbcbatch", "poiseuille"],
                     default=None,
                     help="run one secondary configuration alone and print its JSON (for profiling)")
     args = ap.parse_args()
@@ -766,7 +826,7 @@ def main():
         torch.cuda.set_device(0)
         fn = {"ks": ks_timing, "sh": sh_timing, "closure": kolmo_timing, "couette": couette_timing,
               "lbvp": lbvp_timing, "ckpt": ckpt_timing, "stability": stability_timing,
-              "dtchange": dtchange_timing, "rbcbatch": rbc_batch_timing}[args.only]
+              "dtchange": dtchange_timing, "rbcbatch": rbc_batch_timing, "poiseuille": poiseuille_timing}[args.only]
         print(json.dumps({args.only: fn()}))
         return
 
@@ -854,13 +914,14 @@ def main():
     G.sync()
     graph_sec = (t7 - t6) / args.steps
     traffic = measured_traffic()
-    ks = sh = kol = cou = lbvp = ckpt = stab = dtc = rbatch = None
+    ks = sh = kol = cou = lbvp = ckpt = stab = dtc = rbatch = pois = None
     if not args.skip_extra:
         rbatch = rbc_batch_timing()
         lbvp = lbvp_timing()
         ckpt = ckpt_timing()
         dtc = dtchange_timing()
         stab = stability_timing()
+        pois = poiseuille_timing()
         ks = ks_timing()
         sh = sh_timing()
         kol = kolmo_timing()
@@ -903,6 +964,7 @@ def main():
         "checkpointing_config": ckpt,
         "step_change_config": dtc,
         "stability_config": stab,
+        "poiseuille_config": pois,
         "J": J.item(),
     }
     print(json.dumps(out))

@@ -333,6 +333,38 @@ int sps_stability_vector_sens(sps_problem *P, double sigma, int iters, const dou
 int sps_stability_arnoldi(sps_problem *P, double sigma, int m, int nev, const double *v0, double *lam, double *X,
                           double *res, double *H);
 
+/* Linear stability of plane Poiseuille flow, the paper's neutral-curve example (Results,
+ * "Parametric sensitivity and numerical continuation"; Supplementary, "Eigenvalue problems"):
+ * flow between walls y = 0 and y = 2 with base flow U = y (2 - y), two-dimensional perturbations
+ * (u, v, p) ~ exp(i alpha x + lambda t), (lambda M + L(alpha, Re)) X = 0 with the growth rate
+ * Re(lambda), discretized as the 2D problem (Chebyshev-T unknowns, C2 momentum and C1 continuity
+ * rows, lifted taus; state slots u[0:nz], v[nz:2nz], p[2nz:3nz], tau_u1, tau_v1, tau_u2, tau_v2,
+ * tau_p, S = 3 nz + 5).  The handle holds the operator parts and factor storage for up to
+ * max_systems systems solved at once; 8 <= nz <= 256.  Only sps_poiseuille_solve, sps_sync,
+ * sps_state_size and sps_destroy apply to it. */
+int sps_build_poiseuille(int nz, int max_systems, void *hip_stream, sps_problem **out);
+/* nsys independent systems at once (one thread block each).  params: HOST array [nsys][5] of
+ * (alpha, Re, sigma_re, sigma_im, ds), copied (ds: the continuation step of mode 3).  For each system: the complex banded LU of
+ * sigma M + L with partial pivoting, `iters` inverse iterations for the eigenvalue nearest the
+ * shift sigma and its right eigenvector, and (through the same factors, the conjugate-transposed
+ * solves) the left eigenvector Y, ((conj(lambda) M^H + L^H) Y = 0), then the sensitivities of
+ * equ:eigenvalue_sens, d lambda/dp = -<Y, dL/dp X> / <Y, M X>, for p = Re and p = alpha.
+ * mode 0: that eigenpair; mode 1: Newton's method on the growth rate in Re at fixed alpha
+ * (Re <- Re - Re(lambda) / Re(d lambda/dRe), the next shift at the new eigenvalue) until
+ * |Re(lambda)| <= tol or maxit eigenvalue solves; mode 2: the same in alpha at fixed Re; mode 3: one
+ * step of the continuation along the neutral curve from a point on it (Results, "Parametric
+ * sensitivity and numerical continuation"): the point moves by ds along the tangent of the curve
+ * in (alpha, ln Re) (the gradient (d/dalpha, Re d/dRe) of the growth rate turned by a right angle,
+ * so that the unstable side stays on the same hand), then minimum-norm Newton steps in
+ * (alpha, ln Re) along the gradient bring it back onto the curve (turning points included).  Device
+ * outputs: lam[nsys] complex; dlam[nsys][2] complex (d/dRe, d/dalpha); info[nsys][3] doubles
+ * (alpha, Re at the end, eigenvalue solves used); X, Y (nullable) [nsys][S] complex in the state
+ * layout, unit Euclidean norm.  A Newton run that ends above tol sets a flag that the next
+ * sps_sync() reports as SPS_E_NOCONV, a zero pivot SPS_E_SINGULAR.  Returns after the launch has
+ * read params (the call synchronizes the problem's stream). */
+int sps_poiseuille_solve(sps_problem *P, int nsys, const double *params, int iters, int mode, double tol,
+                         int maxit, double *lam, double *dlam, double *info, double *X, double *Y);
+
 /* A new constant step dt > 0 for the following runs (a step-size change between segments of a
  * run, as an adaptive step controller makes it; equ:imex: the implicit matrices depend on dt).
  * The 2D problem and plane Couette refactor every wavenumber's M + dt gamma L at once (one

@@ -27,6 +27,19 @@ extern "C" {
 int sps_rbc_host_bands(const sps_desc *desc, int *kl, int *ku, double *BM, double *BL, int *rowmap,
                        int *colmap, signed char *rowph, signed char *colph, double *rho);
 
+/* The complex banded matrix the plane Poiseuille stability solver factors (sps_poiseuille_solve)
+ * for streamwise wavenumber alpha, Reynolds number re and shift sigma = sig_re + i sig_im:
+ *     B = P_r (sigma M + L) R P_c,
+ * the operators of the Orr-Sommerfeld problem in primitive variables (paper, Results:
+ * Parametric sensitivity and numerical continuation; the discretization is that of the 2D
+ * problem), rows permuted to the interleaved order rowmap (band row i <- equation slot), columns
+ * to colmap (band column j -> unknown slot), R recombining X[s] = y[s] + rho[s] * y[s + 2].
+ * Fills S = 3 nz + 5, kl, ku and, when non-NULL, band[S][kl + ku + 1] complex (entry (i, j) at
+ * [i][j - i + kl], (re, im) pairs), rowmap[S], colmap[S], rho[S].  Call first with NULL arrays to
+ * learn S, kl and ku.  8 <= nz <= 256.  Returns SPS_OK or an error. */
+int sps_poiseuille_host_band(int nz, double alpha, double re, double sig_re, double sig_im, int *S, int *kl,
+                             int *ku, double *band, int *rowmap, int *colmap, double *rho);
+
 #ifdef __cplusplus
 }
 #endif

@@ -5,7 +5,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["api.cpp", "ckpt.cpp", "rbc.hip", "ks.hip", "sh.hip", "cnn.hip", "kol.hip", "cou.hip"]
+SOURCES = ["api.cpp", "ckpt.cpp", "rbc.hip", "ks.hip", "sh.hip", "cnn.hip", "kol.hip", "cou.hip", "pois.hip"]
 LIB = os.path.join(HERE, "libsps.so")
 
 FLAGS = [

@@ -9,6 +9,7 @@
 #include "cnn.h"
 #include "fft_plan.h"
 #include "sps_internal.h"
+#include "../../include/sps_host.h"
 
 struct sps_problem {
   sps::ProblemImpl* impl;
@@ -314,6 +315,38 @@ int sps_build_couette(int nx, int ny, int nz, double lx, double lz, double re, d
     return fail(e.code, e.what());
   } catch (const std::exception& e) {
     return fail(SPS_E_HIP, e.what());
+  }
+}
+
+int sps_build_poiseuille(int nz, int max_systems, void* hip_stream, sps_problem** out) {
+  if (!out) return fail(SPS_E_ARG, "null argument");
+  *out = nullptr;
+  try {
+    sps::ProblemImpl* impl = sps::make_poiseuille(nz, max_systems, reinterpret_cast<hipStream_t>(hip_stream));
+    *out = new sps_problem{impl};
+    return SPS_OK;
+  } catch (const sps::Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::exception& e) {
+    return fail(SPS_E_HIP, e.what());
+  }
+}
+
+int sps_poiseuille_solve(sps_problem* P, int nsys, const double* params, int iters, int mode, double tol, int maxit,
+                         double* lam, double* dlam, double* info, double* X, double* Y) {
+  return guard(P, [&](sps::ProblemImpl& p) {
+    sps::poiseuille_run(&p, nsys, params, iters, mode, tol, maxit, lam, dlam, info, X, Y);
+  });
+}
+
+int sps_poiseuille_host_band(int nz, double alpha, double re, double sig_re, double sig_im, int* S, int* kl, int* ku,
+                             double* band, int* rowmap, int* colmap, double* rho) {
+  if (!S || !kl || !ku) return fail(SPS_E_ARG, "null argument");
+  try {
+    sps::poiseuille_host_band(nz, alpha, re, sig_re, sig_im, S, kl, ku, band, rowmap, colmap, rho);
+    return SPS_OK;
+  } catch (const sps::Error& e) {
+    return fail(e.code, e.what());
   }
 }
 

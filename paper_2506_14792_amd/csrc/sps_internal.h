@@ -224,6 +224,12 @@ void kolmo_rollout(ProblemImpl* p, const double* X0, const double* targets, int 
 void kolmo_param_vjp(ProblemImpl* p, const double* X, const double* Fbar, double* th_bar);
 void kolmo_adam(ProblemImpl* p, double* theta, const double* grad, double* m1, double* m2, double lr, int t);
 
+ProblemImpl* make_poiseuille(int nz, int max_systems, hipStream_t s);
+void poiseuille_run(ProblemImpl* p, int nsys, const double* params, int iters, int mode, double tol, int maxit,
+                    double* lam, double* dlam, double* info, double* X, double* Y);
+void poiseuille_host_band(int nz, double alpha, double re, double sig_re, double sig_im, int* S, int* kl, int* ku,
+                          double* band, int* rowmap, int* colmap, double* rho);
+
 // Host helpers shared by problem builders.
 std::vector<double2> twiddles(int n);            // exp(-2 pi i t / n), t < n
 

@@ -107,6 +107,13 @@ def lib():
         "sps_destroy": (None, [_P]),
         "sps_rbc_host_bands": (ctypes.c_int, [ctypes.POINTER(SpsDesc), ctypes.POINTER(ctypes.c_int),
                                               ctypes.POINTER(ctypes.c_int), _P, _P, _P, _P, _P, _P, _P]),
+        "sps_build_poiseuille": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _P, ctypes.POINTER(_P)]),
+        "sps_poiseuille_solve": (ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                                ctypes.c_int, _D, _D, _D, _D, _D]),
+        "sps_poiseuille_host_band": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                                    ctypes.c_double, ctypes.POINTER(ctypes.c_int),
+                                                    ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                                    _P, _P, _P, _P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -558,6 +565,55 @@ class ClosureNet:
     def vjp(self, x, ybar, xbar, theta_bar=None):
         _check(lib().sps_cnn_vjp(self._h, _ptr(x, self.npix), _ptr(ybar, self.npix), _ptr(xbar, self.npix),
                                  _ptr(theta_bar, self.nparam)))
+
+
+class PoiseuilleStability(Problem):
+    """Linear stability of plane Poiseuille flow (the neutral-curve example): nsys systems of
+    (alpha, Re, shift) solved at once, one thread block each, by sps_poiseuille_solve.  States are
+    S = 3 nz + 5 complex slots (u, v, p Chebyshev coefficients and five taus)."""
+
+    EIGENPAIR, NEWTON_RE, NEWTON_ALPHA, CONTINUE = 0, 1, 2, 3
+
+    def __init__(self, nz, max_systems=1, stream=None):
+        import torch
+        self.nz = nz
+        self.max_systems = max_systems
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self._stream = stream
+        h = _P()
+        _check(lib().sps_build_poiseuille(int(nz), int(max_systems), ctypes.c_void_p(stream.cuda_stream),
+                                          ctypes.byref(h)))
+        self._h = h
+        self.S = int(lib().sps_state_size(h)) // 2
+        self.n = 2 * self.S
+
+    def solve(self, params, lam, dlam, info, iters=20, mode=0, tol=1e-12, maxit=1, X=None, Y=None):
+        """params: sequence of (alpha, Re, sigma) or (alpha, Re, sigma, ds) with sigma complex;
+        lam (2 nsys doubles), dlam (4 nsys), info (3 nsys), X, Y (2 S nsys, optional): device
+        float64 tensors."""
+        ns = len(params)
+        rows = [tuple(p) + (0.0,) * (4 - len(p)) for p in params]
+        arr = (ctypes.c_double * (5 * ns))(*[float(v) for a, r, sg, ds in rows
+                                              for v in (a, r, complex(sg).real, complex(sg).imag, ds)])
+        _check(lib().sps_poiseuille_solve(self._h, ns, ctypes.cast(arr, ctypes.c_void_p), int(iters), int(mode),
+                                          float(tol), int(maxit), _ptr(lam, 2 * ns), _ptr(dlam, 4 * ns),
+                                          _ptr(info, 3 * ns), _ptr(X, self.n * ns), _ptr(Y, self.n * ns)))
+
+
+def poiseuille_host_band(nz, alpha, Re, sigma):
+    """Host-assembled complex band of sigma M + L of the Poiseuille stability problem (no GPU)."""
+    S, kl, ku = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    sg = complex(sigma)
+    _check(lib().sps_poiseuille_host_band(int(nz), float(alpha), float(Re), sg.real, sg.imag, ctypes.byref(S),
+                                          ctypes.byref(kl), ctypes.byref(ku), None, None, None, None))
+    n, bw = S.value, kl.value + ku.value + 1
+    band = np.zeros((n, bw), complex)
+    rowmap = np.zeros(n, np.int32); colmap = np.zeros(n, np.int32); rho = np.zeros(n)
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    _check(lib().sps_poiseuille_host_band(int(nz), float(alpha), float(Re), sg.real, sg.imag, ctypes.byref(S),
+                                          ctypes.byref(kl), ctypes.byref(ku), p(band), p(rowmap), p(colmap), p(rho)))
+    return dict(S=n, kl=kl.value, ku=ku.value, band=band, rowmap=rowmap, colmap=colmap, rho=rho)
 
 
 def rbc_host_bands(nx, nz, lx, Ra, Pr, dt=1e-3):
