@@ -385,10 +385,16 @@ int sps_set_dt(sps_problem *P, double dt);
  * q = min(n, k): a_j the derivative at t_n of the Lagrange basis polynomial of node t_{n-j}
  * (backward difference of M dX/dt), c_i the value at t_n of the basis polynomial of t_{n-i}
  * on t_{n-1} .. t_{n-q} (extrapolation of F); equal steps give the constant-step rows.
- * With the RK schemes step i + 1 uses dts[i] in its stage coefficients (the implicit matrices
- * are diagonal, so nothing is refactored).
+ * With the RK schemes step i + 1 uses dts[i] in its stage coefficients; KS's implicit matrices
+ * are diagonal, so nothing is refactored.  The 2D problem, its batches and plane Couette (RK222 or
+ * RK443) factor M + dts[i] H_ii L once per distinct step (at most 16 in one call; the factor sets
+ * are kept for later calls, 64 distinct steps over a problem's life) and step i + 1 of a run, its
+ * recomputation and its reverse step use that step's set and stage coefficients, so one
+ * recorded run and its gradient span the step changes (any checkpoint schedule, graph mode
+ * included); runs longer than n steps are refused (SPS_E_ARG).
  * dts = NULL or n = 0 returns to the constant step of the descriptor (sps_solve always uses
- * it).  Drops the recorded forward run.  The KS problem; SPS_E_UNSUPPORTED otherwise. */
+ * it).  Drops the recorded forward run and captured graphs.  SPS_E_UNSUPPORTED for the batched
+ * Swift-Hohenberg and Kolmogorov problems. */
 int sps_set_timesteps(sps_problem *P, const double *dts, int n);
 
 /* Checkpointing of the Runge-Kutta sweeps (Supplementary, "Initial value problems": the reverse

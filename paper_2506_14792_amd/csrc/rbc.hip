@@ -2441,6 +2441,7 @@ class RbcProblem : public ProblemImpl {
 
   void init() {
     dv_.B = B_;
+    cur_dt_ = dt_;
     stream_solve_ = (long long)K_ * B_ > 1024;
     build_tables();
     build_bands();
@@ -2472,10 +2473,82 @@ class RbcProblem : public ProblemImpl {
   // M + dt H_ii L (the implicit diagonal is one value for every stage)
   void factor() override {
     if (factored_) return;
-    hipLaunchKernelGGL(rbc_factor, dim3(K_, B_), dim3(NT), factor_lds(), stream, dv_, BM_, BL_, 1.0,
-                       dt_ * tab_.H[1][1], ops_, BLnu_, BLka_);
-    SPS_CHECK_LAUNCH();
+    factor_into(dt_, ops_);
     factored_ = true;
+  }
+  void factor_into(double dt, double* ops) {
+    RbcDev d = dv_;
+    d.ops = ops;
+    hipLaunchKernelGGL(rbc_factor, dim3(K_, B_), dim3(NT), factor_lds(), stream, d, BM_, BL_, 1.0, dt * tab_.H[1][1],
+                       ops, BLnu_, BLka_);
+    SPS_CHECK_LAUNCH();
+  }
+
+  // Variable steps (equ:imex with step-dependent coefficients): step i of a run takes vdt_[i]
+  // in its stage coefficients and its own factors M + vdt_[i] H_ii L, one factor set per
+  // distinct step (kept for later calls); the reverse sweep uses the same step's set.
+  static constexpr int kMaxStepSets = 16;
+  void set_timesteps(const double* dts, int n) override {
+    drop_graphs();
+    tape_steps_ = -1;
+    if (!dts || n == 0) {
+      vdt_.clear();
+      vset_.clear();
+      return;
+    }
+    SPS_REQUIRE(n >= 1 && n <= desc_.max_steps, "n must be in [1, max_steps]");
+    std::vector<double> v(n);
+    std::vector<int> set(n);
+    std::vector<double> distinct;
+    for (int i = 0; i < n; ++i) {
+      SPS_REQUIRE(std::isfinite(dts[i]) && dts[i] > 0.0, "steps must be positive");
+      v[i] = cou_ ? 0.5 * dts[i] : dts[i];
+      auto it = std::find(distinct.begin(), distinct.end(), v[i]);
+      if (it == distinct.end()) {
+        SPS_REQUIRE((int)distinct.size() < kMaxStepSets, "at most 16 distinct steps");
+        distinct.push_back(v[i]);
+        it = distinct.end() - 1;
+      }
+      set[i] = (int)(it - distinct.begin());
+    }
+    std::vector<double*> ops(distinct.size());
+    for (size_t q = 0; q < distinct.size(); ++q) {
+      auto c = opcache_.find(distinct[q]);
+      if (c == opcache_.end()) {
+        SPS_REQUIRE(opcache_.size() < 4 * kMaxStepSets, "too many distinct steps over the problem's lifetime");
+        double* o = arena_.alloc<double>((size_t)B_ * K_ * dv_.opsize);
+        factor_into(distinct[q], o);
+        c = opcache_.emplace(distinct[q], o).first;
+      }
+      ops[q] = c->second;
+    }
+    vdt_ = v;
+    vset_ = set;
+    vops_ = ops;
+  }
+  // the step and factors of step n of the run (n < 0: the constant step) for the launches
+  // enqueued next
+  void step_setup(int n) {
+    if (n < 0 || vdt_.empty()) {
+      cur_dt_ = dt_;
+      dv_.ops = ops_;
+      return;
+    }
+    const int g = step_base_ + n;
+    cur_dt_ = vdt_[g];
+    dv_.ops = vops_[vset_[g]];
+  }
+  // every sweep leaves the constant step's settings behind, also when it throws
+  struct StepScope {
+    RbcProblem* p;
+    ~StepScope() {
+      p->step_base_ = 0;
+      p->step_setup(-1);
+    }
+  };
+  void check_run_length(int nsteps) const {
+    if (!vdt_.empty() && nsteps > (int)vdt_.size())
+      throw Error(SPS_E_ARG, "nsteps exceeds the number of variable steps set");
   }
 
   // A new step for the following runs: the matrices M + dt H_ii L of every wavenumber are
@@ -2486,6 +2559,7 @@ class RbcProblem : public ProblemImpl {
     drop_graphs();
     desc_.dt = dt;
     dt_ = cou_ ? 0.5 * dt : dt;
+    cur_dt_ = dt_;
     factored_ = false;
     tape_steps_ = -1;
     factor();
@@ -2494,7 +2568,9 @@ class RbcProblem : public ProblemImpl {
   void step(double* X, int nsteps) override {
     SPS_REQUIRE(X != nullptr, "X is null");
     SPS_REQUIRE(nsteps >= 1 && nsteps <= desc_.max_steps, "nsteps out of range");
+    check_run_length(nsteps);
     factor();
+    StepScope scope{this};
     forward(reinterpret_cast<cplx*>(X), nsteps);
   }
 
@@ -2513,6 +2589,7 @@ class RbcProblem : public ProblemImpl {
   void adjoint_step(double* Xbar, int nsteps) override {
     SPS_REQUIRE(Xbar != nullptr, "Xbar is null");
     if (tape_steps_ != nsteps) throw Error(SPS_E_STATE, "adjoint_step: nsteps does not match the recorded forward run");
+    StepScope scope{this};
     reverse(reinterpret_cast<cplx*>(Xbar), nsteps);
   }
 
@@ -2536,6 +2613,8 @@ class RbcProblem : public ProblemImpl {
                 double* J) override {
     SPS_REQUIRE(X0 && dJdX0, "null argument");
     SPS_REQUIRE(nsteps >= 1 && nsteps <= desc_.max_steps, "nsteps out of range");
+    check_run_length(nsteps);
+    StepScope scope{this};
     if (dJdtheta) {
       no_batch("the parameter gradient");
       if (cou_) throw Error(SPS_E_UNSUPPORTED, "parameter gradients are built for the 2D problem");
@@ -3001,7 +3080,7 @@ class RbcProblem : public ProblemImpl {
     a.nl = nl_;
     a.sstr = st();
     a.fstr = (size_t)B_ * K_ * 3 * N_;
-    a.dt = dt_;
+    a.dt = cur_dt_;
     a.nst = tab_.s;
     a.mode = mode;
     return a;
@@ -3064,7 +3143,7 @@ class RbcProblem : public ProblemImpl {
     a.Ybuf = Ybuf_;
     a.nlbar = nlbar_;
     a.sstr = st();
-    a.dt = dt_;
+    a.dt = cur_dt_;
     a.stage = m;
     a.nst = tab_.s;
     if (m >= 1) {
@@ -3166,6 +3245,7 @@ class RbcProblem : public ProblemImpl {
     launch_kf(KF_ZGRID, X, nullptr, zpos(0, 0));
     for (int n = 0; n < nsteps; ++n) {
       if (n % ce == 0) SPS_HIP(hipMemcpyAsync(ckpt(n / ce), X, sizeof(cplx) * st(), hipMemcpyDeviceToDevice, stream));
+      step_setup(n);
       rk_step(stream, X, [&](int q) { return zpos(n, q); }, (n + 1 < nsteps) ? zpos(n + 1, 0) : nullptr,
               [&](int q) { return spos(n, q); });
     }
@@ -3178,9 +3258,11 @@ class RbcProblem : public ProblemImpl {
     const int b = seg & 1;
     SPS_HIP(hipMemcpyAsync(Xw_, ckpt(seg), sizeof(cplx) * st(), hipMemcpyDeviceToDevice, s));
     launch_kf_on(s, KF_ZGRID, Xw_, nullptr, slot(b, 0, 0));
-    for (int j = 0; j < len; ++j)
+    for (int j = 0; j < len; ++j) {
+      step_setup(seg * desc_.checkpoint_every + j);
       rk_step(s, Xw_, [&](int q) { return slot(b, j, q); }, (j + 1 < len) ? slot(b, j + 1, 0) : nullptr,
               [&](int q) { return param_on_ ? sslot(b, j, q) : nullptr; });
+    }
   }
 
   // Reverse sweep.  The recompute of segment seg-1 (auxiliary stream, scratch Xst_, Xw_, nl_, Fst_,
@@ -3220,8 +3302,10 @@ class RbcProblem : public ProblemImpl {
         recompute(seg - 1, seglen(seg - 1), aux_);
         SPS_HIP(hipEventRecord(ev_rec, aux_));
       }
-      for (int j = len - 1; j >= 0; --j)
+      for (int j = len - 1; j >= 0; --j) {
+        step_setup(seg * ce + j);
         reverse_step(Xbar, first, [&](int q) { return slot(b, j, q); }, [&](int q) { return sslot(b, j, q); });
+      }
       SPS_HIP(hipEventRecord(ev_adj, stream));
     }
     last_seg_ok_ = nseg < 3;
@@ -3282,7 +3366,10 @@ class RbcProblem : public ProblemImpl {
   }
   void advance(cplx* X, int a, int b) {
     launch_kf(KF_ZGRID, X, nullptr, zgA_);
-    for (int n = a; n < b; ++n) rk_step(stream, X, [&](int) { return zgA_; }, (n + 1 < b) ? zgA_ : nullptr, no_save);
+    for (int n = a; n < b; ++n) {
+      step_setup(n);
+      rk_step(stream, X, [&](int) { return zgA_; }, (n + 1 < b) ? zgA_ : nullptr, no_save);
+    }
   }
   // forward actions of a schedule on the working state X (stored states in the slots); with
   // to_end false, the advance past the last stored state (to the run's final state) is skipped
@@ -3306,6 +3393,7 @@ class RbcProblem : public ProblemImpl {
         case CK_YOUTURN: {
           auto z = [&](int q) { return slot(0, 0, q); };
           launch_kf(KF_ZGRID, Xw_, nullptr, slot(0, 0, 0));
+          step_setup(c.a);
           rk_step(stream, Xw_, z, nullptr, no_save);
           reverse_step(Xbar, first, z, no_save);
           break;
@@ -3388,8 +3476,10 @@ class RbcProblem : public ProblemImpl {
           // it uses the working state again
           const auto& sc = schedule(seg_len(c.a, nsteps));
           copy_state(Xs_, Xo_);
+          step_base_ = seg_start(c.a, nsteps);   // the segment's schedule counts its own steps
           run_forward_actions(Xs_, sc.first, false);
           run_reverse_actions(Xbar, sc.second, first);
+          step_base_ = 0;
           break;
         }
         default: throw Error(SPS_E_STATE, "bad checkpoint action");
@@ -3408,8 +3498,10 @@ class RbcProblem : public ProblemImpl {
     } else {
       for (int g = 0; g < nseg; ++g) {
         copy_state(host_ckpt_.get() + (size_t)g * K_ * S_, X);
+        step_base_ = g * ce;
         advance(X, 0, seg_len(g, nsteps));
       }
+      step_base_ = 0;
     }
     tape_steps_ = nsteps;
   }
@@ -3435,8 +3527,10 @@ class RbcProblem : public ProblemImpl {
       } else {
         copy_state(Xs_, host_ckpt_.get() + (size_t)g * K_ * S_);
       }
+      step_base_ = g * ce;
       run_forward_actions(Xs_, sc.first, false);
       run_reverse_actions(Xbar, sc.second, first);
+      step_base_ = 0;
     }
     finish_reverse(Xbar);
   }
@@ -3456,8 +3550,10 @@ class RbcProblem : public ProblemImpl {
       copy_state(ckstage_.get() + (size_t)b * K_ * S_, X);
       SPS_HIP(hipEventRecord(ckev_[b], stream));
       pend[b] = g;
+      step_base_ = g * desc_.checkpoint_every;
       advance(X, 0, seg_len(g, nsteps));
     }
+    step_base_ = 0;
     flush(0);
     flush(1);
   }
@@ -3707,6 +3803,12 @@ class RbcProblem : public ProblemImpl {
   bool lfactored_ = false;
   int *err_ = nullptr;
   RkTab tab_;                        // the step's IMEX Runge-Kutta tableau
+  double cur_dt_ = 0.0;              // the step of the launches being enqueued (step_setup)
+  std::vector<double> vdt_;          // variable steps of a run (empty: the constant step)
+  std::vector<int> vset_;            // factor set of each variable step
+  std::vector<double*> vops_;        // factors of each distinct variable step
+  std::map<double, double*> opcache_;   // factor sets built so far, by step
+  int step_base_ = 0;                // run index of local step 0 (a segment's own schedule)
   cplx *Xst_, *Xw_, *Xg_, *acc_, *Ybuf_, *Fst_, *zgA_, *zbar_, *nl_, *nlbar_, *itmp_, *ckpt_, *seg_;
   size_t zsize_ = 0;
   int seglen_ = 0;
