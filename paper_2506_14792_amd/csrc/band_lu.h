@@ -25,8 +25,8 @@ __device__ __forceinline__ double writelane_d(double v, int lane, double old) {
 // be followed by at least SPS_PAD zero entries (positions n .. n + SPS_PAD - 1), which the
 // operators keep at zero.
 // Layout per system: T[nblk][TW][TS] (row-major, padded rows) followed by G[nblk][BLK][GS].
-// One real right-hand side per wave (the real and imaginary parts of a complex right-hand
-// side run on two waves): b[2*i] in LDS; operators in LDS.
+// One complex right-hand side per wave (lanes 0-31 the real parts, 32-63 the imaginary parts):
+// b[2*i], b[2*i + 1] in LDS; operators in LDS.
 #define SPS_BLK 8
 #define SPS_TW 16     // T window: needs SPS_BLK + kl <= SPS_TW
 #define SPS_GW 36     // G width: needs SPS_BLK + uw - 1 <= SPS_GW
@@ -42,13 +42,16 @@ __host__ __device__ inline int blk_ops_size(int n) {
 
 // The four sweeps over a range of blocks [t0, t1), with the operators of that range at T (T
 // blocks t0 .. t1-1) or G (G blocks t0 .. t1-1): forward L sweep (t ascending) and U sweep
-// (t descending), transposed U^T sweep (t ascending) and L^T sweep (t descending).  One wave.
-// L sweep: output r = lane/2 (32 lanes), half h = lane&1 sums columns 8h .. 8h+7
+// (t descending), transposed U^T sweep (t ascending) and L^T sweep (t descending).  One wave
+// per complex right-hand side: lanes 0-31 take the real parts, lanes 32-63 the imaginary parts
+// (element x at b[2x + part]), both halves reading the same operator entries.
+// L sweep: output r = l/2, half h = l&1 sums columns 8h .. 8h+7 (l = lane within the half)
 __device__ inline void blk_L_range(const double* T, int t0, int t1, double* b) {
-  const int lane = lane_id();
-  const int r = (lane >> 1) & (SPS_TW - 1), h = lane & 1;
+  const int lane = lane_id(), l = lane & 31;
+  const int r = l >> 1, h = l & 1;
+  double* bc = b + (lane >> 5);
   for (int t = t0; t < t1; ++t) {
-    const double* v = b + 2 * (t * SPS_BLK + 8 * h);
+    const double* v = bc + 2 * (t * SPS_BLK + 8 * h);
     const double* Tr = T + ((t - t0) * SPS_TW + r) * SPS_TS + 8 * h;
     double a0 = 0.0, a1 = 0.0;
 #pragma unroll
@@ -58,15 +61,16 @@ __device__ inline void blk_L_range(const double* T, int t0, int t1, double* b) {
     }
     double s = a0 + a1;
     s += dpp_xor1(s);
-    if (lane < 2 * SPS_TW && h == 0) b[2 * (t * SPS_BLK + r)] = s;
+    if (h == 0) bc[2 * (t * SPS_BLK + r)] = s;
   }
 }
-// U sweep: output i = lane/4 (32 lanes), quarter q = lane&3 sums columns 9q .. 9q+8
+// U sweep: output i = l/4, quarter q = l&3 sums columns 9q .. 9q+8
 __device__ inline void blk_U_range(const double* G, int t0, int t1, double* b) {
-  const int lane = lane_id();
-  const int i = (lane >> 2) & (SPS_BLK - 1), q = lane & 3;
+  const int lane = lane_id(), l = lane & 31;
+  const int i = l >> 2, q = l & 3;
+  double* bc = b + (lane >> 5);
   for (int t = t1 - 1; t >= t0; --t) {
-    const double* v = b + 2 * (t * SPS_BLK + 9 * q);
+    const double* v = bc + 2 * (t * SPS_BLK + 9 * q);
     const double* Gr = G + ((t - t0) * SPS_BLK + i) * SPS_GS + 9 * q;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
 #pragma unroll
@@ -78,32 +82,39 @@ __device__ inline void blk_U_range(const double* G, int t0, int t1, double* b) {
     double s = (a0 + a1) + a2;
     s += dpp_xor1(s);
     s += dpp_xor2(s);
-    if (lane < 4 * SPS_BLK && q == 0) b[2 * (t * SPS_BLK + i)] = s;
+    if (q == 0) bc[2 * (t * SPS_BLK + i)] = s;
   }
 }
-// U^T sweep: output c = lane (36 lanes) sums the BLK rows of its column
+// U^T sweep: output column c = l sums the BLK rows of its column; lanes l < GW - 32 also take
+// column l + 32 (the others compute a copy of column GW - 1 that they do not store)
 __device__ inline void blk_Ut_range(const double* G, int t0, int t1, double* b) {
-  const int lane = lane_id();
-  const int c = (lane < SPS_GW) ? lane : SPS_GW - 1;
+  const int lane = lane_id(), c = lane & 31, c2 = min(c + 32, SPS_GW - 1);
+  double* bc = b + (lane >> 5);
   for (int t = t0; t < t1; ++t) {
-    const double* v = b + 2 * (t * SPS_BLK);
-    const double* Gc = G + (t - t0) * SPS_BLK * SPS_GS + c;
-    double a0 = 0.0, a1 = 0.0;
+    const double* v = bc + 2 * (t * SPS_BLK);
+    const double* Gc = G + (t - t0) * SPS_BLK * SPS_GS;
+    double a0 = 0.0, a1 = 0.0, e0 = 0.0, e1 = 0.0;
 #pragma unroll
     for (int i = 0; i < SPS_BLK; i += 2) {
-      a0 = fma(Gc[i * SPS_GS], v[2 * (i)], a0);
-      a1 = fma(Gc[(i + 1) * SPS_GS], v[2 * (i + 1)], a1);
+      const double v0 = v[2 * (i)], v1 = v[2 * (i + 1)];
+      a0 = fma(Gc[i * SPS_GS + c], v0, a0);
+      a1 = fma(Gc[(i + 1) * SPS_GS + c], v1, a1);
+      e0 = fma(Gc[i * SPS_GS + c2], v0, e0);
+      e1 = fma(Gc[(i + 1) * SPS_GS + c2], v1, e1);
     }
     const double keep = (c >= SPS_BLK) ? v[2 * (c)] : 0.0;
-    if (lane < SPS_GW) b[2 * (t * SPS_BLK + c)] = keep + (a0 + a1);
+    const double keep2 = v[2 * (c2)];
+    bc[2 * (t * SPS_BLK + c)] = keep + (a0 + a1);
+    if (c + 32 < SPS_GW) bc[2 * (t * SPS_BLK + c2)] = keep2 + (e0 + e1);
   }
 }
-// L^T sweep: output c = lane/2 (32 lanes), half h sums rows 8h .. 8h+7 of column c
+// L^T sweep: output column c = l/2, half h = l&1 sums rows 8h .. 8h+7 of column c
 __device__ inline void blk_Lt_range(const double* T, int t0, int t1, double* b) {
-  const int lane = lane_id();
-  const int c = (lane >> 1) & (SPS_TW - 1), h = lane & 1;
+  const int lane = lane_id(), l = lane & 31;
+  const int c = l >> 1, h = l & 1;
+  double* bc = b + (lane >> 5);
   for (int t = t1 - 1; t >= t0; --t) {
-    const double* v = b + 2 * (t * SPS_BLK + 8 * h);
+    const double* v = bc + 2 * (t * SPS_BLK + 8 * h);
     const double* Tc = T + ((t - t0) * SPS_TW + 8 * h) * SPS_TS + c;
     double a0 = 0.0, a1 = 0.0;
 #pragma unroll
@@ -113,16 +124,16 @@ __device__ inline void blk_Lt_range(const double* T, int t0, int t1, double* b) 
     }
     double s = a0 + a1;
     s += dpp_xor1(s);
-    if (lane < 2 * SPS_TW && h == 0) b[2 * (t * SPS_BLK + c)] = s;
+    if (h == 0) bc[2 * (t * SPS_BLK + c)] = s;
   }
 }
-// x = A^{-1} b for one real vector b (element x at b[2*x], n + SPS_PAD entries, zero tail), one
-// wave, all operators at ops.
+// x = A^{-1} b for one complex vector b (element x at b[2x], b[2x + 1]; n + SPS_PAD entries,
+// zero tail), one wave, all operators at ops.
 __device__ inline void blk_solve_part(const double* ops, int nblk, double* b) {
   blk_L_range(ops, 0, nblk, b);
   blk_U_range(ops + nblk * SPS_TW * SPS_TS, 0, nblk, b);
 }
-// x = A^{-T} b for one real vector b (element x at b[2*x], zero tail), one wave.
+// x = A^{-T} b for one complex vector b (zero tail), one wave.
 __device__ inline void blk_solve_t_part(const double* ops, int nblk, double* b) {
   blk_Ut_range(ops + nblk * SPS_TW * SPS_TS, 0, nblk, b);
   blk_Lt_range(ops, 0, nblk, b);
@@ -156,19 +167,19 @@ __device__ __forceinline__ void ops_store(const OpsRegs& r, int count, double* d
 
 // ---------------------------------------------------------------------------- factor
 // One block (>= 64 threads) per system.  AB: row-band input for this system,
-// band[i*(kl+ku+1) + (c - i + kl)] = A[i][c], combined as a*BM + b*BL.
+// band[i*(kl+ku+1) + (c - i + kl)] = A[i][c], combined as a*BM + b*BL; entries whose column
+// falls outside [0, n) are dropped (so a band pointer offset by m rows with n = n - m gives the
+// trailing diagonal block, and n = m the leading one).
 // LDS layout (LAPACK band with fill rows): ab[c*ldab + (kv + i - c)] = A[i][c],
 // ldab = 2kl + ku + 1, kv = kl + ku.
 // With BLnu and BLka given, the L band is BL + nu BLnu + ka BLka (an operator affine in two
 // parameters, here the diffusivities of one instance of a batch).
-__device__ inline void band_factor_block(const double* __restrict__ BM, const double* __restrict__ BL,
-                                         double a, double bcoef, int n, int kl, int ku, double* ab,
-                                         int* sh, int* spiv, double* OPS, int* err,
-                                         const double* __restrict__ BLnu = nullptr,
-                                         const double* __restrict__ BLka = nullptr, double nu = 0.0,
-                                         double ka = 0.0) {
+__device__ inline void band_lu_factor(const double* __restrict__ BM, const double* __restrict__ BL, double a,
+                                      double bcoef, int n, int kl, int ku, double* ab, int* sh, int* spiv, int* err,
+                                      const double* __restrict__ BLnu = nullptr,
+                                      const double* __restrict__ BLka = nullptr, double nu = 0.0, double ka = 0.0) {
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int ldab = 2 * kl + ku + 1, kv = kl + ku, bw = kl + ku + 1, uw = kl + ku + 1;
+  const int ldab = 2 * kl + ku + 1, kv = kl + ku, bw = kl + ku + 1;
   for (int e = tid; e < n * ldab; e += nt) ab[e] = 0.0;
   __syncthreads();
   for (int e = tid; e < n * bw; e += nt) {
@@ -215,7 +226,13 @@ __device__ inline void band_factor_block(const double* __restrict__ BM, const do
     }
     __syncthreads();
   }
-  // block operators (see above); T_t column c is the image of the window's unit vector e_c
+}
+
+// Block operators (see above) of the factors in ab; T_t column c is the image of the window's
+// unit vector e_c.
+__device__ inline void band_condense(const double* ab, const int* spiv, int n, int kl, int ku, double* OPS) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int ldab = 2 * kl + ku + 1, kv = kl + ku;
   __syncthreads();
   const int nblk = blk_count(n);
   double* T = OPS;
@@ -280,4 +297,124 @@ __device__ inline void band_factor_block(const double* __restrict__ BM, const do
       Gr[c] = sacc;
     }
   }
+}
+
+__device__ inline void band_factor_block(const double* __restrict__ BM, const double* __restrict__ BL,
+                                         double a, double bcoef, int n, int kl, int ku, double* ab,
+                                         int* sh, int* spiv, double* OPS, int* err,
+                                         const double* __restrict__ BLnu = nullptr,
+                                         const double* __restrict__ BLka = nullptr, double nu = 0.0,
+                                         double ka = 0.0) {
+  band_lu_factor(BM, BL, a, bcoef, n, kl, ku, ab, sh, spiv, err, BLnu, BLka, nu, ka);
+  band_condense(ab, spiv, n, kl, ku, OPS);
+}
+
+// Solves with the factors in ab for nr right-hand sides, column c of the n x nr row-major
+// matrix R (LDS) by thread c alone (nr <= blockDim.x): A x = r (row interchanges and L, then
+// U) or A^T x = r (U^T, then L^T with the interchanges in reverse).  For the few columns of the
+// partitioned solve's coupling blocks at factorization time.  Block-wide (ends with a barrier).
+__device__ inline void band_lu_solve_cols(const double* ab, const int* spiv, int n, int kl, int ku, double* R,
+                                          int nr, bool transposed) {
+  const int c = threadIdx.x, ldab = 2 * kl + ku + 1, kv = kl + ku;
+  __syncthreads();
+  if (c < nr) {
+    auto x = [&](int i) -> double& { return R[(size_t)i * nr + c]; };
+    if (!transposed) {
+      for (int j = 0; j < n; ++j) {
+        const int p = spiv[j];
+        if (p != j) {
+          const double t = x(j);
+          x(j) = x(p);
+          x(p) = t;
+        }
+        const double xj = x(j);
+        const int km = min(kl, n - 1 - j);
+        for (int i = 1; i <= km; ++i) x(j + i) -= ab[j * ldab + kv + i] * xj;
+      }
+      for (int j = n - 1; j >= 0; --j) {
+        const double xj = x(j) / ab[j * ldab + kv];
+        x(j) = xj;
+        const int ku2 = min(kv, j);
+        for (int r = 1; r <= ku2; ++r) x(j - r) -= ab[j * ldab + kv - r] * xj;
+      }
+    } else {
+      for (int j = 0; j < n; ++j) {
+        double sacc = x(j);
+        const int ku2 = min(kv, j);
+        for (int r = 1; r <= ku2; ++r) sacc -= ab[j * ldab + kv - r] * x(j - r);
+        x(j) = sacc / ab[j * ldab + kv];
+      }
+      for (int j = n - 2; j >= 0; --j) {
+        double sacc = x(j);
+        const int km = min(kl, n - 1 - j);
+        for (int i = 1; i <= km; ++i) sacc -= ab[j * ldab + kv + i] * x(j + i);
+        const int p = spiv[j];
+        if (p != j) {
+          x(j) = x(p);
+          x(p) = sacc;
+        } else {
+          x(j) = sacc;
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Inverse of the nr x nr matrix A (row-major, LDS; nr <= 32) into Ainv (global, row-major) by
+// Gauss-Jordan elimination with partial pivoting on [A | I] in LDS (aug: nr x 2nr doubles);
+// wave 0, lane c owns column c of the augmented matrix.  Block-wide (ends with a barrier).
+__device__ inline void small_inverse(const double* A, int nr, double* aug, double* Ainv, int* err) {
+  const int tid = threadIdx.x, w = 2 * nr;
+  __syncthreads();
+  for (int e = tid; e < nr * w; e += blockDim.x) {
+    const int i = e / w, c = e - i * w;
+    aug[e] = (c < nr) ? A[i * nr + c] : ((c - nr == i) ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  if (tid < 64) {
+    const int lane = tid;
+    for (int j = 0; j < nr; ++j) {
+      // pivot row: largest |aug[i][j]|, i >= j (every lane scans the same column)
+      int p = j;
+      double best = fabs(aug[j * w + j]);
+      for (int i = j + 1; i < nr; ++i) {
+        const double v = fabs(aug[i * w + j]);
+        if (v > best) { best = v; p = i; }
+      }
+      if (!(best > 0.0) && lane == 0) atomicOr(err, 1);
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      for (int c = lane; c < w; c += 64) {
+        const double t = aug[j * w + c];
+        aug[j * w + c] = aug[p * w + c];
+        aug[p * w + c] = t;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      const double rinv = 1.0 / aug[j * w + j];
+      for (int c = lane; c < w; c += 64) aug[j * w + c] *= rinv;
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      for (int i = 0; i < nr; ++i) {
+        if (i == j) continue;
+        const double f = aug[i * w + j];
+        for (int c = lane; c < w; c += 64) {
+          if (c == j) continue;
+          aug[i * w + c] -= f * aug[j * w + c];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) aug[i * w + j] = 0.0;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < nr * nr; e += blockDim.x) {
+    const int i = e / nr, c = e - i * nr;
+    Ainv[e] = aug[i * w + nr + c];
+  }
+  __syncthreads();
 }

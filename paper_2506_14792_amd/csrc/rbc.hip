@@ -113,7 +113,14 @@ struct RbcDev {
   const double* gram;   // [N][N] int_0^1 T_m T_n dz
   const double* intw;   // [N] int_0^1 T_m(2z-1) dz
   const double* ops;    // [B][K][opsize] block operators of the LU factors (T blocks, then G blocks)
-  int opsize;
+  int opsize;           // doubles per system (stride)
+  int blksz;            // of which block operators (staged into LDS)
+  // Two-partition solve (part > 0, the staged path): the leading part rows and the trailing
+  // n - part rows have their own factors and block operators (blk_ops_size(part) doubles, then
+  // those of the trailing block); spike set dir (0 forward, 1 transposed) at spk[dir]: V
+  // [part][pnt], W [n - part][pnb], the inverse of the coupled entries' system [nr][nr],
+  // nr = pnb + pnt (see rbc_solve_part).
+  int part, pnb[2], pnt[2], spk[2];
   int* err;             // bit 0 singular pivot, bit 1 non-finite state
   // A batch of B instances of the problem (blockIdx.y = instance) that differ in their
   // Rayleigh number: per-instance nu and kappa (null for a single problem), factors and arrays
@@ -439,27 +446,27 @@ __device__ __forceinline__ void modes_to_pair(const double* ct, const cplx* c, i
   }
 }
 
-// Coefficient m of d/dz of a T series on [0,1] (twice the T-basis derivative):
+// Coefficient m of d/dz of a T series on [0,1] (twice the T-basis derivative) is
 // 4 sum_{p > m, p - m odd} p c_p, halved for m = 0.
-__device__ __forceinline__ cplx dz_coef(const cplx* c, int m, int N) {
-  double sr = 0.0, si = 0.0;
-  for (int p = m + 1; p < N; p += 2) {
-    sr = fma((double)p, c[p].x, sr);
-    si = fma((double)p, c[p].y, si);
+// For the three fields of c at once, field f on wave f and mode p on lane p (N <= 64):
+// with w_p = p c_p, coefficient m is the stride-2 suffix sum of w from p = m + 1, formed by
+// shuffles (five steps instead of a serial sum per coefficient).  Called by waves 0-2.
+__device__ __forceinline__ void dz_coefs_wave(const cplx* c, int N, cplx* dz) {
+  const int f = threadIdx.x >> 6, p = threadIdx.x & 63;
+  cplx w = (p < N) ? cscale(c[f * N + p], (double)p) : czero();
+  for (int o = 2; o < 64; o <<= 1) {
+    const double tx = __shfl_down(w.x, o), ty = __shfl_down(w.y, o);
+    if (p + o < 64) {
+      w.x += tx;
+      w.y += ty;
+    }
   }
-  const double sc = (m == 0) ? 2.0 : 4.0;
-  return cmk(sc * sr, sc * si);
+  // w = sum over q >= p of the parity of p of q c_q, the sum that coefficient p - 1 needs
+  if (p >= 1 && p <= N) dz[f * N + p - 1] = cscale(w, p == 1 ? 2.0 : 4.0);
+  if (p == 0 && N == 64) dz[f * N + N - 1] = czero();
 }
-// Entry n of the transpose of that map applied to y: 4 n sum_{p < n, n - p odd} y_p, with y_0 halved.
-__device__ __forceinline__ cplx dzt_coef(const cplx* y, int n) {
-  double sr = 0.0, si = 0.0;
-  for (int p = n - 1; p >= 0; p -= 2) {
-    const double w = (p == 0) ? 0.5 : 1.0;
-    sr = fma(w, y[p].x, sr);
-    si = fma(w, y[p].y, si);
-  }
-  return cmk(4.0 * n * sr, 4.0 * n * si);
-}
+// The transpose of that map applied to y has entry n = 4 n sum_{p < n, n - p odd} y_p, with y_0
+// halved (formed by prefix shuffles in zbar_to_coeffs).
 
 // The banded solves run in solver coordinates: real-ified (phases D_r, D_c), recombined (R)
 // and interleaved by mode (rowmap, colmap).
@@ -535,12 +542,13 @@ __device__ void rbc_scatter_h(const RbcDev& d, const MapRegs& m, const cplx* vA,
   __syncthreads();
 }
 // Write the prefetched block operators into LDS and solve in place on vA (forward or
-// transposed); waves 0 and 1 take the real and imaginary parts.  Block-wide.
+// transposed); wave 0 takes the complex vector (real parts on lanes 0-31, imaginary on 32-63).
+// Block-wide.
 __device__ void rbc_solve_staged(const RbcDev& d, const OpsRegs& regs, double* ops_lds, cplx* vA, bool transposed) {
-  ops_store(regs, d.opsize, ops_lds);
+  ops_store(regs, d.blksz, ops_lds);
   __syncthreads();
-  if (threadIdx.x < 2 * SPS_WAVE) {
-    double* b = reinterpret_cast<double*>(vA) + (threadIdx.x >> 6);
+  if (threadIdx.x < SPS_WAVE) {
+    double* b = reinterpret_cast<double*>(vA);
     if (transposed) blk_solve_t_part(ops_lds, blk_count(d.n), b);
     else blk_solve_part(ops_lds, blk_count(d.n), b);
   }
@@ -548,7 +556,7 @@ __device__ void rbc_solve_staged(const RbcDev& d, const OpsRegs& regs, double* o
 }
 
 // The same solve with the block operators streamed from global memory through two LDS buffers
-// of SPS_CHUNK blocks: waves 0 and 1 run the sweeps over chunk q while the other waves copy
+// of SPS_CHUNK blocks: wave 0 runs the sweeps over chunk q while the other waves copy
 // chunk q + 1 (for launches with many more systems than CUs: no register prefetch and a small
 // LDS footprint, so several blocks share a CU).  Block-wide; buf holds 2 * SOLVE_CHUNK_D doubles.
 constexpr int SPS_CHUNK = 8;
@@ -581,13 +589,13 @@ __device__ void rbc_solve_streamed(const RbcDev& d, const double* gops, double* 
   __syncthreads();
   for (int q = 0; q < Q; ++q) {
     double* cur = buf + (q & 1) * SOLVE_CHUNK_D;
-    if (wave >= 2) {
-      if (q + 1 < Q) copy(q + 1, buf + ((q + 1) & 1) * SOLVE_CHUNK_D, tid - 2 * SPS_WAVE, blockDim.x - 2 * SPS_WAVE);
+    if (wave >= 1) {
+      if (q + 1 < Q) copy(q + 1, buf + ((q + 1) & 1) * SOLVE_CHUNK_D, tid - SPS_WAVE, blockDim.x - SPS_WAVE);
     } else {
       int t0, t1;
       bool useT;
       range(q, &t0, &t1, &useT);
-      double* b = reinterpret_cast<double*>(vA) + wave;
+      double* b = reinterpret_cast<double*>(vA);
       if (!transposed) {
         if (useT) blk_L_range(cur, t0, t1, b);
         else blk_U_range(cur, t0, t1, b);
@@ -600,10 +608,85 @@ __device__ void rbc_solve_streamed(const RbcDev& d, const double* gops, double* 
   }
 }
 
+// The staged solve in two partitions (d.part = m): wave 0 solves the leading m rows with their
+// own block operators, wave 1 the trailing n - m rows (moved to vB, zero tail), at the same
+// time, so the dependent chain is half as long.  With y1, y2 their solutions, the exact solution
+// is x1 = y1 - V x2[0:nt2], x2 = y2 - W x1[m-nb1:m] (V, W the precomputed spikes); the coupled
+// entries (x1[m-nb1:m], x2[0:nt2]) solve a small system whose inverse is precomputed.  The
+// transposed solve uses the transposed spikes.  Waves 2-7 stage the inverse into LDS after the
+// block operators during the sweeps.  Block-wide; vA holds the gathered right-hand side and gets
+// the solution.
+__device__ void rbc_solve_part(const RbcDev& d, int k, const OpsRegs& regs, double* ops_lds, cplx* vA, cplx* vB,
+                               bool transposed) {
+  const int tid = threadIdx.x, wave = tid >> 6, m = d.part, n = d.n, n2 = n - m, dir = transposed ? 1 : 0;
+  double* rinv = ops_lds + d.blksz;
+  const int nb1 = d.pnb[dir], nt2 = d.pnt[dir], nr = nb1 + nt2;
+  const double* sp = d.ops + (size_t)k * d.opsize + d.spk[dir];
+  // this thread's row of V (row tid < m) or of W (m <= tid < n), loaded during the sweeps
+  double vrow[16];
+  const double* vr = (tid < m) ? sp + (size_t)tid * nt2 : sp + (size_t)m * nt2 + (size_t)(tid - m) * nb1;
+  const int vc = (tid < m) ? nt2 : nb1;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) vrow[c] = (tid < n && c < vc) ? vr[c] : 0.0;
+  ops_store(regs, d.blksz, ops_lds);
+  for (int i = tid; i < n2 + SPS_PAD; i += blockDim.x) vB[i] = (i < n2) ? vA[m + i] : czero();
+  __syncthreads();
+  if (wave < 2) {
+    const int part = wave;
+    double* b = reinterpret_cast<double*>(part ? vB : vA);
+    const double* o = ops_lds + (part ? blk_ops_size(m) : 0);
+    const int nb = blk_count(part ? n2 : m);
+    if (transposed) blk_solve_t_part(o, nb, b);
+    else blk_solve_part(o, nb, b);
+  } else {
+    const double* ri = sp + (size_t)m * nt2 + (size_t)n2 * nb1;
+    for (int e = tid - 2 * SPS_WAVE; e < nr * nr; e += blockDim.x - 2 * SPS_WAVE) rinv[e] = ri[e];
+  }
+  __syncthreads();
+  cplx* zs = vA + n;   // the coupled entries, in the zero tail of vA
+  if (tid < 3 * SPS_WAVE) {
+    // row r = 8 wave + lane / 8 of the inverse times the coupled right-hand side: eight lanes
+    // per row take every eighth column, then sum over the eight
+    const int r = 8 * wave + ((tid & 63) >> 3), cc = tid & 7;
+    cplx z = czero();
+    if (r < nr) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const int c = cc + 8 * q;
+        if (c < nr) {
+          const cplx rv = (c < nb1) ? vA[m - nb1 + c] : vB[c - nb1];
+          z = cadd(z, cscale(rv, rinv[r * nr + c]));
+        }
+      }
+    }
+    for (int o = 1; o < 8; o <<= 1) {
+      z.x += __shfl_xor(z.x, o);
+      z.y += __shfl_xor(z.y, o);
+    }
+    if (r < nr && cc == 0) zs[r] = z;
+  }
+  __syncthreads();
+  if (tid < m) {
+    cplx x = vA[tid];
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+      if (c < nt2) x = csub(x, cscale(zs[nb1 + c], vrow[c]));
+    vA[tid] = x;
+  } else if (tid < n) {
+    cplx x = vB[tid - m];
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+      if (c < nb1) x = csub(x, cscale(zs[c], vrow[c]));
+    vA[tid] = x;
+  }
+  __syncthreads();
+}
+
 template <bool STREAM>
 __device__ __forceinline__ void rbc_solve(const RbcDev& d, int k, const OpsRegs& regs, double* lds, cplx* vA,
-                                          bool transposed) {
+                                          cplx* vB, bool transposed) {
   if (STREAM) rbc_solve_streamed(d, d.ops + (size_t)k * d.opsize, lds, vA, transposed);
+  else if (d.part) rbc_solve_part(d, k, regs, lds, vA, vB, transposed);
   else rbc_solve_staged(d, regs, lds, vA, transposed);
 }
 
@@ -744,7 +827,7 @@ __global__ void __launch_bounds__(NTK) rbc_kfwd(RbcDev d, KfArgs a) {
   OpsRegs opsr;
   MapRegs mr;
   if (stage || mode == KF_SOLVE) {
-    if (!STREAM) ops_issue(d.ops + (size_t)k * d.opsize, d.opsize, opsr);
+    if (!STREAM) ops_issue(d.ops + (size_t)k * d.opsize, d.blksz, opsr);
     load_maps(d, mr);
   }
   if (stage) {
@@ -814,7 +897,7 @@ __global__ void __launch_bounds__(NTK) rbc_kfwd(RbcDev d, KfArgs a) {
     __syncthreads();
   } else {
     rbc_gather(d, mr, rr, vA);
-    rbc_solve<STREAM>(d, k, opsr, reinterpret_cast<double*>(un), vA, false);
+    rbc_solve<STREAM>(d, k, opsr, reinterpret_cast<double*>(un), vA, vB, false);
     rbc_scatter(d, mr, vA, vB, vA);   // vA <- new state (ABI slots)
     if (tid < S) {
       const cplx v = vA[tid];
@@ -828,10 +911,7 @@ __global__ void __launch_bounds__(NTK) rbc_kfwd(RbcDev d, KfArgs a) {
   double* ct2 = reinterpret_cast<double*>(un);
   cplx* dz = reinterpret_cast<cplx*>(ct2 + 4 * Ngz);   // 3*N
   if (tid < 4 * Ngz) ct2[tid] = cosr;
-  if (tid < 3 * N) {
-    const int f = tid / N, m = tid - f * N;
-    dz[tid] = dz_coef(vA + f * N, m, N);
-  }
+  if (tid < 3 * SPS_WAVE) dz_coefs_wave(vA, N, dz);
   __syncthreads();
   // a quad per (field group, mirror pair): group 0 = u, w, b; group 1 = their z-derivatives
   for (int e = tid; e < 8 * Hc; e += NTK) {
@@ -1307,9 +1387,21 @@ __device__ void zbar_to_coeffs(const RbcDev& d, const ZbarPair& zp, const double
     }
   }
   __syncthreads();
-  for (int e = tid; e < 3 * N; e += NTK) {
-    const int f = e / N, n = e - f * N;
-    out[e] = cadd(cb[e], dzt_coef(cb + (3 + f) * N, n));
+  // out = cb + the transposed derivative map of the second group: field f on wave f, mode on
+  // lane; entry n needs 4 n times the stride-2 prefix sum of y (y_0 halved) up to n - 1
+  if (tid < 3 * SPS_WAVE) {
+    const int f = tid >> 6, p = tid & 63;
+    const cplx* y = cb + (3 + f) * N;
+    cplx w = (p < N) ? cscale(y[p], p == 0 ? 0.5 : 1.0) : czero();
+    for (int o = 2; o < 64; o <<= 1) {
+      const double tx = __shfl_up(w.x, o), ty = __shfl_up(w.y, o);
+      if (p >= o) {
+        w.x += tx;
+        w.y += ty;
+      }
+    }
+    if (p + 1 < N) out[f * N + p + 1] = cadd(cb[f * N + p + 1], cscale(w, 4.0 * (p + 1)));
+    if (p == 0) out[f * N] = cb[f * N];
   }
   __syncthreads();
 }
@@ -1406,7 +1498,7 @@ __global__ void __launch_bounds__(NTK) rbc_kadj(RbcDev d, KaArgs a) {
   OpsRegs opsr;
   MapRegs mr;
   if (fl & (KA_A | KA_B | KA_SOLVE_T)) {
-    if (!STREAM) ops_issue(d.ops + (size_t)k * d.opsize, d.opsize, opsr);
+    if (!STREAM) ops_issue(d.ops + (size_t)k * d.opsize, d.blksz, opsr);
     load_maps(d, mr);
   }
   if (tid < 4 * Ngz) ct[tid] = cosr;
@@ -1414,7 +1506,7 @@ __global__ void __launch_bounds__(NTK) rbc_kadj(RbcDev d, KaArgs a) {
     if (sl) xbar[tid] = xin;
     __syncthreads();
     rbc_gather_h(d, mr, xbar, vA);
-    rbc_solve<STREAM>(d, k, opsr, ops, vA, true);
+    rbc_solve<STREAM>(d, k, opsr, ops, vA, vB, true);
     rbc_scatter_h(d, mr, vA, vB);
     if (sl) a.Xb_out[ks] = vB[tid];
     return;
@@ -1452,7 +1544,7 @@ __global__ void __launch_bounds__(NTK) rbc_kadj(RbcDev d, KaArgs a) {
   }
   // Y_m = (M + dt H_mm L)^{-H} xbar
   rbc_gather_h(d, mr, xbar, vA);
-  rbc_solve<STREAM>(d, k, opsr, ops, vA, true);
+  rbc_solve<STREAM>(d, k, opsr, ops, vA, vB, true);
   rbc_scatter_h(d, mr, vA, vB);       // vB = Y_m
   if (tid < 4 * Ngz) ct[tid] = cosr;
   const cplx ym = sl ? vB[tid] : czero();
@@ -1477,13 +1569,77 @@ __global__ void __launch_bounds__(NT) rbc_factor(RbcDev d, const double* BM, con
                                                  const double* BLka = nullptr) {
   extern __shared__ double smem_d[];
   __shared__ int sh[4];
-  const int k = blockIdx.x, b = blockIdx.y;
-  const size_t bw = d.kl + d.ku + 1, ko = (size_t)k * d.n * bw;
-  int* spiv = reinterpret_cast<int*>(smem_d + (size_t)d.n * (2 * d.kl + d.ku + 1));
+  const int k = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+  const int bw = d.kl + d.ku + 1, ldab = 2 * d.kl + d.ku + 1;
+  const size_t ko = (size_t)k * d.n * bw;
   const double nu = d.nub ? d.nub[b] : 0.0, ka = d.kab ? d.kab[b] : 0.0;
-  band_factor_block(BM + ko, BL + ko, am, bl, d.n, d.kl, d.ku, smem_d, sh, spiv,
-                    ops + ((size_t)b * d.K + k) * d.opsize, d.err, BLnu ? BLnu + ko : nullptr,
-                    BLka ? BLka + ko : nullptr, nu, ka);
+  double* O = ops + ((size_t)b * d.K + k) * d.opsize;
+  const double* bnu = BLnu ? BLnu + ko : nullptr;
+  const double* bka = BLka ? BLka + ko : nullptr;
+  if (!d.part) {
+    int* spiv = reinterpret_cast<int*>(smem_d + (size_t)d.n * ldab);
+    band_factor_block(BM + ko, BL + ko, am, bl, d.n, d.kl, d.ku, smem_d, sh, spiv, O, d.err, bnu, bka, nu, ka);
+    return;
+  }
+  // Two partitions: the factors and block operators of the leading m x m and trailing
+  // n2 x n2 diagonal blocks, their spikes (the solves of each block with the columns that
+  // couple it to the other, for A and for A^T), and the inverses of the coupled entries' systems.
+  const int m = d.part, n2 = d.n - m, mx = max(m, n2);
+  double* ab = smem_d;                                                   // mx * ldab
+  int* spiv = reinterpret_cast<int*>(ab + (size_t)mx * ldab);            // mx
+  double* R = ab + (size_t)mx * ldab + ((mx + 1) & ~1) / 2 + 1;          // mx * 16
+  double* Rm = R + (size_t)mx * 16;                                      // 24 * 24
+  double* aug = Rm + 24 * 24;                                            // 24 * 48
+  auto Aat = [&](int i, int c) -> double {   // entry (i, c) of a M + b L of the whole system
+    const int q = c - i + d.kl;
+    if (q < 0 || q >= bw) return 0.0;
+    const size_t e = ko + (size_t)i * bw + q;
+    const double l = BLnu ? BL[e] + nu * BLnu[e] + ka * BLka[e] : BL[e];
+    return am * BM[e] + bl * l;
+  };
+  band_lu_factor(BM + ko, BL + ko, am, bl, m, d.kl, d.ku, ab, sh, spiv, d.err, bnu, bka, nu, ka);
+  band_condense(ab, spiv, m, d.kl, d.ku, O);
+  for (int dir = 0; dir < 2; ++dir) {
+    const int nt2 = d.pnt[dir];
+    // V = A1^{-1} A[0:m, m:m+nt2] (forward) or A1^{-T} A^T[0:m, m:m+nt2] (transposed)
+    for (int e = tid; e < m * nt2; e += blockDim.x) {
+      const int i = e / nt2, c = e - i * nt2;
+      R[e] = dir ? Aat(m + c, i) : Aat(i, m + c);
+    }
+    band_lu_solve_cols(ab, spiv, m, d.kl, d.ku, R, nt2, dir == 1);
+    double* V = O + d.spk[dir];
+    for (int e = tid; e < m * nt2; e += blockDim.x) V[e] = R[e];
+  }
+  __syncthreads();
+  band_lu_factor(BM + ko + (size_t)m * bw, BL + ko + (size_t)m * bw, am, bl, n2, d.kl, d.ku, ab, sh, spiv, d.err,
+                 bnu ? bnu + (size_t)m * bw : nullptr, bka ? bka + (size_t)m * bw : nullptr, nu, ka);
+  band_condense(ab, spiv, n2, d.kl, d.ku, O + blk_ops_size(m));
+  for (int dir = 0; dir < 2; ++dir) {
+    const int nb1 = d.pnb[dir], nt2 = d.pnt[dir];
+    // W = A2^{-1} A[m:n, m-nb1:m] (forward) or A2^{-T} A^T[m:n, m-nb1:m] (transposed)
+    for (int e = tid; e < n2 * nb1; e += blockDim.x) {
+      const int i = e / nb1, c = e - i * nb1;
+      R[e] = dir ? Aat(m - nb1 + c, m + i) : Aat(m + i, m - nb1 + c);
+    }
+    band_lu_solve_cols(ab, spiv, n2, d.kl, d.ku, R, nb1, dir == 1);
+    double* W = O + d.spk[dir] + (size_t)m * nt2;
+    for (int e = tid; e < n2 * nb1; e += blockDim.x) W[e] = R[e];
+  }
+  __syncthreads();
+  for (int dir = 0; dir < 2; ++dir) {
+    const int nb1 = d.pnb[dir], nt2 = d.pnt[dir], nr = nb1 + nt2;
+    const double* V = O + d.spk[dir];
+    const double* W = V + (size_t)m * nt2;
+    // [I, V[m-nb1:m, :]; W[0:nt2, :], I] acting on (x1[m-nb1:m], x2[0:nt2])
+    for (int e = tid; e < nr * nr; e += blockDim.x) {
+      const int r = e / nr, c = e - r * nr;
+      double v;
+      if (r < nb1) v = (c < nb1) ? (r == c ? 1.0 : 0.0) : V[(size_t)(m - nb1 + r) * nt2 + (c - nb1)];
+      else v = (c < nb1) ? W[(size_t)(r - nb1) * nb1 + c] : (r == c ? 1.0 : 0.0);
+      Rm[e] = v;
+    }
+    small_inverse(Rm, nr, aug, O + d.spk[dir] + (size_t)m * nt2 + (size_t)n2 * nb1, d.err);
+  }
 }
 
 // ---------------------------------------------------------------------------- linear boundary value problem
@@ -2470,6 +2626,16 @@ class RbcProblem : public ProblemImpl {
     if (B_ > 1 || !rab_.empty()) throw Error(SPS_E_UNSUPPORTED, std::string(what) + " is not built for batches");
   }
 
+  // the descriptor for factors of one unpartitioned system per wavenumber at ops (the boundary
+  // value and eigenvalue problems' factor sets)
+  RbcDev whole_dev(double* ops) const {
+    RbcDev d = dv_;
+    d.ops = ops;
+    d.part = 0;
+    d.blksz = d.opsize = blk_ops_size(S_);
+    return d;
+  }
+
   // M + dt H_ii L (the implicit diagonal is one value for every stage)
   void factor() override {
     if (factored_) return;
@@ -2766,7 +2932,8 @@ class RbcProblem : public ProblemImpl {
       lops_ = arena_.alloc<double>((size_t)K_ * dv_.opsize);
       lrhs_ = arena_.alloc<cplx>((size_t)K_ * S_);
     }
-    hipLaunchKernelGGL(rbc_factor, dim3(K_), dim3(NT), factor_lds(), stream, dv_, BM_, BL_, 0.0, 1.0, lops_);
+    hipLaunchKernelGGL(rbc_factor, dim3(K_), dim3(NT), factor_lds(), stream, whole_dev(lops_), BM_, BL_, 0.0, 1.0,
+                       lops_);
     SPS_CHECK_LAUNCH();
     lfactored_ = true;
   }
@@ -2778,8 +2945,7 @@ class RbcProblem : public ProblemImpl {
     lbvp_factor();
     hipLaunchKernelGGL(rbc_lbvp_rhs, dim3(K_), dim3(NT), 0, stream, dv_, reinterpret_cast<const cplx*>(f), lrhs_);
     SPS_CHECK_LAUNCH();
-    RbcDev dl = dv_;
-    dl.ops = lops_;
+    RbcDev dl = whole_dev(lops_);
     KfArgs a = kf_args(KF_SOLVE);
     a.X0 = lrhs_;
     a.Xout = reinterpret_cast<cplx*>(X);
@@ -2792,8 +2958,7 @@ class RbcProblem : public ProblemImpl {
     if (cou_) throw Error(SPS_E_UNSUPPORTED, "the boundary value problem is built for the 2D problem");
     SPS_REQUIRE(Xbar && fbar, "null argument");
     lbvp_factor();
-    RbcDev dl = dv_;
-    dl.ops = lops_;
+    RbcDev dl = whole_dev(lops_);
     KaArgs a = ka_args(KA_SOLVE_T);
     a.Xb_in = reinterpret_cast<const cplx*>(Xbar);
     a.Xb_out = lrhs_;
@@ -2830,7 +2995,7 @@ class RbcProblem : public ProblemImpl {
       if (lds > factor_lds())
         SPS_HIP(hipFuncSetAttribute((const void*)rbc_factor, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     }
-    RbcDev de = dv_;
+    RbcDev de = whole_dev(eops_);
     de.kl = ekl_;
     de.ku = eku_;
     de.uw = ekl_ + eku_ + 1;
@@ -2995,10 +3160,20 @@ class RbcProblem : public ProblemImpl {
 
  private:
   // ----------------------------------------------------------------- launches
-  size_t factor_lds() const { return (size_t)(2 * kl_ + ku_ + 1) * S_ * sizeof(double) + sizeof(int) * S_; }
+  size_t factor_lds() const {
+    const size_t ldab = 2 * kl_ + ku_ + 1;
+    const size_t whole = ldab * S_ * sizeof(double) + sizeof(int) * S_;
+    if (!dv_.part) return whole;
+    const size_t mx = std::max(dv_.part, S_ - dv_.part);
+    const size_t partd = mx * ldab + (mx + 1) / 2 + 1 + mx * 16 + 24 * 24 + 24 * 48;
+    return std::max(whole, partd * sizeof(double));
+  }
   // staged solves hold a system's block operators in LDS; streamed ones two chunk buffers
   size_t ops_bytes() const {
-    return stream_solve_ ? sizeof(double) * 2 * (size_t)SOLVE_CHUNK_D : sizeof(double) * (size_t)blk_ops_size(S_);
+    if (stream_solve_) return sizeof(double) * 2 * (size_t)SOLVE_CHUNK_D;
+    // staged: the block operators, and the coupled entries' inverse after them (partitioned)
+    const int nr = dv_.part ? dv_.pnb[0] + dv_.pnt[0] : 0;
+    return sizeof(double) * ((size_t)dv_.blksz + (size_t)nr * nr);
   }
   // launches with many more systems than CUs stream the operators (several blocks per CU);
   // smaller ones stage them whole (one block per CU, shortest dependent chain)
@@ -3688,6 +3863,8 @@ class RbcProblem : public ProblemImpl {
       hb.BL = h0.BL;
       BLnu_ = arena_.upload(hn.BL, stream);
       BLka_ = arena_.upload(hk.BL, stream);
+      blnu_h_ = hn.BL;
+      blka_h_ = hk.BL;
       std::vector<double> nub(B_), kab(B_);
       for (int b = 0; b < B_; ++b) {
         nub[b] = std::pow(rab_[b] / desc_.param1, -0.5);
@@ -3697,11 +3874,12 @@ class RbcProblem : public ProblemImpl {
       dv_.kab = arena_.upload(kab, stream);
     }
     SPS_REQUIRE(kl_ + SPS_BLK <= SPS_TW && SPS_BLK + kl_ + ku_ <= SPS_GW, "band too wide for the block solver");
-    SPS_REQUIRE(blk_ops_size(S_) <= 2 * SPS_OPS_REG * NTK, "nz too large for the staged block solver");
+    SPS_REQUIRE(blk_ops_size(S_) <= 2 * SPS_OPS_REG * NTK && N_ <= SPS_WAVE, "nz too large for the staged block solver");
     SPS_REQUIRE(S_ + SPS_PAD <= NTK && 4 * N_ + 28 <= NTK && 4 * Ngz_ <= NTK && 6 * half_nodes(Ngz_) <= NTK,
                 "nz too large for one state entry per thread");
     BM_ = arena_.upload(hb.BM, stream);
     BL_ = arena_.upload(hb.BL, stream);
+    plan_partition(hb);
     dv_.n = S_;
     dv_.kl = kl_;
     dv_.ku = ku_;
@@ -3727,10 +3905,51 @@ class RbcProblem : public ProblemImpl {
     dv_.sflag = arena_.upload(sflag, stream);
   }
 
+  // The staged path solves in two partitions when the systems allow it: split at
+  // m = 8 ceil(nblk / 2), coupling widths from the band pattern (the columns >= m that rows < m
+  // reach, cu, and the columns < m that rows >= m reach, cl; over every wavenumber and, for a
+  // batch, every part of L), the trailing rows and their zero tail fitting vB.
+  void plan_partition(const RbcHostBands& hb) {
+    dv_.part = 0;
+    const int nblk = blk_count(S_), m = SPS_BLK * ((nblk + 1) / 2), n2 = S_ - m, bw = kl_ + ku_ + 1;
+    if (stream_solve_ || n2 + SPS_PAD > S_ || m < 16) return;
+    int cu = 0, cl = 0;
+    auto scan = [&](const std::vector<double>& band) {
+      for (int k = 0; k < K_; ++k)
+        for (int i = 0; i < S_; ++i)
+          for (int q = 0; q < bw; ++q) {
+            const int c = i + q - kl_;
+            if (c < 0 || c >= S_ || band[((size_t)k * S_ + i) * bw + q] == 0.0) continue;
+            if (i < m && c >= m) cu = std::max(cu, c - m + 1);
+            if (i >= m && c < m) cl = std::max(cl, m - c);
+          }
+    };
+    scan(hb.BM);
+    scan(hb.BL);
+    if (!rab_.empty()) {   // the batch's nu and kappa parts of L (host copies)
+      scan(blnu_h_);
+      scan(blka_h_);
+    }
+    if (cu > 16 || cl > 16 || cu + cl > 24) return;
+    dv_.part = m;
+    dv_.pnb[0] = cl;   // forward: x1[m-cl:m] couple to partition 2, x2[0:cu] to partition 1
+    dv_.pnt[0] = cu;
+    dv_.pnb[1] = cu;   // transposed
+    dv_.pnt[1] = cl;
+  }
+
   void alloc_work() {
     const size_t st = (size_t)B_ * K_ * S_;
     zsize_ = (size_t)B_ * 6 * Ngz_ * K_;
-    dv_.opsize = blk_ops_size(S_);
+    if (dv_.part) {
+      const int m = dv_.part, n2 = S_ - m, nr = dv_.pnb[0] + dv_.pnt[0];
+      dv_.blksz = blk_ops_size(m) + blk_ops_size(n2);
+      dv_.spk[0] = dv_.blksz;
+      dv_.spk[1] = dv_.spk[0] + m * dv_.pnt[0] + n2 * dv_.pnb[0] + nr * nr;
+      dv_.opsize = ((dv_.spk[1] + m * dv_.pnt[1] + n2 * dv_.pnb[1] + nr * nr) + 3) / 4 * 4;
+    } else {
+      dv_.blksz = dv_.opsize = blk_ops_size(S_);
+    }
     ops_ = arena_.alloc<double>((size_t)B_ * K_ * dv_.opsize);
     dv_.ops = ops_;
     err_ = arena_.alloc<int>(1);
@@ -3786,6 +4005,7 @@ class RbcProblem : public ProblemImpl {
   int B_ = 1;                        // instances of a batch
   std::vector<double> rab_;          // a batch's Rayleigh numbers (empty: a single problem)
   const double *BLnu_ = nullptr, *BLka_ = nullptr;   // a batch's nu and kappa parts of L
+  std::vector<double> blnu_h_, blka_h_;               // (host copies, for the partition's coupling widths)
   const double2* frame_ = nullptr;   // plane Couette: unit wave vector of each mode   // grid rows of 64 wave_r1_ points use the one-wave-per-FFT kernels
   std::vector<double> kxs_;
   std::vector<unsigned char> ckeep_;
