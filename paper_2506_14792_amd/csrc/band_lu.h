@@ -35,10 +35,12 @@ __device__ __forceinline__ double writelane_d(double v, int lane, double old) {
 #define SPS_PAD 40    // zero tail after the right-hand side (>= SPS_GW)
 
 __host__ __device__ inline int blk_count(int n) { return (n + SPS_BLK - 1) / SPS_BLK; }
-// doubles per system (a multiple of 4, so every system's operators start 32-byte aligned)
-__host__ __device__ inline int blk_ops_size(int n) {
-  return ((blk_count(n) * (SPS_TW * SPS_TS + SPS_BLK * SPS_GS) + 3) / 4) * 4;
-}
+// doubles of the T blocks and of the G blocks of an n-row system (multiples of 4, so every
+// set of operators starts 32-byte aligned), and of both
+__host__ __device__ inline int blk_t_size(int n) { return blk_count(n) * SPS_TW * SPS_TS; }
+__host__ __device__ inline int blk_g_size(int n) { return blk_count(n) * SPS_BLK * SPS_GS; }
+__host__ __device__ inline int blk_ops_size(int n) { return blk_t_size(n) + blk_g_size(n); }
+static_assert((SPS_TW * SPS_TS) % 4 == 0 && (SPS_BLK * SPS_GS) % 4 == 0, "block sizes keep 32-byte alignment");
 
 // The four sweeps over a range of blocks [t0, t1), with the operators of that range at T (T
 // blocks t0 .. t1-1) or G (G blocks t0 .. t1-1): forward L sweep (t ascending) and U sweep
@@ -127,42 +129,52 @@ __device__ inline void blk_Lt_range(const double* T, int t0, int t1, double* b) 
     if (h == 0) bc[2 * (t * SPS_BLK + c)] = s;
   }
 }
-// x = A^{-1} b for one complex vector b (element x at b[2x], b[2x + 1]; n + SPS_PAD entries,
-// zero tail), one wave, all operators at ops.
-__device__ inline void blk_solve_part(const double* ops, int nblk, double* b) {
-  blk_L_range(ops, 0, nblk, b);
-  blk_U_range(ops + nblk * SPS_TW * SPS_TS, 0, nblk, b);
-}
-// x = A^{-T} b for one complex vector b (zero tail), one wave.
-__device__ inline void blk_solve_t_part(const double* ops, int nblk, double* b) {
-  blk_Ut_range(ops + nblk * SPS_TW * SPS_TS, 0, nblk, b);
-  blk_Lt_range(ops, 0, nblk, b);
-}
 // One system's block operators are brought into LDS in two steps so that their memory
 // latency overlaps other work: ops_issue() starts all global loads of this thread's share
-// into registers, ops_store() writes them into LDS once the destination is free.
-// count (doubles) must be a multiple of 2; at most SPS_OPS_REG 16-byte loads per thread.
-#define SPS_OPS_REG 19
+// into registers, ops_store_part() writes one set of them into LDS once the destination is free.
+// The T blocks and the G blocks of a system are loaded and stored separately, so that the set
+// the first sweep needs can go to LDS before the other has arrived.  Counts (doubles) must be
+// multiples of 2; at most SPS_OPS_REG_T / SPS_OPS_REG_G 16-byte loads per thread.
+#define SPS_OPS_REG_T 9
+#define SPS_OPS_REG_G 10
 struct OpsRegs {
-  double2 v[SPS_OPS_REG];
+  double2 t[SPS_OPS_REG_T];
+  double2 g[SPS_OPS_REG_G];
 };
-__device__ __forceinline__ void ops_issue(const double* g, int count, OpsRegs& r) {
+// Every load is issued (an index past the end is clamped to the last element, whose copy is
+// not stored): a load under a branch would leave the compiler unsure how many loads are in
+// flight after an earlier one, and it then waits for all of them before using that one.
+template <int NS>
+__device__ __forceinline__ void ops_issue_part(const double* g, int count, double2 (&v)[NS]) {
   const double2* g2 = reinterpret_cast<const double2*>(g);
   const int h = count / 2;
 #pragma unroll
-  for (int i = 0; i < SPS_OPS_REG; ++i) {
-    const int e = threadIdx.x + i * blockDim.x;
-    r.v[i] = (e < h) ? g2[e] : make_double2(0.0, 0.0);
+  for (int i = 0; i < NS; ++i) {
+    // (field by field: a whole-struct copy from global memory keeps v in scratch memory)
+    const double2* p = g2 + min((int)(threadIdx.x + i * blockDim.x), h - 1);
+    v[i] = make_double2(p->x, p->y);
   }
 }
-__device__ __forceinline__ void ops_store(const OpsRegs& r, int count, double* dst) {
+template <int NS>
+__device__ __forceinline__ void ops_store_part(const double2 (&v)[NS], int count, double* dst) {
   double2* d2 = reinterpret_cast<double2*>(dst);
   const int h = count / 2;
 #pragma unroll
-  for (int i = 0; i < SPS_OPS_REG; ++i) {
+  for (int i = 0; i < NS; ++i) {
     const int e = threadIdx.x + i * blockDim.x;
-    if (e < h) d2[e] = r.v[i];
+    if (e < h) d2[e] = v[i];
   }
+}
+// a system's operators at g: tsz doubles of T blocks, then gsz of G blocks.  The loads return
+// in issue order, so a wait for the set issued first does not wait for the other.
+__device__ __forceinline__ void ops_issue(const double* g, int tsz, int gsz, OpsRegs& r) {
+  ops_issue_part(g, tsz, r.t);
+  ops_issue_part(g + tsz, gsz, r.g);
+}
+// the same with the G blocks issued first
+__device__ __forceinline__ void ops_issue_gt(const double* g, int tsz, int gsz, OpsRegs& r) {
+  ops_issue_part(g + tsz, gsz, r.g);
+  ops_issue_part(g, tsz, r.t);
 }
 
 // ---------------------------------------------------------------------------- factor
@@ -230,13 +242,11 @@ __device__ inline void band_lu_factor(const double* __restrict__ BM, const doubl
 
 // Block operators (see above) of the factors in ab; T_t column c is the image of the window's
 // unit vector e_c.
-__device__ inline void band_condense(const double* ab, const int* spiv, int n, int kl, int ku, double* OPS) {
+__device__ inline void band_condense(const double* ab, const int* spiv, int n, int kl, int ku, double* T, double* G) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int ldab = 2 * kl + ku + 1, kv = kl + ku;
   __syncthreads();
   const int nblk = blk_count(n);
-  double* T = OPS;
-  double* G = OPS + nblk * SPS_TW * SPS_TS;
   for (int e = tid; e < nblk * SPS_TW; e += nt) {
     const int t = e / SPS_TW, c = e - t * SPS_TW, tb = t * SPS_BLK;
     double v[SPS_TW];
@@ -306,7 +316,7 @@ __device__ inline void band_factor_block(const double* __restrict__ BM, const do
                                          const double* __restrict__ BLka = nullptr, double nu = 0.0,
                                          double ka = 0.0) {
   band_lu_factor(BM, BL, a, bcoef, n, kl, ku, ab, sh, spiv, err, BLnu, BLka, nu, ka);
-  band_condense(ab, spiv, n, kl, ku, OPS);
+  band_condense(ab, spiv, n, kl, ku, OPS, OPS + blk_t_size(n));
 }
 
 // Solves with the factors in ab for nr right-hand sides, column c of the n x nr row-major

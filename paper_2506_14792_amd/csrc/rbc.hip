@@ -111,15 +111,15 @@ struct RbcDev {
   const double* hrho;   // rho[s - 2] for s = colmap[i] (0 if s < 2)
   const int* sflag;     // colph[i] (slot i)
   const double* gram;   // [N][N] int_0^1 T_m T_n dz
-  const double* intw;   // [N] int_0^1 T_m(2z-1) dz
   const double* ops;    // [B][K][opsize] block operators of the LU factors (T blocks, then G blocks)
   int opsize;           // doubles per system (stride)
   int blksz;            // of which block operators (staged into LDS)
+  int tsz;              // of which T blocks (the G blocks follow at tsz)
   // Two-partition solve (part > 0, the staged path): the leading part rows and the trailing
-  // n - part rows have their own factors and block operators (blk_ops_size(part) doubles, then
-  // those of the trailing block); spike set dir (0 forward, 1 transposed) at spk[dir]: V
-  // [part][pnt], W [n - part][pnb], the inverse of the coupled entries' system [nr][nr],
-  // nr = pnb + pnt (see rbc_solve_part).
+  // n - part rows have their own factors and block operators (T blocks of the leading rows,
+  // then of the trailing ones; G blocks likewise from tsz); spike set dir (0 forward,
+  // 1 transposed) at spk[dir]: V [part][pnt], W [n - part][pnb], the inverse of the coupled
+  // entries' system [nr][nr], nr = pnb + pnt (see rbc_solve_part).
   int part, pnb[2], pnt[2], spk[2];
   int* err;             // bit 0 singular pivot, bit 1 non-finite state
   // A batch of B instances of the problem (blockIdx.y = instance) that differ in their
@@ -203,14 +203,18 @@ __device__ __forceinline__ cplx dz1t_at(const cplx* y, int m, int N) {
 }
 
 
-// Row s < 4N of (M X) and (L X) for wavenumber k (momentum, buoyancy and continuity rows).
-// X in ABI column slots.
+// int_0^1 T_m(2z - 1) dz: 1 / (1 - m^2) for even m, zero for odd m (computed, not loaded, so
+// that the stage kernels read no global memory between issuing their loads and the solve)
+__device__ __forceinline__ double intw_at(int m) { return (m & 1) ? 0.0 : 1.0 / (1.0 - (double)m * m); }
+
+// Row s < 4N of (M X) and (L X) for wavenumber k (momentum, buoyancy and continuity rows),
+// kx = d.kx[k] (loaded by the caller at kernel start).  X in ABI column slots.
 struct MLRow {
   cplx m, l;
 };
-__device__ MLRow ml_row(const RbcDev& d, int k, const cplx* X, int s) {
+__device__ MLRow ml_row(const RbcDev& d, int k, double kx, const cplx* X, int s) {
   const int N = d.N;
-  const double kx = d.kx[k], k2 = kx * kx;
+  const double k2 = kx * kx;
   const cplx* u = X;
   const cplx* w = X + N;
   const cplx* b = X + 2 * N;
@@ -258,8 +262,9 @@ __device__ __forceinline__ cplx l_bc_row(const RbcDev& d, int k, const cplx* X, 
   } else if (k == 0) {
     const cplx* p = X + 3 * N;
     for (int m = h; m < N; m += 4) {
-      sr = fma(d.intw[m], p[m].x, sr);
-      si = fma(d.intw[m], p[m].y, si);
+      const double w = intw_at(m);
+      sr = fma(w, p[m].x, sr);
+      si = fma(w, p[m].y, si);
     }
   } else if (h == 0) {
     sr = X[4 * N + 6].x;
@@ -268,10 +273,10 @@ __device__ __forceinline__ cplx l_bc_row(const RbcDev& d, int k, const cplx* X, 
   return group_sum<4>(cmk(sr, si));
 }
 
-// Column s of (M^H Y) and (L^H Y); Y in ABI row slots.
-__device__ MLRow mlt_col(const RbcDev& d, int k, const cplx* Y, int s) {
+// Column s of (M^H Y) and (L^H Y), kx = d.kx[k]; Y in ABI row slots.
+__device__ MLRow mlt_col(const RbcDev& d, int k, double kx, const cplx* Y, int s) {
   const int N = d.N;
-  const double kx = d.kx[k], k2 = kx * kx;
+  const double k2 = kx * kx;
   const cplx* yu = Y;
   const cplx* yw = Y + N;
   const cplx* yb = Y + 2 * N;
@@ -294,7 +299,7 @@ __device__ MLRow mlt_col(const RbcDev& d, int k, const cplx* Y, int s) {
   } else if (s < 4 * N) {
     const int m = s - 3 * N;
     cplx l = cadd(cmul_mi(cscale(s10t_at(yu, m, N), kx)), s1dzt_at(yw, m, N));
-    if (k == 0) l = cadd(l, cscale(Y[4 * N + 6], d.intw[m]));
+    if (k == 0) l = cadd(l, cscale(Y[4 * N + 6], intw_at(m)));
     r.l = l;
   } else {
     const int t = s - 4 * N;
@@ -479,26 +484,33 @@ struct MapRegs {
   int gm, hm, cm, sf;
   double hr, rh;
 };
+// (unconditional loads, clamped to the last entry: threads i >= S never use theirs, and loads
+// under a branch would make the compiler wait for every load in flight at their first use)
 __device__ __forceinline__ void load_maps(const RbcDev& d, MapRegs& m) {
-  const int i = threadIdx.x;
-  const bool ok = i < d.S;
-  m.gm = ok ? d.gmap[i] : 0;
-  m.hm = ok ? d.hmap[i] : 0;
-  m.cm = ok ? d.colmap[i] : 0;
-  m.sf = ok ? d.sflag[i] : 0;
-  m.hr = ok ? d.hrho[i] : 0.0;
-  m.rh = ok ? d.rho[i] : 0.0;
+  const int i = min((int)threadIdx.x, d.S - 1);
+  m.gm = d.gmap[i];
+  m.hm = d.hmap[i];
+  m.cm = d.colmap[i];
+  m.sf = d.sflag[i];
+  m.hr = d.hrho[i];
+  m.rh = d.rho[i];
 }
 
+// With a two-partition solve the gathers also put the trailing rows (from d.part on) and their
+// zero tail into vB, where the second partition is solved.
+__device__ __forceinline__ void gather_store(const RbcDev& d, int i, cplx v, cplx* vA, cplx* vB) {
+  vA[i] = v;
+  if (d.part && i >= d.part) vB[i - d.part] = v;
+}
 // r (ABI row slots) -> vA (solver rows), zero tail.  Block-wide, ends with a barrier.
-__device__ void rbc_gather(const RbcDev& d, const MapRegs& m, const cplx* r, cplx* vA) {
+__device__ void rbc_gather(const RbcDev& d, const MapRegs& m, const cplx* r, cplx* vA, cplx* vB) {
   const int i = threadIdx.x;
   if (i < d.S) {
     const int s = m.gm & 0xffff;
     const cplx v = r[s];
-    vA[i] = (m.gm >> 30) ? cmul_mi(v) : v;
+    gather_store(d, i, (m.gm >> 30) ? cmul_mi(v) : v, vA, vB);
   } else if (i < d.S + SPS_PAD) {
-    vA[i] = czero();
+    gather_store(d, i, czero(), vA, vB);
   }
   __syncthreads();
 }
@@ -515,7 +527,7 @@ __device__ void rbc_scatter(const RbcDev& d, const MapRegs& m, const cplx* vA, c
   __syncthreads();
 }
 // g (ABI column slots) -> vA = (R^T D_c^H g)[colmap], zero tail.
-__device__ void rbc_gather_h(const RbcDev& d, const MapRegs& m, const cplx* g, cplx* vA) {
+__device__ void rbc_gather_h(const RbcDev& d, const MapRegs& m, const cplx* g, cplx* vA, cplx* vB) {
   const int i = threadIdx.x;
   if (i < d.S) {
     const int s = m.hm & 0xffff;
@@ -526,9 +538,9 @@ __device__ void rbc_gather_h(const RbcDev& d, const MapRegs& m, const cplx* g, c
       if ((m.hm >> 29) & 1) v2 = cmul_mi(v2);
       v = cadd(v, cscale(v2, m.hr));
     }
-    vA[i] = v;
+    gather_store(d, i, v, vA, vB);
   } else if (i < d.S + SPS_PAD) {
-    vA[i] = czero();
+    gather_store(d, i, czero(), vA, vB);
   }
   __syncthreads();
 }
@@ -541,17 +553,51 @@ __device__ void rbc_scatter_h(const RbcDev& d, const MapRegs& m, const cplx* vA,
   }
   __syncthreads();
 }
-// Write the prefetched block operators into LDS and solve in place on vA (forward or
-// transposed); wave 0 takes the complex vector (real parts on lanes 0-31, imaginary on 32-63).
-// Block-wide.
-__device__ void rbc_solve_staged(const RbcDev& d, const OpsRegs& regs, double* ops_lds, cplx* vA, bool transposed) {
-  ops_store(regs, d.blksz, ops_lds);
+// Staged solves hold a system's block operators in LDS from o.  The set the first sweep reads
+// (T for the forward solve, G for the transposed one: the early set) sits above the other (the
+// late set, from o), so that it can be written while the stage kernel's phase buffers, which
+// share the late set's space, are still in use; the late set is written during the first sweep.
+struct StagedOps {
+  double* T;
+  double* G;
+};
+__device__ __forceinline__ StagedOps staged_ops(const RbcDev& d, double* o, bool transposed) {
+  return transposed ? StagedOps{o, o + d.tsz} : StagedOps{o + (d.blksz - d.tsz), o};
+}
+// This thread's share of the early set into LDS (waits for those loads only, which were issued
+// first).  Every thread, before the block barrier that precedes the solve.
+__device__ __forceinline__ void stage_early(const RbcDev& d, const OpsRegs& r, double* o, bool transposed) {
+  const StagedOps s = staged_ops(d, o, transposed);
+  if (transposed) ops_store_part(r.g, d.blksz - d.tsz, s.G);
+  else ops_store_part(r.t, d.tsz, s.T);
+}
+__device__ __forceinline__ void stage_late(const RbcDev& d, const OpsRegs& r, double* o, bool transposed) {
+  const StagedOps s = staged_ops(d, o, transposed);
+  if (transposed) ops_store_part(r.t, d.tsz, s.T);
+  else ops_store_part(r.g, d.blksz - d.tsz, s.G);
+}
+// The first and second sweeps of one wave's solve of the system whose operators start at T, G.
+__device__ __forceinline__ void sweep_first(const double* T, const double* G, int nblk, double* b, bool transposed) {
+  if (transposed) blk_Ut_range(G, 0, nblk, b);
+  else blk_L_range(T, 0, nblk, b);
+}
+__device__ __forceinline__ void sweep_second(const double* T, const double* G, int nblk, double* b, bool transposed) {
+  if (transposed) blk_Lt_range(T, 0, nblk, b);
+  else blk_U_range(G, 0, nblk, b);
+}
+
+// Solve in place on vA (forward or transposed) with the early set already in LDS (stage_early
+// before the last barrier); wave 0 takes the complex vector (real parts on lanes 0-31,
+// imaginary on 32-63) while the other waves write the late set.  Block-wide.
+__device__ void rbc_solve_staged(const RbcDev& d, const OpsRegs& regs, double* o, cplx* vA, bool transposed) {
+  const StagedOps s = staged_ops(d, o, transposed);
+  const int nblk = blk_count(d.n);
+  double* b = reinterpret_cast<double*>(vA);
+  const bool solver = threadIdx.x < SPS_WAVE;
+  if (solver) sweep_first(s.T, s.G, nblk, b, transposed);
+  stage_late(d, regs, o, transposed);
   __syncthreads();
-  if (threadIdx.x < SPS_WAVE) {
-    double* b = reinterpret_cast<double*>(vA);
-    if (transposed) blk_solve_t_part(ops_lds, blk_count(d.n), b);
-    else blk_solve_part(ops_lds, blk_count(d.n), b);
-  }
+  if (solver) sweep_second(s.T, s.G, nblk, b, transposed);
   __syncthreads();
 }
 
@@ -609,39 +655,43 @@ __device__ void rbc_solve_streamed(const RbcDev& d, const double* gops, double* 
 }
 
 // The staged solve in two partitions (d.part = m): wave 0 solves the leading m rows with their
-// own block operators, wave 1 the trailing n - m rows (moved to vB, zero tail), at the same
+// own block operators, wave 1 the trailing n - m rows (in vB from the gather, zero tail), at the same
 // time, so the dependent chain is half as long.  With y1, y2 their solutions, the exact solution
 // is x1 = y1 - V x2[0:nt2], x2 = y2 - W x1[m-nb1:m] (V, W the precomputed spikes); the coupled
 // entries (x1[m-nb1:m], x2[0:nt2]) solve a small system whose inverse is precomputed.  The
-// transposed solve uses the transposed spikes.  Waves 2-7 stage the inverse into LDS after the
-// block operators during the sweeps.  Block-wide; vA holds the gathered right-hand side and gets
-// the solution.
-__device__ void rbc_solve_part(const RbcDev& d, int k, const OpsRegs& regs, double* ops_lds, cplx* vA, cplx* vB,
+// transposed solve uses the transposed spikes.  The early set is in LDS (stage_early before the
+// last barrier); waves 2-7 write the late set and the inverse (after the operators) during the
+// first sweeps, waves 0-1 their share of the late set after them.  Block-wide; vA holds the
+// gathered right-hand side and gets the solution.
+__device__ void rbc_solve_part(const RbcDev& d, int k, const OpsRegs& regs, double* o, cplx* vA, cplx* vB,
                                bool transposed) {
   const int tid = threadIdx.x, wave = tid >> 6, m = d.part, n = d.n, n2 = n - m, dir = transposed ? 1 : 0;
-  double* rinv = ops_lds + d.blksz;
+  double* rinv = o + d.blksz;
   const int nb1 = d.pnb[dir], nt2 = d.pnt[dir], nr = nb1 + nt2;
   const double* sp = d.ops + (size_t)k * d.opsize + d.spk[dir];
   // this thread's row of V (row tid < m) or of W (m <= tid < n), loaded during the sweeps
+  // (unconditional loads at clamped indices: the entries past the row are never used, and a
+  // load under a branch would make the compiler wait for every load in flight before the sweeps)
   double vrow[16];
-  const double* vr = (tid < m) ? sp + (size_t)tid * nt2 : sp + (size_t)m * nt2 + (size_t)(tid - m) * nb1;
-  const int vc = (tid < m) ? nt2 : nb1;
+  const int tr = min(tid, n - 1);
+  const double* vr = (tr < m) ? sp + (size_t)tr * nt2 : sp + (size_t)m * nt2 + (size_t)(tr - m) * nb1;
+  const int vc = (tr < m) ? nt2 : nb1;
 #pragma unroll
-  for (int c = 0; c < 16; ++c) vrow[c] = (tid < n && c < vc) ? vr[c] : 0.0;
-  ops_store(regs, d.blksz, ops_lds);
-  for (int i = tid; i < n2 + SPS_PAD; i += blockDim.x) vB[i] = (i < n2) ? vA[m + i] : czero();
-  __syncthreads();
-  if (wave < 2) {
-    const int part = wave;
-    double* b = reinterpret_cast<double*>(part ? vB : vA);
-    const double* o = ops_lds + (part ? blk_ops_size(m) : 0);
-    const int nb = blk_count(part ? n2 : m);
-    if (transposed) blk_solve_t_part(o, nb, b);
-    else blk_solve_part(o, nb, b);
-  } else {
+  for (int c = 0; c < 16; ++c) vrow[c] = vr[min(c, vc - 1)];
+  const StagedOps s = staged_ops(d, o, transposed);
+  const int part = wave;
+  double* b = reinterpret_cast<double*>(part ? vB : vA);
+  const double* T = s.T + (part ? blk_t_size(m) : 0);
+  const double* G = s.G + (part ? blk_g_size(m) : 0);
+  const int nb = blk_count(part ? n2 : m);
+  if (wave < 2) sweep_first(T, G, nb, b, transposed);
+  stage_late(d, regs, o, transposed);
+  if (wave >= 2) {
     const double* ri = sp + (size_t)m * nt2 + (size_t)n2 * nb1;
     for (int e = tid - 2 * SPS_WAVE; e < nr * nr; e += blockDim.x - 2 * SPS_WAVE) rinv[e] = ri[e];
   }
+  __syncthreads();
+  if (wave < 2) sweep_second(T, G, nb, b, transposed);
   __syncthreads();
   cplx* zs = vA + n;   // the coupled entries, in the zero tail of vA
   if (tid < 3 * SPS_WAVE) {
@@ -682,6 +732,8 @@ __device__ void rbc_solve_part(const RbcDev& d, int k, const OpsRegs& regs, doub
   __syncthreads();
 }
 
+// The staged solves need stage_early(d, regs, lds, transposed) by every thread before the last
+// barrier.
 template <bool STREAM>
 __device__ __forceinline__ void rbc_solve(const RbcDev& d, int k, const OpsRegs& regs, double* lds, cplx* vA,
                                           cplx* vB, bool transposed) {
@@ -804,21 +856,21 @@ __global__ void __launch_bounds__(NTK) rbc_kfwd(RbcDev d, KfArgs a) {
 
   // Global reads, in the order they are needed: the states and earlier F (combined as they
   // arrive), the mirror pair of the nonlinear terms and one cosine per thread first, then the
-  // block operators (needed last).
+  // permutation maps and the block operators (needed last).
+  const double kxk = d.kx[k];
   const cplx x0 = (mode != KF_EVALF && tid < S) ? a.X0[(size_t)k * S + tid] : czero();
   // (loops over the tableau's fixed size, so that the coefficients are read at constant
-  // indices; the host zeroes them beyond the stage)
-  cplx xc = czero(), fc = czero();
-  if (stage) {
+  // indices; the host zeroes them beyond the stage.  Loaded here, combined once every load is
+  // issued: a sum taken as the loads arrive would wait for each before issuing the next.)
+  cplx xs[RK_MAXS - 1], fs[RK_MAXS - 1];
 #pragma unroll
-    for (int j = 1; j < RK_MAXS; ++j)
-      if (j < si && a.lh[j] != 0.0 && tid < S)
-        xc = cadd(xc, cscale(a.Xst[(size_t)(j - 1) * a.sstr + (size_t)k * S + tid], a.lh[j]));
+  for (int j = 1; j < RK_MAXS; ++j)
+    xs[j - 1] = (stage && j < si && a.lh[j] != 0.0 && tid < S)
+                    ? a.Xst[(size_t)(j - 1) * a.sstr + (size_t)k * S + tid] : czero();
 #pragma unroll
-    for (int j = 0; j + 1 < RK_MAXS; ++j)
-      if (j + 1 < si && a.fa[j] != 0.0 && tid < 3 * N)
-        fc = cadd(fc, cscale(a.Fst[(size_t)j * a.fstr + (size_t)k * 3 * N + tid], a.fa[j]));
-  }
+  for (int j = 0; j + 1 < RK_MAXS; ++j)
+    fs[j] = (stage && j + 1 < si && a.fa[j] != 0.0 && tid < 3 * N)
+                ? a.Fst[(size_t)j * a.fstr + (size_t)k * 3 * N + tid] : czero();
   const int pf = tid / Hc, pj = tid - pf * Hc, pjm = Ngz - 1 - pj;
   const bool pl = nonlin && tid < 3 * Hc;
   const cplx nvj = pl ? a.nl[((size_t)pf * Ngz + pj) * K + k] : czero();
@@ -826,9 +878,18 @@ __global__ void __launch_bounds__(NTK) rbc_kfwd(RbcDev d, KfArgs a) {
   const double cosr = (tid < 4 * Ngz) ? d.cosz[tid] : 0.0;
   OpsRegs opsr;
   MapRegs mr;
-  if (stage || mode == KF_SOLVE) {
-    if (!STREAM) ops_issue(d.ops + (size_t)k * d.opsize, d.blksz, opsr);
-    load_maps(d, mr);
+  // (issued in every mode, so that no load is under a branch; T blocks first: the first sweep
+  // needs them, the G blocks arrive during it)
+  load_maps(d, mr);
+  if (!STREAM) ops_issue(d.ops + (size_t)k * d.opsize, d.tsz, d.blksz - d.tsz, opsr);
+  cplx xc = czero(), fc = czero();
+  if (stage) {
+#pragma unroll
+    for (int j = 1; j < RK_MAXS; ++j)
+      if (j < si && a.lh[j] != 0.0) xc = cadd(xc, cscale(xs[j - 1], a.lh[j]));
+#pragma unroll
+    for (int j = 0; j + 1 < RK_MAXS; ++j)
+      if (j + 1 < si && a.fa[j] != 0.0) fc = cadd(fc, cscale(fs[j], a.fa[j]));
   }
   if (stage) {
     if (tid < S) {
@@ -874,9 +935,9 @@ __global__ void __launch_bounds__(NTK) rbc_kfwd(RbcDev d, KfArgs a) {
     const double dt = a.dt, fl = a.fself;
     if (tid < 4 * N) {
       const int s = tid;
-      const MLRow r0 = ml_row(d, k, xa, s);
+      const MLRow r0 = ml_row(d, k, kxk, xa, s);
       cplx comb = (s < 3 * N) ? cadd(f0s[s], cscale(fr[s], fl)) : czero();
-      if (a.lx) comb = csub(comb, ml_row(d, k, xb, s).l);
+      if (a.lx) comb = csub(comb, ml_row(d, k, kxk, xb, s).l);
       rr[s] = cadd(r0.m, cscale(comb, dt));
     } else if (tid < 4 * N + 28) {
       // boundary and gauge rows: M is zero there and every stage's F holds the boundary data
@@ -896,7 +957,8 @@ __global__ void __launch_bounds__(NTK) rbc_kfwd(RbcDev d, KfArgs a) {
     if (tid < S) vA[tid] = x0;
     __syncthreads();
   } else {
-    rbc_gather(d, mr, rr, vA);
+    if (!STREAM) stage_early(d, opsr, reinterpret_cast<double*>(un), false);
+    rbc_gather(d, mr, rr, vA, vB);
     rbc_solve<STREAM>(d, k, opsr, reinterpret_cast<double*>(un), vA, vB, false);
     rbc_scatter(d, mr, vA, vB, vA);   // vA <- new state (ABI slots)
     if (tid < S) {
@@ -1473,39 +1535,46 @@ __global__ void __launch_bounds__(NTK) rbc_kadj(RbcDev d, KaArgs a) {
   double* p_red = reinterpret_cast<double*>(p_x + S);   // 2 * NTK / 64
 
   // global reads in the order they are needed, the block operators last
+  const double kxk = d.kx[k];
   const bool in_x = (fl & (KA_SOLVE_T | KA_G)) || ((fl & KA_A) && !(fl & KA_C));
   const cplx xin = (in_x && sl) ? a.Xb_in[ks] : czero();
   const cplx accv = ((fl & KA_C) && a.acc && sl) ? a.acc[ks] : czero();
-  // the later stages' adjoints, combined as they arrive: yc = sum_{j>m} H_jm Y_j (implicit
-  // coupling), fs = sum_{j>m} A_{j,m-1} Y_j (F cotangent of stage m-1), ys = sum_{j>m} Y_j
-  // (a loop over the tableau's fixed size: coefficients at constant indices)
-  cplx yc = czero(), fs = czero(), ys = czero();
-  if ((fl & KA_B) && sl) {
+  // the later stages' adjoints, loaded here and combined once every load is issued (a sum
+  // taken as they arrive would wait for each before issuing the next): yc = sum_{j>m} H_jm Y_j
+  // (implicit coupling), fs = sum_{j>m} A_{j,m-1} Y_j (F cotangent of stage m-1),
+  // ys = sum_{j>m} Y_j (loops over the tableau's fixed size: coefficients at constant indices)
+  cplx yv[RK_MAXS - 1];
 #pragma unroll
-    for (int j = 2; j <= RK_MAXS; ++j) {
-      if (j > m && j <= a.nst) {
-        const cplx y = a.Ybuf[(size_t)(j - 2) * a.sstr + ks];
-        yc = cadd(yc, cscale(y, a.hc[j]));
-        fs = cadd(fs, cscale(y, a.fc[j]));
-        ys = cadd(ys, y);
-      }
-    }
-  }
+  for (int j = 2; j <= RK_MAXS; ++j)
+    yv[j - 2] = ((fl & KA_B) && sl && j > m && j <= a.nst) ? a.Ybuf[(size_t)(j - 2) * a.sstr + ks] : czero();
   const bool par = (fl & (KA_A | KA_B)) && a.pacc;
   const cplx xmv = (par && sl) ? a.Xm[ks] : czero();
   const ZbarPair zp = load_zbar_pair(d, a, k, (fl & (KA_C | KA_B)) != 0);
   const double cosr = (tid < 4 * Ngz) ? d.cosz[tid] : 0.0;
   OpsRegs opsr;
   MapRegs mr;
-  if (fl & (KA_A | KA_B | KA_SOLVE_T)) {
-    if (!STREAM) ops_issue(d.ops + (size_t)k * d.opsize, d.blksz, opsr);
-    load_maps(d, mr);
+  // (issued for every flag set, so that no load is under a branch; the transposed solve's first
+  // sweep reads the G blocks: those first)
+  load_maps(d, mr);
+  if (!STREAM) ops_issue_gt(d.ops + (size_t)k * d.opsize, d.tsz, d.blksz - d.tsz, opsr);
+  cplx yc = czero(), fs = czero(), ys = czero();
+  if ((fl & KA_B) && sl) {
+#pragma unroll
+    for (int j = 2; j <= RK_MAXS; ++j) {
+      if (j > m && j <= a.nst) {
+        const cplx y = yv[j - 2];
+        yc = cadd(yc, cscale(y, a.hc[j]));
+        fs = cadd(fs, cscale(y, a.fc[j]));
+        ys = cadd(ys, y);
+      }
+    }
   }
   if (tid < 4 * Ngz) ct[tid] = cosr;
   if (fl & KA_SOLVE_T) {
     if (sl) xbar[tid] = xin;
     __syncthreads();
-    rbc_gather_h(d, mr, xbar, vA);
+    if (!STREAM) stage_early(d, opsr, ops, true);
+    rbc_gather_h(d, mr, xbar, vA, vB);
     rbc_solve<STREAM>(d, k, opsr, ops, vA, vB, true);
     rbc_scatter_h(d, mr, vA, vB);
     if (sl) a.Xb_out[ks] = vB[tid];
@@ -1535,7 +1604,7 @@ __global__ void __launch_bounds__(NTK) rbc_kadj(RbcDev d, KaArgs a) {
     if (sl) y2[tid] = yc;
     __syncthreads();
     if (sl) {
-      const MLRow t = mlt_col(d, k, y2, tid);
+      const MLRow t = mlt_col(d, k, kxk, y2, tid);
       cplx v = cscale(t.l, -dt);
       if (tid < 3 * N) v = cadd(v, vv[tid]);
       xbar[tid] = v;
@@ -1543,7 +1612,8 @@ __global__ void __launch_bounds__(NTK) rbc_kadj(RbcDev d, KaArgs a) {
     __syncthreads();
   }
   // Y_m = (M + dt H_mm L)^{-H} xbar
-  rbc_gather_h(d, mr, xbar, vA);
+  if (!STREAM) stage_early(d, opsr, ops, true);
+  rbc_gather_h(d, mr, xbar, vA, vB);
   rbc_solve<STREAM>(d, k, opsr, ops, vA, vB, true);
   rbc_scatter_h(d, mr, vA, vB);       // vB = Y_m
   if (tid < 4 * Ngz) ct[tid] = cosr;
@@ -1557,7 +1627,7 @@ __global__ void __launch_bounds__(NTK) rbc_kadj(RbcDev d, KaArgs a) {
   }
   __syncthreads();
   if (par) param_accumulate(d, a, k, cadd(yc, cscale(ym, a.hself)), p_x, p_red);
-  if (m == 1 && sl) a.acc[ks] = mlt_col(d, k, p_t, tid).m;
+  if (m == 1 && sl) a.acc[ks] = mlt_col(d, k, kxk, p_t, tid).m;
   g_to_nlbar(d, a, k, ct, p_g, p_nh);
 }
 
@@ -1598,7 +1668,7 @@ __global__ void __launch_bounds__(NT) rbc_factor(RbcDev d, const double* BM, con
     return am * BM[e] + bl * l;
   };
   band_lu_factor(BM + ko, BL + ko, am, bl, m, d.kl, d.ku, ab, sh, spiv, d.err, bnu, bka, nu, ka);
-  band_condense(ab, spiv, m, d.kl, d.ku, O);
+  band_condense(ab, spiv, m, d.kl, d.ku, O, O + d.tsz);
   for (int dir = 0; dir < 2; ++dir) {
     const int nt2 = d.pnt[dir];
     // V = A1^{-1} A[0:m, m:m+nt2] (forward) or A1^{-T} A^T[0:m, m:m+nt2] (transposed)
@@ -1613,7 +1683,7 @@ __global__ void __launch_bounds__(NT) rbc_factor(RbcDev d, const double* BM, con
   __syncthreads();
   band_lu_factor(BM + ko + (size_t)m * bw, BL + ko + (size_t)m * bw, am, bl, n2, d.kl, d.ku, ab, sh, spiv, d.err,
                  bnu ? bnu + (size_t)m * bw : nullptr, bka ? bka + (size_t)m * bw : nullptr, nu, ka);
-  band_condense(ab, spiv, n2, d.kl, d.ku, O + blk_ops_size(m));
+  band_condense(ab, spiv, n2, d.kl, d.ku, O + blk_t_size(m), O + d.tsz + blk_g_size(m));
   for (int dir = 0; dir < 2; ++dir) {
     const int nb1 = d.pnb[dir], nt2 = d.pnt[dir];
     // W = A2^{-1} A[m:n, m-nb1:m] (forward) or A2^{-T} A^T[m:n, m-nb1:m] (transposed)
@@ -2633,6 +2703,7 @@ class RbcProblem : public ProblemImpl {
     d.ops = ops;
     d.part = 0;
     d.blksz = d.opsize = blk_ops_size(S_);
+    d.tsz = blk_t_size(S_);
     return d;
   }
 
@@ -3181,15 +3252,20 @@ class RbcProblem : public ProblemImpl {
   typedef void (*KaFn)(RbcDev, KaArgs);
   KfFn kfwd_fn() const { return stream_solve_ ? rbc_kfwd<true> : rbc_kfwd<false>; }
   KaFn kadj_fn() const { return stream_solve_ ? rbc_kadj<true> : rbc_kadj<false>; }
+  // bytes of the stage kernels' phase buffers before the solve (from the union's start)
+  size_t kf_pre() const {
+    return sizeof(cplx) * (3 * S_ + 6 * half_nodes(Ngz_) + 6 * N_) + sizeof(double) * 4 * Ngz_;
+  }
+  size_t ka_pre() const {
+    return sizeof(double) * 4 * Ngz_ + sizeof(cplx) * (2 * S_ + 12 * half_nodes(Ngz_) + 9 * N_);
+  }
   size_t kf_lds() const {
-    const size_t pre = sizeof(cplx) * (3 * S_ + 6 * half_nodes(Ngz_) + 6 * N_) + sizeof(double) * 4 * Ngz_;
     const size_t post = sizeof(double) * 4 * Ngz_ + sizeof(cplx) * 3 * N_;
-    return sizeof(cplx) * (2 * S_ + SPS_PAD) + std::max({pre, post, ops_bytes()});
+    return sizeof(cplx) * (2 * S_ + SPS_PAD) + std::max({kf_pre(), post, ops_bytes()});
   }
   size_t ka_lds() const {
-    const size_t pre = sizeof(double) * 4 * Ngz_ + sizeof(cplx) * (2 * S_ + 12 * half_nodes(Ngz_) + 9 * N_);
     const size_t post = sizeof(double) * (4 * Ngz_ + 2 * NTK / 64) + sizeof(cplx) * (5 * S_ + 3 * N_);
-    return sizeof(cplx) * (2 * S_ + SPS_PAD) + std::max({pre, post, ops_bytes()});
+    return sizeof(cplx) * (2 * S_ + SPS_PAD) + std::max({ka_pre(), post, ops_bytes()});
   }
   size_t xf_lds() const { return sizeof(cplx) * (9 * K_ + 2 * fpad_size(4 * Ngx_) + Ngx_); }
   size_t xa_lds() const { return sizeof(cplx) * (12 * K_ + 2 * fpad_size(6 * Ngx_) + Ngx_); }
@@ -3840,9 +3916,6 @@ class RbcProblem : public ProblemImpl {
     dv_.twx = arena_.upload(twiddles(Ngx_), stream);
     dv_.twx1 = arena_.upload(twiddles(desc_.nx), stream);
     dv_.gram = arena_.upload(gram, stream);
-    std::vector<double> intw(N, 0.0);
-    for (int m = 0; m < N; m += 2) intw[m] = 1.0 / (1.0 - (double)m * m);
-    dv_.intw = arena_.upload(intw, stream);
   }
 
   void build_bands() {
@@ -3874,7 +3947,7 @@ class RbcProblem : public ProblemImpl {
       dv_.kab = arena_.upload(kab, stream);
     }
     SPS_REQUIRE(kl_ + SPS_BLK <= SPS_TW && SPS_BLK + kl_ + ku_ <= SPS_GW, "band too wide for the block solver");
-    SPS_REQUIRE(blk_ops_size(S_) <= 2 * SPS_OPS_REG * NTK && N_ <= SPS_WAVE, "nz too large for the staged block solver");
+    SPS_REQUIRE(N_ <= SPS_WAVE, "nz too large for the stage kernels");
     SPS_REQUIRE(S_ + SPS_PAD <= NTK && 4 * N_ + 28 <= NTK && 4 * Ngz_ <= NTK && 6 * half_nodes(Ngz_) <= NTK,
                 "nz too large for one state entry per thread");
     BM_ = arena_.upload(hb.BM, stream);
@@ -3941,14 +4014,26 @@ class RbcProblem : public ProblemImpl {
   void alloc_work() {
     const size_t st = (size_t)B_ * K_ * S_;
     zsize_ = (size_t)B_ * 6 * Ngz_ * K_;
+    dv_.tsz = blk_t_size(S_);   // the two partitions together have the same block count
     if (dv_.part) {
       const int m = dv_.part, n2 = S_ - m, nr = dv_.pnb[0] + dv_.pnt[0];
-      dv_.blksz = blk_ops_size(m) + blk_ops_size(n2);
+      dv_.tsz = blk_t_size(m) + blk_t_size(n2);
+      dv_.blksz = dv_.tsz + blk_g_size(m) + blk_g_size(n2);
       dv_.spk[0] = dv_.blksz;
       dv_.spk[1] = dv_.spk[0] + m * dv_.pnt[0] + n2 * dv_.pnb[0] + nr * nr;
       dv_.opsize = ((dv_.spk[1] + m * dv_.pnt[1] + n2 * dv_.pnb[1] + nr * nr) + 3) / 4 * 4;
     } else {
       dv_.blksz = dv_.opsize = blk_ops_size(S_);
+    }
+    if (!stream_solve_) {
+      // the staged solves: each thread's share of either set in registers, and the phase
+      // buffers below the early set (the forward solve's is the T blocks, the transposed one's
+      // the G blocks)
+      const size_t gsz = dv_.blksz - dv_.tsz;
+      SPS_REQUIRE((size_t)dv_.tsz <= 2 * SPS_OPS_REG_T * NTK && gsz <= 2 * SPS_OPS_REG_G * NTK,
+                  "nz too large for the staged block solver");
+      SPS_REQUIRE(kf_pre() <= sizeof(double) * gsz && ka_pre() <= sizeof(double) * dv_.tsz,
+                  "stage buffers overlap the staged operators");
     }
     ops_ = arena_.alloc<double>((size_t)B_ * K_ * dv_.opsize);
     dv_.ops = ops_;
