@@ -46,9 +46,12 @@ static_assert((SPS_TW * SPS_TS) % 4 == 0 && (SPS_BLK * SPS_GS) % 4 == 0, "block 
 // blocks t0 .. t1-1) or G (G blocks t0 .. t1-1): forward L sweep (t ascending) and U sweep
 // (t descending), transposed U^T sweep (t ascending) and L^T sweep (t descending).  One wave
 // per complex right-hand side: lanes 0-31 take the real parts, lanes 32-63 the imaginary parts
-// (element x at b[2x + part]), both halves reading the same operator entries.
+// (element x at b[2x + part]), both halves reading the same operator entries.  Entries at
+// nrow and beyond are read (the operators multiply them by zero, or copy them) but never
+// written, so a system whose rows are followed by another system's live rows can be solved
+// in place while that one is solved by another wave.
 // L sweep: output r = l/2, half h = l&1 sums columns 8h .. 8h+7 (l = lane within the half)
-__device__ inline void blk_L_range(const double* T, int t0, int t1, double* b) {
+__device__ inline void blk_L_range(const double* T, int t0, int t1, double* b, int nrow) {
   const int lane = lane_id(), l = lane & 31;
   const int r = l >> 1, h = l & 1;
   double* bc = b + (lane >> 5);
@@ -63,11 +66,11 @@ __device__ inline void blk_L_range(const double* T, int t0, int t1, double* b) {
     }
     double s = a0 + a1;
     s += dpp_xor1(s);
-    if (h == 0) bc[2 * (t * SPS_BLK + r)] = s;
+    if (h == 0 && t * SPS_BLK + r < nrow) bc[2 * (t * SPS_BLK + r)] = s;
   }
 }
 // U sweep: output i = l/4, quarter q = l&3 sums columns 9q .. 9q+8
-__device__ inline void blk_U_range(const double* G, int t0, int t1, double* b) {
+__device__ inline void blk_U_range(const double* G, int t0, int t1, double* b, int nrow) {
   const int lane = lane_id(), l = lane & 31;
   const int i = l >> 2, q = l & 3;
   double* bc = b + (lane >> 5);
@@ -84,12 +87,12 @@ __device__ inline void blk_U_range(const double* G, int t0, int t1, double* b) {
     double s = (a0 + a1) + a2;
     s += dpp_xor1(s);
     s += dpp_xor2(s);
-    if (q == 0) bc[2 * (t * SPS_BLK + i)] = s;
+    if (q == 0 && t * SPS_BLK + i < nrow) bc[2 * (t * SPS_BLK + i)] = s;
   }
 }
 // U^T sweep: output column c = l sums the BLK rows of its column; lanes l < GW - 32 also take
 // column l + 32 (the others compute a copy of column GW - 1 that they do not store)
-__device__ inline void blk_Ut_range(const double* G, int t0, int t1, double* b) {
+__device__ inline void blk_Ut_range(const double* G, int t0, int t1, double* b, int nrow) {
   const int lane = lane_id(), c = lane & 31, c2 = min(c + 32, SPS_GW - 1);
   double* bc = b + (lane >> 5);
   for (int t = t0; t < t1; ++t) {
@@ -106,12 +109,12 @@ __device__ inline void blk_Ut_range(const double* G, int t0, int t1, double* b) 
     }
     const double keep = (c >= SPS_BLK) ? v[2 * (c)] : 0.0;
     const double keep2 = v[2 * (c2)];
-    bc[2 * (t * SPS_BLK + c)] = keep + (a0 + a1);
-    if (c + 32 < SPS_GW) bc[2 * (t * SPS_BLK + c2)] = keep2 + (e0 + e1);
+    if (t * SPS_BLK + c < nrow) bc[2 * (t * SPS_BLK + c)] = keep + (a0 + a1);
+    if (c + 32 < SPS_GW && t * SPS_BLK + c2 < nrow) bc[2 * (t * SPS_BLK + c2)] = keep2 + (e0 + e1);
   }
 }
 // L^T sweep: output column c = l/2, half h = l&1 sums rows 8h .. 8h+7 of column c
-__device__ inline void blk_Lt_range(const double* T, int t0, int t1, double* b) {
+__device__ inline void blk_Lt_range(const double* T, int t0, int t1, double* b, int nrow) {
   const int lane = lane_id(), l = lane & 31;
   const int c = l >> 1, h = l & 1;
   double* bc = b + (lane >> 5);
@@ -126,7 +129,7 @@ __device__ inline void blk_Lt_range(const double* T, int t0, int t1, double* b) 
     }
     double s = a0 + a1;
     s += dpp_xor1(s);
-    if (h == 0) bc[2 * (t * SPS_BLK + c)] = s;
+    if (h == 0 && t * SPS_BLK + c < nrow) bc[2 * (t * SPS_BLK + c)] = s;
   }
 }
 // One system's block operators are brought into LDS in two steps so that their memory
@@ -371,60 +374,57 @@ __device__ inline void band_lu_solve_cols(const double* ab, const int* spiv, int
   __syncthreads();
 }
 
-// Inverse of the nr x nr matrix A (row-major, LDS; nr <= 32) into Ainv (global, row-major) by
-// Gauss-Jordan elimination with partial pivoting on [A | I] in LDS (aug: nr x 2nr doubles);
-// wave 0, lane c owns column c of the augmented matrix.  Block-wide (ends with a barrier).
-__device__ inline void small_inverse(const double* A, int nr, double* aug, double* Ainv, int* err) {
-  const int tid = threadIdx.x, w = 2 * nr;
+// Inverse of the nr x nr matrix A (row-major, LDS) into Ainv (global, row-major, or
+// column-major if colmajor) by
+// Gauss-Jordan elimination with partial pivoting on [A | I] in LDS (aug: nr x 2nr doubles, then
+// nr doubles of multipliers); sh: one int of LDS.  Block-wide (ends with a barrier).
+__device__ inline void block_inverse(const double* A, int nr, double* aug, double* Ainv, int* err, int* sh,
+                                     bool colmajor = false) {
+  const int tid = threadIdx.x, nt = blockDim.x, w = 2 * nr;
+  double* f = aug + (size_t)nr * w;
   __syncthreads();
-  for (int e = tid; e < nr * w; e += blockDim.x) {
+  for (int e = tid; e < nr * w; e += nt) {
     const int i = e / w, c = e - i * w;
     aug[e] = (c < nr) ? A[i * nr + c] : ((c - nr == i) ? 1.0 : 0.0);
   }
   __syncthreads();
-  if (tid < 64) {
-    const int lane = tid;
-    for (int j = 0; j < nr; ++j) {
-      // pivot row: largest |aug[i][j]|, i >= j (every lane scans the same column)
+  for (int j = 0; j < nr; ++j) {
+    if (tid == 0) {
       int p = j;
       double best = fabs(aug[j * w + j]);
       for (int i = j + 1; i < nr; ++i) {
         const double v = fabs(aug[i * w + j]);
-        if (v > best) { best = v; p = i; }
+        if (v > best) {
+          best = v;
+          p = i;
+        }
       }
-      if (!(best > 0.0) && lane == 0) atomicOr(err, 1);
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      for (int c = lane; c < w; c += 64) {
+      if (!(best > 0.0)) atomicOr(err, 1);
+      sh[0] = p;
+    }
+    __syncthreads();
+    const int p = sh[0];
+    if (p != j)
+      for (int c = tid; c < w; c += nt) {
         const double t = aug[j * w + c];
         aug[j * w + c] = aug[p * w + c];
         aug[p * w + c] = t;
       }
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      const double rinv = 1.0 / aug[j * w + j];
-      for (int c = lane; c < w; c += 64) aug[j * w + c] *= rinv;
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      for (int i = 0; i < nr; ++i) {
-        if (i == j) continue;
-        const double f = aug[i * w + j];
-        for (int c = lane; c < w; c += 64) {
-          if (c == j) continue;
-          aug[i * w + c] -= f * aug[j * w + c];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        if (lane == 0) aug[i * w + j] = 0.0;
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-      }
+    __syncthreads();
+    const double rinv = 1.0 / aug[j * w + j];
+    __syncthreads();
+    for (int c = tid; c < w; c += nt) aug[j * w + c] *= rinv;
+    for (int i = tid; i < nr; i += nt) f[i] = (i == j) ? 0.0 : aug[i * w + j];
+    __syncthreads();
+    for (int e = tid; e < nr * w; e += nt) {
+      const int i = e / w, c = e - i * w;
+      if (i != j) aug[e] -= f[i] * aug[j * w + c];
     }
+    __syncthreads();
   }
-  __syncthreads();
-  for (int e = tid; e < nr * nr; e += blockDim.x) {
+  for (int e = tid; e < nr * nr; e += nt) {
     const int i = e / nr, c = e - i * nr;
-    Ainv[e] = aug[i * w + nr + c];
+    Ainv[colmajor ? c * nr + i : e] = aug[i * w + nr + c];
   }
   __syncthreads();
 }

@@ -82,6 +82,12 @@ namespace {
 
 constexpr int NT = 256;   // threads per block of the grid-row, factor and set-up kernels
 constexpr int NTK = 512;  // threads per block of the per-wavenumber step kernels
+// Partitioned solves: at most SPS_MAXPART partitions; a row's spike entries (both couplings)
+// at most SPS_SPIKE_W; the coupled entries' system at most SPS_RED_MAX unknowns.
+constexpr int SPS_MAXPART = 4;
+constexpr int SPS_SPIKE_W = 24;
+constexpr int SPS_RED_MAX = 72;
+constexpr int SPS_CP_REG = 16;   // 16-byte loads per thread of the spike copy
 constexpr int NTX = 512;  // threads per block of the grid-row step kernels
 
 struct RbcDev {
@@ -115,12 +121,19 @@ struct RbcDev {
   int opsize;           // doubles per system (stride)
   int blksz;            // of which block operators (staged into LDS)
   int tsz;              // of which T blocks (the G blocks follow at tsz)
-  // Two-partition solve (part > 0, the staged path): the leading part rows and the trailing
-  // n - part rows have their own factors and block operators (T blocks of the leading rows,
-  // then of the trailing ones; G blocks likewise from tsz); spike set dir (0 forward,
-  // 1 transposed) at spk[dir]: V [part][pnt], W [n - part][pnb], the inverse of the coupled
-  // entries' system [nr][nr], nr = pnb + pnt (see rbc_solve_part).
-  int part, pnb[2], pnt[2], spk[2];
+  // Partitioned solve (the staged path): part = P > 1 partitions of rows [ps_p, ps_{p+1}),
+  // ps_0 = 0, ps_P = n, the starts multiples of 8.  Each partition has its own factors and
+  // block operators (its T blocks at block ps_p / 8 of the T set, its G blocks likewise).
+  // Direction dir (0 forward, 1 transposed) keeps at spk[dir] the spike rows [V_p | W_p] of
+  // every row i (column-major: entry c of row i at c n + i, so that a wave's rows load
+  // contiguously) and, at spk[dir] + rof[dir], the inverse of the coupled entries' system
+  // (nrr[dir] x nrr[dir], column-major).  smap[dir * n + i].y = row i's widths and
+  // coupled-entry offsets (see rbc_solve_part); coupled entry z of interface q (z >= zb_q) is
+  // the entry of row z + rsh_q.  pmeta holds the layout for the factor kernel.
+  int part, ps1, ps2, ps3;
+  int spk[2], rof[2], nrr[2], zb1[2], zb2[2], rsh0[2], rsh1[2], rsh2[2];
+  const int2* smap;
+  const int* pmeta;
   int* err;             // bit 0 singular pivot, bit 1 non-finite state
   // A batch of B instances of the problem (blockIdx.y = instance) that differ in their
   // Rayleigh number: per-instance nu and kappa (null for a single problem), factors and arrays
@@ -496,21 +509,15 @@ __device__ __forceinline__ void load_maps(const RbcDev& d, MapRegs& m) {
   m.rh = d.rho[i];
 }
 
-// With a two-partition solve the gathers also put the trailing rows (from d.part on) and their
-// zero tail into vB, where the second partition is solved.
-__device__ __forceinline__ void gather_store(const RbcDev& d, int i, cplx v, cplx* vA, cplx* vB) {
-  vA[i] = v;
-  if (d.part && i >= d.part) vB[i - d.part] = v;
-}
 // r (ABI row slots) -> vA (solver rows), zero tail.  Block-wide, ends with a barrier.
-__device__ void rbc_gather(const RbcDev& d, const MapRegs& m, const cplx* r, cplx* vA, cplx* vB) {
+__device__ void rbc_gather(const RbcDev& d, const MapRegs& m, const cplx* r, cplx* vA) {
   const int i = threadIdx.x;
   if (i < d.S) {
     const int s = m.gm & 0xffff;
     const cplx v = r[s];
-    gather_store(d, i, (m.gm >> 30) ? cmul_mi(v) : v, vA, vB);
+    vA[i] = (m.gm >> 30) ? cmul_mi(v) : v;
   } else if (i < d.S + SPS_PAD) {
-    gather_store(d, i, czero(), vA, vB);
+    vA[i] = czero();
   }
   __syncthreads();
 }
@@ -527,7 +534,7 @@ __device__ void rbc_scatter(const RbcDev& d, const MapRegs& m, const cplx* vA, c
   __syncthreads();
 }
 // g (ABI column slots) -> vA = (R^T D_c^H g)[colmap], zero tail.
-__device__ void rbc_gather_h(const RbcDev& d, const MapRegs& m, const cplx* g, cplx* vA, cplx* vB) {
+__device__ void rbc_gather_h(const RbcDev& d, const MapRegs& m, const cplx* g, cplx* vA) {
   const int i = threadIdx.x;
   if (i < d.S) {
     const int s = m.hm & 0xffff;
@@ -538,9 +545,9 @@ __device__ void rbc_gather_h(const RbcDev& d, const MapRegs& m, const cplx* g, c
       if ((m.hm >> 29) & 1) v2 = cmul_mi(v2);
       v = cadd(v, cscale(v2, m.hr));
     }
-    gather_store(d, i, v, vA, vB);
+    vA[i] = v;
   } else if (i < d.S + SPS_PAD) {
-    gather_store(d, i, czero(), vA, vB);
+    vA[i] = czero();
   }
   __syncthreads();
 }
@@ -576,14 +583,15 @@ __device__ __forceinline__ void stage_late(const RbcDev& d, const OpsRegs& r, do
   if (transposed) ops_store_part(r.t, d.tsz, s.T);
   else ops_store_part(r.g, d.blksz - d.tsz, s.G);
 }
-// The first and second sweeps of one wave's solve of the system whose operators start at T, G.
-__device__ __forceinline__ void sweep_first(const double* T, const double* G, int nblk, double* b, bool transposed) {
-  if (transposed) blk_Ut_range(G, 0, nblk, b);
-  else blk_L_range(T, 0, nblk, b);
+// The first and second sweeps of one wave's solve of the nrow-row system whose operators
+// start at T, G.
+__device__ __forceinline__ void sweep_first(const double* T, const double* G, int nrow, double* b, bool transposed) {
+  if (transposed) blk_Ut_range(G, 0, blk_count(nrow), b, nrow);
+  else blk_L_range(T, 0, blk_count(nrow), b, nrow);
 }
-__device__ __forceinline__ void sweep_second(const double* T, const double* G, int nblk, double* b, bool transposed) {
-  if (transposed) blk_Lt_range(T, 0, nblk, b);
-  else blk_U_range(G, 0, nblk, b);
+__device__ __forceinline__ void sweep_second(const double* T, const double* G, int nrow, double* b, bool transposed) {
+  if (transposed) blk_Lt_range(T, 0, blk_count(nrow), b, nrow);
+  else blk_U_range(G, 0, blk_count(nrow), b, nrow);
 }
 
 // Solve in place on vA (forward or transposed) with the early set already in LDS (stage_early
@@ -591,13 +599,12 @@ __device__ __forceinline__ void sweep_second(const double* T, const double* G, i
 // imaginary on 32-63) while the other waves write the late set.  Block-wide.
 __device__ void rbc_solve_staged(const RbcDev& d, const OpsRegs& regs, double* o, cplx* vA, bool transposed) {
   const StagedOps s = staged_ops(d, o, transposed);
-  const int nblk = blk_count(d.n);
   double* b = reinterpret_cast<double*>(vA);
   const bool solver = threadIdx.x < SPS_WAVE;
-  if (solver) sweep_first(s.T, s.G, nblk, b, transposed);
+  if (solver) sweep_first(s.T, s.G, d.n, b, transposed);
   stage_late(d, regs, o, transposed);
   __syncthreads();
-  if (solver) sweep_second(s.T, s.G, nblk, b, transposed);
+  if (solver) sweep_second(s.T, s.G, d.n, b, transposed);
   __syncthreads();
 }
 
@@ -643,90 +650,111 @@ __device__ void rbc_solve_streamed(const RbcDev& d, const double* gops, double* 
       range(q, &t0, &t1, &useT);
       double* b = reinterpret_cast<double*>(vA);
       if (!transposed) {
-        if (useT) blk_L_range(cur, t0, t1, b);
-        else blk_U_range(cur, t0, t1, b);
+        if (useT) blk_L_range(cur, t0, t1, b, d.n);
+        else blk_U_range(cur, t0, t1, b, d.n);
       } else {
-        if (useT) blk_Lt_range(cur, t0, t1, b);
-        else blk_Ut_range(cur, t0, t1, b);
+        if (useT) blk_Lt_range(cur, t0, t1, b, d.n);
+        else blk_Ut_range(cur, t0, t1, b, d.n);
       }
     }
     __syncthreads();
   }
 }
 
-// The staged solve in two partitions (d.part = m): wave 0 solves the leading m rows with their
-// own block operators, wave 1 the trailing n - m rows (in vB from the gather, zero tail), at the same
-// time, so the dependent chain is half as long.  With y1, y2 their solutions, the exact solution
-// is x1 = y1 - V x2[0:nt2], x2 = y2 - W x1[m-nb1:m] (V, W the precomputed spikes); the coupled
-// entries (x1[m-nb1:m], x2[0:nt2]) solve a small system whose inverse is precomputed.  The
-// transposed solve uses the transposed spikes.  The early set is in LDS (stage_early before the
-// last barrier); waves 2-7 write the late set and the inverse (after the operators) during the
-// first sweeps, waves 0-1 their share of the late set after them.  Block-wide; vA holds the
-// gathered right-hand side and gets the solution.
-__device__ void rbc_solve_part(const RbcDev& d, int k, const OpsRegs& regs, double* o, cplx* vA, cplx* vB,
+// The staged solve in P = d.part partitions (a SPIKE solve): wave p < P solves partition p's
+// rows in place in vA with that partition's own block operators (its sweeps never write past
+// its rows, and read the next partition's live rows only through zero operator columns), so
+// the P dependent chains run at the same time.  With y_p the partition solutions and V_p, W_p
+// the precomputed spikes (the partition's inverse applied to the columns that couple it to the
+// next and to the previous partition), the exact solution is
+// x_p = y_p - V_p c_p - W_p a_{p-1}, where a_q (the last entries of partition q) and c_q (the
+// first entries of partition q + 1) are the coupled entries of interface q; they solve a
+// small system R z = g whose right-hand side g is y at the coupled rows and whose inverse is
+// precomputed.  The transposed solve has its own spikes and system.  The early set is in LDS
+// (stage_early before the last barrier); the other waves write the late set during the first
+// sweeps, the solver waves theirs after them.  During the second sweeps the other waves copy
+// the spikes and the inverse into the early set's space (free once every first sweep is
+// done).  vB is scratch (the coupled entries).  Block-wide; vA holds the gathered right-hand
+// side and gets the solution.
+__device__ __forceinline__ void rbc_solve_part(const RbcDev& d, int k, const OpsRegs& regs, double* o, cplx* vA, cplx* vB,
                                bool transposed) {
-  const int tid = threadIdx.x, wave = tid >> 6, m = d.part, n = d.n, n2 = n - m, dir = transposed ? 1 : 0;
-  double* rinv = o + d.blksz;
-  const int nb1 = d.pnb[dir], nt2 = d.pnt[dir], nr = nb1 + nt2;
-  const double* sp = d.ops + (size_t)k * d.opsize + d.spk[dir];
-  // this thread's row of V (row tid < m) or of W (m <= tid < n), loaded during the sweeps
-  // (unconditional loads at clamped indices: the entries past the row are never used, and a
-  // load under a branch would make the compiler wait for every load in flight before the sweeps)
-  double vrow[16];
-  const int tr = min(tid, n - 1);
-  const double* vr = (tr < m) ? sp + (size_t)tr * nt2 : sp + (size_t)m * nt2 + (size_t)(tr - m) * nb1;
-  const int vc = (tr < m) ? nt2 : nb1;
-#pragma unroll
-  for (int c = 0; c < 16; ++c) vrow[c] = vr[min(c, vc - 1)];
+  const int tid = threadIdx.x, wave = tid >> 6, n = d.n, P = d.part, dir = transposed ? 1 : 0;
+  // this wave's partition (sums of differences rather than selects between fields: a select
+  // between two fields of the descriptor becomes a computed offset into it, which keeps a copy
+  // of the whole descriptor in scratch memory)
+  const int ps1 = d.ps1, ps2 = d.ps2, ps3 = d.ps3;
+  auto pstart = [&](int q) { return (q >= 1 ? ps1 : 0) + (q >= 2 ? ps2 - ps1 : 0) + (q >= 3 ? ps3 - ps2 : 0); };
+  const int p0 = pstart(wave), p1 = (wave + 1 >= P) ? n : pstart(wave + 1);
   const StagedOps s = staged_ops(d, o, transposed);
-  const int part = wave;
-  double* b = reinterpret_cast<double*>(part ? vB : vA);
-  const double* T = s.T + (part ? blk_t_size(m) : 0);
-  const double* G = s.G + (part ? blk_g_size(m) : 0);
-  const int nb = blk_count(part ? n2 : m);
-  if (wave < 2) sweep_first(T, G, nb, b, transposed);
+  const double* T = s.T + (p0 / SPS_BLK) * (SPS_TW * SPS_TS);
+  const double* G = s.G + (p0 / SPS_BLK) * (SPS_BLK * SPS_GS);
+  double* b = reinterpret_cast<double*>(vA + p0);
+  if (wave < P) sweep_first(T, G, p1 - p0, b, transposed);
   stage_late(d, regs, o, transposed);
-  if (wave >= 2) {
-    const double* ri = sp + (size_t)m * nt2 + (size_t)n2 * nb1;
-    for (int e = tid - 2 * SPS_WAVE; e < nr * nr; e += blockDim.x - 2 * SPS_WAVE) rinv[e] = ri[e];
+  __syncthreads();
+  // spikes (entry c of row i at c n + i) and the coupled system's inverse (column-major, at
+  // rof), copied from the factors to the early set's space
+  double* lsp = transposed ? s.G : s.T;
+  const int nr = d.nrr[dir];
+  if (wave < P) {
+    sweep_second(T, G, p1 - p0, b, transposed);
+  } else {
+    const double2* src = reinterpret_cast<const double2*>(d.ops + (size_t)k * d.opsize + d.spk[dir]);
+    double2* dst = reinterpret_cast<double2*>(lsp);
+    const int h = (d.rof[dir] + nr * nr + 1) / 2, t0 = tid - P * SPS_WAVE, nth = blockDim.x - P * SPS_WAVE;
+    double2 v[SPS_CP_REG];
+#pragma unroll
+    for (int i = 0; i < SPS_CP_REG; ++i) {
+      const double2* q = src + min(t0 + i * nth, h - 1);
+      v[i] = make_double2(q->x, q->y);
+    }
+#pragma unroll
+    for (int i = 0; i < SPS_CP_REG; ++i)
+      if (t0 + i * nth < h) dst[t0 + i * nth] = v[i];
   }
   __syncthreads();
-  if (wave < 2) sweep_second(T, G, nb, b, transposed);
-  __syncthreads();
-  cplx* zs = vA + n;   // the coupled entries, in the zero tail of vA
-  if (tid < 3 * SPS_WAVE) {
-    // row r = 8 wave + lane / 8 of the inverse times the coupled right-hand side: eight lanes
-    // per row take every eighth column, then sum over the eight
-    const int r = 8 * wave + ((tid & 63) >> 3), cc = tid & 7;
+  cplx* zs = vB;   // the coupled entries
+  const int zb1 = d.zb1[dir], zb2 = d.zb2[dir], rs0 = d.rsh0[dir], rs1 = d.rsh1[dir], rs2 = d.rsh2[dir];
+  const double* rinv = lsp + d.rof[dir];
+  // row r = tid / 4 of z = R^{-1} g, four lanes per row, every fourth column; no branches inside
+  // the sums (columns past the end read a valid entry and take a zero coefficient), in chunks
+  // of six so that several LDS reads are in flight together
+  const int r = tid >> 2, cc = tid & 3;
+  if (r < nr) {
     cplx z = czero();
-    if (r < nr) {
+    for (int c0 = cc; c0 < nr; c0 += 24) {
+      cplx g[6];
+      double rv[6];
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        const int c = cc + 8 * q;
-        if (c < nr) {
-          const cplx rv = (c < nb1) ? vA[m - nb1 + c] : vB[c - nb1];
-          z = cadd(z, cscale(rv, rinv[r * nr + c]));
-        }
+      for (int u = 0; u < 6; ++u) {
+        const int c = min(c0 + 4 * u, nr - 1);
+        g[u] = vA[c + rs0 + (c >= zb1 ? rs1 - rs0 : 0) + (c >= zb2 ? rs2 - rs1 : 0)];
+        rv[u] = rinv[c * nr + r];
       }
+#pragma unroll
+      for (int u = 0; u < 6; ++u) z = cadd(z, cscale(g[u], (c0 + 4 * u < nr) ? rv[u] : 0.0));
     }
-    for (int o = 1; o < 8; o <<= 1) {
-      z.x += __shfl_xor(z.x, o);
-      z.y += __shfl_xor(z.y, o);
-    }
-    if (r < nr && cc == 0) zs[r] = z;
+    z = group_sum<4>(z);
+    if (cc == 0) zs[r] = z;
   }
   __syncthreads();
-  if (tid < m) {
+  if (tid < n) {
+    const int sm = d.smap[dir * n + tid].y;
+    const int wV = sm & 31, wW = (sm >> 5) & 31, zV = (sm >> 10) & 127, zW = (sm >> 17) & 127;
+    const int w = wV + wW;
     cplx x = vA[tid];
+    for (int c0 = 0; c0 < w; c0 += 6) {
+      cplx g[6];
+      double sv[6];
 #pragma unroll
-    for (int c = 0; c < 16; ++c)
-      if (c < nt2) x = csub(x, cscale(zs[nb1 + c], vrow[c]));
-    vA[tid] = x;
-  } else if (tid < n) {
-    cplx x = vB[tid - m];
+      for (int u = 0; u < 6; ++u) {
+        const int c = min(c0 + u, w - 1);
+        g[u] = zs[(c < wV) ? zV + c : zW + c - wV];
+        sv[u] = lsp[c * n + tid];
+      }
 #pragma unroll
-    for (int c = 0; c < 16; ++c)
-      if (c < nb1) x = csub(x, cscale(zs[c], vrow[c]));
+      for (int u = 0; u < 6; ++u) x = csub(x, cscale(g[u], (c0 + u < w) ? sv[u] : 0.0));
+    }
     vA[tid] = x;
   }
   __syncthreads();
@@ -958,7 +986,7 @@ __global__ void __launch_bounds__(NTK) rbc_kfwd(RbcDev d, KfArgs a) {
     __syncthreads();
   } else {
     if (!STREAM) stage_early(d, opsr, reinterpret_cast<double*>(un), false);
-    rbc_gather(d, mr, rr, vA, vB);
+    rbc_gather(d, mr, rr, vA);
     rbc_solve<STREAM>(d, k, opsr, reinterpret_cast<double*>(un), vA, vB, false);
     rbc_scatter(d, mr, vA, vB, vA);   // vA <- new state (ABI slots)
     if (tid < S) {
@@ -1574,7 +1602,7 @@ __global__ void __launch_bounds__(NTK) rbc_kadj(RbcDev d, KaArgs a) {
     if (sl) xbar[tid] = xin;
     __syncthreads();
     if (!STREAM) stage_early(d, opsr, ops, true);
-    rbc_gather_h(d, mr, xbar, vA, vB);
+    rbc_gather_h(d, mr, xbar, vA);
     rbc_solve<STREAM>(d, k, opsr, ops, vA, vB, true);
     rbc_scatter_h(d, mr, vA, vB);
     if (sl) a.Xb_out[ks] = vB[tid];
@@ -1613,7 +1641,7 @@ __global__ void __launch_bounds__(NTK) rbc_kadj(RbcDev d, KaArgs a) {
   }
   // Y_m = (M + dt H_mm L)^{-H} xbar
   if (!STREAM) stage_early(d, opsr, ops, true);
-  rbc_gather_h(d, mr, xbar, vA, vB);
+  rbc_gather_h(d, mr, xbar, vA);
   rbc_solve<STREAM>(d, k, opsr, ops, vA, vB, true);
   rbc_scatter_h(d, mr, vA, vB);       // vB = Y_m
   if (tid < 4 * Ngz) ct[tid] = cosr;
@@ -1651,15 +1679,23 @@ __global__ void __launch_bounds__(NT) rbc_factor(RbcDev d, const double* BM, con
     band_factor_block(BM + ko, BL + ko, am, bl, d.n, d.kl, d.ku, smem_d, sh, spiv, O, d.err, bnu, bka, nu, ka);
     return;
   }
-  // Two partitions: the factors and block operators of the leading m x m and trailing
-  // n2 x n2 diagonal blocks, their spikes (the solves of each block with the columns that
-  // couple it to the other, for A and for A^T), and the inverses of the coupled entries' systems.
-  const int m = d.part, n2 = d.n - m, mx = max(m, n2);
+  // P partitions: each partition's factors and block operators, its spikes (its factors solved
+  // with the columns that couple it to the next and to the previous partition, for A and for
+  // A^T), then the inverses of the coupled entries' systems.  Layout from pmeta: per partition
+  // p (8 ints): start, rows, then per direction the widths of V_p and W_p (and a spare int);
+  // per interface q (6 ints at 8 SPS_MAXPART): per direction the widths of a_q (last entries
+  // of partition q) and c_q (first entries of partition q + 1) and their offset in the
+  // coupled system.  Spike entry c of row i at c n + i; inverses column-major.
+  const int P = d.part;
+  const int* pm = d.pmeta;
+  int mx = 0;
+  for (int p = 0; p < P; ++p) mx = max(mx, pm[8 * p + 1]);
   double* ab = smem_d;                                                   // mx * ldab
   int* spiv = reinterpret_cast<int*>(ab + (size_t)mx * ldab);            // mx
-  double* R = ab + (size_t)mx * ldab + ((mx + 1) & ~1) / 2 + 1;          // mx * 16
-  double* Rm = R + (size_t)mx * 16;                                      // 24 * 24
-  double* aug = Rm + 24 * 24;                                            // 24 * 48
+  double* R = ab + (size_t)mx * ldab + ((mx + 1) & ~1) / 2 + 1;          // mx * SPS_SPIKE_W
+  double* Rm = R + (size_t)mx * SPS_SPIKE_W;                             // nr * nr
+  const int nrm = max(d.nrr[0], d.nrr[1]);
+  double* aug = Rm + (size_t)nrm * nrm;                                  // nr * (2 nr + 1)
   auto Aat = [&](int i, int c) -> double {   // entry (i, c) of a M + b L of the whole system
     const int q = c - i + d.kl;
     if (q < 0 || q >= bw) return 0.0;
@@ -1667,48 +1703,57 @@ __global__ void __launch_bounds__(NT) rbc_factor(RbcDev d, const double* BM, con
     const double l = BLnu ? BL[e] + nu * BLnu[e] + ka * BLka[e] : BL[e];
     return am * BM[e] + bl * l;
   };
-  band_lu_factor(BM + ko, BL + ko, am, bl, m, d.kl, d.ku, ab, sh, spiv, d.err, bnu, bka, nu, ka);
-  band_condense(ab, spiv, m, d.kl, d.ku, O, O + d.tsz);
-  for (int dir = 0; dir < 2; ++dir) {
-    const int nt2 = d.pnt[dir];
-    // V = A1^{-1} A[0:m, m:m+nt2] (forward) or A1^{-T} A^T[0:m, m:m+nt2] (transposed)
-    for (int e = tid; e < m * nt2; e += blockDim.x) {
-      const int i = e / nt2, c = e - i * nt2;
-      R[e] = dir ? Aat(m + c, i) : Aat(i, m + c);
+  for (int p = 0; p < P; ++p) {
+    const int s0 = pm[8 * p], np = pm[8 * p + 1], s1 = s0 + np;
+    band_lu_factor(BM + ko + (size_t)s0 * bw, BL + ko + (size_t)s0 * bw, am, bl, np, d.kl, d.ku, ab, sh, spiv, d.err,
+                   bnu ? bnu + (size_t)s0 * bw : nullptr, bka ? bka + (size_t)s0 * bw : nullptr, nu, ka);
+    band_condense(ab, spiv, np, d.kl, d.ku, O + (s0 / SPS_BLK) * (SPS_TW * SPS_TS),
+                  O + d.tsz + (s0 / SPS_BLK) * (SPS_BLK * SPS_GS));
+    for (int dir = 0; dir < 2; ++dir) {
+      const int wV = pm[8 * p + 2 + 3 * dir], wW = pm[8 * p + 3 + 3 * dir], w = wV + wW;
+      // columns c < wV: the first wV columns of partition p + 1; then the last wW of p - 1
+      // (of A, or of A^T for the transposed direction)
+      for (int e = threadIdx.x; e < np * w; e += blockDim.x) {
+        const int i = e / w, c = e - i * w;
+        const int col = (c < wV) ? s1 + c : s0 - wW + (c - wV);
+        R[e] = dir ? Aat(col, s0 + i) : Aat(s0 + i, col);
+      }
+      band_lu_solve_cols(ab, spiv, np, d.kl, d.ku, R, w, dir == 1);
+      double* out = O + (dir ? d.spk[1] : d.spk[0]) + s0;
+      for (int e = threadIdx.x; e < np * w; e += blockDim.x) {
+        const int i = e / w, c = e - i * w;
+        out[(size_t)c * d.n + i] = R[e];
+      }
+      __syncthreads();   // R is refilled next
     }
-    band_lu_solve_cols(ab, spiv, m, d.kl, d.ku, R, nt2, dir == 1);
-    double* V = O + d.spk[dir];
-    for (int e = tid; e < m * nt2; e += blockDim.x) V[e] = R[e];
   }
-  __syncthreads();
-  band_lu_factor(BM + ko + (size_t)m * bw, BL + ko + (size_t)m * bw, am, bl, n2, d.kl, d.ku, ab, sh, spiv, d.err,
-                 bnu ? bnu + (size_t)m * bw : nullptr, bka ? bka + (size_t)m * bw : nullptr, nu, ka);
-  band_condense(ab, spiv, n2, d.kl, d.ku, O + blk_t_size(m), O + d.tsz + blk_g_size(m));
   for (int dir = 0; dir < 2; ++dir) {
-    const int nb1 = d.pnb[dir], nt2 = d.pnt[dir];
-    // W = A2^{-1} A[m:n, m-nb1:m] (forward) or A2^{-T} A^T[m:n, m-nb1:m] (transposed)
-    for (int e = tid; e < n2 * nb1; e += blockDim.x) {
-      const int i = e / nb1, c = e - i * nb1;
-      R[e] = dir ? Aat(m - nb1 + c, m + i) : Aat(m + i, m - nb1 + c);
+    const int nr = dir ? d.nrr[1] : d.nrr[0];
+    const double* spd = O + (dir ? d.spk[1] : d.spk[0]);
+    for (int e = threadIdx.x; e < nr * nr; e += blockDim.x) Rm[e] = (e / nr == e % nr) ? 1.0 : 0.0;
+    __syncthreads();
+    // R z = g: a_q + V_q c_q + W_q a_{q-1} (rows of a_q, the last entries of partition q) and
+    // c_q + V_{q+1} c_{q+1} + W_{q+1} a_q (rows of c_q, the first entries of partition q + 1)
+    for (int q = 0; q + 1 < P; ++q) {
+      const int* im = pm + 8 * SPS_MAXPART + 6 * q + 3 * dir;
+      const int la = im[0], lc = im[1], zo = im[2];
+      for (int side = 0; side < 2; ++side) {
+        const int p = q + side;   // the partition whose rows these are
+        const int* ppm = pm + 8 * p;
+        const int np = ppm[1], wV = ppm[2 + 3 * dir], wW = ppm[3 + 3 * dir], w = wV + wW;
+        const int nrow = side ? lc : la, row0 = side ? 0 : np - la, zrow = side ? zo + la : zo;
+        // coupled-system columns of the spike columns: V_p -> c_p, W_p -> a_{p-1}
+        const int zc = (p + 1 < P) ? pm[8 * SPS_MAXPART + 6 * p + 3 * dir + 2] + pm[8 * SPS_MAXPART + 6 * p + 3 * dir] : 0;
+        const int za = (p > 0) ? pm[8 * SPS_MAXPART + 6 * (p - 1) + 3 * dir + 2] : 0;
+        const double* rows = spd + ppm[0] + row0;   // spike entry c of the partition's row row0 + t
+        for (int e = threadIdx.x; e < nrow * w; e += blockDim.x) {
+          const int t = e / w, c = e - t * w;
+          const int col = (c < wV) ? zc + c : za + (c - wV);
+          Rm[(size_t)(zrow + t) * nr + col] = rows[(size_t)c * d.n + t];
+        }
+      }
     }
-    band_lu_solve_cols(ab, spiv, n2, d.kl, d.ku, R, nb1, dir == 1);
-    double* W = O + d.spk[dir] + (size_t)m * nt2;
-    for (int e = tid; e < n2 * nb1; e += blockDim.x) W[e] = R[e];
-  }
-  __syncthreads();
-  for (int dir = 0; dir < 2; ++dir) {
-    const int nb1 = d.pnb[dir], nt2 = d.pnt[dir], nr = nb1 + nt2;
-    const double* V = O + d.spk[dir];
-    const double* W = V + (size_t)m * nt2;
-    // [I, V[m-nb1:m, :]; W[0:nt2, :], I] acting on (x1[m-nb1:m], x2[0:nt2])
-    for (int e = tid; e < nr * nr; e += blockDim.x) {
-      const int r = e / nr, c = e - r * nr;
-      double v;
-      if (r < nb1) v = (c < nb1) ? (r == c ? 1.0 : 0.0) : V[(size_t)(m - nb1 + r) * nt2 + (c - nb1)];
-      else v = (c < nb1) ? W[(size_t)(r - nb1) * nb1 + c] : (r == c ? 1.0 : 0.0);
-      Rm[e] = v;
-    }
-    small_inverse(Rm, nr, aug, O + d.spk[dir] + (size_t)m * nt2 + (size_t)n2 * nb1, d.err);
+    block_inverse(Rm, nr, aug, O + (dir ? d.spk[1] + d.rof[1] : d.spk[0] + d.rof[0]), d.err, sh, true);
   }
 }
 
@@ -3235,16 +3280,16 @@ class RbcProblem : public ProblemImpl {
     const size_t ldab = 2 * kl_ + ku_ + 1;
     const size_t whole = ldab * S_ * sizeof(double) + sizeof(int) * S_;
     if (!dv_.part) return whole;
-    const size_t mx = std::max(dv_.part, S_ - dv_.part);
-    const size_t partd = mx * ldab + (mx + 1) / 2 + 1 + mx * 16 + 24 * 24 + 24 * 48;
+    size_t mx = 0;
+    for (int p = 0; p < dv_.part; ++p) mx = std::max<size_t>(mx, pmeta_h_[8 * p + 1]);
+    const size_t nr = std::max(dv_.nrr[0], dv_.nrr[1]);
+    const size_t partd = mx * ldab + (mx + 1) / 2 + 1 + mx * SPS_SPIKE_W + nr * nr + nr * (2 * nr + 1);
     return std::max(whole, partd * sizeof(double));
   }
   // staged solves hold a system's block operators in LDS; streamed ones two chunk buffers
   size_t ops_bytes() const {
     if (stream_solve_) return sizeof(double) * 2 * (size_t)SOLVE_CHUNK_D;
-    // staged: the block operators, and the coupled entries' inverse after them (partitioned)
-    const int nr = dv_.part ? dv_.pnb[0] + dv_.pnt[0] : 0;
-    return sizeof(double) * ((size_t)dv_.blksz + (size_t)nr * nr);
+    return sizeof(double) * (size_t)dv_.blksz;
   }
   // launches with many more systems than CUs stream the operators (several blocks per CU);
   // smaller ones stage them whole (one block per CU, shortest dependent chain)
@@ -3978,23 +4023,27 @@ class RbcProblem : public ProblemImpl {
     dv_.sflag = arena_.upload(sflag, stream);
   }
 
-  // The staged path solves in two partitions when the systems allow it: split at
-  // m = 8 ceil(nblk / 2), coupling widths from the band pattern (the columns >= m that rows < m
-  // reach, cu, and the columns < m that rows >= m reach, cl; over every wavenumber and, for a
-  // batch, every part of L), the trailing rows and their zero tail fitting vB.
+  // The staged path solves in P = 4, 3 or 2 partitions of whole 8-row blocks (spread as evenly
+  // as possible), the most that the couplings allow: from the band pattern (over every
+  // wavenumber and, for a batch, every part of L), rows of a partition may reach only the
+  // neighbouring partitions, each interface's widths (cu: columns of the next partition that
+  // rows above reach, cl: columns of the previous partition that rows below reach) at most 16,
+  // a row's spike entries at most SPS_SPIKE_W and the coupled system at most SPS_RED_MAX
+  // unknowns (and no more than S, its scratch).
   void plan_partition(const RbcHostBands& hb) {
     dv_.part = 0;
-    const int nblk = blk_count(S_), m = SPS_BLK * ((nblk + 1) / 2), n2 = S_ - m, bw = kl_ + ku_ + 1;
-    if (stream_solve_ || n2 + SPS_PAD > S_ || m < 16) return;
-    int cu = 0, cl = 0;
+    if (stream_solve_) return;
+    const int nblk = blk_count(S_), bw = kl_ + ku_ + 1;
+    // the columns each row reaches
+    std::vector<int> cmin(S_, S_), cmax(S_, -1);
     auto scan = [&](const std::vector<double>& band) {
       for (int k = 0; k < K_; ++k)
         for (int i = 0; i < S_; ++i)
           for (int q = 0; q < bw; ++q) {
             const int c = i + q - kl_;
             if (c < 0 || c >= S_ || band[((size_t)k * S_ + i) * bw + q] == 0.0) continue;
-            if (i < m && c >= m) cu = std::max(cu, c - m + 1);
-            if (i >= m && c < m) cl = std::max(cl, m - c);
+            cmin[i] = std::min(cmin[i], c);
+            cmax[i] = std::max(cmax[i], c);
           }
     };
     scan(hb.BM);
@@ -4003,27 +4052,116 @@ class RbcProblem : public ProblemImpl {
       scan(blnu_h_);
       scan(blka_h_);
     }
-    if (cu > 16 || cl > 16 || cu + cl > 24) return;
-    dv_.part = m;
-    dv_.pnb[0] = cl;   // forward: x1[m-cl:m] couple to partition 2, x2[0:cu] to partition 1
-    dv_.pnt[0] = cu;
-    dv_.pnb[1] = cu;   // transposed
-    dv_.pnt[1] = cl;
+    for (int P = SPS_MAXPART; P >= 2; --P) {
+      if (nblk < 2 * P) continue;
+      std::vector<int> st(P + 1, 0);
+      for (int p = 0; p < P; ++p) st[p + 1] = st[p] + SPS_BLK * (nblk / P + (p < nblk % P ? 1 : 0));
+      st[P] = S_;
+      auto part_of = [&](int i) {
+        int p = 0;
+        while (p + 1 < P && i >= st[p + 1]) ++p;
+        return p;
+      };
+      // interface q's widths for A (cu: columns of partition q + 1 that rows of q reach;
+      // cl: columns of q that rows of q + 1 reach) and for A^T (cut: rows of q + 1 that reach
+      // back into q; clt: rows of q that reach into q + 1)
+      std::vector<int> cu(P - 1, 0), cl(P - 1, 0), cut(P - 1, 0), clt(P - 1, 0);
+      bool ok = true;
+      for (int i = 0; i < S_ && ok; ++i) {
+        if (cmax[i] < 0) continue;
+        const int pi = part_of(i), plo = part_of(cmin[i]), phi = part_of(cmax[i]);
+        if (plo < pi - 1 || phi > pi + 1) ok = false;
+        if (phi == pi + 1) {
+          cu[pi] = std::max(cu[pi], cmax[i] - st[pi + 1] + 1);
+          clt[pi] = std::max(clt[pi], st[pi + 1] - i);
+        }
+        if (plo == pi - 1) {
+          cl[pi - 1] = std::max(cl[pi - 1], st[pi] - cmin[i]);
+          cut[pi - 1] = std::max(cut[pi - 1], i - st[pi] + 1);
+        }
+      }
+      if (!ok) continue;
+      int nr0 = 0, nr1 = 0;
+      for (int q = 0; q + 1 < P; ++q) {
+        if (std::max({cu[q], cl[q], cut[q], clt[q]}) > 16) ok = false;
+        nr0 += cu[q] + cl[q];
+        nr1 += cut[q] + clt[q];
+      }
+      for (int p = 0; p < P; ++p) {
+        const int w0 = (p + 1 < P ? cu[p] : 0) + (p > 0 ? cl[p - 1] : 0);
+        const int w1 = (p + 1 < P ? cut[p] : 0) + (p > 0 ? clt[p - 1] : 0);
+        if (std::max(w0, w1) > SPS_SPIKE_W || w0 == 0 || w1 == 0) ok = false;
+      }
+      const int nr = std::max(nr0, nr1);
+      if (!ok || nr > SPS_RED_MAX || nr > S_) continue;
+      // each direction's spikes (the widest partition's columns at stride S, rounded to 4) and
+      // inverse must fit the space of the early set of its solve (the T blocks for the forward
+      // solve, the G blocks for the transposed one) and the copy's loads
+      int wmax[2] = {0, 0};
+      for (int p = 0; p < P; ++p) {
+        wmax[0] = std::max(wmax[0], (p + 1 < P ? cu[p] : 0) + (p > 0 ? cl[p - 1] : 0));
+        wmax[1] = std::max(wmax[1], (p + 1 < P ? cut[p] : 0) + (p > 0 ? clt[p - 1] : 0));
+      }
+      const int area0 = (wmax[0] * S_ + 3) / 4 * 4 + nr0 * nr0, area1 = (wmax[1] * S_ + 3) / 4 * 4 + nr1 * nr1;
+      const int cap = SPS_CP_REG * 2 * (NTK - SPS_WAVE * P);
+      if (area0 > blk_t_size(S_) || area1 > blk_g_size(S_) || area0 + 1 > cap || area1 + 1 > cap) continue;
+      // accepted: descriptor fields and the tables of both directions
+      dv_.part = P;
+      dv_.ps1 = st[1];
+      dv_.ps2 = P > 2 ? st[2] : S_;
+      dv_.ps3 = P > 3 ? st[3] : S_;
+      pmeta_h_.assign(8 * SPS_MAXPART + 6 * (SPS_MAXPART - 1), 0);
+      smap_h_.assign(2 * (size_t)S_, int2{0, 0});
+      for (int dir = 0; dir < 2; ++dir) {
+        std::vector<int> la(P - 1), lc(P - 1), zo(P, 0);
+        for (int q = 0; q + 1 < P; ++q) {
+          la[q] = dir ? clt[q] : cl[q];   // last entries of partition q
+          lc[q] = dir ? cut[q] : cu[q];   // first entries of partition q + 1
+          zo[q + 1] = zo[q] + la[q] + lc[q];
+          int* im = &pmeta_h_[8 * SPS_MAXPART + 6 * q + 3 * dir];
+          im[0] = la[q];
+          im[1] = lc[q];
+          im[2] = zo[q];
+        }
+        int off = 0;
+        for (int p = 0; p < P; ++p) {
+          const int np = st[p + 1] - st[p];
+          const int wV = (p + 1 < P) ? lc[p] : 0, wW = (p > 0) ? la[p - 1] : 0, w = wV + wW;
+          const int zV = wV ? zo[p] + la[p] : 0, zW = wW ? zo[p - 1] : 0;
+          int* pm = &pmeta_h_[8 * p];
+          pm[0] = st[p];
+          pm[1] = np;
+          pm[2 + 3 * dir] = wV;
+          pm[3 + 3 * dir] = wW;
+          for (int i = st[p]; i < st[p + 1]; ++i)
+            smap_h_[(size_t)dir * S_ + i] = int2{0, wV | (wW << 5) | (zV << 10) | (zW << 17)};
+          off = std::max(off, (w * S_ + 3) / 4 * 4);   // column-major at stride S (the widest partition)
+        }
+        const int big = 1 << 20;
+        dv_.rof[dir] = off;
+        dv_.nrr[dir] = dir ? nr1 : nr0;
+        dv_.zb1[dir] = P > 2 ? zo[1] : big;
+        dv_.zb2[dir] = P > 3 ? zo[2] : big;
+        dv_.rsh0[dir] = st[1] - la[0] - zo[0];
+        dv_.rsh1[dir] = P > 2 ? st[2] - la[1] - zo[1] : 0;
+        dv_.rsh2[dir] = P > 3 ? st[3] - la[2] - zo[2] : 0;
+      }
+      return;
+    }
   }
 
   void alloc_work() {
     const size_t st = (size_t)B_ * K_ * S_;
     zsize_ = (size_t)B_ * 6 * Ngz_ * K_;
-    dv_.tsz = blk_t_size(S_);   // the two partitions together have the same block count
+    // (partitions start at whole blocks: together they have the whole system's block count)
+    dv_.tsz = blk_t_size(S_);
+    dv_.blksz = dv_.opsize = blk_ops_size(S_);
     if (dv_.part) {
-      const int m = dv_.part, n2 = S_ - m, nr = dv_.pnb[0] + dv_.pnt[0];
-      dv_.tsz = blk_t_size(m) + blk_t_size(n2);
-      dv_.blksz = dv_.tsz + blk_g_size(m) + blk_g_size(n2);
       dv_.spk[0] = dv_.blksz;
-      dv_.spk[1] = dv_.spk[0] + m * dv_.pnt[0] + n2 * dv_.pnb[0] + nr * nr;
-      dv_.opsize = ((dv_.spk[1] + m * dv_.pnt[1] + n2 * dv_.pnb[1] + nr * nr) + 3) / 4 * 4;
-    } else {
-      dv_.blksz = dv_.opsize = blk_ops_size(S_);
+      dv_.spk[1] = dv_.spk[0] + (dv_.rof[0] + dv_.nrr[0] * dv_.nrr[0] + 3) / 4 * 4;
+      dv_.opsize = (dv_.spk[1] + dv_.rof[1] + dv_.nrr[1] * dv_.nrr[1] + 3) / 4 * 4;
+      dv_.smap = arena_.upload(smap_h_, stream);
+      dv_.pmeta = arena_.upload(pmeta_h_, stream);
     }
     if (!stream_solve_) {
       // the staged solves: each thread's share of either set in registers, and the phase
@@ -4091,6 +4229,8 @@ class RbcProblem : public ProblemImpl {
   std::vector<double> rab_;          // a batch's Rayleigh numbers (empty: a single problem)
   const double *BLnu_ = nullptr, *BLka_ = nullptr;   // a batch's nu and kappa parts of L
   std::vector<double> blnu_h_, blka_h_;               // (host copies, for the partition's coupling widths)
+  std::vector<int> pmeta_h_;                          // partitioned solve: factor-kernel layout
+  std::vector<int2> smap_h_;                          // partitioned solve: per-row spike offsets and widths
   const double2* frame_ = nullptr;   // plane Couette: unit wave vector of each mode   // grid rows of 64 wave_r1_ points use the one-wave-per-FFT kernels
   std::vector<double> kxs_;
   std::vector<unsigned char> ckeep_;
