@@ -679,6 +679,7 @@ __device__ void rbc_solve_streamed(const RbcDev& d, const double* gops, double* 
 __device__ __forceinline__ void rbc_solve_part(const RbcDev& d, int k, const OpsRegs& regs, double* o, cplx* vA, cplx* vB,
                                bool transposed) {
   const int tid = threadIdx.x, wave = tid >> 6, n = d.n, P = d.part, dir = transposed ? 1 : 0;
+  const int sm = d.smap[dir * n + min(tid, n - 1)].y;   // this row's spike widths (used last)
   // this wave's partition (sums of differences rather than selects between fields: a select
   // between two fields of the descriptor becomes a computed offset into it, which keeps a copy
   // of the whole descriptor in scratch memory)
@@ -739,7 +740,6 @@ __device__ __forceinline__ void rbc_solve_part(const RbcDev& d, int k, const Ops
   }
   __syncthreads();
   if (tid < n) {
-    const int sm = d.smap[dir * n + tid].y;
     const int wV = sm & 31, wW = (sm >> 5) & 31, zV = (sm >> 10) & 127, zW = (sm >> 17) & 127;
     const int w = wV + wW;
     cplx x = vA[tid];
