@@ -124,12 +124,13 @@ struct RbcDev {
   // Partitioned solve (the staged path): part = P > 1 partitions of rows [ps_p, ps_{p+1}),
   // ps_0 = 0, ps_P = n, the starts multiples of 8.  Each partition has its own factors and
   // block operators (its T blocks at block ps_p / 8 of the T set, its G blocks likewise).
-  // Direction dir (0 forward, 1 transposed) keeps at spk[dir] the spike rows [V_p | W_p] of
-  // every row i (column-major: entry c of row i at c n + i, so that a wave's rows load
-  // contiguously) and, at spk[dir] + rof[dir], the inverse of the coupled entries' system
-  // (nrr[dir] x nrr[dir], column-major).  smap[dir * n + i].y = row i's widths and
-  // coupled-entry offsets (see rbc_solve_part); coupled entry z of interface q (z >= zb_q) is
-  // the entry of row z + rsh_q.  pmeta holds the layout for the factor kernel.
+  // Direction dir (0 forward, 1 transposed) keeps at spk[dir] each partition's spike rows
+  // [V_p | W_p] (column-major within the partition: entry c of its row t at c n_p + t, so that
+  // a wave's rows load contiguously) and, at spk[dir] + rof[dir], the inverse of the coupled
+  // entries' system (nrr[dir] x nrr[dir], column-major).  smap[dir * n + i] = {offset of row
+  // i's first entry | n_p << 16, its widths and coupled-entry offsets} (see rbc_solve_part);
+  // coupled entry z of interface q (z >= zb_q) is the entry of row z + rsh_q.  pmeta holds the
+  // layout for the factor kernel.
   int part, ps1, ps2, ps3;
   int spk[2], rof[2], nrr[2], zb1[2], zb2[2], rsh0[2], rsh1[2], rsh2[2];
   const int2* smap;
@@ -679,7 +680,8 @@ __device__ void rbc_solve_streamed(const RbcDev& d, const double* gops, double* 
 __device__ __forceinline__ void rbc_solve_part(const RbcDev& d, int k, const OpsRegs& regs, double* o, cplx* vA, cplx* vB,
                                bool transposed) {
   const int tid = threadIdx.x, wave = tid >> 6, n = d.n, P = d.part, dir = transposed ? 1 : 0;
-  const int sm = d.smap[dir * n + min(tid, n - 1)].y;   // this row's spike widths (used last)
+  const int2 sm2 = d.smap[dir * n + min(tid, n - 1)];   // this row's spike layout (used last)
+  const int sm = sm2.y, soff = sm2.x & 0xffff, sstr = sm2.x >> 16;
   // this wave's partition (sums of differences rather than selects between fields: a select
   // between two fields of the descriptor becomes a computed offset into it, which keeps a copy
   // of the whole descriptor in scratch memory)
@@ -750,7 +752,7 @@ __device__ __forceinline__ void rbc_solve_part(const RbcDev& d, int k, const Ops
       for (int u = 0; u < 6; ++u) {
         const int c = min(c0 + u, w - 1);
         g[u] = zs[(c < wV) ? zV + c : zW + c - wV];
-        sv[u] = lsp[c * n + tid];
+        sv[u] = lsp[soff + c * sstr];
       }
 #pragma unroll
       for (int u = 0; u < 6; ++u) x = csub(x, cscale(g[u], (c0 + u < w) ? sv[u] : 0.0));
@@ -1682,10 +1684,10 @@ __global__ void __launch_bounds__(NT) rbc_factor(RbcDev d, const double* BM, con
   // P partitions: each partition's factors and block operators, its spikes (its factors solved
   // with the columns that couple it to the next and to the previous partition, for A and for
   // A^T), then the inverses of the coupled entries' systems.  Layout from pmeta: per partition
-  // p (8 ints): start, rows, then per direction the widths of V_p and W_p (and a spare int);
-  // per interface q (6 ints at 8 SPS_MAXPART): per direction the widths of a_q (last entries
-  // of partition q) and c_q (first entries of partition q + 1) and their offset in the
-  // coupled system.  Spike entry c of row i at c n + i; inverses column-major.
+  // p (8 ints): start, rows, then per direction the widths of V_p and W_p and the offset of its
+  // spike rows (entry c of its row t at c n_p + t); per interface q (6 ints at 8 SPS_MAXPART):
+  // per direction the widths of a_q (last entries of partition q) and c_q (first entries of
+  // partition q + 1) and their offset in the coupled system.  Inverses column-major.
   const int P = d.part;
   const int* pm = d.pmeta;
   int mx = 0;
@@ -1719,10 +1721,10 @@ __global__ void __launch_bounds__(NT) rbc_factor(RbcDev d, const double* BM, con
         R[e] = dir ? Aat(col, s0 + i) : Aat(s0 + i, col);
       }
       band_lu_solve_cols(ab, spiv, np, d.kl, d.ku, R, w, dir == 1);
-      double* out = O + (dir ? d.spk[1] : d.spk[0]) + s0;
+      double* out = O + (dir ? d.spk[1] : d.spk[0]) + pm[8 * p + 4 + 3 * dir];
       for (int e = threadIdx.x; e < np * w; e += blockDim.x) {
         const int i = e / w, c = e - i * w;
-        out[(size_t)c * d.n + i] = R[e];
+        out[(size_t)c * np + i] = R[e];
       }
       __syncthreads();   // R is refilled next
     }
@@ -1745,11 +1747,11 @@ __global__ void __launch_bounds__(NT) rbc_factor(RbcDev d, const double* BM, con
         // coupled-system columns of the spike columns: V_p -> c_p, W_p -> a_{p-1}
         const int zc = (p + 1 < P) ? pm[8 * SPS_MAXPART + 6 * p + 3 * dir + 2] + pm[8 * SPS_MAXPART + 6 * p + 3 * dir] : 0;
         const int za = (p > 0) ? pm[8 * SPS_MAXPART + 6 * (p - 1) + 3 * dir + 2] : 0;
-        const double* rows = spd + ppm[0] + row0;   // spike entry c of the partition's row row0 + t
+        const double* rows = spd + ppm[4 + 3 * dir] + row0;   // entry c of the partition's row row0 + t
         for (int e = threadIdx.x; e < nrow * w; e += blockDim.x) {
           const int t = e / w, c = e - t * w;
           const int col = (c < wV) ? zc + c : za + (c - wV);
-          Rm[(size_t)(zrow + t) * nr + col] = rows[(size_t)c * d.n + t];
+          Rm[(size_t)(zrow + t) * nr + col] = rows[(size_t)c * np + t];
         }
       }
     }
@@ -4094,15 +4096,17 @@ class RbcProblem : public ProblemImpl {
       }
       const int nr = std::max(nr0, nr1);
       if (!ok || nr > SPS_RED_MAX || nr > S_) continue;
-      // each direction's spikes (the widest partition's columns at stride S, rounded to 4) and
-      // inverse must fit the space of the early set of its solve (the T blocks for the forward
-      // solve, the G blocks for the transposed one) and the copy's loads
-      int wmax[2] = {0, 0};
+      // each direction's spikes (rounded to 4 doubles) and inverse must fit the space of the
+      // early set of its solve (the T blocks for the forward solve, the G blocks for the
+      // transposed one) and the copy's loads; offsets below 2^16
+      int sz[2] = {0, 0};
       for (int p = 0; p < P; ++p) {
-        wmax[0] = std::max(wmax[0], (p + 1 < P ? cu[p] : 0) + (p > 0 ? cl[p - 1] : 0));
-        wmax[1] = std::max(wmax[1], (p + 1 < P ? cut[p] : 0) + (p > 0 ? clt[p - 1] : 0));
+        const int np = st[p + 1] - st[p];
+        sz[0] += np * ((p + 1 < P ? cu[p] : 0) + (p > 0 ? cl[p - 1] : 0));
+        sz[1] += np * ((p + 1 < P ? cut[p] : 0) + (p > 0 ? clt[p - 1] : 0));
       }
-      const int area0 = (wmax[0] * S_ + 3) / 4 * 4 + nr0 * nr0, area1 = (wmax[1] * S_ + 3) / 4 * 4 + nr1 * nr1;
+      const int area0 = (sz[0] + 3) / 4 * 4 + nr0 * nr0, area1 = (sz[1] + 3) / 4 * 4 + nr1 * nr1;
+      if (std::max(sz[0], sz[1]) >= 0xffff) continue;
       const int cap = SPS_CP_REG * 2 * (NTK - SPS_WAVE * P);
       if (area0 > blk_t_size(S_) || area1 > blk_g_size(S_) || area0 + 1 > cap || area1 + 1 > cap) continue;
       // accepted: descriptor fields and the tables of both directions
@@ -4133,10 +4137,12 @@ class RbcProblem : public ProblemImpl {
           pm[1] = np;
           pm[2 + 3 * dir] = wV;
           pm[3 + 3 * dir] = wW;
+          pm[4 + 3 * dir] = off;
           for (int i = st[p]; i < st[p + 1]; ++i)
-            smap_h_[(size_t)dir * S_ + i] = int2{0, wV | (wW << 5) | (zV << 10) | (zW << 17)};
-          off = std::max(off, (w * S_ + 3) / 4 * 4);   // column-major at stride S (the widest partition)
+            smap_h_[(size_t)dir * S_ + i] = int2{(off + (i - st[p])) | (np << 16), wV | (wW << 5) | (zV << 10) | (zW << 17)};
+          off += np * w;
         }
+        off = (off + 3) / 4 * 4;
         const int big = 1 << 20;
         dv_.rof[dir] = off;
         dv_.nrr[dir] = dir ? nr1 : nr0;
