@@ -322,52 +322,93 @@ __device__ inline void band_factor_block(const double* __restrict__ BM, const do
   band_condense(ab, spiv, n, kl, ku, OPS, OPS + blk_t_size(n));
 }
 
-// Solves with the factors in ab for nr right-hand sides, column c of the n x nr row-major
-// matrix R (LDS) by thread c alone (nr <= blockDim.x): A x = r (row interchanges and L, then
-// U) or A^T x = r (U^T, then L^T with the interchanges in reverse).  For the few columns of the
-// partitioned solve's coupling blocks at factorization time.  Block-wide (ends with a barrier).
+// Solves with the factors in ab for nr <= blockDim.x / 8 right-hand sides, the columns of the
+// n x nr row-major matrix R (LDS): A x = r (row interchanges and L, then U) or, transposed,
+// A^T x = r (U^T, then L^T and the interchanges in reverse).  Column c is taken by the eight
+// lanes 8c .. 8c + 7 of one wave, so a step needs no block barrier: lane i updates the rows
+// j + i (L, kl <= 7) or j - i, j - i - 8, ... (U), or sums those products for the transposed
+// solve (an eight-lane DPP sum).  Used for the partitioned solve's coupling blocks at
+// factorization time.  Block-wide (ends with a barrier).
 __device__ inline void band_lu_solve_cols(const double* ab, const int* spiv, int n, int kl, int ku, double* R,
                                           int nr, bool transposed) {
-  const int c = threadIdx.x, ldab = 2 * kl + ku + 1, kv = kl + ku;
+  constexpr int KV = SPS_GW - SPS_BLK;   // the widest band of the block operators, kl + ku <= KV
+  const int c = threadIdx.x >> 3, i = threadIdx.x & 7, ldab = 2 * kl + ku + 1, kv = kl + ku;
   __syncthreads();
   if (c < nr) {
-    auto x = [&](int i) -> double& { return R[(size_t)i * nr + c]; };
+    auto x = [&](int r) -> double& { return R[(size_t)r * nr + c]; };
+    auto wsync = [] {
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    };
     if (!transposed) {
       for (int j = 0; j < n; ++j) {
-        const int p = spiv[j];
-        if (p != j) {
-          const double t = x(j);
-          x(j) = x(p);
-          x(p) = t;
+        // row j takes x(p) (the interchange); row j + i, i <= km, the old entry of row j + i
+        // (or of row j if j + i = p) minus l_i times it
+        const int p = spiv[j], km = min(kl, n - 1 - j);
+        const double xj = x(p);
+        double v = 0.0, l = 0.0;
+        if (i >= 1 && i <= km) {
+          v = (j + i == p) ? x(j) : x(j + i);
+          l = ab[j * ldab + kv + i];
         }
-        const double xj = x(j);
-        const int km = min(kl, n - 1 - j);
-        for (int i = 1; i <= km; ++i) x(j + i) -= ab[j * ldab + kv + i] * xj;
+        wsync();
+        if (i == 0) x(j) = xj;
+        else if (i <= km) x(j + i) = v - l * xj;
+        wsync();
       }
       for (int j = n - 1; j >= 0; --j) {
         const double xj = x(j) / ab[j * ldab + kv];
-        x(j) = xj;
         const int ku2 = min(kv, j);
-        for (int r = 1; r <= ku2; ++r) x(j - r) -= ab[j * ldab + kv - r] * xj;
+        double v[KV / 8 + 1], u[KV / 8 + 1];
+#pragma unroll
+        for (int q = 0; q <= KV / 8; ++q) {
+          const int r = i + 8 * q;
+          if (r >= 1 && r <= ku2) {
+            v[q] = x(j - r);
+            u[q] = ab[j * ldab + kv - r];
+          }
+        }
+        wsync();
+        if (i == 0) x(j) = xj;
+#pragma unroll
+        for (int q = 0; q <= KV / 8; ++q) {
+          const int r = i + 8 * q;
+          if (r >= 1 && r <= ku2) x(j - r) = v[q] - u[q] * xj;
+        }
+        wsync();
       }
     } else {
       for (int j = 0; j < n; ++j) {
-        double sacc = x(j);
         const int ku2 = min(kv, j);
-        for (int r = 1; r <= ku2; ++r) sacc -= ab[j * ldab + kv - r] * x(j - r);
-        x(j) = sacc / ab[j * ldab + kv];
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q <= KV / 8; ++q) {
+          const int r = i + 8 * q;
+          if (r >= 1 && r <= ku2) s = fma(ab[j * ldab + kv - r], x(j - r), s);
+        }
+        s = group_sum<8>(s);
+        const double xj = (x(j) - s) / ab[j * ldab + kv];
+        wsync();
+        if (i == 0) x(j) = xj;
+        wsync();
       }
       for (int j = n - 2; j >= 0; --j) {
-        double sacc = x(j);
         const int km = min(kl, n - 1 - j);
-        for (int i = 1; i <= km; ++i) sacc -= ab[j * ldab + kv + i] * x(j + i);
+        double s = (i >= 1 && i <= km) ? ab[j * ldab + kv + i] * x(j + i) : 0.0;
+        s = group_sum<8>(s);
+        const double xjv = x(j) - s;
         const int p = spiv[j];
-        if (p != j) {
-          x(j) = x(p);
-          x(p) = sacc;
-        } else {
-          x(j) = sacc;
+        const double xp = x(p);
+        wsync();
+        if (i == 0) {
+          if (p != j) {
+            x(j) = xp;
+            x(p) = xjv;
+          } else {
+            x(j) = xjv;
+          }
         }
+        wsync();
       }
     }
   }
@@ -375,56 +416,80 @@ __device__ inline void band_lu_solve_cols(const double* ab, const int* spiv, int
 }
 
 // Inverse of the nr x nr matrix A (row-major, LDS) into Ainv (global, row-major, or
-// column-major if colmajor) by
-// Gauss-Jordan elimination with partial pivoting on [A | I] in LDS (aug: nr x 2nr doubles, then
-// nr doubles of multipliers); sh: one int of LDS.  Block-wide (ends with a barrier).
+// column-major if colmajor) by Gauss-Jordan elimination with partial pivoting on [A | I] in LDS
+// (aug: nr x 2nr doubles, then nr doubles of multipliers); sh: one int of LDS.  Thread t takes column t mod 2nr of the augmented matrix and every
+// (blockDim / 2nr)-th row.  Block-wide (ends with a barrier).
 __device__ inline void block_inverse(const double* A, int nr, double* aug, double* Ainv, int* err, int* sh,
                                      bool colmajor = false) {
   const int tid = threadIdx.x, nt = blockDim.x, w = 2 * nr;
   double* f = aug + (size_t)nr * w;
+  const int groups = max(nt / w, 1), g = tid / w, c = tid - g * w;
   __syncthreads();
   for (int e = tid; e < nr * w; e += nt) {
-    const int i = e / w, c = e - i * w;
-    aug[e] = (c < nr) ? A[i * nr + c] : ((c - nr == i) ? 1.0 : 0.0);
+    const int i = e / w, cc = e - i * w;
+    aug[e] = (cc < nr) ? A[i * nr + cc] : ((cc - nr == i) ? 1.0 : 0.0);
   }
   __syncthreads();
   for (int j = 0; j < nr; ++j) {
-    if (tid == 0) {
+    if (tid < 8) {
+      // pivot: the first row i >= j of largest |aug[i][j]| (eight lanes, every eighth row,
+      // then a DPP reduction over the eight that keeps the smaller index of equal values)
       int p = j;
-      double best = fabs(aug[j * w + j]);
-      for (int i = j + 1; i < nr; ++i) {
+      double best = -1.0;
+      for (int i = j + tid; i < nr; i += 8) {
         const double v = fabs(aug[i * w + j]);
         if (v > best) {
           best = v;
           p = i;
         }
       }
-      if (!(best > 0.0)) atomicOr(err, 1);
-      sh[0] = p;
+      auto merge = [&](double ob, int op) {
+        if (ob > best || (ob == best && op < p)) {
+          best = ob;
+          p = op;
+        }
+      };
+      merge(dpp_xor1(best), __builtin_amdgcn_mov_dpp(p, 0xB1, 0xF, 0xF, false));
+      merge(dpp_xor2(best), __builtin_amdgcn_mov_dpp(p, 0x4E, 0xF, 0xF, false));
+      merge(dpp_mirror8(best), __builtin_amdgcn_mov_dpp(p, 0x141, 0xF, 0xF, false));
+      if (tid == 0) {
+        if (!(best > 0.0)) atomicOr(err, 1);
+        sh[0] = p;
+      }
     }
     __syncthreads();
     const int p = sh[0];
-    if (p != j)
-      for (int c = tid; c < w; c += nt) {
-        const double t = aug[j * w + c];
-        aug[j * w + c] = aug[p * w + c];
-        aug[p * w + c] = t;
-      }
+    const double rinv = 1.0 / aug[p * w + j];
+    if (g == 0 && c < w) {
+      // rows j and p exchanged, the new row j scaled by the pivot's reciprocal
+      const double a = aug[j * w + c], b = aug[p * w + c];
+      aug[j * w + c] = b * rinv;
+      if (p != j) aug[p * w + c] = a;
+    }
     __syncthreads();
-    const double rinv = 1.0 / aug[j * w + j];
-    __syncthreads();
-    for (int c = tid; c < w; c += nt) aug[j * w + c] *= rinv;
     for (int i = tid; i < nr; i += nt) f[i] = (i == j) ? 0.0 : aug[i * w + j];
     __syncthreads();
-    for (int e = tid; e < nr * w; e += nt) {
-      const int i = e / w, c = e - i * w;
-      if (i != j) aug[e] -= f[i] * aug[j * w + c];
+    if (g < groups && c < w) {
+      // (four rows at a time: their reads in flight together)
+      const double pj = aug[j * w + c];
+      int i = g;
+      for (; i + 3 * groups < nr; i += 4 * groups) {
+        double v[4], fv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          v[u] = aug[(i + u * groups) * w + c];
+          fv[u] = f[i + u * groups];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) aug[(i + u * groups) * w + c] = v[u] - fv[u] * pj;
+      }
+      for (; i < nr; i += groups) aug[i * w + c] -= f[i] * pj;
     }
     __syncthreads();
   }
   for (int e = tid; e < nr * nr; e += nt) {
-    const int i = e / nr, c = e - i * nr;
-    Ainv[colmajor ? c * nr + i : e] = aug[i * w + nr + c];
+    const int i = e / nr, cc = e - i * nr;
+    Ainv[colmajor ? cc * nr + i : e] = aug[i * w + nr + cc];
   }
   __syncthreads();
 }
