@@ -206,41 +206,72 @@ __device__ inline void band_lu_factor(const double* __restrict__ BM, const doubl
     }
   }
   __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    const int km = min(kl, n - 1 - j);
-    const int wd = min(kv, n - 1 - j);  // columns right of j that can hold fill
-    if (tid == 0) {
-      int jp = 0;
-      double best = fabs(ab[j * ldab + kv]);
-      for (int i = 1; i <= km; ++i) {
-        const double v = fabs(ab[j * ldab + kv + i]);
-        if (v > best) { best = v; jp = i; }
+  // the column steps on wave 0 alone (a step touches at most (kl + 1) x (kl + ku + 1) entries;
+  // the LDS operations of one wave complete in order, so no block barrier is needed per step)
+  if (tid < SPS_WAVE) {
+    const int lane = tid;
+    auto wsync = [] {
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    };
+    for (int j = 0; j < n; ++j) {
+      const int km = min(kl, n - 1 - j);
+      const int wd = min(kv, n - 1 - j);  // columns right of j that can hold fill
+      // pivot: the first row of largest magnitude among j .. j + km (lanes 0 .. 7, DPP merge)
+      int jp = lane;
+      double best = (lane <= km && lane < 8) ? fabs(ab[j * ldab + kv + lane]) : -1.0;
+      auto merge = [&](double ob, int op) {
+        if (ob > best || (ob == best && op < jp)) {
+          best = ob;
+          jp = op;
+        }
+      };
+      merge(dpp_xor1(best), __builtin_amdgcn_mov_dpp(jp, 0xB1, 0xF, 0xF, false));
+      merge(dpp_xor2(best), __builtin_amdgcn_mov_dpp(jp, 0x4E, 0xF, 0xF, false));
+      merge(dpp_mirror8(best), __builtin_amdgcn_mov_dpp(jp, 0x141, 0xF, 0xF, false));
+      jp = __builtin_amdgcn_readfirstlane(jp);
+      best = __shfl(best, 0);
+      if (lane == 0) {
+        spiv[j] = j + jp;
+        if (!(best > 0.0) || !isfinite(best)) atomicOr(err, 1);
       }
-      sh[0] = jp;
-      spiv[j] = j + jp;
-      if (!(best > 0.0) || !isfinite(best)) atomicOr(err, 1);
-    }
-    __syncthreads();
-    const int jp = sh[0];
-    if (jp != 0) {
-      for (int c = j + tid; c <= j + wd; c += nt) {
+      if (jp != 0 && lane <= wd) {
+        const int c = j + lane;
         double* p0 = &ab[c * ldab + kv + j - c];
         double* p1 = &ab[c * ldab + kv + j + jp - c];
-        const double t = *p0; *p0 = *p1; *p1 = t;
+        const double t0 = *p0, t1 = *p1;
+        *p0 = t1;
+        *p1 = t0;
       }
+      wsync();
+      const double rinv = 1.0 / ab[j * ldab + kv];
+      if (lane >= 1 && lane <= km) ab[j * ldab + kv + lane] *= rinv;
+      wsync();
+      // rank-1 update: lane (row j + 1 + (lane & 7), columns j + 1 + (lane >> 3) + 8 q)
+      {
+        const int i = 1 + (lane & 7), c0 = j + 1 + (lane >> 3);
+        if (i <= km) {
+          const double l = ab[j * ldab + kv + i];
+          double u[4], v[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int c = c0 + 8 * q;
+            if (c <= j + wd) {
+              u[q] = ab[c * ldab + kv + j - c];
+              v[q] = ab[c * ldab + kv + j + i - c];
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int c = c0 + 8 * q;
+            if (c <= j + wd) ab[c * ldab + kv + j + i - c] = v[q] - l * u[q];
+          }
+        }
+      }
+      wsync();
     }
-    __syncthreads();
-    const double piv_v = ab[j * ldab + kv];
-    const double rinv = 1.0 / piv_v;
-    for (int i = 1 + tid; i <= km; i += nt) ab[j * ldab + kv + i] *= rinv;
-    __syncthreads();
-    for (int e = tid; e < km * wd; e += nt) {
-      const int i = 1 + e % km;          // row j+i
-      const int c = j + 1 + e / km;      // column c
-      ab[c * ldab + kv + j + i - c] -= ab[j * ldab + kv + i] * ab[c * ldab + kv + j - c];
-    }
-    __syncthreads();
   }
+  __syncthreads();
 }
 
 // Block operators (see above) of the factors in ab; T_t column c is the image of the window's

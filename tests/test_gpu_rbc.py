@@ -4,6 +4,7 @@ RK222 step, the cost seed, the initial transform and its adjoint, and the full
 checkpointed gradient.  Tolerance: 1e-11 of each field's own largest entry (u, w, b, p and
 the taus, the k = 0 row and the rows k >= 1 apart; states with the conduction state
 subtracted), see tests/parity.py; grid arrays and J relative to their largest entry."""
+import gc
 import sys
 
 import numpy as np
@@ -294,17 +295,25 @@ def test_caller_allocator():
     G.gradient(X0, nsteps, None, g_ref, None)
     G.sync()
     torch.cuda.synchronize()
-    before = torch.cuda.memory_allocated()
-    sps.use_torch_allocator(True)
+    # (earlier tests' garbage collected first, and no collection inside the window, so that
+    # only this test's allocations move torch's count)
+    gc.collect()
+    gc.disable()
     try:
-        _, H = build(cfg, ce=2, max_steps=nsteps)
+        before = torch.cuda.memory_allocated()
+        sps.use_torch_allocator(True)
+        try:
+            _, H = build(cfg, ce=2, max_steps=nsteps)
+        finally:
+            sps.use_torch_allocator(False)
+        grown = torch.cuda.memory_allocated() - before
+        H.gradient(X0, nsteps, None, g, None)
+        H.sync()
+        assert torch.equal(g, g_ref)
+        H.close()
+        torch.cuda.synchronize()
+        after = torch.cuda.memory_allocated()
     finally:
-        sps.use_torch_allocator(False)
-    grown = torch.cuda.memory_allocated() - before
-    H.gradient(X0, nsteps, None, g, None)
-    H.sync()
-    assert torch.equal(g, g_ref)
-    H.close()
-    torch.cuda.synchronize()
+        gc.enable()
     note(f"  workspace from torch's allocator: {grown / 1e6:.2f} MB, returned: {torch.cuda.memory_allocated() == before}")
-    assert grown > 1e5 and torch.cuda.memory_allocated() == before
+    assert grown > 1e5 and after == before
