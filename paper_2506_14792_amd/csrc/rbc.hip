@@ -1244,8 +1244,13 @@ __global__ void __launch_bounds__(256) rbc_xfwd_w(RbcDev d, XfArgs a) {
   constexpr int N = W::N, K = W::K, SC = W::SC;
   extern __shared__ double smem_d[];
   cplx* tw = reinterpret_cast<cplx*>(smem_d);   // N
-  cplx* scr = tw + N;                            // 4 x SC
-  cplx* G = scr + 4 * SC;                        // 4 x 8 x 64 grid rows (permuted layout)
+  cplx* scr = tw + N;                            // 4 x SC: each wave's FFT exchange scratch
+  // Grid rows in the permuted layout (8 registers x 8 R1 active lanes = N entries per wave).
+  // Waves 0 and 1 go on to the products and the forward FFTs, so theirs get a region of their
+  // own; waves 2 and 3 are done after the inverse FFT and keep theirs in their own scratch.
+  // (The block takes 3 N + 4 SC complex entries, three blocks per CU.)
+  static_assert(N <= SC, "a wave's grid rows fit its FFT scratch");
+  cplx* G01 = scr + 4 * SC;                      // 2 x N
   const int j = blockIdx.x, tid = threadIdx.x, wv = tid >> 6, l = lane_id();
   cplx* sc = scr + wv * SC;
   // pair wv: (u, w), (ux, uz), (wx, wz), (bx, bz)
@@ -1256,20 +1261,26 @@ __global__ void __launch_bounds__(256) rbc_xfwd_w(RbcDev d, XfArgs a) {
   cplx pv[8];
   wfft_a_to_p<R1, +1>(av, pv, sc, tw);
   if (l < 8 * R1) {
+    cplx* gw = wv < 2 ? G01 + wv * N : sc;
 #pragma unroll
-    for (int h = 0; h < 8; ++h) G[(wv * 8 + h) * 64 + l] = pv[h];
+    for (int h = 0; h < 8; ++h) gw[h * 8 * R1 + l] = pv[h];
   }
   __syncthreads();
   if (wv >= 2) return;
   if (l < 8 * R1) {
+    const cplx* G0 = G01;
+    const cplx* G1 = G01 + N;
+    const cplx* G2 = scr + 2 * SC;
+    const cplx* G3 = scr + 3 * SC;
 #pragma unroll
     for (int h = 0; h < 8; ++h) {
-      const cplx uw = G[(0 * 8 + h) * 64 + l];
+      const int e = h * 8 * R1 + l;
+      const cplx uw = G0[e];
       if (wv == 0) {
-        const cplx ud = G[(1 * 8 + h) * 64 + l], wd = G[(2 * 8 + h) * 64 + l];
+        const cplx ud = G1[e], wd = G2[e];
         pv[h] = cmk(-(uw.x * ud.x + uw.y * ud.y), -(uw.x * wd.x + uw.y * wd.y));   // N_u, N_w
       } else {
-        const cplx bd = G[(3 * 8 + h) * 64 + l];
+        const cplx bd = G3[e];
         pv[h] = cmk(-(uw.x * bd.x + uw.y * bd.y), 0.0);                            // N_b
       }
     }
@@ -1306,8 +1317,13 @@ __global__ void __launch_bounds__(384) rbc_xadj_w(RbcDev d, XaArgs a) {
   constexpr int N = W::N, K = W::K, SC = W::SC;
   extern __shared__ double smem_d[];
   cplx* tw = reinterpret_cast<cplx*>(smem_d);   // N
-  cplx* scr = tw + N;                            // 6 x SC
-  cplx* G = scr + 6 * SC;                        // 6 x 8 x 64 grid rows (permuted layout)
+  cplx* scr = tw + N;                            // 6 x SC: each wave's FFT exchange scratch
+  // Grid rows in the permuted layout (N entries per wave): waves 0-3 go on to the products and
+  // the forward FFTs and get a region of their own; waves 4 and 5 (the cotangent pairs) are
+  // done after the inverse FFT and keep theirs in their own scratch.  (The block takes
+  // 5 N + 6 SC complex entries, two blocks per CU.)
+  static_assert(N <= SC, "a wave's grid rows fit its FFT scratch");
+  cplx* G03 = scr + 6 * SC;                      // 4 x N
   const int j = blockIdx.x, tid = threadIdx.x, wv = tid >> 6, l = lane_id();
   cplx* sc = scr + wv * SC;
   // pairs: (u, w), (ux, uz), (wx, wz), (bx, bz), (Nu_bar, Nw_bar) and (Nb_bar, 0) with halved
@@ -1320,22 +1336,26 @@ __global__ void __launch_bounds__(384) rbc_xadj_w(RbcDev d, XaArgs a) {
   cplx pv[8];
   wfft_a_to_p<R1, +1>(av, pv, sc, tw);
   if (l < 8 * R1) {
+    cplx* gw = wv < 4 ? G03 + wv * N : sc;
 #pragma unroll
-    for (int h = 0; h < 8; ++h) G[(wv * 8 + h) * 64 + l] = pv[h];
+    for (int h = 0; h < 8; ++h) gw[h * 8 * R1 + l] = pv[h];
   }
   __syncthreads();
   if (wv < 4) {
     if (l < 8 * R1) {
       constexpr double inv = 1.0 / N;
+      const cplx* G4 = scr + 4 * SC;
+      const cplx* G5 = scr + 5 * SC;
 #pragma unroll
       for (int h = 0; h < 8; ++h) {
-        const cplx nb = G[(4 * 8 + h) * 64 + l];
-        const double Nub = nb.x * inv, Nwb = nb.y * inv, Nbb = G[(5 * 8 + h) * 64 + l].x * inv;
+        const int e = h * 8 * R1 + l;
+        const cplx nb = G4[e];
+        const double Nub = nb.x * inv, Nwb = nb.y * inv, Nbb = G5[e].x * inv;
         if (wv == 0) {
-          const cplx ud = G[(1 * 8 + h) * 64 + l], wd = G[(2 * 8 + h) * 64 + l], bd = G[(3 * 8 + h) * 64 + l];
+          const cplx ud = G03[N + e], wd = G03[2 * N + e], bd = G03[3 * N + e];
           pv[h] = cmk(-(Nub * ud.x + Nwb * wd.x + Nbb * bd.x), -(Nub * ud.y + Nwb * wd.y + Nbb * bd.y));
         } else {
-          const cplx uw = G[(0 * 8 + h) * 64 + l];
+          const cplx uw = G03[e];
           const double c = (wv == 1) ? Nub : (wv == 2 ? Nwb : Nbb);
           pv[h] = cmk(-c * uw.x, -c * uw.y);   // (x-derivative bar, z-derivative bar) of u, w or b
         }
@@ -3430,8 +3450,8 @@ class RbcProblem : public ProblemImpl {
     else hipExtLaunchKernelGGL(rbc_xfwd, g, dim3(NTX), xf_lds(), s, t ? e0 : nullptr, t ? e1 : nullptr, 0, dv_, a);
     SPS_CHECK_LAUNCH();
   }
-  size_t xfw_lds() const { return sizeof(cplx) * (Ngx_ + 4 * wave_sc() + 4 * 512); }
-  size_t xaw_lds() const { return sizeof(cplx) * (Ngx_ + 6 * wave_sc() + 6 * 512); }
+  size_t xfw_lds() const { return sizeof(cplx) * (3 * Ngx_ + 4 * wave_sc()); }
+  size_t xaw_lds() const { return sizeof(cplx) * (5 * Ngx_ + 6 * wave_sc()); }
   int wave_sc() const { return wave_r1_ == 6 ? WaveRow<6>::SC : WaveRow<3>::SC; }
   // adjoint kernel arguments; stage m (1 .. s) for the stage reverses KA_A (m = s) and KA_B
   KaArgs ka_args(int flags, int m = 0) {
@@ -4230,14 +4250,14 @@ class RbcProblem : public ProblemImpl {
   double nu_, ka_, dt_ = 0.0, cp_ = 1.0, bc0_ = 1.0, cost_scale_ = 1.0;
   int Kz_ = 1, ncost_ = 2;
   bool cou_ = false, stream_solve_ = false;
-  int wave_r1_ = 0;
+  int wave_r1_ = 0;                  // grid rows of 64*wave_r1_ points use the one-wave-per-FFT kernels (0: off)
   int B_ = 1;                        // instances of a batch
   std::vector<double> rab_;          // a batch's Rayleigh numbers (empty: a single problem)
   const double *BLnu_ = nullptr, *BLka_ = nullptr;   // a batch's nu and kappa parts of L
   std::vector<double> blnu_h_, blka_h_;               // (host copies, for the partition's coupling widths)
   std::vector<int> pmeta_h_;                          // partitioned solve: factor-kernel layout
   std::vector<int2> smap_h_;                          // partitioned solve: per-row spike offsets and widths
-  const double2* frame_ = nullptr;   // plane Couette: unit wave vector of each mode   // grid rows of 64 wave_r1_ points use the one-wave-per-FFT kernels
+  const double2* frame_ = nullptr;   // plane Couette: unit wave vector of each mode
   std::vector<double> kxs_;
   std::vector<unsigned char> ckeep_;
   std::unique_ptr<CouettePlanes> planes_;
