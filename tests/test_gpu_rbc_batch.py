@@ -2,7 +2,8 @@
 instance its own factors, every stage launch over all instances) against the FP64 oracle,
 instance by instance, field by field (tests/parity.py): the forward run, J and the gradient at
 24x16 (three instances, ragged checkpoint segments) and at the full 256x64 size (two
-instances); an instance's results do not depend on the other instances of its batch; calls
+instances), and sampled instances of batches whose launches take the streamed solve (24x16 x 96,
+256x64 x 9); an instance's results do not depend on the other instances of its batch; calls
 outside the batch's scope are refused."""
 import sys
 
@@ -38,15 +39,24 @@ def split(t, B, shape):
     return t.cpu().numpy().view(np.complex128).reshape((B,) + shape)
 
 
-@pytest.mark.parametrize("nx,nz,lx,Pr,dt,ras,nsteps,ce", [
-    (24, 16, 3.0, 0.7, 2e-3, (1e5, 3e4, 2e5), 5, 2),
-    (256, 64, 4.0, 1.0, 1e-3, (1e6, 5e5), 3, 2),
-], ids=["24x16x3", "256x64x2"])
-def test_batch_against_oracle(nx, nz, lx, Pr, dt, ras, nsteps, ce):
-    note(f"batch {nx}x{nz} Ra {ras} x {nsteps} steps ce={ce}")
+def seeded_ras(B, lo, hi, seed):
+    return tuple(np.random.default_rng(seed).uniform(lo, hi, B))
+
+
+# more than 1024 systems per launch (K x B) take the streamed solve (operators streamed
+# through LDS in chunks, several blocks per CU): 24x16 x 96 and 256x64 x 9, sampled instances
+@pytest.mark.parametrize("nx,nz,lx,Pr,dt,ras,nsteps,ce,sample", [
+    (24, 16, 3.0, 0.7, 2e-3, (1e5, 3e4, 2e5), 5, 2, None),
+    (256, 64, 4.0, 1.0, 1e-3, (1e6, 5e5), 3, 2, None),
+    (24, 16, 3.0, 0.7, 2e-3, seeded_ras(96, 3e4, 2e5, 7), 5, 2, (0, 37, 95)),
+    (256, 64, 4.0, 1.0, 1e-3, seeded_ras(9, 5e5, 2e6, 8), 3, 2, (4,)),
+], ids=["24x16x3", "256x64x2", "24x16x96-streamed", "256x64x9-streamed"])
+def test_batch_against_oracle(nx, nz, lx, Pr, dt, ras, nsteps, ce, sample):
     B = len(ras)
+    note(f"batch {nx}x{nz} B={B} x {nsteps} steps ce={ce}")
     G = sps.RbcBatch(list(ras), nx, nz, lx, Pr, dt=dt, checkpoint_every=ce, max_steps=nsteps)
-    Ps = [RBC(Nx=nx, Nz=nz, Lx=lx, Ra=r, Pr=Pr) for r in ras]
+    checked = range(B) if sample is None else sample
+    Ps = {b: RBC(Nx=nx, Nz=nz, Lx=lx, Ra=ras[b], Pr=Pr) for b in checked}
     grids = [wl.rbc_b0(seed=30 + b, Nx=nx, Nz=nz, amp=0.1) for b in range(B)]
     X0 = torch.zeros(G.n, dtype=torch.float64, device="cuda")
     G.initial_state(torch.from_numpy(np.concatenate([g.ravel() for g in grids])).cuda(), X0)
@@ -60,7 +70,7 @@ def test_batch_against_oracle(nx, nz, lx, Pr, dt, ras, nsteps, ce):
     shape = (nx // 2, 4 * nz + 7)
     X0h, XNh, gh = split(X0, B, shape), split(XN, B, shape), split(g, B, shape)
     gbh = gb.cpu().numpy().reshape(B, nx, nz)
-    for b, P in enumerate(Ps):
+    for b, P in Ps.items():
         X0r = P.initial_state(grids[b])
         base = P.lbvp_solve(np.zeros(shape, complex))
         check_fields(X0h[b], X0r, nz, TOL, base=base, what=f"instance {b} X0")
