@@ -144,6 +144,17 @@ struct RbcDev {
   const double* kab;    // [B]
 };
 
+// The wavenumber of a per-wavenumber block.  Workgroups are dealt to the eight XCDs in turn, and
+// each XCD has its own L2; the z-column arrays ([field][z][k]) hold eight wavenumbers per
+// 128-byte line, so consecutive wavenumbers go to one XCD (XCD x takes a contiguous range), and
+// the blocks that read or write the same lines share that XCD's L2 instead of each fetching the
+// line from memory.
+__device__ __forceinline__ int xcd_wavenumber(int b, int K) {
+  constexpr int X = 8;
+  const int per = K / X, rem = K - per * X, x = b % X;
+  return x * per + min(x, rem) + b / X;
+}
+
 // Instance b's view of the problem: its diffusivities and its factors.
 __device__ __forceinline__ void rbc_inst(RbcDev& d, int b) {
   if (d.nub) {
@@ -866,7 +877,7 @@ __global__ void __launch_bounds__(NTK) rbc_kfwd(RbcDev d, KfArgs a) {
   }
   extern __shared__ double smem_d[];
   cplx* sm = reinterpret_cast<cplx*>(smem_d);
-  const int k = blockIdx.x, tid = threadIdx.x;
+  const int k = xcd_wavenumber(blockIdx.x, d.K), tid = threadIdx.x;
   const int N = d.N, S = d.S, K = d.K, Ngz = d.Ngz, Hc = half_nodes(Ngz);
   const int mode = a.mode;
   cplx* vA = sm;                // S + SPS_PAD : right-hand side, then solution / state
@@ -1559,7 +1570,7 @@ __global__ void __launch_bounds__(NTK) rbc_kadj(RbcDev d, KaArgs a) {
   }
   extern __shared__ double smem_d[];
   cplx* sm = reinterpret_cast<cplx*>(smem_d);
-  const int k = blockIdx.x, tid = threadIdx.x;
+  const int k = xcd_wavenumber(blockIdx.x, d.K), tid = threadIdx.x;
   const int N = d.N, S = d.S, Ngz = d.Ngz, Hc = half_nodes(Ngz);
   const int fl = a.flags;
   const double dt = a.dt;
