@@ -379,7 +379,7 @@ __device__ __forceinline__ void stage_cos(const double* g, double* ct, int Ng) {
 // sum_j T_n(x_j) v[j] over the Ng nodes (complex v in LDS), cos table ct in LDS.
 __device__ __forceinline__ cplx cheb_sum_nodes(const double* ct, const cplx* v, int n, int Ng) {
   const int P = 4 * Ng, dn = (2 * n) % P;
-  int M = (int)(((long long)n * (2 * Ng - 1)) % P);
+  int M = (int)((unsigned)n * (unsigned)(2 * Ng - 1) % (unsigned)P);
   double sr = 0.0, si = 0.0;
 #pragma unroll 8
   for (int j = 0; j < Ng; ++j) {
@@ -427,8 +427,10 @@ template <int NF, int SPL>
 __device__ __forceinline__ void nodes_to_mode(const double* ct, const cplx* pq, int Hc, int Ng, int n, int h,
                                               cplx (&acc)[NF]) {
   const int P4 = 4 * Ng, par = n & 1;
-  int M = (int)(((long long)n * (2 * (Ng - h) - 1)) % P4);     // T_n(x_j) = ct[n (2 (Ng - j) - 1) mod 4 Ng]
-  const int dn = (int)(((long long)2 * SPL * n) % P4);
+  // T_n(x_j) = ct[n (2 (Ng - j) - 1) mod 4 Ng] (32-bit products: n < 64 and Ng <= 128 here; a
+  // 64-bit remainder is a long instruction sequence)
+  int M = (int)((unsigned)n * (unsigned)(2 * (Ng - h) - 1) % (unsigned)P4);
+  const int dn = (int)((unsigned)(2 * SPL * n) % (unsigned)P4);
 #pragma unroll
   for (int f = 0; f < NF; ++f) acc[f] = czero();
   for (int j = h; j < Hc; j += SPL) {
@@ -453,8 +455,8 @@ template <int NF>
 __device__ __forceinline__ void modes_to_pair(const double* ct, const cplx* c, int cstride, int N, int Ng, int j,
                                               int h, cplx (&val)[NF]) {
   const int P4 = 4 * Ng, dm = 2 * (Ng - j) - 1;
-  int M = (int)(((long long)h * dm) % P4);
-  const int step = (int)(((long long)4 * dm) % P4);
+  int M = (int)((unsigned)h * (unsigned)dm % (unsigned)P4);
+  const int step = (int)((unsigned)(4 * dm) % (unsigned)P4);
 #pragma unroll
   for (int f = 0; f < NF; ++f) val[f] = czero();
   for (int n = h; n < N; n += 4) {
