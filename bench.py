@@ -643,6 +643,7 @@ def kolmo_timing():
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     J_closed = ct.rollout_losses(Ste, held, n, nc, c["Re"], c["drag"], c["dt"], theta)
+    twox = kolmo_twice_resolution(X0, S, Str, Ste, held, picks, c, J_plain, step_ms["closure"])
     return {"workload": "Kolmogorov flow 2D, Re=1000, forcing sin(4y), drag 0.1: coarse 64^2 (dt 0.002) with the "
                         "closure network, trained on 8x spectrally truncated 512^2 fine runs (dt 0.00025) from "
                         "seeded k^-3 vorticity, loss on 200-step coarse rollouts through the adjoint",
@@ -655,7 +656,80 @@ def kolmo_timing():
             "train_loss_first_last": [losses[0], losses[-1]],
             "heldout_windows": len(held), "heldout_error_no_closure": float(J_plain.mean()),
             "heldout_error_trained_closure": float(J_closed.mean()),
-            "error_ratio_no_closure_over_closure": float(J_plain.mean() / J_closed.mean())}
+            "error_ratio_no_closure_over_closure": float(J_plain.mean() / J_closed.mean()),
+            "cost_matched_baseline": twox}
+
+
+def kolmo_rollout_error(H, T, N):
+    """The coarse rollout loss's metric (per window: the mean over the N x N grid of the squared
+    difference, averaged over the steps) of states H against targets T, both [steps][windows][N/2
+    x N complex modes] as the library stores them (kx >= 0 half plane: the kx = 0 row counted
+    once after taking its Hermitian part, the others twice; the ky Nyquist column dropped)."""
+    import torch
+    n, B = H.shape[0], H.shape[1]
+    D = torch.view_as_complex((H - T).reshape(n, B, N // 2, N, 2))
+    iy = torch.arange(N, device=D.device)
+    D0 = 0.5 * (D[:, :, 0, :] + torch.conj(D[:, :, 0, (N - iy) % N]))
+    w = (D0.abs() ** 2)[:, :, iy != N // 2].sum(-1) + 2.0 * (D[:, :, 1:, :].abs() ** 2)[:, :, :, iy != N // 2].sum((-1, -2))
+    return (w.sum(0) / n).cpu().numpy()
+
+
+def kolmo_twice_resolution(X0, S, Str, Ste, held, picks, c, J_plain, closure_step_ms):
+    """Cost-matched baseline of the closure: the unclosed solver at twice the coarse resolution
+    (128^2 modes, step dt/2) started from the same fine runs truncated to 128^2 modes, its state
+    every second step truncated to 64^2 modes and scored against the same held-out targets with the
+    rollout loss's metric, and its cost per coarse time step (two of its steps) beside a closed
+    64^2 step.  The metric is checked against the library's own loss on the unclosed 64^2 runs."""
+    import torch
+    import paper_2506_14792_amd as sps
+    from paper_2506_14792_amd import closure_train as ct
+    nf, fac = c["n_fine"], c["factor"]
+    nc, n2 = nf // fac, 2 * (nf // fac)
+    n, B = c["rollout"], c["batch"]
+    S2 = ct.fine_snapshots(X0, nf, fac // 2, c["Re"], c["drag"], c["dt"] / 2, c["spinup"], 2 * c["nsnap"])
+    ntr = c["ntrain"]
+    # the unclosed 64^2 runs' states through the forward run's snapshots: the metric against J_plain
+    X64, T = ct.gather_windows(Ste, held, n)
+    T = T.view(n, len(held), nc * nc)
+    G = sps.Kolmogorov(len(held), nc, Re=c["Re"], dt=c["dt"], max_steps=1, closure=False, keep_history=False,
+                       drag=c["drag"])
+    H = torch.empty(n * len(held) * nc * nc, dtype=torch.float64, device=X0.device)
+    G.forward(X64, n, snap=H, every=1, nc=nc)
+    torch.cuda.synchronize()
+    G.close()
+    e_plain = kolmo_rollout_error(H.view(n, len(held), nc * nc), T, nc)
+    # the 128^2 runs
+    idx = torch.as_tensor([2 * s for s, _ in held], device=X0.device)
+    inst = torch.as_tensor([ntr + b for _, b in held], device=X0.device)
+    X128 = S2[idx, inst].reshape(-1).contiguous()
+    G = sps.Kolmogorov(len(held), n2, Re=c["Re"], dt=c["dt"] / 2, max_steps=1, closure=False, keep_history=False,
+                       drag=c["drag"])
+    H2 = torch.empty(n * len(held) * nc * nc, dtype=torch.float64, device=X0.device)
+    G.forward(X128, 2 * n, snap=H2, every=2, nc=nc)
+    torch.cuda.synchronize()
+    G.close()
+    e_2x = kolmo_rollout_error(H2.view(n, len(held), nc * nc), T, nc)
+    # cost: B windows, as for the coarse step times
+    idt = torch.as_tensor([2 * s for s, _ in picks], device=X0.device)
+    itr = torch.as_tensor([b for _, b in picks], device=X0.device)
+    Xt = S2[idt, itr].reshape(-1).contiguous()
+    G = sps.Kolmogorov(B, n2, Re=c["Re"], dt=c["dt"] / 2, max_steps=1, closure=False, keep_history=False,
+                       drag=c["drag"])
+    XN = torch.empty_like(Xt)
+    G.forward(Xt, 2 * n, XN=XN)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    G.forward(Xt, 2 * n, XN=XN)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t1) / n * 1e3
+    G.close()
+    del S2
+    return {"solver": "unclosed, 128^2 modes, dt 0.001 (two steps per coarse step), from the fine runs truncated "
+                      "to 128^2, scored on its states truncated to 64^2",
+            "heldout_error": float(e_2x.mean()),
+            "metric_check_max_rel_diff_vs_library_loss": float(np.max(np.abs(e_plain - J_plain) / J_plain)),
+            "ms_per_coarse_time_step": ms,
+            "cost_vs_closed_64_step": ms / closure_step_ms}
 
 
 def copy_calibration(nbytes=1 << 28, reps=5):
