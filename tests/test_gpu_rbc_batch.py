@@ -44,13 +44,16 @@ def seeded_ras(B, lo, hi, seed):
 
 
 # more than 1024 systems per launch (K x B) take the streamed solve (operators streamed
-# through LDS in chunks, several blocks per CU): 24x16 x 96 and 256x64 x 9, sampled instances
+# through LDS in chunks, several blocks per CU): 24x16 x 96 and 256x64 x 9, sampled instances;
+# the one-wave-per-FFT grid-row kernels on batches: 256x64 x 9 (384-point rows) and 128x32 x 9
+# (192-point rows)
 @pytest.mark.parametrize("nx,nz,lx,Pr,dt,ras,nsteps,ce,sample", [
     (24, 16, 3.0, 0.7, 2e-3, (1e5, 3e4, 2e5), 5, 2, None),
     (256, 64, 4.0, 1.0, 1e-3, (1e6, 5e5), 3, 2, None),
     (24, 16, 3.0, 0.7, 2e-3, seeded_ras(96, 3e4, 2e5, 7), 5, 2, (0, 37, 95)),
     (256, 64, 4.0, 1.0, 1e-3, seeded_ras(9, 5e5, 2e6, 8), 3, 2, (4,)),
-], ids=["24x16x3", "256x64x2", "24x16x96-streamed", "256x64x9-streamed"])
+    (128, 32, 4.0, 1.0, 1e-3, seeded_ras(9, 5e5, 2e6, 9), 3, 2, (0, 8)),
+], ids=["24x16x3", "256x64x2", "24x16x96-streamed", "256x64x9-streamed", "128x32x9"])
 def test_batch_against_oracle(nx, nz, lx, Pr, dt, ras, nsteps, ce, sample):
     B = len(ras)
     note(f"batch {nx}x{nz} B={B} x {nsteps} steps ce={ce}")
