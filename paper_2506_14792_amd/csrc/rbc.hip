@@ -986,10 +986,23 @@ __global__ void __launch_bounds__(NTK) rbc_kfwd(RbcDev d, KfArgs a) {
       // boundary and gauge rows: M is zero there and every stage's F holds the boundary data
       // (b = 1 at z = 0 for k = 0), so the row is dt (sum_j A_ij F - L sum_j H_ij X_j)
       const int q = (tid - 4 * N) >> 2, h = tid & 3;
-      const double fbc = (k == 0 && q == 4) ? d.bc0 : 0.0;
-      cplx v = cmk(a.asum * fbc, 0.0);
-      if (a.lx) v = csub(v, l_bc_row(d, k, xb, q, h));
-      if (h == 0) rr[4 * N + q] = cscale(v, dt);
+      if (q < 6 || k != 0) {   // (the k = 0 gauge row: the last wave, below)
+        const double fbc = (k == 0 && q == 4) ? d.bc0 : 0.0;
+        cplx v = cmk(a.asum * fbc, 0.0);
+        if (a.lx) v = csub(v, l_bc_row(d, k, xb, q, h));
+        if (h == 0) rr[4 * N + q] = cscale(v, dt);
+      }
+    } else if (k == 0 && tid >= NTK - SPS_WAVE) {
+      // the k = 0 gauge row, -dt (the mean of p): one mode per lane of the (otherwise idle) last
+      // wave, so that the integration weights' divisions run side by side instead of sixteen in
+      // a row on one quad
+      const int m = tid - (NTK - SPS_WAVE);
+      cplx v = (a.lx && m < N) ? cscale(xb[3 * N + m], -intw_at(m)) : czero();
+      for (int o = SPS_WAVE / 2; o >= 1; o >>= 1) {
+        v.x += __shfl_xor(v.x, o);
+        v.y += __shfl_xor(v.y, o);
+      }
+      if (m == 0) rr[4 * N + 6] = cscale(v, dt);
     }
     __syncthreads();
   } else if (mode == KF_SOLVE) {
