@@ -1649,12 +1649,6 @@ __global__ void __launch_bounds__(NTK) rbc_kadj(RbcDev d, KaArgs a) {
   if (fl & KA_SOLVE_T) {
     if (sl) xbar[tid] = xin;
     __syncthreads();
-    if (!STREAM) stage_early(d, opsr, ops, true);
-    rbc_gather_h(d, mr, xbar, vA);
-    rbc_solve<STREAM>(d, k, opsr, ops, vA, vB, true);
-    rbc_scatter_h(d, mr, vA, vB);
-    if (sl) a.Xb_out[ks] = vB[tid];
-    return;
   }
   if (fl & KA_G) {
     if (sl) p_g[tid] = xin;
@@ -1692,6 +1686,10 @@ __global__ void __launch_bounds__(NTK) rbc_kadj(RbcDev d, KaArgs a) {
   rbc_gather_h(d, mr, xbar, vA);
   rbc_solve<STREAM>(d, k, opsr, ops, vA, vB, true);
   rbc_scatter_h(d, mr, vA, vB);       // vB = Y_m
+  if (fl & KA_SOLVE_T) {
+    if (sl) a.Xb_out[ks] = vB[tid];
+    return;
+  }
   if (tid < 4 * Ngz) ct[tid] = cosr;
   const cplx ym = sl ? vB[tid] : czero();
   if (sl) {
