@@ -446,6 +446,31 @@ def ckpt_timing(slot_counts=(5, 10, 20, 50)):
         G.set_checkpoint_file(os.path.join(tmp, "segment_starts.bin"))
         out["two_level_8_disk"] = {"gradient_s": timed(), "file_MB": (n // ce) * state_mb,
                                    "stored_MB": 8 * state_mb + 2 * stage_mb + 2 * state_mb}
+        # nested on the file with 4 outer states: the binomial placement of the segment starts
+        # against the least-cost placement for outer writes and reads priced at the time of a
+        # state's write and read through a file on this host, in forward steps
+        buf = np.zeros(K * S * 2)
+        path = os.path.join(tmp, "probe.bin")
+        t0 = time.perf_counter()
+        for _ in range(5):
+            buf.tofile(path)
+            np.fromfile(path)
+        io_steps = (time.perf_counter() - t0) / 10 / (out["uniform"]["gradient_s"] / (out["uniform"]["forward_steps"] + n))
+        G.set_outer_slots(4)
+        nseg = n // ce
+
+        def outer_counts(f, r):
+            return {"recomputed_segments": sum(b - a for op, a, b in r if op == 1),
+                    "outer_writes": sum(1 for op, _, _ in f + r if op == 2),
+                    "outer_reads": sum(1 for op, _, _ in r if op == 3)}
+        nb = {"gradient_s": timed(), **outer_counts(*sps.checkpoint_schedule(nseg, 4))}
+        G.set_outer_costs(io_steps, io_steps)
+        fc, rc, _ = sps.checkpoint_schedule_costs(nseg, 4, float(ce), io_steps, io_steps)
+        nc = {"gradient_s": timed(), **outer_counts(fc, rc)}
+        G.set_outer_costs(-1.0, -1.0)
+        G.set_outer_slots(0)
+        out["nested_4_outer_8_device_file"] = {"io_cost_forward_steps": io_steps, "binomial_placement": nb,
+                                               "least_cost_placement": nc}
         G.set_checkpoint_file(None)
     G.set_checkpointing(sps.CKPT_UNIFORM)
     G.sync()

@@ -445,6 +445,18 @@ int sps_set_checkpoint_file(sps_problem *P, const char *path);
  * plane Couette; SPS_E_UNSUPPORTED otherwise. */
 int sps_set_outer_slots(sps_problem *P, int slots);
 
+/* Costs of the outer level of the nested schedule (Supplementary, "Initial value problems":
+ * multi-level schedules on slower storage, whose reads and writes cost time; the paper's runs
+ * use the H-revolve schedule for RAM and disk): write_cost and read_cost are the times of
+ * storing and loading one outer state, in units of one forward step.  Both >= 0: the segment
+ * starts are placed on the outer slots by the schedule of least total cost (forward steps of the
+ * segments recomputed, outer writes and reads; every split of the binomial recursion searched,
+ * segments of checkpoint_every steps) instead of the fewest forward steps; each segment is
+ * still reversed with the binomial schedule of its length on the device slots.  Negative (the
+ * default): the binomial placement.  Gradients are bit-identical either way.  SPS_E_ARG when
+ * only one of the two is negative; SPS_E_UNSUPPORTED as sps_set_outer_slots. */
+int sps_set_outer_costs(sps_problem *P, double write_cost, double read_cost);
+
 /* The binomial schedule for nsteps steps and `slots` stored states (host arrays; no problem
  * or device needed): phase 0 the forward sweep, phase 1 the reverse sweep.  Writes *count
  * actions as (op, a, b) triples into actions (capacity: actions it can hold); op 1 = advance
@@ -453,6 +465,16 @@ int sps_set_outer_slots(sps_problem *P, int slots);
  * recording its stage data and then its adjoint.  The reverse sweep's op-4 actions visit
  * steps nsteps-1 .. 0 in order.  SPS_E_ARG (with *count set) when capacity is too small. */
 int sps_checkpoint_schedule(int nsteps, int slots, int phase, int *actions, int capacity, int *count);
+
+/* The schedule of least cost for the same problem when a forward step costs adv, storing a
+ * state wr and loading one rd (all >= 0; the outer level of sps_set_outer_costs, whose units are
+ * segments): the snapshot positions minimize adv x (forward steps of the reverse sweep)
+ * + wr x (states stored, X_0 included) + rd x (states loaded) over every split of the binomial
+ * recursion, which for wr = rd = 0 gives the fewest forward steps.  Same action format and
+ * errors as sps_checkpoint_schedule (SPS_E_ARG also for a negative or non-finite cost);
+ * *cost (nullable) gets the schedule's total cost. */
+int sps_checkpoint_schedule_costs(int nsteps, int slots, double adv, double wr, double rd, int phase,
+                                  int *actions, int capacity, int *count, double *cost);
 
 /* Linear boundary value problem of the 2D problem's operator (Supplementary, "Linear boundary
  * value problems"): L X = M f + c, the steady state of the IVP without its explicit term,

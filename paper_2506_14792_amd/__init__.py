@@ -7,4 +7,4 @@ from .sps import (ClosureNet, Couette, Kolmogorov, PoiseuilleStability, Problem,
                   poiseuille_host_band, rbc_host_bands,
                   use_torch_allocator, RBC2D, KS1D, SH2D, RK222, SBDF2,
                   SBDF3, SBDF4, RK443, CKPT_UNIFORM, CKPT_BINOMIAL, CKPT_TWO_LEVEL,
-                  checkpoint_schedule)  # noqa: F401
+                  checkpoint_schedule, checkpoint_schedule_costs)  # noqa: F401

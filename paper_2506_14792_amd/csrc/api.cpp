@@ -238,6 +238,10 @@ int sps_set_outer_slots(sps_problem* P, int slots) {
   return guard(P, [&](sps::ProblemImpl& p) { p.set_outer_slots(slots); });
 }
 
+int sps_set_outer_costs(sps_problem* P, double write_cost, double read_cost) {
+  return guard(P, [&](sps::ProblemImpl& p) { p.set_outer_costs(write_cost, read_cost); });
+}
+
 int sps_set_checkpoint_file(sps_problem* P, const char* path) {
   return guard(P, [&](sps::ProblemImpl& p) { p.set_checkpoint_file(path); });
 }
@@ -249,6 +253,31 @@ int sps_checkpoint_schedule(int nsteps, int slots, int phase, int* actions, int 
   try {
     std::vector<sps::CkptAction> fwd, rev;
     sps::binomial_schedule(nsteps, slots, fwd, rev);
+    const std::vector<sps::CkptAction>& v = phase == 0 ? fwd : rev;
+    *count = (int)v.size();
+    if (!actions || capacity < *count) return fail(SPS_E_ARG, "actions array too small");
+    for (size_t i = 0; i < v.size(); ++i) {
+      actions[3 * i] = v[i].op;
+      actions[3 * i + 1] = v[i].a;
+      actions[3 * i + 2] = v[i].b;
+    }
+  } catch (const std::exception& e) {
+    return fail(SPS_E_NOMEM, e.what());
+  }
+  return SPS_OK;
+}
+
+int sps_checkpoint_schedule_costs(int nsteps, int slots, double adv, double wr, double rd, int phase, int* actions,
+                                  int capacity, int* count, double* cost) {
+  if (!count) return fail(SPS_E_ARG, "null count");
+  *count = 0;
+  if (nsteps < 1 || slots < 1 || (phase != 0 && phase != 1)) return fail(SPS_E_ARG, "nsteps, slots >= 1 and phase 0 or 1");
+  if (!(adv >= 0.0 && wr >= 0.0 && rd >= 0.0) || !std::isfinite(adv + wr + rd))
+    return fail(SPS_E_ARG, "costs must be finite and >= 0");
+  try {
+    std::vector<sps::CkptAction> fwd, rev;
+    const double c = sps::cost_schedule(nsteps, slots, adv, wr, rd, fwd, rev);
+    if (cost) *cost = c;
     const std::vector<sps::CkptAction>& v = phase == 0 ? fwd : rev;
     *count = (int)v.size();
     if (!actions || capacity < *count) return fail(SPS_E_ARG, "actions array too small");

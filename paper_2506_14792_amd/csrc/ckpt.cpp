@@ -37,10 +37,74 @@ int split(int n, int s) {
   return (int)std::max<long long>(1, std::min<long long>(n - 1, m));
 }
 
+// Split choices of the cost model: D(n, s) reverses n steps whose first state is stored and in
+// hand, with s more free slots; C(n, s) = rd + D(n, s) has to load that state first; F(n, s)
+// reverses the steps that the forward sweep ran through, which takes the snapshots of the first
+// descent without extra forward steps (and ends with X_n in hand, so its last part loads first).
+//   D(1, s) = 0,  D(n, 0) = adv (n - 1) + (n - 1) rd + adv (n - 1)(n - 2) / 2,
+//   D(n, s) = min(D(n, 0), min_j adv j + wr + D(n - j, s - 1) + C(j, s)),
+//   F(1, s) = rd,  F(n, 0) = C(n, 0),  F(n, s) = min(C(n, 0), min_j wr + F(n - j, s - 1) + C(j, s)),
+// j the length of the left part (the snapshot's offset), the right part reversed first; split 0
+// stands for the first option (no further snapshot: every step recomputed from the interval's
+// first state), which can win when a snapshot costs more than the steps it saves.
+class CostSplits {
+ public:
+  CostSplits(int n, int slots, double adv, double wr, double rd)
+      : n_(n), s_(slots), adv_(adv), wr_(wr), rd_(rd),
+        D_((size_t)(n + 1) * slots, 0.0), F_((size_t)(n + 1) * slots, 0.0),
+        jd_((size_t)(n + 1) * slots, 1), jf_((size_t)(n + 1) * slots, 1) {
+    for (int s = 0; s < s_; ++s)
+      for (int n1 = 1; n1 <= n_; ++n1) {
+        double& d = at(D_, n1, s);
+        double& f = at(F_, n1, s);
+        if (n1 == 1) {
+          d = 0.0;
+          f = rd_;
+        } else if (s == 0) {
+          d = adv_ * (n1 - 1) + (n1 - 1) * rd_ + adv_ * 0.5 * (double)(n1 - 1) * (n1 - 2);
+          f = rd_ + d;
+        } else {
+          double bd = at(D_, n1, 0), bf = at(F_, n1, 0);
+          int id = 0, jf = 0;
+          for (int j = 1; j < n1; ++j) {
+            const double left = rd_ + at(D_, j, s);
+            const double vd = adv_ * j + wr_ + at(D_, n1 - j, s - 1) + left;
+            const double vf = wr_ + at(F_, n1 - j, s - 1) + left;
+            if (vd < bd) {
+              bd = vd;
+              id = j;
+            }
+            if (vf < bf) {
+              bf = vf;
+              jf = j;
+            }
+          }
+          d = bd;
+          f = bf;
+          at(jd_, n1, s) = id;
+          at(jf_, n1, s) = jf;
+        }
+      }
+  }
+  int split(int n, int s, bool descent) const { return at(descent ? jf_ : jd_, n, s); }
+  double total() const { return wr_ + at(F_, n_, s_ - 1); }   // (X_0's snapshot included)
+
+ private:
+  template <typename T>
+  T& at(std::vector<T>& v, int n, int s) { return v[(size_t)n * s_ + s]; }
+  template <typename T>
+  const T& at(const std::vector<T>& v, int n, int s) const { return v[(size_t)n * s_ + s]; }
+  int n_, s_;
+  double adv_, wr_, rd_;
+  std::vector<double> D_, F_;
+  std::vector<int> jd_, jf_;
+};
+
 class Generator {
  public:
-  Generator(int n, int slots, std::vector<CkptAction>& fwd, std::vector<CkptAction>& rev)
-      : n_(n), slots_(slots), fwd_(fwd), rev_(rev) {}
+  Generator(int n, int slots, std::vector<CkptAction>& fwd, std::vector<CkptAction>& rev,
+            const CostSplits* cs = nullptr)
+      : n_(n), slots_(slots), fwd_(fwd), rev_(rev), cs_(cs) {}
 
   void run() {
     fwd_.clear();
@@ -49,8 +113,8 @@ class Generator {
     // recursion, then on to X_N
     fwd_.push_back({CK_TAKESHOT, 0, 0});
     int l = 0, s = slots_ - 1, next = 1;
-    while (n_ - l > 1 && s > 0) {
-      const int m = l + split(n_ - l, s);
+    while (n_ - l > 1 && s > 0 && pick(n_ - l, s, true) > 0) {
+      const int m = l + pick(n_ - l, s, true);
       fwd_.push_back({CK_ADVANCE, l, m});
       fwd_.push_back({CK_TAKESHOT, next, m});
       l = m;
@@ -72,14 +136,14 @@ class Generator {
       youturn(l);
       return;
     }
-    if (s == 0) {
+    if (s == 0 || pick(n, s, taken) == 0) {
       for (int i = r - 1; i >= l; --i) {
         reach(i, l, sl);
         youturn(i);
       }
       return;
     }
-    const int m = l + split(n, s);
+    const int m = l + pick(n, s, taken);
     if (!taken) {
       reach(m, l, sl);
       rev_.push_back({CK_TAKESHOT, next, m});
@@ -102,16 +166,27 @@ class Generator {
     rev_.push_back({CK_YOUTURN, i, 0});
     cur_ = i + 1;
   }
+  // the snapshot offset of an interval of n steps with s free slots (descent: one of the
+  // intervals whose snapshots the forward sweep takes)
+  int pick(int n, int s, bool descent) const { return cs_ ? cs_->split(n, s, descent) : split(n, s); }
 
   int n_, slots_, cur_ = 0;
   std::vector<CkptAction>& fwd_;
   std::vector<CkptAction>& rev_;
+  const CostSplits* cs_;
 };
 
 }  // namespace
 
 void binomial_schedule(int nsteps, int slots, std::vector<CkptAction>& fwd, std::vector<CkptAction>& rev) {
   Generator(nsteps, slots, fwd, rev).run();
+}
+
+double cost_schedule(int nsteps, int slots, double adv, double wr, double rd, std::vector<CkptAction>& fwd,
+                     std::vector<CkptAction>& rev) {
+  const CostSplits cs(nsteps, slots, adv, wr, rd);
+  Generator(nsteps, slots, fwd, rev, &cs).run();
+  return cs.total();
 }
 
 }  // namespace sps

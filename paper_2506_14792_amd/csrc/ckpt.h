@@ -21,4 +21,13 @@ struct CkptAction {
 // visit the steps N-1 .. 0 in order.
 void binomial_schedule(int nsteps, int slots, std::vector<CkptAction>& fwd, std::vector<CkptAction>& rev);
 
+// The same kind of schedule with the snapshot positions chosen for the least total cost when
+// storing and loading a state cost something (a slower level of storage: host memory, disk):
+// adv per forward step of the reverse sweep, wr per snapshot taken (those of the forward sweep
+// included), rd per snapshot loaded.  Every split of the recursion above is searched by dynamic
+// programming; with wr = rd = 0 the forward steps are the fewest, as with binomial_schedule.
+// Returns the schedule's cost.  O(nsteps^2 slots) time.
+double cost_schedule(int nsteps, int slots, double adv, double wr, double rd, std::vector<CkptAction>& fwd,
+                     std::vector<CkptAction>& rev);
+
 }  // namespace sps

@@ -3773,7 +3773,11 @@ class RbcProblem : public ProblemImpl {
     auto it = osched_.find(nseg);
     if (it == osched_.end()) {
       std::pair<std::vector<CkptAction>, std::vector<CkptAction>> sc;
-      binomial_schedule(nseg, outer_slots_, sc.first, sc.second);
+      // (a segment's advance costs checkpoint_every forward steps; the outer costs are in steps)
+      if (outer_wr_ >= 0.0)
+        cost_schedule(nseg, outer_slots_, (double)desc_.checkpoint_every, outer_wr_, outer_rd_, sc.first, sc.second);
+      else
+        binomial_schedule(nseg, outer_slots_, sc.first, sc.second);
       it = osched_.emplace(nseg, std::move(sc)).first;
     }
     return it->second;
@@ -3967,6 +3971,18 @@ class RbcProblem : public ProblemImpl {
     osched_.clear();
     tape_steps_ = -1;
     if (ckpt_mode_ == SPS_CKPT_TWO_LEVEL && ckfd_ < 0) alloc_host_ckpt();
+  }
+  void set_outer_costs(double write_cost, double read_cost) override {
+    no_batch("the nested checkpoint schedule");
+    const bool off = write_cost < 0.0 && read_cost < 0.0;
+    SPS_REQUIRE(off || (write_cost >= 0.0 && read_cost >= 0.0 && std::isfinite(write_cost + read_cost)),
+                "outer costs: both >= 0 and finite, or both negative");
+    drop_graphs();
+    SPS_HIP(hipStreamSynchronize(stream));
+    outer_wr_ = off ? -1.0 : write_cost;
+    outer_rd_ = off ? -1.0 : read_cost;
+    osched_.clear();
+    tape_steps_ = -1;
   }
 
  private:
@@ -4330,6 +4346,7 @@ class RbcProblem : public ProblemImpl {
   std::unique_ptr<cplx, HostFree> ckstage_;     // disk level: two pinned staging buffers
   int host_cap_ = 0;                            // states held by host_ckpt_
   int outer_slots_ = 0;                         // outer-level slots (0: one per segment)
+  double outer_wr_ = -1.0, outer_rd_ = -1.0;    // outer write/read costs in forward steps (< 0: binomial)
   std::map<int, std::pair<std::vector<CkptAction>, std::vector<CkptAction>>> osched_;
   cplx* Xo_ = nullptr;                          // working state of the nested outer schedule
   hipEvent_t ckev_[2] = {nullptr, nullptr};

@@ -185,6 +185,9 @@ class ProblemImpl {
   virtual void set_outer_slots(int) {
     throw Error(SPS_E_UNSUPPORTED, "checkpoint schedules are built for the RK222 problems");
   }
+  virtual void set_outer_costs(double, double) {
+    throw Error(SPS_E_UNSUPPORTED, "checkpoint schedules are built for the RK222 problems");
+  }
   virtual void set_checkpoint_file(const char*) {
     throw Error(SPS_E_UNSUPPORTED, "checkpoint schedules are built for the RK222 problems");
   }

@@ -66,6 +66,11 @@ def lib():
         "sps_set_dt": (ctypes.c_int, [_P, ctypes.c_double]),
         "sps_set_checkpoint_file": (ctypes.c_int, [_P, ctypes.c_char_p]),
         "sps_set_outer_slots": (ctypes.c_int, [_P, ctypes.c_int]),
+        "sps_set_outer_costs": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double]),
+        "sps_checkpoint_schedule_costs": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                                         ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                                         ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                                         ctypes.POINTER(ctypes.c_double)]),
         "sps_stability": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int, _D, _D, _D, _D]),
         "sps_stability_vector_sens": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int, _D, _D, _D, _D, _D]),
         "sps_stability_arnoldi": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int, ctypes.c_int, _D, _D, _D, _D,
@@ -187,6 +192,23 @@ def checkpoint_schedule(nsteps, slots):
         _check(lib().sps_checkpoint_schedule(nsteps, slots, phase, buf, count.value, ctypes.byref(count)))
         out.append([tuple(buf[3 * i:3 * i + 3]) for i in range(count.value)])
     return out[0], out[1]
+
+
+def checkpoint_schedule_costs(nsteps, slots, adv, wr, rd):
+    """The checkpointing schedule of least cost (adv per forward step of the reverse sweep, wr per
+    stored state, rd per loaded state) in the format of checkpoint_schedule, and its cost."""
+    out = []
+    cost = ctypes.c_double(0.0)
+    for phase in (0, 1):
+        count = ctypes.c_int(0)
+        rc = lib().sps_checkpoint_schedule_costs(nsteps, slots, adv, wr, rd, phase, None, 0, ctypes.byref(count), None)
+        if rc not in (0, -1) or count.value == 0:
+            _check(rc)
+        buf = (ctypes.c_int * (3 * count.value))()
+        _check(lib().sps_checkpoint_schedule_costs(nsteps, slots, adv, wr, rd, phase, buf, count.value,
+                                                   ctypes.byref(count), ctypes.byref(cost)))
+        out.append([tuple(buf[3 * i:3 * i + 3]) for i in range(count.value)])
+    return out[0], out[1], cost.value
 
 
 class Problem:
@@ -315,6 +337,12 @@ class Problem:
     def set_outer_slots(self, slots):
         """Outer-level states of CKPT_TWO_LEVEL (0: one per segment; fewer: nested binomial)."""
         _check(lib().sps_set_outer_slots(self._h, int(slots)))
+        self.tape_id += 1
+
+    def set_outer_costs(self, write_cost, read_cost):
+        """Write and read costs of one outer state in forward steps (both >= 0: the nested
+        schedule of least cost; both negative: the binomial placement)."""
+        _check(lib().sps_set_outer_costs(self._h, float(write_cost), float(read_cost)))
         self.tape_id += 1
 
     def set_checkpoint_file(self, path):

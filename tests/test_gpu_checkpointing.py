@@ -261,6 +261,53 @@ def test_disk_level_unsupported_for_multistep_problems(tmp_path):
     assert e.value.code == -7
 
 
+def test_nested_outer_costs_equal_uniform(tmp_path):
+    """The nested schedule with priced outer writes and reads (sps_set_outer_costs: the segment
+    starts placed for the least cost, not the fewest steps) gives the same bits as the uniform
+    schedule at 24x16 (13 steps in 7 segments of 2; 1-2 device slots, 2-3 outer slots, free,
+    moderate and prohibitive outer costs; host memory and a file) and at 256x64 x 1000 steps (20
+    segments on 4 outer and 5 device slots); one negative cost alone is refused."""
+    n, ce = 13, 2
+    note(f"nested two-level with outer costs vs uniform, 24x16, {n} steps, segments of {ce}")
+    P, G, X0h = small_problem(n, ce)
+    X0 = to_dev(X0h)
+    ref = grad(G, X0, n)
+    for slots in (1, 2):
+        G.set_checkpointing(sps.CKPT_TWO_LEVEL, slots)
+        for outer in (2, 3):
+            G.set_outer_slots(outer)
+            for wr, rd in ((0.0, 0.0), (4.0, 1.0), (1e4, 1e4)):
+                G.set_outer_costs(wr, rd)
+                same = all(torch.equal(a, b) for a, b in zip(grad(G, X0, n), ref))
+                note(f"  device slots {slots}, outer slots {outer}, costs ({wr}, {rd}): identical {same}")
+                assert same
+    G.set_checkpoint_file(tmp_path / "nested_costs.bin")
+    G.set_outer_slots(3)
+    G.set_outer_costs(3.0, 3.0)
+    assert all(torch.equal(a, b) for a, b in zip(grad(G, X0, n), ref))
+    with pytest.raises(sps.SpsError) as e:
+        G.set_outer_costs(-1.0, 2.0)
+    assert e.value.code == -1
+    G.set_outer_costs(-1.0, -1.0)
+    G.set_checkpoint_file(None)
+    G.set_outer_slots(0)
+
+    note("nested two-level with outer costs vs uniform, 256x64, 1000 steps, 4 outer and 5 device slots")
+    nx, nz, lx, Ra, Pr, dt = FULL
+    nf = 1000
+    Gf = sps.Problem(sps.RBC2D, nx, nz, lx, Ra, Pr, 1.5, dt, 50, nf)
+    b0 = torch.from_numpy(wl.rbc_b0(seed=0, Nx=nx, Nz=nz).ravel().copy()).cuda()
+    Xf = torch.zeros(Gf.n, dtype=torch.float64, device="cuda")
+    Gf.initial_state(b0, Xf)
+    reff = grad(Gf, Xf, nf)
+    Gf.set_checkpointing(sps.CKPT_TWO_LEVEL, 5)
+    Gf.set_outer_slots(4)
+    Gf.set_outer_costs(5.0, 5.0)
+    same = all(torch.equal(a, b) for a, b in zip(grad(Gf, Xf, nf), reff))
+    note(f"  identical: {same}")
+    assert same
+
+
 def test_nested_outer_slots_equal_uniform(tmp_path):
     """Nested binomial checkpointing (sps_set_outer_slots below the segment count): segment
     starts placed on 1-6 outer slots by the binomial schedule over segments, each segment
