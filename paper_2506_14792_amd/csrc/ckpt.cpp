@@ -49,10 +49,11 @@ int split(int n, int s) {
 // first state), which can win when a snapshot costs more than the steps it saves.
 class CostSplits {
  public:
+  // (more than n slots never help an interval of at most n steps: the table stops at n)
   CostSplits(int n, int slots, double adv, double wr, double rd)
-      : n_(n), s_(slots), adv_(adv), wr_(wr), rd_(rd),
-        D_((size_t)(n + 1) * slots, 0.0), F_((size_t)(n + 1) * slots, 0.0),
-        jd_((size_t)(n + 1) * slots, 1), jf_((size_t)(n + 1) * slots, 1) {
+      : n_(n), s_(std::min(slots, n)), adv_(adv), wr_(wr), rd_(rd),
+        D_((size_t)(n + 1) * s_, 0.0), F_((size_t)(n + 1) * s_, 0.0),
+        jd_((size_t)(n + 1) * s_, 1), jf_((size_t)(n + 1) * s_, 1) {
     for (int s = 0; s < s_; ++s)
       for (int n1 = 1; n1 <= n_; ++n1) {
         double& d = at(D_, n1, s);
@@ -86,7 +87,7 @@ class CostSplits {
         }
       }
   }
-  int split(int n, int s, bool descent) const { return at(descent ? jf_ : jd_, n, s); }
+  int split(int n, int s, bool descent) const { return at(descent ? jf_ : jd_, n, std::min(s, s_ - 1)); }
   double total() const { return wr_ + at(F_, n_, s_ - 1); }   // (X_0's snapshot included)
 
  private:
