@@ -471,8 +471,9 @@ int sps_checkpoint_schedule(int nsteps, int slots, int phase, int *actions, int 
  * segments): the snapshot positions minimize adv x (forward steps of the reverse sweep)
  * + wr x (states stored, X_0 included) + rd x (states loaded) over every split of the binomial
  * recursion, which for wr = rd = 0 gives the fewest forward steps.  Same action format and
- * errors as sps_checkpoint_schedule (SPS_E_ARG also for a negative or non-finite cost);
- * *cost (nullable) gets the schedule's total cost. */
+ * errors as sps_checkpoint_schedule (SPS_E_ARG also for a negative or non-finite cost, and when
+ * nsteps^2 min(slots, nsteps) exceeds 2e10, the search's work); *cost (nullable) gets the
+ * schedule's total cost. */
 int sps_checkpoint_schedule_costs(int nsteps, int slots, double adv, double wr, double rd, int phase,
                                   int *actions, int capacity, int *count, double *cost);
 

@@ -1,6 +1,7 @@
 // C ABI entry points: argument checks, exception-to-status translation, error strings.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -274,6 +275,8 @@ int sps_checkpoint_schedule_costs(int nsteps, int slots, double adv, double wr, 
   if (nsteps < 1 || slots < 1 || (phase != 0 && phase != 1)) return fail(SPS_E_ARG, "nsteps, slots >= 1 and phase 0 or 1");
   if (!(adv >= 0.0 && wr >= 0.0 && rd >= 0.0) || !std::isfinite(adv + wr + rd))
     return fail(SPS_E_ARG, "costs must be finite and >= 0");
+  // (the search takes nsteps^2 min(slots, nsteps) steps)
+  if ((double)nsteps * nsteps * std::min(slots, nsteps) > 2e10) return fail(SPS_E_ARG, "too many steps for the cost search");
   try {
     std::vector<sps::CkptAction> fwd, rev;
     const double c = sps::cost_schedule(nsteps, slots, adv, wr, rd, fwd, rev);

@@ -211,6 +211,7 @@ def test_cost_schedule_trades_steps_for_stores():
 
 
 def test_cost_schedule_bad_arguments():
-    for args in ((0, 3, 1.0, 0.0, 0.0), (10, 0, 1.0, 0.0, 0.0), (10, 3, -1.0, 0.0, 0.0), (10, 3, 1.0, float("nan"), 0.0)):
+    for args in ((0, 3, 1.0, 0.0, 0.0), (10, 0, 1.0, 0.0, 0.0), (10, 3, -1.0, 0.0, 0.0), (10, 3, 1.0, float("nan"), 0.0),
+                 (100000, 1000, 1.0, 1.0, 1.0)):   # (the last: more work than the search accepts)
         with pytest.raises(sps.SpsError):
             sps.checkpoint_schedule_costs(*args)
