@@ -3774,10 +3774,14 @@ class RbcProblem : public ProblemImpl {
     if (it == osched_.end()) {
       std::pair<std::vector<CkptAction>, std::vector<CkptAction>> sc;
       // (a segment's advance costs checkpoint_every forward steps; the outer costs are in steps)
-      if (outer_wr_ >= 0.0)
+      if (outer_wr_ >= 0.0) {
+        // (the search takes nseg^2 min(slots, nseg) steps)
+        SPS_REQUIRE((double)nseg * nseg * std::min(outer_slots_, nseg) <= 2e10,
+                    "too many segments for the outer cost search");
         cost_schedule(nseg, outer_slots_, (double)desc_.checkpoint_every, outer_wr_, outer_rd_, sc.first, sc.second);
-      else
+      } else {
         binomial_schedule(nseg, outer_slots_, sc.first, sc.second);
+      }
       it = osched_.emplace(nseg, std::move(sc)).first;
     }
     return it->second;
