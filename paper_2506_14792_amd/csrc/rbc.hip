@@ -1568,7 +1568,7 @@ __device__ void g_to_nlbar(const RbcDev& d, const KaArgs& a, int k, const double
 // LDS: vA, vB (S complex each) persist; the rest is a union of phase buffers and the
 // staged block operators.  One entry of every length-S vector per thread.
 template <bool STREAM>
-__global__ void __launch_bounds__(NTK) rbc_kadj(RbcDev d, KaArgs a) {
+__global__ void __launch_bounds__(NTK, STREAM ? 6 : 1) rbc_kadj(RbcDev d, KaArgs a) {
   if (blockIdx.y) {
     const int b = blockIdx.y;
     const size_t st = (size_t)d.K * d.S, zs = (size_t)d.Ngz * d.K;
