@@ -626,7 +626,7 @@ __device__ void rbc_solve_staged(const RbcDev& d, const OpsRegs& regs, double* o
 // of SPS_CHUNK blocks: wave 0 runs the sweeps over chunk q while the other waves copy
 // chunk q + 1 (for launches with many more systems than CUs: no register prefetch and a small
 // LDS footprint, so several blocks share a CU).  Block-wide; buf holds 2 * SOLVE_CHUNK_D doubles.
-constexpr int SPS_CHUNK = 8;
+constexpr int SPS_CHUNK = 6;
 constexpr int SOLVE_CHUNK_D = SPS_CHUNK * SPS_BLK * SPS_GS;   // >= SPS_CHUNK * SPS_TW * SPS_TS
 __device__ void rbc_solve_streamed(const RbcDev& d, const double* gops, double* buf, cplx* vA, bool transposed) {
   const int nblk = blk_count(d.n), nch = (nblk + SPS_CHUNK - 1) / SPS_CHUNK, Q = 2 * nch;
