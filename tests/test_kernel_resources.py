@@ -1,8 +1,14 @@
 """Resource usage of the 2D problem's kernels as compiled for gfx950: no kernel of rbc.hip uses
-per-lane scratch memory.  A kernel that indexes an argument struct's array with a run-time index
-after modifying the struct (for example a batch instance's pointer offsets) gets a private copy
-of the struct in scratch memory, which slows every stage launch by about a quarter; this check
-keeps such copies out.  Compiles the device code only (about half a minute)."""
+per-lane scratch memory, except the streamed adjoint stage kernel, whose launch bound holds it to
+80 registers for three blocks per CU at the price of a small spill (bounded here).  A kernel that
+indexes an argument struct's array with a run-time index after modifying the struct (for example
+a batch instance's pointer offsets) gets a private copy of the struct in scratch memory, which
+slows every stage launch by about a quarter; this check keeps such copies out.  Compiles the
+device code only (about half a minute)."""
+
+# the deliberate spill of the streamed adjoint kernel (rbc_kadj<true>): at most this many bytes
+# per lane (a struct copy would take several hundred)
+STREAMED_ADJOINT_SPILL = 96
 import os
 import re
 import shutil
@@ -31,5 +37,6 @@ def test_no_scratch_in_2d_kernels(tmp_path):
         if m and name:
             usage[name] = int(m.group(1))
     assert any("rbc_kfwd" in n for n in usage) and any("rbc_kadj" in n for n in usage)
-    bad = {n: v for n, v in usage.items() if v}
+    bad = {n: v for n, v in usage.items() if v and not ("rbc_kadjILb1" in n and v <= STREAMED_ADJOINT_SPILL)}
     assert not bad, f"kernels with scratch: {bad}"
+    assert all(v == 0 for n, v in usage.items() if "rbc_kadjILb0" in n or "rbc_kfwd" in n)
