@@ -1298,15 +1298,20 @@ __global__ void __launch_bounds__(256) rbc_xfwd_w(RbcDev d, XfArgs a) {
     const cplx* G1 = G01 + N;
     const cplx* G2 = scr + 2 * SC;
     const cplx* G3 = scr + 3 * SC;
+    // (the wave's branch outside the loops: a branch between the rows would make every row's
+    // LDS reads wait for the previous row's)
+    if (wv == 0) {
 #pragma unroll
-    for (int h = 0; h < 8; ++h) {
-      const int e = h * 8 * R1 + l;
-      const cplx uw = G0[e];
-      if (wv == 0) {
-        const cplx ud = G1[e], wd = G2[e];
+      for (int h = 0; h < 8; ++h) {
+        const int e = h * 8 * R1 + l;
+        const cplx uw = G0[e], ud = G1[e], wd = G2[e];
         pv[h] = cmk(-(uw.x * ud.x + uw.y * ud.y), -(uw.x * wd.x + uw.y * wd.y));   // N_u, N_w
-      } else {
-        const cplx bd = G3[e];
+      }
+    } else {
+#pragma unroll
+      for (int h = 0; h < 8; ++h) {
+        const int e = h * 8 * R1 + l;
+        const cplx uw = G0[e], bd = G3[e];
         pv[h] = cmk(-(uw.x * bd.x + uw.y * bd.y), 0.0);                            // N_b
       }
     }
@@ -1372,18 +1377,29 @@ __global__ void __launch_bounds__(384) rbc_xadj_w(RbcDev d, XaArgs a) {
       constexpr double inv = 1.0 / N;
       const cplx* G4 = scr + 4 * SC;
       const cplx* G5 = scr + 5 * SC;
+      // (the wave's branch outside the loops: a branch between the rows would make every row's
+      // LDS reads wait for the previous row's)
+      if (wv == 0) {
 #pragma unroll
-      for (int h = 0; h < 8; ++h) {
-        const int e = h * 8 * R1 + l;
-        const cplx nb = G4[e];
-        const double Nub = nb.x * inv, Nwb = nb.y * inv, Nbb = G5[e].x * inv;
-        if (wv == 0) {
+        for (int h = 0; h < 8; ++h) {
+          const int e = h * 8 * R1 + l;
+          const cplx nb = G4[e];
+          const double Nub = nb.x * inv, Nwb = nb.y * inv, Nbb = G5[e].x * inv;
           const cplx ud = G03[N + e], wd = G03[2 * N + e], bd = G03[3 * N + e];
           pv[h] = cmk(-(Nub * ud.x + Nwb * wd.x + Nbb * bd.x), -(Nub * ud.y + Nwb * wd.y + Nbb * bd.y));
-        } else {
+        }
+      } else {
+        // (x-derivative bar, z-derivative bar) of u, w or b: the cotangent Nu_bar, Nw_bar or Nb_bar
+        // of wave 1, 2 or 3 times (u, w)
+        const cplx* Gc = wv == 3 ? G5 : G4;
+        const bool im = wv == 2;
+#pragma unroll
+        for (int h = 0; h < 8; ++h) {
+          const int e = h * 8 * R1 + l;
+          const cplx nb = Gc[e];
+          const double c = (im ? nb.y : nb.x) * inv;
           const cplx uw = G03[e];
-          const double c = (wv == 1) ? Nub : (wv == 2 ? Nwb : Nbb);
-          pv[h] = cmk(-c * uw.x, -c * uw.y);   // (x-derivative bar, z-derivative bar) of u, w or b
+          pv[h] = cmk(-c * uw.x, -c * uw.y);
         }
       }
     }
