@@ -1238,17 +1238,27 @@ __device__ __forceinline__ void pack_pair_row(const RbcDev& d, const cplx* src, 
   constexpr int N = WaveRow<R1>::N, K = WaveRow<R1>::K;
   const int l = lane_id(), Ngz = d.Ngz;
   const cplx* U = src + ((size_t)fu * Ngz + j) * K;
-  const cplx* V = fv >= 0 ? src + ((size_t)fv * Ngz + j) * K : nullptr;
+  // (without a V the U row is read in its place and the values dropped: every load is issued
+  // unconditionally, since a load under a branch makes the first use wait for all of them)
+  const cplx* V = src + ((size_t)(fv >= 0 ? fv : fu) * Ngz + j) * K;
+  cplx uu[R1], vv[R1];
+  double kk[R1];
+#pragma unroll
+  for (int q = 0; q < R1; ++q) {
+    const int m = l + 64 * q;
+    const int sidx = m < K ? m : (m > N - K ? N - m : 0);
+    uu[q] = U[sidx];
+    vv[q] = V[sidx];
+    kk[q] = d.kx[sidx];
+  }
 #pragma unroll
   for (int q = 0; q < R1; ++q) {
     const int m = l + 64 * q;
     const bool lowm = m < K, highm = m > N - K;
-    const int sidx = lowm ? m : (highm ? N - m : 0);
     cplx u = czero(), v = czero();
     if (lowm || highm) {
-      u = U[sidx];
-      if (du) u = cscale(cmul_i(u), d.kx[sidx]);
-      if (V) v = V[sidx];
+      u = du ? cscale(cmul_i(uu[q]), kk[q]) : uu[q];
+      v = fv >= 0 ? vv[q] : czero();
     }
     cplx r;
     if (m == 0) r = cmk(u.x, v.x);
